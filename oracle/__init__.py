@@ -1,0 +1,276 @@
+"""FP64 CPU oracle for the smoothed sample bispectrum / trispectrum.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library (``paper_1805_11775_amd``) and never imports it;
+the product path never calls into it.
+
+What it computes, and the passages it follows (arXiv:1805.11775):
+
+* mean removal -- Section 1, Algorithm DBS step 2 (subtract the mean of a
+  part), with the whole record as one part (Section 4.1 uses K = 1);
+* the third and fourth sample cumulants -- Section 1 "Problem Statement"
+  (moments of order k, cumulants as functions of moments, time averages in
+  place of ensemble averages); the brute-force sums live in
+  ``hos_oracle.c``;
+* the spectra as Fourier transforms of the cumulants -- Section 1 (the
+  bispectrum transforms the third cumulant, the trispectrum the fourth),
+  with the DFT sign of Algorithm DBS step 3 (exp(-j 2 pi u k / M),
+  unnormalised);
+* the principal domain 0 <= k2 <= k1, k1 + k2 < N/2 -- Algorithm DBS step 4.
+
+Where the paper is silent (normalisation 1/n, lag-window shape, output
+region, loss), each function below states the reading it uses.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hos_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C core with gcc (plain -O2, no fast-math reassociation)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-std=c99", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        lib.or_center.argtypes = [dp, i64, dp]
+        lib.or_c3_at.argtypes = [dp, i64, ip, ip, i64, dp]
+        lib.or_c3_square.argtypes = [dp, i64, i32, dp]
+        lib.or_c2.argtypes = [dp, i64, i32, dp]
+        lib.or_m4_at.argtypes = [dp, i64, ip, ip, ip, i64, dp]
+        lib.or_c4_at.argtypes = [dp, i64, ip, ip, ip, i64, dp]
+        lib.or_c4_cube.argtypes = [dp, i64, i32, dp]
+        for f in (lib.or_center, lib.or_c3_at, lib.or_c3_square, lib.or_c2,
+                  lib.or_m4_at, lib.or_c4_at, lib.or_c4_cube):
+            f.restype = None
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# Step 1: mean removal (Algorithm DBS step 2 with one part, K = 1).
+# --------------------------------------------------------------------------
+def center(x) -> np.ndarray:
+    """x - mean(x) in FP64 (input widened exactly from float32 if needed)."""
+    x = _f64(x)
+    out = np.empty_like(x)
+    _load().or_center(_dp(x), x.size, _dp(out))
+    return out
+
+
+def _prep(x, centered: bool) -> np.ndarray:
+    return center(x) if centered else _f64(x)
+
+
+# --------------------------------------------------------------------------
+# Step 2: sample cumulants (Section 1, Problem Statement), brute force.
+# --------------------------------------------------------------------------
+def c3_at(x, w1, w2, centered: bool = True) -> np.ndarray:
+    """c3(w1[k], w2[k]) = (1/n) sum_t x_t x_{t+w1} x_{t+w2}, any lags."""
+    xt = _prep(x, centered)
+    w1 = np.ascontiguousarray(np.asarray(w1, dtype=np.int32).ravel())
+    w2 = np.ascontiguousarray(np.asarray(w2, dtype=np.int32).ravel())
+    out = np.empty(w1.size, dtype=np.float64)
+    _load().or_c3_at(_dp(xt), xt.size, _ip(w1), _ip(w2), w1.size, _dp(out))
+    return out
+
+
+def c3_square(x, M: int, centered: bool = True) -> np.ndarray:
+    """c3 at every lag of the square |w1|, |w2| <= M; [w1+M, w2+M]."""
+    xt = _prep(x, centered)
+    side = 2 * M + 1
+    out = np.empty((side, side), dtype=np.float64)
+    _load().or_c3_square(_dp(xt), xt.size, int(M), _dp(out))
+    return out
+
+
+def span3(M: int) -> np.ndarray:
+    """max(0,w1,w2) - min(0,w1,w2) over the square, [w1+M, w2+M]."""
+    w = np.arange(-M, M + 1)
+    w1, w2 = np.meshgrid(w, w, indexing="ij")
+    return np.maximum(np.maximum(0, w1), w2) - np.minimum(np.minimum(0, w1), w2)
+
+
+def c3_hexagon(x, M: int, centered: bool = True) -> np.ndarray:
+    """c3 on the hexagon |w1|,|w2|,|w1-w2| <= M, zero on the two corners.
+
+    Output-region reading: the lags requested are |w| <= M; the corner lags
+    (|w1 - w2| > M) are set to 0 because the lag window vanishes there.
+    """
+    c = c3_square(x, M, centered)
+    c[span3(M) > M] = 0.0
+    return c
+
+
+def c2(x, M: int, centered: bool = True) -> np.ndarray:
+    """c2(d) = (1/n) sum_t x_t x_{t+d}, d = 0..M."""
+    xt = _prep(x, centered)
+    out = np.empty(M + 1, dtype=np.float64)
+    _load().or_c2(_dp(xt), xt.size, int(M), _dp(out))
+    return out
+
+
+def m4_at(x, t1, t2, t3, centered: bool = True) -> np.ndarray:
+    xt = _prep(x, centered)
+    t1, t2, t3 = (np.ascontiguousarray(np.asarray(t, dtype=np.int32).ravel())
+                  for t in (t1, t2, t3))
+    out = np.empty(t1.size, dtype=np.float64)
+    _load().or_m4_at(_dp(xt), xt.size, _ip(t1), _ip(t2), _ip(t3), t1.size,
+                     _dp(out))
+    return out
+
+
+def c4_at(x, t1, t2, t3, centered: bool = True) -> np.ndarray:
+    """c4 = m4 - (three products of c2), at arbitrary lag triples."""
+    xt = _prep(x, centered)
+    t1, t2, t3 = (np.ascontiguousarray(np.asarray(t, dtype=np.int32).ravel())
+                  for t in (t1, t2, t3))
+    out = np.empty(t1.size, dtype=np.float64)
+    _load().or_c4_at(_dp(xt), xt.size, _ip(t1), _ip(t2), _ip(t3), t1.size,
+                     _dp(out))
+    return out
+
+
+def c4_cube(x, M: int, centered: bool = True) -> np.ndarray:
+    """c4 at every lag of the cube |t_i| <= M; [t1+M, t2+M, t3+M]."""
+    xt = _prep(x, centered)
+    S = 2 * M + 1
+    out = np.empty((S, S, S), dtype=np.float64)
+    _load().or_c4_cube(_dp(xt), xt.size, int(M), _dp(out))
+    return out
+
+
+def span4(M: int) -> np.ndarray:
+    """max - min of {0, t1, t2, t3} over the cube."""
+    t = np.arange(-M, M + 1)
+    t1, t2, t3 = np.meshgrid(t, t, t, indexing="ij")
+    mx = np.maximum(np.maximum(np.maximum(0, t1), t2), t3)
+    mn = np.minimum(np.minimum(np.minimum(0, t1), t2), t3)
+    return mx - mn
+
+
+def c4_support(x, M: int, centered: bool = True) -> np.ndarray:
+    """c4 on {span(0,t1,t2,t3) <= M}, zero elsewhere in the cube."""
+    c = c4_cube(x, M, centered)
+    c[span4(M) > M] = 0.0
+    return c
+
+
+# --------------------------------------------------------------------------
+# Step 3: lag window (the paper smooths in frequency with a box; the
+# workloads use the Parzen lag window instead -- a reading).
+# --------------------------------------------------------------------------
+def parzen(m, L: int) -> np.ndarray:
+    """Parzen lag window d(m) with scale L: 1-6r^2+6r^3 (r<=1/2),
+    2(1-r)^3 (1/2<r<=1), 0 beyond; r = |m|/L."""
+    r = np.abs(np.asarray(m, dtype=np.float64)) / float(L)
+    return np.where(r <= 0.5, 1.0 - 6.0 * r ** 2 + 6.0 * r ** 3,
+                    np.where(r <= 1.0, 2.0 * (1.0 - r) ** 3, 0.0))
+
+
+def window3(M: int, kind: str = "parzen") -> np.ndarray:
+    """W3(w1,w2) = d(w1) d(w2) d(w1-w2) over the square, scale L = M."""
+    w = np.arange(-M, M + 1)
+    w1, w2 = np.meshgrid(w, w, indexing="ij")
+    if kind == "none":
+        return np.ones_like(w1, dtype=np.float64)
+    return parzen(w1, M) * parzen(w2, M) * parzen(w1 - w2, M)
+
+
+def window4(M: int, kind: str = "parzen") -> np.ndarray:
+    """Product of d over the six pairwise differences of {0,t1,t2,t3}."""
+    t = np.arange(-M, M + 1)
+    t1, t2, t3 = np.meshgrid(t, t, t, indexing="ij")
+    if kind == "none":
+        return np.ones_like(t1, dtype=np.float64)
+    d = lambda m: parzen(m, M)
+    return d(t1) * d(t2) * d(t3) * d(t2 - t1) * d(t3 - t1) * d(t3 - t2)
+
+
+# --------------------------------------------------------------------------
+# Step 4: the DFT (Section 1: spectra are Fourier transforms of cumulants;
+# sign and normalisation of Algorithm DBS step 3).
+# --------------------------------------------------------------------------
+def place_circular(c: np.ndarray, M: int, N: int) -> np.ndarray:
+    """Fold a lag-domain array on [-M, M]^d onto the N^d DFT grid: the value
+    at index m is the sum of c over all lags w with w = m (mod N).  Its DFT is
+    then exactly sum_w c(w) exp(-2 pi i <k, w> / N) at the grid frequencies."""
+    d = c.ndim
+    out = np.zeros((N,) * d, dtype=np.float64)
+    idx = np.arange(-M, M + 1) % N
+    if d == 2:
+        np.add.at(out, np.ix_(idx, idx), c)
+    else:
+        np.add.at(out, np.ix_(idx, idx, idx), c)
+    return out
+
+
+def bispectrum(x, M: int, nfft: int, window: str = "parzen",
+               centered: bool = True):
+    """(c3 on the hexagon, B = 2D DFT of the windowed c3 on an N x N grid).
+
+    B(k1,k2) = sum_w W3(w) c3(w) exp(-2 pi i (k1 w1 + k2 w2)/N), unshifted
+    frequency order, no normalisation.
+    """
+    c = c3_hexagon(x, M, centered)
+    cw = c * window3(M, window)
+    B = np.fft.fft2(place_circular(cw, M, nfft))
+    return c, B
+
+
+def trispectrum(x, M: int, nfft: int, window: str = "parzen",
+                centered: bool = True):
+    """(c4 on its support, T = 3D DFT of the windowed c4 on an N^3 grid)."""
+    c = c4_support(x, M, centered)
+    cw = c * window4(M, window)
+    T = np.fft.fftn(place_circular(cw, M, nfft))
+    return c, T
+
+
+# --------------------------------------------------------------------------
+# Principal domain (Algorithm DBS step 4) and the matching loss.
+# --------------------------------------------------------------------------
+def pd_indices(N: int):
+    """(k1, k2) of the principal domain 0 <= k2 <= k1, k1 + k2 < N/2,
+    in row-major (k1, then k2) order."""
+    k1, k2 = [], []
+    for a in range(N):
+        for b in range(a + 1):
+            if 2 * (a + b) < N:
+                k1.append(a)
+                k2.append(b)
+    return np.asarray(k1, dtype=np.int64), np.asarray(k2, dtype=np.int64)

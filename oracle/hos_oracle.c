@@ -1,0 +1,157 @@
+/*
+ * hos_oracle.c -- plain FP64 reference for the sample cumulants behind the
+ * smoothed bispectrum / trispectrum estimators.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library; the product path never
+ * calls it.
+ *
+ * Every function below is the definition written out as a brute-force sum:
+ * each lag is computed on its own, in natural index order, with no use of
+ * the cumulant symmetries (so symmetry checks on its output are not
+ * circular) and no blocking or reordering.  OpenMP only distributes
+ * independent lags over threads; the arithmetic of one lag is sequential.
+ *
+ * Definitions (paper, Section 1 "Problem Statement": the k-th order moment
+ * as the expectation of a product of k lagged samples; cumulants as
+ * functions of the moments; ensemble averages replaced by time averages):
+ *
+ *   m3(w1,w2)    = (1/n) sum_t x_t x_{t+w1} x_{t+w2}
+ *   m4(t1,t2,t3) = (1/n) sum_t x_t x_{t+t1} x_{t+t2} x_{t+t3}
+ *   c2(d)        = (1/n) sum_t x_t x_{t+d}
+ *
+ * where each sum runs over the t for which every index lies in [0, n)
+ * (the same as zero padding outside the record) and x is the mean-removed
+ * series, so c3 = m3.  The 1/n normalisation (a biased estimator) and the
+ * index range are readings the paper leaves open.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+
+static int64_t imax3(int64_t a, int64_t b, int64_t c)
+{
+    int64_t m = a > b ? a : b;
+    return m > c ? m : c;
+}
+
+static int64_t imin3(int64_t a, int64_t b, int64_t c)
+{
+    int64_t m = a < b ? a : b;
+    return m < c ? m : c;
+}
+
+/* Plain FP64 mean removal: out_t = x_t - (sum_t x_t)/n, summed in order. */
+void or_center(const double *x, int64_t n, double *out)
+{
+    double s = 0.0;
+    for (int64_t t = 0; t < n; ++t)
+        s += x[t];
+    double mu = s / (double)n;
+    for (int64_t t = 0; t < n; ++t)
+        out[t] = x[t] - mu;
+}
+
+/* Third-order moment of x at one lag pair, sum over the valid t range. */
+static double m3_one(const double *x, int64_t n, int64_t w1, int64_t w2)
+{
+    int64_t lo = -imin3(0, w1, w2);         /* all of t, t+w1, t+w2 >= 0 */
+    int64_t hi = n - 1 - imax3(0, w1, w2);  /* all of them <= n-1        */
+    double s = 0.0;
+    for (int64_t t = lo; t <= hi; ++t)
+        s += x[t] * x[t + w1] * x[t + w2];
+    return s / (double)n;
+}
+
+/* c3 at `count` arbitrary lag pairs (w1[k], w2[k]). */
+void or_c3_at(const double *x, int64_t n, const int32_t *w1, const int32_t *w2,
+              int64_t count, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < count; ++k)
+        out[k] = m3_one(x, n, w1[k], w2[k]);
+}
+
+/* c3 over the full square |w1|,|w2| <= M, row-major with lag w at w+M. */
+void or_c3_square(const double *x, int64_t n, int32_t M, double *out)
+{
+    int64_t side = 2 * (int64_t)M + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < side; ++r)
+        for (int64_t c = 0; c < side; ++c)
+            out[r * side + c] = m3_one(x, n, r - M, c - M);
+}
+
+/* Second-order moment (= autocovariance of the centred series) at lag d. */
+static double c2_one(const double *x, int64_t n, int64_t d)
+{
+    if (d < 0)
+        d = -d;
+    double s = 0.0;
+    for (int64_t t = 0; t + d <= n - 1; ++t)
+        s += x[t] * x[t + d];
+    return s / (double)n;
+}
+
+/* c2(d) for d = 0..M. */
+void or_c2(const double *x, int64_t n, int32_t M, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t d = 0; d <= M; ++d)
+        out[d] = c2_one(x, n, d);
+}
+
+static double m4_one(const double *x, int64_t n, int64_t t1, int64_t t2, int64_t t3)
+{
+    int64_t mn = imin3(0, t1, t2 < t3 ? t2 : t3);  /* smallest of 0,t1,t2,t3 */
+    int64_t mx = imax3(0, t1, t2 > t3 ? t2 : t3);  /* largest of 0,t1,t2,t3  */
+    int64_t lo = -mn, hi = n - 1 - mx;
+    double s = 0.0;
+    for (int64_t t = lo; t <= hi; ++t)
+        s += x[t] * x[t + t1] * x[t + t2] * x[t + t3];
+    return s / (double)n;
+}
+
+/* Fourth-order moment at `count` lag triples. */
+void or_m4_at(const double *x, int64_t n, const int32_t *t1, const int32_t *t2,
+              const int32_t *t3, int64_t count, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < count; ++k)
+        out[k] = m4_one(x, n, t1[k], t2[k], t3[k]);
+}
+
+/*
+ * Fourth-order cumulant of the zero-mean series at one lag triple: the
+ * fourth moment minus the three pairings of second-order moments,
+ *   c4 = m4(t1,t2,t3) - c2(t1) c2(t3-t2) - c2(t2) c2(t3-t1) - c2(t3) c2(t2-t1),
+ * the moment-to-cumulant relation for four zero-mean variables
+ * (X0,X1,X2,X3) = (x_t, x_{t+t1}, x_{t+t2}, x_{t+t3}).
+ */
+static double c4_one(const double *x, int64_t n, int64_t t1, int64_t t2, int64_t t3)
+{
+    double m4 = m4_one(x, n, t1, t2, t3);
+    return m4 - c2_one(x, n, t1) * c2_one(x, n, t3 - t2)
+              - c2_one(x, n, t2) * c2_one(x, n, t3 - t1)
+              - c2_one(x, n, t3) * c2_one(x, n, t2 - t1);
+}
+
+void or_c4_at(const double *x, int64_t n, const int32_t *t1, const int32_t *t2,
+              const int32_t *t3, int64_t count, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < count; ++k)
+        out[k] = c4_one(x, n, t1[k], t2[k], t3[k]);
+}
+
+/* c4 over the full cube |t1|,|t2|,|t3| <= M, index ((t1+M)*S + t2+M)*S + t3+M. */
+void or_c4_cube(const double *x, int64_t n, int32_t M, double *out)
+{
+    int64_t S = 2 * (int64_t)M + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < S * S; ++r) {
+        int64_t a = r / S, b = r % S;
+        for (int64_t c = 0; c < S; ++c)
+            out[r * S + c] = c4_one(x, n, a - M, b - M, c - M);
+    }
+}

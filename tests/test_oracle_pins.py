@@ -1,0 +1,344 @@
+"""Pins of the FP64 oracle to facts outside itself.
+
+Each test checks the oracle against something the mathematics or the paper
+fixes -- a closed form, an exact identity with a textbook FFT, a symmetry the
+brute-force code does not use, a hand-worked value, or a population cumulant
+of a process with a known answer -- chosen so that a dropped term, a wrong
+sign or index, or a transposed operand in the oracle fails one of them.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load_gold(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([float(v) for v in line.split()])
+    return np.asarray(rows)
+
+
+# ---------------------------------------------------------------- c3 ----
+def test_c3_matches_literal_loops_tiny():
+    """C core vs an independently spelled pure-Python loop (n = 23, M = 6)."""
+    x = synth.iid_exp_centered(23, 11)
+    xt = brute.center(list(x))
+    c = oracle.c3_square(x, 6)
+    for w1 in range(-6, 7):
+        for w2 in range(-6, 7):
+            assert abs(c[w1 + 6, w2 + 6] - brute.c3(xt, w1, w2)) < 1e-14
+
+
+def test_c3_constant_uncentered_closed_form():
+    """x_t = a: c3(w) = a^3 (n - span(w)) / n, all lags of the square."""
+    n, M, a = 37, 9, 1.75
+    c = oracle.c3_square(np.full(n, a), M, centered=False)
+    expect = a ** 3 * (n - oracle.span3(M)) / n
+    np.testing.assert_allclose(c, expect, rtol=0, atol=1e-13)
+
+
+def test_c3_constant_centered_is_zero():
+    c = oracle.c3_square(np.full(50, 3.25), 7)
+    assert np.max(np.abs(c)) == 0.0
+
+
+def test_c3_impulse_uncentered():
+    """x = A delta_{t0}: c3 = A^3/n at the origin only; B is flat."""
+    n, M, A, t0 = 40, 8, 2.0, 17
+    x = np.zeros(n)
+    x[t0] = A
+    c = oracle.c3_square(x, M, centered=False)
+    expect = np.zeros_like(c)
+    expect[M, M] = A ** 3 / n
+    np.testing.assert_allclose(c, expect, atol=1e-15)
+    _, B = oracle.bispectrum(x, M, 2 * M, "parzen", centered=False)
+    np.testing.assert_allclose(B, np.full_like(B, A ** 3 / n), atol=1e-14)
+
+
+def _impulse_centered_closed_form(n, A, t0, w1, w2):
+    """x~_t = q + p delta_{t,t0} with p = A, q = -A/n.  Expand the product of
+    the three factors over the subsets S of factor positions taking p:
+    S empty contributes q^3 |I(w)|; otherwise every offset in S must be equal
+    and t = t0 - offset must lie in the valid range I(w)."""
+    offs = (0, w1, w2)
+    lo = -min(offs)
+    hi = n - 1 - max(offs)
+    count = max(0, hi - lo + 1)
+    p, q = A, -A / n
+    total = 0.0
+    for r in range(4):
+        for S in itertools.combinations(range(3), r):
+            coef = p ** len(S) * q ** (3 - len(S))
+            if not S:
+                total += coef * count
+                continue
+            o = {offs[k] for k in S}
+            if len(o) != 1:
+                continue
+            t = t0 - o.pop()
+            if lo <= t <= hi:
+                total += coef
+    return total / n
+
+
+def test_c3_impulse_centered_closed_form():
+    n, M, A, t0 = 29, 7, 1.5, 10
+    x = np.zeros(n)
+    x[t0] = A
+    c = oracle.c3_square(x, M)
+    for w1 in range(-M, M + 1):
+        for w2 in range(-M, M + 1):
+            e = _impulse_centered_closed_form(n, A, t0, w1, w2)
+            assert abs(c[w1 + M, w2 + M] - e) < 1e-14, (w1, w2)
+
+
+def test_c3_six_fold_symmetry():
+    """c3(w1,w2) = c3(w2,w1) = c3(-w1,w2-w1) = c3(w1-w2,-w2) = c3(-w2,w1-w2)
+    = c3(w2-w1,-w1), checked where every image stays inside the square."""
+    M = 10
+    x = synth.quadratic_process(300, 5)
+    c = oracle.c3_square(x, M)
+    f = lambda a, b: c[a + M, b + M]
+    for w1 in range(-M, M + 1):
+        for w2 in range(-M, M + 1):
+            imgs = [(w2, w1), (-w1, w2 - w1), (w1 - w2, -w2), (-w2, w1 - w2),
+                    (w2 - w1, -w1)]
+            for a, b in imgs:
+                if abs(a) <= M and abs(b) <= M:
+                    assert abs(f(a, b) - f(w1, w2)) < 1e-15
+
+
+def test_c3_all_lag_sum_is_cube_of_sum():
+    """sum over all lags |w| <= n-1 of n c3(w) = (sum_t x_t)^3."""
+    x = synth.iid_gauss(12, 3) + 0.3
+    n = x.size
+    c = oracle.c3_square(x, n - 1, centered=False)
+    assert abs(c.sum() * n - x.sum() ** 3) < 1e-11
+    cc = oracle.c3_square(x, n - 1)  # centred: the cube of 0
+    assert abs(cc.sum()) < 1e-12
+
+
+@pytest.mark.parametrize("N", [19, 24, 7])
+def test_direct_equals_indirect_bispectrum(N):
+    """No window and M = n-1: the lag-domain DFT equals (1/n) X(k1) X(k2)
+    X*(k1+k2) with X the N-point FFT of the centred record -- Algorithm DBS
+    step 4 with one part and the conjugate on the third factor.  N = 7 checks
+    the folding of aliased lags."""
+    x = synth.iid_exp_centered(10, 21)
+    n = x.size
+    _, B = oracle.bispectrum(x, n - 1, N, window="none")
+    xt = x - x.mean()
+    if N >= n:
+        X = np.fft.fft(xt, N)
+    else:  # fold the record onto the N-grid before the FFT
+        X = np.fft.fft(np.bincount(np.arange(n) % N, weights=xt, minlength=N))
+    k = np.arange(N)
+    ref = X[:, None] * X[None, :] * np.conj(X[(k[:, None] + k[None, :]) % N]) / n
+    np.testing.assert_allclose(B, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_bispectrum_symmetries():
+    """B(k1,k2) = B(k2,k1) = conj B(-k1,-k2) = B(k1, -k1-k2) (mod N)."""
+    M, N = 12, 24
+    x = synth.quadratic_process(400, 8)
+    _, B = oracle.bispectrum(x, M, N)
+    k = np.arange(N)
+    K1, K2 = np.meshgrid(k, k, indexing="ij")
+    tol = 1e-13 * np.abs(B).max()
+    np.testing.assert_allclose(B, B.T, atol=tol)
+    np.testing.assert_allclose(B, np.conj(B[(-K1) % N, (-K2) % N]), atol=tol)
+    np.testing.assert_allclose(B, B[K1, (-K1 - K2) % N], atol=tol)
+
+
+# ---------------------------------------------------------- window ----
+def test_parzen_hand_values():
+    g = _load_gold("parzen_points.txt")
+    for m, L, d in g:
+        assert oracle.parzen(m, int(L)) == pytest.approx(d, abs=1e-15)
+
+
+def test_window3_symmetry_and_support():
+    M = 16
+    W = oracle.window3(M)
+    c = W[M, M]
+    assert c == 1.0
+    f = lambda a, b: W[a + M, b + M]
+    for w1 in range(-M, M + 1):
+        for w2 in range(-M, M + 1):
+            if abs(w1 - w2) <= M:
+                assert abs(f(w2, w1) - f(w1, w2)) < 1e-15
+                assert abs(f(-w1, w2 - w1) - f(w1, w2)) < 1e-15
+            else:
+                assert f(w1, w2) == 0.0
+
+
+# ---------------------------------------------------- c2 / c4 -----
+def test_c4_matches_literal_loops_tiny():
+    x = synth.iid_exp_centered(17, 4)
+    xt = brute.center(list(x))
+    M = 3
+    c = oracle.c4_cube(x, M)
+    for t in itertools.product(range(-M, M + 1), repeat=3):
+        i = tuple(v + M for v in t)
+        assert abs(c[i] - brute.c4(xt, *t)) < 1e-13
+
+
+def test_c2_direct_equals_indirect():
+    """sum_d c2(d) e^{-i w k d} over |d| <= n-1 equals |X(k)|^2 / n."""
+    x = synth.iid_gauss(13, 6)
+    n = x.size
+    c = oracle.c2(x, n - 1)
+    N = 32
+    d = np.arange(-(n - 1), n)
+    full = np.concatenate([c[:0:-1], c])
+    k = np.arange(N)[:, None]
+    S = (full[None, :] * np.exp(-2j * np.pi * k * d[None, :] / N)).sum(1)
+    X = np.fft.fft(x - x.mean(), N)
+    np.testing.assert_allclose(S, np.abs(X) ** 2 / n, atol=1e-12)
+
+
+def test_m4_direct_equals_indirect():
+    """3D DFT of m4 over all lags equals (1/n) X(k1)X(k2)X(k3)X*(k1+k2+k3)."""
+    x = synth.iid_exp_centered(7, 9)
+    n = x.size
+    M = n - 1
+    t = np.arange(-M, M + 1)
+    T1, T2, T3 = np.meshgrid(t, t, t, indexing="ij")
+    m4 = oracle.m4_at(x, T1, T2, T3).reshape(T1.shape)
+    N = 13
+    F = np.fft.fftn(oracle.place_circular(m4, M, N))
+    X = np.fft.fft(x - x.mean(), N)
+    k = np.arange(N)
+    K1, K2, K3 = np.meshgrid(k, k, k, indexing="ij")
+    ref = X[K1] * X[K2] * X[K3] * np.conj(X[(K1 + K2 + K3) % N]) / n
+    np.testing.assert_allclose(F, ref, atol=1e-12 * np.abs(ref).max())
+
+
+def _pairings(pts):
+    """Number of ways the 4 points split into two pairs of equal times,
+    counting only the three pairings the c2 corrections use."""
+    p0, p1, p2, p3 = pts
+    return int(p0 == p1 and p2 == p3) + int(p0 == p2 and p1 == p3) + \
+        int(p0 == p3 and p1 == p2)
+
+
+def test_c4_impulse_uncentered_closed_form():
+    """x = A delta_{t0}: m4 = A^4/n at the origin, c2(d) = A^2/n at d = 0, so
+    c4(t) = A^4/n [t = 0] - A^4/n^2 (number of equal-time pairings)."""
+    n, M, A, t0 = 20, 4, 1.3, 9
+    x = np.zeros(n)
+    x[t0] = A
+    c = oracle.c4_cube(x, M, centered=False)
+    for t in itertools.product(range(-M, M + 1), repeat=3):
+        e = -A ** 4 / n ** 2 * _pairings((0,) + t)
+        if t == (0, 0, 0):
+            e += A ** 4 / n
+        assert abs(c[tuple(v + M for v in t)] - e) < 1e-15, t
+
+
+def test_c4_24_fold_symmetry():
+    M = 4
+    x = synth.cubic_process(120, 2)
+    c = oracle.c4_cube(x, M)
+    f = lambda t: c[t[0] + M, t[1] + M, t[2] + M]
+    for t in itertools.product(range(-M, M + 1), repeat=3):
+        pts = (0,) + t
+        for origin in pts:
+            rest = list(pts)
+            rest.remove(origin)
+            for perm in itertools.permutations(rest):
+                img = tuple(p - origin for p in perm)
+                if max(abs(v) for v in img) <= M:
+                    assert abs(f(img) - f(t)) < 1e-15
+
+
+# -------------------------------------------- population cumulants --
+def _batch_se(prod, nb=64):
+    """Standard error of the mean of a weakly dependent series (batch means)."""
+    m = prod[: prod.size // nb * nb].reshape(nb, -1).mean(1)
+    return m.std(ddof=1) / np.sqrt(nb)
+
+
+def test_exp_third_and_fourth_cumulant():
+    """Centred Exp(1): kappa3 = 2, kappa4 = 6; zero off the origin."""
+    n = 1 << 18
+    x = synth.iid_exp_centered(n, 77)
+    xt = oracle.center(x)
+    c3 = oracle.c3_at(x, [0, 1, 2, 0], [0, 1, 0, 3])
+    se = _batch_se(xt ** 3)
+    assert abs(c3[0] - 2.0) < 6 * se
+    for v in c3[1:]:
+        assert abs(v) < 6 * se
+    c4 = oracle.c4_at(x, [0, 1], [0, 2], [0, 3])
+    se4 = _batch_se(xt ** 4)
+    assert abs(c4[0] - 6.0) < 6 * se4
+    assert abs(c4[1]) < 6 * se4
+
+
+def test_gaussian_cumulants_vanish():
+    """Gaussian input: c3 = c4 = 0 (Section 1, the Gaussianity test); the
+    fourth moment at the origin (about 3) must cancel against the c2 terms."""
+    n = 1 << 18
+    x = synth.iid_gauss(n, 99)
+    xt = oracle.center(x)
+    c3 = oracle.c3_at(x, [0, 1, 3], [0, 2, -1])
+    se = _batch_se(xt ** 3)
+    assert np.all(np.abs(c3) < 6 * se)
+    c4 = oracle.c4_at(x, [0, 1, 0], [0, 1, 2], [0, 1, 0])
+    se4 = _batch_se(xt ** 4)
+    assert np.all(np.abs(c4) < 6 * se4)
+
+
+def test_quadratic_process_c3():
+    g = _load_gold("quadratic_process_c3.txt")
+    n = 1 << 18
+    x = synth.quadratic_process(n, 1234)
+    xt = oracle.center(x)
+    c = oracle.c3_at(x, g[:, 0], g[:, 1])
+    for (w1, w2, true), v in zip(g, c):
+        w1, w2 = int(w1), int(w2)
+        lo = max(0, -w1, -w2)
+        hi = n - max(0, w1, w2)
+        se = _batch_se(xt[lo:hi] * xt[lo + w1:hi + w1] * xt[lo + w2:hi + w2])
+        assert abs(v - true) < 6 * se + 1e-12, (w1, w2, v, true, se)
+
+
+def test_cubic_process_c4():
+    g = _load_gold("cubic_process_c4.txt")
+    n = 1 << 18
+    x = synth.cubic_process(n, 4321)
+    xt = oracle.center(x)
+    c = oracle.c4_at(x, g[:, 0], g[:, 1], g[:, 2])
+    for (t1, t2, t3, true), v in zip(g, c):
+        t = (int(t1), int(t2), int(t3))
+        lo = max(0, -min(t))
+        hi = n - max(0, max(t))
+        prod = xt[lo:hi].copy()
+        for s in t:
+            prod = prod * xt[lo + s:hi + s]
+        se = _batch_se(prod)
+        assert abs(v - true) < 7 * se + 1e-12, (t, v, true, se)
+
+
+# ------------------------------------------------ principal domain --
+def test_principal_domain_count_and_shape():
+    """0 <= k2 <= k1, k1 + k2 < N/2: with h = N/2 even there are
+    h^2/4 + h/2 points (16,512 at N = 512)."""
+    for N in (8, 12, 128, 512):
+        k1, k2 = oracle.pd_indices(N)
+        h = N // 2
+        if h % 2 == 0:
+            assert k1.size == h * h // 4 + h // 2
+        assert np.all(k2 <= k1) and np.all(k1 + k2 < N / 2) and np.all(k2 >= 0)
+    assert oracle.pd_indices(512)[0].size == 16512
