@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the bispectrum path on one MI355X.
+
+Workload: one float32 series of n = 2^20 samples from the quadratic process
+x_t = e_t + 0.5 e_{t-1} e_{t-2} (seeded), maximum lag M = 512, Parzen lag
+window, 1024 x 1024 DFT.  A step is one full call of hos_bispectrum: mean
+removal, operand preparation, the c3 contraction, the partial reduction,
+mirroring + window and the 2D DFT, with the input already resident on the
+GPU.  Metric: cumulant lag-sums per second, n (2M+1)^2 / step time.
+
+Reported for the split-precision FP16 path (the headline ``value``), the
+FP32 path and the split BF16 path, each with its normwise error against the
+FP64 oracle on sampled lags; ``roofline`` is for the dominant kernel (the
+contraction), timed with HIP events on the stream it runs on; the oracle is
+timed on the host cores on a bounded sample of lags (``cpu_baseline``).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cumulant lag-sums/s (n·(2M+1)^2/s), split-prec vs FP32 at ≤1e-5 rel err"
+PEAK = {"fp32": 157.3e12, "split_fp16": 2.5166e15, "split_bf16": 2.5166e15}
+DTYPE = {"fp32": "f32", "split_fp16": "f16", "split_bf16": "bf16"}
+TOL = {"fp32": 1e-6, "split_fp16": 1e-5, "split_bf16": 1e-5}
+
+
+def sample_lags(M, k, seed=11):
+    rng = np.random.default_rng(seed)
+    w1 = rng.integers(-M, M + 1, k)
+    w2 = np.clip(w1 + rng.integers(-M, M + 1, k), -M, M)
+    orbit = np.array([[1, 2], [2, 1], [-1, 1], [1, -1], [-2, -1], [-1, -2], [0, 0]])
+    return np.concatenate([orbit[:, 0], w1]), np.concatenate([orbit[:, 1], w2])
+
+
+def run_path(hos, torch, xt, M, N, path, steps, warmup):
+    n = xt.numel()
+    pth = hos.PATHS[path]
+    wsb = hos.hos_bispectrum_workspace(n, M, N, pth)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    c3 = torch.empty((2 * M + 1, 2 * M + 1), dtype=torch.float64, device="cuda")
+    B = torch.empty((N, N), dtype=torch.complex128, device="cuda")
+    stream = hos._stream_handle(xt.device)
+    args = (xt.data_ptr(), hos.HOS_F32, n, M, hos.HOS_WIN_PARZEN, N, pth, 0,
+            c3.data_ptr(), B.data_ptr(), ws.data_ptr(), wsb, stream)
+
+    def call():
+        st = hos.hos_bispectrum(*args)
+        if st != hos.HOS_OK:
+            raise hos.HosError(st, "hos_bispectrum")
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # per-stage durations: HIP events recorded by the library on `stream`
+    stages = []
+    for _ in range(5):
+        st, d = hos.hos_bispectrum_timed(*args)
+        if st != hos.HOS_OK:
+            raise hos.HosError(st, "hos_bispectrum_timed")
+        stages.append(d)
+    stage_ms = {k: float(np.mean([d[k] for d in stages])) for k in stages[0]}
+    return ms, stage_ms, c3.cpu().numpy()
+
+
+def cpu_baseline(oracle, x, M, seconds):
+    """Oracle c3 (FP64 brute force, OpenMP) on a bounded sample of lags of
+    the same series; rate in lag-sums/s."""
+    n = x.size
+    t0 = time.perf_counter()
+    w1, w2 = sample_lags(M, 32, seed=3)
+    oracle.c3_at(x, w1, w2)
+    t_probe = time.perf_counter() - t0
+    per_lag = t_probe / w1.size
+    k = int(max(32, min(200000, seconds / max(per_lag, 1e-9))))
+    w1, w2 = sample_lags(M, k, seed=4)
+    t0 = time.perf_counter()
+    oracle.c3_at(x, w1, w2)
+    t = time.perf_counter() - t0
+    return {"value": w1.size * n / t, "unit": "lag-sums/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))),
+            "kind": "oracle",
+            "sample": "%d lags of the hexagon x n=%d samples, FP64 brute-force c3 "
+                      "(%.1f s)" % (w1.size, n, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--paths", default="split_fp16,fp32,split_bf16")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the contraction would shard)", file=sys.stderr)
+        sys.exit(2)
+    if "OMP_NUM_THREADS" not in os.environ:
+        os.environ["OMP_NUM_THREADS"] = str(len(os.sched_getaffinity(0)))
+
+    import torch
+
+    import oracle
+    import paper_1805_11775_amd as hos
+    import synth
+
+    x, cfg = synth.workload_long_bispectrum()
+    M, N = cfg["M"], cfg["nfft"]
+    n = x.size
+    xt = torch.from_numpy(x).cuda()
+    lagsums = n * (2 * M + 1) ** 2
+    flops = 2.0 * n * (M + 1) * (M + 2) / 2  # one MAC per (i, a, b) of F
+
+    w1, w2 = sample_lags(M, 200)
+    ref = oracle.c3_at(x, w1, w2)
+    ref[np.abs(w1 - w2) > M] = 0.0
+
+    paths = {}
+    for path in args.paths.split(","):
+        print("bench: path %s" % path, file=sys.stderr, flush=True)
+        ms, stage_ms, c3 = run_path(hos, torch, xt, M, N, path, args.steps, args.warmup)
+        err = float(np.max(np.abs(c3[w1 + M, w2 + M] - ref)) / np.max(np.abs(ref)))
+        t_k = stage_ms["contract"] * 1e-3
+        paths[path] = {
+            "ms_per_step": ms, "value": lagsums / (ms * 1e-3), "rel_err": err,
+            "within_tol": err <= TOL[path], "stage_ms": stage_ms,
+            "contract_tflops": flops / t_k / 1e12,
+            "contract_frac": flops / t_k / PEAK[path],
+            "issued_mfma_frac": (3 if path != "fp32" else 1) * flops / t_k / PEAK[path],
+        }
+        print("bench: %s %.3f ms/step, contract %.3f ms, err %.2e" %
+              (path, ms, stage_ms["contract"], err), file=sys.stderr, flush=True)
+
+    head = "split_fp16" if "split_fp16" in paths else next(iter(paths))
+    hp = paths[head]
+    t_k = hp["stage_ms"]["contract"] * 1e-3
+    rec = {
+        "metric": METRIC, "value": hp["value"], "unit": "lag-sums/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": hp["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[head], "data": "synthetic",
+        "config": {"workload": "bispectrum of one n=2^20 float32 quadratic-process series "
+                               "(x_t = e_t + 0.5 e_{t-1} e_{t-2}), M=512, Parzen window, "
+                               "1024x1024 DFT",
+                   "n": n, "M": M, "nfft": N, "path": head},
+        "roofline": {"bound": "mfma", "kernel": "k_c3_contract", "achieved": flops / t_k / 1e12,
+                     "peak": PEAK[head] / 1e12, "unit": "TFLOP/s",
+                     "frac": flops / t_k / PEAK[head], "traffic": None,
+                     "flops_per_launch": flops, "avg_launch_ms": hp["stage_ms"]["contract"]},
+        "paths": paths,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(oracle, x, M, args.cpu_seconds)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

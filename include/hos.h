@@ -1,0 +1,173 @@
+/*
+ * hos.h -- C ABI of the MI355X (gfx950) higher-order-spectra library.
+ *
+ * The library estimates the smoothed sample bispectrum and trispectrum of a
+ * finite real series (arXiv:1805.11775, Section 1 "Problem Statement": from
+ * X(1..n), compute smoothed sample bispectrum and trispectrum that are
+ * consistent estimates of the true higher-order spectra).  It follows the
+ * indirect route the paper names in Section 1 ("Direct Method for HOS"):
+ * sample cumulant over all lags |w| <= M, lag window, then the DFT.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Memory.    Every array argument is DEVICE memory owned by the caller unless
+ *            the parameter says "host".  The library allocates nothing on the
+ *            call path; scratch space is the caller's workspace `ws`
+ *            (query its size first, 256-byte aligned).  No pointer is kept
+ *            after the call returns.
+ * Streams.   All work is enqueued on `stream` (NULL = the default stream) and
+ *            the call returns without waiting for it.  Results are ready
+ *            when the stream is synchronised.
+ * Errors.    Every function returns an hos_status code; no exception or
+ *            abort crosses the ABI.  Arguments are validated on the host,
+ *            before any HIP call, so a rejected call touches no device state.
+ *            HOS_EDEVICE reports a HIP launch failure.
+ * Estimator. x~_t = x_t - mean(x) (FP64 mean; skipped with HOS_NO_CENTER),
+ *            c3(w1,w2) = (1/n) sum_t x~_t x~_{t+w1} x~_{t+w2} with the sum
+ *            over the t where every index lies in [0,n) (zero padding).
+ *            Internally x~ is multiplied by an exact power of two chosen
+ *            from max|x~| and divided out again, so results do not depend
+ *            on the input scale.
+ * Layouts.   c3: (2M+1)^2 row-major float64, lag (w1,w2) at
+ *            (w1+M)*(2M+1) + (w2+M); lags with |w1-w2| > M are 0.
+ *            B: nfft x nfft interleaved complex128, row-major, frequency
+ *            (k1,k2) at k1*nfft + k2, unshifted.
+ *            B(k1,k2) = sum_w W(w) c3(w) exp(-2 pi i (k1 w1 + k2 w2)/nfft),
+ *            unnormalised, with the sign of the DFT in Algorithm DBS step 3.
+ * Threading. Calls are re-entrant; concurrent calls must use distinct
+ *            workspaces.
+ */
+#ifndef HOS_H
+#define HOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque HIP stream handle (the same type as in the HIP runtime headers). */
+typedef struct ihipStream_t *hipStream_t;
+
+#define HOS_VERSION 10000 /* 1.0.0 */
+
+/* Status codes. */
+typedef enum hos_status {
+    HOS_OK = 0,
+    HOS_EINVAL = -1,       /* an argument is out of range, null or misaligned */
+    HOS_EWORKSPACE = -2,   /* ws_bytes is smaller than the workspace query   */
+    HOS_EDEVICE = -3,      /* a HIP call or kernel launch failed              */
+    HOS_ENODEVICE = -4,    /* no usable gfx950 device is visible              */
+    HOS_EUNSUPPORTED = -5  /* valid request this build does not implement     */
+} hos_status;
+
+/* Element type of the input series. */
+typedef enum hos_dtype { HOS_F32 = 0, HOS_F64 = 1 } hos_dtype;
+
+/* Lag window applied before the DFT.  The paper smooths in frequency with
+ * an M3 x M3 box (Algorithm DBS step 5); this library smooths in the lag
+ * domain instead.  HOS_WIN_PARZEN uses the Parzen window d(m) with scale
+ * L = M: W3(w1,w2) = d(w1) d(w2) d(w1-w2) for the bispectrum and the
+ * product of d over the six pairwise differences of {0,t1,t2,t3} for the
+ * trispectrum. */
+typedef enum hos_window { HOS_WIN_NONE = 0, HOS_WIN_PARZEN = 1 } hos_window;
+
+/* Arithmetic of the cumulant contraction.  Moments, scaling, cross-tile
+ * reductions, windows and DFTs are FP64 on every path.
+ *   HOS_PATH_FP32        FP32 matrix-core products and FP32 accumulation;
+ *   HOS_PATH_SPLIT_FP16  each operand split into FP16 hi + lo, three
+ *                        FP16 products (hi*hi + hi*lo + lo*hi), FP32
+ *                        accumulation;
+ *   HOS_PATH_SPLIT_BF16  the same with BF16 halves.
+ * FP32 partial sums are flushed into FP64 every 512 samples. */
+typedef enum hos_path {
+    HOS_PATH_FP32 = 0,
+    HOS_PATH_SPLIT_FP16 = 1,
+    HOS_PATH_SPLIT_BF16 = 2
+} hos_path;
+
+/* Flags. */
+#define HOS_NO_CENTER 1u /* use x as given (no mean removal); for tests */
+
+/* Human-readable text for a status code (static storage). */
+const char *hos_strerror(int status);
+
+/* HOS_VERSION of the loaded library. */
+int hos_version(void);
+
+/* HOS_OK if a gfx950 device is current, else HOS_ENODEVICE / HOS_EDEVICE. */
+int hos_device_check(void);
+
+/*
+ * Workspace size for hos_bispectrum.
+ *   n      series length, n >= 2.
+ *   M      maximum lag, 0 <= M < n.
+ *   nfft   DFT size per axis, or 0 when no spectrum is requested.
+ *   path   hos_path.
+ *   flags  HOS_* flags.
+ *   bytes  (host) receives the size in bytes.
+ * Returns HOS_EINVAL on a bad argument (same rules as hos_bispectrum).
+ */
+int hos_bispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
+                             uint32_t flags, size_t *bytes);
+
+/*
+ * Third-order cumulant and smoothed bispectrum of one series
+ * (Section 1 "Problem Statement"; indirect method).
+ *   x        device, n elements of dtype (HOS_F32 / HOS_F64), 4/8-byte aligned.
+ *   M        maximum lag, 0 <= M < n.
+ *   window   hos_window.
+ *   nfft     DFT size per axis, 2 <= nfft <= 4096, nfft = 2^a 3^b 5^c;
+ *            nfft >= 2M with HOS_WIN_PARZEN (the window vanishes at |w| = M),
+ *            nfft >= 2M+1 with HOS_WIN_NONE; ignored when B is NULL.
+ *   path     hos_path.
+ *   c3       device, (2M+1)^2 float64 (layout above), or NULL.
+ *   B        device, nfft^2 complex128 (layout above), or NULL.
+ *   ws       device workspace of at least hos_bispectrum_workspace() bytes,
+ *            256-byte aligned; its contents on entry do not matter.
+ * At least one of c3 and B must be non-NULL.
+ */
+int hos_bispectrum(const void *x, int32_t dtype, int64_t n, int32_t M,
+                   int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                   double *c3, double *B, void *ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/*
+ * hos_bispectrum with per-stage timing, for profiling.  Same arguments and
+ * results; additionally records HIP events around each stage on `stream`,
+ * WAITS for the stream, and writes the elapsed milliseconds to stage_ms
+ * (host, 8 floats): [0] mean/range pass, [1] operand preparation,
+ * [2] contraction, [3] leftover diagonal sums, [4] partial reduction,
+ * [5] mirror + window (+ twiddles), [6] DFT, [7] total.  Creates and
+ * destroys its own events (no device memory is allocated).
+ */
+int hos_bispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M,
+                         int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                         double *c3, double *B, void *ws, size_t ws_bytes,
+                         hipStream_t stream, float *stage_ms);
+
+/*
+ * Host-only introspection of the contraction plan (no HIP call, no device
+ * needed).  info (host) receives, in order: persistent workgroups G,
+ * partial slots per workgroup, tile rows, chunks per tile, 32-blocks per
+ * wave side, 32-block rows, leftover diagonal sums, padded length, total
+ * schedule cost, workspace bytes.  ninfo >= 10.  HOS_EINVAL on bad sizes.
+ */
+int hos_c3_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo);
+
+/*
+ * Host-only replay of the contraction's work split, for testing without a
+ * GPU.  For every (tile, chunk) pair k in schedule order (cap >= tiles x
+ * chunks, all arrays host): owner[k] = workgroup that processes it (-1 none,
+ * -2 more than one), slot[k] = partial slot it writes (-3 out of range),
+ * rslot[k] = slot the reduction reads for it (-4 inconsistent owner).
+ */
+int hos_c3_schedule(int64_t n, int32_t M, int32_t path, int64_t *owner, int64_t *slot,
+                    int64_t *rslot, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOS_H */

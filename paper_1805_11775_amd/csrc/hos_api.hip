@@ -1,0 +1,339 @@
+// hos_api.hip -- C ABI entry points: validation, planning, launch order.
+//
+// Every argument is validated on the host before the first HIP call, so a
+// rejected call leaves the device untouched.  The library keeps no state
+// between calls except a per-device "is this a gfx950" flag.
+#include <string.h>
+
+#include <mutex>
+
+#include "hos_internal.h"
+
+namespace hos {
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
+{
+    memset(&p, 0, sizeof(p));
+    p.n = n;
+    p.M = M;
+    p.path = path;
+    p.WT = M >= 128 ? 2 : 1;
+    p.TS = 64 * p.WT;
+    p.NBR = (M + 31) / 32;
+    p.nleft = 1 + M / 32;
+    const int64_t C = (n + KC - 1) / KC;
+    SkGeom &g = p.sk;
+    g.TR = p.NBR > 0 ? (p.NBR + 2 * p.WT - 1) / (2 * p.WT) : 0;
+    g.cf = p.WT == 2 ? 4 : 1;
+    g.cd = p.WT == 2 ? 3 : 1;
+    g.C = C;
+    g.ctot = g.TR > 0 ? sk_row_prefix(g, g.TR) * C : 0;
+    int64_t G = g.ctot / g.cf;  // every workgroup's range holds >= 1 chunk start
+    if (G > SK_MAX_WG)
+        G = SK_MAX_WG;
+    if (G < 1)
+        G = 1;
+    g.G = (int32_t)G;
+    p.smax = g.TR > 0 ? sk_max_segments(g) : 0;
+    p.npad = ((C * KC + (int64_t)g.TR * p.TS + 64) + 63) / 64 * 64;
+    int64_t db = n / 4096;
+    p.dot_blocks = (int32_t)(db < 1 ? 1 : (db > 64 ? 64 : db));
+
+    size_t o = 0;
+    p.off_stats = o;  o = align256(o + 64 * sizeof(double));
+    p.off_mpart = o;  o = align256(o + MOM_BLOCKS * 3 * sizeof(double));
+    p.off_xf = o;     o = align256(o + (size_t)p.npad * sizeof(float));
+    p.off_win4 = o;   o = align256(o + (size_t)p.npad * 16);
+    if (path != HOS_PATH_FP32) {
+        p.off_win8h = o;  o = align256(o + (size_t)p.npad * 16);
+        p.off_win8l = o;  o = align256(o + (size_t)p.npad * 16);
+    }
+    if (M > 0) {
+        p.off_part = o;
+        o = align256(o + (size_t)g.G * p.smax * tile_elems(p.WT) * sizeof(double));
+    }
+    p.off_cfull = o;  o = align256(o + (size_t)(M + 1) * (M + 1) * sizeof(double));
+    p.off_dpart = o;  o = align256(o + (size_t)p.nleft * p.dot_blocks * sizeof(double));
+    if (nfft > 0) {
+        p.off_twid = o;
+        o = align256(o + (size_t)nfft * 2 * sizeof(double));
+    }
+    p.total = o;
+    return HOS_OK;
+}
+
+static bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr & (a - 1)) == 0; }
+
+static int check_bispectrum_args(int64_t n, int32_t M, int32_t window, int32_t nfft,
+                                 int32_t path, uint32_t flags, bool want_B)
+{
+    if (n < 2 || n > ((int64_t)1 << 40))
+        return HOS_EINVAL;
+    if (M < 0 || (int64_t)M >= n || M > 8192)
+        return HOS_EINVAL;
+    if (path != HOS_PATH_FP32 && path != HOS_PATH_SPLIT_FP16 && path != HOS_PATH_SPLIT_BF16)
+        return HOS_EINVAL;
+    if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN)
+        return HOS_EINVAL;
+    if (flags & ~HOS_NO_CENTER)
+        return HOS_EINVAL;
+    if (want_B) {
+        if (!fft_size_ok(nfft))
+            return HOS_EINVAL;
+        const int64_t need = window == HOS_WIN_PARZEN ? 2 * (int64_t)M : 2 * (int64_t)M + 1;
+        if (nfft < need || nfft < 2)
+            return HOS_EINVAL;
+    } else if (nfft < 0) {
+        return HOS_EINVAL;
+    }
+    return HOS_OK;
+}
+
+// Device gate: one check per device id, cached.
+static int device_ok()
+{
+    static std::mutex mu;
+    static int cache[64];
+    static bool init = false;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        return HOS_ENODEVICE;
+    if (dev >= 64)
+        return HOS_ENODEVICE;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!init) {
+        for (int &c : cache)
+            c = 0;
+        init = true;
+    }
+    if (cache[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return HOS_EDEVICE;
+        cache[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    }
+    return cache[dev] == 1 ? HOS_OK : HOS_ENODEVICE;
+}
+
+}  // namespace hos
+
+using namespace hos;
+
+extern "C" {
+
+const char *hos_strerror(int status)
+{
+    switch (status) {
+    case HOS_OK: return "success";
+    case HOS_EINVAL: return "invalid argument";
+    case HOS_EWORKSPACE: return "workspace too small";
+    case HOS_EDEVICE: return "HIP device error";
+    case HOS_ENODEVICE: return "no gfx950 device available";
+    case HOS_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+int hos_version(void) { return HOS_VERSION; }
+
+int hos_device_check(void)
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return HOS_ENODEVICE;
+    return device_ok();
+}
+
+int hos_bispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path, uint32_t flags,
+                             size_t *bytes)
+{
+    if (!bytes)
+        return HOS_EINVAL;
+    const int win = HOS_WIN_NONE;
+    int st = check_bispectrum_args(n, M, win, nfft > 0 ? nfft : 0, path, flags, false);
+    if (st != HOS_OK)
+        return st;
+    if (nfft > 0 && !fft_size_ok(nfft))
+        return HOS_EINVAL;
+    C3Plan p;
+    make_c3_plan(n, M, path, nfft, p);
+    *bytes = p.total;
+    return HOS_OK;
+}
+
+// Shared body of hos_bispectrum and hos_bispectrum_timed: validation, plan,
+// and the launch sequence.  `ev` (8 events or NULL) brackets the stages.
+static int bispectrum_impl(const void *x, int32_t dtype, int64_t n, int32_t M,
+                           int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                           double *c3, double *B, void *ws, size_t ws_bytes,
+                           hipStream_t stream, hipEvent_t *ev)
+{
+    if (!x || !ws || (!c3 && !B))
+        return HOS_EINVAL;
+    if (dtype != HOS_F32 && dtype != HOS_F64)
+        return HOS_EINVAL;
+    if (!aligned(x, dtype == HOS_F64 ? 8 : 4) || !aligned(ws, 256))
+        return HOS_EINVAL;
+    if ((c3 && !aligned(c3, 8)) || (B && !aligned(B, 16)))
+        return HOS_EINVAL;
+    int st = check_bispectrum_args(n, M, window, B ? nfft : 0, path, flags, B != nullptr);
+    if (st != HOS_OK)
+        return st;
+    C3Plan p;
+    make_c3_plan(n, M, path, B ? nfft : 0, p);
+    if (ws_bytes < p.total)
+        return HOS_EWORKSPACE;
+    st = device_ok();
+    if (st != HOS_OK)
+        return st;
+
+    char *w = (char *)ws;
+    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], stream) : hipSuccess; };
+    double2 *tw = B ? (double2 *)(w + p.off_twid) : nullptr;
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = launch_moments(x, dtype, n, flags, p, w, stream);
+    if (e == hipSuccess) e = mark(1);
+    if (e == hipSuccess) e = launch_prep(x, dtype, p, w, stream);
+    if (e == hipSuccess) e = mark(2);
+    if (e == hipSuccess) e = launch_c3_contract(p, w, stream);
+    if (e == hipSuccess) e = mark(3);
+    if (e == hipSuccess) e = launch_diag_dot(p, w, stream);
+    if (e == hipSuccess) e = mark(4);
+    if (e == hipSuccess) e = launch_c3_reduce(p, w, stream);
+    if (e == hipSuccess) e = mark(5);
+    if (e == hipSuccess && B) e = launch_twiddles(tw, nfft, stream);
+    if (e == hipSuccess) e = launch_c3_finish(p, window, nfft, c3, B, w, stream);
+    if (e == hipSuccess) e = mark(6);
+    if (e == hipSuccess && B) e = launch_fft2(B, nfft, tw, stream);
+    if (e == hipSuccess) e = mark(7);
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
+int hos_bispectrum(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                   int32_t nfft, int32_t path, uint32_t flags, double *c3, double *B,
+                   void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return bispectrum_impl(x, dtype, n, M, window, nfft, path, flags, c3, B, ws, ws_bytes,
+                           stream, nullptr);
+}
+
+int hos_bispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                         int32_t nfft, int32_t path, uint32_t flags, double *c3, double *B,
+                         void *ws, size_t ws_bytes, hipStream_t stream, float *stage_ms)
+{
+    if (!stage_ms)
+        return HOS_EINVAL;
+    hipEvent_t ev[8];
+    int made = 0;
+    for (; made < 8; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess)
+            break;
+    int st = made == 8 ? bispectrum_impl(x, dtype, n, M, window, nfft, path, flags, c3, B,
+                                         ws, ws_bytes, stream, ev)
+                       : HOS_EDEVICE;
+    if (st == HOS_OK) {
+        if (hipEventSynchronize(ev[7]) != hipSuccess) {
+            st = HOS_EDEVICE;
+        } else {
+            for (int k = 0; k < 7; ++k)
+                if (hipEventElapsedTime(&stage_ms[k], ev[k], ev[k + 1]) != hipSuccess)
+                    st = HOS_EDEVICE;
+            if (hipEventElapsedTime(&stage_ms[7], ev[0], ev[7]) != hipSuccess)
+                st = HOS_EDEVICE;
+        }
+    }
+    for (int k = 0; k < made; ++k)
+        hipEventDestroy(ev[k]);
+    return st;
+}
+
+// Host-only introspection of the contraction schedule (no HIP call):
+// info[0..9] = G, smax, TR, C, WT, NBR, nleft, npad, ctot, workspace bytes.
+int hos_c3_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo)
+{
+    if (!info || ninfo < 10)
+        return HOS_EINVAL;
+    int st = check_bispectrum_args(n, M, HOS_WIN_NONE, 0, path, 0, false);
+    if (st != HOS_OK)
+        return st;
+    C3Plan p;
+    make_c3_plan(n, M, path, 0, p);
+    info[0] = p.sk.G;
+    info[1] = p.smax;
+    info[2] = p.sk.TR;
+    info[3] = p.sk.C;
+    info[4] = p.WT;
+    info[5] = p.NBR;
+    info[6] = p.nleft;
+    info[7] = p.npad;
+    info[8] = p.sk.ctot;
+    info[9] = (int64_t)p.total;
+    return HOS_OK;
+}
+
+// Host-only replay of the contraction's work split: for every (tile, chunk)
+// in schedule order, owner[k] receives the workgroup that processes it, as
+// the kernel's own iteration finds it, and slot[k] the partial slot it
+// writes; the reduce side's lookup of the same pair is returned in
+// rslot[k].  Used to test the split without a GPU.
+int hos_c3_schedule(int64_t n, int32_t M, int32_t path, int64_t *owner, int64_t *slot,
+                    int64_t *rslot, int64_t cap)
+{
+    if (!owner || !slot || !rslot)
+        return HOS_EINVAL;
+    int st = check_bispectrum_args(n, M, HOS_WIN_NONE, 0, path, 0, false);
+    if (st != HOS_OK)
+        return st;
+    C3Plan p;
+    make_c3_plan(n, M, path, 0, p);
+    const SkGeom &g = p.sk;
+    const int64_t ntiles = (int64_t)g.TR * (g.TR + 1) / 2;
+    if (cap < ntiles * g.C)
+        return HOS_EINVAL;
+    for (int64_t k = 0; k < ntiles * g.C; ++k)
+        owner[k] = slot[k] = rslot[k] = -1;
+    // kernel side
+    for (int64_t w = 0; w < g.G; ++w) {
+        const int64_t S0 = sk_wg_start(g, w), S1 = sk_wg_start(g, w + 1);
+        SkPos q;
+        if (!sk_first_chunk(g, S0, q) || sk_chunk_start(g, q.R, q.Cc, q.c) >= S1)
+            continue;
+        const int64_t tfirst = sk_tile_index(q.R, q.Cc);
+        for (;;) {
+            const int64_t t = sk_tile_index(q.R, q.Cc);
+            const int64_t k = t * g.C + q.c;
+            if (owner[k] != -1)
+                owner[k] = -2;  // processed twice
+            else
+                owner[k] = w;
+            slot[k] = w * p.smax + (t - tfirst);
+            if (t - tfirst >= p.smax)
+                slot[k] = -3;
+            SkPos nq = q;
+            if (!(sk_next(g, nq) && sk_chunk_start(g, nq.R, nq.Cc, nq.c) < S1))
+                break;
+            q = nq;
+        }
+    }
+    // reduce side: for each tile, the workgroups it sums and their slots
+    for (int R = 0; R < g.TR; ++R)
+        for (int Cc = 0; Cc <= R; ++Cc) {
+            const int64_t t = sk_tile_index(R, Cc);
+            const int64_t w_lo = sk_owner(g, sk_chunk_start(g, R, Cc, 0));
+            const int64_t w_hi = sk_owner(g, sk_chunk_start(g, R, Cc, g.C - 1));
+            for (int64_t c = 0; c < g.C; ++c) {
+                const int64_t w = sk_owner(g, sk_chunk_start(g, R, Cc, c));
+                SkPos p0;
+                sk_first_chunk(g, sk_wg_start(g, w), p0);
+                int64_t s = w * p.smax + (t - sk_tile_index(p0.R, p0.Cc));
+                if (w < w_lo || w > w_hi)
+                    s = -4;
+                rslot[t * g.C + c] = s;
+            }
+        }
+    return HOS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// hos_internal.h -- internal plan, workspace layout and launch declarations
+// of the gfx950 higher-order-spectra library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "hos.h"
+
+namespace hos {
+
+// ---------------------------------------------------------------------------
+// Contraction geometry.
+//
+// The third-order sums over the fundamental region F = {0 <= b <= a <= M}
+//     C[a][b] = sum_i x_i x_{i+a} x_{i+b}
+// are computed as a matrix product over the sample index i: for the row
+// r = a - 1 (a = 1..M) the product row Y[r][i] = x_i x_{i+r+1} meets the
+// Hankel operand T[i][b] = x_{i+b}.  Rows and columns are cut into 32 x 32
+// matrix-core blocks; block (R, B) is needed iff B <= R.  Inside a diagonal
+// block the entries with b <= r + 1 are kept, which covers every (a, b) of F
+// except the diagonal entries C[a][a] for a = 0 and a = 32k; those few
+// sums are computed separately (k_diag_dot).
+//
+// Blocks are grouped into square workgroup tiles of TS = 64*WT samples per
+// side (WT = 32-blocks per wave side, 4 waves per workgroup).  The sample
+// axis is cut into chunks of KC samples; a "chunk" of a tile is the unit of
+// work.  Chunks are spread over a fixed number G of persistent workgroups
+// by a weighted contiguous split of the flattened (tile, chunk) sequence
+// ("stream-K"): each workgroup owns the chunks whose start cost falls in its
+// cost range and writes one FP64 partial tile per tile it touches, so the
+// cross-workgroup reduction is a fixed-order sum (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int KC = 512;           // samples per chunk; FP32 -> FP64 flush period
+constexpr int GROUP = 16;         // samples per matrix-core k-group
+constexpr int WG_THREADS = 256;   // 4 waves of 64
+
+struct SkGeom {
+    int32_t TR;     // tile rows (and columns) of the triangle
+    int32_t cf;     // cost of one chunk of an off-diagonal tile
+    int32_t cd;     // cost of one chunk of a diagonal tile
+    int32_t G;      // persistent workgroups
+    int64_t C;      // chunks per tile
+    int64_t ctot;   // total cost
+};
+
+struct SkPos {
+    int32_t R;      // tile row
+    int32_t Cc;     // tile column (Cc <= R)
+    int64_t c;      // chunk index within the tile
+};
+
+__host__ __device__ inline int64_t sk_row_prefix(const SkGeom &g, int64_t R)
+{
+    // cost per chunk-column of all tiles in rows < R (R-1 full + 1 diagonal each)
+    return (R * (R - 1) / 2) * g.cf + R * g.cd;
+}
+
+__host__ __device__ inline int sk_tile_cost(const SkGeom &g, int R, int Cc)
+{
+    return Cc == R ? g.cd : g.cf;
+}
+
+__host__ __device__ inline int64_t sk_tile_index(int R, int Cc)
+{
+    return (int64_t)R * (R + 1) / 2 + Cc;
+}
+
+__host__ __device__ inline int64_t sk_chunk_start(const SkGeom &g, int R, int Cc,
+                                                  int64_t c)
+{
+    int64_t tile_prefix = sk_row_prefix(g, R) + (int64_t)Cc * g.cf;
+    return tile_prefix * g.C + c * sk_tile_cost(g, R, Cc);
+}
+
+__host__ __device__ inline int64_t sk_wg_start(const SkGeom &g, int64_t w)
+{
+    return w * g.ctot / g.G;
+}
+
+// Workgroup owning the chunk that starts at cost S.
+__host__ __device__ inline int64_t sk_owner(const SkGeom &g, int64_t S)
+{
+    return ((S + 1) * g.G - 1) / g.ctot;
+}
+
+// Step to the next chunk in (row, column, chunk) order; false past the end.
+__host__ __device__ inline bool sk_next(const SkGeom &g, SkPos &p)
+{
+    if (++p.c < g.C)
+        return true;
+    p.c = 0;
+    if (p.Cc < p.R) {
+        ++p.Cc;
+        return true;
+    }
+    ++p.R;
+    p.Cc = 0;
+    return p.R < g.TR;
+}
+
+// First chunk whose start cost is >= S; false if there is none.
+__host__ __device__ inline bool sk_first_chunk(const SkGeom &g, int64_t S, SkPos &p)
+{
+    if (S >= sk_row_prefix(g, g.TR) * g.C)
+        return false;
+    int R = 0;
+    while (R + 1 < g.TR && sk_row_prefix(g, R + 1) * g.C <= S)
+        ++R;
+    int64_t u = S - sk_row_prefix(g, R) * g.C;
+    int64_t full_span = (int64_t)R * g.cf * g.C;
+    int Cc;
+    int64_t off;
+    int cost;
+    if (u < full_span) {
+        Cc = (int)(u / ((int64_t)g.cf * g.C));
+        off = u - (int64_t)Cc * g.cf * g.C;
+        cost = g.cf;
+    } else {
+        Cc = R;
+        off = u - full_span;
+        cost = g.cd;
+    }
+    p.R = R;
+    p.Cc = Cc;
+    p.c = (off + cost - 1) / cost;
+    if (p.c >= g.C) {
+        p.c = g.C - 1;
+        return sk_next(g, p);
+    }
+    return true;
+}
+
+// Upper bound on the number of tiles one workgroup's cost range can touch.
+inline int64_t sk_max_segments(const SkGeom &g)
+{
+    int64_t span = (g.ctot + g.G - 1) / g.G;
+    int64_t min_tile = (int64_t)(g.cd < g.cf ? g.cd : g.cf) * g.C;
+    return (span > 0 ? (span - 1) / min_tile : 0) + 2;
+}
+
+// ---------------------------------------------------------------------------
+// Bispectrum plan and workspace layout (all offsets 256-byte aligned).
+// ---------------------------------------------------------------------------
+struct C3Plan {
+    int64_t n;
+    int32_t M;
+    int32_t path;      // hos_path
+    int32_t WT;        // 32-blocks per wave side (1 or 2)
+    int32_t TS;        // tile side in samples (64 * WT)
+    int32_t NBR;       // 32-block rows: rows r = 0 .. M-1
+    int32_t nleft;     // leftover diagonal sums C[a][a], a = 0 and a = 32k <= M
+    int32_t dot_blocks;// workgroups per leftover sum
+    int64_t npad;      // padded series length (multiple of 64)
+    int64_t smax;      // partial slots per workgroup
+    SkGeom sk;
+    // workspace offsets in bytes
+    size_t off_stats, off_mpart, off_xf, off_win4, off_win8h, off_win8l;
+    size_t off_part, off_cfull, off_dpart, off_twid, total;
+};
+
+constexpr int MOM_BLOCKS = 256;     // blocks of the moments pass
+constexpr int SK_MAX_WG = 256;      // persistent workgroups of the contraction
+
+int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p);
+
+// Element count of one FP64 partial tile.
+inline int64_t tile_elems(int WT) { return (int64_t)(64 * WT) * (64 * WT); }
+
+// ---------------------------------------------------------------------------
+// Launchers (enqueue on `s`, return hipError_t of the last launch).
+// ---------------------------------------------------------------------------
+hipError_t launch_moments(const void *x, int dtype, int64_t n, uint32_t flags,
+                          const C3Plan &p, char *ws, hipStream_t s);
+hipError_t launch_prep(const void *x, int dtype, const C3Plan &p, char *ws,
+                       hipStream_t s);
+hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s);
+hipError_t launch_diag_dot(const C3Plan &p, char *ws, hipStream_t s);
+hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s);
+hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3,
+                            double *B, char *ws, hipStream_t s);
+bool fft_size_ok(int N);
+hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s);
+hipError_t launch_fft2(double *B, int N, const double2 *tw, hipStream_t s);
+hipError_t launch_fft3(double *T, int N, const double2 *tw, hipStream_t s);
+
+}  // namespace hos

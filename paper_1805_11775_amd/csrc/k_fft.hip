@@ -1,0 +1,242 @@
+// k_fft.hip -- FP64 complex DFTs of the windowed cumulants.
+//
+// The spectrum is the Fourier transform of the cumulant (Section 1), taken
+// as an unnormalised DFT with the sign of Algorithm DBS step 3,
+//     X(k) = sum_u x(u) exp(-2 pi i u k / N).
+// Multi-dimensional transforms are done one axis at a time in place.  Each
+// workgroup loads CB whole sequences into LDS, runs a self-sorting
+// (Stockham) mixed-radix 4/2/3/5 FFT there -- every stage reads its R
+// inputs per butterfly into registers, barriers, and writes them back in
+// sorted position -- and stores the sequences back.  Twiddles come from a
+// table of the N roots of unity built once per call with sincospi in FP64.
+#include "hos_internal.h"
+
+namespace hos {
+
+namespace {
+
+constexpr int FFT_THREADS = 256;
+constexpr int FFT_LDS_ELEMS = 4096;   // complex doubles per workgroup (64 KB)
+
+struct FftRadices {
+    int n;
+    int r[16];
+};
+
+__device__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__global__ void k_twiddle(double2 *__restrict__ tw, int N)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N)
+        return;
+    double s, c;
+    sincospi(-2.0 * (double)k / (double)N, &s, &c);
+    tw[k] = make_double2(c, s);
+}
+
+// Forward DFT of size R in registers.
+template <int R>
+__device__ inline void dft_small(double2 *v, const double2 *__restrict__ tw, int N)
+{
+    if constexpr (R == 2) {
+        double2 a = v[0], b = v[1];
+        v[0] = make_double2(a.x + b.x, a.y + b.y);
+        v[1] = make_double2(a.x - b.x, a.y - b.y);
+    } else if constexpr (R == 4) {
+        double2 a = v[0], b = v[1], c = v[2], d = v[3];
+        double2 s02 = make_double2(a.x + c.x, a.y + c.y), d02 = make_double2(a.x - c.x, a.y - c.y);
+        double2 s13 = make_double2(b.x + d.x, b.y + d.y), d13 = make_double2(b.x - d.x, b.y - d.y);
+        v[0] = make_double2(s02.x + s13.x, s02.y + s13.y);
+        v[2] = make_double2(s02.x - s13.x, s02.y - s13.y);
+        // -i * d13 = (d13.y, -d13.x)
+        v[1] = make_double2(d02.x + d13.y, d02.y - d13.x);
+        v[3] = make_double2(d02.x - d13.y, d02.y + d13.x);
+    } else {
+        double2 in[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            in[q] = v[q];
+        const int step = N / R;
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+            double2 acc = in[0];
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                double2 t = cmul(in[q], tw[((p * q) % R) * step]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            v[p] = acc;
+        }
+    }
+}
+
+template <int R>
+__device__ inline void stockham_stage(double2 *sm, const double2 *__restrict__ tw, int N,
+                                      int Ns, int CB)
+{
+    constexpr int MAXIT = (FFT_LDS_ELEMS / R + FFT_THREADS - 1) / FFT_THREADS;
+    const int nbf = N / R, total = CB * nbf, stride = N / (Ns * R);
+    double2 v[MAXIT][R];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int u = threadIdx.x + FFT_THREADS * it;
+        if (u < total) {
+            const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                double2 x = sm[cb * N + j + q * nbf];
+                v[it][q] = q == 0 ? x : cmul(x, tw[q * k * stride]);
+            }
+            dft_small<R>(v[it], tw, N);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int u = threadIdx.x + FFT_THREADS * it;
+        if (u < total) {
+            const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
+            const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int p = 0; p < R; ++p)
+                sm[cb * N + idxD + p * Ns] = v[it][p];
+        }
+    }
+    __syncthreads();
+}
+
+// Sequence s starts at (s / b_in) * s_out + (s % b_in) * s_in; element k
+// of it sits k * es further.  CB sequences per workgroup.
+__global__ void __launch_bounds__(FFT_THREADS)
+k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadices fr,
+           int64_t nseq, int64_t es, int64_t b_in, int64_t s_in, int64_t s_out, int CB)
+{
+    __shared__ double2 sm[FFT_LDS_ELEMS];
+    const int N = fr.n;
+    const int64_t seq0 = (int64_t)blockIdx.x * CB;
+    const int tot = CB * N;
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int cb, k;
+        if (es == 1) {
+            cb = e / N;
+            k = e - cb * N;
+        } else {
+            k = e / CB;
+            cb = e - k * CB;
+        }
+        const int64_t s = seq0 + cb;
+        if (s < nseq)
+            sm[cb * N + k] = data[(s / b_in) * s_out + (s % b_in) * s_in + k * es];
+    }
+    __syncthreads();
+    int Ns = 1;
+    for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
+        const int R = fr.r[st];
+        if (R == 4)
+            stockham_stage<4>(sm, tw, N, Ns, CB);
+        else if (R == 2)
+            stockham_stage<2>(sm, tw, N, Ns, CB);
+        else if (R == 3)
+            stockham_stage<3>(sm, tw, N, Ns, CB);
+        else
+            stockham_stage<5>(sm, tw, N, Ns, CB);
+        Ns *= R;
+    }
+    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+        int cb, k;
+        if (es == 1) {
+            cb = e / N;
+            k = e - cb * N;
+        } else {
+            k = e / CB;
+            cb = e - k * CB;
+        }
+        const int64_t s = seq0 + cb;
+        if (s < nseq)
+            data[(s / b_in) * s_out + (s % b_in) * s_in + k * es] = sm[cb * N + k];
+    }
+}
+
+FftRadices factor(int N)
+{
+    FftRadices f;
+    f.n = N;
+    int m = N, k = 0;
+    while (m % 4 == 0) {
+        f.r[k++] = 4;
+        m /= 4;
+    }
+    while (m % 2 == 0) {
+        f.r[k++] = 2;
+        m /= 2;
+    }
+    while (m % 3 == 0) {
+        f.r[k++] = 3;
+        m /= 3;
+    }
+    while (m % 5 == 0) {
+        f.r[k++] = 5;
+        m /= 5;
+    }
+    for (; k < 16; ++k)
+        f.r[k] = 0;
+    return f;
+}
+
+void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq, int64_t es,
+              int64_t b_in, int64_t s_in, int64_t s_out, hipStream_t s)
+{
+    int CB = FFT_LDS_ELEMS / fr.n;
+    if (CB > 32)
+        CB = 32;
+    const int64_t blocks = (nseq + CB - 1) / CB;
+    k_fft_axis<<<blocks, FFT_THREADS, 0, s>>>(d, tw, fr, nseq, es, b_in, s_in, s_out, CB);
+}
+
+}  // namespace
+
+bool fft_size_ok(int N)
+{
+    if (N < 2 || N > FFT_LDS_ELEMS)
+        return false;
+    int m = N;
+    for (int r : {2, 3, 5})
+        while (m % r == 0)
+            m /= r;
+    return m == 1;
+}
+
+hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s)
+{
+    k_twiddle<<<(N + 255) / 256, 256, 0, s>>>(tw, N);
+    return hipGetLastError();
+}
+
+// In-place 2D DFT of an N x N row-major complex array: rows, then columns.
+hipError_t launch_fft2(double *B, int N, const double2 *tw, hipStream_t s)
+{
+    double2 *d = (double2 *)B;
+    const FftRadices fr = factor(N);
+    fft_axis(d, tw, fr, N, 1, 1, 0, N, s);   // along k2 (contiguous)
+    fft_axis(d, tw, fr, N, N, N, 1, 0, s);   // along k1
+    return hipGetLastError();
+}
+
+// In-place 3D DFT of an N^3 row-major complex array, one axis at a time.
+hipError_t launch_fft3(double *T, int N, const double2 *tw, hipStream_t s)
+{
+    double2 *d = (double2 *)T;
+    const FftRadices fr = factor(N);
+    const int64_t N2 = (int64_t)N * N;
+    fft_axis(d, tw, fr, N2, 1, 1, 0, N, s);      // axis 2
+    fft_axis(d, tw, fr, N2, N, N, 1, N2, s);     // axis 1
+    fft_axis(d, tw, fr, N2, N2, N2, 1, 0, s);    // axis 0
+    return hipGetLastError();
+}
+
+}  // namespace hos

@@ -1,0 +1,107 @@
+// k_finish.hip -- normalisation, mirroring and lag window of c3.
+//
+// C[a][b] (0 <= b <= a <= M) holds the scaled third-order sums over the
+// fundamental region.  For a lag pair (w1, w2) the three sample offsets
+// {0, w1, w2}, shifted by their minimum and sorted, are {0, b, a}; because
+// the sum runs over every t with all indices inside the record, shifting
+// t by that minimum maps c3(w1, w2) exactly onto C[a][b] / (n s^3) -- this
+// is the six-fold symmetry of c3, used here only to relabel.  Lags with
+// span a > M are outside the hexagon and set to 0.
+//
+// The lag window replaces the paper's frequency-domain box smoothing
+// (Algorithm DBS step 5): W3(w1,w2) = d(w1) d(w2) d(w1-w2) with the Parzen
+// d and scale L = M.  The windowed cumulant is folded onto the N x N DFT
+// grid (index w mod N; aliased lags add), which makes the grid DFT equal
+// to sum_w W3(w) c3(w) exp(-2 pi i <k,w>/N) exactly.
+#include "hos_internal.h"
+
+namespace hos {
+
+namespace {
+
+__device__ inline double parzen(int m, int L)
+{
+    if (L == 0)
+        return m == 0 ? 1.0 : 0.0;
+    const double r = fabs((double)m) / (double)L;
+    if (r <= 0.5)
+        return 1.0 - 6.0 * r * r + 6.0 * r * r * r;
+    if (r <= 1.0) {
+        const double u = 1.0 - r;
+        return 2.0 * u * u * u;
+    }
+    return 0.0;
+}
+
+// c3(w1, w2) from the fundamental-region table, 0 outside the hexagon.
+__device__ inline double c3_at(const double *__restrict__ cfull, int M, double norm, int w1,
+                               int w2)
+{
+    const int mn = min(0, min(w1, w2)), mx = max(0, max(w1, w2));
+    const int a = mx - mn;
+    if (a > M)
+        return 0.0;
+    const int b = (w1 + w2) - mn - mx - mn;   // middle offset minus the minimum
+    return cfull[(int64_t)a * (M + 1) + b] / norm;
+}
+
+__global__ void __launch_bounds__(256)
+k_c3_out(const double *__restrict__ cfull, const double *__restrict__ stats, int M,
+         double *__restrict__ c3)
+{
+    const int side = 2 * M + 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)side * side)
+        return;
+    const int w1 = (int)(idx / side) - M, w2 = (int)(idx % side) - M;
+    c3[idx] = c3_at(cfull, M, stats[3], w1, w2);
+}
+
+// DFT input: B[m1][m2] = (sum over lags w = m mod N of W3(w) c3(w), 0).
+__global__ void __launch_bounds__(256)
+k_fft_input2(const double *__restrict__ cfull, const double *__restrict__ stats, int M, int N,
+             int window, double2 *__restrict__ B)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N)
+        return;
+    const int m1 = (int)(idx / N), m2 = (int)(idx % N);
+    const double norm = stats[3];
+    double sum = 0.0;
+    // lags congruent to m mod N inside [-M, M]: m - N, m (N >= M + 1)
+    for (int w1 = m1 - N; w1 <= m1; w1 += N) {
+        if (w1 < -M || w1 > M)
+            continue;
+        for (int w2 = m2 - N; w2 <= m2; w2 += N) {
+            if (w2 < -M || w2 > M)
+                continue;
+            const double c = c3_at(cfull, M, norm, w1, w2);
+            const double wgt = window == HOS_WIN_PARZEN
+                                   ? parzen(w1, M) * parzen(w2, M) * parzen(w1 - w2, M)
+                                   : 1.0;
+            sum += wgt * c;
+        }
+    }
+    B[idx] = make_double2(sum, 0.0);
+}
+
+}  // namespace
+
+hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3, double *B,
+                            char *ws, hipStream_t s)
+{
+    const double *cfull = (const double *)(ws + p.off_cfull);
+    const double *stats = (const double *)(ws + p.off_stats);
+    if (c3) {
+        const int64_t tot = (int64_t)(2 * p.M + 1) * (2 * p.M + 1);
+        k_c3_out<<<(tot + 255) / 256, 256, 0, s>>>(cfull, stats, p.M, c3);
+    }
+    if (B) {
+        const int64_t tot = (int64_t)nfft * nfft;
+        k_fft_input2<<<(tot + 255) / 256, 256, 0, s>>>(cfull, stats, p.M, nfft, window,
+                                                       (double2 *)B);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hos

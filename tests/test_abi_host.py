@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI: symbols, validation before any HIP call,
+and the contraction's work split (replayed on the CPU by the library)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1805_11775_amd as hos
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(hos_\w+)\s*\(", txt, flags=re.M)
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared_functions()
+    assert "hos_bispectrum" in names and len(names) >= 7
+    lib = ctypes.CDLL(hos.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_strerror():
+    assert hos.hos_version() == 10000
+    for code in (0, -1, -2, -3, -4, -5, 7):
+        assert isinstance(hos.hos_strerror(code), str)
+
+
+FAKE = 0x10000  # any aligned non-null address; validation fails before use
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=1), hos.HOS_EINVAL),
+    (dict(M=-1), hos.HOS_EINVAL),
+    (dict(M=100, n=100), hos.HOS_EINVAL),
+    (dict(path=3), hos.HOS_EINVAL),
+    (dict(window=2), hos.HOS_EINVAL),
+    (dict(dtype=5), hos.HOS_EINVAL),
+    (dict(flags=8), hos.HOS_EINVAL),
+    (dict(nfft=127), hos.HOS_EINVAL),        # < 2M with Parzen
+    (dict(nfft=7 * 37), hos.HOS_EINVAL),     # not 2^a 3^b 5^c
+    (dict(nfft=128, window=0), hos.HOS_EINVAL),  # < 2M+1 without window
+    (dict(x=None), hos.HOS_EINVAL),
+    (dict(x=FAKE + 2), hos.HOS_EINVAL),      # misaligned float32
+    (dict(ws=FAKE + 64), hos.HOS_EINVAL),    # workspace not 256-aligned
+    (dict(c3=None, B=None), hos.HOS_EINVAL),
+    (dict(ws_bytes=16), hos.HOS_EWORKSPACE),
+])
+def test_validation_before_device(kw, code):
+    a = dict(x=FAKE, dtype=hos.HOS_F32, n=4096, M=64, window=hos.HOS_WIN_PARZEN,
+             nfft=128, path=hos.HOS_PATH_FP32, flags=0, c3=FAKE, B=FAKE, ws=FAKE,
+             ws_bytes=1 << 40, stream=None)
+    a.update(kw)
+    st = hos.hos_bispectrum(a["x"], a["dtype"], a["n"], a["M"], a["window"], a["nfft"],
+                            a["path"], a["flags"], a["c3"], a["B"], a["ws"],
+                            a["ws_bytes"], a["stream"])
+    assert st == code
+
+
+def test_workspace_query():
+    b = hos.hos_bispectrum_workspace(1 << 20, 512, 1024, hos.HOS_PATH_SPLIT_FP16)
+    b32 = hos.hos_bispectrum_workspace(1 << 20, 512, 1024, hos.HOS_PATH_FP32)
+    assert b > b32 > (1 << 20) * 20
+    with pytest.raises(hos.HosError):
+        hos.hos_bispectrum_workspace(10, 10, 0, 0)
+
+
+@pytest.mark.parametrize("n,M,path", [
+    (2048, 64, 0), (1 << 20, 512, 1), (1 << 20, 512, 0), (5000, 33, 2),
+    (65536, 256, 1), (1025, 128, 0), (70001, 300, 1), (3000, 1, 0), (600, 95, 2),
+    (1 << 16, 1000, 0),
+])
+def test_schedule_covers_every_chunk_once(n, M, path):
+    info = hos.hos_c3_plan_info(n, M, path)
+    owner, slot, rslot = hos.hos_c3_schedule(n, M, path)
+    assert len(owner) == info["TR"] * (info["TR"] + 1) // 2 * info["C"]
+    assert min(owner) >= 0, "a chunk is unowned (-1) or owned twice (-2)"
+    assert max(owner) < info["G"]
+    assert min(slot) >= 0 and max(slot) < info["G"] * info["smax"]
+    assert slot == rslot, "reduce reads a different slot than the kernel writes"
+    # every workgroup processes at least one chunk
+    assert len(set(owner)) == info["G"]

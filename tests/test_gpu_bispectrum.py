@@ -1,0 +1,156 @@
+"""GPU parity of the bispectrum path against the FP64 oracle.
+
+Error measure: normwise relative error max|GPU - oracle| / max|oracle| over
+the whole c3 hexagon (and over the N x N spectrum).  Bars: 1e-6 for the
+FP32 path and 1e-5 for the split-precision paths.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-6, "split_fp16": 1e-5, "split_bf16": 1e-5}
+PATHS = list(TOL)
+
+
+def _hos():
+    import paper_1805_11775_amd as hos
+    assert hos.hos_device_check() == hos.HOS_OK, "no gfx950 device"
+    return hos
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _run(x_np, M, nfft=None, window="parzen", path="fp32", center=True, dtype=None):
+    hos = _hos()
+    t = torch.from_numpy(np.ascontiguousarray(x_np)).to("cuda")
+    if dtype is not None:
+        t = t.to(dtype)
+    print("case: n=%d M=%d nfft=%s window=%s path=%s dtype=%s" %
+          (t.numel(), M, nfft, window, path, t.dtype), flush=True)
+    c3, B = hos.bispectrum(t, M, nfft=nfft, window=window, path=path, center=center)
+    torch.cuda.synchronize()
+    return c3.cpu().numpy(), B.cpu().numpy()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_small_workload_exp_n2048_M64(path):
+    """n = 2048 float64 centred Exp(1), M = 64, Parzen, 128-point DFT."""
+    x, cfg = synth.workload_small_bispectrum()
+    c3, B = _run(x, cfg["M"], cfg["nfft"], path=path)
+    c3_ref, B_ref = oracle.bispectrum(x, cfg["M"], cfg["nfft"])
+    assert _rel(c3, c3_ref) < TOL[path]
+    assert _rel(B, B_ref) < TOL[path]
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("n,M", [(700, 0), (700, 1), (701, 5), (3001, 31), (3001, 32),
+                                 (3001, 33), (4100, 95), (2500, 128), (3001, 160),
+                                 (1537, 200)])
+def test_parity_grid(path, n, M):
+    """Ragged lengths (not multiples of the 512-sample chunk) and lags below,
+    at and above the 32-block and 128-tile boundaries."""
+    x = synth.quadratic_process(n, 1000 + n + M).astype(np.float32)
+    c3, B = _run(x, M, path=path)
+    c3_ref, B_ref = oracle.bispectrum(x, M, c3.shape[0] - 1 if M else 2)
+    assert _rel(c3, c3_ref) < TOL[path], (n, M)
+    N = B.shape[0]
+    _, B_ref = oracle.bispectrum(x, M, N)
+    assert _rel(B, B_ref) < TOL[path]
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_gaussian_near_zero_cumulant(path):
+    """i.i.d. Gaussian: c3 is pure sampling noise, the hardest case for a
+    normwise bar; n = 65536, M = 64."""
+    x = synth.iid_gauss(65536, 42).astype(np.float32)
+    c3, _ = _run(x, 64, path=path)
+    assert _rel(c3, oracle.c3_hexagon(x, 64)) < TOL[path]
+
+
+@pytest.mark.parametrize("window", ["none", "parzen"])
+def test_window_and_nfft_variants(window):
+    x = synth.iid_exp_centered(1500, 7)
+    M = 20
+    for nfft in ([41, 45, 64] if window == "none" else [40, 48, 60]):
+        c3, B = _run(x, M, nfft=nfft, window=window)
+        _, B_ref = oracle.bispectrum(x, M, nfft, window=window)
+        assert _rel(B, B_ref) < 1e-6, nfft
+
+
+def test_impulse_uncentered_closed_form():
+    """x = A delta_{t0}, no mean removal: c3 = A^3/n at the origin only and
+    the spectrum is flat."""
+    n, M, A = 4000, 40, 3.0
+    x = np.zeros(n)
+    x[1234] = A
+    c3, B = _run(x, M, nfft=80, center=False)
+    expect = np.zeros_like(c3)
+    expect[M, M] = A ** 3 / n
+    assert np.max(np.abs(c3 - expect)) < 1e-6 * A ** 3 / n
+    assert np.max(np.abs(B - A ** 3 / n)) < 1e-6 * A ** 3 / n
+
+
+def test_constant_series_is_zero():
+    c3, B = _run(np.full(3000, 2.5), 50)
+    assert np.max(np.abs(c3)) == 0.0 and np.max(np.abs(B)) == 0.0
+
+
+def test_deterministic_and_workspace_independent():
+    """Bitwise-equal reruns; a NaN-poisoned workspace changes nothing."""
+    hos = _hos()
+    x = torch.from_numpy(synth.quadratic_process(200000, 3).astype(np.float32)).cuda()
+    M, nfft = 256, 512
+    c3a, Ba = hos.bispectrum(x, M, nfft=nfft, path="split_fp16")
+    nb = hos.hos_bispectrum_workspace(x.numel(), M, nfft, hos.HOS_PATH_SPLIT_FP16)
+    ws = torch.full((nb,), 0xFF, dtype=torch.uint8, device="cuda")  # NaN bytes
+    c3b, Bb = hos.bispectrum(x, M, nfft=nfft, path="split_fp16", workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(c3a, c3b) and torch.equal(Ba, Bb)
+    assert not torch.isnan(c3a).any()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_long_workload_sampled(path):
+    """n = 2^20 float32 quadratic process, M = 512, 1024-point DFT (the
+    benchmark shape and launch configuration): sampled lags against the
+    oracle, spectrum symmetries at every frequency, and sampled frequencies
+    against a direct DFT of the returned c3."""
+    x, cfg = synth.workload_long_bispectrum()
+    M, N = cfg["M"], cfg["nfft"]
+    c3, B = _run(x, M, N, path=path)
+    rng = np.random.default_rng(5)
+    w1 = rng.integers(-M, M + 1, 200)
+    w2 = np.clip(w1 + rng.integers(-M, M + 1, 200), -M, M)
+    orbit = np.array([[1, 2], [2, 1], [-1, 1], [1, -1], [-2, -1], [-1, -2], [0, 0],
+                      [M, 0], [0, M], [M, M], [-M, -M], [M, 1], [32, 32], [64, 0]])
+    w1 = np.concatenate([w1, orbit[:, 0]])
+    w2 = np.concatenate([w2, orbit[:, 1]])
+    ref = oracle.c3_at(x, w1, w2)
+    ref[np.abs(w1 - w2) > M] = 0.0
+    got = c3[w1 + M, w2 + M]
+    scale = np.max(np.abs(c3))
+    assert np.max(np.abs(got - ref)) / scale < TOL[path]
+    assert abs(scale - np.max(np.abs(ref))) / scale < 1e-3  # the max is in the sample
+    # c3 symmetries hold exactly (one table entry per orbit)
+    assert np.array_equal(c3, c3.T)
+    # spectrum symmetries at every frequency
+    k = np.arange(N)
+    tol = 1e-9 * np.max(np.abs(B))
+    assert np.max(np.abs(B - B.T)) < tol
+    assert np.max(np.abs(B - np.conj(B[(-k[:, None]) % N, (-k[None, :]) % N]))) < tol
+    # the DFT stage: sampled frequencies against a direct sum over the lags
+    W = oracle.window3(M)
+    lag = np.arange(-M, M + 1)
+    cw = W * c3
+    for k1, k2 in [(0, 0), (1, 2), (17, 300), (511, 512), (1023, 5)]:
+        e = np.exp(-2j * np.pi * (k1 * lag[:, None] + k2 * lag[None, :]) / N)
+        assert abs(np.sum(cw * e) - B[k1, k2]) < 1e-10 * np.max(np.abs(B))
