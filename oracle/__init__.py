@@ -196,8 +196,12 @@ def c4_support(x, M: int, centered: bool = True) -> np.ndarray:
 # --------------------------------------------------------------------------
 def parzen(m, L: int) -> np.ndarray:
     """Parzen lag window d(m) with scale L: 1-6r^2+6r^3 (r<=1/2),
-    2(1-r)^3 (1/2<r<=1), 0 beyond; r = |m|/L."""
-    r = np.abs(np.asarray(m, dtype=np.float64)) / float(L)
+    2(1-r)^3 (1/2<r<=1), 0 beyond; r = |m|/L.  At L = 0 (maximum lag 0)
+    r is undefined; the limit L -> 0+ gives d(0) = 1 and d(m != 0) = 0."""
+    m = np.asarray(m, dtype=np.float64)
+    if L == 0:
+        return np.where(m == 0, 1.0, 0.0)
+    r = np.abs(m) / float(L)
     return np.where(r <= 0.5, 1.0 - 6.0 * r ** 2 + 6.0 * r ** 3,
                     np.where(r <= 1.0, 2.0 * (1.0 - r) ** 3, 0.0))
 

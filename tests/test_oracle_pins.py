@@ -168,6 +168,12 @@ def test_parzen_hand_values():
         assert oracle.parzen(m, int(L)) == pytest.approx(d, abs=1e-15)
 
 
+def test_parzen_zero_scale_limit():
+    """M = 0 leaves the single lag 0: the window must keep it (weight 1)."""
+    assert oracle.parzen(0, 0) == 1.0 and oracle.parzen(3, 0) == 0.0
+    assert oracle.window3(0)[0, 0] == 1.0
+
+
 def test_window3_symmetry_and_support():
     M = 16
     W = oracle.window3(M)
