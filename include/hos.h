@@ -151,7 +151,7 @@ int hos_bispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M,
  * Host-only introspection of the contraction plan (no HIP call, no device
  * needed).  info (host) receives, in order: persistent workgroups G,
  * partial slots per workgroup, tile rows, chunks per tile, 32-blocks per
- * wave side, 32-block rows, leftover diagonal sums, padded length, total
+ * tile side, 32-block rows, leftover diagonal sums, padded length, total
  * schedule cost, workspace bytes.  ninfo >= 10.  HOS_EINVAL on bad sizes.
  */
 int hos_c3_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo);

@@ -21,7 +21,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhos.so")
+# HOS_LIB_PATH selects another build of the library (e.g. a variant under test).
+LIB_PATH = os.environ.get("HOS_LIB_PATH", os.path.join(_HERE, "libhos.so"))
 
 HOS_OK = 0
 HOS_EINVAL = -1
@@ -139,7 +140,7 @@ def hos_c3_plan_info(n, M, path) -> dict:
     st = lib().hos_c3_plan_info(int(n), int(M), int(path), buf, 10)
     if st != HOS_OK:
         raise HosError(st, "hos_c3_plan_info")
-    keys = ("G", "smax", "TR", "C", "WT", "NBR", "nleft", "npad", "ctot", "ws_bytes")
+    keys = ("G", "smax", "TR", "C", "NB", "NBR", "nleft", "npad", "ctot", "ws_bytes")
     return dict(zip(keys, list(buf)))
 
 

@@ -19,20 +19,26 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     p.n = n;
     p.M = M;
     p.path = path;
-    p.WT = M >= 128 ? 2 : 1;
-    p.TS = 64 * p.WT;
+    // Split paths: 4 column blocks per wave amortise the product-row split
+    // (2-block tiles for small M); FP32 path: 128 x 128 tiles with a 2 x 2
+    // block window per wave.
+    p.NB = (M >= 96 || path == HOS_PATH_FP32) ? 4 : 2;
+    p.TS = 32 * p.NB;
     p.NBR = (M + 31) / 32;
     p.nleft = 1 + M / 32;
     const int64_t C = (n + KC - 1) / KC;
     SkGeom &g = p.sk;
-    g.TR = p.NBR > 0 ? (p.NBR + 2 * p.WT - 1) / (2 * p.WT) : 0;
-    g.cf = p.WT == 2 ? 4 : 1;
-    g.cd = p.WT == 2 ? 3 : 1;
+    g.TR = p.NBR > 0 ? (p.NBR + p.NB - 1) / p.NB : 0;
+    // a tile's time is set by its busiest wave: a strip of NB blocks on every
+    // tile (split paths); 4 blocks off and 3 on the diagonal (FP32 layout)
+    g.cf = path == HOS_PATH_FP32 ? 4 : 1;
+    g.cd = path == HOS_PATH_FP32 ? 3 : 1;
     g.C = C;
     g.ctot = g.TR > 0 ? sk_row_prefix(g, g.TR) * C : 0;
     int64_t G = g.ctot / g.cf;  // every workgroup's range holds >= 1 chunk start
-    if (G > SK_MAX_WG)
-        G = SK_MAX_WG;
+    const int64_t gmax = p.NB == 4 ? SK_MAX_WG : 2 * SK_MAX_WG;  // 2-wave groups pair up
+    if (G > gmax)
+        G = gmax;
     if (G < 1)
         G = 1;
     g.G = (int32_t)G;
@@ -52,7 +58,7 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     }
     if (M > 0) {
         p.off_part = o;
-        o = align256(o + (size_t)g.G * p.smax * tile_elems(p.WT) * sizeof(double));
+        o = align256(o + (size_t)g.G * p.smax * tile_elems(p.NB) * sizeof(double));
     }
     p.off_cfull = o;  o = align256(o + (size_t)(M + 1) * (M + 1) * sizeof(double));
     p.off_dpart = o;  o = align256(o + (size_t)p.nleft * p.dot_blocks * sizeof(double));
@@ -199,7 +205,7 @@ static int bispectrum_impl(const void *x, int32_t dtype, int64_t n, int32_t M,
     if (e == hipSuccess) e = mark(2);
     if (e == hipSuccess) e = launch_c3_contract(p, w, stream);
     if (e == hipSuccess) e = mark(3);
-    if (e == hipSuccess) e = launch_diag_dot(p, w, stream);
+    if (e == hipSuccess) e = launch_diag_dot(x, dtype, p, w, stream);
     if (e == hipSuccess) e = mark(4);
     if (e == hipSuccess) e = launch_c3_reduce(p, w, stream);
     if (e == hipSuccess) e = mark(5);
@@ -250,7 +256,7 @@ int hos_bispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M, int
 }
 
 // Host-only introspection of the contraction schedule (no HIP call):
-// info[0..9] = G, smax, TR, C, WT, NBR, nleft, npad, ctot, workspace bytes.
+// info[0..9] = G, smax, TR, C, NB, NBR, nleft, npad, ctot, workspace bytes.
 int hos_c3_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo)
 {
     if (!info || ninfo < 10)
@@ -264,7 +270,7 @@ int hos_c3_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
     info[1] = p.smax;
     info[2] = p.sk.TR;
     info[3] = p.sk.C;
-    info[4] = p.WT;
+    info[4] = p.NB;
     info[5] = p.NBR;
     info[6] = p.nleft;
     info[7] = p.npad;

@@ -23,8 +23,9 @@ namespace hos {
 // except the diagonal entries C[a][a] for a = 0 and a = 32k; those few
 // sums are computed separately (k_diag_dot).
 //
-// Blocks are grouped into square workgroup tiles of TS = 64*WT samples per
-// side (WT = 32-blocks per wave side, 4 waves per workgroup).  The sample
+// Blocks are grouped into square workgroup tiles of TS = 32*NB samples per
+// side (NB = 2 or 4 blocks); a workgroup has NB waves and wave w owns the
+// 32-row strip w of the tile against all NB column blocks.  The sample
 // axis is cut into chunks of KC samples; a "chunk" of a tile is the unit of
 // work.  Chunks are spread over a fixed number G of persistent workgroups
 // by a weighted contiguous split of the flattened (tile, chunk) sequence
@@ -147,8 +148,8 @@ struct C3Plan {
     int64_t n;
     int32_t M;
     int32_t path;      // hos_path
-    int32_t WT;        // 32-blocks per wave side (1 or 2)
-    int32_t TS;        // tile side in samples (64 * WT)
+    int32_t NB;        // 32-blocks per tile side (2 or 4) = waves per workgroup
+    int32_t TS;        // tile side in samples (32 * NB)
     int32_t NBR;       // 32-block rows: rows r = 0 .. M-1
     int32_t nleft;     // leftover diagonal sums C[a][a], a = 0 and a = 32k <= M
     int32_t dot_blocks;// workgroups per leftover sum
@@ -166,7 +167,7 @@ constexpr int SK_MAX_WG = 256;      // persistent workgroups of the contraction
 int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p);
 
 // Element count of one FP64 partial tile.
-inline int64_t tile_elems(int WT) { return (int64_t)(64 * WT) * (64 * WT); }
+inline int64_t tile_elems(int NB) { return (int64_t)(32 * NB) * (32 * NB); }
 
 // ---------------------------------------------------------------------------
 // Launchers (enqueue on `s`, return hipError_t of the last launch).
@@ -176,7 +177,8 @@ hipError_t launch_moments(const void *x, int dtype, int64_t n, uint32_t flags,
 hipError_t launch_prep(const void *x, int dtype, const C3Plan &p, char *ws,
                        hipStream_t s);
 hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s);
-hipError_t launch_diag_dot(const C3Plan &p, char *ws, hipStream_t s);
+hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws,
+                           hipStream_t s);
 hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s);
 hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3,
                             double *B, char *ws, hipStream_t s);

@@ -43,19 +43,31 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // promotable 1
 template <int PATH>
 struct SplitOps;
 
-// FP16 halves: hi = RNE16(y), lo = RNE16(fma(xi, xa, -hi)) (exact residual of
-// the product, rounded once).
+// FP16 halves of the product y = xi * xa: hi = RNE16(y) and lo =
+// RNE16(y - hi), both taken by one fused multiply-add each straight from
+// the exact product (v_fma_mix{lo,hi}_f16 round a full-precision fma to
+// FP16 and write one half of a packed register), two VALU ops per element.
 template <>
 struct SplitOps<HOS_PATH_SPLIT_FP16> {
     typedef halfx8 vec;
     __device__ static inline void split(const float *xi, const float *xa, vec &h, vec &l)
     {
+        uint32_t hw[4], lw[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            _Float16 hh = (_Float16)(xi[j] * xa[j]);
-            h[j] = hh;
-            l[j] = (_Float16)__builtin_fmaf(xi[j], xa[j], -(float)hh);
+        for (int p = 0; p < 4; ++p) {
+            uint32_t hv, lv;
+            asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(hv) : "v"(xi[2 * p]), "v"(xa[2 * p]));
+            asm("v_fma_mixhi_f16 %0, %1, %2, 0"
+                : "+v"(hv) : "v"(xi[2 * p + 1]), "v"(xa[2 * p + 1]));
+            asm("v_fma_mixlo_f16 %0, %1, %2, -%3 op_sel_hi:[0,0,1]"
+                : "=v"(lv) : "v"(xi[2 * p]), "v"(xa[2 * p]), "v"(hv));
+            asm("v_fma_mixhi_f16 %0, %1, %2, -%3 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+                : "+v"(lv) : "v"(xi[2 * p + 1]), "v"(xa[2 * p + 1]), "v"(hv));
+            hw[p] = hv;
+            lw[p] = lv;
         }
+        h = __builtin_bit_cast(vec, hw);
+        l = __builtin_bit_cast(vec, lw);
     }
     __device__ static inline vec from_bits(uint4 u) { return __builtin_bit_cast(vec, u); }
     __device__ static inline floatx16 mma(vec a, vec b, floatx16 c)
@@ -64,6 +76,7 @@ struct SplitOps<HOS_PATH_SPLIT_FP16> {
     }
 };
 
+// BF16 halves: hi = RNE_bf16(y), lo = RNE_bf16(fma(xi, xa, -hi)).
 template <>
 struct SplitOps<HOS_PATH_SPLIT_BF16> {
     typedef bf16x8 vec;
@@ -89,184 +102,323 @@ __device__ inline void unpack8(float4 a, float4 b, float *v)
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
-// 32 k-groups of one staged chunk for one wave.  MASK bit (2*ra + rb) marks
-// the active 32 x 32 blocks of the wave's 2 x 2 (WT = 2) or 1 x 1 window.
-template <int PATH, int WT, int MASK>
+// The FP64 accumulators are touched once per flush, so they are kept in the
+// accumulation register file (AGPRs): the empty asm pins each value to an
+// AGPR after its update, leaving the VGPRs to the operand pipeline.
+__device__ __attribute__((always_inline)) inline void pin_agpr(double &v)
+{
+    asm volatile("" : "+a"(v));
+}
+
+template <int NB, bool PIN>
+__device__ inline void flush_acc(floatx16 (&acc)[NB], double (&acc64)[NB][16])
+{
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            acc64[cb][v] += (double)acc[cb][v];
+            if (PIN)
+                pin_agpr(acc64[cb][v]);
+            acc[cb][v] = 0.0f;
+        }
+}
+
+// FP32 partial sums move into FP64 every FlushPeriod::GROUPS k-groups.  The
+// matrix-core FP32 accumulation error grows linearly with the length of the
+// chain (measured: the bias of each add is relative to the running sum), and
+// a cumulant that is pure sampling noise (Gaussian input) sits far below the
+// size of its terms, so the chain length sets the relative error there.
+template <int PATH>
+struct FlushPeriod {
+    static constexpr int GROUPS = PATH == HOS_PATH_FP32 ? 4 : KC / GROUP;
+};
+
+// Row-side operands of one 16-sample k-group as read from LDS: x_i and the
+// wave's run x_{i+r+1} (8 samples per lane).
+struct RowRaw {
+    float4 xi0, xi1, xa0, xa1;
+};
+
+__device__ __attribute__((always_inline)) inline void
+fetch_rows(RowRaw &r, const float4 *__restrict__ sxi, const float4 *__restrict__ sxa, int grp,
+           int rw, int rl, int h)
+{
+    const int ib = grp * GROUP + 8 * h;
+    const int o = ib + 32 * rw + rl + 1;
+    r.xi0 = sxi[ib >> 2];
+    r.xi1 = sxi[(ib >> 2) + 1];
+    r.xa0 = sxa[o];
+    r.xa1 = sxa[o + 4];
+}
+
+// Hankel windows.  Column block cb of group g needs T[i][b] = x_{i+b} for
+// the lane's 8 samples i = i0 + 16g + 8h + j and b = b0 + 32cb + rl, i.e. the
+// window table entry at o = 16(g + 2cb) + 8h + rl.  Writing V[u] for the
+// entry at 16u + 8h + rl, group g uses V[g], V[g+2], .., V[g+2(NCOL-1)]:
+// group g+2 reuses all but one of group g's windows, so each group loads a
+// single new window instead of NCOL.  A window is two 16-byte entries --
+// split: T hi, T lo; FP32: T[0..3], T[4..7].
+struct Win {
+    uint4 a, b;
+};
+
+template <int PATH>
+__device__ __attribute__((always_inline)) inline void
+fetch_win(Win &v, const uint4 *__restrict__ sxb, int wlen, int u, int rl, int h)
+{
+    const int o = 16 * u + 8 * h + rl;
+    v.a = sxb[o];
+    v.b = PATH == HOS_PATH_FP32 ? sxb[o + 4] : sxb[wlen + o];
+}
+
+template <int PATH>
+struct Yrow {
+    typename SplitOps<PATH>::vec yh, yl;
+};
+
+template <int PATH>
+__device__ __attribute__((always_inline)) inline void split_rows(Yrow<PATH> &y, const RowRaw &r)
+{
+    float xi[8], xa[8];
+    unpack8(r.xi0, r.xi1, xi);
+    unpack8(r.xa0, r.xa1, xa);
+    SplitOps<PATH>::split(xi, xa, y.yh, y.yl);
+}
+
+// One staged chunk (KC samples = 32 k-groups, fully unrolled so that the
+// window ring and the pipeline stages have fixed registers) for one wave:
+// its 32-row strip rw against the first NCOL column blocks.  At step g the
+// wave issues the LDS reads of window V[g + 2 NCOL] and of the rows of group
+// g+2, splits the product row of group g+1, and runs group g's matrix-core
+// ops.  The fences keep each step's LDS reads ahead of its matrix-core ops
+// (the compiler would otherwise sink them next to their consumers and expose
+// the LDS latency); only VALU ops may cross them, so the split interleaves
+// with the matrix-core ops.  The FP32 path has the same structure with one
+// multiply per product and 8 matrix-core steps per block per group.
+template <int PATH, int NB, int NCOL>
 __device__ inline void chunk_compute(const float4 *__restrict__ sxi,
                                      const float4 *__restrict__ sxa,
-                                     const uint4 *__restrict__ sxb, int wlen,
-                                     int rowbase, int colbase, int rl, int h,
-                                     floatx16 (&acc)[WT][WT])
+                                     const uint4 *__restrict__ sxb, int wlen, int rw, int rl,
+                                     int h, floatx16 (&acc)[NB], double (&acc64)[NB][16])
 {
+    constexpr int NG = KC / GROUP;
+    constexpr int UMAX = NG - 1 + 2 * (NCOL - 1);   // last window used
     constexpr bool SPLIT = PATH != HOS_PATH_FP32;
-#pragma unroll 2
-    for (int grp = 0; grp < KC / GROUP; ++grp) {
-        const int ib = grp * GROUP + 8 * h;
-        float xi[8];
-        unpack8(sxi[ib >> 2], sxi[(ib >> 2) + 1], xi);
-        if constexpr (SPLIT) {
-            typedef SplitOps<PATH> Ops;
-            typename Ops::vec yh[WT], yl[WT], th[WT], tl[WT];
+    if constexpr (SPLIT) {
+        typedef SplitOps<PATH> Ops;
+        Win V[UMAX + 1];
+        RowRaw raw[NG];
 #pragma unroll
-            for (int ra = 0; ra < WT; ++ra) {
-                if (!(MASK & (3 << (2 * ra))))
-                    continue;
-                const int o = ib + 32 * (rowbase + ra) + rl + 1;
-                float xa[8];
-                unpack8(sxa[o], sxa[o + 4], xa);
-                Ops::split(xi, xa, yh[ra], yl[ra]);
-            }
+        for (int u = 0; u < 2 * NCOL && u <= UMAX; ++u)
+            fetch_win<PATH>(V[u], sxb, wlen, u, rl, h);
+        fetch_rows(raw[0], sxi, sxa, 0, rw, rl, h);
+        fetch_rows(raw[1], sxi, sxa, 1, rw, rl, h);
+        Yrow<PATH> Y[NG];
+        split_rows<PATH>(Y[0], raw[0]);
 #pragma unroll
-            for (int rb = 0; rb < WT; ++rb) {
-                if (!(MASK & (5 << rb)))
-                    continue;
-                const int o = ib + 32 * (colbase + rb) + rl;
-                th[rb] = Ops::from_bits(sxb[o]);
-                tl[rb] = Ops::from_bits(sxb[wlen + o]);
-            }
+        for (int g = 0; g < NG; ++g) {
+            if (g + 2 * NCOL <= UMAX)
+                fetch_win<PATH>(V[g + 2 * NCOL], sxb, wlen, g + 2 * NCOL, rl, h);
+            if (g + 2 < NG)
+                fetch_rows(raw[g + 2], sxi, sxa, g + 2, rw, rl, h);
+            if (g + 1 < NG)
+                split_rows<PATH>(Y[g + 1], raw[g + 1]);
+            __builtin_amdgcn_sched_barrier(0x0002);
+            // term-major: consecutive matrix-core ops write different accumulators
 #pragma unroll
-            for (int ra = 0; ra < WT; ++ra)
+            for (int term = 0; term < 3; ++term)
 #pragma unroll
-                for (int rb = 0; rb < WT; ++rb) {
-                    if (!(MASK & (1 << (2 * ra + rb))))
-                        continue;
-                    acc[ra][rb] = Ops::mma(yh[ra], th[rb], acc[ra][rb]);
-                    acc[ra][rb] = Ops::mma(yh[ra], tl[rb], acc[ra][rb]);
-                    acc[ra][rb] = Ops::mma(yl[ra], th[rb], acc[ra][rb]);
+                for (int cb = 0; cb < NCOL; ++cb) {
+                    const Win &w = V[g + 2 * cb];
+                    acc[cb] = Ops::mma(term == 2 ? Y[g].yl : Y[g].yh,
+                                       Ops::from_bits(term == 1 ? w.b : w.a), acc[cb]);
                 }
-        } else {
-            float y[WT][8], t[WT][8];
-#pragma unroll
-            for (int ra = 0; ra < WT; ++ra) {
-                if (!(MASK & (3 << (2 * ra))))
-                    continue;
-                const int o = ib + 32 * (rowbase + ra) + rl + 1;
-                float xa[8];
-                unpack8(sxa[o], sxa[o + 4], xa);
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    y[ra][j] = xi[j] * xa[j];
-            }
-#pragma unroll
-            for (int rb = 0; rb < WT; ++rb) {
-                if (!(MASK & (5 << rb)))
-                    continue;
-                const int o = ib + 32 * (colbase + rb) + rl;
-                const float4 *sb = (const float4 *)sxb;
-                unpack8(sb[o], sb[o + 4], t[rb]);
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-#pragma unroll
-                for (int ra = 0; ra < WT; ++ra)
-#pragma unroll
-                    for (int rb = 0; rb < WT; ++rb) {
-                        if (!(MASK & (1 << (2 * ra + rb))))
-                            continue;
-                        acc[ra][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                            y[ra][j], t[rb][j], acc[ra][rb], 0, 0, 0);
-                    }
+            __builtin_amdgcn_sched_barrier(0x0002);
         }
+    } else {
+        static_assert(SPLIT, "the FP32 path uses chunk_compute_fp32");
     }
 }
 
-// Wave window inside a tile.  Off-diagonal tiles: wave w owns the 2x2 (WT=2)
-// or 1x1 (WT=1) block window at (2*(w/2), 2*(w%2)) resp. (w/2, w%2).  In a
-// diagonal WT=2 tile the 10 lower blocks are split 3/3/2/2 over the waves so
-// that the tile costs 3 block-steps instead of 4.
-__device__ inline void wave_window(int WT, bool diag, int wave, int tileR, int NBR,
-                                   int &rowbase, int &colbase, int &mask)
+// FP32 path: each wave owns a 2 x 2 window of 32 x 32 blocks (rows
+// rowbase, rowbase+1; columns colbase, colbase+1 of the tile), MASK bit
+// (2 ra + rb) marking the active ones.  8 matrix-core steps per block per
+// 16-sample group; the operands of group g+1 are read while group g runs.
+template <int MASK>
+__device__ inline void chunk_compute_fp32(const float4 *__restrict__ sxi,
+                                          const float4 *__restrict__ sxa,
+                                          const uint4 *__restrict__ sxb, int rowbase,
+                                          int colbase, int rl, int h, floatx16 (&acc)[4],
+                                          double (&acc64)[4][16])
 {
-    if (WT == 2) {
-        if (!diag) {
-            rowbase = 2 * (wave >> 1);
-            colbase = 2 * (wave & 1);
-            mask = 0xF;
-        } else if (wave < 2) {
-            rowbase = colbase = 2 * wave;
-            mask = 0xD;           // (0,0) (1,0) (1,1)
-        } else {
-            rowbase = 2;
-            colbase = wave - 2;
-            mask = 0x5;           // (0,0) (1,0)
+    constexpr int NG = KC / GROUP;
+    constexpr int FG = FlushPeriod<HOS_PATH_FP32>::GROUPS;
+    constexpr bool R0 = (MASK & 3) != 0, R1 = (MASK & 12) != 0;
+    constexpr bool C0 = (MASK & 5) != 0, C1 = (MASK & 10) != 0;
+    auto fetch = [&](int g, RowRaw (&rr)[2], Win (&tt)[2]) __attribute__((always_inline)) {
+        fetch_rows(rr[0], sxi, sxa, g, rowbase, rl, h);
+        if (R1) {
+            const int ib = g * GROUP + 8 * h;
+            const int o = ib + 32 * (rowbase + 1) + rl + 1;
+            rr[1].xa0 = sxa[o];
+            rr[1].xa1 = sxa[o + 4];
         }
-    } else {
-        rowbase = wave >> 1;
-        colbase = wave & 1;
-        mask = (diag && colbase > rowbase) ? 0 : 1;
+        if (C0)
+            fetch_win<HOS_PATH_FP32>(tt[0], sxb, 0, g + 2 * colbase, rl, h);
+        if (C1)
+            fetch_win<HOS_PATH_FP32>(tt[1], sxb, 0, g + 2 * colbase + 2, rl, h);
+    };
+    RowRaw r[2], rn[2];
+    Win t[2], tn[2];
+    fetch(0, r, t);
+#pragma unroll 1
+    for (int g = 0; g < NG; ++g) {
+        fetch((g + 1) & (NG - 1), rn, tn);   // wraps to a valid, unused group
+        float xi[8], y[2][8], tv[2][8];
+        unpack8(r[0].xi0, r[0].xi1, xi);
+#pragma unroll
+        for (int ra = 0; ra < 2; ++ra) {
+            float xa[8];
+            unpack8(r[ra].xa0, r[ra].xa1, xa);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                y[ra][j] = xi[j] * xa[j];
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+            unpack8(__builtin_bit_cast(float4, t[rb].a), __builtin_bit_cast(float4, t[rb].b),
+                    tv[rb]);
+        __builtin_amdgcn_sched_barrier(0x0002);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+                    if (MASK & (1 << (2 * ra + rb)))
+                        acc[2 * ra + rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                            y[ra][j], tv[rb][j], acc[2 * ra + rb], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0x0002);
+        r[0] = rn[0];
+        r[1] = rn[1];
+        t[0] = tn[0];
+        t[1] = tn[1];
+        if ((g + 1) % FG == 0)
+            flush_acc<4, false>(acc, acc64);
     }
-    // rows at or beyond NBR 32-blocks (r >= M rounded up) do not exist
-    for (int ra = 0; ra < WT; ++ra)
-        if (tileR * 2 * WT + rowbase + ra >= NBR)
+}
+
+// FP32 wave window inside a 128 x 128 tile.  Off the diagonal wave w owns the
+// 2 x 2 blocks at (2 (w/2), 2 (w%2)); on a diagonal tile the 10 blocks on or
+// below the diagonal are split 3/3/2/2 so the tile costs 3 block-steps.
+__device__ inline void fp32_window(bool diag, int wave, int tileR, int NBR, int &rowbase,
+                                   int &colbase, int &mask)
+{
+    if (!diag) {
+        rowbase = 2 * (wave >> 1);
+        colbase = 2 * (wave & 1);
+        mask = 0xF;
+    } else if (wave < 2) {
+        rowbase = colbase = 2 * wave;
+        mask = 0xD;   // (0,0) (1,0) (1,1)
+    } else {
+        rowbase = 2;
+        colbase = wave - 2;
+        mask = 0x5;   // (0,0) (1,0)
+    }
+    for (int ra = 0; ra < 2; ++ra)
+        if (tileR * 4 + rowbase + ra >= NBR)
             mask &= ~(3 << (2 * ra));
 }
 
-template <int PATH, int WT>
-__device__ inline void dispatch_compute(int mask, const float4 *sxi, const float4 *sxa,
-                                        const uint4 *sxb, int wlen, int rowbase, int colbase,
-                                        int rl, int h, floatx16 (&acc)[WT][WT])
+__device__ inline void dispatch_fp32(int mask, const float4 *sxi, const float4 *sxa,
+                                     const uint4 *sxb, int rowbase, int colbase, int rl, int h,
+                                     floatx16 (&acc)[4], double (&acc64)[4][16])
 {
-    if constexpr (WT == 2) {
-        switch (mask) {
-        case 0xF:
-            chunk_compute<PATH, 2, 0xF>(sxi, sxa, sxb, wlen, rowbase, colbase, rl, h, acc);
-            break;
-        case 0xD:
-            chunk_compute<PATH, 2, 0xD>(sxi, sxa, sxb, wlen, rowbase, colbase, rl, h, acc);
-            break;
-        case 0x5:
-            chunk_compute<PATH, 2, 0x5>(sxi, sxa, sxb, wlen, rowbase, colbase, rl, h, acc);
-            break;
-        case 0x3:
-            chunk_compute<PATH, 2, 0x3>(sxi, sxa, sxb, wlen, rowbase, colbase, rl, h, acc);
-            break;
-        case 0x1:
-            chunk_compute<PATH, 2, 0x1>(sxi, sxa, sxb, wlen, rowbase, colbase, rl, h, acc);
-            break;
-        default:
-            break;  // 0: nothing to do
-        }
-    } else {
-        if (mask & 1)
-            chunk_compute<PATH, 1, 0x1>(sxi, sxa, sxb, wlen, rowbase, colbase, rl, h, acc);
+    switch (mask) {
+    case 0xF: chunk_compute_fp32<0xF>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
+    case 0xD: chunk_compute_fp32<0xD>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
+    case 0x5: chunk_compute_fp32<0x5>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
+    case 0x3: chunk_compute_fp32<0x3>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
+    case 0x1: chunk_compute_fp32<0x1>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
+    default: break;
+    }
+}
+
+// Active column blocks of wave rw's strip in a tile: all NB off the
+// diagonal, rw + 1 on a diagonal tile (blocks above it are outside F), none
+// for strips at or beyond the last 32-row block (rows r >= M).
+__device__ inline int wave_cols(int NB, bool diag, int rw, int tileR, int NBR)
+{
+    if (tileR * NB + rw >= NBR)
+        return 0;
+    return diag ? rw + 1 : NB;
+}
+
+template <int PATH, int NB>
+__device__ inline void dispatch_compute(int ncol, const float4 *sxi, const float4 *sxa,
+                                        const uint4 *sxb, int wlen, int rw, int rl, int h,
+                                        floatx16 (&acc)[NB], double (&acc64)[NB][16])
+{
+    switch (ncol) {
+    case 1:
+        chunk_compute<PATH, NB, 1>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+        break;
+    case 2:
+        chunk_compute<PATH, NB, 2>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+        break;
+    case 3:
+        if constexpr (NB >= 3)
+            chunk_compute<PATH, NB, 3>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+        break;
+    case 4:
+        if constexpr (NB >= 4)
+            chunk_compute<PATH, NB, 4>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+        break;
+    default:
+        break;  // 0: this strip has no output in the tile
     }
 }
 
 // One chunk's LDS operands (xi | xa | xb, contiguous 16-byte entries).
-template <int PATH, int WT>
+template <int PATH, int NB>
 struct ChunkLds {
     static constexpr bool SPLIT = PATH != HOS_PATH_FP32;
-    static constexpr int TS = 64 * WT;
+    static constexpr int NW = NB;                   // waves per workgroup
+    static constexpr int TS = 32 * NB;
     static constexpr int WLEN = KC + TS;            // window entries per chunk
     static constexpr int NXI = KC / 4;              // float4 entries of x_i
     static constexpr int NXB = SPLIT ? 2 * WLEN : WLEN;
     static constexpr int TOTAL = NXI + WLEN + NXB;  // 16-byte entries
     static constexpr int NCH = TOTAL / 64;          // 1 KB wave-chunks
-    static constexpr int NPW = (NCH + 3) / 4;       // wave-chunks per wave
+    static constexpr int NPW = (NCH + NW - 1) / NW; // wave-chunks per wave
     static_assert(NXI % 64 == 0 && WLEN % 64 == 0, "regions must be wave-chunk aligned");
     float4 xi[NXI];
     float4 xa[WLEN];
     uint4 xb[NXB];
 };
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // promotable 16-byte unit
+
 // Global loads of one chunk into registers: wave-chunk j (64 consecutive
-// 16-byte entries, one per lane) is handled by wave j % 4, so every branch
+// 16-byte entries, one per lane) is handled by wave j % NW, so every branch
 // below is wave-uniform and each load is a fully coalesced 1 KB read.
-template <int PATH, int WT, int NPW>
+template <int PATH, int NB, int NPW>
 __device__ __attribute__((always_inline)) inline void
-load_chunk(u32x4 (&stg)[NPW], const float *__restrict__ xf,
-           const uint4 *__restrict__ win4, const uint4 *__restrict__ win8h,
-           const uint4 *__restrict__ win8l, const SkPos &p, int wave, int lane)
+load_chunk(u32x4 (&stg)[NPW], const float *__restrict__ xf, const uint4 *__restrict__ win4,
+           const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l, const SkPos &p,
+           int wave, int lane)
 {
-    typedef ChunkLds<PATH, WT> CL;
+    typedef ChunkLds<PATH, NB> CL;
     const int64_t i0 = p.c * KC;
     const int64_t ra0 = i0 + (int64_t)p.R * CL::TS, rb0 = i0 + (int64_t)p.Cc * CL::TS;
     const u32x4 *xf4 = (const u32x4 *)xf;
     const u32x4 *w4 = (const u32x4 *)win4, *w8h = (const u32x4 *)win8h,
                 *w8l = (const u32x4 *)win8l;
 #pragma unroll
-    for (int m = 0; m < CL::NPW; ++m) {
-        const int j = wave + 4 * m;
+    for (int m = 0; m < NPW; ++m) {
+        const int j = wave + CL::NW * m;
         const int e = 64 * j;    // first entry of the wave-chunk
         const u32x4 *src;
         if (e < CL::NXI)
@@ -287,42 +439,29 @@ load_chunk(u32x4 (&stg)[NPW], const float *__restrict__ xf,
     }
 }
 
-template <int PATH, int WT, int NPW>
+template <int PATH, int NB, int NPW>
 __device__ __attribute__((always_inline)) inline void
-store_chunk(const u32x4 (&stg)[NPW], ChunkLds<PATH, WT> &L, int wave, int lane)
+store_chunk(const u32x4 (&stg)[NPW], ChunkLds<PATH, NB> &L, int wave, int lane)
 {
-    typedef ChunkLds<PATH, WT> CL;
+    typedef ChunkLds<PATH, NB> CL;
     u32x4 *base = (u32x4 *)&L;
 #pragma unroll
-    for (int m = 0; m < CL::NPW; ++m) {
-        const int j = wave + 4 * m;
+    for (int m = 0; m < NPW; ++m) {
+        const int j = wave + CL::NW * m;
         if (j < CL::NCH)
             base[64 * j + lane] = stg[m];
     }
 }
 
-template <int PATH, int WT>
-__device__ inline void flush_acc(floatx16 (&acc)[WT][WT], double (&acc64)[WT][WT][16])
-{
-#pragma unroll
-    for (int ra = 0; ra < WT; ++ra)
-#pragma unroll
-        for (int rb = 0; rb < WT; ++rb)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                acc64[ra][rb][v] += (double)acc[ra][rb][v];
-                acc[ra][rb][v] = 0.0f;
-            }
-}
-
-template <int PATH, int WT>
-__global__ void __launch_bounds__(256, 1)
+// The persistent contraction kernel: NB waves per workgroup, wave rw owning
+// the 32-row strip rw of every tile it visits.
+template <int PATH, int NB>
+__global__ void __launch_bounds__(64 * NB, 1)
 k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
               const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
               double *__restrict__ part, SkGeom g, int64_t smax, int NBR)
 {
-    typedef ChunkLds<PATH, WT> CL;
-    constexpr int NB = 2 * WT;                    // 32-blocks per tile side
+    typedef ChunkLds<PATH, NB> CL;
     constexpr int64_t TILE = (int64_t)CL::TS * CL::TS;
 
     __shared__ CL buf[2];
@@ -338,27 +477,35 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
         return;
     const int64_t tfirst = sk_tile_index(q.R, q.Cc);
 
-    floatx16 acc[WT][WT];
-    double acc64[WT][WT][16];
+    floatx16 acc[NB];
+    double acc64[NB][16];
 #pragma unroll
-    for (int ra = 0; ra < WT; ++ra)
+    for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < WT; ++rb)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                acc[ra][rb][v] = 0.0f;
-                acc64[ra][rb][v] = 0.0;
-            }
+        for (int v = 0; v < 16; ++v) {
+            acc[cb][v] = 0.0f;
+            acc64[cb][v] = 0.0;
+            if (PATH != HOS_PATH_FP32)
+                pin_agpr(acc64[cb][v]);
+        }
 
-    int rowbase, colbase, mask;
-    wave_window(WT, q.Cc == q.R, wave, q.R, NBR, rowbase, colbase, mask);
-    mask = __builtin_amdgcn_readfirstlane(mask);
-    rowbase = __builtin_amdgcn_readfirstlane(rowbase);
-    colbase = __builtin_amdgcn_readfirstlane(colbase);
+    // split paths: wave = row strip with ncol column blocks; FP32: 2 x 2 window
+    int ncol = 0, rowbase = 0, colbase = 0, mask = 0;
+    auto set_layout = [&](const SkPos &p) {
+        if constexpr (PATH == HOS_PATH_FP32) {
+            fp32_window(p.Cc == p.R, wave, p.R, NBR, rowbase, colbase, mask);
+            mask = __builtin_amdgcn_readfirstlane(mask);
+            rowbase = __builtin_amdgcn_readfirstlane(rowbase);
+            colbase = __builtin_amdgcn_readfirstlane(colbase);
+        } else {
+            ncol = __builtin_amdgcn_readfirstlane(wave_cols(NB, p.Cc == p.R, wave, p.R, NBR));
+        }
+    };
+    set_layout(q);
 
     u32x4 stg[CL::NPW];
-    load_chunk<PATH, WT, CL::NPW>(stg, xf, win4, win8h, win8l, q, wave, lane);
-    store_chunk<PATH, WT, CL::NPW>(stg, buf[0], wave, lane);
+    load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, q, wave, lane);
+    store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane);
     __syncthreads();
 
     // Each step prefetches the next chunk into registers, computes on the
@@ -371,42 +518,54 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
         SkPos nq = q;
         const bool has_next = sk_next(g, nq) && sk_chunk_start(g, nq.R, nq.Cc, nq.c) < S1;
         if (has_next)
-            load_chunk<PATH, WT, CL::NPW>(stg, xf, win4, win8h, win8l, nq, wave, lane);
+            load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, nq, wave, lane);
 
-        dispatch_compute<PATH, WT>(mask, buf[cur].xi, buf[cur].xa, buf[cur].xb, CL::WLEN,
-                                   rowbase, colbase, rl, h, acc);
-        flush_acc<PATH, WT>(acc, acc64);
+        if constexpr (PATH == HOS_PATH_FP32) {
+            static_assert(NB == 4, "the FP32 wave layout assumes 4 x 4-block tiles");
+            dispatch_fp32(mask, buf[cur].xi, buf[cur].xa, buf[cur].xb, rowbase, colbase, rl, h,
+                          acc, acc64);
+        } else {
+            dispatch_compute<PATH, NB>(ncol, buf[cur].xi, buf[cur].xa, buf[cur].xb, CL::WLEN,
+                                       wave, rl, h, acc, acc64);
+        }
+        if constexpr (PATH != HOS_PATH_FP32)   // the FP32 path flushes inside
+            flush_acc<NB, true>(acc, acc64);
 
         const bool seg_end = !has_next || nq.R != q.R || nq.Cc != q.Cc;
         if (seg_end) {
             const int64_t t = sk_tile_index(q.R, q.Cc);
             double *dst = part + (w * smax + (t - tfirst)) * TILE;
 #pragma unroll
-            for (int ra = 0; ra < WT; ++ra)
-#pragma unroll
-                for (int rb = 0; rb < WT; ++rb) {
-                    if (mask & (1 << (2 * ra + rb))) {
-                        const int blk = (rowbase + ra) * NB + (colbase + rb);
-#pragma unroll
-                        for (int v = 0; v < 16; ++v)
-                            dst[(blk * 16 + v) * 64 + lane] = acc64[ra][rb][v];
-                    }
+            for (int cb = 0; cb < NB; ++cb) {
+                bool on;
+                int blk;
+                if constexpr (PATH == HOS_PATH_FP32) {
+                    on = (mask >> cb) & 1;
+                    blk = (rowbase + (cb >> 1)) * NB + colbase + (cb & 1);
+                } else {
+                    on = cb < ncol;
+                    blk = wave * NB + cb;
+                }
+                if (on) {
 #pragma unroll
                     for (int v = 0; v < 16; ++v)
-                        acc64[ra][rb][v] = 0.0;
+                        dst[(blk * 16 + v) * 64 + lane] = acc64[cb][v];
                 }
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    acc64[cb][v] = 0.0;
+                    if (PATH != HOS_PATH_FP32)
+                        pin_agpr(acc64[cb][v]);
+                }
+            }
         }
         if (!has_next)
             break;
         cur ^= 1;
-        store_chunk<PATH, WT, CL::NPW>(stg, buf[cur], wave, lane);
+        store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane);
         __syncthreads();
-        if (seg_end) {
-            wave_window(WT, nq.Cc == nq.R, wave, nq.R, NBR, rowbase, colbase, mask);
-            mask = __builtin_amdgcn_readfirstlane(mask);
-            rowbase = __builtin_amdgcn_readfirstlane(rowbase);
-            colbase = __builtin_amdgcn_readfirstlane(colbase);
-        }
+        if (seg_end)
+            set_layout(nq);
         q = nq;
     }
 }
@@ -414,13 +573,12 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
 // Sum the FP64 partial tiles of every workgroup that touched the tile, in
 // workgroup order, and scatter the 32 x 32 block to Cfull[a][b] (a = r + 1).
 // One workgroup per (tile, 32-block).
-template <int WT>
+template <int NB>
 __global__ void __launch_bounds__(256)
 k_c3_reduce(const double *__restrict__ part, SkGeom g, int64_t smax, int NBR, int M,
             double *__restrict__ cfull)
 {
-    constexpr int NB = 2 * WT;
-    constexpr int64_t TILE = (int64_t)(64 * WT) * (64 * WT);
+    constexpr int64_t TILE = (int64_t)(32 * NB) * (32 * NB);
     const int64_t t = blockIdx.x / (NB * NB);
     const int blk = blockIdx.x % (NB * NB);
     int R = 0;
@@ -457,18 +615,22 @@ k_c3_reduce(const double *__restrict__ part, SkGeom g, int64_t smax, int NBR, in
     }
 }
 
-// Leftover diagonal sums C[a][a] = sum_i x_i x_{i+a}^2 for a = 0 and
-// a = 32k <= M, in FP64 from the FP32 operand series (fixed-order partials).
+// Leftover diagonal sums C[a][a] = sum_i x~_i x~_{i+a}^2 for a = 0 and
+// a = 32k <= M, in FP64 from the input itself (x~ = (x - mean) s formed in
+// FP64, not the FP32 operand copy), as fixed-order partials.
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_diag_dot(const float *__restrict__ xf, int64_t n, int nblocks, double *__restrict__ dpart)
+k_diag_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats,
+           int nblocks, double *__restrict__ dpart)
 {
     __shared__ double red[256];
     const int left = blockIdx.x / nblocks, blk = blockIdx.x % nblocks;
     const int64_t a = 32 * (int64_t)left;
+    const double mu = stats[0], sc = stats[1];
     double s = 0.0;
-    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < n; i += (int64_t)nblocks * 256) {
-        const double u = xf[i + a];
-        s += (double)xf[i] * u * u;
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i + a < n; i += (int64_t)nblocks * 256) {
+        const double u = ((double)x[i + a] - mu) * sc;
+        s += (((double)x[i] - mu) * sc) * u * u;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -495,10 +657,10 @@ k_diag_final(const double *__restrict__ dpart, int nleft, int nblocks, int M,
     cfull[a * (M + 1) + a] = s;
 }
 
-template <int PATH, int WT>
+template <int PATH, int NB>
 void launch_contract_t(const C3Plan &p, char *ws, hipStream_t s)
 {
-    k_c3_contract<PATH, WT><<<p.sk.G, WG_THREADS, 0, s>>>(
+    k_c3_contract<PATH, NB><<<p.sk.G, 64 * NB, 0, s>>>(
         (const float *)(ws + p.off_xf), (const uint4 *)(ws + p.off_win4),
         (const uint4 *)(ws + p.off_win8h), (const uint4 *)(ws + p.off_win8l),
         (double *)(ws + p.off_part), p.sk, p.smax, p.NBR);
@@ -509,30 +671,32 @@ void launch_contract_t(const C3Plan &p, char *ws, hipStream_t s)
 hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s)
 {
     if (p.M > 0) {
-        if (p.WT == 2) {
+        if (p.NB == 4) {
             if (p.path == HOS_PATH_FP32)
-                launch_contract_t<HOS_PATH_FP32, 2>(p, ws, s);
+                launch_contract_t<HOS_PATH_FP32, 4>(p, ws, s);
             else if (p.path == HOS_PATH_SPLIT_FP16)
+                launch_contract_t<HOS_PATH_SPLIT_FP16, 4>(p, ws, s);
+            else
+                launch_contract_t<HOS_PATH_SPLIT_BF16, 4>(p, ws, s);
+        } else {
+            if (p.path == HOS_PATH_SPLIT_FP16)
                 launch_contract_t<HOS_PATH_SPLIT_FP16, 2>(p, ws, s);
             else
                 launch_contract_t<HOS_PATH_SPLIT_BF16, 2>(p, ws, s);
-        } else {
-            if (p.path == HOS_PATH_FP32)
-                launch_contract_t<HOS_PATH_FP32, 1>(p, ws, s);
-            else if (p.path == HOS_PATH_SPLIT_FP16)
-                launch_contract_t<HOS_PATH_SPLIT_FP16, 1>(p, ws, s);
-            else
-                launch_contract_t<HOS_PATH_SPLIT_BF16, 1>(p, ws, s);
         }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_diag_dot(const C3Plan &p, char *ws, hipStream_t s)
+hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws, hipStream_t s)
 {
-    k_diag_dot<<<p.nleft * p.dot_blocks, 256, 0, s>>>((const float *)(ws + p.off_xf), p.n,
-                                                     p.dot_blocks,
-                                                     (double *)(ws + p.off_dpart));
+    const double *stats = (const double *)(ws + p.off_stats);
+    double *dpart = (double *)(ws + p.off_dpart);
+    const int grid = p.nleft * p.dot_blocks;
+    if (dtype == HOS_F64)
+        k_diag_dot<double><<<grid, 256, 0, s>>>((const double *)x, p.n, stats, p.dot_blocks, dpart);
+    else
+        k_diag_dot<float><<<grid, 256, 0, s>>>((const float *)x, p.n, stats, p.dot_blocks, dpart);
     return hipGetLastError();
 }
 
@@ -541,12 +705,12 @@ hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s)
     double *cfull = (double *)(ws + p.off_cfull);
     if (p.M > 0) {
         const int64_t ntiles = (int64_t)p.sk.TR * (p.sk.TR + 1) / 2;
-        const int NB = 2 * p.WT;
-        if (p.WT == 2)
-            k_c3_reduce<2><<<ntiles * NB * NB, 256, 0, s>>>((const double *)(ws + p.off_part),
+        const int NB = p.NB;
+        if (NB == 4)
+            k_c3_reduce<4><<<ntiles * NB * NB, 256, 0, s>>>((const double *)(ws + p.off_part),
                                                           p.sk, p.smax, p.NBR, p.M, cfull);
         else
-            k_c3_reduce<1><<<ntiles * NB * NB, 256, 0, s>>>((const double *)(ws + p.off_part),
+            k_c3_reduce<2><<<ntiles * NB * NB, 256, 0, s>>>((const double *)(ws + p.off_part),
                                                           p.sk, p.smax, p.NBR, p.M, cfull);
     }
     k_diag_final<<<(p.nleft + 63) / 64, 64, 0, s>>>((const double *)(ws + p.off_dpart),

