@@ -28,12 +28,21 @@
  *            Internally x~ is multiplied by an exact power of two chosen
  *            from max|x~| and divided out again, so results do not depend
  *            on the input scale.
+ *            c4(t1,t2,t3) = m4(t1,t2,t3) - c2(t1) c2(t3-t2) - c2(t2) c2(t3-t1)
+ *            - c2(t3) c2(t2-t1), with m4 and c2 the sample moments of x~
+ *            formed the same way (the zero-mean moment-to-cumulant relation;
+ *            Section 1 defines cumulants through the moments).
  * Layouts.   c3: (2M+1)^2 row-major float64, lag (w1,w2) at
  *            (w1+M)*(2M+1) + (w2+M); lags with |w1-w2| > M are 0.
  *            B: nfft x nfft interleaved complex128, row-major, frequency
  *            (k1,k2) at k1*nfft + k2, unshifted.
  *            B(k1,k2) = sum_w W(w) c3(w) exp(-2 pi i (k1 w1 + k2 w2)/nfft),
  *            unnormalised, with the sign of the DFT in Algorithm DBS step 3.
+ *            c4: (2M+1)^3 row-major float64, lag (t1,t2,t3) at
+ *            ((t1+M)*(2M+1) + (t2+M))*(2M+1) + (t3+M); lags whose span
+ *            max(0,t1,t2,t3) - min(0,t1,t2,t3) exceeds M are 0.
+ *            T: nfft^3 interleaved complex128, frequency (k1,k2,k3) at
+ *            (k1*nfft + k2)*nfft + k3, unshifted, the 3-D analogue of B.
  * Threading. Calls are re-entrant; concurrent calls must use distinct
  *            workspaces.
  */
@@ -165,6 +174,52 @@ int hos_c3_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  */
 int hos_c3_schedule(int64_t n, int32_t M, int32_t path, int64_t *owner, int64_t *slot,
                     int64_t *rslot, int64_t cap);
+
+/*
+ * Workspace size for hos_trispectrum; arguments as for
+ * hos_bispectrum_workspace, with the limits of hos_trispectrum.
+ */
+int hos_trispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
+                              uint32_t flags, size_t *bytes);
+
+/*
+ * Fourth-order cumulant and smoothed trispectrum of one series (Section 1
+ * "Problem Statement"; the indirect method one order up, as Section 3's
+ * k-th order generalisation describes).  Arguments as for hos_bispectrum,
+ * except:
+ *   M        maximum lag, 0 <= M <= 127 and M < n.
+ *   nfft     DFT size per axis, 2 <= nfft <= 512, nfft = 2^a 3^b 5^c,
+ *            nfft >= 2M (Parzen) / 2M+1 (no window); ignored when T is NULL.
+ *   c4       device, (2M+1)^3 float64 (layout above), or NULL.
+ *   T        device, nfft^3 complex128 (layout above), or NULL.
+ * At least one of c4 and T must be non-NULL.  With HOS_WIN_PARZEN the lag
+ * window is the product of d(m), scale L = M, over the six pairwise
+ * differences of {0, t1, t2, t3}.
+ */
+int hos_trispectrum(const void *x, int32_t dtype, int64_t n, int32_t M,
+                    int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                    double *c4, double *T, void *ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/*
+ * hos_trispectrum with per-stage timing (see hos_bispectrum_timed): WAITS
+ * for the stream and writes 7 floats of milliseconds to stage_ms (host):
+ * [0] mean/range pass, [1] operand preparation, [2] contraction,
+ * [3] partial reduction + second-order moments, [4] cumulant assembly,
+ * window and fold (+ twiddles), [5] DFT, [6] total.
+ */
+int hos_trispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M,
+                          int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                          double *c4, double *T, void *ws, size_t ws_bytes,
+                          hipStream_t stream, float *stage_ms);
+
+/*
+ * Host-only plan of the fourth-order contraction (no HIP call).  info
+ * (host) receives: lag pairs, 32-pair blocks, 32-column blocks, staged
+ * window samples, sample-axis ranges, chunks per range, chunks, workspace
+ * bytes.  ninfo >= 8.  HOS_EINVAL on bad sizes.
+ */
+int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo);
 
 #ifdef __cplusplus
 }

@@ -11,9 +11,9 @@ Two layers:
 * the raw C entry points under their C names (the library is loaded on
   first use, so building never needs an already-built copy) (``hos_bispectrum``, ...),
   taking integer device addresses;
-* ``bispectrum(x, M, ...)``: allocates the outputs and the workspace as
-  torch tensors on ``x.device`` and calls ``hos_bispectrum`` on the current
-  stream.
+* ``bispectrum(x, M, ...)`` / ``trispectrum(x, M, ...)``: allocate the
+  outputs and the workspace as torch tensors on ``x.device`` and call
+  ``hos_bispectrum`` / ``hos_trispectrum`` on the current stream.
 """
 from __future__ import annotations
 
@@ -72,6 +72,14 @@ def _load_lib():
                                                 vp, vp, vp, sz, vp,
                                                 ctypes.POINTER(ctypes.c_float)]),
         "hos_c3_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
+        "hos_trispectrum_workspace": (ctypes.c_int, [i64, i32, i32, i32, u32,
+                                                     ctypes.POINTER(sz)]),
+        "hos_trispectrum": (ctypes.c_int, [vp, i32, i64, i32, i32, i32, i32, u32,
+                                           vp, vp, vp, sz, vp]),
+        "hos_trispectrum_timed": (ctypes.c_int, [vp, i32, i64, i32, i32, i32, i32, u32,
+                                                 vp, vp, vp, sz, vp,
+                                                 ctypes.POINTER(ctypes.c_float)]),
+        "hos_c4_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
         "hos_c3_schedule": (ctypes.c_int, [i64, i32, i32, p64, p64, p64, i64]),
     }
     for name, (res, args) in sig.items():
@@ -155,6 +163,45 @@ def hos_c3_schedule(n, M, path):
     return tuple(list(a)[:cap] for a in arrs)
 
 
+def hos_trispectrum_workspace(n, M, nfft, path, flags=0) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().hos_trispectrum_workspace(int(n), int(M), int(nfft), int(path), int(flags),
+                                        ctypes.byref(out))
+    if st != HOS_OK:
+        raise HosError(st, "hos_trispectrum_workspace")
+    return out.value
+
+
+def hos_trispectrum(x_ptr, dtype, n, M, window, nfft, path, flags, c4_ptr, T_ptr,
+                    ws_ptr, ws_bytes, stream) -> int:
+    """Raw call; returns the status code (does not raise)."""
+    return lib().hos_trispectrum(x_ptr, int(dtype), int(n), int(M), int(window), int(nfft),
+                                int(path), int(flags), c4_ptr, T_ptr, ws_ptr,
+                                int(ws_bytes), stream)
+
+
+STAGES4 = ("moments", "prep", "contract", "reduce", "finish", "dft", "total")
+
+
+def hos_trispectrum_timed(x_ptr, dtype, n, M, window, nfft, path, flags, c4_ptr, T_ptr,
+                          ws_ptr, ws_bytes, stream):
+    """Raw timed call; returns (status, {stage: milliseconds})."""
+    ms = (ctypes.c_float * 7)()
+    st = lib().hos_trispectrum_timed(x_ptr, int(dtype), int(n), int(M), int(window),
+                                    int(nfft), int(path), int(flags), c4_ptr, T_ptr, ws_ptr,
+                                    int(ws_bytes), stream, ms)
+    return st, dict(zip(STAGES4, list(ms)))
+
+
+def hos_c4_plan_info(n, M, path) -> dict:
+    buf = (ctypes.c_int64 * 8)()
+    st = lib().hos_c4_plan_info(int(n), int(M), int(path), buf, 8)
+    if st != HOS_OK:
+        raise HosError(st, "hos_c4_plan_info")
+    keys = ("P", "RB", "NCB", "WX", "S", "CPS", "C", "ws_bytes")
+    return dict(zip(keys, list(buf)))
+
+
 # ------------------------------------------------------------- torch layer
 def _next_fft_size(m: int) -> int:
     k = max(2, int(m))
@@ -214,3 +261,42 @@ def bispectrum(x, M: int, nfft: int | None = None, window: str = "parzen",
     if st != HOS_OK:
         raise HosError(st, "hos_bispectrum")
     return c3, B
+
+
+def trispectrum(x, M: int, nfft: int | None = None, window: str = "parzen",
+                path: str = "fp32", center: bool = True, return_c4: bool = True,
+                return_T: bool = True, workspace=None):
+    """c4 over |t| <= M ((2M+1)^3 float64) and the windowed 3D DFT T
+    (nfft^3 complex128) of a 1-D float32/float64 CUDA tensor.
+
+    Returns (c4 or None, T or None).  ``workspace`` may be a uint8 CUDA
+    tensor of at least ``hos_trispectrum_workspace`` bytes to reuse.
+    """
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError("x must be a CUDA tensor")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
+    x = x.contiguous().view(-1)
+    n = x.numel()
+    pth = PATHS[path]
+    win = WINDOWS[window]
+    if nfft is None:
+        nfft = default_nfft(M, window)
+    flags = 0 if center else HOS_NO_CENTER
+    ws_bytes = hos_trispectrum_workspace(n, M, nfft if return_T else 0, pth, flags)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=x.device)
+    S = 2 * M + 1
+    c4 = torch.empty((S, S, S), dtype=torch.float64,
+                     device=x.device) if return_c4 else None
+    T = torch.empty((nfft, nfft, nfft), dtype=torch.complex128,
+                    device=x.device) if return_T else None
+    st = hos_trispectrum(x.data_ptr(), HOS_F64 if x.dtype == torch.float64 else HOS_F32,
+                         n, M, win, nfft if return_T else 0, pth, flags,
+                         c4.data_ptr() if c4 is not None else None,
+                         T.data_ptr() if T is not None else None,
+                         workspace.data_ptr(), workspace.numel(), _stream_handle(x.device))
+    if st != HOS_OK:
+        raise HosError(st, "hos_trispectrum")
+    return c4, T

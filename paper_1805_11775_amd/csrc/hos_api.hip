@@ -19,6 +19,7 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     p.n = n;
     p.M = M;
     p.path = path;
+    p.scale_top = 7;
     // Split paths: 4 column blocks per wave amortise the product-row split
     // (2-block tiles for small M); FP32 path: 128 x 128 tiles with a 2 x 2
     // block window per wave.
@@ -70,6 +71,54 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     return HOS_OK;
 }
 
+int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p)
+{
+    memset(&p, 0, sizeof(p));
+    p.n = n;
+    p.M = M;
+    p.path = path;
+    p.scale_top = 5;
+    p.P = (M + 1) * (M + 2) / 2;
+    p.RB = (p.P + 31) / 32;
+    p.NCB = (M + 1 + 31) / 32;
+    p.WX = c4_window_entries(M);
+    p.C = (n + KC - 1) / KC;
+    // about two workgroups per compute unit; every range holds >= 1 chunk
+    const int64_t rbg = (p.RB + 3) / 4;
+    int64_t S = (512 + rbg - 1) / rbg;
+    if (S > p.C)
+        S = p.C;
+    if (S < 1)
+        S = 1;
+    const int64_t cps = (p.C + S - 1) / S;
+    p.CPS = (int32_t)cps;
+    p.S = (int32_t)((p.C + cps - 1) / cps);
+    p.npad = ((p.C * KC + p.WX + 64) + 63) / 64 * 64;
+    int64_t db = n / 4096;
+    p.dot_blocks = (int32_t)(db < 1 ? 1 : (db > 64 ? 64 : db));
+
+    size_t o = 0;
+    p.off_stats = o;  o = align256(o + 64 * sizeof(double));
+    p.off_mpart = o;  o = align256(o + MOM_BLOCKS * 3 * sizeof(double));
+    p.off_xf = o;     o = align256(o + (size_t)p.npad * sizeof(float));
+    p.off_win4 = o;   o = align256(o + (size_t)p.npad * 16);
+    if (path != HOS_PATH_FP32) {
+        p.off_win8h = o;  o = align256(o + (size_t)p.npad * 16);
+        p.off_win8l = o;  o = align256(o + (size_t)p.npad * 16);
+    }
+    p.off_part = o;
+    o = align256(o + (size_t)p.S * p.RB * p.NCB * 1024 * sizeof(double));
+    p.off_m4 = o;     o = align256(o + (size_t)p.P * (M + 1) * sizeof(double));
+    p.off_c2part = o; o = align256(o + (size_t)(M + 1) * p.dot_blocks * sizeof(double));
+    p.off_c2 = o;     o = align256(o + (size_t)(M + 1) * sizeof(double));
+    if (nfft > 0) {
+        p.off_twid = o;
+        o = align256(o + (size_t)nfft * 2 * sizeof(double));
+    }
+    p.total = o;
+    return HOS_OK;
+}
+
 static bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr & (a - 1)) == 0; }
 
 static int check_bispectrum_args(int64_t n, int32_t M, int32_t window, int32_t nfft,
@@ -95,6 +144,16 @@ static int check_bispectrum_args(int64_t n, int32_t M, int32_t window, int32_t n
         return HOS_EINVAL;
     }
     return HOS_OK;
+}
+
+static int check_trispectrum_args(int64_t n, int32_t M, int32_t window, int32_t nfft,
+                                  int32_t path, uint32_t flags, bool want_T)
+{
+    if (M > C4_MAX_M)
+        return HOS_EINVAL;
+    if (want_T && nfft > C4_MAX_NFFT)
+        return HOS_EINVAL;
+    return check_bispectrum_args(n, M, window, nfft, path, flags, want_T);
 }
 
 // Device gate: one check per device id, cached.
@@ -253,6 +312,127 @@ int hos_bispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M, int
     for (int k = 0; k < made; ++k)
         hipEventDestroy(ev[k]);
     return st;
+}
+
+int hos_trispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
+                              uint32_t flags, size_t *bytes)
+{
+    if (!bytes)
+        return HOS_EINVAL;
+    int st = check_trispectrum_args(n, M, HOS_WIN_NONE, nfft > 0 ? nfft : 0, path, flags,
+                                    false);
+    if (st != HOS_OK)
+        return st;
+    if (nfft > 0 && (!fft_size_ok(nfft) || nfft > C4_MAX_NFFT))
+        return HOS_EINVAL;
+    C4Plan p;
+    make_c4_plan(n, M, path, nfft, p);
+    *bytes = p.total;
+    return HOS_OK;
+}
+
+static int trispectrum_impl(const void *x, int32_t dtype, int64_t n, int32_t M,
+                            int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                            double *c4, double *T, void *ws, size_t ws_bytes,
+                            hipStream_t stream, hipEvent_t *ev)
+{
+    if (!x || !ws || (!c4 && !T))
+        return HOS_EINVAL;
+    if (dtype != HOS_F32 && dtype != HOS_F64)
+        return HOS_EINVAL;
+    if (!aligned(x, dtype == HOS_F64 ? 8 : 4) || !aligned(ws, 256))
+        return HOS_EINVAL;
+    if ((c4 && !aligned(c4, 8)) || (T && !aligned(T, 16)))
+        return HOS_EINVAL;
+    int st = check_trispectrum_args(n, M, window, T ? nfft : 0, path, flags, T != nullptr);
+    if (st != HOS_OK)
+        return st;
+    C4Plan p;
+    make_c4_plan(n, M, path, T ? nfft : 0, p);
+    if (ws_bytes < p.total)
+        return HOS_EWORKSPACE;
+    st = device_ok();
+    if (st != HOS_OK)
+        return st;
+
+    char *w = (char *)ws;
+    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], stream) : hipSuccess; };
+    double2 *tw = T ? (double2 *)(w + p.off_twid) : nullptr;
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = launch_moments(x, dtype, n, flags, p, w, stream);
+    if (e == hipSuccess) e = mark(1);
+    if (e == hipSuccess) e = launch_prep(x, dtype, p, w, stream);
+    if (e == hipSuccess) e = mark(2);
+    if (e == hipSuccess) e = launch_c4_contract(p, w, stream);
+    if (e == hipSuccess) e = mark(3);
+    if (e == hipSuccess) e = launch_c4_reduce(x, dtype, p, w, stream);
+    if (e == hipSuccess) e = mark(4);
+    if (e == hipSuccess && T) e = launch_twiddles(tw, nfft, stream);
+    if (e == hipSuccess) e = launch_c4_finish(p, window, nfft, c4, T, w, stream);
+    if (e == hipSuccess) e = mark(5);
+    if (e == hipSuccess && T) e = launch_fft3(T, nfft, tw, stream);
+    if (e == hipSuccess) e = mark(6);
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
+int hos_trispectrum(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                    int32_t nfft, int32_t path, uint32_t flags, double *c4, double *T,
+                    void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return trispectrum_impl(x, dtype, n, M, window, nfft, path, flags, c4, T, ws, ws_bytes,
+                            stream, nullptr);
+}
+
+int hos_trispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                          int32_t nfft, int32_t path, uint32_t flags, double *c4, double *T,
+                          void *ws, size_t ws_bytes, hipStream_t stream, float *stage_ms)
+{
+    if (!stage_ms)
+        return HOS_EINVAL;
+    hipEvent_t ev[7];
+    int made = 0;
+    for (; made < 7; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess)
+            break;
+    int st = made == 7 ? trispectrum_impl(x, dtype, n, M, window, nfft, path, flags, c4, T,
+                                          ws, ws_bytes, stream, ev)
+                       : HOS_EDEVICE;
+    if (st == HOS_OK) {
+        if (hipEventSynchronize(ev[6]) != hipSuccess) {
+            st = HOS_EDEVICE;
+        } else {
+            for (int k = 0; k < 6; ++k)
+                if (hipEventElapsedTime(&stage_ms[k], ev[k], ev[k + 1]) != hipSuccess)
+                    st = HOS_EDEVICE;
+            if (hipEventElapsedTime(&stage_ms[6], ev[0], ev[6]) != hipSuccess)
+                st = HOS_EDEVICE;
+        }
+    }
+    for (int k = 0; k < made; ++k)
+        hipEventDestroy(ev[k]);
+    return st;
+}
+
+// Host-only plan of the fourth-order contraction:
+// info[0..7] = P, RB, NCB, WX, S, CPS, C, workspace bytes.
+int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo)
+{
+    if (!info || ninfo < 8)
+        return HOS_EINVAL;
+    int st = check_trispectrum_args(n, M, HOS_WIN_NONE, 0, path, 0, false);
+    if (st != HOS_OK)
+        return st;
+    C4Plan p;
+    make_c4_plan(n, M, path, 0, p);
+    info[0] = p.P;
+    info[1] = p.RB;
+    info[2] = p.NCB;
+    info[3] = p.WX;
+    info[4] = p.S;
+    info[5] = p.CPS;
+    info[6] = p.C;
+    info[7] = (int64_t)p.total;
+    return HOS_OK;
 }
 
 // Host-only introspection of the contraction schedule (no HIP call):

@@ -142,29 +142,55 @@ inline int64_t sk_max_segments(const SkGeom &g)
 }
 
 // ---------------------------------------------------------------------------
-// Bispectrum plan and workspace layout (all offsets 256-byte aligned).
+// Series preparation shared by both estimators: the mean/range pass and the
+// operand tables (all workspace offsets 256-byte aligned).
 // ---------------------------------------------------------------------------
-struct C3Plan {
+struct SeriesPlan {
     int64_t n;
     int32_t M;
     int32_t path;      // hos_path
+    int32_t scale_top; // max|x~| * s lies in [2^(top-1), 2^top)
+    int64_t npad;      // padded series length (multiple of 64)
+    size_t off_stats, off_mpart, off_xf, off_win4, off_win8h, off_win8l;
+};
+
+// Bispectrum plan and workspace layout.
+struct C3Plan : SeriesPlan {
     int32_t NB;        // 32-blocks per tile side (2 or 4) = waves per workgroup
     int32_t TS;        // tile side in samples (32 * NB)
     int32_t NBR;       // 32-block rows: rows r = 0 .. M-1
     int32_t nleft;     // leftover diagonal sums C[a][a], a = 0 and a = 32k <= M
     int32_t dot_blocks;// workgroups per leftover sum
-    int64_t npad;      // padded series length (multiple of 64)
     int64_t smax;      // partial slots per workgroup
     SkGeom sk;
-    // workspace offsets in bytes
-    size_t off_stats, off_mpart, off_xf, off_win4, off_win8h, off_win8l;
     size_t off_part, off_cfull, off_dpart, off_twid, total;
 };
+
+// Trispectrum plan.  The lag pairs (a, b), 0 <= b <= a <= M, are numbered
+// with b ascending, then a; P = (M+1)(M+2)/2 pairs in RB blocks of 32.
+// The sample axis is split into S ranges of CPS chunks; workgroup (x, s)
+// runs pair blocks 4x .. 4x+3 over range s.
+struct C4Plan : SeriesPlan {
+    int32_t P;         // lag pairs
+    int32_t RB;        // 32-pair blocks
+    int32_t NCB;       // 32-column blocks of the third lag c = 0..M
+    int32_t WX;        // staged window beyond the chunk, in samples
+    int32_t S;         // sample-axis ranges
+    int32_t CPS;       // chunks per range
+    int32_t dot_blocks;// workgroups per c2 lag
+    int64_t C;         // chunks of KC samples
+    size_t off_part, off_m4, off_c2part, off_c2, off_twid, total;
+};
+
+constexpr int C4_MAX_M = 127;      // 4 column blocks per pair block
+constexpr int C4_MAX_NFFT = 512;   // N^3 complex128 <= 2 GiB
 
 constexpr int MOM_BLOCKS = 256;     // blocks of the moments pass
 constexpr int SK_MAX_WG = 256;      // persistent workgroups of the contraction
 
 int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p);
+int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p);
+int c4_window_entries(int M);
 
 // Element count of one FP64 partial tile.
 inline int64_t tile_elems(int NB) { return (int64_t)(32 * NB) * (32 * NB); }
@@ -173,8 +199,8 @@ inline int64_t tile_elems(int NB) { return (int64_t)(32 * NB) * (32 * NB); }
 // Launchers (enqueue on `s`, return hipError_t of the last launch).
 // ---------------------------------------------------------------------------
 hipError_t launch_moments(const void *x, int dtype, int64_t n, uint32_t flags,
-                          const C3Plan &p, char *ws, hipStream_t s);
-hipError_t launch_prep(const void *x, int dtype, const C3Plan &p, char *ws,
+                          const SeriesPlan &p, char *ws, hipStream_t s);
+hipError_t launch_prep(const void *x, int dtype, const SeriesPlan &p, char *ws,
                        hipStream_t s);
 hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s);
 hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws,
@@ -186,5 +212,10 @@ bool fft_size_ok(int N);
 hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s);
 hipError_t launch_fft2(double *B, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_fft3(double *T, int N, const double2 *tw, hipStream_t s);
+hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s);
+hipError_t launch_c4_reduce(const void *x, int dtype, const C4Plan &p, char *ws,
+                            hipStream_t s);
+hipError_t launch_c4_finish(const C4Plan &p, int window, int nfft, double *c4, double *T,
+                            char *ws, hipStream_t s);
 
 }  // namespace hos

@@ -1,0 +1,584 @@
+// k_c4.hip -- fourth-order cumulant (trispectrum path) on the matrix cores.
+//
+// The paper extends its bispectrum algorithms to the trispectrum (Section 1;
+// Section 3 states the k-th order generalisation).  The fourth-order sample
+// moment of the mean-removed series over its fundamental region
+// F4 = {0 <= c <= b <= a <= M},
+//     C4[a][b][c] = sum_i x_i x_{i+a} x_{i+b} x_{i+c},
+// is a contraction over the sample index i whose rows are the lag pairs
+// (a, b): the product row Y_ab[i] = x_i x_{i+a} x_{i+b} meets the Hankel
+// operand T[i][c] = x_{i+c}, for c <= b.  Pairs are numbered with b
+// ascending (then a), so a block of 32 consecutive pairs spans few values of
+// b and needs only ceil((b_max + 1) / 32) column blocks.
+//
+// The cumulant follows from the moments by the zero-mean moment-to-cumulant
+// relation (Section 1: cumulants are functions of the moments),
+//     c4(t1,t2,t3) = m4 - c2(t1) c2(t3-t2) - c2(t2) c2(t3-t1) - c2(t3) c2(t2-t1),
+// with the second-order moments c2(d) = (1/n) sum_i x_i x_{i+d} taken in FP64
+// from the input.  Every lag triple maps onto F4 by shifting the four sample
+// offsets {0, t1, t2, t3} by their minimum and sorting (the 24-fold symmetry).
+//
+// Arithmetic, staging and precision handling follow the c3 contraction:
+// FP32 (32x32x2) or FP16/BF16 hi+lo (32x32x16, three products) on the matrix
+// cores, FP32 accumulation flushed to FP64, FP64 partials summed in a fixed
+// order.  One workgroup = 4 waves = 4 pair blocks over a contiguous range of
+// 512-sample chunks; all pair blocks read the same staged window of x.
+#include "hos_internal.h"
+
+namespace hos {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void unpack8(float4 a, float4 b, float *v)
+{
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+// First pair index with second lag b (pairs ordered by b, then a).
+__host__ __device__ inline int pair_offset(int M, int b)
+{
+    return b * (M + 1) - b * (b - 1) / 2;
+}
+
+// (a, b) of pair p; M + 1 - b pairs share each b.
+__device__ inline void pair_ab(int M, int p, int &a, int &b)
+{
+    int bb = 0;
+    while (bb < M && pair_offset(M, bb + 1) <= p)
+        ++bb;
+    b = bb;
+    a = bb + (p - pair_offset(M, bb));
+}
+
+template <int PATH>
+struct C4Ops;
+
+template <>
+struct C4Ops<HOS_PATH_SPLIT_FP16> {
+    typedef halfx8 vec;
+    // hi/lo of p * q rounded from the exact product (see the c3 split)
+    __device__ static inline void split(const float *p, const float *q, vec &h, vec &l)
+    {
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t hv, lv;
+            asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(hv) : "v"(p[2 * k]), "v"(q[2 * k]));
+            asm("v_fma_mixhi_f16 %0, %1, %2, 0"
+                : "+v"(hv) : "v"(p[2 * k + 1]), "v"(q[2 * k + 1]));
+            asm("v_fma_mixlo_f16 %0, %1, %2, -%3 op_sel_hi:[0,0,1]"
+                : "=v"(lv) : "v"(p[2 * k]), "v"(q[2 * k]), "v"(hv));
+            asm("v_fma_mixhi_f16 %0, %1, %2, -%3 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+                : "+v"(lv) : "v"(p[2 * k + 1]), "v"(q[2 * k + 1]), "v"(hv));
+            hw[k] = hv;
+            lw[k] = lv;
+        }
+        h = __builtin_bit_cast(vec, hw);
+        l = __builtin_bit_cast(vec, lw);
+    }
+    __device__ static inline floatx16 mma(vec a, vec b, floatx16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct C4Ops<HOS_PATH_SPLIT_BF16> {
+    typedef bf16x8 vec;
+    __device__ static inline void split(const float *p, const float *q, vec &h, vec &l)
+    {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            __bf16 hh = (__bf16)(p[j] * q[j]);
+            h[j] = hh;
+            l[j] = (__bf16)__builtin_fmaf(p[j], q[j], -(float)hh);
+        }
+    }
+    __device__ static inline floatx16 mma(vec a, vec b, floatx16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Keeps an FP64 running sum in accumulation registers (split paths: the
+// operand and staging registers fill the vector file).
+__device__ __attribute__((always_inline)) inline void pin_agpr(double &v)
+{
+    asm volatile("" : "+a"(v));
+}
+
+constexpr int C4_MAX_NCB = (C4_MAX_M + 1 + 31) / 32;   // column blocks per pair block
+
+template <int PATH, int WX>
+struct C4Lds {
+    static constexpr bool SPLIT = PATH != HOS_PATH_FP32;
+    static constexpr int WLEN = KC + WX;
+    static constexpr int NXI = KC / 4;
+    // split paths: the FP16/BF16 hi and lo tables of the window; the FP32
+    // path reads its Hankel operand from xw
+    static constexpr int NXB = SPLIT ? 2 * WLEN : 0;
+    static constexpr int TOTAL = NXI + WLEN + NXB;
+    static constexpr int NCH = TOTAL / 64;
+    static constexpr int NPW = (NCH + 3) / 4;
+    static_assert(WLEN % 64 == 0, "window must be wave-chunk aligned");
+    float4 xi[NXI];
+    float4 xw[WLEN];            // x window table: entry o = x[i0 + o .. i0 + o + 3]
+    uint4 xb[SPLIT ? NXB : 1];  // hi, then lo window tables of the same range
+};
+
+template <int PATH, int WX, int NPW = C4Lds<PATH, WX>::NPW>
+__device__ __attribute__((always_inline)) inline void
+c4_load(u32x4 (&stg)[NPW], const float *__restrict__ xf,
+        const uint4 *__restrict__ win4, const uint4 *__restrict__ win8h,
+        const uint4 *__restrict__ win8l, int64_t i0, int wave, int lane)
+{
+    typedef C4Lds<PATH, WX> CL;
+    const u32x4 *xf4 = (const u32x4 *)xf, *w4 = (const u32x4 *)win4,
+                *w8h = (const u32x4 *)win8h, *w8l = (const u32x4 *)win8l;
+#pragma unroll
+    for (int m = 0; m < CL::NPW; ++m) {
+        const int j = wave + 4 * m, e = 64 * j;
+        const u32x4 *src;
+        if (e < CL::NXI)
+            src = xf4 + (i0 >> 2) + e;
+        else if (e < CL::NXI + CL::WLEN)
+            src = w4 + i0 + (e - CL::NXI);
+        else {
+            const int e2 = e - CL::NXI - CL::WLEN;
+            if (e2 < CL::WLEN)
+                src = w8h + i0 + e2;
+            else
+                src = w8l + i0 + (e2 - CL::WLEN);
+        }
+        if (j < CL::NCH)
+            stg[m] = src[lane];
+    }
+}
+
+template <int PATH, int WX, int NPW = C4Lds<PATH, WX>::NPW>
+__device__ __attribute__((always_inline)) inline void
+c4_store(const u32x4 (&stg)[NPW], C4Lds<PATH, WX> &L, int wave, int lane)
+{
+    typedef C4Lds<PATH, WX> CL;
+    u32x4 *base = (u32x4 *)&L;
+#pragma unroll
+    for (int m = 0; m < CL::NPW; ++m) {
+        const int j = wave + 4 * m;
+        if (j < CL::NCH)
+            base[64 * j + lane] = stg[m];
+    }
+}
+
+// One chunk for one wave: pair block rows (lane rl holds pair (a, b); `live`
+// zeroes the rows of pairs past the end) against NCOL column blocks.
+template <int PATH, int WX, int NCOL>
+__device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, float live, int rl,
+                                int h, floatx16 (&acc)[NCOL], double (&acc64)[NCOL][16])
+{
+    constexpr int NG = KC / GROUP;
+    constexpr int WLEN = C4Lds<PATH, WX>::WLEN;
+#pragma unroll 2
+    for (int g = 0; g < NG; ++g) {
+        const int ib = g * GROUP + 8 * h;
+        float xi[8], xa[8], xb[8], p[8];
+        unpack8(L.xi[ib >> 2], L.xi[(ib >> 2) + 1], xi);
+        unpack8(L.xw[ib + a], L.xw[ib + a + 4], xa);
+        unpack8(L.xw[ib + b], L.xw[ib + b + 4], xb);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            p[j] = xi[j] * xa[j] * live;
+        if constexpr (PATH == HOS_PATH_FP32) {
+            float y[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                y[j] = p[j] * xb[j];
+#pragma unroll
+            for (int cb = 0; cb < NCOL; ++cb) {
+                const int o = ib + 32 * cb + rl;
+                float t[8];
+                unpack8(L.xw[o], L.xw[o + 4], t);
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(y[j], t[j], acc[cb], 0, 0, 0);
+            }
+            if ((g & 3) == 3) {
+#pragma unroll
+                for (int cb = 0; cb < NCOL; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        acc64[cb][v] += (double)acc[cb][v];
+                        acc[cb][v] = 0.0f;
+                    }
+            }
+        } else {
+            typedef C4Ops<PATH> Ops;
+            typename Ops::vec yh, yl;
+            Ops::split(p, xb, yh, yl);
+#pragma unroll
+            for (int cb = 0; cb < NCOL; ++cb) {
+                const int o = ib + 32 * cb + rl;
+                const typename Ops::vec th = __builtin_bit_cast(typename Ops::vec, L.xb[o]);
+                const typename Ops::vec tl = __builtin_bit_cast(typename Ops::vec, L.xb[WLEN + o]);
+                acc[cb] = Ops::mma(yh, th, acc[cb]);
+                acc[cb] = Ops::mma(yh, tl, acc[cb]);
+                acc[cb] = Ops::mma(yl, th, acc[cb]);
+            }
+        }
+    }
+    if constexpr (PATH != HOS_PATH_FP32) {
+#pragma unroll
+        for (int cb = 0; cb < NCOL; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                acc64[cb][v] += (double)acc[cb][v];
+                pin_agpr(acc64[cb][v]);
+                acc[cb][v] = 0.0f;
+            }
+    }
+}
+
+// The chunk loop of one workgroup with NCOL column blocks per wave (uniform
+// over the workgroup, so every wave takes the same instantiation and meets
+// the same barriers).
+template <int PATH, int WX, int NCOL>
+__device__ inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict__ xf,
+                              const uint4 *__restrict__ win4, const uint4 *__restrict__ win8h,
+                              const uint4 *__restrict__ win8l, double *__restrict__ part,
+                              int a, int b, float live, int rb, int s, int RB, int NCB,
+                              int64_t c0, int64_t c1, int wave, int lane)
+{
+    const int rl = lane & 31, h = lane >> 5;
+    floatx16 acc[NCOL];
+    double acc64[NCOL][16];
+#pragma unroll
+    for (int cb = 0; cb < NCOL; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            acc[cb][v] = 0.0f;
+            acc64[cb][v] = 0.0;
+            if constexpr (PATH != HOS_PATH_FP32)
+                pin_agpr(acc64[cb][v]);
+        }
+
+    u32x4 stg[C4Lds<PATH, WX>::NPW];
+    c4_load<PATH, WX>(stg, xf, win4, win8h, win8l, c0 * KC, wave, lane);
+    c4_store<PATH, WX>(stg, buf[0], wave, lane);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t c = c0; c < c1; ++c) {
+        const bool has_next = c + 1 < c1;
+        if (has_next)
+            c4_load<PATH, WX>(stg, xf, win4, win8h, win8l, (c + 1) * KC, wave, lane);
+        c4_chunk<PATH, WX, NCOL>(buf[cur], a, b, live, rl, h, acc, acc64);
+        if (!has_next)
+            break;
+        cur ^= 1;
+        c4_store<PATH, WX>(stg, buf[cur], wave, lane);
+        __syncthreads();
+    }
+    if (rb < RB) {
+#pragma unroll
+        for (int cb = 0; cb < NCOL; ++cb) {
+            double *dst = part + (((int64_t)s * RB + rb) * NCB + cb) * 1024;
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                dst[v * 64 + lane] = acc64[cb][v];
+        }
+    }
+}
+
+// Grid (ceil(RB/4), S): workgroup (x, s) runs pair blocks 4x .. 4x+3 over
+// chunks [s*CPS, min((s+1)*CPS, C)) and writes one FP64 partial per pair
+// block and column block.
+template <int PATH, int WX>
+__global__ void __launch_bounds__(256, 1)
+k_c4_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
+              const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
+              double *__restrict__ part, int M, int P, int RB, int NCB, int64_t C, int CPS)
+{
+    __shared__ C4Lds<PATH, WX> buf[2];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, rl = lane & 31;
+    const int rb = blockIdx.x * 4 + wave;
+    const int s = blockIdx.y;
+    const int64_t c0 = (int64_t)s * CPS;
+    const int64_t c1 = c0 + CPS < C ? c0 + CPS : C;
+    if (c0 >= c1)
+        return;
+
+    // this lane's pair; column blocks = those of the workgroup's last pair
+    // (pairs are ordered by b, so it has the largest b)
+    int a = 0, b = 0;
+    float live = 0.0f;
+    if (rb < RB && rb * 32 + rl < P) {
+        pair_ab(M, rb * 32 + rl, a, b);
+        live = 1.0f;
+    }
+    int last = blockIdx.x * 128 + 127;
+    if (last > P - 1)
+        last = P - 1;
+    int al, bl;
+    pair_ab(M, last, al, bl);
+    const int ncol = __builtin_amdgcn_readfirstlane(bl / 32 + 1);
+    switch (ncol) {
+#define C4CASE(K)                                                                       \
+    case K:                                                                             \
+        if constexpr (32 * K <= WX)                                                     \
+            c4_run<PATH, WX, K>(buf, xf, win4, win8h, win8l, part, a, b, live, rb, s, RB, \
+                                NCB, c0, c1, wave, lane);                               \
+        break;
+        C4CASE(1) C4CASE(2) C4CASE(3) C4CASE(4)
+#undef C4CASE
+    default:
+        break;
+    }
+}
+
+// Sum the S chunk-range partials of one (pair block, column block) in a fixed
+// order and scatter to m4tab[p][c] (scaled sums, c <= b only).
+__global__ void __launch_bounds__(256)
+k_c4_reduce(const double *__restrict__ part, int M, int P, int RB, int NCB, int S,
+            double *__restrict__ m4tab)
+{
+    const int rb = blockIdx.x / NCB, cb = blockIdx.x % NCB;
+    int al, bl;
+    pair_ab(M, (rb * 32 + 31 < P ? rb * 32 + 31 : P - 1), al, bl);
+    if (cb > bl / 32)
+        return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        double sum = 0.0;
+        for (int s = 0; s < S; ++s)
+            sum += part[(((int64_t)s * RB + rb) * NCB + cb) * 1024 + e];
+        const int v = e >> 6, lane = e & 63;
+        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), col = lane & 31;
+        const int p = rb * 32 + row, c = cb * 32 + col;
+        if (p < P) {
+            int a, b;
+            pair_ab(M, p, a, b);
+            if (c <= b)
+                m4tab[(int64_t)p * (M + 1) + c] = sum;
+        }
+    }
+}
+
+// c2 partial sums sum_i x~_i x~_{i+d} (scaled by s^2), d = 0..M, FP64 from
+// the input.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_c2_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats, int nblocks,
+         double *__restrict__ dpart)
+{
+    __shared__ double red[256];
+    const int d = blockIdx.x / nblocks, blk = blockIdx.x % nblocks;
+    const double mu = stats[0], sc = stats[1];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i + d < n; i += (int64_t)nblocks * 256)
+        acc += (((double)x[i] - mu) * sc) * (((double)x[i + d] - mu) * sc);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        dpart[blockIdx.x] = red[0];
+}
+
+// c2(d) = (sum of partials) / (n s^2), d = 0..M.
+__global__ void __launch_bounds__(64)
+k_c2_final(const double *__restrict__ dpart, int M, int nblocks, const double *__restrict__ stats,
+           int64_t n, double *__restrict__ c2)
+{
+    const int d = blockIdx.x * 64 + threadIdx.x;
+    if (d > M)
+        return;
+    double s = 0.0;
+    for (int k = 0; k < nblocks; ++k)
+        s += dpart[d * nblocks + k];
+    const double sc = stats[1];
+    c2[d] = s / ((double)n * sc * sc);
+}
+
+__device__ inline double parzen(int m, int L)
+{
+    if (L == 0)
+        return m == 0 ? 1.0 : 0.0;
+    const double r = fabs((double)m) / (double)L;
+    if (r <= 0.5)
+        return 1.0 - 6.0 * r * r + 6.0 * r * r * r;
+    if (r <= 1.0) {
+        const double u = 1.0 - r;
+        return 2.0 * u * u * u;
+    }
+    return 0.0;
+}
+
+__device__ inline void sort4(int *v)
+{
+#define SW(i, j)                 \
+    if (v[i] > v[j]) {           \
+        const int t_ = v[i];     \
+        v[i] = v[j];             \
+        v[j] = t_;               \
+    }
+    SW(0, 1) SW(2, 3) SW(0, 2) SW(1, 3) SW(1, 2)
+#undef SW
+}
+
+// c4(t1,t2,t3), 0 outside {span <= M}.  Evaluated at the orbit's canonical
+// member (c, b, a) -- the sorted offsets shifted to start at 0 -- so every
+// member of an orbit gets the bitwise same value.
+__device__ inline double c4_at(const double *__restrict__ m4tab, const double *__restrict__ c2,
+                               int M, double norm4, int t1, int t2, int t3)
+{
+    int v[4] = {0, t1, t2, t3};
+    sort4(v);
+    const int a = v[3] - v[0];
+    if (a > M)
+        return 0.0;
+    const int b = v[2] - v[0], c = v[1] - v[0];
+    const int p = pair_offset(M, b) + (a - b);
+    const double m4 = m4tab[(int64_t)p * (M + 1) + c] / norm4;
+    return m4 - c2[c] * c2[a - b] - c2[b] * c2[a - c] - c2[a] * c2[b - c];
+}
+
+__global__ void __launch_bounds__(256)
+k_c4_out(const double *__restrict__ m4tab, const double *__restrict__ c2,
+         const double *__restrict__ stats, int M, double *__restrict__ out)
+{
+    const int side = 2 * M + 1;
+    const int64_t tot = (int64_t)side * side * side;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot)
+        return;
+    const int t3 = (int)(idx % side) - M;
+    const int t2 = (int)((idx / side) % side) - M;
+    const int t1 = (int)(idx / ((int64_t)side * side)) - M;
+    out[idx] = c4_at(m4tab, c2, M, stats[4], t1, t2, t3);
+}
+
+// DFT input on the N^3 grid: sum over lags congruent to m (mod N) of W4 c4.
+__global__ void __launch_bounds__(256)
+k_fft_input3(const double *__restrict__ m4tab, const double *__restrict__ c2,
+             const double *__restrict__ stats, int M, int N, int window,
+             double2 *__restrict__ T)
+{
+    const int64_t tot = (int64_t)N * N * N;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tot)
+        return;
+    const int m3 = (int)(idx % N), m2 = (int)((idx / N) % N), m1 = (int)(idx / ((int64_t)N * N));
+    const double norm4 = stats[4];
+    double sum = 0.0;
+    for (int t1 = m1 - N; t1 <= m1; t1 += N) {
+        if (t1 < -M || t1 > M)
+            continue;
+        for (int t2 = m2 - N; t2 <= m2; t2 += N) {
+            if (t2 < -M || t2 > M)
+                continue;
+            for (int t3 = m3 - N; t3 <= m3; t3 += N) {
+                if (t3 < -M || t3 > M)
+                    continue;
+                const double c = c4_at(m4tab, c2, M, norm4, t1, t2, t3);
+                double w = 1.0;
+                if (window == HOS_WIN_PARZEN)
+                    w = parzen(t1, M) * parzen(t2, M) * parzen(t3, M) * parzen(t2 - t1, M) *
+                        parzen(t3 - t1, M) * parzen(t3 - t2, M);
+                sum += w * c;
+            }
+        }
+    }
+    T[idx] = make_double2(sum, 0.0);
+}
+
+template <int PATH, int WX>
+void launch_c4_t(const C4Plan &p, char *ws, hipStream_t s)
+{
+    dim3 grid((p.RB + 3) / 4, p.S);
+    k_c4_contract<PATH, WX><<<grid, 256, 0, s>>>(
+        (const float *)(ws + p.off_xf), (const uint4 *)(ws + p.off_win4),
+        (const uint4 *)(ws + p.off_win8h), (const uint4 *)(ws + p.off_win8l),
+        (double *)(ws + p.off_part), p.M, p.P, p.RB, p.NCB, p.C, p.CPS);
+}
+
+template <int WX>
+void launch_c4_path(const C4Plan &p, char *ws, hipStream_t s)
+{
+    if (p.path == HOS_PATH_FP32)
+        launch_c4_t<HOS_PATH_FP32, WX>(p, ws, s);
+    else if (p.path == HOS_PATH_SPLIT_FP16)
+        launch_c4_t<HOS_PATH_SPLIT_FP16, WX>(p, ws, s);
+    else
+        launch_c4_t<HOS_PATH_SPLIT_BF16, WX>(p, ws, s);
+}
+
+}  // namespace
+
+int c4_window_entries(int M)
+{
+    // the staged window must reach x_{i+a}, x_{i+b} (+7) and the Hankel
+    // columns 32 NCB - 1 (+7) past the chunk's last group: one of 64/128/192
+    const int ncb = (M + 1 + 31) / 32;
+    const int need = 32 * ncb + 16;
+    if (need <= 64)
+        return 64;
+    if (need <= 128)
+        return 128;
+    return 192;
+}
+
+hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s)
+{
+    switch (p.WX) {
+    case 64: launch_c4_path<64>(p, ws, s); break;
+    case 128: launch_c4_path<128>(p, ws, s); break;
+    default: launch_c4_path<192>(p, ws, s); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_c4_reduce(const void *x, int dtype, const C4Plan &p, char *ws, hipStream_t s)
+{
+    k_c4_reduce<<<p.RB * p.NCB, 256, 0, s>>>((const double *)(ws + p.off_part), p.M, p.P, p.RB,
+                                            p.NCB, p.S, (double *)(ws + p.off_m4));
+    const double *stats = (const double *)(ws + p.off_stats);
+    double *dpart = (double *)(ws + p.off_c2part);
+    const int grid = (p.M + 1) * p.dot_blocks;
+    if (dtype == HOS_F64)
+        k_c2_dot<double><<<grid, 256, 0, s>>>((const double *)x, p.n, stats, p.dot_blocks, dpart);
+    else
+        k_c2_dot<float><<<grid, 256, 0, s>>>((const float *)x, p.n, stats, p.dot_blocks, dpart);
+    k_c2_final<<<(p.M + 64) / 64, 64, 0, s>>>(dpart, p.M, p.dot_blocks, stats, p.n,
+                                              (double *)(ws + p.off_c2));
+    return hipGetLastError();
+}
+
+hipError_t launch_c4_finish(const C4Plan &p, int window, int nfft, double *c4, double *T,
+                            char *ws, hipStream_t s)
+{
+    const double *m4 = (const double *)(ws + p.off_m4);
+    const double *c2 = (const double *)(ws + p.off_c2);
+    const double *stats = (const double *)(ws + p.off_stats);
+    if (c4) {
+        const int64_t side = 2 * p.M + 1, tot = side * side * side;
+        k_c4_out<<<(tot + 255) / 256, 256, 0, s>>>(m4, c2, stats, p.M, c4);
+    }
+    if (T) {
+        const int64_t tot = (int64_t)nfft * nfft * nfft;
+        k_fft_input3<<<(tot + 255) / 256, 256, 0, s>>>(m4, c2, stats, p.M, nfft, window,
+                                                      (double2 *)T);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hos

@@ -3,9 +3,11 @@
 // Step 1 of the estimator is the mean removal of Algorithm DBS step 2, with
 // the whole record as the one part (Section 4.1 uses K = 1).  The mean is a
 // fixed-order FP64 reduction.  The centred series is then multiplied by an
-// exact power of two s that puts max|x~ s| in [64, 128): it keeps every
-// FP16 product of the split path inside the FP16 range and is divided out
-// exactly (as s^3 or s^4) when the cumulant is normalised.
+// exact power of two s that puts max|x~ s| in [2^(top-1), 2^top): [64, 128)
+// for the third order and [16, 32) for the fourth, which keeps every FP16
+// product row (x~ x~, resp. x~ x~ x~, below 2^15) inside the FP16 range.  The
+// factor is divided out exactly (as s^2, s^3 or s^4) when the cumulant is
+// normalised.
 //
 // Operand tables written for the contraction (n_pad >= n, zero beyond n):
 //   xf[o]    = float(x~_o s)                       plain FP32 series
@@ -62,7 +64,7 @@ __global__ void __launch_bounds__(256) k_moments_partial(const T *__restrict__ x
 // stats[3] = n s^3, stats[4] = n s^4 (exact: s is a power of two)
 __global__ void __launch_bounds__(64) k_moments_final(const double *__restrict__ part,
                                                       int nblk, int64_t n, uint32_t flags,
-                                                      double *__restrict__ stats)
+                                                      int top, double *__restrict__ stats)
 {
     if (threadIdx.x != 0)
         return;
@@ -78,7 +80,7 @@ __global__ void __launch_bounds__(64) k_moments_final(const double *__restrict__
     if (amax > 0.0 && isfinite(amax)) {
         int e;
         frexp(amax, &e);          // amax = m 2^e, m in [0.5, 1)
-        s = ldexp(1.0, 7 - e);    // amax * s in [64, 128)
+        s = ldexp(1.0, top - e);  // amax * s in [2^(top-1), 2^top)
     }
     stats[0] = mu;
     stats[1] = s;
@@ -164,7 +166,7 @@ __global__ void __launch_bounds__(256) k_prep_split(const T *__restrict__ x, int
 }  // namespace
 
 hipError_t launch_moments(const void *x, int dtype, int64_t n, uint32_t flags,
-                          const C3Plan &p, char *ws, hipStream_t s)
+                          const SeriesPlan &p, char *ws, hipStream_t s)
 {
     double *part = (double *)(ws + p.off_mpart);
     double *stats = (double *)(ws + p.off_stats);
@@ -172,11 +174,11 @@ hipError_t launch_moments(const void *x, int dtype, int64_t n, uint32_t flags,
         k_moments_partial<double><<<MOM_BLOCKS, 256, 0, s>>>((const double *)x, n, part);
     else
         k_moments_partial<float><<<MOM_BLOCKS, 256, 0, s>>>((const float *)x, n, part);
-    k_moments_final<<<1, 64, 0, s>>>(part, MOM_BLOCKS, n, flags, stats);
+    k_moments_final<<<1, 64, 0, s>>>(part, MOM_BLOCKS, n, flags, p.scale_top, stats);
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const void *x, int dtype, const C3Plan &p, char *ws, hipStream_t s)
+hipError_t launch_prep(const void *x, int dtype, const SeriesPlan &p, char *ws, hipStream_t s)
 {
     const double *stats = (const double *)(ws + p.off_stats);
     float *xf = (float *)(ws + p.off_xf);

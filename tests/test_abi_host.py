@@ -89,3 +89,50 @@ def test_schedule_covers_every_chunk_once(n, M, path):
     assert slot == rslot, "reduce reads a different slot than the kernel writes"
     # every workgroup processes at least one chunk
     assert len(set(owner)) == info["G"]
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=1), hos.HOS_EINVAL),
+    (dict(M=128, nfft=256), hos.HOS_EINVAL),   # beyond the fourth-order lag limit
+    (dict(M=-1), hos.HOS_EINVAL),
+    (dict(M=40, n=40), hos.HOS_EINVAL),
+    (dict(path=3), hos.HOS_EINVAL),
+    (dict(window=2), hos.HOS_EINVAL),
+    (dict(flags=2), hos.HOS_EINVAL),
+    (dict(nfft=95), hos.HOS_EINVAL),          # < 2M with Parzen
+    (dict(nfft=96, window=0), hos.HOS_EINVAL),  # < 2M+1 without window
+    (dict(nfft=7 * 16), hos.HOS_EINVAL),      # not 2^a 3^b 5^c
+    (dict(nfft=600), hos.HOS_EINVAL),         # N^3 grid beyond 512 per axis
+    (dict(x=FAKE + 4, dtype=hos.HOS_F64), hos.HOS_EINVAL),
+    (dict(T=FAKE + 8), hos.HOS_EINVAL),       # complex128 needs 16-byte alignment
+    (dict(c4=None, T=None), hos.HOS_EINVAL),
+    (dict(ws_bytes=1024), hos.HOS_EWORKSPACE),
+])
+def test_trispectrum_validation_before_device(kw, code):
+    a = dict(x=FAKE, dtype=hos.HOS_F32, n=1 << 18, M=48, window=hos.HOS_WIN_PARZEN,
+             nfft=96, path=hos.HOS_PATH_SPLIT_FP16, flags=0, c4=FAKE, T=FAKE, ws=FAKE,
+             ws_bytes=1 << 40, stream=None)
+    a.update(kw)
+    st = hos.hos_trispectrum(a["x"], a["dtype"], a["n"], a["M"], a["window"], a["nfft"],
+                             a["path"], a["flags"], a["c4"], a["T"], a["ws"],
+                             a["ws_bytes"], a["stream"])
+    assert st == code
+
+
+@pytest.mark.parametrize("n,M,path", [
+    (1 << 18, 48, 1), (1 << 18, 48, 0), (700, 0, 0), (701, 31, 2), (3001, 32, 1),
+    (5000, 127, 0), (1 << 22, 127, 1), (513, 5, 2), (100000, 63, 1),
+])
+def test_c4_plan(n, M, path):
+    """Pair count and blocking, window reach, and the sample-axis split:
+    S ranges of CPS chunks, every range non-empty, together covering C."""
+    info = hos.hos_c4_plan_info(n, M, path)
+    assert info["P"] == (M + 1) * (M + 2) // 2
+    assert info["RB"] == -(-info["P"] // 32)
+    assert info["NCB"] == -(-(M + 1) // 32)
+    assert info["WX"] >= 32 * info["NCB"] + 16 and info["WX"] % 64 == 0
+    assert info["C"] == -(-n // 512)
+    S, cps, C = info["S"], info["CPS"], info["C"]
+    assert (S - 1) * cps < C <= S * cps
+    assert info["ws_bytes"] == hos.hos_trispectrum_workspace(n, M, 0, path)
+    assert hos.hos_trispectrum_workspace(n, M, hos.default_nfft(M), path) > info["ws_bytes"]
