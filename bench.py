@@ -14,9 +14,19 @@ FP64 oracle on sampled lags; ``roofline`` is for the dominant kernel (the
 contraction), timed with HIP events on the stream it runs on; the oracle is
 timed on the host cores on a bounded sample of lags (``cpu_baseline``).
 
+A second record inside the line, ``trispectrum``, measures the fourth-order
+path on its own workload: n = 2^18 float32 samples of the cubic process
+x_t = e_t + 0.4 e_{t-1} e_{t-2} e_{t-3}, M = 48, six-factor Parzen window,
+96^3 DFT; metric n (2M+1)^3 lag-sums per second.
+
+``traffic`` (HBM bytes per launch of the contraction) is read from the
+committed PMC summary when the contraction's source still matches the one it
+was measured on, else null.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +39,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "cumulant lag-sums/s (n·(2M+1)^2/s), split-prec vs FP32 at ≤1e-5 rel err"
+METRIC4 = "cumulant lag-sums/s (n·(2M+1)^3/s)"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_c3_contract_n2p20_M512_traffic.txt")
+C3_SOURCE = os.path.join(ROOT, "paper_1805_11775_amd", "csrc", "k_c3.hip")
 PEAK = {"fp32": 157.3e12, "split_fp16": 2.5166e15, "split_bf16": 2.5166e15}
 DTYPE = {"fp32": "f32", "split_fp16": "f16", "split_bf16": "bf16"}
 TOL = {"fp32": 1e-6, "split_fp16": 1e-5, "split_bf16": 1e-5}
@@ -80,6 +93,120 @@ def run_path(hos, torch, xt, M, N, path, steps, warmup):
     return ms, stage_ms, c3.cpu().numpy()
 
 
+def run_tri_path(hos, torch, xt, M, N, path, steps, warmup):
+    n = xt.numel()
+    pth = hos.PATHS[path]
+    wsb = hos.hos_trispectrum_workspace(n, M, N, pth)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    c4 = torch.empty((2 * M + 1,) * 3, dtype=torch.float64, device="cuda")
+    T = torch.empty((N, N, N), dtype=torch.complex128, device="cuda")
+    stream = hos._stream_handle(xt.device)
+    args = (xt.data_ptr(), hos.HOS_F32, n, M, hos.HOS_WIN_PARZEN, N, pth, 0,
+            c4.data_ptr(), T.data_ptr(), ws.data_ptr(), wsb, stream)
+
+    def call():
+        st = hos.hos_trispectrum(*args)
+        if st != hos.HOS_OK:
+            raise hos.HosError(st, "hos_trispectrum")
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    stages = []
+    for _ in range(5):
+        st, d = hos.hos_trispectrum_timed(*args)
+        if st != hos.HOS_OK:
+            raise hos.HosError(st, "hos_trispectrum_timed")
+        stages.append(d)
+    stage_ms = {k: float(np.mean([d[k] for d in stages])) for k in stages[0]}
+    return ms, stage_ms, c4.cpu().numpy()
+
+
+def bench_trispectrum(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds):
+    x, cfg = synth.workload_trispectrum()
+    M, N = cfg["M"], cfg["nfft"]
+    n = x.size
+    xt = torch.from_numpy(x).cuda()
+    lagsums = n * (2 * M + 1) ** 3
+    flops = 2.0 * n * (M + 1) * (M + 2) * (M + 3) / 6  # one MAC per (i, a, b, c) of F4
+    rng = np.random.default_rng(12)
+    t = np.concatenate([[[1, 2, 3], [0, 0, 0], [3, 2, 1]], rng.integers(-M, M + 1, (200, 3))])
+    ref = oracle.c4_at(x, t[:, 0], t[:, 1], t[:, 2])
+    span = np.maximum(t.max(1), 0) - np.minimum(t.min(1), 0)
+    ref[span > M] = 0.0
+    m4_0 = float(oracle.m4_at(x, [0], [0], [0])[0])
+    out = {}
+    for path in paths:
+        print("bench: trispectrum path %s" % path, file=sys.stderr, flush=True)
+        ms, stage_ms, c4 = run_tri_path(hos, torch, xt, M, N, path, steps, warmup)
+        got = c4[t[:, 0] + M, t[:, 1] + M, t[:, 2] + M]
+        err = float(np.max(np.abs(got - ref)) / m4_0)
+        t_k = stage_ms["contract"] * 1e-3
+        out[path] = {"ms_per_step": ms, "value": lagsums / (ms * 1e-3), "rel_err_m4": err,
+                     "within_tol": err <= TOL[path], "stage_ms": stage_ms,
+                     "contract_tflops": flops / t_k / 1e12,
+                     "contract_frac": flops / t_k / PEAK[path]}
+        print("bench: trispectrum %s %.3f ms/step, contract %.3f ms, err %.2e" %
+              (path, ms, stage_ms["contract"], err), file=sys.stderr, flush=True)
+    head = "split_fp16" if "split_fp16" in out else next(iter(out))
+    hp = out[head]
+    t_k = hp["stage_ms"]["contract"] * 1e-3
+    rec = {"metric": METRIC4, "value": hp["value"], "unit": "lag-sums/s",
+           "ms_per_step": hp["ms_per_step"], "dtype": DTYPE[head],
+           "config": {"workload": "trispectrum of one n=2^18 float32 cubic-process series "
+                                  "(x_t = e_t + 0.4 e_{t-1} e_{t-2} e_{t-3}), M=48, "
+                                  "six-factor Parzen window, 96^3 DFT",
+                      "n": n, "M": M, "nfft": N, "path": head},
+           "roofline": {"bound": "mfma", "kernel": "k_c4_contract",
+                        "achieved": flops / t_k / 1e12, "peak": PEAK[head] / 1e12,
+                        "unit": "TFLOP/s", "frac": flops / t_k / PEAK[head], "traffic": None,
+                        "flops_per_launch": flops, "avg_launch_ms": hp["stage_ms"]["contract"]},
+           "paths": out}
+    if cpu_seconds > 0:
+        # the oracle's c4 at a bounded sample of lags of the same series
+        t0 = time.perf_counter()
+        k = 16
+        while True:
+            tt = rng.integers(-M, M + 1, (k, 3))
+            oracle.c4_at(x, tt[:, 0], tt[:, 1], tt[:, 2])
+            el = time.perf_counter() - t0
+            if el > cpu_seconds or k > 1 << 22:
+                break
+            k *= 2
+            t0 = time.perf_counter()
+        rec["cpu_oracle"] = {"value": k * n / el, "unit": "lag-sums/s", "kind": "oracle",
+                             "sample": "%d random lags x n=%d, FP64 brute-force c4 (%.1f s)"
+                                       % (k, n, el)}
+    return rec
+
+
+def traffic_record(_unused=None):
+    """HBM bytes per launch of the c3 contraction from the committed PMC
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = hashlib.sha256(open(C3_SOURCE, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(oracle, x, M, seconds):
     """Oracle c3 (FP64 brute force, OpenMP) on a bounded sample of lags of
     the same series; rate in lag-sums/s."""
@@ -104,11 +231,15 @@ def cpu_baseline(oracle, x, M, seconds):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--paths", default="split_fp16,fp32,split_bf16")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tri", action="store_true", help="skip the trispectrum record")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (the "
+                         "reference kernel for scaling HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -123,6 +254,16 @@ def main():
     import oracle
     import paper_1805_11775_amd as hos
     import synth
+
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: copy of %d bytes done" % nb, file=sys.stderr, flush=True)
+        del src, dst
 
     x, cfg = synth.workload_long_bispectrum()
     M, N = cfg["M"], cfg["nfft"]
@@ -165,10 +306,14 @@ def main():
                    "n": n, "M": M, "nfft": N, "path": head},
         "roofline": {"bound": "mfma", "kernel": "k_c3_contract", "achieved": flops / t_k / 1e12,
                      "peak": PEAK[head] / 1e12, "unit": "TFLOP/s",
-                     "frac": flops / t_k / PEAK[head], "traffic": None,
+                     "frac": flops / t_k / PEAK[head], "traffic": traffic_record(None),
                      "flops_per_launch": flops, "avg_launch_ms": hp["stage_ms"]["contract"]},
         "paths": paths,
     }
+    if not args.no_tri:
+        rec["trispectrum"] = bench_trispectrum(
+            hos, torch, oracle, synth, list(paths), args.steps, args.warmup,
+            0.0 if args.no_cpu_baseline else 5.0)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(oracle, x, M, args.cpu_seconds)
