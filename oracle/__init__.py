@@ -62,8 +62,9 @@ def _load():
         lib.or_m4_at.argtypes = [dp, i64, ip, ip, ip, i64, dp]
         lib.or_c4_at.argtypes = [dp, i64, ip, ip, ip, i64, dp]
         lib.or_c4_cube.argtypes = [dp, i64, i32, dp]
+        lib.or_c3_grad.argtypes = [dp, i64, i32, dp, dp]
         for f in (lib.or_center, lib.or_c3_at, lib.or_c3_square, lib.or_c2,
-                  lib.or_m4_at, lib.or_c4_at, lib.or_c4_cube):
+                  lib.or_m4_at, lib.or_c4_at, lib.or_c4_cube, lib.or_c3_grad):
             f.restype = None
         _lib = lib
     return _lib
@@ -278,3 +279,52 @@ def pd_indices(N: int):
                 k1.append(a)
                 k2.append(b)
     return np.asarray(k1, dtype=np.int64), np.asarray(k2, dtype=np.int64)
+
+
+def bispectrum_pd(x, M: int, nfft: int, window: str = "parzen", centered: bool = True):
+    """B at the principal-domain frequencies, in ``pd_indices`` order."""
+    _, B = bispectrum(x, M, nfft, window, centered)
+    k1, k2 = pd_indices(nfft)
+    return B[k1, k2]
+
+
+def bispectrum_loss(X, M: int, nfft: int, target_pd, window: str = "parzen"):
+    """L = sum over series and principal-domain frequencies of
+    |B(x_b)(k) - target(k)|^2; X is (batch, n) or (n,)."""
+    X = np.atleast_2d(_f64(X))
+    t = np.asarray(target_pd, dtype=np.complex128)
+    return float(sum(np.sum(np.abs(bispectrum_pd(xb, M, nfft, window) - t) ** 2)
+                     for xb in X))
+
+
+def loss_weight(x, M: int, nfft: int, target_pd, window: str = "parzen") -> np.ndarray:
+    """G(w) = dL/dc3(w) over the square for one series: with R = B - target
+    on the principal domain and B = sum_w W3(w) c3(w) e^{-2 pi i <k,w>/N},
+    dL/dc3(w) = 2 W3(w) Re sum_k R_k e^{+2 pi i <k,w>/N}; lags outside the
+    hexagon (where c3 is defined as 0) get 0."""
+    k1, k2 = pd_indices(nfft)
+    R = bispectrum_pd(x, M, nfft, window) - np.asarray(target_pd, dtype=np.complex128)
+    Rm = np.zeros((nfft, nfft), dtype=np.complex128)
+    Rm[k1, k2] = R
+    w = np.arange(-M, M + 1)
+    E = np.exp(2j * np.pi * np.outer(np.arange(nfft), w) / nfft)   # E[k, w]
+    S = E.T @ Rm @ E                                               # sum_k R_k e^{+i..}
+    G = 2.0 * window3(M, window) * S.real
+    G[span3(M) > M] = 0.0
+    return G
+
+
+def bispectrum_loss_grad(X, M: int, nfft: int, target_pd, window: str = "parzen",
+                         dL: float = 1.0) -> np.ndarray:
+    """dL/dx for every series (same shape as X): the chain rule through
+    c3 (``or_c3_grad``) and through the mean removal, d/dx_j = d/dx~_j minus
+    the mean over j of d/dx~."""
+    X2 = np.atleast_2d(_f64(X))
+    out = np.empty_like(X2)
+    for b, xb in enumerate(X2):
+        G = np.ascontiguousarray(loss_weight(xb, M, nfft, target_pd, window))
+        xt = center(xb)
+        g = np.empty_like(xt)
+        _load().or_c3_grad(_dp(xt), xt.size, int(M), _dp(G), _dp(g))
+        out[b] = dL * (g - np.mean(g))
+    return out.reshape(np.shape(X))

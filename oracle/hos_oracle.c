@@ -155,3 +155,40 @@ void or_c4_cube(const double *x, int64_t n, int32_t M, double *out)
             out[r * S + c] = c4_one(x, n, a - M, b - M, c - M);
     }
 }
+
+/*
+ * Gradient of a function of c3 with respect to the mean-removed series.
+ * G is dF/dc3(w1,w2) over the square |w| <= M, row-major [(w1+M)(2M+1) +
+ * (w2+M)].  Differentiating c3(w) = (1/n) sum_t x_t x_{t+w1} x_{t+w2} by x_j
+ * gives one term for each of the three factors that can sit at j:
+ *
+ *   g_j = (1/n) sum_w G(w) [ x_{j+w1} x_{j+w2}          (t = j)
+ *                          + x_{j-w1} x_{j-w1+w2}       (t + w1 = j)
+ *                          + x_{j-w2} x_{j-w2+w1} ]     (t + w2 = j)
+ *
+ * with x = 0 outside [0, n) (the same index range as c3 itself).
+ */
+static double xz(const double *x, int64_t n, int64_t i)
+{
+    return (i >= 0 && i < n) ? x[i] : 0.0;
+}
+
+void or_c3_grad(const double *x, int64_t n, int32_t M, const double *G, double *out)
+{
+    const int64_t S = 2 * (int64_t)M + 1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int64_t w1 = -M; w1 <= M; ++w1)
+            for (int64_t w2 = -M; w2 <= M; ++w2) {
+                const double g = G[(w1 + M) * S + (w2 + M)];
+                if (g == 0.0)
+                    continue;
+                const double d = xz(x, n, j + w1) * xz(x, n, j + w2)
+                               + xz(x, n, j - w1) * xz(x, n, j - w1 + w2)
+                               + xz(x, n, j - w2) * xz(x, n, j - w2 + w1);
+                s += g * d;
+            }
+        out[j] = s / (double)n;
+    }
+}

@@ -348,3 +348,56 @@ def test_principal_domain_count_and_shape():
             assert k1.size == h * h // 4 + h // 2
         assert np.all(k2 <= k1) and np.all(k1 + k2 < N / 2) and np.all(k2 >= 0)
     assert oracle.pd_indices(512)[0].size == 16512
+
+
+# --------------------------------------------------------------------------
+# Bispectrum-matching loss and its gradient
+# --------------------------------------------------------------------------
+def _loss_case(n, M, N, seed, window="parzen"):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n) + 0.3 * rng.standard_normal(n) ** 2
+    npd = len(oracle.pd_indices(N)[0])
+    target = 0.05 * (rng.standard_normal(npd) + 1j * rng.standard_normal(npd))
+    return x, target
+
+
+@pytest.mark.parametrize("n,M,N,window", [(48, 6, 12, "parzen"), (40, 6, 13, "none"),
+                                          (33, 4, 9, "none")])
+def test_loss_gradient_matches_central_differences(n, M, N, window):
+    """L is a polynomial of degree 6 in x, so central differences with a small
+    step agree with the exact gradient to O(h^2)."""
+    x, target = _loss_case(n, M, N, 31 + n, window)
+    g = oracle.bispectrum_loss_grad(x, M, N, target, window)
+    h = 1e-5
+    fd = np.empty(n)
+    for j in range(n):
+        xp = x.copy()
+        xm = x.copy()
+        xp[j] += h
+        xm[j] -= h
+        fd[j] = (oracle.bispectrum_loss(xp, M, N, target, window) -
+                 oracle.bispectrum_loss(xm, M, N, target, window)) / (2 * h)
+    assert np.max(np.abs(g - fd)) < 1e-6 * np.max(np.abs(g))
+
+
+def test_loss_gradient_euler_identity():
+    """With a zero target L(lambda x) = lambda^6 L(x) (c3 is cubic in the
+    mean-removed series, which is linear in x), so <x, grad L> = 6 L."""
+    x, _ = _loss_case(200, 10, 20, 5)
+    target = np.zeros(len(oracle.pd_indices(20)[0]), dtype=np.complex128)
+    L = oracle.bispectrum_loss(x, 10, 20, target)
+    g = oracle.bispectrum_loss_grad(x, 10, 20, target)
+    assert abs(np.dot(x, g) - 6.0 * L) < 1e-10 * 6.0 * L
+
+
+def test_loss_gradient_shift_invariance():
+    """Mean removal makes L(x + c) = L(x), so the gradient sums to zero; and
+    the gradient of a batch is the per-series gradients stacked."""
+    x, target = _loss_case(150, 12, 24, 6)
+    y, _ = _loss_case(150, 12, 24, 7)
+    g = oracle.bispectrum_loss_grad(np.stack([x, y]), 12, 24, target)
+    assert abs(np.sum(g[0])) < 1e-12 * np.max(np.abs(g[0])) * x.size
+    assert np.array_equal(g[1], oracle.bispectrum_loss_grad(y, 12, 24, target))
+    assert abs(oracle.bispectrum_loss(np.stack([x, y]), 12, 24, target) -
+               oracle.bispectrum_loss(x, 12, 24, target) -
+               oracle.bispectrum_loss(y, 12, 24, target)) < 1e-12
