@@ -97,7 +97,8 @@ typedef enum hos_path {
 } hos_path;
 
 /* Flags. */
-#define HOS_NO_CENTER 1u /* use x as given (no mean removal); for tests */
+#define HOS_NO_CENTER 1u     /* use x as given (no mean removal); for tests      */
+#define HOS_PLAN_ADJOINT 16u /* batch plan flag: also lay out the adjoint buffers */
 
 /* Human-readable text for a status code (static storage). */
 const char *hos_strerror(int status);
@@ -220,6 +221,91 @@ int hos_trispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M,
  * bytes.  ninfo >= 8.  HOS_EINVAL on bad sizes.
  */
 int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo);
+
+/*
+ * ------------------------------------------------------------------------
+ * Batches of series.
+ *
+ * A batch is described by a PLAN built on the host (no device needed):
+ * series s has n[s] samples, stored at x + sum_{t<s} n[t] of one packed
+ * device array, and maximum lag M[s].  Its DFT size is the smallest
+ * 2^a 3^b 5^c >= 2M[s] (Parzen) or 2M[s]+1 (no window).  The plan lays out
+ * the workspace and cuts every series' c3 contraction into work items
+ * (series, tile, chunk range) that it assigns to persistent workgroups by
+ * the longest-processing-time rule.  The caller copies the plan bytes
+ * unchanged to device memory (256-byte aligned) and passes BOTH copies to
+ * the batched calls: the host copy sets up the launches, the kernels read
+ * the device copy.  A plan may be reused for any number of calls.
+ *
+ * Outputs are packed in series order: c3 of series s (its (2M+1)^2 block,
+ * layout as above) starts at element sum_{t<s} (2M[t]+1)^2; B on the
+ * principal domain 0 <= k2 <= k1, k1+k2 < N/2 (Algorithm DBS step 4, here on
+ * the N grid), in row-major (k1, then k2) order, starts at complex element
+ * sum_{t<s} npd(N[t]).  hos_batch_series reports every offset.
+ * ------------------------------------------------------------------------
+ */
+
+/* Plan and workspace sizes for a batch.  n, M: host arrays of `batch`
+ * entries (n >= 2, 0 <= M < n, M <= 2048; M <= 320 with HOS_PLAN_ADJOINT).
+ * window: hos_window.  flags: HOS_NO_CENTER, HOS_PLAN_ADJOINT (lay out the
+ * buffers hos_bispectrum_loss_bwd needs).  Host only. */
+int hos_batch_plan_size(int32_t batch, const int64_t *n, const int32_t *M, int32_t window,
+                        int32_t path, uint32_t flags, size_t *plan_bytes, size_t *ws_bytes);
+
+/* Writes the plan into host memory `plan` (8-byte aligned, plan_bytes from
+ * hos_batch_plan_size).  Host only. */
+int hos_batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window,
+                   int32_t path, uint32_t flags, void *plan, size_t plan_bytes);
+
+/* Host-only queries of a plan (host copy).  hos_batch_plan_info: info[0..11]
+ * = batch, c3 elements, principal-domain points, input samples, workspace
+ * bytes, plan bytes, work items and workgroups of the 2x2- and 4x4-block
+ * tile classes (items0, items1, G0, G1), the common M (or -1), the largest
+ * principal domain.  hos_batch_series: 8 int64 per series = n, M, N, npd,
+ * x offset, c3 offset, B offset, tile class.  hos_batch_items: 8 int64 per
+ * work item of class cls = class, workgroup, series, tile row, tile
+ * column, first chunk, end chunk, partial slot. */
+int hos_batch_plan_info(const void *plan, int64_t *info, int32_t ninfo);
+int hos_batch_series(const void *plan, int64_t *out, int64_t cap);
+int hos_batch_items(const void *plan, int32_t cls, int64_t *out, int64_t cap);
+
+/*
+ * Bispectra of every series of a batch in one pass (the estimator of
+ * hos_bispectrum applied to each series; window and path from the plan).
+ *   x          device, packed series of dtype.
+ *   plan_host  the host plan; plan_dev its device copy.
+ *   c3         device, packed c3 blocks (plan_info[1] float64), or NULL.
+ *   B_pd       device, packed principal-domain spectra (plan_info[2]
+ *              complex128), or NULL.  At least one must be non-NULL.
+ *   ws         device workspace of plan_info[4] bytes, 256-byte aligned.
+ */
+int hos_bispectrum_batched(const void *x, int32_t dtype, const void *plan_host,
+                           const void *plan_dev, double *c3, double *B_pd, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Bispectrum-matching loss over a batch whose series share one M:
+ *   L = sum_s sum_{k in PD} |B_s(k) - target(k)|^2.
+ *   target_pd  device, npd complex128 (the principal domain of the common N).
+ *   B_pd       device, receives the batch's principal-domain spectra.
+ *   loss       device, one float64.
+ */
+int hos_bispectrum_loss_fwd(const void *x, int32_t dtype, const void *plan_host,
+                            const void *plan_dev, const double *target_pd, double *B_pd,
+                            double *loss, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Gradient of the loss: dx = dL * dL/dx for every sample of every series,
+ * with B_pd from hos_bispectrum_loss_fwd on the same x and plan, and dL a
+ * device float64 (the upstream gradient).  The plan must have been made
+ * with HOS_PLAN_ADJOINT.  dx: device, same dtype and packing as x.  The
+ * product terms are recomputed from x; nothing of the forward pass but B_pd
+ * is needed.
+ */
+int hos_bispectrum_loss_bwd(const void *x, int32_t dtype, const void *plan_host,
+                            const void *plan_dev, const double *B_pd, const double *target_pd,
+                            const double *dL, void *dx, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -63,8 +63,11 @@ def _load():
         lib.or_c4_at.argtypes = [dp, i64, ip, ip, ip, i64, dp]
         lib.or_c4_cube.argtypes = [dp, i64, i32, dp]
         lib.or_c3_grad.argtypes = [dp, i64, i32, dp, dp]
+        lib.or_c3_grad_at.argtypes = [dp, i64, i32, dp, ctypes.POINTER(ctypes.c_int64), i64,
+                                      dp]
         for f in (lib.or_center, lib.or_c3_at, lib.or_c3_square, lib.or_c2,
-                  lib.or_m4_at, lib.or_c4_at, lib.or_c4_cube, lib.or_c3_grad):
+                  lib.or_m4_at, lib.or_c4_at, lib.or_c4_cube, lib.or_c3_grad,
+                  lib.or_c3_grad_at):
             f.restype = None
         _lib = lib
     return _lib
@@ -328,3 +331,15 @@ def bispectrum_loss_grad(X, M: int, nfft: int, target_pd, window: str = "parzen"
         _load().or_c3_grad(_dp(xt), xt.size, int(M), _dp(G), _dp(g))
         out[b] = dL * (g - np.mean(g))
     return out.reshape(np.shape(X))
+
+
+def loss_grad_at(x, M: int, nfft: int, target_pd, idx, window: str = "parzen") -> np.ndarray:
+    """dL/dx~_j (before the mean-removal term) of one series at the indices
+    ``idx``; differences of these equal differences of dL/dx."""
+    G = np.ascontiguousarray(loss_weight(x, M, nfft, target_pd, window))
+    xt = center(x)
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    out = np.empty(idx.size, dtype=np.float64)
+    _load().or_c3_grad_at(_dp(xt), xt.size, int(M), _dp(G),
+                          idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.size, _dp(out))
+    return out

@@ -173,22 +173,35 @@ static double xz(const double *x, int64_t n, int64_t i)
     return (i >= 0 && i < n) ? x[i] : 0.0;
 }
 
-void or_c3_grad(const double *x, int64_t n, int32_t M, const double *G, double *out)
+static double grad_one(const double *x, int64_t n, int32_t M, const double *G, int64_t j)
 {
     const int64_t S = 2 * (int64_t)M + 1;
+    double s = 0.0;
+    for (int64_t w1 = -M; w1 <= M; ++w1)
+        for (int64_t w2 = -M; w2 <= M; ++w2) {
+            const double g = G[(w1 + M) * S + (w2 + M)];
+            if (g == 0.0)
+                continue;
+            const double d = xz(x, n, j + w1) * xz(x, n, j + w2)
+                           + xz(x, n, j - w1) * xz(x, n, j - w1 + w2)
+                           + xz(x, n, j - w2) * xz(x, n, j - w2 + w1);
+            s += g * d;
+        }
+    return s / (double)n;
+}
+
+void or_c3_grad(const double *x, int64_t n, int32_t M, const double *G, double *out)
+{
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int64_t w1 = -M; w1 <= M; ++w1)
-            for (int64_t w2 = -M; w2 <= M; ++w2) {
-                const double g = G[(w1 + M) * S + (w2 + M)];
-                if (g == 0.0)
-                    continue;
-                const double d = xz(x, n, j + w1) * xz(x, n, j + w2)
-                               + xz(x, n, j - w1) * xz(x, n, j - w1 + w2)
-                               + xz(x, n, j - w2) * xz(x, n, j - w2 + w1);
-                s += g * d;
-            }
-        out[j] = s / (double)n;
-    }
+    for (int64_t j = 0; j < n; ++j)
+        out[j] = grad_one(x, n, M, G, j);
+}
+
+/* The same at the sample indices idx[0..count). */
+void or_c3_grad_at(const double *x, int64_t n, int32_t M, const double *G, const int64_t *idx,
+                   int64_t count, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < count; ++k)
+        out[k] = grad_one(x, n, M, G, idx[k]);
 }

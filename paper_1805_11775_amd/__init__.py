@@ -39,6 +39,7 @@ HOS_PATH_FP32 = 0
 HOS_PATH_SPLIT_FP16 = 1
 HOS_PATH_SPLIT_BF16 = 2
 HOS_NO_CENTER = 1
+HOS_PLAN_ADJOINT = 16
 
 PATHS = {"fp32": HOS_PATH_FP32, "split_fp16": HOS_PATH_SPLIT_FP16,
          "split_bf16": HOS_PATH_SPLIT_BF16}
@@ -80,6 +81,18 @@ def _load_lib():
                                                  vp, vp, vp, sz, vp,
                                                  ctypes.POINTER(ctypes.c_float)]),
         "hos_c4_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
+        "hos_batch_plan_size": (ctypes.c_int, [i32, p64, ctypes.POINTER(ctypes.c_int32), i32,
+                                               i32, u32, ctypes.POINTER(sz),
+                                               ctypes.POINTER(sz)]),
+        "hos_batch_plan": (ctypes.c_int, [i32, p64, ctypes.POINTER(ctypes.c_int32), i32, i32,
+                                          u32, vp, sz]),
+        "hos_batch_plan_info": (ctypes.c_int, [vp, p64, i32]),
+        "hos_batch_series": (ctypes.c_int, [vp, p64, i64]),
+        "hos_batch_items": (ctypes.c_int, [vp, i32, p64, i64]),
+        "hos_bispectrum_batched": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
+        "hos_bispectrum_loss_fwd": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "hos_bispectrum_loss_bwd": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz,
+                                                   vp]),
         "hos_c3_schedule": (ctypes.c_int, [i64, i32, i32, p64, p64, p64, i64]),
     }
     for name, (res, args) in sig.items():
@@ -300,3 +313,185 @@ def trispectrum(x, M: int, nfft: int | None = None, window: str = "parzen",
     if st != HOS_OK:
         raise HosError(st, "hos_trispectrum")
     return c4, T
+
+
+# ------------------------------------------------------------------ batches
+def _i64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _i32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+BATCH_INFO_KEYS = ("batch", "c3_elems", "pd_elems", "x_elems", "ws_bytes", "plan_bytes",
+                   "items0", "items1", "G0", "G1", "uniform_M", "max_npd")
+
+
+class BatchPlan:
+    """A host-built plan for a batch of series (see ``hos_batch_plan``):
+    lengths ``n``, maximum lags ``M``.  Holds the host bytes and, once
+    ``to(device)`` has run, an identical device copy."""
+
+    def __init__(self, n, M, window="parzen", path="fp32", center=True, adjoint=False):
+        import numpy as np
+        self.n = np.ascontiguousarray(np.asarray(n, dtype=np.int64).ravel())
+        self.M = np.ascontiguousarray(np.asarray(M, dtype=np.int32).ravel())
+        if self.n.size != self.M.size or self.n.size == 0:
+            raise ValueError("n and M must be non-empty and of equal length")
+        self.window, self.path = window, path
+        self.flags = (0 if center else HOS_NO_CENTER) | (HOS_PLAN_ADJOINT if adjoint else 0)
+        pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        st = lib().hos_batch_plan_size(self.n.size, _i64p(self.n), _i32p(self.M),
+                                       WINDOWS[window], PATHS[path], self.flags,
+                                       ctypes.byref(pb), ctypes.byref(wb))
+        if st != HOS_OK:
+            raise HosError(st, "hos_batch_plan_size")
+        self.host = np.zeros((pb.value + 7) // 8, dtype=np.int64)   # 8-byte aligned bytes
+        st = lib().hos_batch_plan(self.n.size, _i64p(self.n), _i32p(self.M), WINDOWS[window],
+                                  PATHS[path], self.flags, self.host.ctypes.data, pb.value)
+        if st != HOS_OK:
+            raise HosError(st, "hos_batch_plan")
+        info = np.zeros(12, dtype=np.int64)
+        st = lib().hos_batch_plan_info(self.host.ctypes.data, _i64p(info), 12)
+        if st != HOS_OK:
+            raise HosError(st, "hos_batch_plan_info")
+        self.info = dict(zip(BATCH_INFO_KEYS, [int(v) for v in info]))
+        self.dev = None
+        self._ws = None
+
+    def series(self):
+        """Per-series rows: n, M, N, npd, x offset, c3 offset, B offset, class."""
+        import numpy as np
+        out = np.zeros((self.n.size, 8), dtype=np.int64)
+        st = lib().hos_batch_series(self.host.ctypes.data, _i64p(out), out.size)
+        if st != HOS_OK:
+            raise HosError(st, "hos_batch_series")
+        return out
+
+    def items(self, cls):
+        import numpy as np
+        k = self.info["items%d" % cls]
+        out = np.zeros((max(k, 1), 8), dtype=np.int64)
+        st = lib().hos_batch_items(self.host.ctypes.data, int(cls), _i64p(out), out.size)
+        if st != HOS_OK:
+            raise HosError(st, "hos_batch_items")
+        return out[:k]
+
+    def to(self, device):
+        import torch
+        if self.dev is None or self.dev.device != torch.device(device):
+            h = torch.from_numpy(self.host.view("uint8"))
+            self.dev = h.to(device)
+            self._ws = None
+        return self
+
+    def workspace(self, device):
+        import torch
+        if self._ws is None or self._ws.device != torch.device(device):
+            self._ws = torch.empty(self.info["ws_bytes"], dtype=torch.uint8, device=device)
+        return self._ws
+
+
+def _check_packed(x, plan):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError("x must be a CUDA tensor")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
+    x = x.contiguous().view(-1)
+    if x.numel() != plan.info["x_elems"]:
+        raise ValueError("x holds %d samples, the plan %d" % (x.numel(), plan.info["x_elems"]))
+    return x
+
+
+def bispectrum_batched(x, plan: BatchPlan, return_c3=True, return_B=True):
+    """Packed c3 blocks and principal-domain spectra of every series of
+    ``plan`` (``x`` packed in series order).  Returns (c3 or None, B_pd or
+    None) as flat float64 / complex128 tensors."""
+    import torch
+    x = _check_packed(x, plan)
+    plan.to(x.device)
+    ws = plan.workspace(x.device)
+    c3 = torch.empty(plan.info["c3_elems"], dtype=torch.float64,
+                     device=x.device) if return_c3 else None
+    B = torch.empty(plan.info["pd_elems"], dtype=torch.complex128,
+                    device=x.device) if return_B else None
+    st = lib().hos_bispectrum_batched(
+        x.data_ptr(), HOS_F64 if x.dtype == torch.float64 else HOS_F32,
+        plan.host.ctypes.data, plan.dev.data_ptr(),
+        c3.data_ptr() if c3 is not None else None, B.data_ptr() if B is not None else None,
+        ws.data_ptr(), ws.numel(), _stream_handle(x.device))
+    if st != HOS_OK:
+        raise HosError(st, "hos_bispectrum_batched")
+    return c3, B
+
+
+def bispectrum_loss_fwd(x, target_pd, plan: BatchPlan):
+    """(loss as a 0-d float64 tensor, B_pd) for packed x."""
+    import torch
+    x = _check_packed(x, plan)
+    plan.to(x.device)
+    ws = plan.workspace(x.device)
+    target_pd = target_pd.to(device=x.device, dtype=torch.complex128).contiguous()
+    B = torch.empty(plan.info["pd_elems"], dtype=torch.complex128, device=x.device)
+    loss = torch.empty((), dtype=torch.float64, device=x.device)
+    st = lib().hos_bispectrum_loss_fwd(
+        x.data_ptr(), HOS_F64 if x.dtype == torch.float64 else HOS_F32, plan.host.ctypes.data,
+        plan.dev.data_ptr(), target_pd.data_ptr(), B.data_ptr(), loss.data_ptr(),
+        ws.data_ptr(), ws.numel(), _stream_handle(x.device))
+    if st != HOS_OK:
+        raise HosError(st, "hos_bispectrum_loss_fwd")
+    return loss, B
+
+
+def bispectrum_loss_bwd(x, target_pd, B_pd, dL, plan: BatchPlan):
+    """dL * dLoss/dx for packed x (same dtype and shape as x)."""
+    import torch
+    xf = _check_packed(x, plan)
+    plan.to(xf.device)
+    ws = plan.workspace(xf.device)
+    target_pd = target_pd.to(device=xf.device, dtype=torch.complex128).contiguous()
+    dL = dL.to(device=xf.device, dtype=torch.float64).contiguous().reshape(())
+    dx = torch.empty_like(xf)
+    st = lib().hos_bispectrum_loss_bwd(
+        xf.data_ptr(), HOS_F64 if xf.dtype == torch.float64 else HOS_F32,
+        plan.host.ctypes.data, plan.dev.data_ptr(), B_pd.data_ptr(), target_pd.data_ptr(),
+        dL.data_ptr(), dx.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(xf.device))
+    if st != HOS_OK:
+        raise HosError(st, "hos_bispectrum_loss_bwd")
+    return dx.view_as(x)
+
+
+def _loss_function():
+    import torch
+
+    class BispectrumLoss(torch.autograd.Function):
+        """L(x) = sum over series and principal-domain frequencies of
+        |B(x_s) - target|^2, with the hand-written adjoint as backward."""
+
+        @staticmethod
+        def forward(ctx, x, target_pd, plan):
+            loss, B = bispectrum_loss_fwd(x, target_pd, plan)
+            ctx.save_for_backward(x, target_pd, B)
+            ctx.plan = plan
+            return loss
+
+        @staticmethod
+        def backward(ctx, grad):
+            x, target_pd, B = ctx.saved_tensors
+            return bispectrum_loss_bwd(x, target_pd, B, grad, ctx.plan), None, None
+
+    return BispectrumLoss
+
+
+_LOSS_FN = None
+
+
+def bispectrum_loss(x, target_pd, plan: BatchPlan):
+    """Differentiable loss of a (batch, n) or packed tensor ``x`` (plan made
+    with ``adjoint=True``)."""
+    global _LOSS_FN
+    if _LOSS_FN is None:
+        _LOSS_FN = _loss_function()
+    return _LOSS_FN.apply(x, target_pd, plan)

@@ -182,6 +182,8 @@ static int device_ok()
     return cache[dev] == 1 ? HOS_OK : HOS_ENODEVICE;
 }
 
+int device_ok_public() { return device_ok(); }
+
 }  // namespace hos
 
 using namespace hos;

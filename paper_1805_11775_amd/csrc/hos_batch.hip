@@ -1,0 +1,519 @@
+// hos_batch.hip -- batches of series: the host planner and the batched C
+// entry points (bispectra of many series of uneven length and lag, and the
+// bispectrum-matching loss with its adjoint).
+//
+// The planner runs on the host only.  It lays out one workspace region per
+// series, groups the series by DFT size, and cuts every series' c3
+// contraction into work items (series, tile, chunk range).  Items are
+// assigned to a fixed number of persistent workgroups by the longest-
+// processing-time rule: sorted by cost, each goes to the least-loaded
+// workgroup.  Every item writes its own FP64 partial tile; a tile's items
+// take consecutive slots, summed in chunk order, so results do not depend on
+// which workgroup ran what (bitwise deterministic).
+#include <string.h>
+
+#include <algorithm>
+#include <queue>
+#include <vector>
+
+#include "hos_internal.h"
+
+namespace hos {
+
+static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+static int64_t up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+static bool fft_ok(int N)
+{
+    if (N < 2 || N > 4096)
+        return false;
+    int m = N;
+    for (int r : {2, 3, 5})
+        while (m % r == 0)
+            m /= r;
+    return m == 1;
+}
+
+// Smallest 2^a 3^b 5^c >= need (need >= 2).
+static int next_fft(int need)
+{
+    for (int k = need < 2 ? 2 : need;; ++k)
+        if (fft_ok(k))
+            return k;
+}
+
+static int pd_count(int N)
+{
+    int c = 0;
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b <= a; ++b)
+            if (2 * (a + b) < N)
+                ++c;
+    return c;
+}
+
+int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window, int32_t path,
+               uint32_t flags, void *blob, size_t blob_bytes, BatchHeader *hdr_out)
+{
+    if (batch < 1 || batch > (1 << 20) || !n || !M)
+        return HOS_EINVAL;
+    if (path != HOS_PATH_FP32 && path != HOS_PATH_SPLIT_FP16 && path != HOS_PATH_SPLIT_BF16)
+        return HOS_EINVAL;
+    if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN)
+        return HOS_EINVAL;
+    if (flags & ~(HOS_NO_CENTER | HOS_PLAN_ADJOINT))
+        return HOS_EINVAL;
+    const bool adj = (flags & HOS_PLAN_ADJOINT) != 0;
+    const bool split = path != HOS_PATH_FP32;
+    BatchHeader h;
+    memset(&h, 0, sizeof(h));
+    h.magic = BATCH_MAGIC;
+    h.batch = batch;
+    h.path = path;
+    h.flags = flags;
+    h.window = window;
+    h.uniform_M = M[0];
+    h.uniform_n = n[0];
+    for (int s = 0; s < batch; ++s) {
+        if (n[s] < 2 || n[s] > ((int64_t)1 << 36) || M[s] < 0 || (int64_t)M[s] >= n[s] ||
+            M[s] > 2048)
+            return HOS_EINVAL;
+        if (adj && M[s] > ADJ_MAX_M)
+            return HOS_EINVAL;
+        if (M[s] != h.uniform_M)
+            h.uniform_M = -1;
+        if (n[s] != h.uniform_n)
+            h.uniform_n = -1;
+        h.max_n = std::max<int64_t>(h.max_n, n[s]);
+    }
+    h.momb = std::min<int64_t>(256, std::max<int64_t>(1, (h.max_n + 4095) / 4096));
+    h.dot_blocks = std::min<int64_t>(64, std::max<int64_t>(1, h.max_n / 4096));
+
+    std::vector<SeriesDesc> sd(batch);
+    size_t o = 0;
+    int64_t xo = 0, c3o = 0, pdo = 0;
+    for (int s = 0; s < batch; ++s) {
+        SeriesDesc &d = sd[s];
+        memset(&d, 0, sizeof(d));
+        d.n = n[s];
+        d.M = M[s];
+        d.x_off = xo;
+        xo += n[s];
+        d.c3_off = c3o;
+        c3o += (int64_t)(2 * d.M + 1) * (2 * d.M + 1);
+        d.N = next_fft(window == HOS_WIN_PARZEN ? 2 * d.M : 2 * d.M + 1);
+        d.npd = pd_count(d.N);
+        d.pd_off = pdo;
+        pdo += d.npd;
+        d.cls = (d.M >= 96 || !split) ? 1 : 0;
+        d.NB = d.cls ? 4 : 2;
+        d.NBR = (d.M + 31) / 32;
+        d.TR = d.NBR > 0 ? (d.NBR + d.NB - 1) / d.NB : 0;
+        d.nleft = 1 + d.M / 32;
+        d.C = (d.n + KC - 1) / KC;
+        d.KP = adj ? (int32_t)up(2 * d.M + 1, 32) : 0;
+        d.lpad = adj ? up(d.M, 64) : 0;
+        int64_t npad = up(d.C * KC + (int64_t)d.TR * 32 * d.NB + 64, 64);
+        if (adj)
+            npad = std::max<int64_t>(npad, up(up(d.n, 256) + 256 + d.KP + 128, 64));
+        d.npad = npad;
+        const int64_t ent = d.lpad + d.npad;
+        d.ws_off = (int64_t)o;
+        size_t r = 0;
+        d.o_stats = r;  r = a256(r + 64 * sizeof(double));
+        d.o_mpart = r;  r = a256(r + (size_t)h.momb * 3 * sizeof(double));
+        d.o_xf = r + d.lpad * 4;      r = a256(r + (size_t)ent * 4);
+        d.o_win4 = r + d.lpad * 16;   r = a256(r + (size_t)ent * 16);
+        if (split) {
+            d.o_win8h = r + d.lpad * 16;  r = a256(r + (size_t)ent * 16);
+            d.o_win8l = r + d.lpad * 16;  r = a256(r + (size_t)ent * 16);
+        }
+        d.o_cfull = r;  r = a256(r + (size_t)(d.M + 1) * (d.M + 1) * sizeof(double));
+        d.o_dpart = r;  r = a256(r + (size_t)d.nleft * h.dot_blocks * sizeof(double));
+        if (adj) {
+            const size_t kp2 = (size_t)d.KP * d.KP;
+            d.o_gtil = r;  r = a256(r + (size_t)d.n * sizeof(double));
+            d.o_k64 = r;   r = a256(r + kp2 * sizeof(double));
+            d.o_kh = r;    r = a256(r + kp2 * (split ? 2 : 4));
+            if (split) {
+                d.o_kl = r;  r = a256(r + kp2 * 2);
+            }
+        }
+        o += r;
+        h.max_npad = std::max<int64_t>(h.max_npad, d.npad);
+        h.max_lpad = std::max<int64_t>(h.max_lpad, d.lpad);
+        h.max_M = std::max<int64_t>(h.max_M, d.M);
+        h.max_N = std::max<int64_t>(h.max_N, d.N);
+        h.max_nleft = std::max<int64_t>(h.max_nleft, d.nleft);
+        h.max_npd = std::max<int64_t>(h.max_npd, d.npd);
+        h.max_side2 = std::max<int64_t>(h.max_side2, (int64_t)(2 * d.M + 1) * (2 * d.M + 1));
+        h.max_KP = std::max<int64_t>(h.max_KP, d.KP);
+    }
+    h.c3_total = c3o;
+    h.pd_total = pdo;
+    h.x_total = xo;
+
+    // DFT groups: grids of one size contiguous, in series order
+    std::vector<int> sizes;
+    for (auto &d : sd)
+        sizes.push_back(d.N);
+    std::sort(sizes.begin(), sizes.end());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    std::vector<FftGroup> groups(sizes.size());
+    for (size_t g = 0; g < sizes.size(); ++g) {
+        groups[g].N = sizes[g];
+        groups[g].count = 0;
+        groups[g].twid_off = (int64_t)o;
+        o = a256(o + (size_t)sizes[g] * 16);
+    }
+    for (auto &d : sd) {
+        const int g = (int)(std::lower_bound(sizes.begin(), sizes.end(), d.N) - sizes.begin());
+        d.group = g;
+        groups[g].count++;
+    }
+    for (auto &gr : groups) {
+        gr.grid_off = (int64_t)o;
+        o = a256(o + (size_t)gr.count * gr.N * gr.N * 16);
+    }
+    {
+        std::vector<int> fill(groups.size(), 0);
+        for (auto &d : sd) {
+            FftGroup &gr = groups[d.group];
+            d.grid_off = gr.grid_off + (int64_t)fill[d.group]++ * gr.N * gr.N * 16;
+        }
+    }
+    h.loss_off = (int64_t)o;
+    o = a256(o + (size_t)batch * sizeof(double));
+
+    // contraction work items, per tile class
+    std::vector<C3Item> items[BATCH_CLASSES];
+    std::vector<int32_t> wgfirst[BATCH_CLASSES];
+    std::vector<C3TileRef> tiles[BATCH_CLASSES];
+    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
+        const int64_t gmax = cls ? 256 : 512;
+        const int cf = split ? 1 : 4, cd = split ? 1 : 3;
+        int64_t units = 0;
+        for (auto &d : sd)
+            if (d.cls == cls)
+                units += ((int64_t)d.TR * (d.TR - 1) / 2 * cf + (int64_t)d.TR * cd) * d.C;
+        if (units == 0)
+            continue;
+        const int64_t piece = std::max<int64_t>(1, units / (4 * gmax));  // cost per item
+        std::vector<int64_t> cost;
+        int64_t slot = 0;
+        for (int s = 0; s < batch; ++s) {
+            const SeriesDesc &d = sd[s];
+            if (d.cls != cls)
+                continue;
+            for (int R = 0; R < d.TR; ++R)
+                for (int Cc = 0; Cc <= R; ++Cc) {
+                    const int ct = Cc == R ? cd : cf;
+                    const int64_t pc = std::max<int64_t>(1, piece / ct);
+                    C3TileRef t;
+                    t.series = s;
+                    t.R = R;
+                    t.Cc = Cc;
+                    t.slot0 = slot;
+                    t.nslot = 0;
+                    for (int64_t c0 = 0; c0 < d.C; c0 += pc) {
+                        C3Item it;
+                        it.series = s;
+                        it.R = R;
+                        it.Cc = Cc;
+                        it.pad = 0;
+                        it.c0 = c0;
+                        it.c1 = std::min<int64_t>(d.C, c0 + pc);
+                        it.slot = slot++;
+                        items[cls].push_back(it);
+                        cost.push_back((it.c1 - it.c0) * ct);
+                        t.nslot++;
+                    }
+                    tiles[cls].push_back(t);
+                }
+        }
+        const int64_t ni = (int64_t)items[cls].size();
+        const int64_t G = std::min<int64_t>(gmax, ni);
+        // longest processing time first, ties in plan order
+        std::vector<int64_t> ord(ni);
+        for (int64_t k = 0; k < ni; ++k)
+            ord[k] = k;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+        typedef std::pair<int64_t, int64_t> LW;   // (load, workgroup)
+        std::priority_queue<LW, std::vector<LW>, std::greater<LW>> heap;
+        for (int64_t w = 0; w < G; ++w)
+            heap.push(LW(0, w));
+        std::vector<std::vector<int64_t>> per(G);
+        for (int64_t k : ord) {
+            LW top = heap.top();
+            heap.pop();
+            per[top.second].push_back(k);
+            heap.push(LW(top.first + cost[k], top.second));
+        }
+        std::vector<C3Item> sorted;
+        sorted.reserve(ni);
+        wgfirst[cls].push_back(0);
+        for (int64_t w = 0; w < G; ++w) {
+            for (int64_t k : per[w])
+                sorted.push_back(items[cls][k]);
+            wgfirst[cls].push_back((int32_t)sorted.size());
+        }
+        items[cls].swap(sorted);
+        h.n_items[cls] = ni;
+        h.G[cls] = G;
+        h.n_tiles[cls] = (int64_t)tiles[cls].size();
+        const int64_t tile = (int64_t)(32 * (cls ? 4 : 2)) * (32 * (cls ? 4 : 2));
+        h.part_off[cls] = (int64_t)o;
+        o = a256(o + (size_t)slot * tile * sizeof(double));
+    }
+    h.ws_bytes = (int64_t)o;
+
+    // blob: header | series | (items | wgfirst | tiles) per class | groups
+    size_t b = up(sizeof(BatchHeader), 64);
+    h.series_off = (int64_t)b;
+    b += sizeof(SeriesDesc) * batch;
+    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
+        h.items_off[cls] = (int64_t)b;
+        b += sizeof(C3Item) * items[cls].size();
+        h.wgfirst_off[cls] = (int64_t)b;
+        b += up(sizeof(int32_t) * wgfirst[cls].size(), 8);
+        h.tiles_off[cls] = (int64_t)b;
+        b += sizeof(C3TileRef) * tiles[cls].size();
+    }
+    h.groups_off = (int64_t)b;
+    h.n_groups = (int64_t)groups.size();
+    b += sizeof(FftGroup) * groups.size();
+    h.blob_bytes = (int64_t)up(b, 256);
+
+    if (hdr_out)
+        *hdr_out = h;
+    if (!blob)
+        return HOS_OK;
+    if (blob_bytes < (size_t)h.blob_bytes)
+        return HOS_EINVAL;
+    char *p = (char *)blob;
+    memset(p, 0, h.blob_bytes);
+    memcpy(p, &h, sizeof(h));
+    memcpy(p + h.series_off, sd.data(), sizeof(SeriesDesc) * batch);
+    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
+        if (!items[cls].empty())
+            memcpy(p + h.items_off[cls], items[cls].data(), sizeof(C3Item) * items[cls].size());
+        if (!wgfirst[cls].empty())
+            memcpy(p + h.wgfirst_off[cls], wgfirst[cls].data(),
+                   sizeof(int32_t) * wgfirst[cls].size());
+        if (!tiles[cls].empty())
+            memcpy(p + h.tiles_off[cls], tiles[cls].data(), sizeof(C3TileRef) * tiles[cls].size());
+    }
+    memcpy(p + h.groups_off, groups.data(), sizeof(FftGroup) * groups.size());
+    return HOS_OK;
+}
+
+// The host copy of a plan, checked for integrity.
+static const BatchHeader *plan_header(const void *plan_host)
+{
+    if (!plan_host || ((uintptr_t)plan_host & 7))
+        return nullptr;
+    const BatchHeader *h = (const BatchHeader *)plan_host;
+    if (h->magic != BATCH_MAGIC || h->batch < 1 || h->blob_bytes < (int64_t)sizeof(BatchHeader))
+        return nullptr;
+    return h;
+}
+
+static bool aligned_to(const void *p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+}  // namespace hos
+
+using namespace hos;
+
+extern "C" {
+
+int hos_batch_plan_size(int32_t batch, const int64_t *n, const int32_t *M, int32_t window,
+                        int32_t path, uint32_t flags, size_t *plan_bytes, size_t *ws_bytes)
+{
+    if (!plan_bytes || !ws_bytes)
+        return HOS_EINVAL;
+    BatchHeader h;
+    const int st = batch_plan(batch, n, M, window, path, flags, nullptr, 0, &h);
+    if (st != HOS_OK)
+        return st;
+    *plan_bytes = (size_t)h.blob_bytes;
+    *ws_bytes = (size_t)h.ws_bytes;
+    return HOS_OK;
+}
+
+int hos_batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window,
+                   int32_t path, uint32_t flags, void *plan, size_t plan_bytes)
+{
+    if (!plan || !aligned_to(plan, 8))
+        return HOS_EINVAL;
+    return batch_plan(batch, n, M, window, path, flags, plan, plan_bytes, nullptr);
+}
+
+int hos_batch_plan_info(const void *plan, int64_t *info, int32_t ninfo)
+{
+    const BatchHeader *h = plan_header(plan);
+    if (!h || !info || ninfo < 12)
+        return HOS_EINVAL;
+    info[0] = h->batch;
+    info[1] = h->c3_total;
+    info[2] = h->pd_total;
+    info[3] = h->x_total;
+    info[4] = h->ws_bytes;
+    info[5] = h->blob_bytes;
+    info[6] = h->n_items[0];
+    info[7] = h->n_items[1];
+    info[8] = h->G[0];
+    info[9] = h->G[1];
+    info[10] = h->uniform_M;
+    info[11] = h->max_npd;
+    return HOS_OK;
+}
+
+// Host-only listing of the plan's work items, for tests: row k of `out`
+// (7 int64 each) = class, workgroup, series, R, Cc, c0, c1 ... plus slot.
+int hos_batch_items(const void *plan, int32_t cls, int64_t *out, int64_t cap)
+{
+    const BatchHeader *h = plan_header(plan);
+    if (!h || !out || cls < 0 || cls >= BATCH_CLASSES)
+        return HOS_EINVAL;
+    const int64_t ni = h->n_items[cls];
+    if (cap < ni * 8)
+        return HOS_EINVAL;
+    const char *p = (const char *)plan;
+    const C3Item *it = (const C3Item *)(p + h->items_off[cls]);
+    const int32_t *wf = (const int32_t *)(p + h->wgfirst_off[cls]);
+    for (int64_t w = 0; w < h->G[cls]; ++w)
+        for (int64_t k = wf[w]; k < wf[w + 1]; ++k) {
+            int64_t *r = out + 8 * k;
+            r[0] = cls;
+            r[1] = w;
+            r[2] = it[k].series;
+            r[3] = it[k].R;
+            r[4] = it[k].Cc;
+            r[5] = it[k].c0;
+            r[6] = it[k].c1;
+            r[7] = it[k].slot;
+        }
+    return HOS_OK;
+}
+
+// Per-series layout for tests: row s (8 int64) = n, M, N, npd, x_off, c3_off,
+// pd_off, cls.
+int hos_batch_series(const void *plan, int64_t *out, int64_t cap)
+{
+    const BatchHeader *h = plan_header(plan);
+    if (!h || !out || cap < h->batch * 8)
+        return HOS_EINVAL;
+    const SeriesDesc *sd = (const SeriesDesc *)((const char *)plan + h->series_off);
+    for (int64_t s = 0; s < h->batch; ++s) {
+        int64_t *r = out + 8 * s;
+        r[0] = sd[s].n;
+        r[1] = sd[s].M;
+        r[2] = sd[s].N;
+        r[3] = sd[s].npd;
+        r[4] = sd[s].x_off;
+        r[5] = sd[s].c3_off;
+        r[6] = sd[s].pd_off;
+        r[7] = sd[s].cls;
+    }
+    return HOS_OK;
+}
+
+static int batch_common(const void *x, int32_t dtype, const void *plan_host,
+                        const void *plan_dev, void *ws, size_t ws_bytes,
+                        const BatchHeader **hout)
+{
+    const BatchHeader *h = plan_header(plan_host);
+    if (!h || !x || !plan_dev || !ws)
+        return HOS_EINVAL;
+    if (dtype != HOS_F32 && dtype != HOS_F64)
+        return HOS_EINVAL;
+    if (!aligned_to(x, dtype == HOS_F64 ? 8 : 4) || !aligned_to(ws, 256) ||
+        !aligned_to(plan_dev, 256))
+        return HOS_EINVAL;
+    if (ws_bytes < (size_t)h->ws_bytes)
+        return HOS_EWORKSPACE;
+    *hout = h;
+    return device_ok_public();
+}
+
+// The shared forward: moments, operands, contraction, reduction.
+static hipError_t batch_forward(const void *x, int32_t dtype, const BatchHeader &h,
+                                const char *dplan, char *w, hipStream_t stream)
+{
+    hipError_t e = launch_batch_prep(x, dtype, h, dplan, w, stream);
+    if (e == hipSuccess) e = launch_batch_contract(h, dplan, w, stream);
+    if (e == hipSuccess) e = launch_batch_reduce(x, dtype, h, dplan, w, stream);
+    return e;
+}
+
+int hos_bispectrum_batched(const void *x, int32_t dtype, const void *plan_host,
+                           const void *plan_dev, double *c3, double *B_pd, void *ws,
+                           size_t ws_bytes, hipStream_t stream)
+{
+    const BatchHeader *h = nullptr;
+    if (!c3 && !B_pd)
+        return HOS_EINVAL;
+    if ((c3 && !aligned_to(c3, 8)) || (B_pd && !aligned_to(B_pd, 16)))
+        return HOS_EINVAL;
+    int st = batch_common(x, dtype, plan_host, plan_dev, ws, ws_bytes, &h);
+    if (st != HOS_OK)
+        return st;
+    char *w = (char *)ws;
+    hipError_t e = batch_forward(x, dtype, *h, (const char *)plan_dev, w, stream);
+    if (e == hipSuccess)
+        e = launch_batch_spectra(*h, (const char *)plan_dev, (int)h->window, c3, B_pd, w, stream);
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
+int hos_bispectrum_loss_fwd(const void *x, int32_t dtype, const void *plan_host,
+                            const void *plan_dev, const double *target_pd, double *B_pd,
+                            double *loss, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const BatchHeader *h = nullptr;
+    if (!target_pd || !B_pd || !loss)
+        return HOS_EINVAL;
+    if (!aligned_to(target_pd, 16) || !aligned_to(B_pd, 16) || !aligned_to(loss, 8))
+        return HOS_EINVAL;
+    const BatchHeader *hh = plan_header(plan_host);
+    if (hh && hh->uniform_M < 0)
+        return HOS_EINVAL;   // one target needs one DFT size
+    int st = batch_common(x, dtype, plan_host, plan_dev, ws, ws_bytes, &h);
+    if (st != HOS_OK)
+        return st;
+    char *w = (char *)ws;
+    hipError_t e = batch_forward(x, dtype, *h, (const char *)plan_dev, w, stream);
+    if (e == hipSuccess)
+        e = launch_batch_spectra(*h, (const char *)plan_dev, (int)h->window, nullptr, B_pd, w,
+                                 stream);
+    if (e == hipSuccess)
+        e = launch_batch_loss(*h, (const char *)plan_dev, B_pd, target_pd, loss, w, stream);
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
+int hos_bispectrum_loss_bwd(const void *x, int32_t dtype, const void *plan_host,
+                            const void *plan_dev, const double *B_pd, const double *target_pd,
+                            const double *dL, void *dx, void *ws, size_t ws_bytes,
+                            hipStream_t stream)
+{
+    const BatchHeader *h = nullptr;
+    if (!B_pd || !target_pd || !dL || !dx)
+        return HOS_EINVAL;
+    if (!aligned_to(B_pd, 16) || !aligned_to(target_pd, 16) || !aligned_to(dL, 8) ||
+        !aligned_to(dx, dtype == HOS_F64 ? 8 : 4))
+        return HOS_EINVAL;
+    const BatchHeader *hh = plan_header(plan_host);
+    if (hh && (hh->uniform_M < 0 || !(hh->flags & HOS_PLAN_ADJOINT)))
+        return HOS_EINVAL;
+    int st = batch_common(x, dtype, plan_host, plan_dev, ws, ws_bytes, &h);
+    if (st != HOS_OK)
+        return st;
+    char *w = (char *)ws;
+    hipError_t e = launch_batch_prep(x, dtype, *h, (const char *)plan_dev, w, stream);
+    if (e == hipSuccess)
+        e = launch_batch_adjoint(x, dtype, *h, (const char *)plan_dev, (int)h->window, B_pd,
+                                 target_pd, dL, dx, w, stream);
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
+}  // extern "C"

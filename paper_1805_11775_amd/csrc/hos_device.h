@@ -1,0 +1,77 @@
+// hos_device.h -- small device helpers shared by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hos {
+
+// Parzen lag window d(m) with scale L (the lag-window reading of the
+// smoothing step, Algorithm DBS step 5): 1 - 6r^2 + 6r^3 for r = |m|/L <=
+// 1/2, 2(1 - r)^3 for 1/2 < r <= 1, 0 beyond.  At L = 0 it is its L -> 0+
+// limit: 1 at m = 0, 0 elsewhere.
+__device__ inline double parzen_d(int m, int L)
+{
+    if (L == 0)
+        return m == 0 ? 1.0 : 0.0;
+    const double r = fabs((double)m) / (double)L;
+    if (r <= 0.5)
+        return 1.0 - 6.0 * r * r + 6.0 * r * r * r;
+    if (r <= 1.0) {
+        const double u = 1.0 - r;
+        return 2.0 * u * u * u;
+    }
+    return 0.0;
+}
+
+// W3(w1, w2) = d(w1) d(w2) d(w1 - w2) (Parzen) or 1 (no window).
+__device__ inline double window3(int w1, int w2, int M, bool parzen)
+{
+    return parzen ? parzen_d(w1, M) * parzen_d(w2, M) * parzen_d(w1 - w2, M) : 1.0;
+}
+
+// c3(w1, w2) from the fundamental-region table C[a][b] (row stride M + 1):
+// the offsets {0, w1, w2} shifted by their minimum and sorted are {0, b, a};
+// lags with span a > M lie outside the hexagon and give 0.
+__device__ inline double c3_from_table(const double *__restrict__ cfull, int M, double norm,
+                                       int w1, int w2)
+{
+    const int mn = min(0, min(w1, w2)), mx = max(0, max(w1, w2));
+    const int a = mx - mn;
+    if (a > M)
+        return 0.0;
+    const int b = (w1 + w2) - mn - mx - mn;
+    return cfull[(int64_t)a * (M + 1) + b] / norm;
+}
+
+// SplitMix64 output function (Steele, Lea and Flood, "Fast splittable
+// pseudorandom number generators", OOPSLA 2014): a counter-based mix of z.
+__device__ inline uint64_t splitmix64(uint64_t z)
+{
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// v rounded to FP32 by stochastic rounding: up with probability equal to
+// the fraction of the gap below v, down otherwise, the uniform draw being a
+// deterministic function of `key` (the sample index).  Unlike round-to-
+// nearest, the rounding error has zero mean for EVERY value, so rounding a
+// centred series cannot leave a systematic offset (round-to-nearest of
+// (x - mean) s has one: its error depends on the low bits of mean * s).
+// Exact values, zero among them, are returned unchanged.
+__device__ inline float round_stochastic_f32(double v, uint64_t key)
+{
+    const float f = (float)v;
+    const double fd = (double)f;
+    if (fd == v || !isfinite(v))
+        return f;
+    const float lo = fd < v ? f : nextafterf(f, -__builtin_huge_valf());
+    const float hi = fd < v ? nextafterf(f, __builtin_huge_valf()) : f;
+    const double frac = (v - (double)lo) / ((double)hi - (double)lo);
+    const double u = (double)(splitmix64(key) >> 11) * 0x1.0p-53;
+    return u < frac ? hi : lo;
+}
+
+}  // namespace hos

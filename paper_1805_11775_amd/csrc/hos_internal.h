@@ -192,6 +192,68 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p);
 int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p);
 int c4_window_entries(int M);
 
+// ---------------------------------------------------------------------------
+// Batches.  A host-built plan ("blob", copied unchanged to device memory by
+// the caller) describes every series and the contraction's work items.
+// Series s occupies samples [x_off, x_off + n) of the packed input and a
+// region of the workspace at ws_off; all offsets inside it are bytes.
+// ---------------------------------------------------------------------------
+struct SeriesDesc {
+    int64_t n, x_off, ws_off;
+    int64_t c3_off;       // first element of its (2M+1)^2 block of the packed c3
+    int64_t pd_off;       // first complex element of its principal-domain block
+    int64_t grid_off;     // byte offset (from the workspace base) of its N x N grid
+    int64_t npad;         // table entries from sample 0 (zero beyond n)
+    int64_t lpad;         // zero table entries before sample 0
+    int32_t M, N, NB, NBR, TR, nleft, npd, group, KP, cls;
+    int64_t C;            // 512-sample chunks
+    // byte offsets inside the series region; table offsets point at sample 0
+    int64_t o_stats, o_mpart, o_xf, o_win4, o_win8h, o_win8l, o_cfull, o_dpart;
+    int64_t o_gtil, o_k64, o_kh, o_kl;   // adjoint buffers (plans made for the adjoint)
+};
+
+struct C3Item {           // one (series, tile, chunk range) of the contraction
+    int32_t series, R, Cc, pad;
+    int64_t c0, c1;       // chunks [c0, c1)
+    int64_t slot;         // partial tile written
+};
+
+struct C3TileRef {        // the slots of one (series, tile), summed in order
+    int32_t series, R, Cc, nslot;
+    int64_t slot0;
+};
+
+struct FftGroup {         // series sharing one DFT size, grids contiguous
+    int32_t N, count;
+    int64_t grid_off;     // byte offset of the first grid
+    int64_t twid_off;     // byte offset of the N twiddles
+};
+
+constexpr int64_t BATCH_MAGIC = 0x484f53424154434bLL;   // "HOSBATCK"
+constexpr int BATCH_CLASSES = 2;                         // tiles of 2 x 2 / 4 x 4 blocks
+
+struct BatchHeader {
+    int64_t magic, blob_bytes, ws_bytes;
+    int64_t batch, path, flags, window;
+    int64_t momb, dot_blocks;
+    int64_t max_n, max_npad, max_lpad, max_M, max_N, max_nleft, max_npd, max_side2, max_KP;
+    int64_t uniform_M, uniform_n;   // shared by every series, else -1
+    int64_t c3_total, pd_total, x_total;
+    int64_t series_off;             // byte offsets of the arrays inside the blob
+    int64_t items_off[BATCH_CLASSES], n_items[BATCH_CLASSES];
+    int64_t wgfirst_off[BATCH_CLASSES], G[BATCH_CLASSES];
+    int64_t tiles_off[BATCH_CLASSES], n_tiles[BATCH_CLASSES];
+    int64_t part_off[BATCH_CLASSES];  // byte offsets of the partial arenas in the workspace
+    int64_t groups_off, n_groups;
+    int64_t loss_off;               // byte offset of the per-series loss partials
+};
+
+// Plan flags (in hos.h: HOS_PLAN_ADJOINT).
+int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window, int32_t path,
+               uint32_t flags, void *blob, size_t blob_bytes, BatchHeader *hdr_out);
+int device_ok_public();
+constexpr int ADJ_MAX_M = 320;     // staged adjoint window <= 48 KB of LDS
+
 // Element count of one FP64 partial tile.
 inline int64_t tile_elems(int NB) { return (int64_t)(32 * NB) * (32 * NB); }
 
@@ -213,6 +275,24 @@ hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s);
 hipError_t launch_fft2(double *B, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_fft3(double *T, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s);
+hipError_t launch_fft2_batch(double *grids, int N, int count, const double2 *tw, hipStream_t s);
+
+// Batched launchers: `hdr` is the host copy of the plan, `dplan` its device
+// copy, `ws` the workspace base.
+hipError_t launch_batch_prep(const void *x, int dtype, const BatchHeader &hdr,
+                             const char *dplan, char *ws, hipStream_t s);
+hipError_t launch_batch_contract(const BatchHeader &hdr, const char *dplan, char *ws,
+                                 hipStream_t s);
+hipError_t launch_batch_reduce(const void *x, int dtype, const BatchHeader &hdr,
+                               const char *dplan, char *ws, hipStream_t s);
+hipError_t launch_batch_spectra(const BatchHeader &hdr, const char *dplan, int window,
+                                double *c3, double *B_pd, char *ws, hipStream_t s);
+hipError_t launch_batch_loss(const BatchHeader &hdr, const char *dplan, const double *B_pd,
+                             const double *target, double *loss, char *ws, hipStream_t s);
+hipError_t launch_batch_adjoint(const void *x, int dtype, const BatchHeader &hdr,
+                                const char *dplan, int window, const double *B_pd,
+                                const double *target, const double *dL, void *dx, char *ws,
+                                hipStream_t s);
 hipError_t launch_c4_reduce(const void *x, int dtype, const C4Plan &p, char *ws,
                             hipStream_t s);
 hipError_t launch_c4_finish(const C4Plan &p, int window, int nfft, double *c4, double *T,

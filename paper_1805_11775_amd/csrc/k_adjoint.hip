@@ -1,0 +1,382 @@
+// k_adjoint.hip -- gradient of the bispectrum-matching loss with respect to
+// the input series (the adjoint of the estimator), recomputing the product
+// terms from the series instead of storing anything of the forward pass.
+//
+// Loss: L = sum_k |B(k) - T(k)|^2 over the principal domain, B the windowed
+// DFT of c3 (Algorithm DBS steps 3-4 for the sign and the domain).  With
+// R = B - T, the weight of each lag is
+//     G(w) = dL/dc3(w) = 2 W3(w) Re sum_k R_k e^{+2 pi i <k,w>/N},
+// obtained as the real part of a forward DFT of conj(2 R) placed on the
+// grid.  Differentiating c3(w) = (1/n) sum_t x_t x_{t+w1} x_{t+w2} gives,
+// for the mean-removed series x,
+//     g_j = dL/dx_j = sum_{u,v} K(u,v) x_{j+u} x_{j+v},
+//     K(u,v) = (1/n) [G(u,v) + G(-u, v-u) + G(v-u, -u)],
+// a quadratic form of the (2M+1)-sample window around j (K vanishes
+// outside the hexagon |u|,|v|,|u-v| <= M).  Only the symmetric part of K
+// matters; it is stored block-upper-triangular (32 x 32 blocks: diagonal
+// blocks once, blocks above twice, below none), so
+//     g_j = sum_u x_{j+u} Z[j][u],   Z[j][u] = sum_v K2(u,v) x_{j+v}:
+// a matrix-core contraction of the Hankel matrix H[j][v] = x_{j+v} with K2,
+// followed by a row-wise dot product with the same Hankel rows.  The mean
+// removal contributes dL/dx_j = g_j - mean(g).
+#include "hos_internal.h"
+#include "hos_device.h"
+
+namespace hos {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int ADJ_ROWS = 256;   // rows j per workgroup: 4 waves x 2 blocks of 32
+
+__device__ inline int pd_row_len(int k1, int H) { return k1 <= H ? min(k1, H - k1) + 1 : 0; }
+
+__device__ inline int pd_index(int k1, int k2, int N)
+{
+    const int H = (N - 1) / 2;
+    if (k2 > k1 || k1 + k2 > H)
+        return -1;
+    int p = 0;
+    for (int a = 0; a < k1; ++a)
+        p += pd_row_len(a, H);
+    return p + k2;
+}
+
+// grid = conj(2 dL (B - T)) on the principal domain, 0 elsewhere.
+__global__ void __launch_bounds__(256)
+k_adj_resid(const SeriesDesc *__restrict__ sd, const double2 *__restrict__ B_pd,
+            const double2 *__restrict__ target, const double *__restrict__ dL,
+            char *__restrict__ ws)
+{
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int N = d.N;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N)
+        return;
+    const int p = pd_index((int)(idx / N), (int)(idx % N), N);
+    double2 v = make_double2(0.0, 0.0);
+    if (p >= 0) {
+        const double2 b = B_pd[d.pd_off + p], t = target[p];
+        const double c = 2.0 * dL[0];
+        v = make_double2(c * (b.x - t.x), -c * (b.y - t.y));
+    }
+    ((double2 *)(ws + d.grid_off))[idx] = v;
+}
+
+// G(w) from the transformed grid (0 outside the hexagon).
+__device__ inline double g_at(const double2 *__restrict__ F, int N, int M, bool parzen, int w1,
+                              int w2)
+{
+    if (w1 < -M || w1 > M || w2 < -M || w2 > M || w1 - w2 < -M || w1 - w2 > M)
+        return 0.0;
+    const int m1 = w1 < 0 ? w1 + N : w1, m2 = w2 < 0 ? w2 + N : w2;
+    return window3(w1, w2, M, parzen) * F[(int64_t)m1 * N + m2].x;
+}
+
+// K2 in FP64 over [0, KP)^2 (u' = u + M, v' = v + M; padding is 0).
+__global__ void __launch_bounds__(256)
+k_adj_kbuild(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int window)
+{
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int KP = d.KP, M = d.M;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)KP * KP)
+        return;
+    const int up = (int)(idx / KP), vp = (int)(idx % KP);
+    double val = 0.0;
+    const int bu = up >> 5, bv = vp >> 5;
+    if (up <= 2 * M && vp <= 2 * M && bv >= bu) {
+        const double2 *F = (const double2 *)(ws + d.grid_off);
+        const bool pz = window == HOS_WIN_PARZEN;
+        const int u = up - M, v = vp - M;
+        auto K = [&](int a, int b) {
+            return g_at(F, d.N, M, pz, a, b) + g_at(F, d.N, M, pz, -a, b - a) +
+                   g_at(F, d.N, M, pz, b - a, -a);
+        };
+        const double ks = 0.5 * (K(u, v) + K(v, u)) / (double)d.n;
+        val = bv > bu ? 2.0 * ks : ks;
+    }
+    ((double *)(ws + d.ws_off + d.o_k64))[idx] = val;
+}
+
+// Power-of-two scale sk with max|K2| sk in [2^14, 2^15): stats[5] = sk.
+__global__ void __launch_bounds__(1024)
+k_adj_kmax(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
+{
+    __shared__ double red[1024];
+    const SeriesDesc &d = sd[blockIdx.x];
+    char *r = ws + d.ws_off;
+    const double *k64 = (const double *)(r + d.o_k64);
+    const int64_t tot = (int64_t)d.KP * d.KP;
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < tot; i += 1024)
+        m = fmax(m, fabs(k64[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double sk = 1.0;
+        if (red[0] > 0.0 && isfinite(red[0])) {
+            int e;
+            frexp(red[0], &e);
+            sk = ldexp(1.0, 15 - e);
+        }
+        ((double *)(r + d.o_stats))[5] = sk;
+    }
+}
+
+// K2 sk rounded for the matrix cores: FP32, or hi + lo halves.
+template <int PATH>
+__global__ void __launch_bounds__(256)
+k_adj_ksplit(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
+{
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)d.KP * d.KP)
+        return;
+    char *r = ws + d.ws_off;
+    // rows of odd 32-blocks of u are stored negated (see k_adj_contract)
+    const double sk = ((const double *)(r + d.o_stats))[5];
+    const double sg = ((idx / d.KP) >> 5) & 1 ? -1.0 : 1.0;
+    const float v = (float)(((const double *)(r + d.o_k64))[idx] * sk * sg);
+    if constexpr (PATH == HOS_PATH_FP32) {
+        ((float *)(r + d.o_kh))[idx] = v;
+    } else if constexpr (PATH == HOS_PATH_SPLIT_FP16) {
+        const _Float16 hi = (_Float16)v;
+        const _Float16 lo = (_Float16)(v - (float)hi);
+        ((_Float16 *)(r + d.o_kh))[idx] = hi;
+        ((_Float16 *)(r + d.o_kl))[idx] = lo;
+    } else {
+        const __bf16 hi = (__bf16)v;
+        const __bf16 lo = (__bf16)(v - (float)hi);
+        ((__bf16 *)(r + d.o_kh))[idx] = hi;
+        ((__bf16 *)(r + d.o_kl))[idx] = lo;
+    }
+}
+
+template <int PATH>
+__device__ inline floatx16 mma16(uint4 a, uint4 b, floatx16 c)
+{
+    if constexpr (PATH == HOS_PATH_SPLIT_FP16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a),
+                                                      __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// g_j s^2 sk for ADJ_ROWS rows j per workgroup (blockIdx.y = series).  The
+// workgroup stages the table entries its rows touch, [j0 - M, j0 + ROWS +
+// KP + 64 - M), in LDS; wave w owns rows j0 + 64w + [0, 64) as two 32-row
+// blocks.  For each 32-column block U of u it accumulates Z = H K2^T over
+// the v blocks V >= U within the hexagon's reach (A = Hankel rows from LDS,
+// B = K2 rows from global memory), then folds x_{j+u} Z[j][u] into FP64
+// row partials; the 32 columns are summed across lanes at the end.
+template <int PATH>
+__global__ void __launch_bounds__(256, 2)
+k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
+{
+    extern __shared__ uint4 lds[];
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int64_t j0 = (int64_t)blockIdx.x * ADJ_ROWS;
+    if (j0 >= d.n)
+        return;
+    const int M = d.M, KP = d.KP, NU = KP >> 5, reach = (M + 31) >> 5;
+    char *r = ws + d.ws_off;
+    constexpr bool SPLIT = PATH != HOS_PATH_FP32;
+    float4 *s_f4 = (float4 *)lds;
+    uint4 *s_h = lds + WA, *s_l = lds + 2 * WA;
+    {
+        // this series' window (WA is the largest over the batch)
+        const int WAs = ADJ_ROWS + KP + 64;
+        const int64_t g0 = j0 - M;
+        const float4 *f4 = (const float4 *)(r + d.o_win4);
+        for (int e = threadIdx.x; e < WAs; e += 256)
+            s_f4[e] = f4[g0 + e];
+        if constexpr (SPLIT) {
+            const uint4 *h = (const uint4 *)(r + d.o_win8h), *l = (const uint4 *)(r + d.o_win8l);
+            for (int e = threadIdx.x; e < WAs; e += 256) {
+                s_h[e] = h[g0 + e];
+                s_l[e] = l[g0 + e];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, rl = lane & 31, h = lane >> 5;
+    const int jr0 = wave * 64, jr1 = wave * 64 + 32;
+    double E0[16], E1[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        E0[v] = 0.0;
+        E1[v] = 0.0;
+    }
+    const uint4 *kh = (const uint4 *)(r + d.o_kh), *kl = (const uint4 *)(r + d.o_kl);
+    for (int U = 0; U < NU; ++U) {
+        floatx16 a0, a1;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            a0[v] = 0.0f;
+            a1[v] = 0.0f;
+        }
+        const int Vmax = min(NU - 1, U + reach);
+        const int64_t krow = (int64_t)(U * 32 + rl) * KP;
+        for (int V = U; V <= Vmax; ++V) {
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const int vl = V * 32 + 16 * g + 8 * h;   // first v' of this lane's 8
+                if constexpr (SPLIT) {
+                    const uint4 bh = kh[(krow + vl) >> 3], bl = kl[(krow + vl) >> 3];
+                    const uint4 ah0 = s_h[jr0 + rl + vl], al0 = s_l[jr0 + rl + vl];
+                    const uint4 ah1 = s_h[jr1 + rl + vl], al1 = s_l[jr1 + rl + vl];
+                    a0 = mma16<PATH>(ah0, bh, a0);
+                    a1 = mma16<PATH>(ah1, bh, a1);
+                    a0 = mma16<PATH>(ah0, bl, a0);
+                    a1 = mma16<PATH>(ah1, bl, a1);
+                    a0 = mma16<PATH>(al0, bh, a0);
+                    a1 = mma16<PATH>(al1, bh, a1);
+                } else {
+                    const float4 *kf = (const float4 *)(r + d.o_kh);
+                    const float4 b0 = kf[(krow + vl) >> 2], b1 = kf[((krow + vl) >> 2) + 1];
+                    const float4 x00 = s_f4[jr0 + rl + vl], x01 = s_f4[jr0 + rl + vl + 4];
+                    const float4 x10 = s_f4[jr1 + rl + vl], x11 = s_f4[jr1 + rl + vl + 4];
+                    const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+                    const float xa[8] = {x00.x, x00.y, x00.z, x00.w, x01.x, x01.y, x01.z, x01.w};
+                    const float xb[8] = {x10.x, x10.y, x10.z, x10.w, x11.x, x11.y, x11.z, x11.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[e], bb[e], a0, 0, 0, 0);
+                        a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xb[e], bb[e], a1, 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // fold x_{j+u} Z[j][u]: element v of a lane is row 8(v/4) + 4h + v%4,
+        // column u' = 32U + rl.  Odd U ran on negated K2 rows, so the
+        // matrix cores' rounding bias (toward -infinity) alternates in sign
+        // between column blocks and cancels; the sign is undone here.
+        const double sg = (U & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 y0 = s_f4[jr0 + 8 * q + 4 * h + U * 32 + rl];
+            const float4 y1 = s_f4[jr1 + 8 * q + 4 * h + U * 32 + rl];
+            E0[4 * q + 0] += sg * ((double)a0[4 * q + 0] * (double)y0.x);
+            E0[4 * q + 1] += sg * ((double)a0[4 * q + 1] * (double)y0.y);
+            E0[4 * q + 2] += sg * ((double)a0[4 * q + 2] * (double)y0.z);
+            E0[4 * q + 3] += sg * ((double)a0[4 * q + 3] * (double)y0.w);
+            E1[4 * q + 0] += sg * ((double)a1[4 * q + 0] * (double)y1.x);
+            E1[4 * q + 1] += sg * ((double)a1[4 * q + 1] * (double)y1.y);
+            E1[4 * q + 2] += sg * ((double)a1[4 * q + 2] * (double)y1.z);
+            E1[4 * q + 3] += sg * ((double)a1[4 * q + 3] * (double)y1.w);
+        }
+    }
+    // sum each row over the 32 columns (the lanes of a half-wave)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+            E0[v] += __shfl_xor(E0[v], off, 64);
+            E1[v] += __shfl_xor(E1[v], off, 64);
+        }
+    }
+    if (rl == 0) {
+        double *gt = (double *)(r + d.o_gtil);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = 8 * (v >> 2) + 4 * h + (v & 3);
+            const int64_t ja = j0 + jr0 + row, jb = j0 + jr1 + row;
+            if (ja < d.n)
+                gt[ja] = E0[v];
+            if (jb < d.n)
+                gt[jb] = E1[v];
+        }
+    }
+}
+
+// dx_j = (g_j - mean g) / (s^2 sk), mean in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_adj_final(const SeriesDesc *__restrict__ sd, const char *__restrict__ ws, T *__restrict__ dx)
+{
+    __shared__ double red[1024];
+    const SeriesDesc &d = sd[blockIdx.x];
+    const char *r = ws + d.ws_off;
+    const double *gt = (const double *)(r + d.o_gtil);
+    const double *stats = (const double *)(r + d.o_stats);
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < d.n; j += 1024)
+        s += gt[j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double mean = red[0] / (double)d.n;
+    const double inv = 1.0 / (stats[1] * stats[1] * stats[5]);
+    for (int64_t j = threadIdx.x; j < d.n; j += 1024)
+        dx[d.x_off + j] = (T)((gt[j] - mean) * inv);
+}
+
+template <int PATH>
+void launch_adj_contract(const BatchHeader &h, const SeriesDesc *sd, char *ws, hipStream_t s)
+{
+    const int WA = (int)(ADJ_ROWS + h.max_KP + 64);
+    const size_t lds = (size_t)WA * 16 * (PATH == HOS_PATH_FP32 ? 1 : 3);
+    const dim3 grid((unsigned)((h.max_n + ADJ_ROWS - 1) / ADJ_ROWS), (unsigned)h.batch);
+    k_adj_contract<PATH><<<grid, 256, lds, s>>>(sd, ws, WA);
+}
+
+}  // namespace
+
+hipError_t launch_batch_adjoint(const void *x, int dtype, const BatchHeader &h, const char *dplan,
+                                int window, const double *B_pd, const double *target,
+                                const double *dL, void *dx, char *ws, hipStream_t s)
+{
+    (void)x;
+    const SeriesDesc *sd = (const SeriesDesc *)(dplan + h.series_off);
+    const int B = (int)h.batch;
+    const int64_t n2 = h.max_N * h.max_N;
+    k_adj_resid<<<dim3((unsigned)((n2 + 255) / 256), B), 256, 0, s>>>(
+        sd, (const double2 *)B_pd, (const double2 *)target, dL, ws);
+    const FftGroup *groups = (const FftGroup *)((const char *)&h + h.groups_off);
+    for (int g = 0; g < (int)h.n_groups; ++g) {
+        const FftGroup &gr = groups[g];
+        double2 *tw = (double2 *)(ws + gr.twid_off);
+        hipError_t e = launch_twiddles(tw, gr.N, s);
+        if (e == hipSuccess)
+            e = launch_fft2_batch((double *)(ws + gr.grid_off), gr.N, gr.count, tw, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    const int64_t k2 = h.max_KP * h.max_KP;
+    k_adj_kbuild<<<dim3((unsigned)((k2 + 255) / 256), B), 256, 0, s>>>(sd, ws, window);
+    k_adj_kmax<<<B, 1024, 0, s>>>(sd, ws);
+    const dim3 gk((unsigned)((k2 + 255) / 256), B);
+    if (h.path == HOS_PATH_FP32) {
+        k_adj_ksplit<HOS_PATH_FP32><<<gk, 256, 0, s>>>(sd, ws);
+        launch_adj_contract<HOS_PATH_FP32>(h, sd, ws, s);
+    } else if (h.path == HOS_PATH_SPLIT_FP16) {
+        k_adj_ksplit<HOS_PATH_SPLIT_FP16><<<gk, 256, 0, s>>>(sd, ws);
+        launch_adj_contract<HOS_PATH_SPLIT_FP16>(h, sd, ws, s);
+    } else {
+        k_adj_ksplit<HOS_PATH_SPLIT_BF16><<<gk, 256, 0, s>>>(sd, ws);
+        launch_adj_contract<HOS_PATH_SPLIT_BF16>(h, sd, ws, s);
+    }
+    if (dtype == HOS_F64)
+        k_adj_final<double><<<B, 1024, 0, s>>>(sd, ws, (double *)dx);
+    else
+        k_adj_final<float><<<B, 1024, 0, s>>>(sd, ws, (float *)dx);
+    return hipGetLastError();
+}
+
+}  // namespace hos

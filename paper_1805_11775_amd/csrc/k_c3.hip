@@ -110,14 +110,15 @@ __device__ __attribute__((always_inline)) inline void pin_agpr(double &v)
     asm volatile("" : "+a"(v));
 }
 
+// sgn = -1 undoes the negated product rows of an odd chunk (see below).
 template <int NB, bool PIN>
-__device__ inline void flush_acc(floatx16 (&acc)[NB], double (&acc64)[NB][16])
+__device__ inline void flush_acc(floatx16 (&acc)[NB], double (&acc64)[NB][16], float sgn)
 {
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            acc64[cb][v] += (double)acc[cb][v];
+            acc64[cb][v] += (double)(sgn * acc[cb][v]);
             if (PIN)
                 pin_agpr(acc64[cb][v]);
             acc[cb][v] = 0.0f;
@@ -129,6 +130,15 @@ __device__ inline void flush_acc(floatx16 (&acc)[NB], double (&acc64)[NB][16])
 // chain (measured: the bias of each add is relative to the running sum), and
 // a cumulant that is pure sampling noise (Gaussian input) sits far below the
 // size of its terms, so the chain length sets the relative error there.
+//
+// The error also has a direction: measured on gfx950, a matrix-core op that
+// sums products of mixed sign is biased toward -infinity (about -0.6 to
+// -2.7 ulp of its result for FP16 inputs, -0.05 ulp for FP32), whatever
+// the sign of the result.  Summed over every chunk and then over every lag
+// by the DFT, that bias would add up coherently.  Odd chunks therefore run
+// on negated x_i (so every product row, and the chunk's sum, changes sign;
+// the negation is exact) and are flushed with sgn = -1: their bias points
+// the other way and the two halves cancel.
 template <int PATH>
 struct FlushPeriod {
     static constexpr int GROUPS = PATH == HOS_PATH_FP32 ? 4 : KC / GROUP;
@@ -197,7 +207,7 @@ __device__ __attribute__((always_inline)) inline void split_rows(Yrow<PATH> &y, 
 // with the matrix-core ops.  The FP32 path has the same structure with one
 // multiply per product and 8 matrix-core steps per block per group.
 template <int PATH, int NB, int NCOL>
-__device__ inline void chunk_compute(const float4 *__restrict__ sxi,
+__device__ __attribute__((always_inline)) inline void chunk_compute(const float4 *__restrict__ sxi,
                                      const float4 *__restrict__ sxa,
                                      const uint4 *__restrict__ sxb, int wlen, int rw, int rl,
                                      int h, floatx16 (&acc)[NB], double (&acc64)[NB][16])
@@ -246,11 +256,11 @@ __device__ inline void chunk_compute(const float4 *__restrict__ sxi,
 // (2 ra + rb) marking the active ones.  8 matrix-core steps per block per
 // 16-sample group; the operands of group g+1 are read while group g runs.
 template <int MASK>
-__device__ inline void chunk_compute_fp32(const float4 *__restrict__ sxi,
+__device__ __attribute__((always_inline)) inline void chunk_compute_fp32(const float4 *__restrict__ sxi,
                                           const float4 *__restrict__ sxa,
                                           const uint4 *__restrict__ sxb, int rowbase,
                                           int colbase, int rl, int h, floatx16 (&acc)[4],
-                                          double (&acc64)[4][16])
+                                          double (&acc64)[4][16], float sgn)
 {
     constexpr int NG = KC / GROUP;
     constexpr int FG = FlushPeriod<HOS_PATH_FP32>::GROUPS;
@@ -305,7 +315,7 @@ __device__ inline void chunk_compute_fp32(const float4 *__restrict__ sxi,
         t[0] = tn[0];
         t[1] = tn[1];
         if ((g + 1) % FG == 0)
-            flush_acc<4, false>(acc, acc64);
+            flush_acc<4, false>(acc, acc64, sgn);
     }
 }
 
@@ -332,16 +342,16 @@ __device__ inline void fp32_window(bool diag, int wave, int tileR, int NBR, int 
             mask &= ~(3 << (2 * ra));
 }
 
-__device__ inline void dispatch_fp32(int mask, const float4 *sxi, const float4 *sxa,
+__device__ __attribute__((always_inline)) inline void dispatch_fp32(int mask, const float4 *sxi, const float4 *sxa,
                                      const uint4 *sxb, int rowbase, int colbase, int rl, int h,
-                                     floatx16 (&acc)[4], double (&acc64)[4][16])
+                                     floatx16 (&acc)[4], double (&acc64)[4][16], float sgn)
 {
     switch (mask) {
-    case 0xF: chunk_compute_fp32<0xF>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
-    case 0xD: chunk_compute_fp32<0xD>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
-    case 0x5: chunk_compute_fp32<0x5>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
-    case 0x3: chunk_compute_fp32<0x3>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
-    case 0x1: chunk_compute_fp32<0x1>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64); break;
+    case 0xF: chunk_compute_fp32<0xF>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64, sgn); break;
+    case 0xD: chunk_compute_fp32<0xD>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64, sgn); break;
+    case 0x5: chunk_compute_fp32<0x5>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64, sgn); break;
+    case 0x3: chunk_compute_fp32<0x3>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64, sgn); break;
+    case 0x1: chunk_compute_fp32<0x1>(sxi, sxa, sxb, rowbase, colbase, rl, h, acc, acc64, sgn); break;
     default: break;
     }
 }
@@ -357,7 +367,7 @@ __device__ inline int wave_cols(int NB, bool diag, int rw, int tileR, int NBR)
 }
 
 template <int PATH, int NB>
-__device__ inline void dispatch_compute(int ncol, const float4 *sxi, const float4 *sxa,
+__device__ __attribute__((always_inline)) inline void dispatch_compute(int ncol, const float4 *sxi, const float4 *sxa,
                                         const uint4 *sxb, int wlen, int rw, int rl, int h,
                                         floatx16 (&acc)[NB], double (&acc64)[NB][16])
 {
@@ -439,17 +449,19 @@ load_chunk(u32x4 (&stg)[NPW], const float *__restrict__ xf, const uint4 *__restr
     }
 }
 
+// neg: store the x_i run with its sign flipped (odd chunks).
 template <int PATH, int NB, int NPW>
 __device__ __attribute__((always_inline)) inline void
-store_chunk(const u32x4 (&stg)[NPW], ChunkLds<PATH, NB> &L, int wave, int lane)
+store_chunk(const u32x4 (&stg)[NPW], ChunkLds<PATH, NB> &L, int wave, int lane, bool neg)
 {
     typedef ChunkLds<PATH, NB> CL;
     u32x4 *base = (u32x4 *)&L;
+    const unsigned flip = neg ? 0x80000000u : 0u;
 #pragma unroll
     for (int m = 0; m < NPW; ++m) {
         const int j = wave + CL::NW * m;
         if (j < CL::NCH)
-            base[64 * j + lane] = stg[m];
+            base[64 * j + lane] = 64 * j < CL::NXI ? (stg[m] ^ flip) : stg[m];
     }
 }
 
@@ -505,7 +517,7 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
 
     u32x4 stg[CL::NPW];
     load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, q, wave, lane);
-    store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane);
+    store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
     __syncthreads();
 
     // Each step prefetches the next chunk into registers, computes on the
@@ -520,16 +532,17 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
         if (has_next)
             load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, nq, wave, lane);
 
+        const float sgn = (q.c & 1) ? -1.0f : 1.0f;
         if constexpr (PATH == HOS_PATH_FP32) {
             static_assert(NB == 4, "the FP32 wave layout assumes 4 x 4-block tiles");
             dispatch_fp32(mask, buf[cur].xi, buf[cur].xa, buf[cur].xb, rowbase, colbase, rl, h,
-                          acc, acc64);
+                          acc, acc64, sgn);
         } else {
             dispatch_compute<PATH, NB>(ncol, buf[cur].xi, buf[cur].xa, buf[cur].xb, CL::WLEN,
                                        wave, rl, h, acc, acc64);
         }
         if constexpr (PATH != HOS_PATH_FP32)   // the FP32 path flushes inside
-            flush_acc<NB, true>(acc, acc64);
+            flush_acc<NB, true>(acc, acc64, sgn);
 
         const bool seg_end = !has_next || nq.R != q.R || nq.Cc != q.Cc;
         if (seg_end) {
@@ -562,7 +575,7 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
         if (!has_next)
             break;
         cur ^= 1;
-        store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane);
+        store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane, nq.c & 1);
         __syncthreads();
         if (seg_end)
             set_layout(nq);
@@ -657,6 +670,253 @@ k_diag_final(const double *__restrict__ dpart, int nleft, int nblocks, int M,
     cfull[a * (M + 1) + a] = s;
 }
 
+// ------------------------------------------------------------------ batches
+// The persistent contraction over a batch: workgroup w runs the work items
+// wgfirst[w] .. wgfirst[w+1]-1 of the plan (each a chunk range of one tile
+// of one series) with the same per-chunk pipeline as k_c3_contract; the
+// next chunk, possibly of the next item and another series, is prefetched
+// while the current one is computed.  Each item writes its own partial tile.
+struct SeriesPtrs {
+    const float *xf;
+    const uint4 *w4, *w8h, *w8l;
+    int NBR;
+};
+
+__device__ inline SeriesPtrs series_ptrs(const SeriesDesc &d, const char *ws)
+{
+    const char *r = ws + d.ws_off;
+    SeriesPtrs p;
+    p.xf = (const float *)(r + d.o_xf);
+    p.w4 = (const uint4 *)(r + d.o_win4);
+    p.w8h = (const uint4 *)(r + d.o_win8h);
+    p.w8l = (const uint4 *)(r + d.o_win8l);
+    p.NBR = d.NBR;
+    return p;
+}
+
+template <int PATH, int NB>
+__global__ void __launch_bounds__(64 * NB, 1)
+k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
+           const int32_t *__restrict__ wgfirst, const char *__restrict__ ws,
+           double *__restrict__ part)
+{
+    typedef ChunkLds<PATH, NB> CL;
+    constexpr int64_t TILE = (int64_t)CL::TS * CL::TS;
+
+    __shared__ CL buf[2];
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, rl = lane & 31, h = lane >> 5;
+    const int k1 = wgfirst[blockIdx.x + 1];
+    int k = wgfirst[blockIdx.x];
+    if (k >= k1)
+        return;
+
+    C3Item it = items[k];
+    SeriesPtrs sp = series_ptrs(sd[it.series], ws);
+    SkPos q;
+    q.R = it.R;
+    q.Cc = it.Cc;
+    q.c = it.c0;
+
+    floatx16 acc[NB];
+    double acc64[NB][16];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            acc[cb][v] = 0.0f;
+            acc64[cb][v] = 0.0;
+            if (PATH != HOS_PATH_FP32)
+                pin_agpr(acc64[cb][v]);
+        }
+
+    int ncol = 0, rowbase = 0, colbase = 0, mask = 0;
+    auto set_layout = [&](const SkPos &p, int NBR) {
+        if constexpr (PATH == HOS_PATH_FP32) {
+            fp32_window(p.Cc == p.R, wave, p.R, NBR, rowbase, colbase, mask);
+            mask = __builtin_amdgcn_readfirstlane(mask);
+            rowbase = __builtin_amdgcn_readfirstlane(rowbase);
+            colbase = __builtin_amdgcn_readfirstlane(colbase);
+        } else {
+            ncol = __builtin_amdgcn_readfirstlane(wave_cols(NB, p.Cc == p.R, wave, p.R, NBR));
+        }
+    };
+    set_layout(q, sp.NBR);
+
+    u32x4 stg[CL::NPW];
+    load_chunk<PATH, NB, CL::NPW>(stg, sp.xf, sp.w4, sp.w8h, sp.w8l, q, wave, lane);
+    store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
+    __syncthreads();
+
+    int cur = 0;
+    for (;;) {
+        // the next chunk: the same item, else the first chunk of the next item
+        SkPos nq = q;
+        C3Item nit = it;
+        SeriesPtrs nsp = sp;
+        bool has_next = true, new_item = false;
+        if (q.c + 1 < it.c1) {
+            nq.c = q.c + 1;
+        } else if (k + 1 < k1) {
+            nit = items[k + 1];
+            nsp = series_ptrs(sd[nit.series], ws);
+            nq.R = nit.R;
+            nq.Cc = nit.Cc;
+            nq.c = nit.c0;
+            new_item = true;
+        } else {
+            has_next = false;
+        }
+        if (has_next)
+            load_chunk<PATH, NB, CL::NPW>(stg, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq, wave, lane);
+
+        const float sgn = (q.c & 1) ? -1.0f : 1.0f;
+        if constexpr (PATH == HOS_PATH_FP32) {
+            dispatch_fp32(mask, buf[cur].xi, buf[cur].xa, buf[cur].xb, rowbase, colbase, rl, h,
+                          acc, acc64, sgn);
+        } else {
+            dispatch_compute<PATH, NB>(ncol, buf[cur].xi, buf[cur].xa, buf[cur].xb, CL::WLEN,
+                                       wave, rl, h, acc, acc64);
+        }
+        if constexpr (PATH != HOS_PATH_FP32)
+            flush_acc<NB, true>(acc, acc64, sgn);
+
+        if (!has_next || new_item) {
+            double *dst = part + it.slot * TILE;
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                bool on;
+                int blk;
+                if constexpr (PATH == HOS_PATH_FP32) {
+                    on = (mask >> cb) & 1;
+                    blk = (rowbase + (cb >> 1)) * NB + colbase + (cb & 1);
+                } else {
+                    on = cb < ncol;
+                    blk = wave * NB + cb;
+                }
+                if (on) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v)
+                        dst[(blk * 16 + v) * 64 + lane] = acc64[cb][v];
+                }
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    acc64[cb][v] = 0.0;
+                    if (PATH != HOS_PATH_FP32)
+                        pin_agpr(acc64[cb][v]);
+                }
+            }
+        }
+        if (!has_next)
+            break;
+        cur ^= 1;
+        store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane, nq.c & 1);
+        __syncthreads();
+        if (new_item) {
+            ++k;
+            it = nit;
+            sp = nsp;
+            set_layout(nq, sp.NBR);
+        }
+        q = nq;
+    }
+}
+
+// Sum the slots of one (series, tile) in order and scatter one 32 x 32 block
+// into the series' C[a][b] table.  One workgroup per (tile, block).
+template <int NB>
+__global__ void __launch_bounds__(256)
+k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict__ tiles,
+                  const double *__restrict__ part, char *__restrict__ ws)
+{
+    constexpr int64_t TILE = (int64_t)(32 * NB) * (32 * NB);
+    const C3TileRef t = tiles[blockIdx.x / (NB * NB)];
+    const int blk = blockIdx.x % (NB * NB);
+    const SeriesDesc &d = sd[t.series];
+    const int bR = blk / NB, bC = blk % NB;
+    const int Rg = t.R * NB + bR, Bg = t.Cc * NB + bC;
+    if (Rg >= d.NBR || Bg > Rg)
+        return;
+    const int M = d.M;
+    double *cfull = (double *)(ws + d.ws_off + d.o_cfull);
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < t.nslot; ++j) {
+        const double *src = part + (t.slot0 + j) * TILE + (int64_t)blk * 1024;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            sum[k] += src[threadIdx.x + 256 * k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        const int v = e >> 6, lane = e & 63;
+        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = lane & 31;
+        const int r = Rg * 32 + row, b = Bg * 32 + col;
+        if (r < M && (Bg < Rg || col <= row + 1))
+            cfull[(int64_t)(r + 1) * (M + 1) + b] = sum[k];
+    }
+}
+
+// Leftover diagonal sums per series: blockIdx.y = series, blockIdx.x =
+// (leftover, block); blocks past the series' own leftovers return.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bdiag_dot(const T *__restrict__ x, const SeriesDesc *__restrict__ sd, char *__restrict__ ws,
+            int nblocks)
+{
+    __shared__ double red[256];
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int left = blockIdx.x / nblocks, blk = blockIdx.x % nblocks;
+    if (left >= d.nleft)
+        return;
+    char *r = ws + d.ws_off;
+    const double *stats = (const double *)(r + d.o_stats);
+    const T *xs = x + d.x_off;
+    const int64_t a = 32 * (int64_t)left, n = d.n;
+    const double mu = stats[0], sc = stats[1];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i + a < n; i += (int64_t)nblocks * 256) {
+        const double u = ((double)xs[i + a] - mu) * sc;
+        s += (((double)xs[i] - mu) * sc) * u * u;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int wdt = 128; wdt > 0; wdt >>= 1) {
+        if (threadIdx.x < wdt)
+            red[threadIdx.x] += red[threadIdx.x + wdt];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        ((double *)(r + d.o_dpart))[left * nblocks + blk] = red[0];
+}
+
+__global__ void __launch_bounds__(64)
+k_bdiag_final(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int nblocks)
+{
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int left = blockIdx.x * 64 + threadIdx.x;
+    if (left >= d.nleft)
+        return;
+    char *r = ws + d.ws_off;
+    const double *dpart = (const double *)(r + d.o_dpart);
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b)
+        s += dpart[left * nblocks + b];
+    const int64_t a = 32 * (int64_t)left;
+    ((double *)(r + d.o_cfull))[a * (d.M + 1) + a] = s;
+}
+
+template <int PATH, int NB>
+void launch_items_t(const BatchHeader &h, int cls, const char *dplan, char *ws, hipStream_t s)
+{
+    k_c3_items<PATH, NB><<<(unsigned)h.G[cls], 64 * NB, 0, s>>>(
+        (const SeriesDesc *)(dplan + h.series_off), (const C3Item *)(dplan + h.items_off[cls]),
+        (const int32_t *)(dplan + h.wgfirst_off[cls]), ws, (double *)(ws + h.part_off[cls]));
+}
+
 template <int PATH, int NB>
 void launch_contract_t(const C3Plan &p, char *ws, hipStream_t s)
 {
@@ -715,6 +975,57 @@ hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s)
     }
     k_diag_final<<<(p.nleft + 63) / 64, 64, 0, s>>>((const double *)(ws + p.off_dpart),
                                                    p.nleft, p.dot_blocks, p.M, cfull);
+    return hipGetLastError();
+}
+
+}  // namespace hos
+
+namespace hos {
+
+hipError_t launch_batch_contract(const BatchHeader &h, const char *dplan, char *ws,
+                                 hipStream_t s)
+{
+    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
+        if (h.n_items[cls] == 0)
+            continue;
+        if (cls == 1) {
+            if (h.path == HOS_PATH_FP32)
+                launch_items_t<HOS_PATH_FP32, 4>(h, cls, dplan, ws, s);
+            else if (h.path == HOS_PATH_SPLIT_FP16)
+                launch_items_t<HOS_PATH_SPLIT_FP16, 4>(h, cls, dplan, ws, s);
+            else
+                launch_items_t<HOS_PATH_SPLIT_BF16, 4>(h, cls, dplan, ws, s);
+        } else {
+            if (h.path == HOS_PATH_SPLIT_FP16)
+                launch_items_t<HOS_PATH_SPLIT_FP16, 2>(h, cls, dplan, ws, s);
+            else
+                launch_items_t<HOS_PATH_SPLIT_BF16, 2>(h, cls, dplan, ws, s);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(const void *x, int dtype, const BatchHeader &h, const char *dplan,
+                               char *ws, hipStream_t s)
+{
+    const SeriesDesc *sd = (const SeriesDesc *)(dplan + h.series_off);
+    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
+        if (h.n_tiles[cls] == 0)
+            continue;
+        const C3TileRef *t = (const C3TileRef *)(dplan + h.tiles_off[cls]);
+        const double *part = (const double *)(ws + h.part_off[cls]);
+        if (cls == 1)
+            k_c3_reduce_items<4><<<(unsigned)(h.n_tiles[cls] * 16), 256, 0, s>>>(sd, t, part, ws);
+        else
+            k_c3_reduce_items<2><<<(unsigned)(h.n_tiles[cls] * 4), 256, 0, s>>>(sd, t, part, ws);
+    }
+    const int B = (int)h.batch, nb = (int)h.dot_blocks;
+    const dim3 grid((unsigned)(h.max_nleft * nb), B);
+    if (dtype == HOS_F64)
+        k_bdiag_dot<double><<<grid, 256, 0, s>>>((const double *)x, sd, ws, nb);
+    else
+        k_bdiag_dot<float><<<grid, 256, 0, s>>>((const float *)x, sd, ws, nb);
+    k_bdiag_final<<<dim3((unsigned)((h.max_nleft + 63) / 64), B), 64, 0, s>>>(sd, ws, nb);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@
 // order.  One workgroup = 4 waves = 4 pair blocks over a contiguous range of
 // 512-sample chunks; all pair blocks read the same staged window of x.
 #include "hos_internal.h"
+#include "hos_device.h"
 
 namespace hos {
 
@@ -161,17 +162,21 @@ c4_load(u32x4 (&stg)[NPW], const float *__restrict__ xf,
     }
 }
 
+// neg: store the x_i run with its sign flipped.  Odd chunks run on -x_i and
+// are flushed with a minus sign, which cancels the matrix cores' directed
+// (toward -infinity) rounding bias between chunks.
 template <int PATH, int WX, int NPW = C4Lds<PATH, WX>::NPW>
 __device__ __attribute__((always_inline)) inline void
-c4_store(const u32x4 (&stg)[NPW], C4Lds<PATH, WX> &L, int wave, int lane)
+c4_store(const u32x4 (&stg)[NPW], C4Lds<PATH, WX> &L, int wave, int lane, bool neg)
 {
     typedef C4Lds<PATH, WX> CL;
     u32x4 *base = (u32x4 *)&L;
+    const unsigned flip = neg ? 0x80000000u : 0u;
 #pragma unroll
     for (int m = 0; m < CL::NPW; ++m) {
         const int j = wave + 4 * m;
         if (j < CL::NCH)
-            base[64 * j + lane] = stg[m];
+            base[64 * j + lane] = 64 * j < CL::NXI ? (stg[m] ^ flip) : stg[m];
     }
 }
 
@@ -179,7 +184,8 @@ c4_store(const u32x4 (&stg)[NPW], C4Lds<PATH, WX> &L, int wave, int lane)
 // zeroes the rows of pairs past the end) against NCOL column blocks.
 template <int PATH, int WX, int NCOL>
 __device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, float live, int rl,
-                                int h, floatx16 (&acc)[NCOL], double (&acc64)[NCOL][16])
+                                int h, floatx16 (&acc)[NCOL], double (&acc64)[NCOL][16],
+                                float sgn)
 {
     constexpr int NG = KC / GROUP;
     constexpr int WLEN = C4Lds<PATH, WX>::WLEN;
@@ -212,7 +218,7 @@ __device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, float li
                 for (int cb = 0; cb < NCOL; ++cb)
 #pragma unroll
                     for (int v = 0; v < 16; ++v) {
-                        acc64[cb][v] += (double)acc[cb][v];
+                        acc64[cb][v] += (double)(sgn * acc[cb][v]);
                         acc[cb][v] = 0.0f;
                     }
             }
@@ -236,7 +242,7 @@ __device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, float li
         for (int cb = 0; cb < NCOL; ++cb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                acc64[cb][v] += (double)acc[cb][v];
+                acc64[cb][v] += (double)(sgn * acc[cb][v]);
                 pin_agpr(acc64[cb][v]);
                 acc[cb][v] = 0.0f;
             }
@@ -268,18 +274,19 @@ __device__ inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict
 
     u32x4 stg[C4Lds<PATH, WX>::NPW];
     c4_load<PATH, WX>(stg, xf, win4, win8h, win8l, c0 * KC, wave, lane);
-    c4_store<PATH, WX>(stg, buf[0], wave, lane);
+    c4_store<PATH, WX>(stg, buf[0], wave, lane, c0 & 1);
     __syncthreads();
     int cur = 0;
     for (int64_t c = c0; c < c1; ++c) {
         const bool has_next = c + 1 < c1;
         if (has_next)
             c4_load<PATH, WX>(stg, xf, win4, win8h, win8l, (c + 1) * KC, wave, lane);
-        c4_chunk<PATH, WX, NCOL>(buf[cur], a, b, live, rl, h, acc, acc64);
+        c4_chunk<PATH, WX, NCOL>(buf[cur], a, b, live, rl, h, acc, acc64,
+                                 (c & 1) ? -1.0f : 1.0f);
         if (!has_next)
             break;
         cur ^= 1;
-        c4_store<PATH, WX>(stg, buf[cur], wave, lane);
+        c4_store<PATH, WX>(stg, buf[cur], wave, lane, (c + 1) & 1);
         __syncthreads();
     }
     if (rb < RB) {
@@ -409,20 +416,6 @@ k_c2_final(const double *__restrict__ dpart, int M, int nblocks, const double *_
     c2[d] = s / ((double)n * sc * sc);
 }
 
-__device__ inline double parzen(int m, int L)
-{
-    if (L == 0)
-        return m == 0 ? 1.0 : 0.0;
-    const double r = fabs((double)m) / (double)L;
-    if (r <= 0.5)
-        return 1.0 - 6.0 * r * r + 6.0 * r * r * r;
-    if (r <= 1.0) {
-        const double u = 1.0 - r;
-        return 2.0 * u * u * u;
-    }
-    return 0.0;
-}
-
 __device__ inline void sort4(int *v)
 {
 #define SW(i, j)                 \
@@ -492,8 +485,8 @@ k_fft_input3(const double *__restrict__ m4tab, const double *__restrict__ c2,
                 const double c = c4_at(m4tab, c2, M, norm4, t1, t2, t3);
                 double w = 1.0;
                 if (window == HOS_WIN_PARZEN)
-                    w = parzen(t1, M) * parzen(t2, M) * parzen(t3, M) * parzen(t2 - t1, M) *
-                        parzen(t3 - t1, M) * parzen(t3 - t2, M);
+                    w = parzen_d(t1, M) * parzen_d(t2, M) * parzen_d(t3, M) *
+                        parzen_d(t2 - t1, M) * parzen_d(t3 - t1, M) * parzen_d(t3 - t2, M);
                 sum += w * c;
             }
         }

@@ -240,3 +240,18 @@ hipError_t launch_fft3(double *T, int N, const double2 *tw, hipStream_t s)
 }
 
 }  // namespace hos
+
+namespace hos {
+
+// In-place 2-D DFTs of `count` contiguous N x N row-major complex grids.
+hipError_t launch_fft2_batch(double *grids, int N, int count, const double2 *tw, hipStream_t s)
+{
+    double2 *d = (double2 *)grids;
+    const FftRadices fr = factor(N);
+    const int64_t rows = (int64_t)count * N;
+    fft_axis(d, tw, fr, rows, 1, 1, 0, N, s);                    // along k2, every grid
+    fft_axis(d, tw, fr, rows, N, N, 1, (int64_t)N * N, s);       // along k1
+    return hipGetLastError();
+}
+
+}  // namespace hos

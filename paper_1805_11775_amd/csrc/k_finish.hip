@@ -14,36 +14,11 @@
 // grid (index w mod N; aliased lags add), which makes the grid DFT equal
 // to sum_w W3(w) c3(w) exp(-2 pi i <k,w>/N) exactly.
 #include "hos_internal.h"
+#include "hos_device.h"
 
 namespace hos {
 
 namespace {
-
-__device__ inline double parzen(int m, int L)
-{
-    if (L == 0)
-        return m == 0 ? 1.0 : 0.0;
-    const double r = fabs((double)m) / (double)L;
-    if (r <= 0.5)
-        return 1.0 - 6.0 * r * r + 6.0 * r * r * r;
-    if (r <= 1.0) {
-        const double u = 1.0 - r;
-        return 2.0 * u * u * u;
-    }
-    return 0.0;
-}
-
-// c3(w1, w2) from the fundamental-region table, 0 outside the hexagon.
-__device__ inline double c3_at(const double *__restrict__ cfull, int M, double norm, int w1,
-                               int w2)
-{
-    const int mn = min(0, min(w1, w2)), mx = max(0, max(w1, w2));
-    const int a = mx - mn;
-    if (a > M)
-        return 0.0;
-    const int b = (w1 + w2) - mn - mx - mn;   // middle offset minus the minimum
-    return cfull[(int64_t)a * (M + 1) + b] / norm;
-}
 
 __global__ void __launch_bounds__(256)
 k_c3_out(const double *__restrict__ cfull, const double *__restrict__ stats, int M,
@@ -54,7 +29,7 @@ k_c3_out(const double *__restrict__ cfull, const double *__restrict__ stats, int
     if (idx >= (int64_t)side * side)
         return;
     const int w1 = (int)(idx / side) - M, w2 = (int)(idx % side) - M;
-    c3[idx] = c3_at(cfull, M, stats[3], w1, w2);
+    c3[idx] = c3_from_table(cfull, M, stats[3], w1, w2);
 }
 
 // DFT input: B[m1][m2] = (sum over lags w = m mod N of W3(w) c3(w), 0).
@@ -75,11 +50,8 @@ k_fft_input2(const double *__restrict__ cfull, const double *__restrict__ stats,
         for (int w2 = m2 - N; w2 <= m2; w2 += N) {
             if (w2 < -M || w2 > M)
                 continue;
-            const double c = c3_at(cfull, M, norm, w1, w2);
-            const double wgt = window == HOS_WIN_PARZEN
-                                   ? parzen(w1, M) * parzen(w2, M) * parzen(w1 - w2, M)
-                                   : 1.0;
-            sum += wgt * c;
+            sum += window3(w1, w2, M, window == HOS_WIN_PARZEN) *
+                   c3_from_table(cfull, M, norm, w1, w2);
         }
     }
     B[idx] = make_double2(sum, 0.0);

@@ -118,3 +118,21 @@ def workload_trispectrum(n: int = 1 << 18):
     """n=2^18 float32 cubic process, maximum lag 48, 96^3 DFT."""
     x = cubic_process(n, SEED_BASE + 3).astype(np.float32)
     return x, dict(M=48, nfft=96)
+
+
+def workload_batched(batch: int = 4096):
+    """4096 series: n uniform in [1024, 65536], M uniform over {32,64,128,256},
+    even index N(0,1), odd index Exp(1) - 1 (float64 here; cast to float32
+    for the benchmark)."""
+    return batched_series(batch, SEED_BASE + 4)
+
+
+def workload_loss(batch: int = 64, n: int = 65536):
+    """(X, target series, config): X is `batch` i.i.d. N(0,1) float32 series
+    of length n (one spawned stream each); the target spectrum comes from a
+    quadratic-process series of the same length; M = 256, 512-point DFT."""
+    ss = np.random.SeedSequence(SEED_BASE + 5)
+    X = np.stack([np.random.Generator(np.random.PCG64(c)).standard_normal(int(n))
+                  for c in ss.spawn(int(batch))]).astype(np.float32)
+    target = quadratic_process(n, SEED_BASE + 6)
+    return X, target, dict(M=256, nfft=512)

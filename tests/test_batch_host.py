@@ -1,0 +1,156 @@
+"""Host-side checks of batch plans: work items cover every (series, tile,
+chunk) once, slots are consistent, the LPT assignment is balanced, series
+offsets and DFT sizes follow the documented packing, and the batched entry
+points reject bad arguments before touching a device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1805_11775_amd as hos
+import synth
+
+
+def _fft_ok(N):
+    m = N
+    for r in (2, 3, 5):
+        while m % r == 0:
+            m //= r
+    return m == 1
+
+
+def _expected_N(M, window):
+    k = max(2, 2 * M if window == "parzen" else 2 * M + 1)
+    while not _fft_ok(k):
+        k += 1
+    return k
+
+
+CASES = [
+    ([700, 5000, 3001, 1200, 65536], [0, 5, 64, 100, 256], "split_fp16"),
+    ([2048] * 8, [64] * 8, "fp32"),
+    ([65536] * 64, [256] * 64, "split_fp16"),
+    ([1500, 1501, 97, 4096, 513], [31, 32, 33, 96, 95], "split_bf16"),
+]
+
+
+@pytest.mark.parametrize("n,M,path", CASES)
+def test_items_cover_every_chunk_once(n, M, path):
+    plan = hos.BatchPlan(n, M, path=path)
+    S = plan.series()
+    for cls in (0, 1):
+        NB = 4 if cls else 2
+        it = plan.items(cls)
+        assert len(it) == plan.info["items%d" % cls]
+        seen = {}
+        slots = set()
+        for row in it:
+            c, w, s, R, Cc, c0, c1, slot = (int(v) for v in row)
+            assert c == cls and 0 <= w < plan.info["G%d" % cls] and 0 <= c0 < c1
+            assert S[s, 7] == cls and 0 <= Cc <= R
+            assert slot not in slots
+            slots.add(slot)
+            for ch in range(c0, c1):
+                key = (s, R, Cc, ch)
+                assert key not in seen
+                seen[key] = slot
+        # every tile of every series of the class, every chunk
+        expect = 0
+        for s in range(len(n)):
+            if S[s, 7] != cls:
+                continue
+            nbr = (M[s] + 31) // 32
+            tr = (nbr + NB - 1) // NB if nbr else 0
+            expect += tr * (tr + 1) // 2 * ((n[s] + 511) // 512)
+        assert len(seen) == expect
+        if slots:
+            assert slots == set(range(len(slots)))
+
+
+@pytest.mark.parametrize("n,M,path", CASES)
+def test_lpt_balance(n, M, path):
+    """Longest-processing-time assignment: no workgroup carries more than
+    the mean load plus one item (the greedy rule's bound)."""
+    plan = hos.BatchPlan(n, M, path=path)
+    for cls in (0, 1):
+        it = plan.items(cls)
+        if len(it) == 0:
+            continue
+        cost = (it[:, 6] - it[:, 5]).astype(float)
+        if path == "fp32":
+            cost *= np.where(it[:, 3] == it[:, 4], 3.0, 4.0)
+        G = plan.info["G%d" % cls]
+        load = np.bincount(it[:, 1], weights=cost, minlength=G)
+        assert load.max() <= load.sum() / G + cost.max() + 1e-9
+        assert np.all(load > 0)
+
+
+@pytest.mark.parametrize("window", ["parzen", "none"])
+def test_series_layout(window):
+    n, M = synth.batched_series(40, 3)[1:]
+    plan = hos.BatchPlan(n, M, window=window, path="split_fp16")
+    S = plan.series()
+    assert np.array_equal(S[:, 0], n) and np.array_equal(S[:, 1], M)
+    assert np.array_equal(S[:, 4], np.concatenate([[0], np.cumsum(n)[:-1]]))
+    side2 = (2 * np.asarray(M) + 1) ** 2
+    assert np.array_equal(S[:, 5], np.concatenate([[0], np.cumsum(side2)[:-1]]))
+    for s in range(len(n)):
+        N = _expected_N(int(M[s]), window)
+        assert S[s, 2] == N and S[s, 3] == len(oracle.pd_indices(N)[0])
+    assert np.array_equal(S[:, 6], np.concatenate([[0], np.cumsum(S[:, 3])[:-1]]))
+    assert plan.info["c3_elems"] == side2.sum() and plan.info["pd_elems"] == S[:, 3].sum()
+    assert plan.info["x_elems"] == np.sum(n)
+
+
+@pytest.mark.parametrize("n,M,kw", [
+    ([100], [100], {}),                 # M >= n
+    ([1], [0], {}),                     # n < 2
+    ([5000], [2049], {}),               # M beyond the batch limit
+    ([5000], [321], {"adjoint": True}),  # beyond the adjoint's staged window
+    ([100, 200], [5], {}),              # lengths differ
+])
+def test_plan_rejects(n, M, kw):
+    with pytest.raises((hos.HosError, ValueError)):
+        hos.BatchPlan(n, M, **kw)
+
+
+def test_plan_rejects_enums():
+    lib = hos.lib()
+    n = np.array([1000], dtype=np.int64)
+    M = np.array([10], dtype=np.int32)
+    pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    args = (1, hos._i64p(n), hos._i32p(M))
+    assert lib.hos_batch_plan_size(*args, 2, 0, 0, ctypes.byref(pb), ctypes.byref(wb)) == -1
+    assert lib.hos_batch_plan_size(*args, 1, 3, 0, ctypes.byref(pb), ctypes.byref(wb)) == -1
+    assert lib.hos_batch_plan_size(*args, 1, 0, 4, ctypes.byref(pb), ctypes.byref(wb)) == -1
+    assert lib.hos_batch_plan_size(*args, 1, 0, 0, ctypes.byref(pb), ctypes.byref(wb)) == 0
+
+
+FAKE = 0x10000
+
+
+def test_batched_entry_points_validate_before_device():
+    lib = hos.lib()
+    plan = hos.BatchPlan([3000, 2000], [20, 20], adjoint=True)
+    ph = plan.host.ctypes.data
+    wsb = plan.info["ws_bytes"]
+    f = lib.hos_bispectrum_batched
+    assert f(FAKE, 0, ph, FAKE, FAKE, FAKE, FAKE, wsb - 1, None) == hos.HOS_EWORKSPACE
+    assert f(None, 0, ph, FAKE, FAKE, FAKE, FAKE, wsb, None) == hos.HOS_EINVAL
+    assert f(FAKE, 0, ph, FAKE, None, None, FAKE, wsb, None) == hos.HOS_EINVAL
+    assert f(FAKE, 0, ph, FAKE + 8, FAKE, FAKE, FAKE, wsb, None) == hos.HOS_EINVAL
+    assert f(FAKE, 0, ph, FAKE, FAKE, FAKE + 8, FAKE, wsb, None) == hos.HOS_EINVAL
+    bad = plan.host.copy()
+    bad[0] = 0   # not a plan
+    assert f(FAKE, 0, bad.ctypes.data, FAKE, FAKE, FAKE, FAKE, wsb, None) == hos.HOS_EINVAL
+    g = lib.hos_bispectrum_loss_fwd
+    assert g(FAKE, 0, ph, FAKE, None, FAKE, FAKE, FAKE, wsb, None) == hos.HOS_EINVAL
+    mixed = hos.BatchPlan([3000, 2000], [20, 21])
+    assert g(FAKE, 0, mixed.host.ctypes.data, FAKE, FAKE, FAKE, FAKE, FAKE,
+             mixed.info["ws_bytes"], None) == hos.HOS_EINVAL   # one target needs one M
+    b = lib.hos_bispectrum_loss_bwd
+    fwd_only = hos.BatchPlan([3000, 2000], [20, 20])
+    assert b(FAKE, 0, fwd_only.host.ctypes.data, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+             fwd_only.info["ws_bytes"], None) == hos.HOS_EINVAL  # no adjoint buffers
+    assert b(FAKE, 0, ph, FAKE, FAKE, FAKE, FAKE, FAKE + 2, FAKE, wsb, None) == hos.HOS_EINVAL

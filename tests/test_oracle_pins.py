@@ -401,3 +401,13 @@ def test_loss_gradient_shift_invariance():
     assert abs(oracle.bispectrum_loss(np.stack([x, y]), 12, 24, target) -
                oracle.bispectrum_loss(x, 12, 24, target) -
                oracle.bispectrum_loss(y, 12, 24, target)) < 1e-12
+
+
+def test_loss_gradient_at_indices_agrees_with_full():
+    """The sampled form returns the full gradient's entries before the mean
+    term: differences between indices agree exactly."""
+    x, target = _loss_case(120, 8, 16, 9)
+    g = oracle.bispectrum_loss_grad(x, 8, 16, target)
+    idx = np.array([0, 5, 60, 119])
+    ga = oracle.loss_grad_at(x, 8, 16, target, idx)
+    assert np.allclose(ga - ga[0], g[idx] - g[idx[0]], rtol=0, atol=1e-13 * np.max(np.abs(g)))
