@@ -188,6 +188,114 @@ def bench_trispectrum(hos, torch, oracle, synth, paths, steps, warmup, cpu_secon
     return rec
 
 
+def _time(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_batched(hos, torch, oracle, synth, paths, steps, warmup):
+    """4096 float32 series of uneven length and lag in one batched call
+    (principal-domain spectra only); metric sum_s n_s (2 M_s + 1)^2 / t."""
+    xs, n, M = synth.workload_batched()
+    x = torch.from_numpy(np.concatenate(xs).astype(np.float32)).cuda()
+    lagsums = float(np.sum(n * (2 * M + 1.0) ** 2))
+    flops = float(np.sum(2.0 * n * (M + 1.0) * (M + 2.0) / 2))
+    out = {}
+    for path in paths:
+        print("bench: batched path %s" % path, file=sys.stderr, flush=True)
+        plan = hos.BatchPlan(n, M, path=path)
+        plan.to(x.device)
+        ms = _time(torch, lambda: hos.bispectrum_batched(x, plan, return_c3=False),
+                   max(2, steps // 10), max(1, warmup // 10))
+        _, B = hos.bispectrum_batched(x, plan, return_c3=False)
+        S = plan.series()
+        s = int(np.argmin(n))
+        N, npd, pdo = int(S[s, 2]), int(S[s, 3]), int(S[s, 6])
+        _, Bref = oracle.bispectrum(xs[s].astype(np.float32), int(M[s]), N)
+        k1, k2 = oracle.pd_indices(N)
+        err = float(np.max(np.abs(B[pdo:pdo + npd].cpu().numpy() - Bref[k1, k2])) /
+                    np.max(np.abs(Bref[k1, k2])))
+        out[path] = {"ms_per_call": ms, "value": lagsums / (ms * 1e-3),
+                     "tflops_whole_call": flops / (ms * 1e-3) / 1e12,
+                     "frac_whole_call": flops / (ms * 1e-3) / PEAK[path],
+                     "rel_err_B_pd_shortest_series": err, "within_tol": err <= TOL[path],
+                     "work_items": [plan.info["items0"], plan.info["items1"]],
+                     "workgroups": [plan.info["G0"], plan.info["G1"]],
+                     "ws_bytes": plan.info["ws_bytes"]}
+        print("bench: batched %s %.3f ms/call, err %.2e" % (path, ms, err), file=sys.stderr,
+              flush=True)
+        del plan
+    head = "split_fp16" if "split_fp16" in out else next(iter(out))
+    return {"metric": "cumulant lag-sums/s (sum_s n_s (2M_s+1)^2 / s)",
+            "value": out[head]["value"], "unit": "lag-sums/s",
+            "ms_per_step": out[head]["ms_per_call"], "dtype": DTYPE[head],
+            "config": {"workload": "4096 float32 series, n uniform in [1024, 65536], M uniform "
+                                   "in {32, 64, 128, 256}, even index N(0,1), odd index "
+                                   "Exp(1)-1; Parzen window, N = 2M; principal-domain spectra",
+                       "series": len(n), "samples": int(np.sum(n)), "path": head},
+            "paths": out}
+
+
+def bench_loss(hos, torch, oracle, synth, paths, steps, warmup):
+    """Loss forward and hand-written backward over 64 float32 N(0,1) series,
+    n = 65536, M = 256, N = 512."""
+    X, tgt, cfg = synth.workload_loss()
+    M, N = cfg["M"], cfg["nfft"]
+    B_, n_ = X.shape
+    x = torch.from_numpy(X).cuda()
+    _, target = hos.bispectrum_batched(torch.from_numpy(tgt.astype(np.float32)).cuda(),
+                                       hos.BatchPlan([tgt.size], [M], path="fp32"),
+                                       return_c3=False)
+    lagsums = float(B_ * n_ * (2 * M + 1) ** 2)
+    hexagon = 3 * M * M + 3 * M + 1
+    fwd_flops = B_ * 2.0 * n_ * (M + 1) * (M + 2) / 2
+    bwd_flops = B_ * 2.0 * n_ * hexagon   # the quadratic form over the hexagon per sample
+    dL = torch.ones((), dtype=torch.float64, device="cuda")
+    out = {}
+    for path in paths:
+        print("bench: loss path %s" % path, file=sys.stderr, flush=True)
+        plan = hos.BatchPlan([n_] * B_, [M] * B_, path=path, adjoint=True)
+        plan.to(x.device)
+        loss, Bpd = hos.bispectrum_loss_fwd(x, target, plan)
+        t_f = _time(torch, lambda: hos.bispectrum_loss_fwd(x, target, plan),
+                    max(2, steps // 5), max(1, warmup // 5))
+        t_b = _time(torch, lambda: hos.bispectrum_loss_bwd(x, target, Bpd, dL, plan),
+                    max(2, steps // 5), max(1, warmup // 5))
+        b = 37
+        Bref = oracle.bispectrum_pd(X[b], M, N)
+        npd = Bpd.numel() // B_
+        err = float(np.max(np.abs(Bpd[b * npd:(b + 1) * npd].cpu().numpy() - Bref)) /
+                    np.max(np.abs(Bref)))
+        out[path] = {"fwd_ms": t_f, "bwd_ms": t_b, "fwd_value": lagsums / (t_f * 1e-3),
+                     "fwd_tflops": fwd_flops / (t_f * 1e-3) / 1e12,
+                     "bwd_tflops": bwd_flops / (t_b * 1e-3) / 1e12,
+                     "bwd_frac": bwd_flops / (t_b * 1e-3) / PEAK[path],
+                     "loss": float(loss), "rel_err_B_pd_series37": err,
+                     "within_tol": err <= TOL[path]}
+        print("bench: loss %s fwd %.3f ms bwd %.3f ms err %.2e" % (path, t_f, t_b, err),
+              file=sys.stderr, flush=True)
+        del plan
+    head = "split_fp16" if "split_fp16" in out else next(iter(out))
+    return {"metric": "forward lag-sums/s; backward ms", "value": out[head]["fwd_value"],
+            "unit": "lag-sums/s", "dtype": DTYPE[head],
+            "config": {"workload": "bispectrum-matching loss, 64 float32 N(0,1) series, "
+                                   "n=65536, M=256, N=512, target from a quadratic-process "
+                                   "series; forward + hand-written adjoint",
+                       "batch": B_, "n": n_, "M": M, "nfft": N, "path": head},
+            "bwd_flops_definition": "2 n (3M^2+3M+1) per series: the quadratic form of the "
+                                    "(2M+1)-sample window over the hexagon",
+            "paths": out}
+
+
 def traffic_record(_unused=None):
     """HBM bytes per launch of the c3 contraction from the committed PMC
     summary, if it was taken on the current kernel source."""
@@ -237,6 +345,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tri", action="store_true", help="skip the trispectrum record")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched and loss records")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (the "
                          "reference kernel for scaling HBM counters)")
@@ -310,6 +419,11 @@ def main():
                      "flops_per_launch": flops, "avg_launch_ms": hp["stage_ms"]["contract"]},
         "paths": paths,
     }
+    if not args.no_batch:
+        rec["batched"] = bench_batched(hos, torch, oracle, synth, list(paths), args.steps,
+                                       args.warmup)
+        rec["loss"] = bench_loss(hos, torch, oracle, synth, list(paths), args.steps,
+                                 args.warmup)
     if not args.no_tri:
         rec["trispectrum"] = bench_trispectrum(
             hos, torch, oracle, synth, list(paths), args.steps, args.warmup,
