@@ -175,11 +175,20 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         gr.grid_off = (int64_t)o;
         o = a256(o + (size_t)gr.count * gr.N * gr.N * 16);
     }
+    std::vector<int32_t> gseries;
     {
         std::vector<int> fill(groups.size(), 0);
         for (auto &d : sd) {
             FftGroup &gr = groups[d.group];
             d.grid_off = gr.grid_off + (int64_t)fill[d.group]++ * gr.N * gr.N * 16;
+        }
+        int64_t first = 0;
+        for (size_t g = 0; g < groups.size(); ++g) {
+            groups[g].first = first;
+            for (int s = 0; s < batch; ++s)
+                if (sd[s].group == (int)g)
+                    gseries.push_back(s);
+            first += groups[g].count;
         }
     }
     h.loss_off = (int64_t)o;
@@ -283,6 +292,8 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
     h.groups_off = (int64_t)b;
     h.n_groups = (int64_t)groups.size();
     b += sizeof(FftGroup) * groups.size();
+    h.gseries_off = (int64_t)b;
+    b += up(sizeof(int32_t) * batch, 8);
     h.blob_bytes = (int64_t)up(b, 256);
 
     if (hdr_out)
@@ -305,6 +316,7 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
             memcpy(p + h.tiles_off[cls], tiles[cls].data(), sizeof(C3TileRef) * tiles[cls].size());
     }
     memcpy(p + h.groups_off, groups.data(), sizeof(FftGroup) * groups.size());
+    memcpy(p + h.gseries_off, gseries.data(), sizeof(int32_t) * batch);
     return HOS_OK;
 }
 

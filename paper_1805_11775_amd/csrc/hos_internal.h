@@ -227,6 +227,7 @@ struct FftGroup {         // series sharing one DFT size, grids contiguous
     int32_t N, count;
     int64_t grid_off;     // byte offset of the first grid
     int64_t twid_off;     // byte offset of the N twiddles
+    int64_t first;        // its series: gseries[first .. first + count)
 };
 
 constexpr int64_t BATCH_MAGIC = 0x484f53424154434bLL;   // "HOSBATCK"
@@ -245,6 +246,7 @@ struct BatchHeader {
     int64_t tiles_off[BATCH_CLASSES], n_tiles[BATCH_CLASSES];
     int64_t part_off[BATCH_CLASSES];  // byte offsets of the partial arenas in the workspace
     int64_t groups_off, n_groups;
+    int64_t gseries_off;            // int32 series indices ordered by DFT group
     int64_t loss_off;               // byte offset of the per-series loss partials
 };
 
@@ -276,6 +278,8 @@ hipError_t launch_fft2(double *B, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_fft3(double *T, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s);
 hipError_t launch_fft2_batch(double *grids, int N, int count, const double2 *tw, hipStream_t s);
+hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window, char *ws,
+                             double *B_pd, hipStream_t s);
 
 // Batched launchers: `hdr` is the host copy of the plan, `dplan` its device
 // copy, `ws` the workspace base.

@@ -10,6 +10,7 @@
 // sorted position -- and stores the sequences back.  Twiddles come from a
 // table of the N roots of unity built once per call with sincospi in FP64.
 #include "hos_internal.h"
+#include "hos_device.h"
 
 namespace hos {
 
@@ -251,6 +252,155 @@ hipError_t launch_fft2_batch(double *grids, int N, int count, const double2 *tw,
     const int64_t rows = (int64_t)count * N;
     fft_axis(d, tw, fr, rows, 1, 1, 0, N, s);                    // along k2, every grid
     fft_axis(d, tw, fr, rows, N, N, 1, (int64_t)N * N, s);       // along k1
+    return hipGetLastError();
+}
+
+}  // namespace hos
+
+// ------------------------------------------------------------------------
+// Principal-domain spectra of a batch.  Only 0 <= k2 <= k1, k1 + k2 < N/2
+// is returned, so k2 <= N/4 and k1 < N/2: the 2-D DFT runs as row
+// transforms (along m2) that keep the K2 = N/4 + 1 lowest k2, then column
+// transforms of those K2 columns that keep the principal-domain k1.  The
+// windowed, folded cumulant is formed directly in LDS by the row pass, so
+// no N x N grid is written.
+// ------------------------------------------------------------------------
+namespace hos {
+
+namespace {
+
+__device__ inline int pd_len(int k1, int H) { return k1 <= H ? min(k1, H - k1) + 1 : 0; }
+
+// Rows: blockIdx.y = series of group g, blockIdx.x = block of CB rows m1.
+// T1[m1][k2] (k2 < K2) goes to the series' grid region.
+__global__ void __launch_bounds__(FFT_THREADS)
+k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, int first,
+          char *__restrict__ ws, const double2 *__restrict__ tw, FftRadices fr, int CB,
+          int window)
+{
+    __shared__ double2 sm[FFT_LDS_ELEMS];
+    __shared__ double dwin[FFT_LDS_ELEMS / 2 + 1];   // d(m), m = 0..M (M < N/2 + 1)
+    const SeriesDesc &d = sd[gser[first + blockIdx.y]];
+    const int N = fr.n, M = d.M, K2 = N / 4 + 1;
+    const char *r = ws + d.ws_off;
+    const double *cfull = (const double *)(r + d.o_cfull);
+    const double norm = ((const double *)(r + d.o_stats))[3];
+    const bool pz = window == HOS_WIN_PARZEN;
+    for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
+        dwin[m] = pz ? parzen_d(m, M) : 1.0;
+    __syncthreads();
+    const int m1_0 = blockIdx.x * CB;
+    for (int e = threadIdx.x; e < CB * N; e += FFT_THREADS) {
+        const int cb = e / N, m2 = e - cb * N, m1 = m1_0 + cb;
+        double sum = 0.0;
+        if (m1 < N) {
+            for (int w1 = m1 - N; w1 <= m1; w1 += N) {
+                if (w1 < -M || w1 > M)
+                    continue;
+                for (int w2 = m2 - N; w2 <= m2; w2 += N) {
+                    const int dw = w1 - w2;
+                    if (w2 < -M || w2 > M || dw < -M || dw > M)
+                        continue;   // outside the hexagon c3 is 0
+                    sum += dwin[abs(w1)] * dwin[abs(w2)] * dwin[abs(dw)] *
+                           c3_from_table(cfull, M, norm, w1, w2);
+                }
+            }
+        }
+        sm[e] = make_double2(sum, 0.0);
+    }
+    __syncthreads();
+    int Ns = 1;
+    for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
+        const int R = fr.r[st];
+        if (R == 4)
+            stockham_stage<4>(sm, tw, N, Ns, CB);
+        else if (R == 2)
+            stockham_stage<2>(sm, tw, N, Ns, CB);
+        else if (R == 3)
+            stockham_stage<3>(sm, tw, N, Ns, CB);
+        else
+            stockham_stage<5>(sm, tw, N, Ns, CB);
+        Ns *= R;
+    }
+    double2 *T1 = (double2 *)(ws + d.grid_off);
+    for (int e = threadIdx.x; e < CB * K2; e += FFT_THREADS) {
+        const int cb = e / K2, k2 = e - cb * K2, m1 = m1_0 + cb;
+        if (m1 < N)
+            T1[(int64_t)m1 * K2 + k2] = sm[cb * N + k2];
+    }
+}
+
+// Columns: blockIdx.x = block of CB columns k2 < K2; transforms along m1 and
+// writes the principal-domain points of those columns.
+__global__ void __launch_bounds__(FFT_THREADS)
+k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, int first,
+          const char *__restrict__ ws, const double2 *__restrict__ tw, FftRadices fr, int CB,
+          double2 *__restrict__ B_pd)
+{
+    __shared__ double2 sm[FFT_LDS_ELEMS];
+    __shared__ int rowstart[FFT_LDS_ELEMS / 2 + 1];
+    const SeriesDesc &d = sd[gser[first + blockIdx.y]];
+    const int N = fr.n, K2 = N / 4 + 1, H = (N - 1) / 2;
+    const int k2_0 = blockIdx.x * CB;
+    const double2 *T1 = (const double2 *)(ws + d.grid_off);
+    for (int e = threadIdx.x; e < CB * N; e += FFT_THREADS) {
+        const int m1 = e / CB, cb = e - m1 * CB, k2 = k2_0 + cb;
+        sm[cb * N + m1] = k2 < K2 ? T1[(int64_t)m1 * K2 + k2] : make_double2(0.0, 0.0);
+    }
+    if (threadIdx.x == 0) {
+        int p = 0;
+        for (int a = 0; a <= H && a < N / 2 + 1; ++a) {
+            rowstart[a] = p;
+            p += pd_len(a, H);
+        }
+    }
+    __syncthreads();
+    int Ns = 1;
+    for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
+        const int R = fr.r[st];
+        if (R == 4)
+            stockham_stage<4>(sm, tw, N, Ns, CB);
+        else if (R == 2)
+            stockham_stage<2>(sm, tw, N, Ns, CB);
+        else if (R == 3)
+            stockham_stage<3>(sm, tw, N, Ns, CB);
+        else
+            stockham_stage<5>(sm, tw, N, Ns, CB);
+        Ns *= R;
+    }
+    const int half = H + 1;   // k1 <= H
+    for (int e = threadIdx.x; e < CB * half; e += FFT_THREADS) {
+        const int cb = e / half, k1 = e - cb * half, k2 = k2_0 + cb;
+        if (k2 < K2 && k2 <= k1 && k1 + k2 <= H)
+            B_pd[d.pd_off + rowstart[k1] + k2] = sm[cb * N + k1];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window, char *ws,
+                             double *B_pd, hipStream_t s)
+{
+    const SeriesDesc *sd = (const SeriesDesc *)(dplan + h.series_off);
+    const int32_t *gser = (const int32_t *)(dplan + h.gseries_off);
+    const FftGroup *groups = (const FftGroup *)((const char *)&h + h.groups_off);
+    for (int g = 0; g < (int)h.n_groups; ++g) {
+        const FftGroup &gr = groups[g];
+        const int N = gr.N;
+        double2 *tw = (double2 *)(ws + gr.twid_off);
+        hipError_t e = launch_twiddles(tw, N, s);
+        if (e != hipSuccess)
+            return e;
+        const FftRadices fr = factor(N);
+        int CB = FFT_LDS_ELEMS / N;
+        if (CB > 32)
+            CB = 32;
+        const int K2 = N / 4 + 1;
+        k_pd_rows<<<dim3((N + CB - 1) / CB, gr.count), FFT_THREADS, 0, s>>>(
+            sd, gser, (int)gr.first, ws, tw, fr, CB, window);
+        k_pd_cols<<<dim3((K2 + CB - 1) / CB, gr.count), FFT_THREADS, 0, s>>>(
+            sd, gser, (int)gr.first, ws, tw, fr, CB, (double2 *)B_pd);
+    }
     return hipGetLastError();
 }
 

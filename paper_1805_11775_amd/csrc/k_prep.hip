@@ -126,21 +126,6 @@ __device__ inline float centred(const T *__restrict__ x, int64_t n, int64_t o, d
                              : 0.0f;
 }
 
-// Table entry o (o < 0 is left padding): xf[o] and win4[o].
-template <typename T>
-__device__ inline void prep_f32_body(const T *__restrict__ x, int64_t n, int64_t o,
-                                     const double *__restrict__ stats, float *__restrict__ xf,
-                                     float4 *__restrict__ win4)
-{
-    const double mu = stats[0], s = stats[1];
-    float v[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-        v[e] = centred(x, n, o + e, mu, s);
-    xf[o] = v[0];
-    win4[o] = make_float4(v[0], v[1], v[2], v[3]);
-}
-
 __device__ inline void split16(float v, uint16_t &h, uint16_t &l)
 {
     _Float16 hh = (_Float16)v;
@@ -157,55 +142,56 @@ __device__ inline void splitbf(float v, uint16_t &h, uint16_t &l)
     l = __builtin_bit_cast(uint16_t, ll);
 }
 
-// Table entry o: win8h[o], win8l[o] (8 halves each).
-template <typename T, bool BF16>
-__device__ inline void prep_split_body(const T *__restrict__ x, int64_t n, int64_t o,
-                                       const double *__restrict__ stats,
-                                       uint4 *__restrict__ win8h, uint4 *__restrict__ win8l)
+// Table entries [o0, o0 + 256) of one workgroup (entries past oend are not
+// written): the 263 samples they touch are rounded once into LDS, then every
+// table is written from there.  MODE 0: xf and win4; 1/2: also the FP16/BF16
+// hi|lo window tables.
+template <typename T, int MODE>
+__device__ inline void prep_block(const T *__restrict__ x, int64_t n, int64_t o0, int64_t oend,
+                                  const double *__restrict__ stats, float *__restrict__ xf,
+                                  float4 *__restrict__ win4, uint4 *__restrict__ win8h,
+                                  uint4 *__restrict__ win8l)
 {
+    __shared__ float sv[256 + 8];
     const double mu = stats[0], s = stats[1];
-    uint32_t hw[4], lw[4];
+    const int t = threadIdx.x;
+    sv[t] = centred(x, n, o0 + t, mu, s);
+    if (t < 8)
+        sv[256 + t] = centred(x, n, o0 + 256 + t, mu, s);
+    __syncthreads();
+    const int64_t o = o0 + t;
+    if (o >= oend)
+        return;
+    xf[o] = sv[t];
+    win4[o] = make_float4(sv[t], sv[t + 1], sv[t + 2], sv[t + 3]);
+    if constexpr (MODE != 0) {
+        uint32_t hw[4], lw[4];
 #pragma unroll
-    for (int e = 0; e < 8; e += 2) {
-        uint16_t h0, l0, h1, l1;
-        float v0 = centred(x, n, o + e, mu, s), v1 = centred(x, n, o + e + 1, mu, s);
-        if (BF16) {
-            splitbf(v0, h0, l0);
-            splitbf(v1, h1, l1);
-        } else {
-            split16(v0, h0, l0);
-            split16(v1, h1, l1);
+        for (int e = 0; e < 8; e += 2) {
+            uint16_t h0, l0, h1, l1;
+            if (MODE == 2) {
+                splitbf(sv[t + e], h0, l0);
+                splitbf(sv[t + e + 1], h1, l1);
+            } else {
+                split16(sv[t + e], h0, l0);
+                split16(sv[t + e + 1], h1, l1);
+            }
+            hw[e / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+            lw[e / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
         }
-        hw[e / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-        lw[e / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+        win8h[o] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        win8l[o] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
     }
-    win8h[o] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-    win8l[o] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
 }
 
-// One thread per table entry o of [0, npad).
-template <typename T>
-__global__ void __launch_bounds__(256) k_prep_f32(const T *__restrict__ x, int64_t n,
-                                                  int64_t npad,
-                                                  const double *__restrict__ stats,
-                                                  float *__restrict__ xf,
-                                                  float4 *__restrict__ win4)
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_prep(const T *__restrict__ x, int64_t n, int64_t npad,
+                                              const double *__restrict__ stats,
+                                              float *__restrict__ xf, float4 *__restrict__ win4,
+                                              uint4 *__restrict__ win8h,
+                                              uint4 *__restrict__ win8l)
 {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o < npad)
-        prep_f32_body(x, n, o, stats, xf, win4);
-}
-
-template <typename T, bool BF16>
-__global__ void __launch_bounds__(256) k_prep_split(const T *__restrict__ x, int64_t n,
-                                                    int64_t npad,
-                                                    const double *__restrict__ stats,
-                                                    uint4 *__restrict__ win8h,
-                                                    uint4 *__restrict__ win8l)
-{
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o < npad)
-        prep_split_body<T, BF16>(x, n, o, stats, win8h, win8l);
+    prep_block<T, MODE>(x, n, (int64_t)blockIdx.x * 256, npad, stats, xf, win4, win8h, win8l);
 }
 
 // ------------------------------------------------------------------ batches
@@ -231,23 +217,19 @@ __global__ void __launch_bounds__(256) k_bmoments_final(const SeriesDesc *__rest
                        (double *)(r + d.o_stats));
 }
 
-template <typename T, int PATH>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_bprep(const T *__restrict__ x,
                                                const SeriesDesc *__restrict__ sd,
                                                char *__restrict__ ws)
 {
     const SeriesDesc &d = sd[blockIdx.y];
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - d.lpad;
-    if (o >= d.npad)
+    const int64_t o0 = (int64_t)blockIdx.x * 256 - d.lpad;
+    if (o0 >= d.npad)
         return;
     char *r = ws + d.ws_off;
-    const T *xs = x + d.x_off;
-    const double *stats = (const double *)(r + d.o_stats);
-    prep_f32_body(xs, d.n, o, stats, (float *)(r + d.o_xf), (float4 *)(r + d.o_win4));
-    if constexpr (PATH != HOS_PATH_FP32)
-        prep_split_body<T, PATH == HOS_PATH_SPLIT_BF16>(xs, d.n, o, stats,
-                                                       (uint4 *)(r + d.o_win8h),
-                                                       (uint4 *)(r + d.o_win8l));
+    prep_block<T, MODE>(x + d.x_off, d.n, o0, d.npad, (const double *)(r + d.o_stats),
+                        (float *)(r + d.o_xf), (float4 *)(r + d.o_win4),
+                        (uint4 *)(r + d.o_win8h), (uint4 *)(r + d.o_win8l));
 }
 
 template <typename T>
@@ -259,11 +241,11 @@ void launch_bprep_t(const T *x, const BatchHeader &h, const SeriesDesc *sd, char
     k_bmoments_final<<<B, 256, 0, s>>>(sd, ws, (int)h.momb, (uint32_t)h.flags, 7);
     const dim3 grid((unsigned)((h.max_lpad + h.max_npad + 255) / 256), B);
     if (h.path == HOS_PATH_FP32)
-        k_bprep<T, HOS_PATH_FP32><<<grid, 256, 0, s>>>(x, sd, ws);
+        k_bprep<T, 0><<<grid, 256, 0, s>>>(x, sd, ws);
     else if (h.path == HOS_PATH_SPLIT_FP16)
-        k_bprep<T, HOS_PATH_SPLIT_FP16><<<grid, 256, 0, s>>>(x, sd, ws);
+        k_bprep<T, 1><<<grid, 256, 0, s>>>(x, sd, ws);
     else
-        k_bprep<T, HOS_PATH_SPLIT_BF16><<<grid, 256, 0, s>>>(x, sd, ws);
+        k_bprep<T, 2><<<grid, 256, 0, s>>>(x, sd, ws);
 }
 
 }  // namespace
@@ -281,31 +263,28 @@ hipError_t launch_moments(const void *x, int dtype, int64_t n, uint32_t flags,
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const void *x, int dtype, const SeriesPlan &p, char *ws, hipStream_t s)
+template <typename T>
+void launch_prep_t(const T *x, const SeriesPlan &p, char *ws, hipStream_t s)
 {
     const double *stats = (const double *)(ws + p.off_stats);
     float *xf = (float *)(ws + p.off_xf);
     float4 *win4 = (float4 *)(ws + p.off_win4);
+    uint4 *h = (uint4 *)(ws + p.off_win8h), *l = (uint4 *)(ws + p.off_win8l);
     const int64_t blocks = (p.npad + 255) / 256;
-    if (dtype == HOS_F64)
-        k_prep_f32<double><<<blocks, 256, 0, s>>>((const double *)x, p.n, p.npad, stats, xf, win4);
+    if (p.path == HOS_PATH_FP32)
+        k_prep<T, 0><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l);
+    else if (p.path == HOS_PATH_SPLIT_FP16)
+        k_prep<T, 1><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l);
     else
-        k_prep_f32<float><<<blocks, 256, 0, s>>>((const float *)x, p.n, p.npad, stats, xf, win4);
-    if (p.path != HOS_PATH_FP32) {
-        uint4 *h = (uint4 *)(ws + p.off_win8h), *l = (uint4 *)(ws + p.off_win8l);
-        const bool bf = p.path == HOS_PATH_SPLIT_BF16;
-        if (dtype == HOS_F64) {
-            if (bf)
-                k_prep_split<double, true><<<blocks, 256, 0, s>>>((const double *)x, p.n, p.npad, stats, h, l);
-            else
-                k_prep_split<double, false><<<blocks, 256, 0, s>>>((const double *)x, p.n, p.npad, stats, h, l);
-        } else {
-            if (bf)
-                k_prep_split<float, true><<<blocks, 256, 0, s>>>((const float *)x, p.n, p.npad, stats, h, l);
-            else
-                k_prep_split<float, false><<<blocks, 256, 0, s>>>((const float *)x, p.n, p.npad, stats, h, l);
-        }
-    }
+        k_prep<T, 2><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l);
+}
+
+hipError_t launch_prep(const void *x, int dtype, const SeriesPlan &p, char *ws, hipStream_t s)
+{
+    if (dtype == HOS_F64)
+        launch_prep_t<double>((const double *)x, p, ws, s);
+    else
+        launch_prep_t<float>((const float *)x, p, ws, s);
     return hipGetLastError();
 }
 
