@@ -209,13 +209,17 @@ def bench_batched(hos, torch, oracle, synth, paths, steps, warmup):
     x = torch.from_numpy(np.concatenate(xs).astype(np.float32)).cuda()
     lagsums = float(np.sum(n * (2 * M + 1.0) ** 2))
     flops = float(np.sum(2.0 * n * (M + 1.0) * (M + 2.0) / 2))
+    from paper_1805_11775_amd import tune as hos_tune
     out = {}
     for path in paths:
-        print("bench: batched path %s" % path, file=sys.stderr, flush=True)
-        plan = hos.BatchPlan(n, M, path=path)
+        print("bench: batched path %s (tuning tiles)" % path, file=sys.stderr, flush=True)
+        tuned = hos_tune.tune(sorted(set(int(m) for m in M)), path=path, series=32, reps=3)
+        plan = hos.BatchPlan(n, M, path=path, tile=tuned["choices"])
         plan.to(x.device)
         ms = _time(torch, lambda: hos.bispectrum_batched(x, plan, return_c3=False),
                    max(2, steps // 10), max(1, warmup // 10))
+        stages = [hos.bispectrum_batched_timed(x, plan)[2] for _ in range(3)]
+        stage_ms = {k: float(np.mean([d[k] for d in stages])) for k in stages[0]}
         _, B = hos.bispectrum_batched(x, plan, return_c3=False)
         S = plan.series()
         s = int(np.argmin(n))
@@ -226,8 +230,13 @@ def bench_batched(hos, torch, oracle, synth, paths, steps, warmup):
                     np.max(np.abs(Bref[k1, k2])))
         out[path] = {"ms_per_call": ms, "value": lagsums / (ms * 1e-3),
                      "tflops_whole_call": flops / (ms * 1e-3) / 1e12,
+                     "stage_ms": stage_ms,
+                     "contract_tflops": flops / (stage_ms["contract"] * 1e-3) / 1e12,
+                     "contract_frac": flops / (stage_ms["contract"] * 1e-3) / PEAK[path],
                      "frac_whole_call": flops / (ms * 1e-3) / PEAK[path],
                      "rel_err_B_pd_shortest_series": err, "within_tol": err <= TOL[path],
+                     "tile_choices": {str(k): v for k, v in tuned["choices"].items()},
+                     "tune_ms": {str(k): v for k, v in tuned["ms"].items()},
                      "work_items": [plan.info["items0"], plan.info["items1"]],
                      "workgroups": [plan.info["G0"], plan.info["G1"]],
                      "ws_bytes": plan.info["ws_bytes"]}
@@ -240,7 +249,8 @@ def bench_batched(hos, torch, oracle, synth, paths, steps, warmup):
             "ms_per_step": out[head]["ms_per_call"], "dtype": DTYPE[head],
             "config": {"workload": "4096 float32 series, n uniform in [1024, 65536], M uniform "
                                    "in {32, 64, 128, 256}, even index N(0,1), odd index "
-                                   "Exp(1)-1; Parzen window, N = 2M; principal-domain spectra",
+                                   "Exp(1)-1; Parzen window, N = 2M; principal-domain spectra; "
+                                   "tiles from the autotuner",
                        "series": len(n), "samples": int(np.sum(n)), "path": head},
             "paths": out}
 

@@ -248,14 +248,20 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
 /* Plan and workspace sizes for a batch.  n, M: host arrays of `batch`
  * entries (n >= 2, 0 <= M < n, M <= 2048; M <= 320 with HOS_PLAN_ADJOINT).
  * window: hos_window.  flags: HOS_NO_CENTER, HOS_PLAN_ADJOINT (lay out the
- * buffers hos_bispectrum_loss_bwd needs).  Host only. */
+ * buffers hos_bispectrum_loss_bwd needs).  tile_nb: NULL, or a host array
+ * of `batch` tile choices for the contraction, 0 = built-in rule, 2 = tiles
+ * of 2 x 2 matrix-core blocks (split paths only), 4 = 4 x 4 blocks; this is
+ * what the package's tuner (paper_1805_11775_amd.tune) chooses per lag.
+ * Host only. */
 int hos_batch_plan_size(int32_t batch, const int64_t *n, const int32_t *M, int32_t window,
-                        int32_t path, uint32_t flags, size_t *plan_bytes, size_t *ws_bytes);
+                        int32_t path, uint32_t flags, const int32_t *tile_nb,
+                        size_t *plan_bytes, size_t *ws_bytes);
 
 /* Writes the plan into host memory `plan` (8-byte aligned, plan_bytes from
- * hos_batch_plan_size).  Host only. */
+ * hos_batch_plan_size with the same arguments).  Host only. */
 int hos_batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window,
-                   int32_t path, uint32_t flags, void *plan, size_t plan_bytes);
+                   int32_t path, uint32_t flags, const int32_t *tile_nb, void *plan,
+                   size_t plan_bytes);
 
 /* Host-only queries of a plan (host copy).  hos_batch_plan_info: info[0..11]
  * = batch, c3 elements, principal-domain points, input samples, workspace
@@ -282,6 +288,17 @@ int hos_batch_items(const void *plan, int32_t cls, int64_t *out, int64_t cap);
 int hos_bispectrum_batched(const void *x, int32_t dtype, const void *plan_host,
                            const void *plan_dev, double *c3, double *B_pd, void *ws,
                            size_t ws_bytes, hipStream_t stream);
+
+/*
+ * hos_bispectrum_batched with per-stage timing (HIP events on `stream`);
+ * WAITS for the stream and writes 5 floats of milliseconds to stage_ms
+ * (host): [0] mean/range and operand tables, [1] contraction, [2] partial
+ * and diagonal sums, [3] c3 output and spectra, [4] total.  Used by the
+ * tile tuner to time the contraction on its own.
+ */
+int hos_bispectrum_batched_timed(const void *x, int32_t dtype, const void *plan_host,
+                                 const void *plan_dev, double *c3, double *B_pd, void *ws,
+                                 size_t ws_bytes, hipStream_t stream, float *stage_ms);
 
 /*
  * Bispectrum-matching loss over a batch whose series share one M:

@@ -82,14 +82,16 @@ def _load_lib():
                                                  ctypes.POINTER(ctypes.c_float)]),
         "hos_c4_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
         "hos_batch_plan_size": (ctypes.c_int, [i32, p64, ctypes.POINTER(ctypes.c_int32), i32,
-                                               i32, u32, ctypes.POINTER(sz),
-                                               ctypes.POINTER(sz)]),
+                                               i32, u32, ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(sz), ctypes.POINTER(sz)]),
         "hos_batch_plan": (ctypes.c_int, [i32, p64, ctypes.POINTER(ctypes.c_int32), i32, i32,
-                                          u32, vp, sz]),
+                                          u32, ctypes.POINTER(ctypes.c_int32), vp, sz]),
         "hos_batch_plan_info": (ctypes.c_int, [vp, p64, i32]),
         "hos_batch_series": (ctypes.c_int, [vp, p64, i64]),
         "hos_batch_items": (ctypes.c_int, [vp, i32, p64, i64]),
         "hos_bispectrum_batched": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
+        "hos_bispectrum_batched_timed": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, sz, vp,
+                                                        ctypes.POINTER(ctypes.c_float)]),
         "hos_bispectrum_loss_fwd": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
         "hos_bispectrum_loss_bwd": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz,
                                                    vp]),
@@ -333,7 +335,10 @@ class BatchPlan:
     lengths ``n``, maximum lags ``M``.  Holds the host bytes and, once
     ``to(device)`` has run, an identical device copy."""
 
-    def __init__(self, n, M, window="parzen", path="fp32", center=True, adjoint=False):
+    def __init__(self, n, M, window="parzen", path="fp32", center=True, adjoint=False,
+                 tile=None):
+        """``tile``: None (built-in rule), a mapping M -> tile choice (0, 2 or 4,
+        e.g. the output of ``tune.tune``), or one choice per series."""
         import numpy as np
         self.n = np.ascontiguousarray(np.asarray(n, dtype=np.int64).ravel())
         self.M = np.ascontiguousarray(np.asarray(M, dtype=np.int32).ravel())
@@ -341,15 +346,25 @@ class BatchPlan:
             raise ValueError("n and M must be non-empty and of equal length")
         self.window, self.path = window, path
         self.flags = (0 if center else HOS_NO_CENTER) | (HOS_PLAN_ADJOINT if adjoint else 0)
+        if tile is None:
+            self.tile = None
+        elif isinstance(tile, dict):
+            self.tile = np.ascontiguousarray(
+                [int(tile.get(int(m), tile.get(str(int(m)), 0))) for m in self.M], dtype=np.int32)
+        else:
+            self.tile = np.ascontiguousarray(np.asarray(tile, dtype=np.int32).ravel())
+            if self.tile.size != self.n.size:
+                raise ValueError("one tile choice per series")
+        tp = _i32p(self.tile) if self.tile is not None else None
         pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
         st = lib().hos_batch_plan_size(self.n.size, _i64p(self.n), _i32p(self.M),
-                                       WINDOWS[window], PATHS[path], self.flags,
+                                       WINDOWS[window], PATHS[path], self.flags, tp,
                                        ctypes.byref(pb), ctypes.byref(wb))
         if st != HOS_OK:
             raise HosError(st, "hos_batch_plan_size")
         self.host = np.zeros((pb.value + 7) // 8, dtype=np.int64)   # 8-byte aligned bytes
         st = lib().hos_batch_plan(self.n.size, _i64p(self.n), _i32p(self.M), WINDOWS[window],
-                                  PATHS[path], self.flags, self.host.ctypes.data, pb.value)
+                                  PATHS[path], self.flags, tp, self.host.ctypes.data, pb.value)
         if st != HOS_OK:
             raise HosError(st, "hos_batch_plan")
         info = np.zeros(12, dtype=np.int64)
@@ -425,6 +440,30 @@ def bispectrum_batched(x, plan: BatchPlan, return_c3=True, return_B=True):
     if st != HOS_OK:
         raise HosError(st, "hos_bispectrum_batched")
     return c3, B
+
+
+BATCH_STAGES = ("prep", "contract", "reduce", "spectra", "total")
+
+
+def bispectrum_batched_timed(x, plan: BatchPlan, return_c3=False):
+    """Like ``bispectrum_batched`` (principal-domain spectra always); also
+    returns {stage: milliseconds} measured with HIP events (waits)."""
+    import torch
+    x = _check_packed(x, plan)
+    plan.to(x.device)
+    ws = plan.workspace(x.device)
+    c3 = torch.empty(plan.info["c3_elems"], dtype=torch.float64,
+                     device=x.device) if return_c3 else None
+    B = torch.empty(plan.info["pd_elems"], dtype=torch.complex128, device=x.device)
+    ms = (ctypes.c_float * 5)()
+    st = lib().hos_bispectrum_batched_timed(
+        x.data_ptr(), HOS_F64 if x.dtype == torch.float64 else HOS_F32,
+        plan.host.ctypes.data, plan.dev.data_ptr(),
+        c3.data_ptr() if c3 is not None else None, B.data_ptr(),
+        ws.data_ptr(), ws.numel(), _stream_handle(x.device), ms)
+    if st != HOS_OK:
+        raise HosError(st, "hos_bispectrum_batched_timed")
+    return c3, B, dict(zip(BATCH_STAGES, list(ms)))
 
 
 def bispectrum_loss_fwd(x, target_pd, plan: BatchPlan):

@@ -53,7 +53,8 @@ static int pd_count(int N)
 }
 
 int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window, int32_t path,
-               uint32_t flags, void *blob, size_t blob_bytes, BatchHeader *hdr_out)
+               uint32_t flags, const int32_t *tile_nb, void *blob, size_t blob_bytes,
+               BatchHeader *hdr_out)
 {
     if (batch < 1 || batch > (1 << 20) || !n || !M)
         return HOS_EINVAL;
@@ -80,6 +81,8 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
             return HOS_EINVAL;
         if (adj && M[s] > ADJ_MAX_M)
             return HOS_EINVAL;
+        if (tile_nb && tile_nb[s] != 0 && tile_nb[s] != 4 && !(tile_nb[s] == 2 && split))
+            return HOS_EINVAL;   // the FP32 path has 4 x 4-block tiles only
         if (M[s] != h.uniform_M)
             h.uniform_M = -1;
         if (n[s] != h.uniform_n)
@@ -106,6 +109,8 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         d.pd_off = pdo;
         pdo += d.npd;
         d.cls = (d.M >= 96 || !split) ? 1 : 0;
+        if (tile_nb && tile_nb[s] != 0)
+            d.cls = tile_nb[s] == 4 ? 1 : 0;
         d.NB = d.cls ? 4 : 2;
         d.NBR = (d.M + 31) / 32;
         d.TR = d.NBR > 0 ? (d.NBR + d.NB - 1) / d.NB : 0;
@@ -340,12 +345,13 @@ using namespace hos;
 extern "C" {
 
 int hos_batch_plan_size(int32_t batch, const int64_t *n, const int32_t *M, int32_t window,
-                        int32_t path, uint32_t flags, size_t *plan_bytes, size_t *ws_bytes)
+                        int32_t path, uint32_t flags, const int32_t *tile_nb, size_t *plan_bytes,
+                        size_t *ws_bytes)
 {
     if (!plan_bytes || !ws_bytes)
         return HOS_EINVAL;
     BatchHeader h;
-    const int st = batch_plan(batch, n, M, window, path, flags, nullptr, 0, &h);
+    const int st = batch_plan(batch, n, M, window, path, flags, tile_nb, nullptr, 0, &h);
     if (st != HOS_OK)
         return st;
     *plan_bytes = (size_t)h.blob_bytes;
@@ -354,11 +360,12 @@ int hos_batch_plan_size(int32_t batch, const int64_t *n, const int32_t *M, int32
 }
 
 int hos_batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window,
-                   int32_t path, uint32_t flags, void *plan, size_t plan_bytes)
+                   int32_t path, uint32_t flags, const int32_t *tile_nb, void *plan,
+                   size_t plan_bytes)
 {
     if (!plan || !aligned_to(plan, 8))
         return HOS_EINVAL;
-    return batch_plan(batch, n, M, window, path, flags, plan, plan_bytes, nullptr);
+    return batch_plan(batch, n, M, window, path, flags, tile_nb, plan, plan_bytes, nullptr);
 }
 
 int hos_batch_plan_info(const void *plan, int64_t *info, int32_t ninfo)
@@ -459,9 +466,9 @@ static hipError_t batch_forward(const void *x, int32_t dtype, const BatchHeader 
     return e;
 }
 
-int hos_bispectrum_batched(const void *x, int32_t dtype, const void *plan_host,
-                           const void *plan_dev, double *c3, double *B_pd, void *ws,
-                           size_t ws_bytes, hipStream_t stream)
+static int batched_impl(const void *x, int32_t dtype, const void *plan_host,
+                        const void *plan_dev, double *c3, double *B_pd, void *ws,
+                        size_t ws_bytes, hipStream_t stream, hipEvent_t *ev)
 {
     const BatchHeader *h = nullptr;
     if (!c3 && !B_pd)
@@ -472,10 +479,55 @@ int hos_bispectrum_batched(const void *x, int32_t dtype, const void *plan_host,
     if (st != HOS_OK)
         return st;
     char *w = (char *)ws;
-    hipError_t e = batch_forward(x, dtype, *h, (const char *)plan_dev, w, stream);
-    if (e == hipSuccess)
-        e = launch_batch_spectra(*h, (const char *)plan_dev, (int)h->window, c3, B_pd, w, stream);
+    const char *dp = (const char *)plan_dev;
+    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], stream) : hipSuccess; };
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = launch_batch_prep(x, dtype, *h, dp, w, stream);
+    if (e == hipSuccess) e = mark(1);
+    if (e == hipSuccess) e = launch_batch_contract(*h, dp, w, stream);
+    if (e == hipSuccess) e = mark(2);
+    if (e == hipSuccess) e = launch_batch_reduce(x, dtype, *h, dp, w, stream);
+    if (e == hipSuccess) e = mark(3);
+    if (e == hipSuccess) e = launch_batch_spectra(*h, dp, (int)h->window, c3, B_pd, w, stream);
+    if (e == hipSuccess) e = mark(4);
     return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
+int hos_bispectrum_batched(const void *x, int32_t dtype, const void *plan_host,
+                           const void *plan_dev, double *c3, double *B_pd, void *ws,
+                           size_t ws_bytes, hipStream_t stream)
+{
+    return batched_impl(x, dtype, plan_host, plan_dev, c3, B_pd, ws, ws_bytes, stream, nullptr);
+}
+
+int hos_bispectrum_batched_timed(const void *x, int32_t dtype, const void *plan_host,
+                                 const void *plan_dev, double *c3, double *B_pd, void *ws,
+                                 size_t ws_bytes, hipStream_t stream, float *stage_ms)
+{
+    if (!stage_ms)
+        return HOS_EINVAL;
+    hipEvent_t ev[5];
+    int made = 0;
+    for (; made < 5; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess)
+            break;
+    int st = made == 5 ? batched_impl(x, dtype, plan_host, plan_dev, c3, B_pd, ws, ws_bytes,
+                                      stream, ev)
+                       : HOS_EDEVICE;
+    if (st == HOS_OK) {
+        if (hipEventSynchronize(ev[4]) != hipSuccess) {
+            st = HOS_EDEVICE;
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (hipEventElapsedTime(&stage_ms[k], ev[k], ev[k + 1]) != hipSuccess)
+                    st = HOS_EDEVICE;
+            if (hipEventElapsedTime(&stage_ms[4], ev[0], ev[4]) != hipSuccess)
+                st = HOS_EDEVICE;
+        }
+    }
+    for (int k = 0; k < made; ++k)
+        hipEventDestroy(ev[k]);
+    return st;
 }
 
 int hos_bispectrum_loss_fwd(const void *x, int32_t dtype, const void *plan_host,

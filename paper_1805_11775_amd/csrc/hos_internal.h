@@ -252,7 +252,8 @@ struct BatchHeader {
 
 // Plan flags (in hos.h: HOS_PLAN_ADJOINT).
 int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window, int32_t path,
-               uint32_t flags, void *blob, size_t blob_bytes, BatchHeader *hdr_out);
+               uint32_t flags, const int32_t *tile_nb, void *blob, size_t blob_bytes,
+               BatchHeader *hdr_out);
 int device_ok_public();
 constexpr int ADJ_MAX_M = 320;     // staged adjoint window <= 48 KB of LDS
 

@@ -121,10 +121,10 @@ def test_plan_rejects_enums():
     M = np.array([10], dtype=np.int32)
     pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
     args = (1, hos._i64p(n), hos._i32p(M))
-    assert lib.hos_batch_plan_size(*args, 2, 0, 0, ctypes.byref(pb), ctypes.byref(wb)) == -1
-    assert lib.hos_batch_plan_size(*args, 1, 3, 0, ctypes.byref(pb), ctypes.byref(wb)) == -1
-    assert lib.hos_batch_plan_size(*args, 1, 0, 4, ctypes.byref(pb), ctypes.byref(wb)) == -1
-    assert lib.hos_batch_plan_size(*args, 1, 0, 0, ctypes.byref(pb), ctypes.byref(wb)) == 0
+    assert lib.hos_batch_plan_size(*args, 2, 0, 0, None, ctypes.byref(pb), ctypes.byref(wb)) == -1
+    assert lib.hos_batch_plan_size(*args, 1, 3, 0, None, ctypes.byref(pb), ctypes.byref(wb)) == -1
+    assert lib.hos_batch_plan_size(*args, 1, 0, 4, None, ctypes.byref(pb), ctypes.byref(wb)) == -1
+    assert lib.hos_batch_plan_size(*args, 1, 0, 0, None, ctypes.byref(pb), ctypes.byref(wb)) == 0
 
 
 FAKE = 0x10000
@@ -154,3 +154,31 @@ def test_batched_entry_points_validate_before_device():
     assert b(FAKE, 0, fwd_only.host.ctypes.data, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
              fwd_only.info["ws_bytes"], None) == hos.HOS_EINVAL  # no adjoint buffers
     assert b(FAKE, 0, ph, FAKE, FAKE, FAKE, FAKE, FAKE + 2, FAKE, wsb, None) == hos.HOS_EINVAL
+
+
+def test_tile_choice_moves_series_between_classes():
+    n, M = [5000, 5000, 5000], [64, 64, 200]
+    base = hos.BatchPlan(n, M, path="split_fp16")
+    assert list(base.series()[:, 7]) == [0, 0, 1]
+    forced = hos.BatchPlan(n, M, path="split_fp16", tile={64: 4, 200: 2})
+    assert list(forced.series()[:, 7]) == [1, 1, 0]
+    per = hos.BatchPlan(n, M, path="split_fp16", tile=[2, 4, 0])
+    assert list(per.series()[:, 7]) == [0, 1, 1]
+    with pytest.raises(hos.HosError):
+        hos.BatchPlan(n, M, path="fp32", tile=[2, 2, 2])     # FP32 has 4 x 4 tiles only
+    with pytest.raises(hos.HosError):
+        hos.BatchPlan(n, M, path="split_fp16", tile=[3, 0, 0])
+    # the split of a forced plan still covers every chunk once
+    for cls in (0, 1):
+        it = forced.items(cls)
+        keys = set()
+        for row in it:
+            for ch in range(row[5], row[6]):
+                key = (row[2], row[3], row[4], ch)
+                assert key not in keys
+                keys.add(key)
+
+
+def test_tune_module_imports():
+    from paper_1805_11775_amd import tune
+    assert tune.CANDIDATES["fp32"] == (4,)

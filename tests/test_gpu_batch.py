@@ -217,3 +217,46 @@ def test_loss_workload_sampled(path):
         assert e < TOL[path]
         assert abs(np.sum(dxn[b].astype(np.float64))) < 1e-3 * np.max(np.abs(dxn[b])) * 256
     assert np.isfinite(float(loss))
+
+
+def test_tuner_choices_are_valid_and_correct():
+    """The tuner returns one tile choice per lag among the candidates, and a
+    plan built from them matches the oracle."""
+    hos = _hos()
+    from paper_1805_11775_amd import tune
+    res = tune.tune([32, 128], path="split_fp16", n_lo=1024, n_hi=8192, series=6, reps=2)
+    print("tuned:", res, flush=True)
+    assert set(res["choices"]) == {32, 128}
+    assert all(v in (2, 4) for v in res["choices"].values())
+    xs = [synth.iid_exp_centered(3000, 91).astype(np.float32),
+          synth.iid_gauss(2500, 92).astype(np.float32)]
+    plan = hos.BatchPlan([3000, 2500], [32, 128], path="split_fp16", tile=res["choices"])
+    c3, B = hos.bispectrum_batched(torch.from_numpy(np.concatenate(xs)).cuda(), plan)
+    torch.cuda.synchronize()
+    S = plan.series()
+    for s in range(2):
+        Ms, N, npd, c3o, pdo = (int(v) for v in (S[s, 1], S[s, 2], S[s, 3], S[s, 5], S[s, 6]))
+        c_ref, B_ref = oracle.bispectrum(xs[s], Ms, N)
+        k1, k2 = oracle.pd_indices(N)
+        got = c3[c3o:c3o + (2 * Ms + 1) ** 2].cpu().numpy().reshape(2 * Ms + 1, -1)
+        assert _rel(got, c_ref) < 1e-5
+        assert _rel(B[pdo:pdo + npd].cpu().numpy(), B_ref[k1, k2]) < 1e-5
+
+
+@pytest.mark.parametrize("tile", [2, 4])
+def test_forced_tile_classes_match_oracle(tile):
+    """Every series on one tile class, whatever its lag."""
+    hos = _hos()
+    xs, n, M = _uneven()
+    plan = hos.BatchPlan(n, M, path="split_fp16", tile=[tile] * len(n))
+    x = torch.from_numpy(np.concatenate(xs)).cuda()
+    c3, B = hos.bispectrum_batched(x, plan)
+    torch.cuda.synchronize()
+    c3, B = c3.cpu().numpy(), B.cpu().numpy()
+    S = plan.series()
+    for s in range(len(n)):
+        Ms, N, npd, c3o, pdo = (int(v) for v in (S[s, 1], S[s, 2], S[s, 3], S[s, 5], S[s, 6]))
+        c_ref, B_ref = oracle.bispectrum(xs[s], Ms, N)
+        k1, k2 = oracle.pd_indices(N)
+        got = c3[c3o:c3o + (2 * Ms + 1) ** 2].reshape(2 * Ms + 1, 2 * Ms + 1)
+        assert _rel(got, c_ref) < 1e-5 and _rel(B[pdo:pdo + npd], B_ref[k1, k2]) < 1e-5, s
