@@ -246,7 +246,8 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  */
 
 /* Plan and workspace sizes for a batch.  n, M: host arrays of `batch`
- * entries (n >= 2, 0 <= M < n, M <= 2048; M <= 320 with HOS_PLAN_ADJOINT).
+ * entries (n >= 2, 0 <= M < n, DFT size N <= 2048, i.e. M <= 1024 with
+ * the Parzen window and M <= 1023 without; M <= 320 with HOS_PLAN_ADJOINT).
  * window: hos_window.  flags: HOS_NO_CENTER, HOS_PLAN_ADJOINT (lay out the
  * buffers hos_bispectrum_loss_bwd needs).  tile_nb: NULL, or a host array
  * of `batch` tile choices for the contraction, 0 = built-in rule, 2 = tiles

@@ -105,6 +105,8 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         d.c3_off = c3o;
         c3o += (int64_t)(2 * d.M + 1) * (2 * d.M + 1);
         d.N = next_fft(window == HOS_WIN_PARZEN ? 2 * d.M : 2 * d.M + 1);
+        if (d.N > 2048)
+            return HOS_EINVAL;   // principal-domain DFTs stage 2048-point sequences
         d.npd = pd_count(d.N);
         d.pd_off = pdo;
         pdo += d.npd;

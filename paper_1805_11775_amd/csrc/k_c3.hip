@@ -860,39 +860,37 @@ k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict
     }
 }
 
-// Leftover diagonal sums per series, one workgroup per series: for each
-// leftover a = 0, 32, 64, ... <= M the threads sum strided samples in FP64
-// from the input and a fixed-order tree combines them into C[a][a].
+// Leftover diagonal sums: one workgroup per (series, leftover a = 32
+// blockIdx.y <= M); strided FP64 partial sums from the input combined by a
+// fixed-order tree into C[a][a].
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_bdiag(const T *__restrict__ x, const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
 {
     __shared__ double red[256];
     const SeriesDesc &d = sd[blockIdx.x];
+    const int left = blockIdx.y;
+    if (left >= d.nleft)
+        return;
     char *r = ws + d.ws_off;
     const double *stats = (const double *)(r + d.o_stats);
-    double *cfull = (double *)(r + d.o_cfull);
     const T *xs = x + d.x_off;
-    const int64_t n = d.n;
+    const int64_t n = d.n, a = 32 * (int64_t)left;
     const double mu = stats[0], sc = stats[1];
-    for (int left = 0; left < d.nleft; ++left) {
-        const int64_t a = 32 * (int64_t)left;
-        double s = 0.0;
-        for (int64_t i = threadIdx.x; i + a < n; i += 256) {
-            const double u = ((double)xs[i + a] - mu) * sc;
-            s += (((double)xs[i] - mu) * sc) * u * u;
-        }
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w)
-                red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0)
-            cfull[a * (d.M + 1) + a] = red[0];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i + a < n; i += 256) {
+        const double u = ((double)xs[i + a] - mu) * sc;
+        s += (((double)xs[i] - mu) * sc) * u * u;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    if (threadIdx.x == 0)
+        ((double *)(r + d.o_cfull))[a * (d.M + 1) + a] = red[0];
 }
 
 template <int PATH, int NB>
@@ -1005,11 +1003,11 @@ hipError_t launch_batch_reduce(const void *x, int dtype, const BatchHeader &h, c
         else
             k_c3_reduce_items<2><<<(unsigned)(h.n_tiles[cls] * 4), 256, 0, s>>>(sd, t, part, ws);
     }
-    const int B = (int)h.batch;
+    const dim3 grid((unsigned)h.batch, (unsigned)h.max_nleft);
     if (dtype == HOS_F64)
-        k_bdiag<double><<<B, 256, 0, s>>>((const double *)x, sd, ws);
+        k_bdiag<double><<<grid, 256, 0, s>>>((const double *)x, sd, ws);
     else
-        k_bdiag<float><<<B, 256, 0, s>>>((const float *)x, sd, ws);
+        k_bdiag<float><<<grid, 256, 0, s>>>((const float *)x, sd, ws);
     return hipGetLastError();
 }
 

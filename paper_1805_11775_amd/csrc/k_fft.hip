@@ -271,15 +271,38 @@ namespace {
 
 __device__ inline int pd_len(int k1, int H) { return k1 <= H ? min(k1, H - k1) + 1 : 0; }
 
-// Rows: blockIdx.y = series of group g, blockIdx.x = block of CB rows m1.
+constexpr int PD_LDS_ELEMS = 2048;   // complex doubles per workgroup (32 KB): 4+ per CU
+
+__device__ inline void fft_lds(double2 *sm, const double2 *__restrict__ tw, const FftRadices &fr,
+                               int CB)
+{
+    int Ns = 1;
+    for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
+        const int R = fr.r[st];
+        if (R == 4)
+            stockham_stage<4>(sm, tw, fr.n, Ns, CB);
+        else if (R == 2)
+            stockham_stage<2>(sm, tw, fr.n, Ns, CB);
+        else if (R == 3)
+            stockham_stage<3>(sm, tw, fr.n, Ns, CB);
+        else
+            stockham_stage<5>(sm, tw, fr.n, Ns, CB);
+        Ns *= R;
+    }
+}
+
+// Rows: blockIdx.y = series of group g, blockIdx.x = block of 2 CBP rows m1.
+// The folded rows are real, so rows m1 and m1 + 1 travel as the real and
+// imaginary parts of one complex sequence; after its DFT Z,
+//   X_{m1}(k) = (Z(k) + conj Z(N-k)) / 2,  X_{m1+1}(k) = (Z(k) - conj Z(N-k)) / 2i.
 // T1[m1][k2] (k2 < K2) goes to the series' grid region.
 __global__ void __launch_bounds__(FFT_THREADS)
 k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, int first,
-          char *__restrict__ ws, const double2 *__restrict__ tw, FftRadices fr, int CB,
+          char *__restrict__ ws, const double2 *__restrict__ tw, FftRadices fr, int CBP,
           int window)
 {
-    __shared__ double2 sm[FFT_LDS_ELEMS];
-    __shared__ double dwin[FFT_LDS_ELEMS / 2 + 1];   // d(m), m = 0..M (M < N/2 + 1)
+    __shared__ double2 sm[PD_LDS_ELEMS];
+    __shared__ double dwin[FFT_LDS_ELEMS / 2 + 1];   // d(m), m = 0..M (M <= N/2)
     const SeriesDesc &d = sd[gser[first + blockIdx.y]];
     const int N = fr.n, M = d.M, K2 = N / 4 + 1;
     const char *r = ws + d.ws_off;
@@ -289,9 +312,7 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
     for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
-    const int m1_0 = blockIdx.x * CB;
-    for (int e = threadIdx.x; e < CB * N; e += FFT_THREADS) {
-        const int cb = e / N, m2 = e - cb * N, m1 = m1_0 + cb;
+    auto fold = [&](int m1, int m2) {
         double sum = 0.0;
         if (m1 < N) {
             for (int w1 = m1 - N; w1 <= m1; w1 += N) {
@@ -306,27 +327,25 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
                 }
             }
         }
-        sm[e] = make_double2(sum, 0.0);
+        return sum;
+    };
+    const int m1_0 = blockIdx.x * 2 * CBP;
+    for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
+        const int p = e / N, m2 = e - p * N, m1 = m1_0 + 2 * p;
+        sm[e] = make_double2(fold(m1, m2), fold(m1 + 1, m2));
     }
     __syncthreads();
-    int Ns = 1;
-    for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
-        const int R = fr.r[st];
-        if (R == 4)
-            stockham_stage<4>(sm, tw, N, Ns, CB);
-        else if (R == 2)
-            stockham_stage<2>(sm, tw, N, Ns, CB);
-        else if (R == 3)
-            stockham_stage<3>(sm, tw, N, Ns, CB);
-        else
-            stockham_stage<5>(sm, tw, N, Ns, CB);
-        Ns *= R;
-    }
+    fft_lds(sm, tw, fr, CBP);
     double2 *T1 = (double2 *)(ws + d.grid_off);
-    for (int e = threadIdx.x; e < CB * K2; e += FFT_THREADS) {
-        const int cb = e / K2, k2 = e - cb * K2, m1 = m1_0 + cb;
+    for (int e = threadIdx.x; e < CBP * K2; e += FFT_THREADS) {
+        const int p = e / K2, k2 = e - p * K2, m1 = m1_0 + 2 * p;
+        const double2 z = sm[p * N + k2], zc = sm[p * N + (k2 == 0 ? 0 : N - k2)];
+        // conj(Z(N-k)) = (zc.x, -zc.y)
         if (m1 < N)
-            T1[(int64_t)m1 * K2 + k2] = sm[cb * N + k2];
+            T1[(int64_t)m1 * K2 + k2] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+        if (m1 + 1 < N)
+            T1[(int64_t)(m1 + 1) * K2 + k2] =
+                make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
     }
 }
 
@@ -337,7 +356,7 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
           const char *__restrict__ ws, const double2 *__restrict__ tw, FftRadices fr, int CB,
           double2 *__restrict__ B_pd)
 {
-    __shared__ double2 sm[FFT_LDS_ELEMS];
+    __shared__ double2 sm[PD_LDS_ELEMS];
     __shared__ int rowstart[FFT_LDS_ELEMS / 2 + 1];
     const SeriesDesc &d = sd[gser[first + blockIdx.y]];
     const int N = fr.n, K2 = N / 4 + 1, H = (N - 1) / 2;
@@ -355,19 +374,7 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
         }
     }
     __syncthreads();
-    int Ns = 1;
-    for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
-        const int R = fr.r[st];
-        if (R == 4)
-            stockham_stage<4>(sm, tw, N, Ns, CB);
-        else if (R == 2)
-            stockham_stage<2>(sm, tw, N, Ns, CB);
-        else if (R == 3)
-            stockham_stage<3>(sm, tw, N, Ns, CB);
-        else
-            stockham_stage<5>(sm, tw, N, Ns, CB);
-        Ns *= R;
-    }
+    fft_lds(sm, tw, fr, CB);
     const int half = H + 1;   // k1 <= H
     for (int e = threadIdx.x; e < CB * half; e += FFT_THREADS) {
         const int cb = e / half, k1 = e - cb * half, k2 = k2_0 + cb;
@@ -392,14 +399,18 @@ hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window
         if (e != hipSuccess)
             return e;
         const FftRadices fr = factor(N);
-        int CB = FFT_LDS_ELEMS / N;
+        int CB = PD_LDS_ELEMS / N;
         if (CB > 32)
             CB = 32;
         const int K2 = N / 4 + 1;
-        k_pd_rows<<<dim3((N + CB - 1) / CB, gr.count), FFT_THREADS, 0, s>>>(
-            sd, gser, (int)gr.first, ws, tw, fr, CB, window);
-        k_pd_cols<<<dim3((K2 + CB - 1) / CB, gr.count), FFT_THREADS, 0, s>>>(
-            sd, gser, (int)gr.first, ws, tw, fr, CB, (double2 *)B_pd);
+        if (CB >= 1) {
+            k_pd_rows<<<dim3((N + 2 * CB - 1) / (2 * CB), gr.count), FFT_THREADS, 0, s>>>(
+                sd, gser, (int)gr.first, ws, tw, fr, CB, window);
+            k_pd_cols<<<dim3((K2 + CB - 1) / CB, gr.count), FFT_THREADS, 0, s>>>(
+                sd, gser, (int)gr.first, ws, tw, fr, CB, (double2 *)B_pd);
+        } else {
+            return hipErrorInvalidValue;   // N > 2048: not planned for batches
+        }
     }
     return hipGetLastError();
 }

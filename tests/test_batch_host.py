@@ -106,7 +106,7 @@ def test_series_layout(window):
 @pytest.mark.parametrize("n,M,kw", [
     ([100], [100], {}),                 # M >= n
     ([1], [0], {}),                     # n < 2
-    ([5000], [2049], {}),               # M beyond the batch limit
+    ([5000], [1025], {}),               # DFT size beyond the batch limit
     ([5000], [321], {"adjoint": True}),  # beyond the adjoint's staged window
     ([100, 200], [5], {}),              # lengths differ
 ])
