@@ -45,8 +45,11 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     g.G = (int32_t)G;
     p.smax = g.TR > 0 ? sk_max_segments(g) : 0;
     p.npad = ((C * KC + (int64_t)g.TR * p.TS + 64) + 63) / 64 * 64;
+    // leftover diagonal sums: one pass over x in up to 256 sample ranges
+    // (k_diag_fused) when nleft <= 32, else nleft x 64 strided blocks
     int64_t db = n / 4096;
-    p.dot_blocks = (int32_t)(db < 1 ? 1 : (db > 64 ? 64 : db));
+    const int64_t dbmax = p.nleft <= 32 ? 256 : 64;
+    p.dot_blocks = (int32_t)(db < 1 ? 1 : (db > dbmax ? dbmax : db));
 
     size_t o = 0;
     p.off_stats = o;  o = align256(o + 64 * sizeof(double));

@@ -592,8 +592,10 @@ k_c3_reduce(const double *__restrict__ part, SkGeom g, int64_t smax, int NBR, in
             double *__restrict__ cfull)
 {
     constexpr int64_t TILE = (int64_t)(32 * NB) * (32 * NB);
-    const int64_t t = blockIdx.x / (NB * NB);
-    const int blk = blockIdx.x % (NB * NB);
+    // blockIdx.x = (tile, 32-block, quarter of the block's 1024 elements)
+    const int q = blockIdx.x & 3;
+    const int64_t t = (blockIdx.x >> 2) / (NB * NB);
+    const int blk = (blockIdx.x >> 2) % (NB * NB);
     int R = 0;
     while (sk_tile_index(R + 1, 0) <= t)
         ++R;
@@ -602,30 +604,24 @@ k_c3_reduce(const double *__restrict__ part, SkGeom g, int64_t smax, int NBR, in
     const int Rg = R * NB + bR, Bg = Cc * NB + bC;
     if (Rg >= NBR || Bg > Rg)
         return;
+    const int e = threadIdx.x + 256 * q;
     const int64_t w_lo = sk_owner(g, sk_chunk_start(g, R, Cc, 0));
     const int64_t w_hi = sk_owner(g, sk_chunk_start(g, R, Cc, g.C - 1));
-    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    double sum = 0.0;
     for (int64_t w = w_lo; w <= w_hi; ++w) {
         SkPos p;
         sk_first_chunk(g, sk_wg_start(g, w), p);
         const int64_t slot = w * smax + (t - sk_tile_index(p.R, p.Cc));
-        const double *src = part + slot * TILE + (int64_t)blk * 1024;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            sum[k] += src[threadIdx.x + 256 * k];
+        sum += part[slot * TILE + (int64_t)blk * 1024 + e];
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int e = threadIdx.x + 256 * k;
-        const int v = e >> 6, lane = e & 63;
-        // 32x32 MFMA accumulator layout: column = lane % 32,
-        // row = 8 (v / 4) + 4 (lane / 32) + v % 4
-        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int col = lane & 31;
-        const int r = Rg * 32 + row, b = Bg * 32 + col;
-        if (r < M && (Bg < Rg || col <= row + 1))
-            cfull[(int64_t)(r + 1) * (M + 1) + b] = sum[k];
-    }
+    const int v = e >> 6, lane = e & 63;
+    // 32x32 MFMA accumulator layout: column = lane % 32,
+    // row = 8 (v / 4) + 4 (lane / 32) + v % 4
+    const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int col = lane & 31;
+    const int r = Rg * 32 + row, b = Bg * 32 + col;
+    if (r < M && (Bg < Rg || col <= row + 1))
+        cfull[(int64_t)(r + 1) * (M + 1) + b] = sum;
 }
 
 // Leftover diagonal sums C[a][a] = sum_i x~_i x~_{i+a}^2 for a = 0 and
@@ -654,6 +650,57 @@ k_diag_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats,
     }
     if (threadIdx.x == 0)
         dpart[blockIdx.x] = red[0];
+}
+
+// The same sums for nleft <= DIAG_FUSED_MAX leftovers in one pass over x:
+// workgroup b takes the samples [b L, (b+1) L), stages x~ (FP64) for 1024
+// samples plus the 32 (nleft-1) halo in LDS, and each thread accumulates every
+// leftover's products for its samples.  dpart[left * nblocks + b].
+constexpr int DIAG_FUSED_MAX = 32;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_diag_fused(const T *__restrict__ x, int64_t n, const double *__restrict__ stats, int nleft,
+             int64_t L, double *__restrict__ dpart)
+{
+    __shared__ double sx[1024 + 32 * (DIAG_FUSED_MAX - 1)];
+    __shared__ double red[256];
+    const double mu = stats[0], sc = stats[1];
+    const int64_t b0 = (int64_t)blockIdx.x * L, b1 = b0 + L < n ? b0 + L : n;
+    const int halo = 32 * (nleft - 1);
+    double acc[DIAG_FUSED_MAX];
+#pragma unroll
+    for (int k = 0; k < DIAG_FUSED_MAX; ++k)
+        acc[k] = 0.0;
+    for (int64_t i0 = b0; i0 < b1; i0 += 1024) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 1024 + halo; e += 256) {
+            const int64_t i = i0 + e;
+            sx[e] = i < n ? ((double)x[i] - mu) * sc : 0.0;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < 1024 && i0 + j < b1; j += 256) {
+            const double xi = sx[j];
+#pragma unroll
+            for (int k = 0; k < DIAG_FUSED_MAX; ++k)
+                if (k < nleft) {
+                    const double u = sx[j + 32 * k];
+                    acc[k] += xi * u * u;
+                }
+        }
+    }
+    for (int k = 0; k < nleft; ++k) {
+        __syncthreads();
+        red[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w)
+                red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            dpart[k * gridDim.x + blockIdx.x] = red[0];
+    }
 }
 
 __global__ void __launch_bounds__(64)
@@ -832,8 +879,10 @@ k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict
                   const double *__restrict__ part, char *__restrict__ ws)
 {
     constexpr int64_t TILE = (int64_t)(32 * NB) * (32 * NB);
-    const C3TileRef t = tiles[blockIdx.x / (NB * NB)];
-    const int blk = blockIdx.x % (NB * NB);
+    // blockIdx.x = (tile, 32-block, quarter of the block's 1024 elements)
+    const int q = blockIdx.x & 3;
+    const C3TileRef t = tiles[(blockIdx.x >> 2) / (NB * NB)];
+    const int blk = (blockIdx.x >> 2) % (NB * NB);
     const SeriesDesc &d = sd[t.series];
     const int bR = blk / NB, bC = blk % NB;
     const int Rg = t.R * NB + bR, Bg = t.Cc * NB + bC;
@@ -841,23 +890,16 @@ k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict
         return;
     const int M = d.M;
     double *cfull = (double *)(ws + d.ws_off + d.o_cfull);
-    double sum[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j < t.nslot; ++j) {
-        const double *src = part + (t.slot0 + j) * TILE + (int64_t)blk * 1024;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            sum[k] += src[threadIdx.x + 256 * k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int e = threadIdx.x + 256 * k;
-        const int v = e >> 6, lane = e & 63;
-        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int col = lane & 31;
-        const int r = Rg * 32 + row, b = Bg * 32 + col;
-        if (r < M && (Bg < Rg || col <= row + 1))
-            cfull[(int64_t)(r + 1) * (M + 1) + b] = sum[k];
-    }
+    const int e = threadIdx.x + 256 * q;
+    double sum = 0.0;
+    for (int j = 0; j < t.nslot; ++j)
+        sum += part[(t.slot0 + j) * TILE + (int64_t)blk * 1024 + e];
+    const int v = e >> 6, lane = e & 63;
+    const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int col = lane & 31;
+    const int r = Rg * 32 + row, b = Bg * 32 + col;
+    if (r < M && (Bg < Rg || col <= row + 1))
+        cfull[(int64_t)(r + 1) * (M + 1) + b] = sum;
 }
 
 // Leftover diagonal sums: one workgroup per (series, leftover a = 32
@@ -936,6 +978,16 @@ hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws, 
 {
     const double *stats = (const double *)(ws + p.off_stats);
     double *dpart = (double *)(ws + p.off_dpart);
+    if (p.nleft <= DIAG_FUSED_MAX) {
+        const int64_t L = (p.n + p.dot_blocks - 1) / p.dot_blocks;
+        if (dtype == HOS_F64)
+            k_diag_fused<double><<<p.dot_blocks, 256, 0, s>>>((const double *)x, p.n, stats,
+                                                              p.nleft, L, dpart);
+        else
+            k_diag_fused<float><<<p.dot_blocks, 256, 0, s>>>((const float *)x, p.n, stats,
+                                                             p.nleft, L, dpart);
+        return hipGetLastError();
+    }
     const int grid = p.nleft * p.dot_blocks;
     if (dtype == HOS_F64)
         k_diag_dot<double><<<grid, 256, 0, s>>>((const double *)x, p.n, stats, p.dot_blocks, dpart);
@@ -951,10 +1003,10 @@ hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s)
         const int64_t ntiles = (int64_t)p.sk.TR * (p.sk.TR + 1) / 2;
         const int NB = p.NB;
         if (NB == 4)
-            k_c3_reduce<4><<<ntiles * NB * NB, 256, 0, s>>>((const double *)(ws + p.off_part),
+            k_c3_reduce<4><<<ntiles * NB * NB * 4, 256, 0, s>>>((const double *)(ws + p.off_part),
                                                           p.sk, p.smax, p.NBR, p.M, cfull);
         else
-            k_c3_reduce<2><<<ntiles * NB * NB, 256, 0, s>>>((const double *)(ws + p.off_part),
+            k_c3_reduce<2><<<ntiles * NB * NB * 4, 256, 0, s>>>((const double *)(ws + p.off_part),
                                                           p.sk, p.smax, p.NBR, p.M, cfull);
     }
     k_diag_final<<<(p.nleft + 63) / 64, 64, 0, s>>>((const double *)(ws + p.off_dpart),
@@ -999,9 +1051,9 @@ hipError_t launch_batch_reduce(const void *x, int dtype, const BatchHeader &h, c
         const C3TileRef *t = (const C3TileRef *)(dplan + h.tiles_off[cls]);
         const double *part = (const double *)(ws + h.part_off[cls]);
         if (cls == 1)
-            k_c3_reduce_items<4><<<(unsigned)(h.n_tiles[cls] * 16), 256, 0, s>>>(sd, t, part, ws);
+            k_c3_reduce_items<4><<<(unsigned)(h.n_tiles[cls] * 16 * 4), 256, 0, s>>>(sd, t, part, ws);
         else
-            k_c3_reduce_items<2><<<(unsigned)(h.n_tiles[cls] * 4), 256, 0, s>>>(sd, t, part, ws);
+            k_c3_reduce_items<2><<<(unsigned)(h.n_tiles[cls] * 4 * 4), 256, 0, s>>>(sd, t, part, ws);
     }
     const dim3 grid((unsigned)h.batch, (unsigned)h.max_nleft);
     if (dtype == HOS_F64)

@@ -349,31 +349,30 @@ k_c4_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
 }
 
 // Sum the S chunk-range partials of one (pair block, column block) in a fixed
-// order and scatter to m4tab[p][c] (scaled sums, c <= b only).
+// order and scatter to m4tab[p][c] (scaled sums, c <= b only).  One thread
+// per element: blockIdx.x = (pair block, column block, quarter).
 __global__ void __launch_bounds__(256)
 k_c4_reduce(const double *__restrict__ part, int M, int P, int RB, int NCB, int S,
             double *__restrict__ m4tab)
 {
-    const int rb = blockIdx.x / NCB, cb = blockIdx.x % NCB;
+    const int q = blockIdx.x & 3;
+    const int rb = (blockIdx.x >> 2) / NCB, cb = (blockIdx.x >> 2) % NCB;
     int al, bl;
     pair_ab(M, (rb * 32 + 31 < P ? rb * 32 + 31 : P - 1), al, bl);
     if (cb > bl / 32)
         return;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int e = threadIdx.x + 256 * k;
-        double sum = 0.0;
-        for (int s = 0; s < S; ++s)
-            sum += part[(((int64_t)s * RB + rb) * NCB + cb) * 1024 + e];
-        const int v = e >> 6, lane = e & 63;
-        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), col = lane & 31;
-        const int p = rb * 32 + row, c = cb * 32 + col;
-        if (p < P) {
-            int a, b;
-            pair_ab(M, p, a, b);
-            if (c <= b)
-                m4tab[(int64_t)p * (M + 1) + c] = sum;
-        }
+    const int e = threadIdx.x + 256 * q;
+    double sum = 0.0;
+    for (int s = 0; s < S; ++s)
+        sum += part[(((int64_t)s * RB + rb) * NCB + cb) * 1024 + e];
+    const int v = e >> 6, lane = e & 63;
+    const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), col = lane & 31;
+    const int p = rb * 32 + row, c = cb * 32 + col;
+    if (p < P) {
+        int a, b;
+        pair_ab(M, p, a, b);
+        if (c <= b)
+            m4tab[(int64_t)p * (M + 1) + c] = sum;
     }
 }
 
@@ -542,7 +541,7 @@ hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s)
 
 hipError_t launch_c4_reduce(const void *x, int dtype, const C4Plan &p, char *ws, hipStream_t s)
 {
-    k_c4_reduce<<<p.RB * p.NCB, 256, 0, s>>>((const double *)(ws + p.off_part), p.M, p.P, p.RB,
+    k_c4_reduce<<<p.RB * p.NCB * 4, 256, 0, s>>>((const double *)(ws + p.off_part), p.M, p.P, p.RB,
                                             p.NCB, p.S, (double *)(ws + p.off_m4));
     const double *stats = (const double *)(ws + p.off_stats);
     double *dpart = (double *)(ws + p.off_c2part);
