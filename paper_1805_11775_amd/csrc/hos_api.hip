@@ -45,11 +45,14 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     g.G = (int32_t)G;
     p.smax = g.TR > 0 ? sk_max_segments(g) : 0;
     p.npad = ((C * KC + (int64_t)g.TR * p.TS + 64) + 63) / 64 * 64;
-    // leftover diagonal sums: one pass over x in up to 256 sample ranges
+    // leftover diagonal sums: one pass over x in 1024-sample blocks
     // (k_diag_fused) when nleft <= 32, else nleft x 64 strided blocks
-    int64_t db = n / 4096;
-    const int64_t dbmax = p.nleft <= 32 ? 256 : 64;
-    p.dot_blocks = (int32_t)(db < 1 ? 1 : (db > dbmax ? dbmax : db));
+    if (p.nleft <= 32) {
+        p.dot_blocks = (int32_t)((n + 1023) / 1024);
+    } else {
+        const int64_t db = n / 4096;
+        p.dot_blocks = (int32_t)(db < 1 ? 1 : (db > 64 ? 64 : db));
+    }
 
     size_t o = 0;
     p.off_stats = o;  o = align256(o + 64 * sizeof(double));
@@ -63,6 +66,8 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     if (M > 0) {
         p.off_part = o;
         o = align256(o + (size_t)g.G * p.smax * tile_elems(p.NB) * sizeof(double));
+        p.off_tfirst = o;
+        o = align256(o + (size_t)g.G * sizeof(int64_t));
     }
     p.off_cfull = o;  o = align256(o + (size_t)(M + 1) * (M + 1) * sizeof(double));
     p.off_dpart = o;  o = align256(o + (size_t)p.nleft * p.dot_blocks * sizeof(double));

@@ -163,7 +163,7 @@ struct C3Plan : SeriesPlan {
     int32_t dot_blocks;// workgroups per leftover sum
     int64_t smax;      // partial slots per workgroup
     SkGeom sk;
-    size_t off_part, off_cfull, off_dpart, off_twid, total;
+    size_t off_part, off_tfirst, off_cfull, off_dpart, off_twid, total;
 };
 
 // Trispectrum plan.  The lag pairs (a, b), 0 <= b <= a <= M, are numbered

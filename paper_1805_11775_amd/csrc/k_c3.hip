@@ -583,13 +583,27 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
     }
 }
 
+// tfirst[w] = the tile of workgroup w's first chunk (its slot 0), or -1 for
+// a workgroup with no chunk: the same walk the contraction does at its start.
+__global__ void __launch_bounds__(256)
+k_sk_tfirst(SkGeom g, int64_t *__restrict__ tfirst)
+{
+    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (w >= g.G)
+        return;
+    SkPos q;
+    const int64_t S0 = sk_wg_start(g, w), S1 = sk_wg_start(g, w + 1);
+    tfirst[w] = (sk_first_chunk(g, S0, q) && sk_chunk_start(g, q.R, q.Cc, q.c) < S1)
+                    ? sk_tile_index(q.R, q.Cc) : -1;
+}
+
 // Sum the FP64 partial tiles of every workgroup that touched the tile, in
 // workgroup order, and scatter the 32 x 32 block to Cfull[a][b] (a = r + 1).
 // One workgroup per (tile, 32-block).
 template <int NB>
 __global__ void __launch_bounds__(256)
-k_c3_reduce(const double *__restrict__ part, SkGeom g, int64_t smax, int NBR, int M,
-            double *__restrict__ cfull)
+k_c3_reduce(const double *__restrict__ part, const int64_t *__restrict__ tfirst, SkGeom g,
+            int64_t smax, int NBR, int M, double *__restrict__ cfull)
 {
     constexpr int64_t TILE = (int64_t)(32 * NB) * (32 * NB);
     // blockIdx.x = (tile, 32-block, quarter of the block's 1024 elements)
@@ -609,9 +623,7 @@ k_c3_reduce(const double *__restrict__ part, SkGeom g, int64_t smax, int NBR, in
     const int64_t w_hi = sk_owner(g, sk_chunk_start(g, R, Cc, g.C - 1));
     double sum = 0.0;
     for (int64_t w = w_lo; w <= w_hi; ++w) {
-        SkPos p;
-        sk_first_chunk(g, sk_wg_start(g, w), p);
-        const int64_t slot = w * smax + (t - sk_tile_index(p.R, p.Cc));
+        const int64_t slot = w * smax + (t - tfirst[w]);
         sum += part[slot * TILE + (int64_t)blk * 1024 + e];
     }
     const int v = e >> 6, lane = e & 63;
@@ -653,68 +665,83 @@ k_diag_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats,
 }
 
 // The same sums for nleft <= DIAG_FUSED_MAX leftovers in one pass over x:
-// workgroup b takes the samples [b L, (b+1) L), stages x~ (FP64) for 1024
-// samples plus the 32 (nleft-1) halo in LDS, and each thread accumulates every
-// leftover's products for its samples.  dpart[left * nblocks + b].
+// workgroup b stages x~ (FP64) for the samples [1024 b, 1024 (b+1)) plus the
+// 32 (nleft-1) halo in LDS; each thread accumulates every leftover's
+// products for its 4 samples; waves reduce by lane shuffles, then the 4 wave
+// sums are added in order.  dpart[left * nblocks + b].
 constexpr int DIAG_FUSED_MAX = 32;
 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_diag_fused(const T *__restrict__ x, int64_t n, const double *__restrict__ stats, int nleft,
-             int64_t L, double *__restrict__ dpart)
+             double *__restrict__ dpart)
 {
     __shared__ double sx[1024 + 32 * (DIAG_FUSED_MAX - 1)];
-    __shared__ double red[256];
+    __shared__ double wsum[4][DIAG_FUSED_MAX];
     const double mu = stats[0], sc = stats[1];
-    const int64_t b0 = (int64_t)blockIdx.x * L, b1 = b0 + L < n ? b0 + L : n;
+    const int64_t i0 = (int64_t)blockIdx.x * 1024;
     const int halo = 32 * (nleft - 1);
+    for (int e = threadIdx.x; e < 1024 + halo; e += 256) {
+        const int64_t i = i0 + e;
+        sx[e] = i < n ? ((double)x[i] - mu) * sc : 0.0;
+    }
+    __syncthreads();
     double acc[DIAG_FUSED_MAX];
 #pragma unroll
     for (int k = 0; k < DIAG_FUSED_MAX; ++k)
         acc[k] = 0.0;
-    for (int64_t i0 = b0; i0 < b1; i0 += 1024) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < 1024 + halo; e += 256) {
-            const int64_t i = i0 + e;
-            sx[e] = i < n ? ((double)x[i] - mu) * sc : 0.0;
-        }
-        __syncthreads();
-        for (int j = threadIdx.x; j < 1024 && i0 + j < b1; j += 256) {
-            const double xi = sx[j];
 #pragma unroll
-            for (int k = 0; k < DIAG_FUSED_MAX; ++k)
-                if (k < nleft) {
-                    const double u = sx[j + 32 * k];
-                    acc[k] += xi * u * u;
-                }
+    for (int q = 0; q < 4; ++q) {
+        const int j = threadIdx.x + 256 * q;
+        const double xi = sx[j];
+#pragma unroll
+        for (int k = 0; k < DIAG_FUSED_MAX; ++k)
+            if (k < nleft) {
+                const double u = sx[j + 32 * k];
+                acc[k] += xi * u * u;
+            }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < DIAG_FUSED_MAX; ++k) {
+        if (k < nleft) {
+            double v = acc[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+                v += __shfl_xor(v, off, 64);
+            if (lane == 0)
+                wsum[wv][k] = v;
         }
     }
-    for (int k = 0; k < nleft; ++k) {
-        __syncthreads();
-        red[threadIdx.x] = acc[k];
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w)
-                red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0)
-            dpart[k * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+    if (threadIdx.x < nleft) {
+        const int k = threadIdx.x;
+        dpart[k * gridDim.x + blockIdx.x] = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
     }
 }
 
-__global__ void __launch_bounds__(64)
+// C[a][a] = the leftover's block partials summed in block order (strided over
+// 256 threads, then a fixed tree).  One workgroup per leftover.
+__global__ void __launch_bounds__(256)
 k_diag_final(const double *__restrict__ dpart, int nleft, int nblocks, int M,
              double *__restrict__ cfull)
 {
-    const int left = blockIdx.x * 64 + threadIdx.x;
-    if (left >= nleft)
-        return;
+    __shared__ double red[256];
+    const int left = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b)
+    for (int b = threadIdx.x; b < nblocks; b += 256)
         s += dpart[left * nblocks + b];
-    const int64_t a = 32 * (int64_t)left;
-    cfull[a * (M + 1) + a] = s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t a = 32 * (int64_t)left;
+        cfull[a * (M + 1) + a] = red[0];
+    }
 }
 
 // ------------------------------------------------------------------ batches
@@ -978,14 +1005,13 @@ hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws, 
 {
     const double *stats = (const double *)(ws + p.off_stats);
     double *dpart = (double *)(ws + p.off_dpart);
-    if (p.nleft <= DIAG_FUSED_MAX) {
-        const int64_t L = (p.n + p.dot_blocks - 1) / p.dot_blocks;
+    if (p.nleft <= DIAG_FUSED_MAX) {   // the plan made dot_blocks = ceil(n / 1024)
         if (dtype == HOS_F64)
             k_diag_fused<double><<<p.dot_blocks, 256, 0, s>>>((const double *)x, p.n, stats,
-                                                              p.nleft, L, dpart);
+                                                              p.nleft, dpart);
         else
             k_diag_fused<float><<<p.dot_blocks, 256, 0, s>>>((const float *)x, p.n, stats,
-                                                             p.nleft, L, dpart);
+                                                             p.nleft, dpart);
         return hipGetLastError();
     }
     const int grid = p.nleft * p.dot_blocks;
@@ -1002,15 +1028,18 @@ hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s)
     if (p.M > 0) {
         const int64_t ntiles = (int64_t)p.sk.TR * (p.sk.TR + 1) / 2;
         const int NB = p.NB;
+        k_sk_tfirst<<<(p.sk.G + 255) / 256, 256, 0, s>>>(p.sk, (int64_t *)(ws + p.off_tfirst));
         if (NB == 4)
-            k_c3_reduce<4><<<ntiles * NB * NB * 4, 256, 0, s>>>((const double *)(ws + p.off_part),
-                                                          p.sk, p.smax, p.NBR, p.M, cfull);
+            k_c3_reduce<4><<<ntiles * NB * NB * 4, 256, 0, s>>>(
+                (const double *)(ws + p.off_part), (const int64_t *)(ws + p.off_tfirst), p.sk,
+                p.smax, p.NBR, p.M, cfull);
         else
-            k_c3_reduce<2><<<ntiles * NB * NB * 4, 256, 0, s>>>((const double *)(ws + p.off_part),
-                                                          p.sk, p.smax, p.NBR, p.M, cfull);
+            k_c3_reduce<2><<<ntiles * NB * NB * 4, 256, 0, s>>>(
+                (const double *)(ws + p.off_part), (const int64_t *)(ws + p.off_tfirst), p.sk,
+                p.smax, p.NBR, p.M, cfull);
     }
-    k_diag_final<<<(p.nleft + 63) / 64, 64, 0, s>>>((const double *)(ws + p.off_dpart),
-                                                   p.nleft, p.dot_blocks, p.M, cfull);
+    k_diag_final<<<p.nleft, 256, 0, s>>>((const double *)(ws + p.off_dpart), p.nleft,
+                                        p.dot_blocks, p.M, cfull);
     return hipGetLastError();
 }
 
