@@ -149,7 +149,8 @@ int hos_bispectrum(const void *x, int32_t dtype, int64_t n, int32_t M,
  * WAITS for the stream, and writes the elapsed milliseconds to stage_ms
  * (host, 8 floats): [0] mean/range pass, [1] operand preparation,
  * [2] contraction, [3] leftover diagonal sums, [4] partial reduction,
- * [5] mirror + window (+ twiddles), [6] DFT, [7] total.  Creates and
+ * [5] mirror, window and the DFT along k2 (+ twiddles), [6] the DFT along
+ * k1, [7] total.  Creates and
  * destroys its own events (no device memory is allocated).
  */
 int hos_bispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M,
@@ -207,7 +208,8 @@ int hos_trispectrum(const void *x, int32_t dtype, int64_t n, int32_t M,
  * for the stream and writes 7 floats of milliseconds to stage_ms (host):
  * [0] mean/range pass, [1] operand preparation, [2] contraction,
  * [3] partial reduction + second-order moments, [4] cumulant assembly,
- * window and fold (+ twiddles), [5] DFT, [6] total.
+ * window, fold and the DFT along k3 (+ twiddles), [5] the DFTs along k2 and
+ * k1, [6] total.
  */
 int hos_trispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M,
                           int32_t window, int32_t nfft, int32_t path, uint32_t flags,

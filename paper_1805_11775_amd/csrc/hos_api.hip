@@ -281,7 +281,7 @@ static int bispectrum_impl(const void *x, int32_t dtype, int64_t n, int32_t M,
     if (e == hipSuccess && B) e = launch_twiddles(tw, nfft, stream);
     if (e == hipSuccess) e = launch_c3_finish(p, window, nfft, c3, B, w, stream);
     if (e == hipSuccess) e = mark(6);
-    if (e == hipSuccess && B) e = launch_fft2(B, nfft, tw, stream);
+    if (e == hipSuccess && B) e = launch_fft_cols(B, nfft, tw, stream);
     if (e == hipSuccess) e = mark(7);
     return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
 }
@@ -380,7 +380,7 @@ static int trispectrum_impl(const void *x, int32_t dtype, int64_t n, int32_t M,
     if (e == hipSuccess && T) e = launch_twiddles(tw, nfft, stream);
     if (e == hipSuccess) e = launch_c4_finish(p, window, nfft, c4, T, w, stream);
     if (e == hipSuccess) e = mark(5);
-    if (e == hipSuccess && T) e = launch_fft3(T, nfft, tw, stream);
+    if (e == hipSuccess && T) e = launch_fft3_tail(T, nfft, tw, stream);
     if (e == hipSuccess) e = mark(6);
     return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
 }

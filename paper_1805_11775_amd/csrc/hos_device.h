@@ -44,6 +44,43 @@ __device__ inline double c3_from_table(const double *__restrict__ cfull, int M, 
     return cfull[(int64_t)a * (M + 1) + b] / norm;
 }
 
+// Fourth-order table helpers.  The lag pairs (a, b), 0 <= b <= a <= M, are
+// numbered with b ascending, then a; pair_offset(M, b) is the first pair with
+// second lag b.
+__host__ __device__ inline int pair_offset(int M, int b)
+{
+    return b * (M + 1) - b * (b - 1) / 2;
+}
+
+__device__ inline void sort4(int *v)
+{
+#define SW(i, j)                 \
+    if (v[i] > v[j]) {           \
+        const int t_ = v[i];     \
+        v[i] = v[j];             \
+        v[j] = t_;               \
+    }
+    SW(0, 1) SW(2, 3) SW(0, 2) SW(1, 3) SW(1, 2)
+#undef SW
+}
+
+// c4(t1,t2,t3), 0 outside {span <= M}.  Evaluated at the orbit's canonical
+// member (c, b, a) -- the sorted offsets shifted to start at 0 -- so every
+// member of an orbit gets the bitwise same value.
+__device__ inline double c4_at(const double *__restrict__ m4tab, const double *__restrict__ c2,
+                               int M, double norm4, int t1, int t2, int t3)
+{
+    int v[4] = {0, t1, t2, t3};
+    sort4(v);
+    const int a = v[3] - v[0];
+    if (a > M)
+        return 0.0;
+    const int b = v[2] - v[0], c = v[1] - v[0];
+    const int p = pair_offset(M, b) + (a - b);
+    const double m4 = m4tab[(int64_t)p * (M + 1) + c] / norm4;
+    return m4 - c2[c] * c2[a - b] - c2[b] * c2[a - c] - c2[a] * c2[b - c];
+}
+
 // SplitMix64 output function (Steele, Lea and Flood, "Fast splittable
 // pseudorandom number generators", OOPSLA 2014): a counter-based mix of z.
 __device__ inline uint64_t splitmix64(uint64_t z)

@@ -275,8 +275,12 @@ hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3,
                             double *B, char *ws, hipStream_t s);
 bool fft_size_ok(int N);
 hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s);
-hipError_t launch_fft2(double *B, int N, const double2 *tw, hipStream_t s);
-hipError_t launch_fft3(double *T, int N, const double2 *tw, hipStream_t s);
+hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int N, int window,
+                            const double2 *tw, double *B, hipStream_t s);
+hipError_t launch_fft_cols(double *B, int N, const double2 *tw, hipStream_t s);
+hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double *stats, int M,
+                            int N, int window, const double2 *tw, double *T, hipStream_t s);
+hipError_t launch_fft3_tail(double *T, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s);
 hipError_t launch_fft2_batch(double *grids, int N, int count, const double2 *tw, hipStream_t s);
 hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window, char *ws,

@@ -41,12 +41,6 @@ __device__ inline void unpack8(float4 a, float4 b, float *v)
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
-// First pair index with second lag b (pairs ordered by b, then a).
-__host__ __device__ inline int pair_offset(int M, int b)
-{
-    return b * (M + 1) - b * (b - 1) / 2;
-}
-
 // (a, b) of pair p; M + 1 - b pairs share each b.
 __device__ inline void pair_ab(int M, int p, int &a, int &b)
 {
@@ -415,35 +409,6 @@ k_c2_final(const double *__restrict__ dpart, int M, int nblocks, const double *_
     c2[d] = s / ((double)n * sc * sc);
 }
 
-__device__ inline void sort4(int *v)
-{
-#define SW(i, j)                 \
-    if (v[i] > v[j]) {           \
-        const int t_ = v[i];     \
-        v[i] = v[j];             \
-        v[j] = t_;               \
-    }
-    SW(0, 1) SW(2, 3) SW(0, 2) SW(1, 3) SW(1, 2)
-#undef SW
-}
-
-// c4(t1,t2,t3), 0 outside {span <= M}.  Evaluated at the orbit's canonical
-// member (c, b, a) -- the sorted offsets shifted to start at 0 -- so every
-// member of an orbit gets the bitwise same value.
-__device__ inline double c4_at(const double *__restrict__ m4tab, const double *__restrict__ c2,
-                               int M, double norm4, int t1, int t2, int t3)
-{
-    int v[4] = {0, t1, t2, t3};
-    sort4(v);
-    const int a = v[3] - v[0];
-    if (a > M)
-        return 0.0;
-    const int b = v[2] - v[0], c = v[1] - v[0];
-    const int p = pair_offset(M, b) + (a - b);
-    const double m4 = m4tab[(int64_t)p * (M + 1) + c] / norm4;
-    return m4 - c2[c] * c2[a - b] - c2[b] * c2[a - c] - c2[a] * c2[b - c];
-}
-
 __global__ void __launch_bounds__(256)
 k_c4_out(const double *__restrict__ m4tab, const double *__restrict__ c2,
          const double *__restrict__ stats, int M, double *__restrict__ out)
@@ -457,40 +422,6 @@ k_c4_out(const double *__restrict__ m4tab, const double *__restrict__ c2,
     const int t2 = (int)((idx / side) % side) - M;
     const int t1 = (int)(idx / ((int64_t)side * side)) - M;
     out[idx] = c4_at(m4tab, c2, M, stats[4], t1, t2, t3);
-}
-
-// DFT input on the N^3 grid: sum over lags congruent to m (mod N) of W4 c4.
-__global__ void __launch_bounds__(256)
-k_fft_input3(const double *__restrict__ m4tab, const double *__restrict__ c2,
-             const double *__restrict__ stats, int M, int N, int window,
-             double2 *__restrict__ T)
-{
-    const int64_t tot = (int64_t)N * N * N;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= tot)
-        return;
-    const int m3 = (int)(idx % N), m2 = (int)((idx / N) % N), m1 = (int)(idx / ((int64_t)N * N));
-    const double norm4 = stats[4];
-    double sum = 0.0;
-    for (int t1 = m1 - N; t1 <= m1; t1 += N) {
-        if (t1 < -M || t1 > M)
-            continue;
-        for (int t2 = m2 - N; t2 <= m2; t2 += N) {
-            if (t2 < -M || t2 > M)
-                continue;
-            for (int t3 = m3 - N; t3 <= m3; t3 += N) {
-                if (t3 < -M || t3 > M)
-                    continue;
-                const double c = c4_at(m4tab, c2, M, norm4, t1, t2, t3);
-                double w = 1.0;
-                if (window == HOS_WIN_PARZEN)
-                    w = parzen_d(t1, M) * parzen_d(t2, M) * parzen_d(t3, M) *
-                        parzen_d(t2 - t1, M) * parzen_d(t3 - t1, M) * parzen_d(t3 - t2, M);
-                sum += w * c;
-            }
-        }
-    }
-    T[idx] = make_double2(sum, 0.0);
 }
 
 template <int PATH, int WX>
@@ -565,10 +496,11 @@ hipError_t launch_c4_finish(const C4Plan &p, int window, int nfft, double *c4, d
         const int64_t side = 2 * p.M + 1, tot = side * side * side;
         k_c4_out<<<(tot + 255) / 256, 256, 0, s>>>(m4, c2, stats, p.M, c4);
     }
-    if (T) {
-        const int64_t tot = (int64_t)nfft * nfft * nfft;
-        k_fft_input3<<<(tot + 255) / 256, 256, 0, s>>>(m4, c2, stats, p.M, nfft, window,
-                                                      (double2 *)T);
+    if (T) {   // fold + window + the m3 transforms (k_fft.hip); k2 and k1 follow
+        hipError_t e = launch_tri_lines(m4, c2, stats, p.M, nfft, window,
+                                        (const double2 *)(ws + p.off_twid), T, s);
+        if (e != hipSuccess)
+            return e;
     }
     return hipGetLastError();
 }

@@ -218,27 +218,6 @@ hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s)
     return hipGetLastError();
 }
 
-// In-place 2D DFT of an N x N row-major complex array: rows, then columns.
-hipError_t launch_fft2(double *B, int N, const double2 *tw, hipStream_t s)
-{
-    double2 *d = (double2 *)B;
-    const FftRadices fr = factor(N);
-    fft_axis(d, tw, fr, N, 1, 1, 0, N, s);   // along k2 (contiguous)
-    fft_axis(d, tw, fr, N, N, N, 1, 0, s);   // along k1
-    return hipGetLastError();
-}
-
-// In-place 3D DFT of an N^3 row-major complex array, one axis at a time.
-hipError_t launch_fft3(double *T, int N, const double2 *tw, hipStream_t s)
-{
-    double2 *d = (double2 *)T;
-    const FftRadices fr = factor(N);
-    const int64_t N2 = (int64_t)N * N;
-    fft_axis(d, tw, fr, N2, 1, 1, 0, N, s);      // axis 2
-    fft_axis(d, tw, fr, N2, N, N, 1, N2, s);     // axis 1
-    fft_axis(d, tw, fr, N2, N2, N2, 1, 0, s);    // axis 0
-    return hipGetLastError();
-}
 
 }  // namespace hos
 
@@ -383,6 +362,117 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
     }
 }
 
+
+// The full N x N spectrum of one series: fold + window into LDS, row DFTs with
+// two real rows per complex sequence (as k_pd_rows), every k2 written to B;
+// the column pass then runs in place (launch_fft_cols).
+template <int ELEMS>
+__global__ void __launch_bounds__(FFT_THREADS)
+k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, int M,
+            const double2 *__restrict__ tw, FftRadices fr, int CBP, int window,
+            double2 *__restrict__ B)
+{
+    __shared__ double2 sm[ELEMS];
+    __shared__ double dwin[FFT_LDS_ELEMS / 2 + 1];
+    const int N = fr.n;
+    const double norm = stats[3];
+    const bool pz = window == HOS_WIN_PARZEN;
+    for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
+        dwin[m] = pz ? parzen_d(m, M) : 1.0;
+    __syncthreads();
+    auto fold = [&](int m1, int m2) {
+        double sum = 0.0;
+        if (m1 < N) {
+            for (int w1 = m1 - N; w1 <= m1; w1 += N) {
+                if (w1 < -M || w1 > M)
+                    continue;
+                for (int w2 = m2 - N; w2 <= m2; w2 += N) {
+                    const int dw = w1 - w2;
+                    if (w2 < -M || w2 > M || dw < -M || dw > M)
+                        continue;
+                    sum += dwin[abs(w1)] * dwin[abs(w2)] * dwin[abs(dw)] *
+                           c3_from_table(cfull, M, norm, w1, w2);
+                }
+            }
+        }
+        return sum;
+    };
+    const int m1_0 = blockIdx.x * 2 * CBP;
+    for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
+        const int p = e / N, m2 = e - p * N, m1 = m1_0 + 2 * p;
+        sm[e] = make_double2(fold(m1, m2), fold(m1 + 1, m2));
+    }
+    __syncthreads();
+    fft_lds(sm, tw, fr, CBP);
+    for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
+        const int p = e / N, k = e - p * N, m1 = m1_0 + 2 * p;
+        const double2 z = sm[p * N + k], zc = sm[p * N + (k == 0 ? 0 : N - k)];
+        if (m1 < N)
+            B[(int64_t)m1 * N + k] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+        if (m1 + 1 < N)
+            B[(int64_t)(m1 + 1) * N + k] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+    }
+}
+
+// The trispectrum's N^3 grid: fold + six-factor window of c4 into LDS for
+// lines of fixed (m1, m2) (line L = m1 N + m2), transforms along m3 with two
+// real lines per complex sequence, every k3 written to T; the k2 and k1
+// passes follow (launch_fft3_tail).
+__global__ void __launch_bounds__(FFT_THREADS)
+k_tri_lines(const double *__restrict__ m4tab, const double *__restrict__ c2,
+            const double *__restrict__ stats, int M, const double2 *__restrict__ tw,
+            FftRadices fr, int CBP, int window, double2 *__restrict__ T)
+{
+    __shared__ double2 sm[PD_LDS_ELEMS];
+    __shared__ double dwin[PD_LDS_ELEMS / 2 + 1];
+    const int N = fr.n;
+    const int64_t lines = (int64_t)N * N;
+    const double norm4 = stats[4];
+    const bool pz = window == HOS_WIN_PARZEN;
+    for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
+        dwin[m] = pz ? parzen_d(m, M) : 1.0;
+    __syncthreads();
+    auto fold = [&](int64_t L, int m3) {
+        double sum = 0.0;
+        if (L >= lines)
+            return sum;
+        const int m1 = (int)(L / N), m2 = (int)(L - (int64_t)m1 * N);
+        for (int t1 = m1 - N; t1 <= m1; t1 += N) {
+            if (t1 < -M || t1 > M)
+                continue;
+            for (int t2 = m2 - N; t2 <= m2; t2 += N) {
+                if (t2 < -M || t2 > M || abs(t2 - t1) > M)
+                    continue;
+                for (int t3 = m3 - N; t3 <= m3; t3 += N) {
+                    if (t3 < -M || t3 > M || abs(t3 - t1) > M || abs(t3 - t2) > M)
+                        continue;   // outside the span <= M support c4 is 0
+                    const double w = dwin[abs(t1)] * dwin[abs(t2)] * dwin[abs(t3)] *
+                                     dwin[abs(t2 - t1)] * dwin[abs(t3 - t1)] *
+                                     dwin[abs(t3 - t2)];
+                    sum += w * c4_at(m4tab, c2, M, norm4, t1, t2, t3);
+                }
+            }
+        }
+        return sum;
+    };
+    const int64_t L0 = (int64_t)blockIdx.x * 2 * CBP;
+    for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
+        const int p = e / N, m3 = e - p * N;
+        sm[e] = make_double2(fold(L0 + 2 * p, m3), fold(L0 + 2 * p + 1, m3));
+    }
+    __syncthreads();
+    fft_lds(sm, tw, fr, CBP);
+    for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
+        const int p = e / N, k = e - p * N;
+        const int64_t L = L0 + 2 * p;
+        const double2 z = sm[p * N + k], zc = sm[p * N + (k == 0 ? 0 : N - k)];
+        if (L < lines)
+            T[L * N + k] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+        if (L + 1 < lines)
+            T[(L + 1) * N + k] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+    }
+}
+
 }  // namespace
 
 hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window, char *ws,
@@ -412,6 +502,52 @@ hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window
             return hipErrorInvalidValue;   // N > 2048: not planned for batches
         }
     }
+    return hipGetLastError();
+}
+
+// Fold, window and row transforms of one series' N x N spectrum into B.
+hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int N, int window,
+                            const double2 *tw, double *B, hipStream_t s)
+{
+    const FftRadices fr = factor(N);
+    if (N <= PD_LDS_ELEMS) {
+        const int CBP = PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
+        k_full_rows<PD_LDS_ELEMS><<<(N + 2 * CBP - 1) / (2 * CBP), FFT_THREADS, 0, s>>>(
+            cfull, stats, M, tw, fr, CBP, window, (double2 *)B);
+    } else {
+        k_full_rows<FFT_LDS_ELEMS><<<(N + 1) / 2, FFT_THREADS, 0, s>>>(
+            cfull, stats, M, tw, fr, 1, window, (double2 *)B);
+    }
+    return hipGetLastError();
+}
+
+// In-place DFTs along k1 of an N x N row-major complex array.
+hipError_t launch_fft_cols(double *B, int N, const double2 *tw, hipStream_t s)
+{
+    fft_axis((double2 *)B, tw, factor(N), N, N, N, 1, 0, s);
+    return hipGetLastError();
+}
+
+// Fold, window and m3 transforms of the trispectrum grid into T.
+hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double *stats, int M,
+                            int N, int window, const double2 *tw, double *T, hipStream_t s)
+{
+    const FftRadices fr = factor(N);
+    const int CBP = PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
+    const int64_t lines = (int64_t)N * N;
+    k_tri_lines<<<(unsigned)((lines + 2 * CBP - 1) / (2 * CBP)), FFT_THREADS, 0, s>>>(
+        m4tab, c2, stats, M, tw, fr, CBP, window, (double2 *)T);
+    return hipGetLastError();
+}
+
+// The k2 and k1 passes of an in-place N^3 DFT whose k3 pass is done.
+hipError_t launch_fft3_tail(double *T, int N, const double2 *tw, hipStream_t s)
+{
+    double2 *d = (double2 *)T;
+    const FftRadices fr = factor(N);
+    const int64_t N2 = (int64_t)N * N;
+    fft_axis(d, tw, fr, N2, N, N, 1, N2, s);     // axis 1
+    fft_axis(d, tw, fr, N2, N2, N2, 1, 0, s);    // axis 0
     return hipGetLastError();
 }
 

@@ -12,7 +12,9 @@
 // (Algorithm DBS step 5): W3(w1,w2) = d(w1) d(w2) d(w1-w2) with the Parzen
 // d and scale L = M.  The windowed cumulant is folded onto the N x N DFT
 // grid (index w mod N; aliased lags add), which makes the grid DFT equal
-// to sum_w W3(w) c3(w) exp(-2 pi i <k,w>/N) exactly.
+// to sum_w W3(w) c3(w) exp(-2 pi i <k,w>/N) exactly; the fold happens inside
+// the row-transform kernel (k_full_rows, k_fft.hip), which never writes the
+// real grid.
 #include "hos_internal.h"
 #include "hos_device.h"
 
@@ -32,31 +34,6 @@ k_c3_out(const double *__restrict__ cfull, const double *__restrict__ stats, int
     c3[idx] = c3_from_table(cfull, M, stats[3], w1, w2);
 }
 
-// DFT input: B[m1][m2] = (sum over lags w = m mod N of W3(w) c3(w), 0).
-__global__ void __launch_bounds__(256)
-k_fft_input2(const double *__restrict__ cfull, const double *__restrict__ stats, int M, int N,
-             int window, double2 *__restrict__ B)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)N * N)
-        return;
-    const int m1 = (int)(idx / N), m2 = (int)(idx % N);
-    const double norm = stats[3];
-    double sum = 0.0;
-    // lags congruent to m mod N inside [-M, M]: m - N, m (N >= M + 1)
-    for (int w1 = m1 - N; w1 <= m1; w1 += N) {
-        if (w1 < -M || w1 > M)
-            continue;
-        for (int w2 = m2 - N; w2 <= m2; w2 += N) {
-            if (w2 < -M || w2 > M)
-                continue;
-            sum += window3(w1, w2, M, window == HOS_WIN_PARZEN) *
-                   c3_from_table(cfull, M, norm, w1, w2);
-        }
-    }
-    B[idx] = make_double2(sum, 0.0);
-}
-
 }  // namespace
 
 hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3, double *B,
@@ -68,10 +45,11 @@ hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3, d
         const int64_t tot = (int64_t)(2 * p.M + 1) * (2 * p.M + 1);
         k_c3_out<<<(tot + 255) / 256, 256, 0, s>>>(cfull, stats, p.M, c3);
     }
-    if (B) {
-        const int64_t tot = (int64_t)nfft * nfft;
-        k_fft_input2<<<(tot + 255) / 256, 256, 0, s>>>(cfull, stats, p.M, nfft, window,
-                                                       (double2 *)B);
+    if (B) {   // fold + window + row transforms (k_fft.hip); the columns follow
+        hipError_t e = launch_full_rows(cfull, stats, p.M, nfft, window,
+                                        (const double2 *)(ws + p.off_twid), B, s);
+        if (e != hipSuccess)
+            return e;
     }
     return hipGetLastError();
 }
