@@ -79,8 +79,13 @@ typedef enum hos_dtype { HOS_F32 = 0, HOS_F64 = 1 } hos_dtype;
  * domain instead.  HOS_WIN_PARZEN uses the Parzen window d(m) with scale
  * L = M: W3(w1,w2) = d(w1) d(w2) d(w1-w2) for the bispectrum and the
  * product of d over the six pairwise differences of {0,t1,t2,t3} for the
- * trispectrum. */
-typedef enum hos_window { HOS_WIN_NONE = 0, HOS_WIN_PARZEN = 1 } hos_window;
+ * trispectrum.  HOS_WIN_PARZEN_SEPARABLE is the product over the lags only
+ * (the alternative reading): d(w1) d(w2), resp. d(t1) d(t2) d(t3). */
+typedef enum hos_window {
+    HOS_WIN_NONE = 0,
+    HOS_WIN_PARZEN = 1,
+    HOS_WIN_PARZEN_SEPARABLE = 2   /* d(w1) d(w2); trispectrum d(t1) d(t2) d(t3) */
+} hos_window;
 
 /* Arithmetic of the cumulant contraction.  Moments, scaling, cross-tile
  * reductions, windows and DFTs are FP64 on every path.
@@ -129,7 +134,7 @@ int hos_bispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
  *   M        maximum lag, 0 <= M < n.
  *   window   hos_window.
  *   nfft     DFT size per axis, 2 <= nfft <= 4096, nfft = 2^a 3^b 5^c;
- *            nfft >= 2M with HOS_WIN_PARZEN (the window vanishes at |w| = M),
+ *            nfft >= 2M with either Parzen window (it vanishes at |w| = M),
  *            nfft >= 2M+1 with HOS_WIN_NONE; ignored when B is NULL.
  *   path     hos_path.
  *   c3       device, (2M+1)^2 float64 (layout above), or NULL.

@@ -211,21 +211,27 @@ def parzen(m, L: int) -> np.ndarray:
 
 
 def window3(M: int, kind: str = "parzen") -> np.ndarray:
-    """W3(w1,w2) = d(w1) d(w2) d(w1-w2) over the square, scale L = M."""
+    """W3(w1,w2) = d(w1) d(w2) d(w1-w2) over the square, scale L = M;
+    kind "separable": d(w1) d(w2); "none": 1."""
     w = np.arange(-M, M + 1)
     w1, w2 = np.meshgrid(w, w, indexing="ij")
     if kind == "none":
         return np.ones_like(w1, dtype=np.float64)
+    if kind == "separable":
+        return parzen(w1, M) * parzen(w2, M)
     return parzen(w1, M) * parzen(w2, M) * parzen(w1 - w2, M)
 
 
 def window4(M: int, kind: str = "parzen") -> np.ndarray:
-    """Product of d over the six pairwise differences of {0,t1,t2,t3}."""
+    """Product of d over the six pairwise differences of {0,t1,t2,t3};
+    kind "separable": d(t1) d(t2) d(t3); "none": 1."""
     t = np.arange(-M, M + 1)
     t1, t2, t3 = np.meshgrid(t, t, t, indexing="ij")
     if kind == "none":
         return np.ones_like(t1, dtype=np.float64)
     d = lambda m: parzen(m, M)
+    if kind == "separable":
+        return d(t1) * d(t2) * d(t3)
     return d(t1) * d(t2) * d(t3) * d(t2 - t1) * d(t3 - t1) * d(t3 - t2)
 
 

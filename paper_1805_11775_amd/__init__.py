@@ -35,6 +35,7 @@ HOS_F32 = 0
 HOS_F64 = 1
 HOS_WIN_NONE = 0
 HOS_WIN_PARZEN = 1
+HOS_WIN_PARZEN_SEPARABLE = 2
 HOS_PATH_FP32 = 0
 HOS_PATH_SPLIT_FP16 = 1
 HOS_PATH_SPLIT_BF16 = 2
@@ -43,7 +44,8 @@ HOS_PLAN_ADJOINT = 16
 
 PATHS = {"fp32": HOS_PATH_FP32, "split_fp16": HOS_PATH_SPLIT_FP16,
          "split_bf16": HOS_PATH_SPLIT_BF16}
-WINDOWS = {"none": HOS_WIN_NONE, "parzen": HOS_WIN_PARZEN}
+WINDOWS = {"none": HOS_WIN_NONE, "parzen": HOS_WIN_PARZEN,
+           "separable": HOS_WIN_PARZEN_SEPARABLE}
 
 
 class HosError(RuntimeError):
@@ -231,7 +233,7 @@ def _next_fft_size(m: int) -> int:
 
 
 def default_nfft(M: int, window: str = "parzen") -> int:
-    need = 2 * M if window == "parzen" else 2 * M + 1
+    need = 2 * M if window != "none" else 2 * M + 1
     return _next_fft_size(max(need, 2))
 
 

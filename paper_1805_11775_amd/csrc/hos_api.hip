@@ -138,14 +138,14 @@ static int check_bispectrum_args(int64_t n, int32_t M, int32_t window, int32_t n
         return HOS_EINVAL;
     if (path != HOS_PATH_FP32 && path != HOS_PATH_SPLIT_FP16 && path != HOS_PATH_SPLIT_BF16)
         return HOS_EINVAL;
-    if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN)
+    if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN && window != HOS_WIN_PARZEN_SEPARABLE)
         return HOS_EINVAL;
     if (flags & ~HOS_NO_CENTER)
         return HOS_EINVAL;
     if (want_B) {
         if (!fft_size_ok(nfft))
             return HOS_EINVAL;
-        const int64_t need = window == HOS_WIN_PARZEN ? 2 * (int64_t)M : 2 * (int64_t)M + 1;
+        const int64_t need = window != HOS_WIN_NONE ? 2 * (int64_t)M : 2 * (int64_t)M + 1;
         if (nfft < need || nfft < 2)
             return HOS_EINVAL;
     } else if (nfft < 0) {

@@ -60,7 +60,7 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         return HOS_EINVAL;
     if (path != HOS_PATH_FP32 && path != HOS_PATH_SPLIT_FP16 && path != HOS_PATH_SPLIT_BF16)
         return HOS_EINVAL;
-    if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN)
+    if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN && window != HOS_WIN_PARZEN_SEPARABLE)
         return HOS_EINVAL;
     if (flags & ~(HOS_NO_CENTER | HOS_PLAN_ADJOINT))
         return HOS_EINVAL;
@@ -104,7 +104,7 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         xo += n[s];
         d.c3_off = c3o;
         c3o += (int64_t)(2 * d.M + 1) * (2 * d.M + 1);
-        d.N = next_fft(window == HOS_WIN_PARZEN ? 2 * d.M : 2 * d.M + 1);
+        d.N = next_fft(window != HOS_WIN_NONE ? 2 * d.M : 2 * d.M + 1);
         if (d.N > 2048)
             return HOS_EINVAL;   // principal-domain DFTs stage 2048-point sequences
         d.npd = pd_count(d.N);

@@ -24,10 +24,14 @@ __device__ inline double parzen_d(int m, int L)
     return 0.0;
 }
 
-// W3(w1, w2) = d(w1) d(w2) d(w1 - w2) (Parzen) or 1 (no window).
-__device__ inline double window3(int w1, int w2, int M, bool parzen)
+// W3(w1, w2) = d(w1) d(w2) d(w1 - w2) (Parzen), d(w1) d(w2) (separable
+// Parzen) or 1 (no window); `window` is an hos_window.
+__device__ inline double window3(int w1, int w2, int M, int window)
 {
-    return parzen ? parzen_d(w1, M) * parzen_d(w2, M) * parzen_d(w1 - w2, M) : 1.0;
+    if (window == HOS_WIN_NONE)
+        return 1.0;
+    const double s = parzen_d(w1, M) * parzen_d(w2, M);
+    return window == HOS_WIN_PARZEN ? s * parzen_d(w1 - w2, M) : s;
 }
 
 // c3(w1, w2) from the fundamental-region table C[a][b] (row stride M + 1):

@@ -67,13 +67,13 @@ k_adj_resid(const SeriesDesc *__restrict__ sd, const double2 *__restrict__ B_pd,
 }
 
 // G(w) from the transformed grid (0 outside the hexagon).
-__device__ inline double g_at(const double2 *__restrict__ F, int N, int M, bool parzen, int w1,
+__device__ inline double g_at(const double2 *__restrict__ F, int N, int M, int window, int w1,
                               int w2)
 {
     if (w1 < -M || w1 > M || w2 < -M || w2 > M || w1 - w2 < -M || w1 - w2 > M)
         return 0.0;
     const int m1 = w1 < 0 ? w1 + N : w1, m2 = w2 < 0 ? w2 + N : w2;
-    return window3(w1, w2, M, parzen) * F[(int64_t)m1 * N + m2].x;
+    return window3(w1, w2, M, window) * F[(int64_t)m1 * N + m2].x;
 }
 
 // K2 in FP64 over [0, KP)^2 (u' = u + M, v' = v + M; padding is 0).
@@ -90,11 +90,10 @@ k_adj_kbuild(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int windo
     const int bu = up >> 5, bv = vp >> 5;
     if (up <= 2 * M && vp <= 2 * M && bv >= bu) {
         const double2 *F = (const double2 *)(ws + d.grid_off);
-        const bool pz = window == HOS_WIN_PARZEN;
         const int u = up - M, v = vp - M;
         auto K = [&](int a, int b) {
-            return g_at(F, d.N, M, pz, a, b) + g_at(F, d.N, M, pz, -a, b - a) +
-                   g_at(F, d.N, M, pz, b - a, -a);
+            return g_at(F, d.N, M, window, a, b) + g_at(F, d.N, M, window, -a, b - a) +
+                   g_at(F, d.N, M, window, b - a, -a);
         };
         const double ks = 0.5 * (K(u, v) + K(v, u)) / (double)d.n;
         val = bv > bu ? 2.0 * ks : ks;

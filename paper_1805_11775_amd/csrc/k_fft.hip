@@ -287,7 +287,8 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
     const char *r = ws + d.ws_off;
     const double *cfull = (const double *)(r + d.o_cfull);
     const double norm = ((const double *)(r + d.o_stats))[3];
-    const bool pz = window == HOS_WIN_PARZEN;
+    const bool pz = window != HOS_WIN_NONE;            // d on the lags
+    const bool pdiff = window == HOS_WIN_PARZEN;        // and on their differences
     for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
@@ -301,7 +302,7 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
                     const int dw = w1 - w2;
                     if (w2 < -M || w2 > M || dw < -M || dw > M)
                         continue;   // outside the hexagon c3 is 0
-                    sum += dwin[abs(w1)] * dwin[abs(w2)] * dwin[abs(dw)] *
+                    sum += dwin[abs(w1)] * dwin[abs(w2)] * (pdiff ? dwin[abs(dw)] : 1.0) *
                            c3_from_table(cfull, M, norm, w1, w2);
                 }
             }
@@ -376,7 +377,8 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
     __shared__ double dwin[FFT_LDS_ELEMS / 2 + 1];
     const int N = fr.n;
     const double norm = stats[3];
-    const bool pz = window == HOS_WIN_PARZEN;
+    const bool pz = window != HOS_WIN_NONE;            // d on the lags
+    const bool pdiff = window == HOS_WIN_PARZEN;        // and on their differences
     for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
@@ -390,7 +392,7 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
                     const int dw = w1 - w2;
                     if (w2 < -M || w2 > M || dw < -M || dw > M)
                         continue;
-                    sum += dwin[abs(w1)] * dwin[abs(w2)] * dwin[abs(dw)] *
+                    sum += dwin[abs(w1)] * dwin[abs(w2)] * (pdiff ? dwin[abs(dw)] : 1.0) *
                            c3_from_table(cfull, M, norm, w1, w2);
                 }
             }
@@ -428,7 +430,8 @@ k_tri_lines(const double *__restrict__ m4tab, const double *__restrict__ c2,
     const int N = fr.n;
     const int64_t lines = (int64_t)N * N;
     const double norm4 = stats[4];
-    const bool pz = window == HOS_WIN_PARZEN;
+    const bool pz = window != HOS_WIN_NONE;            // d on the lags
+    const bool pdiff = window == HOS_WIN_PARZEN;        // and on their differences
     for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
@@ -446,9 +449,10 @@ k_tri_lines(const double *__restrict__ m4tab, const double *__restrict__ c2,
                 for (int t3 = m3 - N; t3 <= m3; t3 += N) {
                     if (t3 < -M || t3 > M || abs(t3 - t1) > M || abs(t3 - t2) > M)
                         continue;   // outside the span <= M support c4 is 0
-                    const double w = dwin[abs(t1)] * dwin[abs(t2)] * dwin[abs(t3)] *
-                                     dwin[abs(t2 - t1)] * dwin[abs(t3 - t1)] *
-                                     dwin[abs(t3 - t2)];
+                    const double wl = dwin[abs(t1)] * dwin[abs(t2)] * dwin[abs(t3)];
+                    const double w = pdiff ? wl * dwin[abs(t2 - t1)] * dwin[abs(t3 - t1)] *
+                                                 dwin[abs(t3 - t2)]
+                                           : wl;
                     sum += w * c4_at(m4tab, c2, M, norm4, t1, t2, t3);
                 }
             }

@@ -43,7 +43,7 @@ FAKE = 0x10000  # any aligned non-null address; validation fails before use
     (dict(M=-1), hos.HOS_EINVAL),
     (dict(M=100, n=100), hos.HOS_EINVAL),
     (dict(path=3), hos.HOS_EINVAL),
-    (dict(window=2), hos.HOS_EINVAL),
+    (dict(window=3), hos.HOS_EINVAL),
     (dict(dtype=5), hos.HOS_EINVAL),
     (dict(flags=8), hos.HOS_EINVAL),
     (dict(nfft=127), hos.HOS_EINVAL),        # < 2M with Parzen
@@ -97,7 +97,7 @@ def test_schedule_covers_every_chunk_once(n, M, path):
     (dict(M=-1), hos.HOS_EINVAL),
     (dict(M=40, n=40), hos.HOS_EINVAL),
     (dict(path=3), hos.HOS_EINVAL),
-    (dict(window=2), hos.HOS_EINVAL),
+    (dict(window=3), hos.HOS_EINVAL),
     (dict(flags=2), hos.HOS_EINVAL),
     (dict(nfft=95), hos.HOS_EINVAL),          # < 2M with Parzen
     (dict(nfft=96, window=0), hos.HOS_EINVAL),  # < 2M+1 without window

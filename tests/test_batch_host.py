@@ -121,7 +121,7 @@ def test_plan_rejects_enums():
     M = np.array([10], dtype=np.int32)
     pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
     args = (1, hos._i64p(n), hos._i32p(M))
-    assert lib.hos_batch_plan_size(*args, 2, 0, 0, None, ctypes.byref(pb), ctypes.byref(wb)) == -1
+    assert lib.hos_batch_plan_size(*args, 3, 0, 0, None, ctypes.byref(pb), ctypes.byref(wb)) == -1
     assert lib.hos_batch_plan_size(*args, 1, 3, 0, None, ctypes.byref(pb), ctypes.byref(wb)) == -1
     assert lib.hos_batch_plan_size(*args, 1, 0, 4, None, ctypes.byref(pb), ctypes.byref(wb)) == -1
     assert lib.hos_batch_plan_size(*args, 1, 0, 0, None, ctypes.byref(pb), ctypes.byref(wb)) == 0

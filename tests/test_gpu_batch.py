@@ -260,3 +260,19 @@ def test_forced_tile_classes_match_oracle(tile):
         k1, k2 = oracle.pd_indices(N)
         got = c3[c3o:c3o + (2 * Ms + 1) ** 2].reshape(2 * Ms + 1, 2 * Ms + 1)
         assert _rel(got, c_ref) < 1e-5 and _rel(B[pdo:pdo + npd], B_ref[k1, k2]) < 1e-5, s
+
+
+def test_batch_separable_window():
+    hos = _hos()
+    xs, n, M = _uneven()
+    plan = hos.BatchPlan(n, M, window="separable", path="fp32")
+    x = torch.from_numpy(np.concatenate(xs)).cuda()
+    _, B = hos.bispectrum_batched(x, plan, return_c3=False)
+    torch.cuda.synchronize()
+    B = B.cpu().numpy()
+    S = plan.series()
+    for s in range(len(n)):
+        Ms, N, npd, pdo = (int(v) for v in (S[s, 1], S[s, 2], S[s, 3], S[s, 6]))
+        _, B_ref = oracle.bispectrum(xs[s], Ms, N, window="separable")
+        k1, k2 = oracle.pd_indices(N)
+        assert _rel(B[pdo:pdo + npd], B_ref[k1, k2]) < 1e-6, s

@@ -78,7 +78,7 @@ def test_gaussian_near_zero_cumulant(path):
     assert e < TOL[path]
 
 
-@pytest.mark.parametrize("window", ["none", "parzen"])
+@pytest.mark.parametrize("window", ["none", "parzen", "separable"])
 def test_window_and_nfft_variants(window):
     x = synth.iid_exp_centered(1500, 7)
     M = 20

@@ -196,3 +196,13 @@ def test_workload_sampled(path):
         ph = np.exp(-2j * np.pi * (k1 * lag[:, None, None] + k2 * lag[None, :, None] +
                                    k3 * lag[None, None, :]) / N)
         assert abs(np.sum(cw * ph) - T[k1, k2, k3]) < 1e-10 * np.max(np.abs(T))
+
+
+@pytest.mark.parametrize("path", ["fp32", "split_fp16"])
+def test_separable_window(path):
+    x, c_ref, _ = _oracle_case(1500, 20, 321, False)
+    c4, T = _run(x, 20, 40, window="separable", path=path)
+    _, T_ref = oracle.trispectrum(x, 20, 40, window="separable")
+    e = _err(T, T_ref, np.max(np.abs(T_ref)))
+    print("separable T rel err %.3e" % e)
+    assert e < TOL[path] and _err(c4, c_ref, _m4_origin(x)) < TOL[path]

@@ -411,3 +411,18 @@ def test_loss_gradient_at_indices_agrees_with_full():
     idx = np.array([0, 5, 60, 119])
     ga = oracle.loss_grad_at(x, 8, 16, target, idx)
     assert np.allclose(ga - ga[0], g[idx] - g[idx[0]], rtol=0, atol=1e-13 * np.max(np.abs(g)))
+
+
+def test_separable_window_hand_values():
+    """Separable Parzen (the product over the lags only) against hand values:
+    at L = 4, d(2) = 1 - 6/4 + 6/8 = 1/4 and d(4) = 0, so at (w1, w2) = (2, -2)
+    the separable window is 1/16 while the full one (times d(w1 - w2) = d(4))
+    is 0; at (1, 1) both are d(1)^2 (times d(0) = 1)."""
+    M = 4
+    ws, wf = oracle.window3(M, "separable"), oracle.window3(M, "parzen")
+    d1 = 1 - 6 * (1 / 4) ** 2 + 6 * (1 / 4) ** 3
+    assert ws[2 + M, -2 + M] == 0.0625 and wf[2 + M, -2 + M] == 0.0
+    assert abs(ws[1 + M, 1 + M] - d1 * d1) < 1e-15 and abs(wf[1 + M, 1 + M] - d1 * d1) < 1e-15
+    w4 = oracle.window4(M, "separable")
+    assert abs(w4[2 + M, -2 + M, 1 + M] - 0.0625 * d1) < 1e-15
+    assert oracle.window4(M, "parzen")[2 + M, -2 + M, 1 + M] == 0.0
