@@ -349,3 +349,60 @@ def loss_grad_at(x, M: int, nfft: int, target_pd, idx, window: str = "parzen") -
     _load().or_c3_grad_at(_dp(xt), xt.size, int(M), _dp(G),
                           idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.size, _dp(out))
     return out
+
+
+# --------------------------------------------------------------------------
+# The paper's direct method (Algorithm DBS), in its own step order.
+# Readings: K = floor(n / P) parts of P samples (trailing samples unused);
+# the raw bispectrum uses F(k1) F(k2) conj(F(k1+k2)) / P (the conjugate the
+# printed step 4 lacks); the M3 x M3 box takes exactly M3 offsets per axis,
+# n in [-floor(M3/2), M3 - 1 - floor(M3/2)], indices modulo P.
+# --------------------------------------------------------------------------
+def dbs_raw(part) -> np.ndarray:
+    """Steps 2-4 for one part: mean removed, P-point DFT, and the raw
+    bispectrum C(k1, k2) = F(k1) F(k2) conj(F(k1 + k2)) / P on the whole
+    P x P grid (indices modulo P)."""
+    xp = _f64(part)
+    xp = xp - np.mean(xp)
+    P = xp.size
+    F = np.fft.fft(xp)
+    k = np.arange(P)
+    return F[:, None] * F[None, :] * np.conj(F[(k[:, None] + k[None, :]) % P]) / P
+
+
+def dbs_smooth(C, M3: int) -> np.ndarray:
+    """Step 5: average of C over the M3 x M3 box of offsets around each
+    point, indices modulo the grid size (written as the double sum)."""
+    lo = M3 // 2
+    out = np.zeros_like(C)
+    for n1 in range(-lo, M3 - lo):
+        for n2 in range(-lo, M3 - lo):
+            out += np.roll(np.roll(C, -n1, axis=0), -n2, axis=1)
+    return out / float(M3 * M3)
+
+
+def dbs(x, P: int, M3: int) -> np.ndarray:
+    """Algorithm DBS: partition, per part raw bispectrum and smoothing, then
+    the average over parts; returned on the principal domain (pd_indices(P)
+    order)."""
+    x = _f64(x)
+    K = x.size // P
+    acc = np.zeros((P, P), dtype=np.complex128)
+    for i in range(K):
+        acc += dbs_smooth(dbs_raw(x[i * P:(i + 1) * P]), M3)
+    k1, k2 = pd_indices(P)
+    return (acc / K)[k1, k2]
+
+
+def c3_circular(part) -> np.ndarray:
+    """(1/P) sum_t x_t x_{(t+w1) mod P} x_{(t+w2) mod P} for the mean-removed
+    part, every (w1, w2) in [0, P)^2, by brute force (pins dbs_raw)."""
+    xp = _f64(part)
+    xp = xp - np.mean(xp)
+    P = xp.size
+    out = np.empty((P, P))
+    t = np.arange(P)
+    for w1 in range(P):
+        for w2 in range(P):
+            out[w1, w2] = np.sum(xp * xp[(t + w1) % P] * xp[(t + w2) % P]) / P
+    return out

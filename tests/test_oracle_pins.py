@@ -426,3 +426,60 @@ def test_separable_window_hand_values():
     w4 = oracle.window4(M, "separable")
     assert abs(w4[2 + M, -2 + M, 1 + M] - 0.0625 * d1) < 1e-15
     assert oracle.window4(M, "parzen")[2 + M, -2 + M, 1 + M] == 0.0
+
+
+# --------------------------------------------------------------------------
+# The direct method (Algorithm DBS)
+# --------------------------------------------------------------------------
+def test_dbs_raw_is_dft_of_circular_triple_correlation():
+    """F(k1)F(k2)conj(F(k1+k2))/P equals the unnormalised 2-D DFT of the
+    circular third moment, computed here by brute force: pins the conjugate
+    placement and the 1/P."""
+    x = synth.iid_exp_centered(24, 3)
+    raw = oracle.dbs_raw(x)
+    c = oracle.c3_circular(x)
+    P = x.size
+    w = np.arange(P)
+    E = np.exp(-2j * np.pi * np.outer(w, w) / P)
+    assert np.max(np.abs(raw - E @ c @ E.T)) < 1e-12 * np.max(np.abs(raw))
+
+
+def test_dbs_smoothing_box():
+    """A unit impulse at (p1, p2) spreads 1/M3^2 over exactly the points whose
+    window contains it: k - n = p for n in [-floor(M3/2), M3-1-floor(M3/2)],
+    with wrap-around; a constant grid is unchanged."""
+    P = 16
+    for M3 in (1, 4, 5):
+        C = np.zeros((P, P), dtype=np.complex128)
+        C[3, 14] = 1.0
+        S = oracle.dbs_smooth(C, M3)
+        lo = M3 // 2
+        expect = np.zeros((P, P))
+        for n1 in range(-lo, M3 - lo):
+            for n2 in range(-lo, M3 - lo):
+                expect[(3 - n1) % P, (14 - n2) % P] = 1.0 / M3 ** 2
+        assert np.allclose(S, expect, atol=1e-15)
+        assert np.allclose(oracle.dbs_smooth(np.full((P, P), 2.5 + 1j), M3), 2.5 + 1j)
+
+
+def test_dbs_averaging_and_mean_removal():
+    """K copies of one part give that part's result; adding a constant to a
+    part changes nothing; trailing samples beyond K P are ignored."""
+    part = synth.quadratic_process(32, 4)
+    one = oracle.dbs(part, 32, 3)
+    x = np.concatenate([part, part + 7.0, part - 1.5, [9.0] * 5])
+    assert np.allclose(oracle.dbs(x, 32, 3), one, rtol=0, atol=1e-12 * np.max(np.abs(one)))
+
+
+def test_dbs_matches_indirect_with_one_part_and_no_smoothing():
+    """K = 1, M3 = 1, with the part zero-padded to length >= 2n-1 outside the
+    estimator: the direct raw bispectrum of the padded part is n/N' times the
+    indirect B of the unpadded series with no window and M = n-1 (the
+    circular and the zero-padded third moments then coincide)."""
+    x = synth.iid_exp_centered(20, 8)
+    n, N = x.size, 40
+    xt = x - np.mean(x)
+    padded = np.concatenate([xt, np.zeros(N - n)])
+    raw = oracle.dbs_raw(padded)      # its mean removal shifts nothing: mean(padded) = 0
+    _, B = oracle.bispectrum(x, n - 1, N, window="none")
+    assert np.max(np.abs(raw * N / n - B)) < 1e-10 * np.max(np.abs(B))
