@@ -332,6 +332,71 @@ int hos_bispectrum_loss_bwd(const void *x, int32_t dtype, const void *plan_host,
                             const double *dL, void *dx, void *ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/*
+ * ------------------------------------------------------------------------
+ * The direct method (Algorithm DBS, Section 1) with the window-sum smoothing
+ * of Section 3 (Algorithm WS, Theorem directseq).
+ *
+ * The first K = floor(n / P) * P samples are cut into K parts of P samples
+ * (trailing samples are not used).  Each part loses its own mean (FP64;
+ * kept with HOS_NO_CENTER) and gets a P-point DFT
+ *     F_i(k) = sum_u x_i(u) exp(-2 pi i u k / P)                  (step 3).
+ * The raw bispectrum of a part is F_i(k1) F_i(k2) conj F_i(k1 + k2) / P
+ * (step 4, indices modulo P; the conjugate on the third factor is what
+ * makes the estimate agree with the Fourier transform of the third
+ * moment).  It is averaged over the M3 x M3 box of offsets
+ * n1, n2 in [-floor(M3/2), M3 - 1 - floor(M3/2)] around each point, indices
+ * modulo P (step 5; for even M3 this is the printed range -M3/2 .. M3/2-1),
+ * and over the K parts (step 6).  Every value is computed in FP64.
+ *
+ * Output: the principal domain 0 <= k2 <= k1, k1 + k2 < P/2 of the P grid,
+ * row-major in (k1, k2) -- row k1 (0 <= k1 <= H = floor((P-1)/2)) holds
+ * k2 = 0 .. min(k1, H - k1) -- as interleaved complex128.
+ *
+ * Limits: 2 <= P <= 65536 with no prime factor but 2, 3, 5; n >= P;
+ * 1 <= M3 <= min(P, 2048).  Cost: O(n log P) for the DFTs, O(K) per output
+ * for the part sums (K >= 2), and O(1) per output for the smoothing,
+ * independent of M3.
+ * ------------------------------------------------------------------------
+ */
+
+/* Workspace bytes (host-only).  HOS_EINVAL on bad sizes. */
+int hos_dbs_workspace(int64_t n, int32_t P, int32_t M3, size_t *bytes);
+
+/*
+ * x: device, n samples (HOS_F32 or HOS_F64).  flags: 0 or HOS_NO_CENTER.
+ * B_pd: device, 16-byte aligned, npd complex128 (npd from
+ * hos_dbs_plan_info).  ws: device, 256-byte aligned, >= hos_dbs_workspace
+ * bytes; no contents are assumed on entry.  Asynchronous on `stream`;
+ * nothing is allocated.  Deterministic: a fixed summation order throughout.
+ * Returns HOS_EINVAL / HOS_EWORKSPACE before any device work, HOS_EDEVICE
+ * if a launch fails.
+ */
+int hos_dbs(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3, uint32_t flags,
+            double *B_pd, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * hos_dbs with stage timing (synchronises the stream): stage_ms (host, 4
+ * floats) receives the part means and DFTs, the part sums (0 when K = 1),
+ * the smoothing, and the total, in milliseconds.  seg_rows > 0 sets the
+ * output rows per smoothing workgroup (0: the built-in rule); results do not
+ * depend on it.
+ */
+int hos_dbs_timed(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3,
+                  uint32_t flags, double *B_pd, void *ws, size_t ws_bytes, hipStream_t stream,
+                  int32_t seg_rows, float *stage_ms);
+
+/*
+ * Host-only plan (no HIP call).  info (host, ninfo >= 16) receives: K,
+ * mode (0: products formed from the spectrum, K = 1; 1: part sums first),
+ * P1, P2 (the part DFT as P1 x P2 passes; P2 = 1 for one pass), widened
+ * strip width, output strip width, strips, output rows per workgroup, row
+ * segments, part-sum rectangle rows and columns, part groups, parts per
+ * group, principal-domain points npd, workspace bytes, columns per thread.
+ */
+int hos_dbs_plan_info(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, int64_t *info,
+                      int32_t ninfo);
+
 #ifdef __cplusplus
 }
 #endif

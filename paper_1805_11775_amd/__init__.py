@@ -98,6 +98,11 @@ def _load_lib():
         "hos_bispectrum_loss_bwd": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz,
                                                    vp]),
         "hos_c3_schedule": (ctypes.c_int, [i64, i32, i32, p64, p64, p64, i64]),
+        "hos_dbs_workspace": (ctypes.c_int, [i64, i32, i32, ctypes.POINTER(sz)]),
+        "hos_dbs": (ctypes.c_int, [vp, i32, i64, i32, i32, u32, vp, vp, sz, vp]),
+        "hos_dbs_timed": (ctypes.c_int, [vp, i32, i64, i32, i32, u32, vp, vp, sz, vp, i32,
+                                         ctypes.POINTER(ctypes.c_float)]),
+        "hos_dbs_plan_info": (ctypes.c_int, [i64, i32, i32, i32, p64, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -219,6 +224,42 @@ def hos_c4_plan_info(n, M, path) -> dict:
     return dict(zip(keys, list(buf)))
 
 
+DBS_INFO_KEYS = ("K", "mode", "P1", "P2", "W", "TW", "NS", "R", "NSEG", "SR", "SC", "G",
+                 "Kg", "npd", "ws_bytes", "CPT")
+DBS_STAGES = ("dft", "part_sums", "smooth", "total")
+
+
+def hos_dbs_plan_info(n, P, M3, seg_rows=0) -> dict:
+    buf = (ctypes.c_int64 * 16)()
+    st = lib().hos_dbs_plan_info(int(n), int(P), int(M3), int(seg_rows), buf, 16)
+    if st != HOS_OK:
+        raise HosError(st, "hos_dbs_plan_info")
+    return dict(zip(DBS_INFO_KEYS, list(buf)))
+
+
+def hos_dbs_workspace(n, P, M3) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().hos_dbs_workspace(int(n), int(P), int(M3), ctypes.byref(out))
+    if st != HOS_OK:
+        raise HosError(st, "hos_dbs_workspace")
+    return out.value
+
+
+def hos_dbs(x_ptr, dtype, n, P, M3, flags, B_ptr, ws_ptr, ws_bytes, stream) -> int:
+    """Raw call; returns the status code (does not raise)."""
+    return lib().hos_dbs(x_ptr, int(dtype), int(n), int(P), int(M3), int(flags), B_ptr,
+                         ws_ptr, int(ws_bytes), stream)
+
+
+def hos_dbs_timed(x_ptr, dtype, n, P, M3, flags, B_ptr, ws_ptr, ws_bytes, stream,
+                  seg_rows=0):
+    """Raw timed call; returns (status, {stage: milliseconds})."""
+    ms = (ctypes.c_float * 4)()
+    st = lib().hos_dbs_timed(x_ptr, int(dtype), int(n), int(P), int(M3), int(flags), B_ptr,
+                             ws_ptr, int(ws_bytes), stream, int(seg_rows), ms)
+    return st, dict(zip(DBS_STAGES, list(ms)))
+
+
 # ------------------------------------------------------------- torch layer
 def _next_fft_size(m: int) -> int:
     k = max(2, int(m))
@@ -317,6 +358,40 @@ def trispectrum(x, M: int, nfft: int | None = None, window: str = "parzen",
     if st != HOS_OK:
         raise HosError(st, "hos_trispectrum")
     return c4, T
+
+
+def dbs(x, P: int, M3: int, center: bool = True, workspace=None, timed: bool = False,
+        seg_rows: int = 0):
+    """The direct method (``hos_dbs``): parts of P samples, an M3 x M3 box.
+    Returns the principal domain of the P grid (complex128, row-major in
+    (k1, k2)); with ``timed`` also the stage times in ms."""
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError("x must be a CUDA tensor")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
+    x = x.contiguous().view(-1)
+    n = x.numel()
+    info = hos_dbs_plan_info(n, P, M3, seg_rows)
+    ws_bytes = info["ws_bytes"]
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=x.device)
+    B = torch.empty(info["npd"], dtype=torch.complex128, device=x.device)
+    args = (x.data_ptr(), HOS_F64 if x.dtype == torch.float64 else HOS_F32, n, P, M3,
+            0 if center else HOS_NO_CENTER, B.data_ptr(), workspace.data_ptr(),
+            workspace.numel(), _stream_handle(x.device))
+    if timed:
+        st, ms = hos_dbs_timed(*args, seg_rows=seg_rows)
+        if st != HOS_OK:
+            raise HosError(st, "hos_dbs_timed")
+        return B, ms
+    if seg_rows:
+        st, _ = hos_dbs_timed(*args, seg_rows=seg_rows)
+    else:
+        st = hos_dbs(*args)
+    if st != HOS_OK:
+        raise HosError(st, "hos_dbs")
+    return B
 
 
 # ------------------------------------------------------------------ batches

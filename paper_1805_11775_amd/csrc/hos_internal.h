@@ -257,6 +257,36 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
 int device_ok_public();
 constexpr int ADJ_MAX_M = 320;     // staged adjoint window <= 48 KB of LDS
 
+// ---------------------------------------------------------------------------
+// Direct method (Algorithm DBS): K parts of P samples, an M3 x M3 box.
+// ---------------------------------------------------------------------------
+constexpr int DBS_MAX_P = 65536;       // part length (2, 3, 5-smooth)
+constexpr int DBS_MAX_M3 = 2048;       // box side (<= one 2048-column strip)
+constexpr int DBS_LDS_FFT = 4096;      // longest part DFT done in one LDS pass
+
+struct DbsGeom {          // what the smoothing kernels need
+    int32_t P, M3, lo, hi, H;
+    int32_t CPT, W, TW;   // columns per thread, extended and output strip widths
+    int32_t NS, R, NSEG;  // strips, output rows per segment, segments of strip 0
+    int32_t SC;           // row stride of the part-sum rectangle (S mode)
+    double norm;          // 1 / (K P M3^2)
+};
+
+struct DbsPlan {
+    int64_t n, K;
+    int32_t mode;         // 0: K = 1, products from the spectrum; 1: from part sums
+    int32_t P1, P2;       // two-pass DFT P = P1 * P2 (P2 = 1: one pass)
+    int32_t SR;           // rows of the part-sum rectangle
+    int32_t G, Kg;        // part groups of the sums, parts per group
+    int64_t npd;          // principal-domain points of the P grid
+    DbsGeom g;
+    size_t off_mean, off_F, off_T, off_tw, off_tw1, off_tw2, off_S, total;
+};
+
+int make_dbs_plan(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, DbsPlan &p);
+hipError_t launch_dbs(const void *x, int dtype, uint32_t flags, const DbsPlan &p, double *B_pd,
+                      char *ws, hipStream_t s, hipEvent_t *ev);
+
 // Element count of one FP64 partial tile.
 inline int64_t tile_elems(int NB) { return (int64_t)(32 * NB) * (32 * NB); }
 

@@ -136,3 +136,12 @@ def workload_loss(batch: int = 64, n: int = 65536):
                   for c in ss.spawn(int(batch))]).astype(np.float32)
     target = quadratic_process(n, SEED_BASE + 6)
     return X, target, dict(M=256, nfft=512)
+
+
+def workload_dbs(n: int = 1 << 16):
+    """Direct method: one float32 quadratic-process series of 2^16 samples
+    taken as a single part (K = 1, P = n), smoothed over a 1023 x 1023 box
+    (the window lengths of the paper's timing table grow by about 1.54 per
+    doubling of n, which puts n = 2^16 near 1020)."""
+    x = quadratic_process(n, SEED_BASE + 7).astype(np.float32)
+    return x, dict(P=int(n), M3=1023)

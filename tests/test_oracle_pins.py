@@ -483,3 +483,15 @@ def test_dbs_matches_indirect_with_one_part_and_no_smoothing():
     raw = oracle.dbs_raw(padded)      # its mean removal shifts nothing: mean(padded) = 0
     _, B = oracle.bispectrum(x, n - 1, N, window="none")
     assert np.max(np.abs(raw * N / n - B)) < 1e-10 * np.max(np.abs(B))
+
+
+def test_dbs_at_matches_dbs():
+    """The sampled form agrees with the whole-grid form, K = 3, odd and even
+    box sizes, including points whose box wraps around the grid."""
+    x = synth.iid_exp_centered(3 * 30 + 7, 12)
+    k1, k2 = oracle.pd_indices(30)
+    for M3 in (1, 4, 7):
+        full = oracle.dbs(x, 30, M3)
+        pick = np.arange(0, k1.size, 5)
+        got = oracle.dbs_at(x, 30, M3, k1[pick], k2[pick])
+        assert np.max(np.abs(got - full[pick])) < 1e-12 * np.max(np.abs(full))
