@@ -406,3 +406,26 @@ def c3_circular(part) -> np.ndarray:
         for w2 in range(P):
             out[w1, w2] = np.sum(xp * xp[(t + w1) % P] * xp[(t + w2) % P]) / P
     return out
+
+
+def dbs_at(x, P: int, M3: int, k1, k2) -> np.ndarray:
+    """Algorithm DBS at chosen frequencies only: for each (k1, k2), the
+    M3 x M3 box of raw part bispectra written out as an explicit double sum
+    (indices modulo P), averaged over the parts.  For outputs of grids too
+    large for ``dbs``."""
+    x = _f64(x)
+    K = x.size // P
+    k1 = np.atleast_1d(np.asarray(k1, dtype=np.int64))
+    k2 = np.atleast_1d(np.asarray(k2, dtype=np.int64))
+    lo = M3 // 2
+    off = np.arange(-lo, M3 - lo)
+    out = np.zeros(k1.size, dtype=np.complex128)
+    for i in range(K):
+        xp = x[i * P:(i + 1) * P]
+        F = np.fft.fft(xp - np.mean(xp))
+        for j in range(k1.size):
+            a = (k1[j] + off) % P
+            b = (k2[j] + off) % P
+            raw = F[a][:, None] * F[b][None, :] * np.conj(F[(a[:, None] + b[None, :]) % P])
+            out[j] += np.sum(raw) / P
+    return out / (K * float(M3 * M3))
