@@ -378,24 +378,28 @@ int hos_dbs(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3, uint
 /*
  * hos_dbs with stage timing (synchronises the stream): stage_ms (host, 4
  * floats) receives the part means and DFTs, the part sums (0 when K = 1),
- * the smoothing, and the total, in milliseconds.  seg_rows > 0 sets the
- * output rows per smoothing workgroup (0: the built-in rule); results do not
- * depend on it.
+ * the smoothing, and the total, in milliseconds.  Two tuning arguments
+ * (0: the built-in rule): seg_rows > 0 sets the output rows per smoothing
+ * workgroup; strip_w in {512, 1024, 2048}, >= M3, sets the widened strip
+ * width.  Results differ from hos_dbs by rounding only.  The workspace must
+ * hold the byte count hos_dbs_plan_info gives for the same arguments.
  */
 int hos_dbs_timed(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3,
                   uint32_t flags, double *B_pd, void *ws, size_t ws_bytes, hipStream_t stream,
-                  int32_t seg_rows, float *stage_ms);
+                  int32_t seg_rows, int32_t strip_w, float *stage_ms);
 
 /*
- * Host-only plan (no HIP call).  info (host, ninfo >= 16) receives: K,
+ * Host-only plan (no HIP call), for the tuning arguments of hos_dbs_timed
+ * (0, 0: the plan of hos_dbs).  info (host, ninfo >= 16) receives: K,
  * mode (0: products formed from the spectrum, K = 1; 1: part sums first),
  * P1, P2 (the part DFT as P1 x P2 passes; P2 = 1 for one pass), widened
- * strip width, output strip width, strips, output rows per workgroup, row
- * segments, part-sum rectangle rows and columns, part groups, parts per
- * group, principal-domain points npd, workspace bytes, columns per thread.
+ * strip width, output strip width, strips, rows per smoothing workgroup,
+ * smoothing workgroups, part-sum rectangle rows and columns, part groups,
+ * parts per group, principal-domain points npd, workspace bytes, and the
+ * strips' rows in total.
  */
-int hos_dbs_plan_info(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, int64_t *info,
-                      int32_t ninfo);
+int hos_dbs_plan_info(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, int32_t strip_w,
+                      int64_t *info, int32_t ninfo);
 
 #ifdef __cplusplus
 }

@@ -101,8 +101,8 @@ def _load_lib():
         "hos_dbs_workspace": (ctypes.c_int, [i64, i32, i32, ctypes.POINTER(sz)]),
         "hos_dbs": (ctypes.c_int, [vp, i32, i64, i32, i32, u32, vp, vp, sz, vp]),
         "hos_dbs_timed": (ctypes.c_int, [vp, i32, i64, i32, i32, u32, vp, vp, sz, vp, i32,
-                                         ctypes.POINTER(ctypes.c_float)]),
-        "hos_dbs_plan_info": (ctypes.c_int, [i64, i32, i32, i32, p64, i32]),
+                                         i32, ctypes.POINTER(ctypes.c_float)]),
+        "hos_dbs_plan_info": (ctypes.c_int, [i64, i32, i32, i32, i32, p64, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -224,14 +224,14 @@ def hos_c4_plan_info(n, M, path) -> dict:
     return dict(zip(keys, list(buf)))
 
 
-DBS_INFO_KEYS = ("K", "mode", "P1", "P2", "W", "TW", "NS", "R", "NSEG", "SR", "SC", "G",
-                 "Kg", "npd", "ws_bytes", "CPT")
+DBS_INFO_KEYS = ("K", "mode", "P1", "P2", "W", "TW", "NS", "R", "NWG", "SR", "SC", "G",
+                 "Kg", "npd", "ws_bytes", "rows")
 DBS_STAGES = ("dft", "part_sums", "smooth", "total")
 
 
-def hos_dbs_plan_info(n, P, M3, seg_rows=0) -> dict:
+def hos_dbs_plan_info(n, P, M3, seg_rows=0, strip_w=0) -> dict:
     buf = (ctypes.c_int64 * 16)()
-    st = lib().hos_dbs_plan_info(int(n), int(P), int(M3), int(seg_rows), buf, 16)
+    st = lib().hos_dbs_plan_info(int(n), int(P), int(M3), int(seg_rows), int(strip_w), buf, 16)
     if st != HOS_OK:
         raise HosError(st, "hos_dbs_plan_info")
     return dict(zip(DBS_INFO_KEYS, list(buf)))
@@ -252,11 +252,11 @@ def hos_dbs(x_ptr, dtype, n, P, M3, flags, B_ptr, ws_ptr, ws_bytes, stream) -> i
 
 
 def hos_dbs_timed(x_ptr, dtype, n, P, M3, flags, B_ptr, ws_ptr, ws_bytes, stream,
-                  seg_rows=0):
+                  seg_rows=0, strip_w=0):
     """Raw timed call; returns (status, {stage: milliseconds})."""
     ms = (ctypes.c_float * 4)()
     st = lib().hos_dbs_timed(x_ptr, int(dtype), int(n), int(P), int(M3), int(flags), B_ptr,
-                             ws_ptr, int(ws_bytes), stream, int(seg_rows), ms)
+                             ws_ptr, int(ws_bytes), stream, int(seg_rows), int(strip_w), ms)
     return st, dict(zip(DBS_STAGES, list(ms)))
 
 
@@ -361,10 +361,11 @@ def trispectrum(x, M: int, nfft: int | None = None, window: str = "parzen",
 
 
 def dbs(x, P: int, M3: int, center: bool = True, workspace=None, timed: bool = False,
-        seg_rows: int = 0):
+        seg_rows: int = 0, strip_w: int = 0):
     """The direct method (``hos_dbs``): parts of P samples, an M3 x M3 box.
     Returns the principal domain of the P grid (complex128, row-major in
-    (k1, k2)); with ``timed`` also the stage times in ms."""
+    (k1, k2)); with ``timed`` also the stage times in ms.  ``seg_rows`` and
+    ``strip_w`` are the tuning arguments of ``hos_dbs_timed``."""
     import torch
     if not (isinstance(x, torch.Tensor) and x.is_cuda):
         raise TypeError("x must be a CUDA tensor")
@@ -372,7 +373,7 @@ def dbs(x, P: int, M3: int, center: bool = True, workspace=None, timed: bool = F
         raise TypeError("x must be float32 or float64")
     x = x.contiguous().view(-1)
     n = x.numel()
-    info = hos_dbs_plan_info(n, P, M3, seg_rows)
+    info = hos_dbs_plan_info(n, P, M3, seg_rows, strip_w)
     ws_bytes = info["ws_bytes"]
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=x.device)
@@ -381,12 +382,12 @@ def dbs(x, P: int, M3: int, center: bool = True, workspace=None, timed: bool = F
             0 if center else HOS_NO_CENTER, B.data_ptr(), workspace.data_ptr(),
             workspace.numel(), _stream_handle(x.device))
     if timed:
-        st, ms = hos_dbs_timed(*args, seg_rows=seg_rows)
+        st, ms = hos_dbs_timed(*args, seg_rows=seg_rows, strip_w=strip_w)
         if st != HOS_OK:
             raise HosError(st, "hos_dbs_timed")
         return B, ms
-    if seg_rows:
-        st, _ = hos_dbs_timed(*args, seg_rows=seg_rows)
+    if seg_rows or strip_w:
+        st, _ = hos_dbs_timed(*args, seg_rows=seg_rows, strip_w=strip_w)
     else:
         st = hos_dbs(*args)
     if st != HOS_OK:

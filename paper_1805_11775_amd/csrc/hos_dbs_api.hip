@@ -41,7 +41,8 @@ static int64_t pd_points(int H)
     return s;
 }
 
-int make_dbs_plan(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, DbsPlan &p)
+int make_dbs_plan(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, int32_t strip_w,
+                  DbsPlan &p)
 {
     memset(&p, 0, sizeof(p));
     DbsGeom &g = p.g;
@@ -70,29 +71,33 @@ int make_dbs_plan(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, DbsPlan &p
         p.P1 = best;
         p.P2 = P / best;
     }
-    // strip width: the widened strip W holds the box's M3 - 1 extra columns
-    // with at least half of it left for outputs when possible
+    // strip width: W widened columns (4 per thread) hold the box's M3 - 1
+    // extra columns and TW = W - M3 + 1 outputs; the widest of 512, 1024,
+    // 2048 that the grid's columns fill (wider strips repeat less of the
+    // box's overlap and run as fewer, longer row steps)
     g.W = 2048;
-    for (int w : {256, 512, 1024})
-        if (M3 - 1 <= w / 2) {
-            g.W = w;
-            break;
-        }
-    g.CPT = g.W == 2048 ? 4 : g.W / 256;
+    if (Hc + M3 <= 1024)
+        g.W = 1024;
+    if (Hc + M3 <= 512)
+        g.W = 512;
+    if (strip_w > 0)
+        g.W = strip_w;
+    g.CPT = 4;
     g.TW = g.W - M3 + 1;
     g.NS = (Hc + 1 + g.TW - 1) / g.TW;
-    int64_t rows = 0;
+    g.rows = 0;
     for (int s = 0; s < g.NS; ++s)
-        rows += (int64_t)g.H - 2 * (int64_t)s * g.TW + 1;
-    int64_t R = seg_rows > 0 ? seg_rows : (rows + 1023) / 1024;
-    if (seg_rows <= 0) {
-        if (R < (M3 + 1) / 2)
-            R = (M3 + 1) / 2;
-        if (R < 32)
-            R = 32;
-    }
+        g.rows += (int64_t)g.H - 2 * (int64_t)s * g.TW + 1;
+    // the strips' rows laid end to end and cut into equal runs, one per
+    // workgroup, as many as fit on the chip at once (a run may cross into
+    // the next strip; each strip part restarts its box)
+    const int per_cu = g.W == 2048 ? 1 : (g.W == 1024 ? 2 : 4);
+    const int64_t target = (int64_t)DBS_CUS * per_cu;
+    int64_t R = seg_rows > 0 ? seg_rows : (g.rows + target - 1) / target;
+    if (seg_rows <= 0 && R < 16)
+        R = 16;
     g.R = (int32_t)R;
-    g.NSEG = (int32_t)((g.H + 1 + R - 1) / R);
+    g.NSEG = (int32_t)((g.rows + R - 1) / R);
     g.SC = (g.NS - 1) * g.TW + g.W;
     g.norm = 1.0 / ((double)p.K * (double)P * (double)M3 * (double)M3);
     p.SR = g.H + M3;
@@ -129,9 +134,20 @@ int make_dbs_plan(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, DbsPlan &p
 
 static bool dbs_aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr & (a - 1)) == 0; }
 
+// Tuning arguments of the timed entry point: rows per smoothing workgroup
+// (>= 0) and widened strip width (0, or 512 / 1024 / 2048 and >= M3).
+static bool tune_ok(int32_t seg_rows, int32_t strip_w, int32_t M3)
+{
+    if (seg_rows < 0)
+        return false;
+    if (strip_w == 0)
+        return true;
+    return (strip_w == 512 || strip_w == 1024 || strip_w == 2048) && strip_w >= M3;
+}
+
 static int dbs_impl(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3,
                     uint32_t flags, double *B_pd, void *ws, size_t ws_bytes, hipStream_t stream,
-                    int32_t seg_rows, hipEvent_t *ev)
+                    int32_t seg_rows, int32_t strip_w, hipEvent_t *ev)
 {
     if (!x || !B_pd || !ws)
         return HOS_EINVAL;
@@ -140,13 +156,13 @@ static int dbs_impl(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t 
     if (!dbs_aligned(x, dtype == HOS_F64 ? 8 : 4) || !dbs_aligned(B_pd, 16) ||
         !dbs_aligned(ws, 256))
         return HOS_EINVAL;
-    if (seg_rows < 0)
-        return HOS_EINVAL;
     int st = check_dbs_args(n, P, M3, flags);
     if (st != HOS_OK)
         return st;
+    if (!tune_ok(seg_rows, strip_w, M3))
+        return HOS_EINVAL;
     DbsPlan p;
-    make_dbs_plan(n, P, M3, seg_rows, p);
+    make_dbs_plan(n, P, M3, seg_rows, strip_w, p);
     if (ws_bytes < p.total)
         return HOS_EWORKSPACE;
     st = device_ok_public();
@@ -171,7 +187,7 @@ int hos_dbs_workspace(int64_t n, int32_t P, int32_t M3, size_t *bytes)
     if (st != HOS_OK)
         return st;
     DbsPlan p;
-    make_dbs_plan(n, P, M3, 0, p);
+    make_dbs_plan(n, P, M3, 0, 0, p);
     *bytes = p.total;
     return HOS_OK;
 }
@@ -179,14 +195,14 @@ int hos_dbs_workspace(int64_t n, int32_t P, int32_t M3, size_t *bytes)
 int hos_dbs(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3, uint32_t flags,
             double *B_pd, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    return dbs_impl(x, dtype, n, P, M3, flags, B_pd, ws, ws_bytes, stream, 0, nullptr);
+    return dbs_impl(x, dtype, n, P, M3, flags, B_pd, ws, ws_bytes, stream, 0, 0, nullptr);
 }
 
 int hos_dbs_timed(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3,
                   uint32_t flags, double *B_pd, void *ws, size_t ws_bytes, hipStream_t stream,
-                  int32_t seg_rows, float *stage_ms)
+                  int32_t seg_rows, int32_t strip_w, float *stage_ms)
 {
-    if (!stage_ms || seg_rows < 0)
+    if (!stage_ms)
         return HOS_EINVAL;
     // the checks of dbs_impl, before any HIP call (events included)
     if (!x || !B_pd || !ws || (dtype != HOS_F32 && dtype != HOS_F64))
@@ -194,13 +210,15 @@ int hos_dbs_timed(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3
     int vst = check_dbs_args(n, P, M3, flags);
     if (vst != HOS_OK)
         return vst;
+    if (!tune_ok(seg_rows, strip_w, M3))
+        return HOS_EINVAL;
     hipEvent_t ev[4];
     int made = 0;
     for (; made < 4; ++made)
         if (hipEventCreate(&ev[made]) != hipSuccess)
             break;
     int st = made == 4 ? dbs_impl(x, dtype, n, P, M3, flags, B_pd, ws, ws_bytes, stream,
-                                  seg_rows, ev)
+                                  seg_rows, strip_w, ev)
                        : HOS_EDEVICE;
     if (st == HOS_OK) {
         if (hipEventSynchronize(ev[3]) != hipSuccess) {
@@ -218,19 +236,21 @@ int hos_dbs_timed(const void *x, int32_t dtype, int64_t n, int32_t P, int32_t M3
     return st;
 }
 
-int hos_dbs_plan_info(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, int64_t *info,
-                      int32_t ninfo)
+int hos_dbs_plan_info(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, int32_t strip_w,
+                      int64_t *info, int32_t ninfo)
 {
-    if (!info || ninfo < 16 || seg_rows < 0)
+    if (!info || ninfo < 16)
         return HOS_EINVAL;
     int st = check_dbs_args(n, P, M3, 0);
     if (st != HOS_OK)
         return st;
+    if (!tune_ok(seg_rows, strip_w, M3))
+        return HOS_EINVAL;
     DbsPlan p;
-    make_dbs_plan(n, P, M3, seg_rows, p);
+    make_dbs_plan(n, P, M3, seg_rows, strip_w, p);
     const int64_t v[16] = {p.K, p.mode, p.P1, p.P2, p.g.W, p.g.TW, p.g.NS, p.g.R,
                            p.g.NSEG, p.SR, p.g.SC, p.G, p.Kg, p.npd, (int64_t)p.total,
-                           p.g.CPT};
+                           p.g.rows};
     for (int k = 0; k < 16; ++k)
         info[k] = v[k];
     return HOS_OK;

@@ -263,11 +263,14 @@ constexpr int ADJ_MAX_M = 320;     // staged adjoint window <= 48 KB of LDS
 constexpr int DBS_MAX_P = 65536;       // part length (2, 3, 5-smooth)
 constexpr int DBS_MAX_M3 = 2048;       // box side (<= one 2048-column strip)
 constexpr int DBS_LDS_FFT = 4096;      // longest part DFT done in one LDS pass
+constexpr int DBS_CUS = 256;           // compute units the smoothing grid is sized for
 
 struct DbsGeom {          // what the smoothing kernels need
     int32_t P, M3, lo, hi, H;
     int32_t CPT, W, TW;   // columns per thread, extended and output strip widths
-    int32_t NS, R, NSEG;  // strips, output rows per segment, segments of strip 0
+    int32_t NS;           // strips; strip s holds the output rows [s TW, H - s TW]
+    int32_t R, NSEG;      // rows per workgroup (of the strips' rows laid end to end), workgroups
+    int64_t rows;         // sum of the strips' row counts
     int32_t SC;           // row stride of the part-sum rectangle (S mode)
     double norm;          // 1 / (K P M3^2)
 };
@@ -283,7 +286,8 @@ struct DbsPlan {
     size_t off_mean, off_F, off_T, off_tw, off_tw1, off_tw2, off_S, total;
 };
 
-int make_dbs_plan(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, DbsPlan &p);
+int make_dbs_plan(int64_t n, int32_t P, int32_t M3, int32_t seg_rows, int32_t strip_w,
+                  DbsPlan &p);
 hipError_t launch_dbs(const void *x, int dtype, uint32_t flags, const DbsPlan &p, double *B_pd,
                       char *ws, hipStream_t s, hipEvent_t *ev);
 

@@ -280,132 +280,214 @@ k_dbs_sreduce(double2 *__restrict__ S, int G, int64_t count)
     S[e] = s;
 }
 
-// The smoothing: one strip (blockIdx.y) and one run of output rows
-// (blockIdx.x) per workgroup.  Thread t owns the CPT consecutive widened
-// columns e = t CPT + m (for the scan) and the output columns j = t + NT k.
-template <int MODE, int NT, int CPT>
-__global__ void __launch_bounds__(NT)
-k_dbs_box(const double2 *__restrict__ F, const double2 *__restrict__ S, DbsGeom g,
-          double2 *__restrict__ out)
+// 64-lane inclusive scan of a complex double with DPP lane moves: four
+// in-row shifts (Hillis-Steele over 16 lanes), then the last lane of rows
+// 0 and 2 into rows 1 and 3, then lane 31 into rows 2 and 3.  Lanes whose
+// source is outside the row, or whose row is masked off, receive 0.
+// Lane moves of a complex double.  Shifts within rows of 16 lanes write 0
+// to the lanes with no source; the row broadcasts leave masked rows at 0.
+template <int CTRL>
+__device__ inline double dpp_shr(double v)
 {
-    constexpr int W = NT * CPT;
-    constexpr int NW = NT / 64;
-    constexpr int PADW = W + (CPT > 1 ? W / CPT : 0);
-    __shared__ double2 lin[PADW], lout[PADW];
-    __shared__ double2 wtot[2][NW];
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
 
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+template <int CTRL, int ROWS>
+__device__ inline double dpp_bcast(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+template <int CTRL>
+__device__ inline double2 shr_c(double2 v)
+{
+    return make_double2(dpp_shr<CTRL>(v.x), dpp_shr<CTRL>(v.y));
+}
+
+template <int CTRL, int ROWS>
+__device__ inline double2 bcast_c(double2 v)
+{
+    return make_double2(dpp_bcast<CTRL, ROWS>(v.x), dpp_bcast<CTRL, ROWS>(v.y));
+}
+
+// 64-lane inclusive scan: four in-row shifts (Hillis-Steele over 16
+// lanes), then the last lane of rows 0 and 2 into rows 1 and 3, then lane
+// 31 into rows 2 and 3.
+__device__ inline double2 wave_scan_incl(double2 v)
+{
+    v = cadd(v, shr_c<0x111>(v));          // row_shr:1
+    v = cadd(v, shr_c<0x112>(v));          // row_shr:2
+    v = cadd(v, shr_c<0x114>(v));          // row_shr:4
+    v = cadd(v, shr_c<0x118>(v));          // row_shr:8
+    v = cadd(v, bcast_c<0x142, 0xa>(v));   // row_bcast:15 -> rows 1, 3
+    v = cadd(v, bcast_c<0x143, 0xc>(v));   // row_bcast:31 -> rows 2, 3
+    return v;
+}
+
+__device__ inline int inc_wrap(int i, int P) { return i + 1 == P ? 0 : i + 1; }
+
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS (and scalar) operations, not for its global loads and stores,
+// which stay in flight across it (no value crosses threads through global
+// memory in the smoothing kernel).  s_waitcnt 0xc07f = lgkmcnt(0) with the
+// vector-memory and export counters left at their maxima.
+__device__ inline void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Sum of the totals of the waves before this one (wave is uniform): lane
+// l reads the total of wave l mod NW, a short in-row scan forms the
+// running sums over lanes 0 .. NW-1, and lane wave - 1 holds the answer.
+template <int NW>
+__device__ inline double2 waves_before(const double2 *tot, int lane, int wave)
+{
+    if (wave == 0)
+        return make_double2(0.0, 0.0);
+    double2 v = tot[lane & (NW - 1)];
+    v = cadd(v, shr_c<0x111>(v));
+    if constexpr (NW > 2)
+        v = cadd(v, shr_c<0x112>(v));
+    if constexpr (NW > 4)
+        v = cadd(v, shr_c<0x114>(v));
+    const int src = wave - 1;
+    const long long bx = __double_as_longlong(v.x), by = __double_as_longlong(v.y);
+    const int xl = __builtin_amdgcn_readlane((int)bx, src);
+    const int xh = __builtin_amdgcn_readlane((int)(bx >> 32), src);
+    const int yl = __builtin_amdgcn_readlane((int)by, src);
+    const int yh = __builtin_amdgcn_readlane((int)(by >> 32), src);
+    return make_double2(__longlong_as_double((long long)(unsigned)xl | ((long long)xh << 32)),
+                        __longlong_as_double((long long)(unsigned)yl | ((long long)yh << 32)));
+}
+
+// The smoothing, one strip of TW output columns and a run of its rows at a
+// time.  Window sums are linear, so each row step scans one row of
+// differences d(c) = raw(q_in, c) - raw(q_out, c) between the row entering
+// the box and the row leaving it (raw(q_in) alone while the box fills), and
+// the column sums take the window sums of d.  Thread t scans the 4
+// consecutive widened columns e = 4t .. 4t+3 and keeps the column sums of
+// the output columns j = t + NT k, whose window e = j .. j+M3-1 is the
+// difference of two prefix sums read from LDS.  LDS rows are stored with
+// the 4 entries of each thread rotated by (e >> 4) & 3, which keeps the
+// writes and the reads free of bank conflicts.  Rows go two at a time:
+// their scans share one pair of barriers.
+constexpr int BOX_CPT = 4;
+
+// acc + a * b and acc - a * b for complex doubles, as fused multiply-adds
+__device__ inline double2 cfma(double2 a, double2 b, double2 acc)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+
+__device__ inline double2 cfms(double2 a, double2 b, double2 acc)
+{
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+
+// One run: output rows [ra, rb) of the strip starting at column c0.
+template <int MODE, int NT>
+__device__ __forceinline__ void box_run(const double2 *__restrict__ F,
+                                        const double2 *__restrict__ S, const DbsGeom &g,
+                                        double2 *__restrict__ out, int c0, int ra, int rb,
+                                        double2 (*lrow)[NT * BOX_CPT], double2 (*wtot)[NT / 64])
+{
+    constexpr int CPT = BOX_CPT;
+    constexpr int NW = NT / 64;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int H = g.H, P = g.P, M3 = g.M3, TW = g.TW;
-    const int c0 = blockIdx.y * TW;
-    const int ra = c0 + blockIdx.x * g.R;
-    const int rend = H - c0 + 1;              // the strip's rows are [c0, H - c0]
-    if (ra >= rend)
-        return;                               // whole workgroup
-    const int rb = min(ra + g.R, rend);
     const int T = (rb - ra) + M3 - 1;         // rows entering the box
     const int qa = ra - g.lo;                 // first of them
-    const int e0 = t * CPT;                   // first owned widened column
+    const int e0 = t * CPT;                   // first owned widened (and output) column
     const int64_t cb = (int64_t)c0 - g.lo + e0;
-    auto pad = [](int e) { return CPT > 1 ? e + e / CPT : e; };
+    auto sw = [](int e) { return (e & ~3) | (((e & 3) + (e >> 4)) & 3); };
 
     double2 v[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k)
         v[k] = make_double2(0.0, 0.0);
+    int r = ra;                               // next output row and its offset
+    int64_t ro = pd_row_off(ra, H);
 
-    // One row step: u (the products of the entering row, and of the leaving
-    // row when has_out) -> window sums along k2 -> the column sums v; then
-    // the output row when the box is full.
-    // inclusive scan of the products within the wave: u[m] becomes the
-    // sum up to element m of the thread's wave; returns the wave total in
-    // lane 63's copy
-    auto wave_scan = [&](double2 (&u)[CPT]) {
+    // d -> global inclusive prefix sums in d, with the exclusive prefix at
+    // the thread's first column in ex.  Phase 1 (before the barrier):
+    // in-thread and in-wave scans; phase 2: the earlier waves, published.
+    auto scan1 = [&](double2 (&d)[CPT], double2 *tot, double2 &ex) {
 #pragma unroll
         for (int m = 1; m < CPT; ++m)
-            u[m] = cadd(u[m], u[m - 1]);
-        double2 tot = u[CPT - 1];
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const double2 y = shfl_up2(tot, d);
-            if (lane >= d)
-                tot = cadd(tot, y);
-        }
-        double2 ex = shfl_up2(tot, 1);
-        if (lane == 0)
-            ex = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int m = 0; m < CPT; ++m)
-            u[m] = cadd(ex, u[m]);
-        return tot;
-    };
-    // sum of the totals of the waves before this one
-    auto wave_off = [&](const double2 *tot) {
-        double2 o = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int w = 0; w < NW - 1; ++w)
-            if (w < wave)
-                o = cadd(o, tot[w]);
-        return o;
-    };
-    // sum of the first m products of a row (prefix sums stored from index 1)
-    auto pfx = [&](const double2 *row, int m) {
-        return m == 0 ? make_double2(0.0, 0.0) : row[pad(m - 1)];
-    };
-
-    // One row step: ui (the products of the entering row) and, when has_out,
-    // uo (of the row leaving the box) -> window sums along k2 -> the column
-    // sums v; then the output row once the box is full.  Two barriers: the
-    // wave totals, then the complete prefix sums.
-    auto step = [&](double2 (&ui)[CPT], double2 (&uo)[CPT], int st, bool has_out,
-                    double2 ain, double2 aout) {
-        const double2 ti = wave_scan(ui);
+            d[m] = cadd(d[m], d[m - 1]);
+        const double2 inc = wave_scan_incl(d[CPT - 1]);
+        ex = csub(inc, d[CPT - 1]);
         if (lane == 63)
-            wtot[0][wave] = ti;
-        if (has_out) {
-            const double2 to = wave_scan(uo);
-            if (lane == 63)
-                wtot[1][wave] = to;
-        }
-        __syncthreads();
-        const double2 oi = wave_off(wtot[0]);
+            tot[wave] = inc;
+    };
+    auto scan2 = [&](double2 (&d)[CPT], const double2 *tot, double2 &ex, double2 *row) {
+        ex = cadd(ex, waves_before<NW>(tot, lane, wave));
 #pragma unroll
-        for (int m = 0; m < CPT; ++m)
-            lin[pad(e0 + m)] = cadd(oi, ui[m]);
-        if (has_out) {
-            const double2 oo = wave_off(wtot[1]);
-#pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                lout[pad(e0 + m)] = cadd(oo, uo[m]);
+        for (int m = 0; m < CPT; ++m) {
+            d[m] = cadd(ex, d[m]);
+            row[sw(e0 + m)] = d[m];
         }
-        __syncthreads();
-        const int r = qa + st - g.hi;         // output row when the box is full
+    };
+    // v += window sums of d; then the output row if the box is full.
+    // Output column j = t + NT k, so each store instruction covers
+    // consecutive columns; both prefix sums of its window come from LDS.
+    auto update = [&](const double2 *row, int st) {
         const bool emit = st >= M3 - 1 && st < T;
         const int L = min(r, H - r);
-        const int64_t ro = emit ? pd_row_off(r, H) : 0;
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int j = t + NT * k;
             if (j < TW) {
-                const double2 hin = csub(pfx(lin, j + M3), pfx(lin, j));
-                double2 acc = cadd(v[k], cmul(ain, hin));
-                if (has_out) {
-                    const double2 hout = csub(pfx(lout, j + M3), pfx(lout, j));
-                    acc = csub(acc, cmul(aout, hout));
-                }
-                v[k] = acc;
+                const double2 top = row[sw(j + M3 - 1)];
+                const double2 bot = j > 0 ? row[sw(j - 1)] : make_double2(0.0, 0.0);
+                v[k] = cadd(v[k], csub(top, bot));
                 if (emit && c0 + j <= L)
-                    out[ro + c0 + j] = cscale(acc, g.norm);
+                    out[ro + c0 + j] = cscale(v[k], g.norm);
             }
         }
+        if (emit) {
+            ro += L + 1;
+            ++r;
+        }
+    };
+    // Row steps st and st + 1 from their difference rows.
+    auto step2 = [&](double2 (&d0)[CPT], double2 (&d1)[CPT], int st) {
+        double2 x0, x1;
+        scan1(d0, wtot[0], x0);
+        scan1(d1, wtot[1], x1);
+        lds_barrier();
+        scan2(d0, wtot[0], x0, lrow[0]);
+        scan2(d1, wtot[1], x1, lrow[1]);
+        lds_barrier();
+        update(lrow[0], st);
+        update(lrow[1], st + 1);
     };
 
     if constexpr (MODE == 0) {
-        // K = 1: u_e = F(c_e) conj F(q + c_e); F(q) multiplies the row's
-        // window sums.  conj F(q + cb + m) for the rows of the current
-        // block of CPT steps comes from two register halves A (this block)
-        // and B (the next): a value is dead once its row has passed and is
-        // reloaded at once for the block after next, so each step loads one
-        // value per half pair.
+        // K = 1: raw(q, c) = F(c) [F(q) conj F(q + c)].  conj F(q + cb + m)
+        // for the rows of the current block of CPT steps comes from two
+        // register halves C (this block) and N (the next): a value is dead
+        // once its row has passed and is reloaded at once for the block
+        // after next, so each step loads one value per half pair, CPT steps
+        // before its use.  Entering rows use Ci/Ni, leaving rows Co/No.
         double2 Fc[CPT], Ai[CPT], Bi[CPT], Ao[CPT], Bo[CPT];
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
@@ -415,26 +497,66 @@ k_dbs_box(const double2 *__restrict__ F, const double2 *__restrict__ S, DbsGeom 
             Ao[m] = cconj(F[wrap_p((int64_t)qa - M3 + cb + m, P)]);
             Bo[m] = cconj(F[wrap_p((int64_t)qa - M3 + CPT + cb + m, P)]);
         }
+        int ldi = wrap_p((int64_t)qa + 2 * CPT + cb, P);
+        int ldo = wrap_p((int64_t)qa - M3 + 2 * CPT + cb, P);
+        // Row factors F(q) of the entering and leaving rows: lane k of every
+        // wave loads the one of row k of the block after next (a vector load,
+        // so the LDS barriers never wait for it) and each step reads its
+        // row's value out of that lane.
+        const int kq = lane & (2 * CPT - 1);
+        int ai = wrap_p((int64_t)qa + kq, P), ao = wrap_p((int64_t)qa - M3 + kq, P);
+        double2 fav = F[ai], fbv = F[ao];
+        auto adv = [&](int &i) { i += 2 * CPT; if (i >= P) i -= P; if (i >= P) i %= P; };
+        auto lane_c = [](double2 v, int k) {
+            const long long bx = __double_as_longlong(v.x), by = __double_as_longlong(v.y);
+            const int xl = __builtin_amdgcn_readlane((int)bx, k);
+            const int xh = __builtin_amdgcn_readlane((int)(bx >> 32), k);
+            const int yl = __builtin_amdgcn_readlane((int)by, k);
+            const int yh = __builtin_amdgcn_readlane((int)(by >> 32), k);
+            return make_double2(
+                __longlong_as_double((long long)(unsigned)xl | ((long long)xh << 32)),
+                __longlong_as_double((long long)(unsigned)yl | ((long long)yh << 32)));
+        };
+        double2 fa_cur = fav, fb_cur = fbv;
         auto block = [&](double2 (&Ci)[CPT], double2 (&Ni)[CPT], double2 (&Co)[CPT],
                          double2 (&No)[CPT], int sb) {
+            // fa_cur / fb_cur hold rows sb .. sb + 2 CPT - 1 (lane k: row sb + k);
+            // the next pair of blocks' factors are loaded at its first block
+            const int kb = sb & (2 * CPT - 1);
+            if (kb == 0) {
+                fa_cur = fav;
+                fb_cur = fbv;
+                adv(ai);
+                adv(ao);
+                fav = F[ai];
+                fbv = F[ao];
+            }
 #pragma unroll
-            for (int u = 0; u < CPT; ++u) {
+            for (int u = 0; u < CPT; u += 2) {
                 const int st = sb + u;
-                const int64_t qi = (int64_t)qa + st, qo = qi - M3;
-                const double2 ain = F[wrap_p(qi, P)];
-                const bool has_out = st >= M3;
-                const double2 aout = has_out ? F[wrap_p(qo, P)] : make_double2(0.0, 0.0);
-                double2 ui[CPT], uo[CPT];
+                // the leaving rows' factors are 0 while the box fills
+                const double2 zero = make_double2(0.0, 0.0);
+                const double2 a0 = lane_c(fa_cur, kb + u), a1 = lane_c(fa_cur, kb + u + 1);
+                const double2 fb0 = lane_c(fb_cur, kb + u), fb1 = lane_c(fb_cur, kb + u + 1);
+                const double2 b0 = st >= M3 ? fb0 : zero, b1 = st + 1 >= M3 ? fb1 : zero;
+                double2 d0[CPT], d1[CPT];
 #pragma unroll
                 for (int m = 0; m < CPT; ++m) {
-                    ui[m] = cmul(Fc[m], m + u < CPT ? Ci[m + u] : Ni[m + u - CPT]);
-                    uo[m] = has_out ? cmul(Fc[m], m + u < CPT ? Co[m + u] : No[m + u - CPT])
-                                    : make_double2(0.0, 0.0);
+                    const double2 ci0 = m + u < CPT ? Ci[m + u] : Ni[m + u - CPT];
+                    const double2 ci1 = m + u + 1 < CPT ? Ci[m + u + 1] : Ni[m + u + 1 - CPT];
+                    const double2 co0 = m + u < CPT ? Co[m + u] : No[m + u - CPT];
+                    const double2 co1 = m + u + 1 < CPT ? Co[m + u + 1] : No[m + u + 1 - CPT];
+                    d0[m] = cmul(Fc[m], cfms(b0, co0, cmul(a0, ci0)));
+                    d1[m] = cmul(Fc[m], cfms(b1, co1, cmul(a1, ci1)));
                 }
-                // Ci[u] now serves no later row: reload it for block sb + 2 CPT
-                Ci[u] = cconj(F[wrap_p(qi + 2 * CPT + cb, P)]);
-                Co[u] = cconj(F[wrap_p(qo + 2 * CPT + cb, P)]);
-                step(ui, uo, st, has_out, ain, aout);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    Ci[u + k] = cconj(F[ldi]);
+                    Co[u + k] = cconj(F[ldo]);
+                    ldi = inc_wrap(ldi, P);
+                    ldo = inc_wrap(ldo, P);
+                }
+                step2(d0, d1, st);
             }
         };
         for (int sb = 0; sb < T; sb += 2 * CPT) {
@@ -443,33 +565,72 @@ k_dbs_box(const double2 *__restrict__ F, const double2 *__restrict__ S, DbsGeom 
                 block(Bi, Ai, Bo, Ao, sb + CPT);
         }
     } else {
-        // K >= 2: the products are the part sums, read row by row.
+        // K >= 2: raw is the part sums, read two rows ahead; d = entering
+        // row - leaving row.  Rows past the last entering one are not read
+        // (nothing is emitted from them).
         const double2 *Sb = S + cb + g.lo;     // column of element 0 in the rectangle
-        auto load_row = [&](double2 (&u)[CPT], int64_t q) {
-            const double2 *row = Sb + (q + g.lo) * g.SC;
+        auto load_d = [&](double2 (&d)[CPT], int stn) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
-                u[m] = row[m];
-        };
-        double2 ni[CPT], no[CPT];
-        load_row(ni, qa);
+                d[m] = make_double2(0.0, 0.0);
+            if (stn < T) {
+                const double2 *rin = Sb + ((int64_t)qa + stn + g.lo) * g.SC;
 #pragma unroll
-        for (int m = 0; m < CPT; ++m)
-            no[m] = make_double2(0.0, 0.0);
-        const double2 one = make_double2(1.0, 0.0);
-        for (int st = 0; st < T; ++st) {
-            double2 ui[CPT], uo[CPT];
+                for (int m = 0; m < CPT; ++m)
+                    d[m] = rin[m];
+                if (stn >= M3) {
+                    const double2 *rout = Sb + ((int64_t)qa + stn - M3 + g.lo) * g.SC;
+#pragma unroll
+                    for (int m = 0; m < CPT; ++m)
+                        d[m] = csub(d[m], rout[m]);
+                }
+            }
+        };
+        double2 n0[CPT], n1[CPT];
+        load_d(n0, 0);
+        load_d(n1, 1);
+        for (int st = 0; st < T; st += 2) {
+            double2 d0[CPT], d1[CPT];
 #pragma unroll
             for (int m = 0; m < CPT; ++m) {
-                ui[m] = ni[m];
-                uo[m] = no[m];
+                d0[m] = n0[m];
+                d1[m] = n1[m];
             }
-            if (st + 1 < T)
-                load_row(ni, (int64_t)qa + st + 1);
-            if (st + 1 >= M3 && st + 1 < T)
-                load_row(no, (int64_t)qa + st + 1 - M3);
-            step(ui, uo, st, st >= M3, one, one);
+            load_d(n0, st + 2);
+            load_d(n1, st + 3);
+            step2(d0, d1, st);
         }
+    }
+}
+
+// The strips' rows laid end to end are cut into runs of g.R rows, one per
+// workgroup; a run that reaches the end of a strip continues at the start
+// of the next.  Strip s starts at row offset s (H + 1) - TW s (s - 1).
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT)
+k_dbs_box(const double2 *__restrict__ F, const double2 *__restrict__ S, DbsGeom g,
+          double2 *__restrict__ out)
+{
+    __shared__ double2 lrow[2][NT * BOX_CPT];   // prefix sums of the two rows of a step
+    __shared__ double2 wtot[2][NT / 64];
+    auto first_row = [&](int64_t s) { return s * (g.H + 1) - (int64_t)g.TW * s * (s - 1); };
+    int64_t a = (int64_t)blockIdx.x * g.R;
+    const int64_t b = min(a + (int64_t)g.R, g.rows);
+    while (a < b) {
+        int s0 = 0, s1 = g.NS - 1;
+        while (s0 < s1) {
+            const int mid = (s0 + s1 + 1) >> 1;
+            if (first_row(mid) <= a)
+                s0 = mid;
+            else
+                s1 = mid - 1;
+        }
+        const int64_t o = first_row(s0);
+        const int c0 = s0 * g.TW;
+        const int ra = c0 + (int)(a - o);
+        const int rb = (int)min((int64_t)c0 + (b - o), (int64_t)g.H - c0 + 1);
+        box_run<MODE, NT>(F, S, g, out, c0, ra, rb, lrow, wtot);
+        a += rb - ra;
     }
 }
 
@@ -478,12 +639,11 @@ hipError_t launch_box(const DbsPlan &p, const double2 *F, const double2 *S, doub
                       hipStream_t s)
 {
     const DbsGeom &g = p.g;
-    const dim3 grid((unsigned)g.NSEG, (unsigned)g.NS);
+    const dim3 grid((unsigned)g.NSEG);
     switch (g.W) {
-    case 256:  k_dbs_box<MODE, 256, 1><<<grid, 256, 0, s>>>(F, S, g, out); break;
-    case 512:  k_dbs_box<MODE, 256, 2><<<grid, 256, 0, s>>>(F, S, g, out); break;
-    case 1024: k_dbs_box<MODE, 256, 4><<<grid, 256, 0, s>>>(F, S, g, out); break;
-    default:   k_dbs_box<MODE, 512, 4><<<grid, 512, 0, s>>>(F, S, g, out); break;
+    case 512:  k_dbs_box<MODE, 128><<<grid, 128, 0, s>>>(F, S, g, out); break;
+    case 1024: k_dbs_box<MODE, 256><<<grid, 256, 0, s>>>(F, S, g, out); break;
+    default:   k_dbs_box<MODE, 512><<<grid, 512, 0, s>>>(F, S, g, out); break;
     }
     return hipGetLastError();
 }

@@ -37,8 +37,11 @@ def test_validation_before_device(kw, code):
     assert st == code
 
 
-def test_timed_rejects_negative_rows():
-    st, _ = hos.hos_dbs_timed(FAKE, 0, 4096, 128, 9, 0, FAKE, FAKE, 1 << 40, None, seg_rows=-1)
+@pytest.mark.parametrize("seg,strip", [(-1, 0), (0, 256), (0, 1000), (0, 512)])
+def test_timed_rejects_bad_tuning(seg, strip):
+    M3 = 600 if strip == 512 else 9           # a strip narrower than the box
+    st, _ = hos.hos_dbs_timed(FAKE, 0, 4096, 2048, M3, 0, FAKE, FAKE, 1 << 40, None,
+                              seg_rows=seg, strip_w=strip)
     assert st == hos.HOS_EINVAL
 
 
@@ -56,7 +59,8 @@ def test_plan(n, P, M3):
     W, TW = info["W"], info["TW"]
     assert TW == W - M3 + 1 and TW >= 1
     assert info["NS"] * TW >= H // 2 + 1 > (info["NS"] - 1) * TW    # strips cover k2 <= H/2
-    assert info["NSEG"] * info["R"] >= H + 1
+    assert info["rows"] == sum(H - 2 * s * TW + 1 for s in range(info["NS"]))
+    assert info["NWG"] * info["R"] >= info["rows"] > (info["NWG"] - 1) * info["R"]
     if info["mode"] == 1:
         assert info["G"] * info["Kg"] >= info["K"] > (info["G"] - 1) * info["Kg"]
         assert info["SR"] == H + M3 and info["SC"] >= (info["NS"] - 1) * TW + W
@@ -69,48 +73,56 @@ def _pd_row_off(r, H):
     return tri(r) if r <= m + 1 else tri(m + 1) + tri(H - m) - tri(H + 1 - r)
 
 
-def _replay(x, P, M3, seg_rows=0):
-    """The smoothing kernel's loop order in numpy, workgroup by workgroup."""
-    info = hos.hos_dbs_plan_info(x.size, P, M3, seg_rows)
+def _replay(x, P, M3, seg_rows=0, strip_w=0):
+    """The smoothing kernel's work split and loop order in numpy: the
+    strips' rows end to end, cut into runs of R rows per workgroup."""
+    info = hos.hos_dbs_plan_info(x.size, P, M3, seg_rows, strip_w)
     K, W, TW, R = info["K"], info["W"], info["TW"], info["R"]
     lo, H = M3 // 2, (P - 1) // 2
     hi = M3 - 1 - lo
     F = np.array([np.fft.fft(x[i * P:(i + 1) * P] - x[i * P:(i + 1) * P].mean())
                   for i in range(K)])
     out = np.full(info["npd"], np.nan, dtype=np.complex128)
-    for s in range(info["NS"]):
-        for j in range(info["NSEG"]):
-            c0 = s * TW
-            ra, rend = c0 + j * R, H - c0 + 1
-            if ra >= rend:
-                continue
-            rb = min(ra + R, rend)
-            T, qa = rb - ra + M3 - 1, ra - lo
-            cw = c0 - lo + np.arange(W)
+    first = lambda s: s * (H + 1) - TW * s * (s - 1)
 
-            def hsum(q):
-                u = np.sum(F[:, q % P][:, None] * F[:, cw % P] * np.conj(F[:, (q + cw) % P]), 0)
-                pf = np.concatenate([[0], np.cumsum(u)])
-                return pf[np.arange(TW) + M3] - pf[np.arange(TW)]
-            v = np.zeros(TW, dtype=np.complex128)
-            for st in range(T):
-                v = v + hsum(qa + st) - (hsum(qa + st - M3) if st >= M3 else 0)
-                if st >= M3 - 1:
-                    r = qa + st - hi
-                    c = c0 + np.arange(TW)
-                    c = c[c <= min(r, H - r)]
-                    idx = _pd_row_off(r, H) + c
-                    assert np.isnan(out[idx]).all()
-                    out[idx] = v[:c.size] / (K * P * M3 * M3)
+    def run(c0, ra, rb):
+        T, qa = rb - ra + M3 - 1, ra - lo
+        cw = c0 - lo + np.arange(W)
+
+        def hsum(q):
+            u = np.sum(F[:, q % P][:, None] * F[:, cw % P] * np.conj(F[:, (q + cw) % P]), 0)
+            pf = np.concatenate([[0], np.cumsum(u)])
+            return pf[np.arange(TW) + M3] - pf[np.arange(TW)]
+        v = np.zeros(TW, dtype=np.complex128)
+        for st in range(T):
+            v = v + hsum(qa + st) - (hsum(qa + st - M3) if st >= M3 else 0)
+            if st >= M3 - 1:
+                r = qa + st - hi
+                c = c0 + np.arange(TW)
+                c = c[c <= min(r, H - r)]
+                idx = _pd_row_off(r, H) + c
+                assert np.isnan(out[idx]).all()
+                out[idx] = v[:c.size] / (K * P * M3 * M3)
+
+    for w in range(info["NWG"]):
+        a, b = w * R, min(w * R + R, info["rows"])
+        while a < b:
+            s = max(k for k in range(info["NS"]) if first(k) <= a)
+            c0 = s * TW
+            ra = c0 + a - first(s)
+            rb = min(c0 + b - first(s), H - c0 + 1)
+            run(c0, ra, rb)
+            a += rb - ra
     return out
 
 
-@pytest.mark.parametrize("n,P,M3,seg", [(64, 64, 5, 0), (300, 30, 4, 0), (97, 32, 1, 0),
-                                        (40, 40, 40, 0), (700, 300, 7, 0), (700, 300, 7, 5),
-                                        (1200, 600, 257, 0)])
-def test_kernel_loop_order_replay(n, P, M3, seg):
+@pytest.mark.parametrize("n,P,M3,seg,strip", [
+    (64, 64, 5, 0, 0), (300, 30, 4, 0, 0), (97, 32, 1, 0, 0), (40, 40, 40, 0, 0),
+    (700, 300, 7, 0, 0), (700, 300, 7, 5, 0), (1200, 600, 257, 0, 0), (3000, 3000, 300, 64, 512),
+    (2000, 2000, 5, 0, 1024)])
+def test_kernel_loop_order_replay(n, P, M3, seg, strip):
     x = synth.iid_exp_centered(n, 3)
-    got = _replay(x, P, M3, seg)
+    got = _replay(x, P, M3, seg, strip)
     assert not np.isnan(got).any()
     if P <= 300:
         ref = oracle.dbs(x, P, M3)
