@@ -17,7 +17,11 @@ timed on the host cores on a bounded sample of lags (``cpu_baseline``).
 A second record inside the line, ``trispectrum``, measures the fourth-order
 path on its own workload: n = 2^18 float32 samples of the cubic process
 x_t = e_t + 0.4 e_{t-1} e_{t-2} e_{t-3}, M = 48, six-factor Parzen window,
-96^3 DFT; metric n (2M+1)^3 lag-sums per second.
+96^3 DFT; metric n (2M+1)^3 lag-sums per second.  Further records:
+``batched`` (4096 uneven series in one call), ``loss`` (bispectrum-matching
+loss forward and adjoint) and ``direct_method`` (Algorithm DBS with
+window-sum smoothing, n = 2^16 as one part, 1023 x 1023 box, with an HBM
+roofline of the smoothing kernel).
 
 ``traffic`` (HBM bytes per launch of the contraction) is read from the
 committed PMC summary when the contraction's source still matches the one it
@@ -306,6 +310,70 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup):
             "paths": out}
 
 
+def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds):
+    """The direct method (Algorithm DBS with window-sum smoothing): one
+    float32 quadratic-process series of 2^16 samples as one part, a
+    1023 x 1023 box; metric smoothed principal-domain points per second.
+    Roofline of the smoothing kernel against HBM: its algorithmic traffic is
+    the principal-domain output (16 B a point; the 1 MB spectrum it reads is
+    L2-resident)."""
+    x, cfg = synth.workload_dbs()
+    P, M3 = cfg["P"], cfg["M3"]
+    xt = torch.from_numpy(x).cuda()
+    info = hos.hos_dbs_plan_info(x.size, P, M3)
+    ws = torch.empty(info["ws_bytes"], dtype=torch.uint8, device="cuda")
+    npd = info["npd"]
+    print("bench: direct method n=%d M3=%d" % (x.size, M3), file=sys.stderr, flush=True)
+    ms = _time(torch, lambda: hos.dbs(xt, P, M3, workspace=ws), max(3, steps // 5),
+               max(2, warmup // 5))
+    stages = [hos.dbs(xt, P, M3, workspace=ws, timed=True)[1] for _ in range(5)]
+    stage_ms = {k: float(np.median([d[k] for d in stages])) for k in stages[0]}
+    B = hos.dbs(xt, P, M3, workspace=ws).cpu().numpy()
+    H = (P - 1) // 2
+    rows = np.arange(H + 1)
+    lens = np.minimum(rows, H - rows) + 1
+    k1 = np.repeat(rows, lens)
+    k2 = np.arange(k1.size) - np.repeat(np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    pick = np.random.default_rng(5).integers(0, npd, 12)
+    ref = oracle.dbs_at(x, P, M3, k1[pick], k2[pick])
+    err = float(np.max(np.abs(B[pick] - ref)) / np.max(np.abs(ref)))
+    out_bytes = 16.0 * npd
+    t_s = stage_ms["smooth"] * 1e-3
+    sweep = {}
+    for m3 in (5, 255):
+        st = [hos.dbs(xt, P, m3, workspace=None, timed=True)[1]["smooth"] for _ in range(4)]
+        sweep[str(m3)] = {"smooth_ms": float(np.median(st)),
+                          "hbm_frac": out_bytes / (np.median(st) * 1e-3) / 8.0e12}
+    rec = {"metric": "smoothed bispectrum points/s (principal domain of the P grid)",
+           "value": npd / (ms * 1e-3), "unit": "points/s", "ms_per_step": ms, "dtype": "f64",
+           "config": {"workload": "direct method (Algorithm DBS): one float32 "
+                                  "quadratic-process series, n = 2^16, one part P = 2^16, "
+                                  "box M3 = 1023, principal-domain output",
+                      "n": int(x.size), "P": P, "M3": M3, "K": info["K"], "points": npd},
+           "stage_ms": stage_ms, "rel_err_sampled": err, "within_tol": err <= 1e-10,
+           "roofline": {"bound": "hbm", "kernel": "k_dbs_box",
+                        "achieved": out_bytes / t_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                        "frac": out_bytes / t_s / 8.0e12, "traffic": None,
+                        "bytes_per_launch": out_bytes, "avg_launch_ms": stage_ms["smooth"]},
+           "box_sweep_same_series": sweep}
+    if cpu_seconds > 0:
+        # the oracle's explicit box sums at sampled points (M3^2 products each)
+        t0 = time.perf_counter()
+        oracle.dbs_at(x, P, M3, k1[:2], k2[:2])
+        per = (time.perf_counter() - t0) / 2
+        k = int(max(4, min(2000, cpu_seconds / max(per, 1e-9))))
+        sel = np.random.default_rng(6).integers(0, npd, k)
+        t0 = time.perf_counter()
+        oracle.dbs_at(x, P, M3, k1[sel], k2[sel])
+        t = time.perf_counter() - t0
+        rec["cpu_oracle"] = {"value": k / t, "unit": "points/s", "cores": 1, "kind": "oracle",
+                             "sample": "%d principal-domain points, explicit %d x %d box "
+                                       "sums in FP64 numpy (%.1f s)" % (k, M3, M3, t)}
+    print("bench: direct method %.3f ms/call (smooth %.3f ms), err %.2e" %
+          (ms, stage_ms["smooth"], err), file=sys.stderr, flush=True)
+    return rec
+
+
 def traffic_record(_unused=None):
     """HBM bytes per launch of the c3 contraction from the committed PMC
     summary, if it was taken on the current kernel source."""
@@ -356,6 +424,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tri", action="store_true", help="skip the trispectrum record")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and loss records")
+    ap.add_argument("--no-dbs", action="store_true", help="skip the direct-method record")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (the "
                          "reference kernel for scaling HBM counters)")
@@ -438,6 +507,9 @@ def main():
         rec["trispectrum"] = bench_trispectrum(
             hos, torch, oracle, synth, list(paths), args.steps, args.warmup,
             0.0 if args.no_cpu_baseline else 5.0)
+    if not args.no_dbs:
+        rec["direct_method"] = bench_dbs(hos, torch, oracle, synth, args.steps, args.warmup,
+                                         0.0 if args.no_cpu_baseline else 5.0)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(oracle, x, M, args.cpu_seconds)

@@ -376,9 +376,7 @@ __device__ inline double2 waves_before(const double2 *tot, int lane, int wave)
 // the column sums take the window sums of d.  Thread t scans the 4
 // consecutive widened columns e = 4t .. 4t+3 and keeps the column sums of
 // the output columns j = t + NT k, whose window e = j .. j+M3-1 is the
-// difference of two prefix sums read from LDS.  LDS rows are stored with
-// the 4 entries of each thread rotated by (e >> 4) & 3, which keeps the
-// writes and the reads free of bank conflicts.  Rows go two at a time:
+// difference of two prefix sums read from LDS.  Rows go RPS at a time:
 // their scans share one pair of barriers.
 constexpr int BOX_CPT = 4;
 
@@ -402,11 +400,12 @@ __device__ inline double2 cfms(double2 a, double2 b, double2 acc)
 }
 
 // One run: output rows [ra, rb) of the strip starting at column c0.
-template <int MODE, int NT>
+template <int MODE, int NT, int RPS>
 __device__ __forceinline__ void box_run(const double2 *__restrict__ F,
                                         const double2 *__restrict__ S, const DbsGeom &g,
                                         double2 *__restrict__ out, int c0, int ra, int rb,
-                                        double2 (*lrow)[NT * BOX_CPT], double2 (*wtot)[NT / 64])
+                                        double2 (*lrow)[BOX_CPT * (NT + 4)],
+                                        double2 (*wtot)[NT / 64])
 {
     constexpr int CPT = BOX_CPT;
     constexpr int NW = NT / 64;
@@ -417,7 +416,10 @@ __device__ __forceinline__ void box_run(const double2 *__restrict__ F,
     const int qa = ra - g.lo;                 // first of them
     const int e0 = t * CPT;                   // first owned widened (and output) column
     const int64_t cb = (int64_t)c0 - g.lo + e0;
-    auto sw = [](int e) { return (e & ~3) | (((e & 3) + (e >> 4)) & 3); };
+    // LDS position of widened column e: four segments (e mod 4) of NT + 4
+    // entries; the writes of one m by consecutive lanes are consecutive, and
+    // a read of 16 consecutive columns touches 16 distinct bank groups
+    auto sw = [](int e) { return (e & 3) * (NT + 4) + (e >> 2); };
 
     double2 v[CPT];
 #pragma unroll
@@ -468,26 +470,29 @@ __device__ __forceinline__ void box_run(const double2 *__restrict__ F,
             ++r;
         }
     };
-    // Row steps st and st + 1 from their difference rows.
-    auto step2 = [&](double2 (&d0)[CPT], double2 (&d1)[CPT], int st) {
-        double2 x0, x1;
-        scan1(d0, wtot[0], x0);
-        scan1(d1, wtot[1], x1);
+    // Row steps st .. st + RPS - 1 from their difference rows.
+    auto stepn = [&](double2 (&d)[RPS][CPT], int st) {
+        double2 x[RPS];
+#pragma unroll
+        for (int k = 0; k < RPS; ++k)
+            scan1(d[k], wtot[k], x[k]);
         lds_barrier();
-        scan2(d0, wtot[0], x0, lrow[0]);
-        scan2(d1, wtot[1], x1, lrow[1]);
+#pragma unroll
+        for (int k = 0; k < RPS; ++k)
+            scan2(d[k], wtot[k], x[k], lrow[k]);
         lds_barrier();
-        update(lrow[0], st);
-        update(lrow[1], st + 1);
+#pragma unroll
+        for (int k = 0; k < RPS; ++k)
+            update(lrow[k], st + k);
     };
 
     if constexpr (MODE == 0) {
         // K = 1: raw(q, c) = F(c) [F(q) conj F(q + c)].  conj F(q + cb + m)
-        // for the rows of the current block of CPT steps comes from two
-        // register halves C (this block) and N (the next): a value is dead
-        // once its row has passed and is reloaded at once for the block
-        // after next, so each step loads one value per half pair, CPT steps
-        // before its use.  Entering rows use Ci/Ni, leaving rows Co/No.
+        // for the CPT rows of the current block comes from two register
+        // halves C (this block) and N (the next); once the block's products
+        // are formed C is reloaded for the block after next, so the loads
+        // are issued a whole block before their use.  Entering rows use
+        // Ci/Ni, leaving rows Co/No.
         double2 Fc[CPT], Ai[CPT], Bi[CPT], Ao[CPT], Bo[CPT];
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
@@ -531,32 +536,36 @@ __device__ __forceinline__ void box_run(const double2 *__restrict__ F,
                 fav = F[ai];
                 fbv = F[ao];
             }
+            const double2 zero = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int u = 0; u < CPT; u += 2) {
-                const int st = sb + u;
-                // the leaving rows' factors are 0 while the box fills
-                const double2 zero = make_double2(0.0, 0.0);
-                const double2 a0 = lane_c(fa_cur, kb + u), a1 = lane_c(fa_cur, kb + u + 1);
-                const double2 fb0 = lane_c(fb_cur, kb + u), fb1 = lane_c(fb_cur, kb + u + 1);
-                const double2 b0 = st >= M3 ? fb0 : zero, b1 = st + 1 >= M3 ? fb1 : zero;
-                double2 d0[CPT], d1[CPT];
+            for (int u0 = 0; u0 < CPT; u0 += RPS) {
+                double2 d[RPS][CPT];
 #pragma unroll
-                for (int m = 0; m < CPT; ++m) {
-                    const double2 ci0 = m + u < CPT ? Ci[m + u] : Ni[m + u - CPT];
-                    const double2 ci1 = m + u + 1 < CPT ? Ci[m + u + 1] : Ni[m + u + 1 - CPT];
-                    const double2 co0 = m + u < CPT ? Co[m + u] : No[m + u - CPT];
-                    const double2 co1 = m + u + 1 < CPT ? Co[m + u + 1] : No[m + u + 1 - CPT];
-                    d0[m] = cmul(Fc[m], cfms(b0, co0, cmul(a0, ci0)));
-                    d1[m] = cmul(Fc[m], cfms(b1, co1, cmul(a1, ci1)));
+                for (int k = 0; k < RPS; ++k) {
+                    const int u = u0 + k, st = sb + u;
+                    // the leaving rows' factors are 0 while the box fills
+                    const double2 a = lane_c(fa_cur, kb + u);
+                    const double2 fb = lane_c(fb_cur, kb + u);
+                    const double2 b = st >= M3 ? fb : zero;
+#pragma unroll
+                    for (int m = 0; m < CPT; ++m) {
+                        const double2 ci = m + u < CPT ? Ci[m + u] : Ni[m + u - CPT];
+                        const double2 co = m + u < CPT ? Co[m + u] : No[m + u - CPT];
+                        d[k][m] = cmul(Fc[m], cfms(b, co, cmul(a, ci)));
+                    }
                 }
+                if (u0 + RPS == CPT) {
+                    // every value of Ci / Co has served: reload them for the
+                    // block after next
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    Ci[u + k] = cconj(F[ldi]);
-                    Co[u + k] = cconj(F[ldo]);
-                    ldi = inc_wrap(ldi, P);
-                    ldo = inc_wrap(ldo, P);
+                    for (int k = 0; k < CPT; ++k) {
+                        Ci[k] = cconj(F[ldi]);
+                        Co[k] = cconj(F[ldo]);
+                        ldi = inc_wrap(ldi, P);
+                        ldo = inc_wrap(ldo, P);
+                    }
                 }
-                step2(d0, d1, st);
+                stepn(d, sb + u0);
             }
         };
         for (int sb = 0; sb < T; sb += 2 * CPT) {
@@ -565,7 +574,7 @@ __device__ __forceinline__ void box_run(const double2 *__restrict__ F,
                 block(Bi, Ai, Bo, Ao, sb + CPT);
         }
     } else {
-        // K >= 2: raw is the part sums, read two rows ahead; d = entering
+        // K >= 2: raw is the part sums, read one step ahead; d = entering
         // row - leaving row.  Rows past the last entering one are not read
         // (nothing is emitted from them).
         const double2 *Sb = S + cb + g.lo;     // column of element 0 in the rectangle
@@ -586,19 +595,21 @@ __device__ __forceinline__ void box_run(const double2 *__restrict__ F,
                 }
             }
         };
-        double2 n0[CPT], n1[CPT];
-        load_d(n0, 0);
-        load_d(n1, 1);
-        for (int st = 0; st < T; st += 2) {
-            double2 d0[CPT], d1[CPT];
+        double2 n[RPS][CPT];
 #pragma unroll
-            for (int m = 0; m < CPT; ++m) {
-                d0[m] = n0[m];
-                d1[m] = n1[m];
-            }
-            load_d(n0, st + 2);
-            load_d(n1, st + 3);
-            step2(d0, d1, st);
+        for (int k = 0; k < RPS; ++k)
+            load_d(n[k], k);
+        for (int st = 0; st < T; st += RPS) {
+            double2 d[RPS][CPT];
+#pragma unroll
+            for (int k = 0; k < RPS; ++k)
+#pragma unroll
+                for (int m = 0; m < CPT; ++m)
+                    d[k][m] = n[k][m];
+#pragma unroll
+            for (int k = 0; k < RPS; ++k)
+                load_d(n[k], st + RPS + k);
+            stepn(d, st);
         }
     }
 }
@@ -606,13 +617,15 @@ __device__ __forceinline__ void box_run(const double2 *__restrict__ F,
 // The strips' rows laid end to end are cut into runs of g.R rows, one per
 // workgroup; a run that reaches the end of a strip continues at the start
 // of the next.  Strip s starts at row offset s (H + 1) - TW s (s - 1).
+// Rows per step: 4 (2 for the widest strips, whose registers would not hold 4).
 template <int MODE, int NT>
 __global__ void __launch_bounds__(NT)
 k_dbs_box(const double2 *__restrict__ F, const double2 *__restrict__ S, DbsGeom g,
           double2 *__restrict__ out)
 {
-    __shared__ double2 lrow[2][NT * BOX_CPT];   // prefix sums of the two rows of a step
-    __shared__ double2 wtot[2][NT / 64];
+    constexpr int RPS = NT >= 512 ? 2 : 4;
+    __shared__ double2 lrow[RPS][BOX_CPT * (NT + 4)];   // prefix sums of the rows of a step
+    __shared__ double2 wtot[RPS][NT / 64];
     auto first_row = [&](int64_t s) { return s * (g.H + 1) - (int64_t)g.TW * s * (s - 1); };
     int64_t a = (int64_t)blockIdx.x * g.R;
     const int64_t b = min(a + (int64_t)g.R, g.rows);
@@ -629,7 +642,7 @@ k_dbs_box(const double2 *__restrict__ F, const double2 *__restrict__ S, DbsGeom 
         const int c0 = s0 * g.TW;
         const int ra = c0 + (int)(a - o);
         const int rb = (int)min((int64_t)c0 + (b - o), (int64_t)g.H - c0 + 1);
-        box_run<MODE, NT>(F, S, g, out, c0, ra, rb, lrow, wtot);
+        box_run<MODE, NT, RPS>(F, S, g, out, c0, ra, rb, lrow, wtot);
         a += rb - ra;
     }
 }
