@@ -46,6 +46,8 @@ METRIC = "cumulant lag-sums/s (n·(2M+1)^2/s), split-prec vs FP32 at ≤1e-5 rel
 METRIC4 = "cumulant lag-sums/s (n·(2M+1)^3/s)"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_c3_contract_n2p20_M512_traffic.txt")
 C3_SOURCE = os.path.join(ROOT, "paper_1805_11775_amd", "csrc", "k_c3.hip")
+DBS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dbs_box_n2p16_M3_1023_traffic.txt")
+DBS_SOURCE = os.path.join(ROOT, "paper_1805_11775_amd", "csrc", "k_dbs.hip")
 PEAK = {"fp32": 157.3e12, "split_fp16": 2.5166e15, "split_bf16": 2.5166e15}
 DTYPE = {"fp32": "f32", "split_fp16": "f16", "split_bf16": "bf16"}
 TOL = {"fp32": 1e-6, "split_fp16": 1e-5, "split_bf16": 1e-5}
@@ -310,7 +312,7 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup):
             "paths": out}
 
 
-def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds):
+def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds, sweep_box=True):
     """The direct method (Algorithm DBS with window-sum smoothing): one
     float32 quadratic-process series of 2^16 samples as one part, a
     1023 x 1023 box; metric smoothed principal-domain points per second.
@@ -340,7 +342,7 @@ def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds):
     out_bytes = 16.0 * npd
     t_s = stage_ms["smooth"] * 1e-3
     sweep = {}
-    for m3 in (5, 255):
+    for m3 in (5, 255) if sweep_box else ():
         st = [hos.dbs(xt, P, m3, workspace=None, timed=True)[1]["smooth"] for _ in range(4)]
         sweep[str(m3)] = {"smooth_ms": float(np.median(st)),
                           "hbm_frac": out_bytes / (np.median(st) * 1e-3) / 8.0e12}
@@ -353,7 +355,8 @@ def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds):
            "stage_ms": stage_ms, "rel_err_sampled": err, "within_tol": err <= 1e-10,
            "roofline": {"bound": "hbm", "kernel": "k_dbs_box",
                         "achieved": out_bytes / t_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                        "frac": out_bytes / t_s / 8.0e12, "traffic": None,
+                        "frac": out_bytes / t_s / 8.0e12,
+                        "traffic": traffic_record(DBS_TRAFFIC_FILE, DBS_SOURCE),
                         "bytes_per_launch": out_bytes, "avg_launch_ms": stage_ms["smooth"]},
            "box_sweep_same_series": sweep}
     if cpu_seconds > 0:
@@ -374,17 +377,17 @@ def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds):
     return rec
 
 
-def traffic_record(_unused=None):
-    """HBM bytes per launch of the c3 contraction from the committed PMC
-    summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_record(path=TRAFFIC_FILE, source=C3_SOURCE):
+    """HBM bytes per launch of a kernel from its committed PMC summary, if
+    that was taken on the current kernel source."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = hashlib.sha256(open(C3_SOURCE, "rb").read()).hexdigest()
+    src = hashlib.sha256(open(source, "rb").read()).hexdigest()
     if kv.get("kernel_source_sha256") != src:
         return None
     try:
@@ -425,6 +428,8 @@ def main():
     ap.add_argument("--no-tri", action="store_true", help="skip the trispectrum record")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and loss records")
     ap.add_argument("--no-dbs", action="store_true", help="skip the direct-method record")
+    ap.add_argument("--no-dbs-sweep", action="store_true",
+                    help="time the direct method at its workload's box size only")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (the "
                          "reference kernel for scaling HBM counters)")
@@ -494,7 +499,7 @@ def main():
                    "n": n, "M": M, "nfft": N, "path": head},
         "roofline": {"bound": "mfma", "kernel": "k_c3_contract", "achieved": flops / t_k / 1e12,
                      "peak": PEAK[head] / 1e12, "unit": "TFLOP/s",
-                     "frac": flops / t_k / PEAK[head], "traffic": traffic_record(None),
+                     "frac": flops / t_k / PEAK[head], "traffic": traffic_record(),
                      "flops_per_launch": flops, "avg_launch_ms": hp["stage_ms"]["contract"]},
         "paths": paths,
     }
@@ -509,7 +514,8 @@ def main():
             0.0 if args.no_cpu_baseline else 5.0)
     if not args.no_dbs:
         rec["direct_method"] = bench_dbs(hos, torch, oracle, synth, args.steps, args.warmup,
-                                         0.0 if args.no_cpu_baseline else 5.0)
+                                         0.0 if args.no_cpu_baseline else 5.0,
+                                         not args.no_dbs_sweep)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(oracle, x, M, args.cpu_seconds)
