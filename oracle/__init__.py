@@ -275,6 +275,24 @@ def trispectrum(x, M: int, nfft: int, window: str = "parzen",
     return c, T
 
 
+def bispectrum_segments(x, P: int, M: int, nfft: int, window: str = "parzen",
+                        centered: bool = True):
+    """Segment averaging for the indirect estimator: Algorithm DBS steps 1,
+    2 and 6 around the cumulant.  K = floor(n / P) segments of P consecutive
+    samples (trailing samples unused), each centred on its own mean (step 2),
+    the third cumulant of each (the single-series estimator above, with the
+    segment as the record), their average over the segments (step 6), then
+    the window and the DFT as in ``bispectrum``.  Returns (c3, B)."""
+    x = _f64(x)
+    K = x.size // P
+    c = np.zeros((2 * M + 1, 2 * M + 1))
+    for i in range(K):
+        c += c3_hexagon(x[i * P:(i + 1) * P], M, centered)
+    c /= K
+    B = np.fft.fft2(place_circular(c * window3(M, window), M, nfft))
+    return c, B
+
+
 # --------------------------------------------------------------------------
 # Principal domain (Algorithm DBS step 4) and the matching loss.
 # --------------------------------------------------------------------------

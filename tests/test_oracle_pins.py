@@ -495,3 +495,45 @@ def test_dbs_at_matches_dbs():
         pick = np.arange(0, k1.size, 5)
         got = oracle.dbs_at(x, 30, M3, k1[pick], k2[pick])
         assert np.max(np.abs(got - full[pick])) < 1e-12 * np.max(np.abs(full))
+
+
+# --------------------------------------------------------------------------
+# Segment averaging for the indirect estimator
+# --------------------------------------------------------------------------
+def test_segments_lag_zero_is_mean_central_third_moment():
+    """M = 0: c3(0,0) is the average over segments of each segment's third
+    central moment (scipy's, with 1/P)."""
+    from scipy import stats
+    x = synth.iid_exp_centered(5 * 40 + 3, 21)
+    c, _ = oracle.bispectrum_segments(x, 40, 0, 2, window="none")
+    expect = np.mean([stats.moment(x[i * 40:(i + 1) * 40], 3) for i in range(5)])
+    assert abs(c[0, 0] - expect) < 1e-13 * abs(expect)
+
+
+def test_segments_centre_each_segment():
+    """A different constant added to each segment changes nothing; K copies
+    of one segment give that segment's estimate; trailing samples are
+    ignored."""
+    seg = synth.quadratic_process(50, 9)
+    x = np.concatenate([seg + 3.0, seg - 7.5, seg, [100.0] * 7])
+    c, B = oracle.bispectrum_segments(x, 50, 6, 12)
+    c1, B1 = oracle.bispectrum(seg, 6, 12)
+    assert np.max(np.abs(c - c1)) < 1e-12 * np.max(np.abs(c1))
+    assert np.max(np.abs(B - B1)) < 1e-12 * np.max(np.abs(B1))
+
+
+def test_segments_match_direct_method_parts():
+    """No window, M = P - 1, N = 2P: each segment's indirect B equals N/P
+    times the direct method's raw product of the segment centred and
+    zero-padded to N, so the segment average on the principal domain is N/P
+    times the direct method over those padded parts with no smoothing."""
+    P, K, N = 12, 4, 24
+    x = synth.iid_exp_centered(P * K, 31)
+    _, B = oracle.bispectrum_segments(x, P, P - 1, N, window="none")
+    parts = []
+    for i in range(K):
+        s = x[i * P:(i + 1) * P]
+        parts.append(np.concatenate([s - s.mean(), np.zeros(N - P)]))
+    direct = oracle.dbs(np.concatenate(parts), N, 1)
+    k1, k2 = oracle.pd_indices(N)
+    assert np.max(np.abs(B[k1, k2] - direct * N / P)) < 1e-10 * np.max(np.abs(direct))
