@@ -19,7 +19,9 @@ path on its own workload: n = 2^18 float32 samples of the cubic process
 x_t = e_t + 0.4 e_{t-1} e_{t-2} e_{t-3}, M = 48, six-factor Parzen window,
 96^3 DFT; metric n (2M+1)^3 lag-sums per second.  Further records:
 ``batched`` (4096 uneven series in one call), ``loss`` (bispectrum-matching
-loss forward and adjoint) and ``direct_method`` (Algorithm DBS with
+loss forward and adjoint), ``segments`` (the headline series in 16
+segments, each centred on its own mean, cumulants averaged) and
+``direct_method`` (Algorithm DBS with
 window-sum smoothing, n = 2^16 as one part, 1023 x 1023 box, with an HBM
 roofline of the smoothing kernel).
 
@@ -312,6 +314,69 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup):
             "paths": out}
 
 
+def bench_segments(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds):
+    """Segment averaging: the headline series cut into 16 segments of
+    65536 samples, each centred on its own mean, c3 averaged, Parzen window,
+    1024 x 1024 DFT; metric n (2M+1)^2 lag-sums/s as for one series.  The
+    contraction (k_c3_items over the 16 segments) is timed by the batched
+    entry point's stage events on the same plan."""
+    x, cfg = synth.workload_segments()
+    P, M = cfg["P"], cfg["M"]
+    K = x.size // P
+    xt = torch.from_numpy(x).cuda()
+    lagsums = float(K * P) * (2 * M + 1) ** 2
+    flops = K * 2.0 * P * (M + 1) * (M + 2) / 2
+    w1, w2 = sample_lags(M, 120, seed=13)
+    ref = np.mean([oracle.c3_at(x[i * P:(i + 1) * P], w1, w2) for i in range(K)], 0)
+    ref[np.abs(w1 - w2) > M] = 0.0
+    out = {}
+    for path in paths:
+        plan = hos.BatchPlan([P] * K, [M] * K, path=path, segments=True)
+        ms = _time(torch, lambda: hos.bispectrum_segments(xt, P, M, path=path, plan=plan),
+                   max(3, steps // 5), max(2, warmup // 5))
+        st = [hos.bispectrum_batched_timed(xt, plan)[2] for _ in range(3)]
+        stage_ms = {k: float(np.median([d[k] for d in st])) for k in st[0]}
+        c3, _ = hos.bispectrum_segments(xt, P, M, path=path, plan=plan)
+        c3 = c3.cpu().numpy()
+        err = float(np.max(np.abs(c3[w1 + M, w2 + M] - ref)) / np.max(np.abs(ref)))
+        out[path] = {"ms_per_call": ms, "value": lagsums / (ms * 1e-3), "rel_err": err,
+                     "within_tol": err <= TOL[path], "batched_stage_ms": stage_ms,
+                     "contract_tflops": flops / (stage_ms["contract"] * 1e-3) / 1e12,
+                     "contract_frac": flops / (stage_ms["contract"] * 1e-3) / PEAK[path]}
+        print("bench: segments %s %.3f ms/call, err %.2e" % (path, ms, err), file=sys.stderr,
+              flush=True)
+        del plan
+    head = "split_fp16" if "split_fp16" in out else next(iter(out))
+    h = out[head]
+    rec = {"metric": METRIC, "value": h["value"], "unit": "lag-sums/s",
+           "ms_per_step": h["ms_per_call"], "dtype": DTYPE[head],
+           "config": {"workload": "segment-averaged bispectrum: n=2^20 float32 quadratic "
+                                  "process in 16 segments of 65536 (each centred on its own "
+                                  "mean), M=512, Parzen window, 1024x1024 DFT",
+                      "n": int(K * P), "P": P, "K": K, "M": M, "path": head},
+           "roofline": {"bound": "mfma", "kernel": "k_c3_items",
+                        "achieved": flops / (h["batched_stage_ms"]["contract"] * 1e-3) / 1e12,
+                        "peak": PEAK[head] / 1e12, "unit": "TFLOP/s",
+                        "frac": h["contract_frac"], "traffic": None,
+                        "flops_per_launch": flops,
+                        "avg_launch_ms": h["batched_stage_ms"]["contract"]},
+           "paths": out}
+    if cpu_seconds > 0:
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < cpu_seconds:
+            oracle.c3_at(x[k % K * P:(k % K + 1) * P], w1, w2)
+            k += 1
+        t = time.perf_counter() - t0
+        rec["cpu_oracle"] = {"value": k * w1.size * P / t, "unit": "lag-sums/s",
+                             "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                         len(os.sched_getaffinity(0)))),
+                             "kind": "oracle",
+                             "sample": "%d segments x %d lags x %d samples, FP64 brute-force "
+                                       "c3 (%.1f s)" % (k, w1.size, P, t)}
+    return rec
+
+
 def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds, sweep_box=True):
     """The direct method (Algorithm DBS with window-sum smoothing): one
     float32 quadratic-process series of 2^16 samples as one part, a
@@ -512,6 +577,9 @@ def main():
         rec["trispectrum"] = bench_trispectrum(
             hos, torch, oracle, synth, list(paths), args.steps, args.warmup,
             0.0 if args.no_cpu_baseline else 5.0)
+    if not args.no_batch:
+        rec["segments"] = bench_segments(hos, torch, oracle, synth, list(paths), args.steps,
+                                         args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
     if not args.no_dbs:
         rec["direct_method"] = bench_dbs(hos, torch, oracle, synth, args.steps, args.warmup,
                                          0.0 if args.no_cpu_baseline else 5.0,

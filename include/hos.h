@@ -104,6 +104,7 @@ typedef enum hos_path {
 /* Flags. */
 #define HOS_NO_CENTER 1u     /* use x as given (no mean removal); for tests      */
 #define HOS_PLAN_ADJOINT 16u /* batch plan flag: also lay out the adjoint buffers */
+#define HOS_PLAN_SEGMENTS 32u /* batch plan flag: lay out hos_bispectrum_segments' buffers */
 
 /* Human-readable text for a status code (static storage). */
 const char *hos_strerror(int status);
@@ -255,7 +256,8 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
 /* Plan and workspace sizes for a batch.  n, M: host arrays of `batch`
  * entries (n >= 2, 0 <= M < n, DFT size N <= 2048, i.e. M <= 1024 with
  * the Parzen window and M <= 1023 without; M <= 320 with HOS_PLAN_ADJOINT).
- * window: hos_window.  flags: HOS_NO_CENTER, HOS_PLAN_ADJOINT (lay out the
+ * window: hos_window.  flags: HOS_NO_CENTER, HOS_PLAN_SEGMENTS (see
+ * hos_bispectrum_segments; needs one M for every series), HOS_PLAN_ADJOINT (lay out the
  * buffers hos_bispectrum_loss_bwd needs).  tile_nb: NULL, or a host array
  * of `batch` tile choices for the contraction, 0 = built-in rule, 2 = tiles
  * of 2 x 2 matrix-core blocks (split paths only), 4 = 4 x 4 blocks; this is
@@ -331,6 +333,24 @@ int hos_bispectrum_loss_bwd(const void *x, int32_t dtype, const void *plan_host,
                             const void *plan_dev, const double *B_pd, const double *target_pd,
                             const double *dL, void *dx, void *ws, size_t ws_bytes,
                             hipStream_t stream);
+
+/*
+ * Segment averaging (Algorithm DBS steps 1, 2 and 6 around the cumulant):
+ * the series of a batch plan are the segments of one record, each centred on
+ * its own mean; their third cumulants are averaged,
+ *   c3(w) = (1/S) sum_s c3_s(w),
+ * and the average is windowed and transformed as by hos_bispectrum.  The
+ * plan must have been made with HOS_PLAN_SEGMENTS, every series with the same
+ * M (then one DFT size N, the plan's); x is the packed input, so segments of
+ * P consecutive samples of one record are a plan with n[s] = P.
+ *   c3  device, (2M+1)^2 float64 (as hos_bispectrum), or NULL.
+ *   B   device, N x N interleaved complex128 (as hos_bispectrum), or NULL
+ *       (not both NULL).
+ * Returns HOS_EINVAL for a plan without the flag or without one M.
+ */
+int hos_bispectrum_segments(const void *x, int32_t dtype, const void *plan_host,
+                            const void *plan_dev, double *c3, double *B, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
 
 /*
  * ------------------------------------------------------------------------

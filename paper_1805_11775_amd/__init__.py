@@ -41,6 +41,7 @@ HOS_PATH_SPLIT_FP16 = 1
 HOS_PATH_SPLIT_BF16 = 2
 HOS_NO_CENTER = 1
 HOS_PLAN_ADJOINT = 16
+HOS_PLAN_SEGMENTS = 32
 
 PATHS = {"fp32": HOS_PATH_FP32, "split_fp16": HOS_PATH_SPLIT_FP16,
          "split_bf16": HOS_PATH_SPLIT_BF16}
@@ -95,6 +96,7 @@ def _load_lib():
         "hos_bispectrum_batched_timed": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, sz, vp,
                                                         ctypes.POINTER(ctypes.c_float)]),
         "hos_bispectrum_loss_fwd": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "hos_bispectrum_segments": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
         "hos_bispectrum_loss_bwd": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz,
                                                    vp]),
         "hos_c3_schedule": (ctypes.c_int, [i64, i32, i32, p64, p64, p64, i64]),
@@ -414,16 +416,18 @@ class BatchPlan:
     ``to(device)`` has run, an identical device copy."""
 
     def __init__(self, n, M, window="parzen", path="fp32", center=True, adjoint=False,
-                 tile=None):
+                 tile=None, segments=False):
         """``tile``: None (built-in rule), a mapping M -> tile choice (0, 2 or 4,
-        e.g. the output of ``tune.tune``), or one choice per series."""
+        e.g. the output of ``tune.tune``), or one choice per series.
+        ``segments``: also lay out the buffers of ``bispectrum_segments``."""
         import numpy as np
         self.n = np.ascontiguousarray(np.asarray(n, dtype=np.int64).ravel())
         self.M = np.ascontiguousarray(np.asarray(M, dtype=np.int32).ravel())
         if self.n.size != self.M.size or self.n.size == 0:
             raise ValueError("n and M must be non-empty and of equal length")
         self.window, self.path = window, path
-        self.flags = (0 if center else HOS_NO_CENTER) | (HOS_PLAN_ADJOINT if adjoint else 0)
+        self.flags = ((0 if center else HOS_NO_CENTER) | (HOS_PLAN_ADJOINT if adjoint else 0) |
+                      (HOS_PLAN_SEGMENTS if segments else 0))
         if tile is None:
             self.tile = None
         elif isinstance(tile, dict):
@@ -517,6 +521,43 @@ def bispectrum_batched(x, plan: BatchPlan, return_c3=True, return_B=True):
         ws.data_ptr(), ws.numel(), _stream_handle(x.device))
     if st != HOS_OK:
         raise HosError(st, "hos_bispectrum_batched")
+    return c3, B
+
+
+def bispectrum_segments(x, P: int, M: int, window: str = "parzen", path: str = "fp32",
+                        center: bool = True, return_c3: bool = True, return_B: bool = True,
+                        tile=None, plan: "BatchPlan | None" = None):
+    """Segment averaging (``hos_bispectrum_segments``): the first K = n // P
+    segments of P samples of a 1-D CUDA tensor, each centred on its own mean,
+    their c3 averaged, then windowed and transformed on the N x N grid of the
+    plan (N as for ``default_nfft(M, window)``).  Returns (c3 or None, B or
+    None).  A ``plan`` from an earlier call with the same arguments may be
+    passed back in."""
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError("x must be a CUDA tensor")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
+    x = x.contiguous().view(-1)
+    K = x.numel() // int(P)
+    if K < 1:
+        raise ValueError("fewer than P samples")
+    if plan is None:
+        plan = BatchPlan([P] * K, [M] * K, window=window, path=path, center=center, tile=tile,
+                         segments=True)
+    plan.to(x.device)
+    ws = plan.workspace(x.device)
+    N = int(plan.series()[0, 2])
+    c3 = torch.empty((2 * M + 1, 2 * M + 1), dtype=torch.float64,
+                     device=x.device) if return_c3 else None
+    B = torch.empty((N, N), dtype=torch.complex128, device=x.device) if return_B else None
+    st = lib().hos_bispectrum_segments(
+        x.data_ptr(), HOS_F64 if x.dtype == torch.float64 else HOS_F32,
+        plan.host.ctypes.data, plan.dev.data_ptr(),
+        c3.data_ptr() if c3 is not None else None, B.data_ptr() if B is not None else None,
+        ws.data_ptr(), ws.numel(), _stream_handle(x.device))
+    if st != HOS_OK:
+        raise HosError(st, "hos_bispectrum_segments")
     return c3, B
 
 

@@ -62,7 +62,7 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         return HOS_EINVAL;
     if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN && window != HOS_WIN_PARZEN_SEPARABLE)
         return HOS_EINVAL;
-    if (flags & ~(HOS_NO_CENTER | HOS_PLAN_ADJOINT))
+    if (flags & ~(HOS_NO_CENTER | HOS_PLAN_ADJOINT | HOS_PLAN_SEGMENTS))
         return HOS_EINVAL;
     const bool adj = (flags & HOS_PLAN_ADJOINT) != 0;
     const bool split = path != HOS_PATH_FP32;
@@ -200,6 +200,13 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
     }
     h.loss_off = (int64_t)o;
     o = a256(o + (size_t)batch * sizeof(double));
+    if (flags & HOS_PLAN_SEGMENTS) {
+        if (h.uniform_M < 0)
+            return HOS_EINVAL;   // one averaged table needs one M
+        const size_t ne = (size_t)(h.uniform_M + 1) * (h.uniform_M + 1);
+        h.seg_off = (int64_t)o;  // averaged table and 64 stats, then N twiddles
+        o = a256(o + a256((ne + 64) * sizeof(double)) + (size_t)sd[0].N * 16);
+    }
 
     // contraction work items, per tile class
     std::vector<C3Item> items[BATCH_CLASSES];
@@ -530,6 +537,37 @@ int hos_bispectrum_batched_timed(const void *x, int32_t dtype, const void *plan_
     for (int k = 0; k < made; ++k)
         hipEventDestroy(ev[k]);
     return st;
+}
+
+int hos_bispectrum_segments(const void *x, int32_t dtype, const void *plan_host,
+                            const void *plan_dev, double *c3, double *B, void *ws,
+                            size_t ws_bytes, hipStream_t stream)
+{
+    if (!c3 && !B)
+        return HOS_EINVAL;
+    if ((c3 && !aligned_to(c3, 8)) || (B && !aligned_to(B, 16)))
+        return HOS_EINVAL;
+    const BatchHeader *hh = plan_header(plan_host);
+    if (hh && (hh->uniform_M < 0 || !(hh->flags & HOS_PLAN_SEGMENTS)))
+        return HOS_EINVAL;
+    const BatchHeader *h = nullptr;
+    int st = batch_common(x, dtype, plan_host, plan_dev, ws, ws_bytes, &h);
+    if (st != HOS_OK)
+        return st;
+    char *w = (char *)ws;
+    const char *dp = (const char *)plan_dev;
+    const SeriesDesc *sd = (const SeriesDesc *)((const char *)plan_host + h->series_off);
+    const int M = (int)h->uniform_M, N = sd[0].N;
+    const int64_t ne = (int64_t)(M + 1) * (M + 1);
+    const double *avg = (const double *)(w + h->seg_off);
+    double2 *tw = (double2 *)(w + h->seg_off + a256((size_t)(ne + 64) * sizeof(double)));
+    hipError_t e = batch_forward(x, dtype, *h, dp, w, stream);
+    if (e == hipSuccess) e = launch_seg_average(*h, dp, w, stream);
+    if (e == hipSuccess && B) e = launch_twiddles(tw, N, stream);
+    if (e == hipSuccess)
+        e = launch_c3_finish_table(avg, avg + ne, M, (int)h->window, N, tw, c3, B, stream);
+    if (e == hipSuccess && B) e = launch_fft_cols(B, N, tw, stream);
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
 }
 
 int hos_bispectrum_loss_fwd(const void *x, int32_t dtype, const void *plan_host,

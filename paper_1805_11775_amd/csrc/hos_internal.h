@@ -248,6 +248,7 @@ struct BatchHeader {
     int64_t groups_off, n_groups;
     int64_t gseries_off;            // int32 series indices ordered by DFT group
     int64_t loss_off;               // byte offset of the per-series loss partials
+    int64_t seg_off;                // segments: averaged table, its stats, twiddles (or 0)
 };
 
 // Plan flags (in hos.h: HOS_PLAN_ADJOINT).
@@ -307,6 +308,11 @@ hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws,
 hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s);
 hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3,
                             double *B, char *ws, hipStream_t s);
+hipError_t launch_c3_finish_table(const double *cfull, const double *stats, int M, int window,
+                                  int nfft, const double2 *tw, double *c3, double *B,
+                                  hipStream_t s);
+hipError_t launch_seg_average(const BatchHeader &hdr, const char *dplan, char *ws,
+                              hipStream_t s);
 bool fft_size_ok(int N);
 hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s);
 hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int N, int window,

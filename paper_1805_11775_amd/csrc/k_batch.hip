@@ -69,7 +69,40 @@ k_bloss_final(const double *__restrict__ part, int batch, double *__restrict__ l
         loss[0] = red[0];
 }
 
+// Segment averaging: entry e of the reduced tables of every series (each
+// divided by its own n s^3), summed in series order and divided by the
+// number of series; stats[3] = 1 then makes the average the table that the
+// single-series finishing kernels read.
+__global__ void __launch_bounds__(256)
+k_seg_avg(const SeriesDesc *__restrict__ sd, int64_t S, int M, const char *__restrict__ ws,
+          double *__restrict__ avg, double *__restrict__ stats)
+{
+    const int64_t ne = (int64_t)(M + 1) * (M + 1);
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < 64)
+        stats[threadIdx.x] = threadIdx.x == 3 ? 1.0 : 0.0;
+    if (e >= ne)
+        return;
+    double s = 0.0;
+    for (int64_t i = 0; i < S; ++i) {
+        const char *r = ws + sd[i].ws_off;
+        s += ((const double *)(r + sd[i].o_cfull))[e] / ((const double *)(r + sd[i].o_stats))[3];
+    }
+    avg[e] = s / (double)S;
+}
+
 }  // namespace
+
+hipError_t launch_seg_average(const BatchHeader &h, const char *dplan, char *ws, hipStream_t s)
+{
+    const SeriesDesc *sd = (const SeriesDesc *)(dplan + h.series_off);
+    const int M = (int)h.uniform_M;
+    const int64_t ne = (int64_t)(M + 1) * (M + 1);
+    double *avg = (double *)(ws + h.seg_off);
+    double *stats = avg + ne;
+    k_seg_avg<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(sd, h.batch, M, ws, avg, stats);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_spectra(const BatchHeader &h, const char *dplan, int window, double *c3,
                                 double *B_pd, char *ws, hipStream_t s)

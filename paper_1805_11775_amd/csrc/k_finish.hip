@@ -36,22 +36,29 @@ k_c3_out(const double *__restrict__ cfull, const double *__restrict__ stats, int
 
 }  // namespace
 
-hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3, double *B,
-                            char *ws, hipStream_t s)
+// c3 and the row transforms of B from a reduced table (stats[3] divides it).
+hipError_t launch_c3_finish_table(const double *cfull, const double *stats, int M, int window,
+                                  int nfft, const double2 *tw, double *c3, double *B,
+                                  hipStream_t s)
 {
-    const double *cfull = (const double *)(ws + p.off_cfull);
-    const double *stats = (const double *)(ws + p.off_stats);
     if (c3) {
-        const int64_t tot = (int64_t)(2 * p.M + 1) * (2 * p.M + 1);
-        k_c3_out<<<(tot + 255) / 256, 256, 0, s>>>(cfull, stats, p.M, c3);
+        const int64_t tot = (int64_t)(2 * M + 1) * (2 * M + 1);
+        k_c3_out<<<(tot + 255) / 256, 256, 0, s>>>(cfull, stats, M, c3);
     }
     if (B) {   // fold + window + row transforms (k_fft.hip); the columns follow
-        hipError_t e = launch_full_rows(cfull, stats, p.M, nfft, window,
-                                        (const double2 *)(ws + p.off_twid), B, s);
+        hipError_t e = launch_full_rows(cfull, stats, M, nfft, window, tw, B, s);
         if (e != hipSuccess)
             return e;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3, double *B,
+                            char *ws, hipStream_t s)
+{
+    return launch_c3_finish_table((const double *)(ws + p.off_cfull),
+                                  (const double *)(ws + p.off_stats), p.M, window, nfft,
+                                  (const double2 *)(ws + p.off_twid), c3, B, s);
 }
 
 }  // namespace hos

@@ -145,3 +145,11 @@ def workload_dbs(n: int = 1 << 16):
     doubling of n, which puts n = 2^16 near 1020)."""
     x = quadratic_process(n, SEED_BASE + 7).astype(np.float32)
     return x, dict(P=int(n), M3=1023)
+
+
+def workload_segments(n: int = 1 << 20):
+    """Segment averaging: the long bispectrum's series (n = 2^20 float32
+    quadratic process) cut into 16 segments of 65536 samples, maximum lag
+    512, 1024-point DFT."""
+    x, cfg = workload_long_bispectrum(n)
+    return x, dict(P=n // 16, M=cfg["M"], nfft=cfg["nfft"])

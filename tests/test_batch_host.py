@@ -182,3 +182,22 @@ def test_tile_choice_moves_series_between_classes():
 def test_tune_module_imports():
     from paper_1805_11775_amd import tune
     assert tune.CANDIDATES["fp32"] == (4,)
+
+
+def test_segments_plan_and_validation():
+    """HOS_PLAN_SEGMENTS needs one M; hos_bispectrum_segments checks its
+    plan and outputs before touching a device."""
+    with pytest.raises(hos.HosError):
+        hos.BatchPlan([1000, 1000], [20, 21], segments=True)
+    seg = hos.BatchPlan([1000] * 4, [20] * 4, segments=True)
+    plain = hos.BatchPlan([1000] * 4, [20] * 4)
+    assert seg.info["ws_bytes"] > plain.info["ws_bytes"]
+    f = hos.lib().hos_bispectrum_segments
+    wsb = seg.info["ws_bytes"]
+    ph = seg.host.ctypes.data
+    assert f(FAKE, 0, ph, FAKE, FAKE, FAKE, FAKE, wsb - 1, None) == hos.HOS_EWORKSPACE
+    assert f(FAKE, 0, ph, FAKE, None, None, FAKE, wsb, None) == hos.HOS_EINVAL
+    assert f(FAKE, 0, ph, FAKE, FAKE, FAKE + 8, FAKE, wsb, None) == hos.HOS_EINVAL
+    assert f(FAKE, 0, plain.host.ctypes.data, FAKE, FAKE, FAKE, FAKE,
+             plain.info["ws_bytes"], None) == hos.HOS_EINVAL     # plan without the flag
+    assert f(None, 0, ph, FAKE, FAKE, FAKE, FAKE, wsb, None) == hos.HOS_EINVAL
