@@ -62,12 +62,15 @@ def _load():
         lib.or_m4_at.argtypes = [dp, i64, ip, ip, ip, i64, dp]
         lib.or_c4_at.argtypes = [dp, i64, ip, ip, ip, i64, dp]
         lib.or_c4_cube.argtypes = [dp, i64, i32, dp]
+        lib.or_m5_at.argtypes = [dp, i64, ip, ip, ip, ip, i64, dp]
+        lib.or_c5_at.argtypes = [dp, i64, ip, ip, ip, ip, i64, dp]
+        lib.or_c5_hyper.argtypes = [dp, i64, i32, dp]
         lib.or_c3_grad.argtypes = [dp, i64, i32, dp, dp]
         lib.or_c3_grad_at.argtypes = [dp, i64, i32, dp, ctypes.POINTER(ctypes.c_int64), i64,
                                       dp]
         for f in (lib.or_center, lib.or_c3_at, lib.or_c3_square, lib.or_c2,
                   lib.or_m4_at, lib.or_c4_at, lib.or_c4_cube, lib.or_c3_grad,
-                  lib.or_c3_grad_at):
+                  lib.or_c3_grad_at, lib.or_m5_at, lib.or_c5_at, lib.or_c5_hyper):
             f.restype = None
         _lib = lib
     return _lib
@@ -194,6 +197,59 @@ def c4_support(x, M: int, centered: bool = True) -> np.ndarray:
     return c
 
 
+def _quad(t1, t2, t3, t4):
+    return tuple(np.ascontiguousarray(np.asarray(t, dtype=np.int32).ravel())
+                 for t in (t1, t2, t3, t4))
+
+
+def m5_at(x, t1, t2, t3, t4, centered: bool = True) -> np.ndarray:
+    """Fifth-order sample moment (1/n) sum_t x_t x_{t+t1} .. x_{t+t4}."""
+    xt = _prep(x, centered)
+    t1, t2, t3, t4 = _quad(t1, t2, t3, t4)
+    out = np.empty(t1.size, dtype=np.float64)
+    _load().or_m5_at(_dp(xt), xt.size, _ip(t1), _ip(t2), _ip(t3), _ip(t4), t1.size,
+                     _dp(out))
+    return out
+
+
+def c5_at(x, t1, t2, t3, t4, centered: bool = True) -> np.ndarray:
+    """c5 = m5 - (ten products c2 * m3 over the pair / triple partitions of
+    the five offsets), at arbitrary lag quadruples (Section 1: cumulants as
+    functions of moments, the order-5 case of the moment-to-cumulant
+    relation for zero-mean variables)."""
+    xt = _prep(x, centered)
+    t1, t2, t3, t4 = _quad(t1, t2, t3, t4)
+    out = np.empty(t1.size, dtype=np.float64)
+    _load().or_c5_at(_dp(xt), xt.size, _ip(t1), _ip(t2), _ip(t3), _ip(t4), t1.size,
+                     _dp(out))
+    return out
+
+
+def c5_hyper(x, M: int, centered: bool = True) -> np.ndarray:
+    """c5 at every lag of the hypercube |t_i| <= M; [t1+M, t2+M, t3+M, t4+M]."""
+    xt = _prep(x, centered)
+    S = 2 * M + 1
+    out = np.empty((S, S, S, S), dtype=np.float64)
+    _load().or_c5_hyper(_dp(xt), xt.size, int(M), _dp(out))
+    return out
+
+
+def span5(M: int) -> np.ndarray:
+    """max - min of {0, t1, t2, t3, t4} over the hypercube."""
+    t = np.arange(-M, M + 1)
+    g = np.meshgrid(t, t, t, t, indexing="ij")
+    mx = np.maximum.reduce([np.zeros_like(g[0])] + list(g))
+    mn = np.minimum.reduce([np.zeros_like(g[0])] + list(g))
+    return mx - mn
+
+
+def c5_support(x, M: int, centered: bool = True) -> np.ndarray:
+    """c5 on {span(0,t1,t2,t3,t4) <= M}, zero elsewhere in the hypercube."""
+    c = c5_hyper(x, M, centered)
+    c[span5(M) > M] = 0.0
+    return c
+
+
 # --------------------------------------------------------------------------
 # Step 3: lag window (the paper smooths in frequency with a box; the
 # workloads use the Parzen lag window instead -- a reading).
@@ -235,6 +291,24 @@ def window4(M: int, kind: str = "parzen") -> np.ndarray:
     return d(t1) * d(t2) * d(t3) * d(t2 - t1) * d(t3 - t1) * d(t3 - t2)
 
 
+def window5(M: int, kind: str = "parzen") -> np.ndarray:
+    """Product of d over the ten pairwise differences of {0,t1,t2,t3,t4};
+    kind "separable": d(t1) d(t2) d(t3) d(t4); "none": 1."""
+    t = np.arange(-M, M + 1)
+    g = np.meshgrid(t, t, t, t, indexing="ij")
+    if kind == "none":
+        return np.ones_like(g[0], dtype=np.float64)
+    d = lambda m: parzen(m, M)
+    if kind == "separable":
+        return d(g[0]) * d(g[1]) * d(g[2]) * d(g[3])
+    pts = [np.zeros_like(g[0])] + list(g)
+    w = np.ones_like(g[0], dtype=np.float64)
+    for j in range(5):
+        for k in range(j + 1, 5):
+            w = w * d(pts[k] - pts[j])
+    return w
+
+
 # --------------------------------------------------------------------------
 # Step 4: the DFT (Section 1: spectra are Fourier transforms of cumulants;
 # sign and normalisation of Algorithm DBS step 3).
@@ -246,10 +320,7 @@ def place_circular(c: np.ndarray, M: int, N: int) -> np.ndarray:
     d = c.ndim
     out = np.zeros((N,) * d, dtype=np.float64)
     idx = np.arange(-M, M + 1) % N
-    if d == 2:
-        np.add.at(out, np.ix_(idx, idx), c)
-    else:
-        np.add.at(out, np.ix_(idx, idx, idx), c)
+    np.add.at(out, np.ix_(*([idx] * d)), c)
     return out
 
 
@@ -264,6 +335,15 @@ def bispectrum(x, M: int, nfft: int, window: str = "parzen",
     cw = c * window3(M, window)
     B = np.fft.fft2(place_circular(cw, M, nfft))
     return c, B
+
+
+def spectrum5(x, M: int, nfft: int, window: str = "parzen", centered: bool = True):
+    """(c5 on its support, Q = 4D DFT of the windowed c5 on an N^4 grid): the
+    order-5 member of the family (the paper's k-th order spectrum)."""
+    c = c5_support(x, M, centered)
+    cw = c * window5(M, window)
+    Q = np.fft.fftn(place_circular(cw, M, nfft))
+    return c, Q
 
 
 def trispectrum(x, M: int, nfft: int, window: str = "parzen",

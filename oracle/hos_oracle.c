@@ -19,6 +19,7 @@
  *
  *   m3(w1,w2)    = (1/n) sum_t x_t x_{t+w1} x_{t+w2}
  *   m4(t1,t2,t3) = (1/n) sum_t x_t x_{t+t1} x_{t+t2} x_{t+t3}
+ *   m5(t1..t4)   = (1/n) sum_t x_t x_{t+t1} x_{t+t2} x_{t+t3} x_{t+t4}
  *   c2(d)        = (1/n) sum_t x_t x_{t+d}
  *
  * where each sum runs over the t for which every index lies in [0, n)
@@ -153,6 +154,77 @@ void or_c4_cube(const double *x, int64_t n, int32_t M, double *out)
         int64_t a = r / S, b = r % S;
         for (int64_t c = 0; c < S; ++c)
             out[r * S + c] = c4_one(x, n, a - M, b - M, c - M);
+    }
+}
+
+/* Fifth-order moment at one lag quadruple. */
+static double m5_one(const double *x, int64_t n, int64_t t1, int64_t t2, int64_t t3, int64_t t4)
+{
+    int64_t mn = 0, mx = 0;
+    const int64_t t[4] = {t1, t2, t3, t4};
+    for (int k = 0; k < 4; ++k) {
+        if (t[k] < mn)
+            mn = t[k];
+        if (t[k] > mx)
+            mx = t[k];
+    }
+    int64_t lo = -mn, hi = n - 1 - mx;
+    double s = 0.0;
+    for (int64_t i = lo; i <= hi; ++i)
+        s += x[i] * x[i + t1] * x[i + t2] * x[i + t3] * x[i + t4];
+    return s / (double)n;
+}
+
+void or_m5_at(const double *x, int64_t n, const int32_t *t1, const int32_t *t2,
+              const int32_t *t3, const int32_t *t4, int64_t count, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < count; ++k)
+        out[k] = m5_one(x, n, t1[k], t2[k], t3[k], t4[k]);
+}
+
+/*
+ * Fifth-order cumulant of the zero-mean series at one lag quadruple: with
+ * offsets o = (0, t1, t2, t3, t4) of the five variables X_k = x_{t+o_k},
+ * the moment-to-cumulant relation for zero-mean variables keeps, besides
+ * the fifth moment, only the partitions of {0..4} into a pair and a triple:
+ *   c5 = m5 - sum over the ten pairs {j,k} of c2(o_k - o_j) m3(rest),
+ * m3 of the remaining three offsets {p,q,r} taken relative to the first.
+ */
+static double c5_one(const double *x, int64_t n, int64_t t1, int64_t t2, int64_t t3, int64_t t4)
+{
+    const int64_t o[5] = {0, t1, t2, t3, t4};
+    double c = m5_one(x, n, t1, t2, t3, t4);
+    for (int j = 0; j < 5; ++j)
+        for (int k = j + 1; k < 5; ++k) {
+            int64_t r[3];
+            int m = 0;
+            for (int q = 0; q < 5; ++q)
+                if (q != j && q != k)
+                    r[m++] = o[q];
+            c -= c2_one(x, n, o[k] - o[j]) * m3_one(x, n, r[1] - r[0], r[2] - r[0]);
+        }
+    return c;
+}
+
+void or_c5_at(const double *x, int64_t n, const int32_t *t1, const int32_t *t2,
+              const int32_t *t3, const int32_t *t4, int64_t count, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < count; ++k)
+        out[k] = c5_one(x, n, t1[k], t2[k], t3[k], t4[k]);
+}
+
+/* c5 over the hypercube |t_i| <= M, index (((t1+M)S + t2+M)S + t3+M)S + t4+M. */
+void or_c5_hyper(const double *x, int64_t n, int32_t M, double *out)
+{
+    int64_t S = 2 * (int64_t)M + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < S * S; ++r) {
+        int64_t a = r / S, b = r % S;
+        for (int64_t c = 0; c < S; ++c)
+            for (int64_t d = 0; d < S; ++d)
+                out[(r * S + c) * S + d] = c5_one(x, n, a - M, b - M, c - M, d - M);
     }
 }
 

@@ -537,3 +537,103 @@ def test_segments_match_direct_method_parts():
     direct = oracle.dbs(np.concatenate(parts), N, 1)
     k1, k2 = oracle.pd_indices(N)
     assert np.max(np.abs(B[k1, k2] - direct * N / P)) < 1e-10 * np.max(np.abs(direct))
+
+
+# --------------------------------------------------------------------------
+# Order five
+# --------------------------------------------------------------------------
+def test_c5_matches_literal_loops():
+    """The C core against the pure-Python literal loops on a tiny record,
+    every lag of the hypercube M = 2 plus lags reaching past the record."""
+    x = synth.iid_exp_centered(9, 17)
+    c = oracle.c5_hyper(x, 2)
+    xt = brute.center(list(x))
+    rng = np.random.default_rng(0)
+    for t in [tuple(v) for v in rng.integers(-2, 3, (60, 4))] + [(0, 0, 0, 0), (2, -2, 1, 0)]:
+        assert abs(c[tuple(np.asarray(t) + 2)] - brute.c5(xt, *t)) < 1e-13
+    for t in [(8, 0, 0, 0), (-8, 3, 1, 0), (5, -4, 0, 2)]:
+        assert abs(oracle.c5_at(x, *[[v] for v in t])[0] - brute.c5(xt, *t)) < 1e-13
+
+
+def test_c5_lag_zero_is_fifth_cumulant_of_the_sample():
+    """At the origin c5 is the fifth cumulant of the sample's own
+    distribution, mu5 - 10 mu2 mu3 for central moments (scipy's)."""
+    from scipy import stats
+    x = synth.quadratic_process(300, 2)
+    mu = [stats.moment(x, k) for k in (2, 3, 5)]
+    got = oracle.c5_at(x, [0], [0], [0], [0])[0]
+    assert abs(got - (mu[2] - 10 * mu[0] * mu[1])) < 1e-12 * abs(mu[2])
+
+
+def test_c5_uncentred_impulse_closed_form():
+    """x = A delta_{t0}, no mean removal: m5 = A^5/n at the origin only,
+    c2 = A^2/n at lag 0, c3 = A^3/n at (0,0); so c5 = A^5/n [all offsets
+    equal] - (A^2/n)(A^3/n) times the number of pair / triple splits of the
+    five offsets whose pair and triple are each constant."""
+    n, A, M = 40, 1.7, 2
+    x = np.zeros(n)
+    x[20] = A
+    c = oracle.c5_hyper(x, M, centered=False)
+    t = np.arange(-M, M + 1)
+    g = np.meshgrid(t, t, t, t, indexing="ij")
+    pts = [np.zeros_like(g[0])] + list(g)
+    count = np.zeros_like(g[0], dtype=float)
+    for j in range(5):
+        for k in range(j + 1, 5):
+            rest = [pts[i] for i in range(5) if i not in (j, k)]
+            count += ((pts[j] == pts[k]) & (rest[0] == rest[1]) & (rest[1] == rest[2]))
+    alleq = (g[0] == 0) & (g[1] == 0) & (g[2] == 0) & (g[3] == 0)
+    expect = A ** 5 / n * alleq - (A ** 2 / n) * (A ** 3 / n) * count
+    assert np.max(np.abs(c - expect)) < 1e-14
+
+
+def test_c5_symmetries_and_zero_for_constants():
+    """The 120-fold symmetry (permutations of t1..t4 and the shift
+    (t1..t4) -> (-t1, t2-t1, t3-t1, t4-t1)) holds without being used; a
+    centred constant gives 0."""
+    x = synth.iid_exp_centered(60, 4)
+    c = oracle.c5_hyper(x, 2)
+    for perm in [(1, 0, 2, 3), (0, 2, 1, 3), (0, 1, 3, 2), (3, 2, 1, 0)]:
+        assert np.max(np.abs(c - c.transpose(perm))) < 1e-14 * np.max(np.abs(c))
+    M = 2
+    t = np.arange(-M, M + 1)
+    a, b, cc, d = np.meshgrid(t, t, t, t, indexing="ij")
+    ok = (np.abs(b - a) <= M) & (np.abs(cc - a) <= M) & (np.abs(d - a) <= M)
+    lhs = c[ok]
+    rhs = c[(-a)[ok] + M, (b - a)[ok] + M, (cc - a)[ok] + M, (d - a)[ok] + M]
+    assert np.max(np.abs(lhs - rhs)) < 1e-14 * np.max(np.abs(c))
+    assert np.max(np.abs(oracle.c5_hyper(np.full(30, 2.5), 1))) < 1e-12
+
+
+def test_window5_hand_values():
+    """Product of d over the ten differences of {0, t1, t2, t3, t4}, M = 4:
+    d(0) = 1, d(1) = 1 - 6/16 + 6/64 = 0.71875, d(2) = 0.25 (r = 1/2:
+    1 - 6/4 + 6/8), d(3) = 2 (1/4)^3 = 0.03125, d(4) = 0."""
+    w = oracle.window5(4)
+    d = {0: 1.0, 1: 0.71875, 2: 0.25, 3: 0.03125, 4: 0.0}
+    at = lambda *t: w[tuple(np.asarray(t) + 4)]
+    # (1, 1, 0, 0): differences 1,1,0,0, 0,1,1, 1,1, 0
+    assert abs(at(1, 1, 0, 0) - d[1] ** 6) < 1e-15
+    # (1, 2, 0, -1): offsets {0,1,2,0,-1}: |diffs| = 1,2,0,1, 1,1,2, 2,3, 1
+    assert abs(at(1, 2, 0, -1) - d[1] ** 5 * d[2] ** 3 * d[3] * d[0]) < 1e-15
+    assert at(4, 0, 0, 0) == 0.0
+
+
+def test_spectrum5_fold_and_symmetry():
+    """With N = 2M the folded 4-D DFT equals the direct sum over every lag
+    (aliases included) at sampled frequencies; the spectrum is Hermitian and
+    symmetric under permutations of (k1..k4)."""
+    x = synth.iid_exp_centered(70, 6)
+    M, N = 2, 4
+    c, Q = oracle.spectrum5(x, M, N)
+    cw = c * oracle.window5(M)
+    lag = np.arange(-M, M + 1)
+    for k in [(0, 0, 0, 0), (1, 2, 3, 0), (3, 3, 1, 2)]:
+        ph = np.exp(-2j * np.pi * (k[0] * lag[:, None, None, None] + k[1] * lag[None, :, None, None]
+                                   + k[2] * lag[None, None, :, None]
+                                   + k[3] * lag[None, None, None, :]) / N)
+        assert abs(np.sum(cw * ph) - Q[k]) < 1e-12 * np.max(np.abs(Q))
+    kk = np.arange(N)
+    Qm = Q[np.ix_(*[(-kk) % N] * 4)]
+    assert np.max(np.abs(Q - np.conj(Qm))) < 1e-12 * np.max(np.abs(Q))
+    assert np.max(np.abs(Q - Q.transpose(1, 0, 3, 2))) < 1e-12 * np.max(np.abs(Q))
