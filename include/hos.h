@@ -232,6 +232,42 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
 
 /*
  * ------------------------------------------------------------------------
+ * Order five (the k-th order generalisation of Section 3 at k = 5).
+ *
+ * m5(t1..t4) = (1/n) sum_t x~_t x~_{t+t1} x~_{t+t2} x~_{t+t3} x~_{t+t4} (same
+ * index range and normalisation as c3), and for the zero-mean series the
+ * moment-to-cumulant relation keeps besides m5 only the splits of the five
+ * offsets {0, t1, t2, t3, t4} into a pair and a triple:
+ *   c5 = m5 - sum over the ten pairs {j,k} of c2(o_k - o_j) c3(the other three),
+ * with c2 and c3 the sample cumulants of the same series.  Lags whose span
+ * max - min of {0, t1..t4} exceeds M are 0.  Window (window = HOS_WIN_PARZEN):
+ * d over the ten pairwise differences of the offsets (L = M);
+ * HOS_WIN_PARZEN_SEPARABLE: d(t1) d(t2) d(t3) d(t4); HOS_WIN_NONE: 1.
+ *   Q(k1..k4) = sum_t W5(t) c5(t) exp(-2 pi i <k, t> / N).
+ * Outputs: c5 (2M+1)^4 float64 row-major, lag t at t+M per axis; Q N^4
+ * interleaved complex128, unshifted.  Either may be NULL (not both).  Limits:
+ * M <= 40, N <= 96 (2, 3, 5-smooth, >= 2M with a window, >= 2M+1 without).
+ * The fifth moments come from the matrix cores (rows x_i x_{i+a} x_{i+b}
+ * x_{i+c}, 0 <= c <= b <= a <= M, against the columns x_{i+d}, d <= c);
+ * c2 and c3 are FP64 sums over the input.
+ * ------------------------------------------------------------------------
+ */
+int hos_cumulant5_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path, uint32_t flags,
+                            size_t *bytes);
+int hos_cumulant5(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                  int32_t nfft, int32_t path, uint32_t flags, double *c5, double *Q, void *ws,
+                  size_t ws_bytes, hipStream_t stream);
+/* stage_ms (host, 5 floats): moments and operands, contraction, reduction
+ * with c2 / c3 and the fold, the 4-D DFT, total.  Synchronises the stream. */
+int hos_cumulant5_timed(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                        int32_t nfft, int32_t path, uint32_t flags, double *c5, double *Q,
+                        void *ws, size_t ws_bytes, hipStream_t stream, float *stage_ms);
+/* Host-only plan of the order-five contraction; info as hos_c4_plan_info
+ * (the first entry counts lag triples). */
+int hos_c5_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo);
+
+/*
+ * ------------------------------------------------------------------------
  * Batches of series.
  *
  * A batch is described by a PLAN built on the host (no device needed):

@@ -84,6 +84,14 @@ def _load_lib():
                                                  vp, vp, vp, sz, vp,
                                                  ctypes.POINTER(ctypes.c_float)]),
         "hos_c4_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
+        "hos_c5_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
+        "hos_cumulant5_workspace": (ctypes.c_int, [i64, i32, i32, i32, u32,
+                                                   ctypes.POINTER(sz)]),
+        "hos_cumulant5": (ctypes.c_int, [vp, i32, i64, i32, i32, i32, i32, u32,
+                                         vp, vp, vp, sz, vp]),
+        "hos_cumulant5_timed": (ctypes.c_int, [vp, i32, i64, i32, i32, i32, i32, u32,
+                                               vp, vp, vp, sz, vp,
+                                               ctypes.POINTER(ctypes.c_float)]),
         "hos_batch_plan_size": (ctypes.c_int, [i32, p64, ctypes.POINTER(ctypes.c_int32), i32,
                                                i32, u32, ctypes.POINTER(ctypes.c_int32),
                                                ctypes.POINTER(sz), ctypes.POINTER(sz)]),
@@ -395,6 +403,61 @@ def dbs(x, P: int, M3: int, center: bool = True, workspace=None, timed: bool = F
     if st != HOS_OK:
         raise HosError(st, "hos_dbs")
     return B
+
+
+STAGES5 = ("prep", "contract", "reduce_fold", "dft", "total")
+
+
+def hos_c5_plan_info(n, M, path) -> dict:
+    buf = (ctypes.c_int64 * 8)()
+    st = lib().hos_c5_plan_info(int(n), int(M), int(path), buf, 8)
+    if st != HOS_OK:
+        raise HosError(st, "hos_c5_plan_info")
+    keys = ("P", "RB", "NCB", "WX", "S", "CPS", "C", "ws_bytes")
+    return dict(zip(keys, list(buf)))
+
+
+def cumulant5(x, M: int, nfft: int | None = None, window: str = "parzen", path: str = "fp32",
+              center: bool = True, return_c5: bool = True, return_Q: bool = True,
+              workspace=None, timed: bool = False):
+    """Order five (``hos_cumulant5``): c5 over |t| <= M ((2M+1)^4 float64)
+    and its windowed 4-D DFT Q (nfft^4 complex128).  Returns (c5 or None,
+    Q or None), and the stage times in ms with ``timed``."""
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError("x must be a CUDA tensor")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
+    x = x.contiguous().view(-1)
+    n = x.numel()
+    pth, win = PATHS[path], WINDOWS[window]
+    if nfft is None:
+        nfft = default_nfft(M, window)
+    flags = 0 if center else HOS_NO_CENTER
+    out = ctypes.c_size_t(0)
+    st = lib().hos_cumulant5_workspace(n, M, nfft if return_Q else 0, pth, flags,
+                                      ctypes.byref(out))
+    if st != HOS_OK:
+        raise HosError(st, "hos_cumulant5_workspace")
+    if workspace is None or workspace.numel() < out.value:
+        workspace = torch.empty(out.value, dtype=torch.uint8, device=x.device)
+    S = 2 * M + 1
+    c5 = torch.empty((S, S, S, S), dtype=torch.float64, device=x.device) if return_c5 else None
+    Q = torch.empty((nfft,) * 4, dtype=torch.complex128, device=x.device) if return_Q else None
+    args = (x.data_ptr(), HOS_F64 if x.dtype == torch.float64 else HOS_F32, n, M, win,
+            nfft if return_Q else 0, pth, flags, c5.data_ptr() if c5 is not None else None,
+            Q.data_ptr() if Q is not None else None, workspace.data_ptr(), workspace.numel(),
+            _stream_handle(x.device))
+    if timed:
+        ms = (ctypes.c_float * 5)()
+        st = lib().hos_cumulant5_timed(*args, ms)
+        if st != HOS_OK:
+            raise HosError(st, "hos_cumulant5_timed")
+        return c5, Q, dict(zip(STAGES5, list(ms)))
+    st = lib().hos_cumulant5(*args)
+    if st != HOS_OK:
+        raise HosError(st, "hos_cumulant5")
+    return c5, Q
 
 
 # ------------------------------------------------------------------ batches

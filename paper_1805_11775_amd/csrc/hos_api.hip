@@ -79,14 +79,17 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     return HOS_OK;
 }
 
-int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p)
+int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p, int ord)
 {
     memset(&p, 0, sizeof(p));
     p.n = n;
     p.M = M;
     p.path = path;
-    p.scale_top = 5;
-    p.P = (M + 1) * (M + 2) / 2;
+    p.ord = ord;
+    // the split paths round the product rows to FP16: |x~ s| < 32 keeps a
+    // product of three samples below 2^15, |x~ s| < 8 one of four
+    p.scale_top = ord == 5 ? 3 : 5;
+    p.P = ord == 5 ? (M + 1) * (M + 2) * (M + 3) / 6 : (M + 1) * (M + 2) / 2;
     p.RB = (p.P + 31) / 32;
     p.NCB = (M + 1 + 31) / 32;
     p.WX = c4_window_entries(M);
@@ -119,6 +122,12 @@ int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p)
     p.off_m4 = o;     o = align256(o + (size_t)p.P * (M + 1) * sizeof(double));
     p.off_c2part = o; o = align256(o + (size_t)(M + 1) * p.dot_blocks * sizeof(double));
     p.off_c2 = o;     o = align256(o + (size_t)(M + 1) * sizeof(double));
+    if (ord == 5) {
+        p.off_c3part = o;
+        o = align256(o + (size_t)(M + 1) * (M + 2) / 2 * p.dot_blocks * sizeof(double));
+        p.off_c3tab = o;
+        o = align256(o + (size_t)(M + 1) * (M + 1) * sizeof(double));
+    }
     if (nfft > 0) {
         p.off_twid = o;
         o = align256(o + (size_t)nfft * 2 * sizeof(double));
@@ -152,6 +161,16 @@ static int check_bispectrum_args(int64_t n, int32_t M, int32_t window, int32_t n
         return HOS_EINVAL;
     }
     return HOS_OK;
+}
+
+static int check_c5_args(int64_t n, int32_t M, int32_t window, int32_t nfft, int32_t path,
+                         uint32_t flags, bool want_Q)
+{
+    if (M > C5_MAX_M)
+        return HOS_EINVAL;
+    if (want_Q && nfft > C5_MAX_NFFT)
+        return HOS_EINVAL;
+    return check_bispectrum_args(n, M, window, nfft, path, flags, want_Q);
 }
 
 static int check_trispectrum_args(int64_t n, int32_t M, int32_t window, int32_t nfft,
@@ -336,7 +355,7 @@ int hos_trispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
     if (nfft > 0 && (!fft_size_ok(nfft) || nfft > C4_MAX_NFFT))
         return HOS_EINVAL;
     C4Plan p;
-    make_c4_plan(n, M, path, nfft, p);
+    make_c4_plan(n, M, path, nfft, p, 4);
     *bytes = p.total;
     return HOS_OK;
 }
@@ -358,7 +377,7 @@ static int trispectrum_impl(const void *x, int32_t dtype, int64_t n, int32_t M,
     if (st != HOS_OK)
         return st;
     C4Plan p;
-    make_c4_plan(n, M, path, T ? nfft : 0, p);
+    make_c4_plan(n, M, path, T ? nfft : 0, p, 4);
     if (ws_bytes < p.total)
         return HOS_EWORKSPACE;
     st = device_ok();
@@ -425,15 +444,113 @@ int hos_trispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M, in
 
 // Host-only plan of the fourth-order contraction:
 // info[0..7] = P, RB, NCB, WX, S, CPS, C, workspace bytes.
-int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo)
+// Order five: the same stages as the trispectrum with lag-triple rows, the
+// third-order corrections, and the 4-D fold and DFT.
+static int cumulant5_impl(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                          int32_t nfft, int32_t path, uint32_t flags, double *c5, double *Q,
+                          void *ws, size_t ws_bytes, hipStream_t stream, hipEvent_t *ev)
 {
-    if (!info || ninfo < 8)
+    if (!x || !ws || (!c5 && !Q))
         return HOS_EINVAL;
-    int st = check_trispectrum_args(n, M, HOS_WIN_NONE, 0, path, 0, false);
+    if (dtype != HOS_F32 && dtype != HOS_F64)
+        return HOS_EINVAL;
+    if (!aligned(x, dtype == HOS_F64 ? 8 : 4) || !aligned(ws, 256))
+        return HOS_EINVAL;
+    if ((c5 && !aligned(c5, 8)) || (Q && !aligned(Q, 16)))
+        return HOS_EINVAL;
+    int st = check_c5_args(n, M, window, Q ? nfft : 0, path, flags, Q != nullptr);
     if (st != HOS_OK)
         return st;
     C4Plan p;
-    make_c4_plan(n, M, path, 0, p);
+    make_c4_plan(n, M, path, Q ? nfft : 0, p, 5);
+    if (ws_bytes < p.total)
+        return HOS_EWORKSPACE;
+    st = device_ok();
+    if (st != HOS_OK)
+        return st;
+    char *w = (char *)ws;
+    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], stream) : hipSuccess; };
+    double2 *tw = Q ? (double2 *)(w + p.off_twid) : nullptr;
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = launch_moments(x, dtype, n, flags, p, w, stream);
+    if (e == hipSuccess) e = launch_prep(x, dtype, p, w, stream);
+    if (e == hipSuccess) e = mark(1);
+    if (e == hipSuccess) e = launch_c4_contract(p, w, stream);
+    if (e == hipSuccess) e = mark(2);
+    if (e == hipSuccess) e = launch_c4_reduce(x, dtype, p, w, stream);
+    if (e == hipSuccess && Q) e = launch_twiddles(tw, nfft, stream);
+    if (e == hipSuccess) e = launch_c5_finish(p, window, nfft, c5, Q, w, stream);
+    if (e == hipSuccess) e = mark(3);
+    if (e == hipSuccess && Q) e = launch_fft4_axes(Q, nfft, tw, stream);
+    if (e == hipSuccess) e = mark(4);
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
+int hos_cumulant5_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path, uint32_t flags,
+                            size_t *bytes)
+{
+    if (!bytes)
+        return HOS_EINVAL;
+    int st = check_c5_args(n, M, HOS_WIN_NONE, nfft > 0 ? nfft : 0, path, flags, false);
+    if (st != HOS_OK)
+        return st;
+    if (nfft > 0 && (!fft_size_ok(nfft) || nfft > C5_MAX_NFFT))
+        return HOS_EINVAL;
+    C4Plan p;
+    make_c4_plan(n, M, path, nfft, p, 5);
+    *bytes = p.total;
+    return HOS_OK;
+}
+
+int hos_cumulant5(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                  int32_t nfft, int32_t path, uint32_t flags, double *c5, double *Q, void *ws,
+                  size_t ws_bytes, hipStream_t stream)
+{
+    return cumulant5_impl(x, dtype, n, M, window, nfft, path, flags, c5, Q, ws, ws_bytes,
+                          stream, nullptr);
+}
+
+int hos_cumulant5_timed(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                        int32_t nfft, int32_t path, uint32_t flags, double *c5, double *Q,
+                        void *ws, size_t ws_bytes, hipStream_t stream, float *stage_ms)
+{
+    if (!stage_ms)
+        return HOS_EINVAL;
+    hipEvent_t ev[5];
+    int made = 0;
+    for (; made < 5; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess)
+            break;
+    int st = made == 5 ? cumulant5_impl(x, dtype, n, M, window, nfft, path, flags, c5, Q, ws,
+                                        ws_bytes, stream, ev)
+                       : HOS_EDEVICE;
+    if (st == HOS_OK) {
+        if (hipEventSynchronize(ev[4]) != hipSuccess) {
+            st = HOS_EDEVICE;
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (hipEventElapsedTime(&stage_ms[k], ev[k], ev[k + 1]) != hipSuccess)
+                    st = HOS_EDEVICE;
+            if (hipEventElapsedTime(&stage_ms[4], ev[0], ev[4]) != hipSuccess)
+                st = HOS_EDEVICE;
+        }
+    }
+    for (int k = 0; k < made; ++k)
+        hipEventDestroy(ev[k]);
+    return st;
+}
+
+static int moment_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo,
+                            int ord)
+{
+    if (!info || ninfo < 8)
+        return HOS_EINVAL;
+    int st = ord == 5 ? check_c5_args(n, M, HOS_WIN_NONE, 0, path, 0, false)
+                      : check_trispectrum_args(n, M, HOS_WIN_NONE, 0, path, 0, false);
+    if (st != HOS_OK)
+        return st;
+    C4Plan p;
+    make_c4_plan(n, M, path, 0, p, ord);
     info[0] = p.P;
     info[1] = p.RB;
     info[2] = p.NCB;
@@ -443,6 +560,16 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
     info[6] = p.C;
     info[7] = (int64_t)p.total;
     return HOS_OK;
+}
+
+int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo)
+{
+    return moment_plan_info(n, M, path, info, ninfo, 4);
+}
+
+int hos_c5_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo)
+{
+    return moment_plan_info(n, M, path, info, ninfo, 5);
 }
 
 // Host-only introspection of the contraction schedule (no HIP call):

@@ -85,6 +85,77 @@ __device__ inline double c4_at(const double *__restrict__ m4tab, const double *_
     return m4 - c2[c] * c2[a - b] - c2[b] * c2[a - c] - c2[a] * c2[b - c];
 }
 
+// Order five.  The fundamental region F5 = {0 <= d <= c <= b <= a <= M} is
+// stored as rows (a, b, c) numbered with c ascending, and within one c as
+// the pairs (a - c, b - c) of the lag range M - c; triple_offset(M, c) is
+// the first row with smallest offset c.
+__host__ __device__ inline int64_t triple_offset(int M, int c)
+{
+    int64_t s = 0;
+    for (int k = 0; k < c; ++k)
+        s += (int64_t)(M - k + 1) * (M - k + 2) / 2;
+    return s;
+}
+
+__device__ inline void sort5(int *v)
+{
+#define SW(i, j)                 \
+    if (v[i] > v[j]) {           \
+        const int t_ = v[i];     \
+        v[i] = v[j];             \
+        v[j] = t_;               \
+    }
+    SW(0, 1) SW(3, 4) SW(2, 4) SW(2, 3) SW(0, 3) SW(0, 2) SW(1, 4) SW(1, 3) SW(1, 2)
+#undef SW
+}
+
+// c5(t1..t4), 0 outside {span <= M}: the fifth moment minus c2 * c3 over the
+// ten ways to split the five offsets into a pair and a triple, evaluated at
+// the orbit's canonical member (sorted offsets from 0) so that every member
+// of an orbit gets the bitwise same value.  c3tab[a][b] (b <= a, stride
+// M + 1) holds the final third-order cumulants.
+__device__ inline double c5_at(const double *__restrict__ m5tab, const double *__restrict__ c2,
+                               const double *__restrict__ c3tab, int M, double norm5, int t1,
+                               int t2, int t3, int t4)
+{
+    int v[5] = {0, t1, t2, t3, t4};
+    sort5(v);
+    const int q[5] = {0, v[1] - v[0], v[2] - v[0], v[3] - v[0], v[4] - v[0]};
+    const int a = q[4], b = q[3], c = q[2], d = q[1];
+    if (a > M)
+        return 0.0;
+    const int64_t r = triple_offset(M, c) + pair_offset(M - c, b - c) + (a - b);
+    double v5 = m5tab[r * (M + 1) + d] / norm5;
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+        for (int k = j + 1; k < 5; ++k) {
+            int u[3], m = 0;
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                if (i != j && i != k)
+                    u[m++] = q[i];
+            v5 -= c2[q[k] - q[j]] * c3tab[(u[2] - u[0]) * (M + 1) + (u[1] - u[0])];
+        }
+    return v5;
+}
+
+// Lag window of order five: d over the ten pairwise differences of
+// {0, t1, t2, t3, t4} (HOS_WIN_PARZEN), d(t1) d(t2) d(t3) d(t4) (separable),
+// or 1.
+__device__ inline double window5(int t1, int t2, int t3, int t4, int M, int window)
+{
+    if (window == HOS_WIN_NONE)
+        return 1.0;
+    const int o[5] = {0, t1, t2, t3, t4};
+    double w = parzen_d(t1, M) * parzen_d(t2, M) * parzen_d(t3, M) * parzen_d(t4, M);
+    if (window == HOS_WIN_PARZEN)
+        for (int j = 1; j < 5; ++j)
+            for (int k = j + 1; k < 5; ++k)
+                w *= parzen_d(o[k] - o[j], M);
+    return w;
+}
+
 // SplitMix64 output function (Steele, Lea and Flood, "Fast splittable
 // pseudorandom number generators", OOPSLA 2014): a counter-based mix of z.
 __device__ inline uint64_t splitmix64(uint64_t z)

@@ -171,6 +171,7 @@ struct C3Plan : SeriesPlan {
 // The sample axis is split into S ranges of CPS chunks; workgroup (x, s)
 // runs pair blocks 4x .. 4x+3 over range s.
 struct C4Plan : SeriesPlan {
+    int32_t ord;       // 4 (trispectrum) or 5 (order five: P rows are lag triples)
     int32_t P;         // lag pairs
     int32_t RB;        // 32-pair blocks
     int32_t NCB;       // 32-column blocks of the third lag c = 0..M
@@ -180,16 +181,19 @@ struct C4Plan : SeriesPlan {
     int32_t dot_blocks;// workgroups per c2 lag
     int64_t C;         // chunks of KC samples
     size_t off_part, off_m4, off_c2part, off_c2, off_twid, total;
+    size_t off_c3part, off_c3tab;   // order five: third-order corrections
 };
 
 constexpr int C4_MAX_M = 127;      // 4 column blocks per pair block
+constexpr int C5_MAX_M = 40;       // order five: (2M+1)^4 lags of output
+constexpr int C5_MAX_NFFT = 96;    // order five: N^4 complex128 spectrum
 constexpr int C4_MAX_NFFT = 512;   // N^3 complex128 <= 2 GiB
 
 constexpr int MOM_BLOCKS = 256;     // blocks of the moments pass
 constexpr int SK_MAX_WG = 256;      // persistent workgroups of the contraction
 
 int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p);
-int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p);
+int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p, int ord);
 int c4_window_entries(int M);
 
 // ---------------------------------------------------------------------------
@@ -346,5 +350,8 @@ hipError_t launch_c4_reduce(const void *x, int dtype, const C4Plan &p, char *ws,
                             hipStream_t s);
 hipError_t launch_c4_finish(const C4Plan &p, int window, int nfft, double *c4, double *T,
                             char *ws, hipStream_t s);
+hipError_t launch_c5_finish(const C4Plan &p, int window, int nfft, double *c5, double *Q,
+                            char *ws, hipStream_t s);
+hipError_t launch_fft4_axes(double *Q, int N, const double2 *tw, hipStream_t s);
 
 }  // namespace hos

@@ -51,6 +51,36 @@ __device__ inline void pair_ab(int M, int p, int &a, int &b)
     a = bb + (p - pair_offset(M, bb));
 }
 
+// (a, b, c) of order-five row r: rows with smallest offset c come in the
+// pair order of the lag range M - c, shifted by c.
+__device__ inline void triple_abc(int M, int r, int &a, int &b, int &c)
+{
+    int cc = 0;
+    while (cc < M && triple_offset(M, cc + 1) <= r)
+        ++cc;
+    int ap, bp;
+    pair_ab(M - cc, r - (int)triple_offset(M, cc), ap, bp);
+    a = ap + cc;
+    b = bp + cc;
+    c = cc;
+}
+
+// Row r of the order-ORD contraction: the lag offsets whose samples multiply
+// x_i (a, b for order four; a, b, c for order five) and the bound of its
+// Hankel columns (the smallest offset: b, resp. c).
+template <int ORD>
+__device__ inline void row_offsets(int M, int r, int &a, int &b, int &c, int &bound)
+{
+    if constexpr (ORD == 4) {
+        pair_ab(M, r, a, b);
+        c = 0;
+        bound = b;
+    } else {
+        triple_abc(M, r, a, b, c);
+        bound = c;
+    }
+}
+
 template <int PATH>
 struct C4Ops;
 
@@ -174,12 +204,14 @@ c4_store(const u32x4 (&stg)[NPW], C4Lds<PATH, WX> &L, int wave, int lane, bool n
     }
 }
 
-// One chunk for one wave: pair block rows (lane rl holds pair (a, b); `live`
-// zeroes the rows of pairs past the end) against NCOL column blocks.
-template <int PATH, int WX, int NCOL>
-__device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, float live, int rl,
-                                int h, floatx16 (&acc)[NCOL], double (&acc64)[NCOL][16],
-                                float sgn)
+// One chunk for one wave: row block rows (lane rl holds row (a, b[, c]);
+// `live` zeroes the rows past the end) against NCOL column blocks.  Order
+// four: product row x_i x_{i+a} x_{i+b}; order five: x_i x_{i+a} x_{i+b}
+// x_{i+c}; its last factor is split from the exact FP32 product.
+template <int ORD, int PATH, int WX, int NCOL>
+__device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, int c, float live,
+                                int rl, int h, floatx16 (&acc)[NCOL],
+                                double (&acc64)[NCOL][16], float sgn)
 {
     constexpr int NG = KC / GROUP;
     constexpr int WLEN = C4Lds<PATH, WX>::WLEN;
@@ -193,6 +225,16 @@ __device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, float li
 #pragma unroll
         for (int j = 0; j < 8; ++j)
             p[j] = xi[j] * xa[j] * live;
+        if constexpr (ORD == 5) {
+            // x_{i+b} joins the product; x_{i+c} is the last factor
+            float xc[8];
+            unpack8(L.xw[ib + c], L.xw[ib + c + 4], xc);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                p[j] *= xb[j];
+                xb[j] = xc[j];
+            }
+        }
         if constexpr (PATH == HOS_PATH_FP32) {
             float y[8];
 #pragma unroll
@@ -246,11 +288,11 @@ __device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, float li
 // The chunk loop of one workgroup with NCOL column blocks per wave (uniform
 // over the workgroup, so every wave takes the same instantiation and meets
 // the same barriers).
-template <int PATH, int WX, int NCOL>
+template <int ORD, int PATH, int WX, int NCOL>
 __device__ inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict__ xf,
                               const uint4 *__restrict__ win4, const uint4 *__restrict__ win8h,
                               const uint4 *__restrict__ win8l, double *__restrict__ part,
-                              int a, int b, float live, int rb, int s, int RB, int NCB,
+                              int a, int b, int c3, float live, int rb, int s, int RB, int NCB,
                               int64_t c0, int64_t c1, int wave, int lane)
 {
     const int rl = lane & 31, h = lane >> 5;
@@ -275,8 +317,8 @@ __device__ inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict
         const bool has_next = c + 1 < c1;
         if (has_next)
             c4_load<PATH, WX>(stg, xf, win4, win8h, win8l, (c + 1) * KC, wave, lane);
-        c4_chunk<PATH, WX, NCOL>(buf[cur], a, b, live, rl, h, acc, acc64,
-                                 (c & 1) ? -1.0f : 1.0f);
+        c4_chunk<ORD, PATH, WX, NCOL>(buf[cur], a, b, c3, live, rl, h, acc, acc64,
+                                      (c & 1) ? -1.0f : 1.0f);
         if (!has_next)
             break;
         cur ^= 1;
@@ -294,16 +336,18 @@ __device__ inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict
     }
 }
 
-// Grid (ceil(RB/4), S): workgroup (x, s) runs pair blocks 4x .. 4x+3 over
-// chunks [s*CPS, min((s+1)*CPS, C)) and writes one FP64 partial per pair
+// Grid (ceil(RB/4), S): workgroup (x, s) runs row blocks 4x .. 4x+3 over
+// chunks [s*CPS, min((s+1)*CPS, C)) and writes one FP64 partial per row
 // block and column block.
-template <int PATH, int WX>
-__global__ void __launch_bounds__(256, 1)
-k_c4_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
-              const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
-              double *__restrict__ part, int M, int P, int RB, int NCB, int64_t C, int CPS)
+template <int ORD, int PATH, int WX>
+__device__ __forceinline__ void moment_contract(C4Lds<PATH, WX> (&buf)[2],
+                                                const float *__restrict__ xf,
+                                                const uint4 *__restrict__ win4,
+                                                const uint4 *__restrict__ win8h,
+                                                const uint4 *__restrict__ win8l,
+                                                double *__restrict__ part, int M, int P, int RB,
+                                                int NCB, int64_t C, int CPS)
 {
-    __shared__ C4Lds<PATH, WX> buf[2];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63, rl = lane & 31;
@@ -314,26 +358,26 @@ k_c4_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
     if (c0 >= c1)
         return;
 
-    // this lane's pair; column blocks = those of the workgroup's last pair
-    // (pairs are ordered by b, so it has the largest b)
-    int a = 0, b = 0;
+    // this lane's row; column blocks = those of the workgroup's last row
+    // (rows are ordered by their bound, so it has the largest)
+    int a = 0, b = 0, c = 0, bound = 0;
     float live = 0.0f;
     if (rb < RB && rb * 32 + rl < P) {
-        pair_ab(M, rb * 32 + rl, a, b);
+        row_offsets<ORD>(M, rb * 32 + rl, a, b, c, bound);
         live = 1.0f;
     }
     int last = blockIdx.x * 128 + 127;
     if (last > P - 1)
         last = P - 1;
-    int al, bl;
-    pair_ab(M, last, al, bl);
-    const int ncol = __builtin_amdgcn_readfirstlane(bl / 32 + 1);
+    int al, bl, cl, boundl;
+    row_offsets<ORD>(M, last, al, bl, cl, boundl);
+    const int ncol = __builtin_amdgcn_readfirstlane(boundl / 32 + 1);
     switch (ncol) {
-#define C4CASE(K)                                                                       \
-    case K:                                                                             \
-        if constexpr (32 * K <= WX)                                                     \
-            c4_run<PATH, WX, K>(buf, xf, win4, win8h, win8l, part, a, b, live, rb, s, RB, \
-                                NCB, c0, c1, wave, lane);                               \
+#define C4CASE(K)                                                                           \
+    case K:                                                                                 \
+        if constexpr (32 * K <= WX)                                                         \
+            c4_run<ORD, PATH, WX, K>(buf, xf, win4, win8h, win8l, part, a, b, c, live, rb, s, \
+                                     RB, NCB, c0, c1, wave, lane);                          \
         break;
         C4CASE(1) C4CASE(2) C4CASE(3) C4CASE(4)
 #undef C4CASE
@@ -342,18 +386,40 @@ k_c4_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
     }
 }
 
-// Sum the S chunk-range partials of one (pair block, column block) in a fixed
-// order and scatter to m4tab[p][c] (scaled sums, c <= b only).  One thread
-// per element: blockIdx.x = (pair block, column block, quarter).
-__global__ void __launch_bounds__(256)
-k_c4_reduce(const double *__restrict__ part, int M, int P, int RB, int NCB, int S,
-            double *__restrict__ m4tab)
+template <int PATH, int WX>
+__global__ void __launch_bounds__(256, 1)
+k_c4_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
+              const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
+              double *__restrict__ part, int M, int P, int RB, int NCB, int64_t C, int CPS)
+{
+    __shared__ C4Lds<PATH, WX> buf[2];
+    moment_contract<4, PATH, WX>(buf, xf, win4, win8h, win8l, part, M, P, RB, NCB, C, CPS);
+}
+
+// Order five: rows (a, b, c), product row x_i x_{i+a} x_{i+b} x_{i+c}
+// against the Hankel columns x_{i+d}, d <= c.
+template <int PATH, int WX>
+__global__ void __launch_bounds__(256, 1)
+k_c5_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
+              const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
+              double *__restrict__ part, int M, int P, int RB, int NCB, int64_t C, int CPS)
+{
+    __shared__ C4Lds<PATH, WX> buf[2];
+    moment_contract<5, PATH, WX>(buf, xf, win4, win8h, win8l, part, M, P, RB, NCB, C, CPS);
+}
+
+// Sum the S chunk-range partials of one (row block, column block) in a fixed
+// order and scatter to mtab[r][d] (scaled sums, d <= the row's bound only).
+// One thread per element: blockIdx.x = (row block, column block, quarter).
+template <int ORD>
+__device__ __forceinline__ void moment_reduce(const double *__restrict__ part, int M, int P,
+                                              int RB, int NCB, int S, double *__restrict__ mtab)
 {
     const int q = blockIdx.x & 3;
     const int rb = (blockIdx.x >> 2) / NCB, cb = (blockIdx.x >> 2) % NCB;
-    int al, bl;
-    pair_ab(M, (rb * 32 + 31 < P ? rb * 32 + 31 : P - 1), al, bl);
-    if (cb > bl / 32)
+    int al, bl, cl, boundl;
+    row_offsets<ORD>(M, (rb * 32 + 31 < P ? rb * 32 + 31 : P - 1), al, bl, cl, boundl);
+    if (cb > boundl / 32)
         return;
     const int e = threadIdx.x + 256 * q;
     double sum = 0.0;
@@ -361,13 +427,27 @@ k_c4_reduce(const double *__restrict__ part, int M, int P, int RB, int NCB, int 
         sum += part[(((int64_t)s * RB + rb) * NCB + cb) * 1024 + e];
     const int v = e >> 6, lane = e & 63;
     const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), col = lane & 31;
-    const int p = rb * 32 + row, c = cb * 32 + col;
-    if (p < P) {
-        int a, b;
-        pair_ab(M, p, a, b);
-        if (c <= b)
-            m4tab[(int64_t)p * (M + 1) + c] = sum;
+    const int r = rb * 32 + row, d = cb * 32 + col;
+    if (r < P) {
+        int a, b, c, bound;
+        row_offsets<ORD>(M, r, a, b, c, bound);
+        if (d <= bound)
+            mtab[(int64_t)r * (M + 1) + d] = sum;
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_c4_reduce(const double *__restrict__ part, int M, int P, int RB, int NCB, int S,
+            double *__restrict__ m4tab)
+{
+    moment_reduce<4>(part, M, P, RB, NCB, S, m4tab);
+}
+
+__global__ void __launch_bounds__(256)
+k_c5_reduce(const double *__restrict__ part, int M, int P, int RB, int NCB, int S,
+            double *__restrict__ m5tab)
+{
+    moment_reduce<5>(part, M, P, RB, NCB, S, m5tab);
 }
 
 // c2 partial sums sum_i x~_i x~_{i+d} (scaled by s^2), d = 0..M, FP64 from
@@ -424,6 +504,108 @@ k_c4_out(const double *__restrict__ m4tab, const double *__restrict__ c2,
     out[idx] = c4_at(m4tab, c2, M, stats[4], t1, t2, t3);
 }
 
+// Order five needs the third-order cumulants for its corrections: the FP64
+// sums sum_i x~_i x~_{i+a} x~_{i+b} (scaled by s^3) over the pairs b <= a of
+// F, one block of workgroups per pair, from the input.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_c3_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats, int M,
+         int nblocks, double *__restrict__ dpart)
+{
+    __shared__ double red[256];
+    const int pr = blockIdx.x / nblocks, blk = blockIdx.x % nblocks;
+    int a, b;
+    pair_ab(M, pr, a, b);
+    const double mu = stats[0], sc = stats[1];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i + a < n; i += (int64_t)nblocks * 256)
+        acc += (((double)x[i] - mu) * sc) * (((double)x[i + a] - mu) * sc) *
+               (((double)x[i + b] - mu) * sc);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        dpart[blockIdx.x] = red[0];
+}
+
+// c3tab[a][b] = (sum of partials) / (n s^3), b <= a (stride M + 1).
+__global__ void __launch_bounds__(64)
+k_c3_final(const double *__restrict__ dpart, int M, int nblocks,
+           const double *__restrict__ stats, int64_t n, double *__restrict__ c3tab)
+{
+    const int pr = blockIdx.x * 64 + threadIdx.x;
+    if (pr >= (M + 1) * (M + 2) / 2)
+        return;
+    int a, b;
+    pair_ab(M, pr, a, b);
+    double s = 0.0;
+    for (int k = 0; k < nblocks; ++k)
+        s += dpart[(int64_t)pr * nblocks + k];
+    const double sc = stats[1];
+    c3tab[a * (M + 1) + b] = s / ((double)n * sc * sc * sc);
+}
+
+__global__ void __launch_bounds__(256)
+k_c5_out(const double *__restrict__ m5tab, const double *__restrict__ c2,
+         const double *__restrict__ c3tab, const double *__restrict__ stats, int M,
+         double *__restrict__ out)
+{
+    const int64_t side = 2 * M + 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= side * side * side * side)
+        return;
+    const int t4 = (int)(idx % side) - M;
+    const int t3 = (int)((idx / side) % side) - M;
+    const int t2 = (int)((idx / (side * side)) % side) - M;
+    const int t1 = (int)(idx / (side * side * side)) - M;
+    out[idx] = c5_at(m5tab, c2, c3tab, M, stats[4] * stats[1], t1, t2, t3, t4);
+}
+
+// The windowed c5 folded onto the N^4 DFT grid (index w mod N, aliases
+// summed), as complex values for the in-place axis transforms.
+__global__ void __launch_bounds__(256)
+k_c5_fold(const double *__restrict__ m5tab, const double *__restrict__ c2,
+          const double *__restrict__ c3tab, const double *__restrict__ stats, int M, int N,
+          int window, double2 *__restrict__ Q)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t NN = (int64_t)N * N;
+    if (idx >= NN * NN)
+        return;
+    const int m[4] = {(int)(idx / (NN * N)), (int)((idx / NN) % N), (int)((idx / N) % N),
+                      (int)(idx % N)};
+    const double norm5 = stats[4] * stats[1];
+    double sum = 0.0;
+    for (int k0 = 0; k0 < 2; ++k0) {
+        const int w1 = m[0] - k0 * N;
+        if (w1 < -M || w1 > M)
+            continue;
+        for (int k1 = 0; k1 < 2; ++k1) {
+            const int w2 = m[1] - k1 * N;
+            if (w2 < -M || w2 > M)
+                continue;
+            for (int k2 = 0; k2 < 2; ++k2) {
+                const int w3 = m[2] - k2 * N;
+                if (w3 < -M || w3 > M)
+                    continue;
+                for (int k3 = 0; k3 < 2; ++k3) {
+                    const int w4 = m[3] - k3 * N;
+                    if (w4 < -M || w4 > M)
+                        continue;
+                    const double wv = window5(w1, w2, w3, w4, M, window);
+                    if (wv != 0.0)
+                        sum += wv * c5_at(m5tab, c2, c3tab, M, norm5, w1, w2, w3, w4);
+                }
+            }
+        }
+    }
+    Q[idx] = make_double2(sum, 0.0);
+}
+
 template <int PATH, int WX>
 void launch_c4_t(const C4Plan &p, char *ws, hipStream_t s)
 {
@@ -434,9 +616,28 @@ void launch_c4_t(const C4Plan &p, char *ws, hipStream_t s)
         (double *)(ws + p.off_part), p.M, p.P, p.RB, p.NCB, p.C, p.CPS);
 }
 
+template <int PATH, int WX>
+void launch_c5_t(const C4Plan &p, char *ws, hipStream_t s)
+{
+    dim3 grid((p.RB + 3) / 4, p.S);
+    k_c5_contract<PATH, WX><<<grid, 256, 0, s>>>(
+        (const float *)(ws + p.off_xf), (const uint4 *)(ws + p.off_win4),
+        (const uint4 *)(ws + p.off_win8h), (const uint4 *)(ws + p.off_win8l),
+        (double *)(ws + p.off_part), p.M, p.P, p.RB, p.NCB, p.C, p.CPS);
+}
+
 template <int WX>
 void launch_c4_path(const C4Plan &p, char *ws, hipStream_t s)
 {
+    if (p.ord == 5) {
+        if (p.path == HOS_PATH_FP32)
+            launch_c5_t<HOS_PATH_FP32, WX>(p, ws, s);
+        else if (p.path == HOS_PATH_SPLIT_FP16)
+            launch_c5_t<HOS_PATH_SPLIT_FP16, WX>(p, ws, s);
+        else
+            launch_c5_t<HOS_PATH_SPLIT_BF16, WX>(p, ws, s);
+        return;
+    }
     if (p.path == HOS_PATH_FP32)
         launch_c4_t<HOS_PATH_FP32, WX>(p, ws, s);
     else if (p.path == HOS_PATH_SPLIT_FP16)
@@ -472,8 +673,12 @@ hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s)
 
 hipError_t launch_c4_reduce(const void *x, int dtype, const C4Plan &p, char *ws, hipStream_t s)
 {
-    k_c4_reduce<<<p.RB * p.NCB * 4, 256, 0, s>>>((const double *)(ws + p.off_part), p.M, p.P, p.RB,
-                                            p.NCB, p.S, (double *)(ws + p.off_m4));
+    if (p.ord == 5)
+        k_c5_reduce<<<p.RB * p.NCB * 4, 256, 0, s>>>((const double *)(ws + p.off_part), p.M, p.P,
+                                                     p.RB, p.NCB, p.S, (double *)(ws + p.off_m4));
+    else
+        k_c4_reduce<<<p.RB * p.NCB * 4, 256, 0, s>>>((const double *)(ws + p.off_part), p.M, p.P,
+                                                     p.RB, p.NCB, p.S, (double *)(ws + p.off_m4));
     const double *stats = (const double *)(ws + p.off_stats);
     double *dpart = (double *)(ws + p.off_c2part);
     const int grid = (p.M + 1) * p.dot_blocks;
@@ -483,6 +688,38 @@ hipError_t launch_c4_reduce(const void *x, int dtype, const C4Plan &p, char *ws,
         k_c2_dot<float><<<grid, 256, 0, s>>>((const float *)x, p.n, stats, p.dot_blocks, dpart);
     k_c2_final<<<(p.M + 64) / 64, 64, 0, s>>>(dpart, p.M, p.dot_blocks, stats, p.n,
                                               (double *)(ws + p.off_c2));
+    if (p.ord == 5) {
+        const int pairs = (p.M + 1) * (p.M + 2) / 2;
+        double *c3part = (double *)(ws + p.off_c3part);
+        const int g3 = pairs * p.dot_blocks;
+        if (dtype == HOS_F64)
+            k_c3_dot<double><<<g3, 256, 0, s>>>((const double *)x, p.n, stats, p.M,
+                                                p.dot_blocks, c3part);
+        else
+            k_c3_dot<float><<<g3, 256, 0, s>>>((const float *)x, p.n, stats, p.M,
+                                               p.dot_blocks, c3part);
+        k_c3_final<<<(pairs + 63) / 64, 64, 0, s>>>(c3part, p.M, p.dot_blocks, stats, p.n,
+                                                   (double *)(ws + p.off_c3tab));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_c5_finish(const C4Plan &p, int window, int nfft, double *c5, double *Q,
+                            char *ws, hipStream_t s)
+{
+    const double *m5 = (const double *)(ws + p.off_m4);
+    const double *c2 = (const double *)(ws + p.off_c2);
+    const double *c3 = (const double *)(ws + p.off_c3tab);
+    const double *stats = (const double *)(ws + p.off_stats);
+    if (c5) {
+        const int64_t side = 2 * p.M + 1, tot = side * side * side * side;
+        k_c5_out<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(m5, c2, c3, stats, p.M, c5);
+    }
+    if (Q) {
+        const int64_t tot = (int64_t)nfft * nfft * nfft * nfft;
+        k_c5_fold<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(m5, c2, c3, stats, p.M, nfft,
+                                                               window, (double2 *)Q);
+    }
     return hipGetLastError();
 }
 

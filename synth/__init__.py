@@ -60,6 +60,14 @@ def cubic_process(n: int, seed: int, b: float = 0.4) -> np.ndarray:
     return e[3:] + b * e[2:-1] * e[1:-2] * e[:-3]
 
 
+def quartic_process(n: int, seed: int, b: float = 0.3) -> np.ndarray:
+    """x_t = e_t + b e_{t-1} e_{t-2} e_{t-3} e_{t-4} for t = 0..n-1, e ~ N(0,1):
+    its fifth cumulant is b at the offsets {0, 1, 2, 3, 4} (up to order b^3)."""
+    n = int(n)
+    e = _rng(seed).standard_normal(n + 4)  # e[k] is e_{k-4}
+    return e[4:] + b * e[3:-1] * e[2:-2] * e[1:-3] * e[:-4]
+
+
 def batched_series(batch: int, seed: int, n_range=BATCH_N_RANGE,
                    m_choices=BATCH_M_CHOICES):
     """Return (list of float64 series, lengths, max lags) for a batch.
@@ -153,3 +161,9 @@ def workload_segments(n: int = 1 << 20):
     512, 1024-point DFT."""
     x, cfg = workload_long_bispectrum(n)
     return x, dict(P=n // 16, M=cfg["M"], nfft=cfg["nfft"])
+
+
+def workload_cumulant5(n: int = 1 << 18):
+    """Order five: n = 2^18 float32 quartic process, maximum lag 24, 48^4 DFT."""
+    x = quartic_process(n, SEED_BASE + 8).astype(np.float32)
+    return x, dict(M=24, nfft=48)

@@ -136,3 +136,30 @@ def test_c4_plan(n, M, path):
     assert (S - 1) * cps < C <= S * cps
     assert info["ws_bytes"] == hos.hos_trispectrum_workspace(n, M, 0, path)
     assert hos.hos_trispectrum_workspace(n, M, hos.default_nfft(M), path) > info["ws_bytes"]
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(M=41), hos.HOS_EINVAL),              # beyond the order-five lag limit
+    (dict(nfft=120, M=40), hos.HOS_EINVAL),    # beyond the 4-D DFT limit
+    (dict(nfft=20, M=12), hos.HOS_EINVAL),     # < 2M with Parzen
+    (dict(window=3), hos.HOS_EINVAL),
+    (dict(c5=None, Q=None), hos.HOS_EINVAL),
+    (dict(Q=FAKE + 8), hos.HOS_EINVAL),
+    (dict(ws_bytes=16), hos.HOS_EWORKSPACE),
+])
+def test_cumulant5_validation_before_device(kw, code):
+    a = dict(x=FAKE, dtype=hos.HOS_F32, n=4096, M=8, window=hos.HOS_WIN_PARZEN,
+             nfft=16, path=hos.HOS_PATH_SPLIT_FP16, flags=0, c5=FAKE, Q=FAKE, ws=FAKE,
+             ws_bytes=1 << 40)
+    a.update(kw)
+    st = hos.lib().hos_cumulant5(a["x"], a["dtype"], a["n"], a["M"], a["window"], a["nfft"],
+                                 a["path"], a["flags"], a["c5"], a["Q"], a["ws"],
+                                 a["ws_bytes"], None)
+    assert st == code
+
+
+def test_c5_plan():
+    info = hos.hos_c5_plan_info(1 << 18, 24, hos.HOS_PATH_SPLIT_FP16)
+    assert info["P"] == 25 * 26 * 27 // 6 and info["RB"] == (info["P"] + 31) // 32
+    assert info["NCB"] == 1 and info["WX"] >= 32 * info["NCB"] + 16
+    assert info["S"] * info["CPS"] >= info["C"]
