@@ -20,7 +20,8 @@ x_t = e_t + 0.4 e_{t-1} e_{t-2} e_{t-3}, M = 48, six-factor Parzen window,
 96^3 DFT; metric n (2M+1)^3 lag-sums per second.  Further records:
 ``batched`` (4096 uneven series in one call), ``loss`` (bispectrum-matching
 loss forward and adjoint), ``segments`` (the headline series in 16
-segments, each centred on its own mean, cumulants averaged) and
+segments, each centred on its own mean, cumulants averaged), ``order5``
+(the fifth cumulant and its 4-D spectrum, n = 2^18, M = 24) and
 ``direct_method`` (Algorithm DBS with
 window-sum smoothing, n = 2^16 as one part, 1023 x 1023 box, with an HBM
 roofline of the smoothing kernel).
@@ -192,6 +193,74 @@ def bench_trispectrum(hos, torch, oracle, synth, paths, steps, warmup, cpu_secon
             t0 = time.perf_counter()
         rec["cpu_oracle"] = {"value": k * n / el, "unit": "lag-sums/s", "kind": "oracle",
                              "sample": "%d random lags x n=%d, FP64 brute-force c4 (%.1f s)"
+                                       % (k, n, el)}
+    return rec
+
+
+def bench_cumulant5(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds):
+    """Order five: n = 2^18 float32 quartic process, M = 24, ten-difference
+    Parzen window, 48^4 DFT; metric n (2M+1)^4 lag-sums/s; roofline of the
+    fifth-moment contraction (one MAC per (i, a, b, c, d) of F5)."""
+    x, cfg = synth.workload_cumulant5()
+    M, N = cfg["M"], cfg["nfft"]
+    n = x.size
+    xt = torch.from_numpy(x).cuda()
+    lagsums = float(n) * (2 * M + 1) ** 4
+    flops = 2.0 * n * (M + 1) * (M + 2) * (M + 3) * (M + 4) / 24
+    rng = np.random.default_rng(14)
+    t = np.concatenate([[[1, 2, 3, 4], [0, 0, 0, 0]], rng.integers(-M, M + 1, (120, 4))])
+    ref = oracle.c5_at(x, t[:, 0], t[:, 1], t[:, 2], t[:, 3])
+    span = np.maximum(t.max(1), 0) - np.minimum(t.min(1), 0)
+    ref[span > M] = 0.0
+    scale = float(np.mean(np.abs(x.astype(np.float64) - np.mean(x.astype(np.float64))) ** 5))
+    out = {}
+    ws = None
+    for path in paths:
+        print("bench: order five path %s" % path, file=sys.stderr, flush=True)
+        c5, _ = hos.cumulant5(xt, M, N, path=path)
+        ms = _time(torch, lambda: hos.cumulant5(xt, M, N, path=path), max(3, steps // 5),
+                   max(2, warmup // 5))
+        st = [hos.cumulant5(xt, M, N, path=path, timed=True)[2] for _ in range(5)]
+        stage_ms = {k: float(np.median([d[k] for d in st])) for k in st[0]}
+        got = c5.cpu().numpy()[t[:, 0] + M, t[:, 1] + M, t[:, 2] + M, t[:, 3] + M]
+        err = float(np.max(np.abs(got - ref)) / scale)
+        t_k = stage_ms["contract"] * 1e-3
+        out[path] = {"ms_per_step": ms, "value": lagsums / (ms * 1e-3), "rel_err_m5abs": err,
+                     "within_tol": err <= TOL[path], "stage_ms": stage_ms,
+                     "contract_tflops": flops / t_k / 1e12,
+                     "contract_frac": flops / t_k / PEAK[path]}
+        print("bench: order five %s %.3f ms/step, contract %.3f ms, err %.2e" %
+              (path, ms, stage_ms["contract"], err), file=sys.stderr, flush=True)
+    head = "split_fp16" if "split_fp16" in out else next(iter(out))
+    hp = out[head]
+    t_k = hp["stage_ms"]["contract"] * 1e-3
+    rec = {"metric": "cumulant lag-sums/s (n·(2M+1)^4/s)", "value": hp["value"],
+           "unit": "lag-sums/s", "ms_per_step": hp["ms_per_step"], "dtype": DTYPE[head],
+           "config": {"workload": "order-five cumulant and 4-D spectrum of one n=2^18 float32 "
+                                  "quartic-process series (x_t = e_t + 0.3 e_{t-1} e_{t-2} "
+                                  "e_{t-3} e_{t-4}), M=24, ten-difference Parzen window, "
+                                  "48^4 DFT",
+                      "n": n, "M": M, "nfft": N, "path": head},
+           "roofline": {"bound": "mfma", "kernel": "k_c5_contract",
+                        "achieved": flops / t_k / 1e12, "peak": PEAK[head] / 1e12,
+                        "unit": "TFLOP/s", "frac": flops / t_k / PEAK[head], "traffic": None,
+                        "flops_per_launch": flops, "avg_launch_ms": hp["stage_ms"]["contract"]},
+           "paths": out}
+    if cpu_seconds > 0:
+        t0 = time.perf_counter()
+        k = 16
+        while True:
+            tt = rng.integers(-M, M + 1, (k, 4))
+            oracle.c5_at(x, tt[:, 0], tt[:, 1], tt[:, 2], tt[:, 3])
+            el = time.perf_counter() - t0
+            if el > cpu_seconds or k > 1 << 20:
+                break
+            k *= 2
+            t0 = time.perf_counter()
+        rec["cpu_oracle"] = {"value": k * n / el, "unit": "lag-sums/s", "kind": "oracle",
+                             "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                         len(os.sched_getaffinity(0)))),
+                             "sample": "%d random lags x n=%d, FP64 brute-force c5 (%.1f s)"
                                        % (k, n, el)}
     return rec
 
@@ -577,6 +646,9 @@ def main():
         rec["trispectrum"] = bench_trispectrum(
             hos, torch, oracle, synth, list(paths), args.steps, args.warmup,
             0.0 if args.no_cpu_baseline else 5.0)
+    if not args.no_tri:
+        rec["order5"] = bench_cumulant5(hos, torch, oracle, synth, list(paths), args.steps,
+                                        args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
     if not args.no_batch:
         rec["segments"] = bench_segments(hos, torch, oracle, synth, list(paths), args.steps,
                                          args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
