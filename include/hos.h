@@ -231,6 +231,29 @@ int hos_trispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M,
 int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t ninfo);
 
 /*
+ * A record in host memory, streamed (the memory frugality of Section 3's
+ * window-sum theorems, for the indirect estimator): the same c3 and B as
+ * hos_bispectrum on the whole record, computed through a device workspace
+ * whose size depends on the piece length P and M but not on n.  The record
+ * is read twice in pieces of P samples (hipMemcpyAsync on `stream`): first
+ * for its FP64 mean and scale, then each piece with the M samples after it,
+ * whose sums are added to a running FP64 table.
+ *   x_host  host memory, n samples (pinned memory lets the copies run at
+ *           full speed; pageable memory works too), HOS_F32 or HOS_F64.
+ *   piece   P: a multiple of 1024, >= 4096, >= M.
+ *   c3, B, window, nfft, path, flags: as hos_bispectrum (device outputs).
+ * Workspace: hos_bispectrum_streamed_workspace (dtype sets the size of the
+ * piece buffer).  Results equal hos_bispectrum's up to the order of FP64
+ * additions.
+ */
+int hos_bispectrum_streamed_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
+                                      int32_t dtype, int64_t piece, size_t *bytes);
+int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_t M,
+                            int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                            int64_t piece, double *c3, double *B, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/*
  * ------------------------------------------------------------------------
  * Order five (the k-th order generalisation of Section 3 at k = 5).
  *

@@ -85,6 +85,10 @@ def _load_lib():
                                                  ctypes.POINTER(ctypes.c_float)]),
         "hos_c4_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
         "hos_c5_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
+        "hos_bispectrum_streamed_workspace": (ctypes.c_int, [i64, i32, i32, i32, i32, i64,
+                                                             ctypes.POINTER(sz)]),
+        "hos_bispectrum_streamed": (ctypes.c_int, [vp, i32, i64, i32, i32, i32, i32, u32, i64,
+                                                   vp, vp, vp, sz, vp]),
         "hos_cumulant5_workspace": (ctypes.c_int, [i64, i32, i32, i32, u32,
                                                    ctypes.POINTER(sz)]),
         "hos_cumulant5": (ctypes.c_int, [vp, i32, i64, i32, i32, i32, i32, u32,
@@ -403,6 +407,49 @@ def dbs(x, P: int, M3: int, center: bool = True, workspace=None, timed: bool = F
     if st != HOS_OK:
         raise HosError(st, "hos_dbs")
     return B
+
+
+def bispectrum_streamed(x, M: int, piece: int = 1 << 22, nfft: int | None = None,
+                        window: str = "parzen", path: str = "fp32", center: bool = True,
+                        device="cuda", return_c3: bool = True, return_B: bool = True,
+                        workspace=None):
+    """``hos_bispectrum_streamed``: c3 and B of a record held in host memory
+    (a CPU torch tensor, ideally pinned, or a numpy array), streamed in
+    pieces of ``piece`` samples through a device workspace independent of
+    n.  Outputs are CUDA tensors on ``device``."""
+    import numpy as np
+    import torch
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    if not isinstance(x, torch.Tensor) or x.is_cuda:
+        raise TypeError("x must be a host (CPU) tensor or a numpy array")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
+    x = x.contiguous().view(-1)
+    n = x.numel()
+    dtype = HOS_F64 if x.dtype == torch.float64 else HOS_F32
+    pth, win = PATHS[path], WINDOWS[window]
+    if nfft is None:
+        nfft = default_nfft(M, window)
+    nf = nfft if return_B else 0
+    out = ctypes.c_size_t(0)
+    st = lib().hos_bispectrum_streamed_workspace(n, M, nf, pth, dtype, int(piece),
+                                                ctypes.byref(out))
+    if st != HOS_OK:
+        raise HosError(st, "hos_bispectrum_streamed_workspace")
+    dev = torch.device(device)
+    if workspace is None or workspace.numel() < out.value:
+        workspace = torch.empty(out.value, dtype=torch.uint8, device=dev)
+    c3 = torch.empty((2 * M + 1, 2 * M + 1), dtype=torch.float64,
+                     device=dev) if return_c3 else None
+    B = torch.empty((nfft, nfft), dtype=torch.complex128, device=dev) if return_B else None
+    st = lib().hos_bispectrum_streamed(
+        x.data_ptr(), dtype, n, M, win, nf, pth, 0 if center else HOS_NO_CENTER, int(piece),
+        c3.data_ptr() if c3 is not None else None, B.data_ptr() if B is not None else None,
+        workspace.data_ptr(), workspace.numel(), _stream_handle(dev))
+    if st != HOS_OK:
+        raise HosError(st, "hos_bispectrum_streamed")
+    return c3, B
 
 
 STAGES5 = ("prep", "contract", "reduce_fold", "dft", "total")

@@ -305,10 +305,14 @@ inline int64_t tile_elems(int NB) { return (int64_t)(32 * NB) * (32 * NB); }
 hipError_t launch_moments(const void *x, int dtype, int64_t n, uint32_t flags,
                           const SeriesPlan &p, char *ws, hipStream_t s);
 hipError_t launch_prep(const void *x, int dtype, const SeriesPlan &p, char *ws,
-                       hipStream_t s);
+                       hipStream_t s, int64_t key0 = 0, int64_t nfirst = -1);
+hipError_t launch_moments_piece(const void *x, int dtype, int64_t len, int first,
+                                const SeriesPlan &p, char *ws, double *acc, hipStream_t s);
+hipError_t launch_moments_total(const double *acc, int64_t n, uint32_t flags, int top,
+                                double *stats, hipStream_t s);
 hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s);
 hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws,
-                           hipStream_t s);
+                           hipStream_t s, int64_t nfirst = -1);
 hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s);
 hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3,
                             double *B, char *ws, hipStream_t s);

@@ -1,0 +1,215 @@
+// hos_stream.hip -- the bispectrum of a record held in host memory, streamed
+// through a device workspace whose size depends on the piece length and M,
+// not on n (the memory frugality of Section 3's window-sum theorems, applied
+// to the indirect estimator).
+//
+// The record is read twice, piece by piece (P samples a piece).  Pass one
+// accumulates the sum, minimum and maximum in FP64, in piece order, giving
+// the whole record's mean and scale.  Pass two copies each piece together
+// with the next M samples (its halo) and runs the single-series stages on
+// it: the operands are rounded with the keys of their place in the record,
+// the first factor x_i stops at the piece's end, so the contraction and the
+// diagonal sums add exactly the terms with i in the piece; the piece's
+// reduced table is added to a running FP64 table.  The sum over the pieces
+// is the sum over the record, so the result is the whole record's c3 and B
+// (up to the order of FP64 additions).
+#include <string.h>
+
+#include "hos_internal.h"
+
+namespace hos {
+
+namespace {
+
+__global__ void __launch_bounds__(256)
+k_table_add(double *__restrict__ acc, const double *__restrict__ add, int64_t count, int first)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count)
+        return;
+    acc[e] = first ? add[e] : acc[e] + add[e];
+}
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// samples piece k reads: its own, then up to M of the next piece's
+int64_t piece_len(int64_t n, int64_t P, int64_t k) { return n - k * P < P ? n - k * P : P; }
+int64_t piece_data(int64_t n, int32_t M, int64_t P, int64_t k)
+{
+    const int64_t len = piece_len(n, P, k), rest = n - k * P;
+    return rest < len + M ? rest : len + M;
+}
+
+struct StreamLayout {
+    int64_t P, halo;          // piece length, halo samples
+    size_t plan_bytes;        // largest single-series plan of a piece
+    size_t off_acc, off_mom, off_x, total;
+};
+
+int stream_layout(int64_t n, int32_t M, int32_t nfft, int32_t path, int64_t P, int esize,
+                  StreamLayout &L)
+{
+    memset(&L, 0, sizeof(L));
+    L.P = P;
+    L.halo = M;
+    // pieces k hold samples [kP, kP + len) and read data = min(len + M,
+    // n - kP) of them; every piece before the last two reads the same data
+    // run as piece 0, so the plans of pieces 0, pieces-2 and pieces-1 bound
+    // them all
+    const int64_t pieces = (n + P - 1) / P;
+    size_t mx = 0;
+    int64_t data_max = 0;
+    for (int64_t k : {(int64_t)0, pieces - 2, pieces - 1}) {
+        if (k < 0)
+            continue;
+        const int64_t data = piece_data(n, M, P, k);
+        C3Plan p;
+        make_c3_plan(data, M, path, nfft, p);
+        if (p.total > mx)
+            mx = p.total;
+        if (data > data_max)
+            data_max = data;
+    }
+    L.plan_bytes = al256(mx);
+    size_t o = L.plan_bytes;
+    L.off_acc = o;  o = al256(o + (size_t)(M + 1) * (M + 1) * sizeof(double));
+    L.off_mom = o;  o = al256(o + 4 * sizeof(double));
+    L.off_x = o;    o = al256(o + (size_t)data_max * esize);
+    L.total = o;
+    return HOS_OK;
+}
+
+}  // namespace
+
+}  // namespace hos
+
+using namespace hos;
+
+static bool st_aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr & (a - 1)) == 0; }
+
+static int check_stream_args(int64_t n, int32_t M, int32_t window, int32_t nfft, int32_t path,
+                             uint32_t flags, int64_t P, bool want_B)
+{
+    if (n < 2 || n > ((int64_t)1 << 40) || M < 0 || (int64_t)M >= n || M > 8192)
+        return HOS_EINVAL;
+    if (P < 4096 || P > ((int64_t)1 << 31) || P < M || P % 1024 != 0)
+        return HOS_EINVAL;
+    if (path != HOS_PATH_FP32 && path != HOS_PATH_SPLIT_FP16 && path != HOS_PATH_SPLIT_BF16)
+        return HOS_EINVAL;
+    if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN && window != HOS_WIN_PARZEN_SEPARABLE)
+        return HOS_EINVAL;
+    if (flags & ~HOS_NO_CENTER)
+        return HOS_EINVAL;
+    if (want_B) {
+        if (!fft_size_ok(nfft))
+            return HOS_EINVAL;
+        const int64_t need = window != HOS_WIN_NONE ? 2 * (int64_t)M : 2 * (int64_t)M + 1;
+        if (nfft < need || nfft < 2)
+            return HOS_EINVAL;
+    }
+    return HOS_OK;
+}
+
+extern "C" {
+
+int hos_bispectrum_streamed_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
+                                      int32_t dtype, int64_t piece, size_t *bytes)
+{
+    if (!bytes || (dtype != HOS_F32 && dtype != HOS_F64))
+        return HOS_EINVAL;
+    int st = check_stream_args(n, M, HOS_WIN_NONE, 0, path, 0, piece, false);
+    if (st != HOS_OK)
+        return st;
+    if (nfft > 0 && !fft_size_ok(nfft))
+        return HOS_EINVAL;
+    StreamLayout L;
+    stream_layout(n, M, nfft > 0 ? nfft : 0, path, piece, dtype == HOS_F64 ? 8 : 4, L);
+    *bytes = L.total;
+    return HOS_OK;
+}
+
+int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_t M,
+                            int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                            int64_t piece, double *c3, double *B, void *ws, size_t ws_bytes,
+                            hipStream_t stream)
+{
+    if (!x_host || !ws || (!c3 && !B))
+        return HOS_EINVAL;
+    if (dtype != HOS_F32 && dtype != HOS_F64)
+        return HOS_EINVAL;
+    if (!st_aligned(ws, 256) || (c3 && !st_aligned(c3, 8)) || (B && !st_aligned(B, 16)))
+        return HOS_EINVAL;
+    int st = check_stream_args(n, M, window, B ? nfft : 0, path, flags, piece, B != nullptr);
+    if (st != HOS_OK)
+        return st;
+    const int esize = dtype == HOS_F64 ? 8 : 4;
+    StreamLayout L;
+    stream_layout(n, M, B ? nfft : 0, path, piece, esize, L);
+    if (ws_bytes < L.total)
+        return HOS_EWORKSPACE;
+    st = device_ok_public();
+    if (st != HOS_OK)
+        return st;
+
+    char *w = (char *)ws;
+    double *acc = (double *)(w + L.off_acc);
+    double *mom = (double *)(w + L.off_mom);
+    char *xd = w + L.off_x;
+    const char *xh = (const char *)x_host;
+    const int64_t pieces = (n + piece - 1) / piece;
+    hipError_t e = hipSuccess;
+
+    // pass one: sum, minimum, maximum of the record, piece by piece (p0 is
+    // the plan of a full piece with its halo, within the workspace layout)
+    C3Plan p0;
+    make_c3_plan(piece_data(n, M, piece, 0), M, path, B ? nfft : 0, p0);
+    for (int64_t k = 0; k < pieces && e == hipSuccess; ++k) {
+        const int64_t g0 = k * piece, len = piece_len(n, piece, k);
+        e = hipMemcpyAsync(xd, xh + g0 * esize, (size_t)len * esize, hipMemcpyHostToDevice,
+                           stream);
+        if (e == hipSuccess)
+            e = launch_moments_piece(xd, dtype, len, k == 0, p0, w, mom, stream);
+    }
+    // the record's mean and scale into the stats every piece plan reads
+    // (each plan puts its stats at offset 0 of the workspace)
+    double *stats = (double *)(w + p0.off_stats);
+    if (e == hipSuccess)
+        e = launch_moments_total(mom, n, flags, p0.scale_top, stats, stream);
+
+    // pass two: each piece with its halo through the single-series stages
+    const int64_t ne = (int64_t)(M + 1) * (M + 1);
+    for (int64_t k = 0; k < pieces && e == hipSuccess; ++k) {
+        const int64_t g0 = k * piece, len = piece_len(n, piece, k);
+        const int64_t data = piece_data(n, M, piece, k);
+        C3Plan p;
+        make_c3_plan(data, M, path, B ? nfft : 0, p);
+        if (al256(p.total) > L.plan_bytes) {   // the layout bounds every piece's plan
+            e = hipErrorInvalidValue;
+            break;
+        }
+        e = hipMemcpyAsync(xd, xh + g0 * esize, (size_t)data * esize, hipMemcpyHostToDevice,
+                           stream);
+        if (e == hipSuccess) e = launch_prep(xd, dtype, p, w, stream, g0, len);
+        if (e == hipSuccess) e = launch_c3_contract(p, w, stream);
+        if (e == hipSuccess) e = launch_diag_dot(xd, dtype, p, w, stream, len);
+        if (e == hipSuccess) e = launch_c3_reduce(p, w, stream);
+        if (e == hipSuccess) {
+            k_table_add<<<(unsigned)((ne + 255) / 256), 256, 0, stream>>>(
+                acc, (const double *)(w + p.off_cfull), ne, k == 0);
+            e = hipGetLastError();
+        }
+    }
+    // normalise by the whole record (stats[3] = n s^3), window, DFT
+    if (e == hipSuccess) {
+        double2 *tw = B ? (double2 *)(w + p0.off_twid) : nullptr;
+        if (B)
+            e = launch_twiddles(tw, nfft, stream);
+        if (e == hipSuccess)
+            e = launch_c3_finish_table(acc, stats, M, window, nfft, tw, c3, B, stream);
+        if (e == hipSuccess && B)
+            e = launch_fft_cols(B, nfft, tw, stream);
+    }
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
+}  // extern "C"

@@ -639,17 +639,20 @@ k_c3_reduce(const double *__restrict__ part, const int64_t *__restrict__ tfirst,
 // Leftover diagonal sums C[a][a] = sum_i x~_i x~_{i+a}^2 for a = 0 and
 // a = 32k <= M, in FP64 from the input itself (x~ = (x - mean) s formed in
 // FP64, not the FP32 operand copy), as fixed-order partials.
+// The first factor x_i runs over i < nfirst only (a piece of a record with
+// its halo: nfirst is the piece's own length; n for a whole record).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_diag_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats,
-           int nblocks, double *__restrict__ dpart)
+           int nblocks, double *__restrict__ dpart, int64_t nfirst)
 {
     __shared__ double red[256];
     const int left = blockIdx.x / nblocks, blk = blockIdx.x % nblocks;
     const int64_t a = 32 * (int64_t)left;
     const double mu = stats[0], sc = stats[1];
     double s = 0.0;
-    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i + a < n; i += (int64_t)nblocks * 256) {
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i + a < n && i < nfirst;
+         i += (int64_t)nblocks * 256) {
         const double u = ((double)x[i + a] - mu) * sc;
         s += (((double)x[i] - mu) * sc) * u * u;
     }
@@ -674,7 +677,7 @@ constexpr int DIAG_FUSED_MAX = 32;
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_diag_fused(const T *__restrict__ x, int64_t n, const double *__restrict__ stats, int nleft,
-             double *__restrict__ dpart)
+             double *__restrict__ dpart, int64_t nfirst)
 {
     __shared__ double sx[1024 + 32 * (DIAG_FUSED_MAX - 1)];
     __shared__ double wsum[4][DIAG_FUSED_MAX];
@@ -693,7 +696,7 @@ k_diag_fused(const T *__restrict__ x, int64_t n, const double *__restrict__ stat
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int j = threadIdx.x + 256 * q;
-        const double xi = sx[j];
+        const double xi = i0 + j < nfirst ? sx[j] : 0.0;
 #pragma unroll
         for (int k = 0; k < DIAG_FUSED_MAX; ++k)
             if (k < nleft) {
@@ -1001,24 +1004,29 @@ hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws, hipStream_t s)
+hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws, hipStream_t s,
+                           int64_t nfirst)
 {
     const double *stats = (const double *)(ws + p.off_stats);
     double *dpart = (double *)(ws + p.off_dpart);
+    if (nfirst < 0)
+        nfirst = p.n;
     if (p.nleft <= DIAG_FUSED_MAX) {   // the plan made dot_blocks = ceil(n / 1024)
         if (dtype == HOS_F64)
             k_diag_fused<double><<<p.dot_blocks, 256, 0, s>>>((const double *)x, p.n, stats,
-                                                              p.nleft, dpart);
+                                                              p.nleft, dpart, nfirst);
         else
             k_diag_fused<float><<<p.dot_blocks, 256, 0, s>>>((const float *)x, p.n, stats,
-                                                             p.nleft, dpart);
+                                                             p.nleft, dpart, nfirst);
         return hipGetLastError();
     }
     const int grid = p.nleft * p.dot_blocks;
     if (dtype == HOS_F64)
-        k_diag_dot<double><<<grid, 256, 0, s>>>((const double *)x, p.n, stats, p.dot_blocks, dpart);
+        k_diag_dot<double><<<grid, 256, 0, s>>>((const double *)x, p.n, stats, p.dot_blocks, dpart,
+                                                nfirst);
     else
-        k_diag_dot<float><<<grid, 256, 0, s>>>((const float *)x, p.n, stats, p.dot_blocks, dpart);
+        k_diag_dot<float><<<grid, 256, 0, s>>>((const float *)x, p.n, stats, p.dot_blocks, dpart,
+                                               nfirst);
     return hipGetLastError();
 }
 

@@ -116,14 +116,16 @@ __global__ void __launch_bounds__(256) k_moments_final(const double *__restrict_
 }
 
 // (x_o - mean) s formed in FP64 and rounded stochastically to FP32 (keyed by
-// the sample index, so every table entry holding sample o agrees); 0 outside
-// the record.
+// the sample's index in the whole record, key0 + o, so every table entry
+// holding a sample agrees, in whichever piece of the record it is
+// prepared); 0 outside the data.
 template <typename T>
 __device__ inline float centred(const T *__restrict__ x, int64_t n, int64_t o, double mu,
-                                double s)
+                                double s, int64_t key0)
 {
-    return (o >= 0 && o < n) ? round_stochastic_f32(((double)x[o] - mu) * s, (uint64_t)o)
-                             : 0.0f;
+    return (o >= 0 && o < n)
+               ? round_stochastic_f32(((double)x[o] - mu) * s, (uint64_t)(key0 + o))
+               : 0.0f;
 }
 
 __device__ inline void split16(float v, uint16_t &h, uint16_t &l)
@@ -145,24 +147,28 @@ __device__ inline void splitbf(float v, uint16_t &h, uint16_t &l)
 // Table entries [o0, o0 + 256) of one workgroup (entries past oend are not
 // written): the 263 samples they touch are rounded once into LDS, then every
 // table is written from there.  MODE 0: xf and win4; 1/2: also the FP16/BF16
-// hi|lo window tables.
+// hi|lo window tables.  xf -- the first factor x_i of every product -- is 0
+// from nfirst on, so a piece of a record (its samples plus the following
+// M as a halo) sums exactly over its own i while the window tables reach
+// into the halo; nfirst = n for a whole record.
 template <typename T, int MODE>
 __device__ inline void prep_block(const T *__restrict__ x, int64_t n, int64_t o0, int64_t oend,
                                   const double *__restrict__ stats, float *__restrict__ xf,
                                   float4 *__restrict__ win4, uint4 *__restrict__ win8h,
-                                  uint4 *__restrict__ win8l)
+                                  uint4 *__restrict__ win8l, int64_t key0 = 0,
+                                  int64_t nfirst = INT64_MAX)
 {
     __shared__ float sv[256 + 8];
     const double mu = stats[0], s = stats[1];
     const int t = threadIdx.x;
-    sv[t] = centred(x, n, o0 + t, mu, s);
+    sv[t] = centred(x, n, o0 + t, mu, s, key0);
     if (t < 8)
-        sv[256 + t] = centred(x, n, o0 + 256 + t, mu, s);
+        sv[256 + t] = centred(x, n, o0 + 256 + t, mu, s, key0);
     __syncthreads();
     const int64_t o = o0 + t;
     if (o >= oend)
         return;
-    xf[o] = sv[t];
+    xf[o] = o < nfirst ? sv[t] : 0.0f;
     win4[o] = make_float4(sv[t], sv[t + 1], sv[t + 2], sv[t + 3]);
     if constexpr (MODE != 0) {
         uint32_t hw[4], lw[4];
@@ -189,9 +195,11 @@ __global__ void __launch_bounds__(256) k_prep(const T *__restrict__ x, int64_t n
                                               const double *__restrict__ stats,
                                               float *__restrict__ xf, float4 *__restrict__ win4,
                                               uint4 *__restrict__ win8h,
-                                              uint4 *__restrict__ win8l)
+                                              uint4 *__restrict__ win8l, int64_t key0,
+                                              int64_t nfirst)
 {
-    prep_block<T, MODE>(x, n, (int64_t)blockIdx.x * 256, npad, stats, xf, win4, win8h, win8l);
+    prep_block<T, MODE>(x, n, (int64_t)blockIdx.x * 256, npad, stats, xf, win4, win8h, win8l,
+                        key0, nfirst);
 }
 
 // ------------------------------------------------------------------ batches
@@ -264,7 +272,8 @@ hipError_t launch_moments(const void *x, int dtype, int64_t n, uint32_t flags,
 }
 
 template <typename T>
-void launch_prep_t(const T *x, const SeriesPlan &p, char *ws, hipStream_t s)
+void launch_prep_t(const T *x, const SeriesPlan &p, char *ws, hipStream_t s, int64_t key0,
+                   int64_t nfirst)
 {
     const double *stats = (const double *)(ws + p.off_stats);
     float *xf = (float *)(ws + p.off_xf);
@@ -272,19 +281,66 @@ void launch_prep_t(const T *x, const SeriesPlan &p, char *ws, hipStream_t s)
     uint4 *h = (uint4 *)(ws + p.off_win8h), *l = (uint4 *)(ws + p.off_win8l);
     const int64_t blocks = (p.npad + 255) / 256;
     if (p.path == HOS_PATH_FP32)
-        k_prep<T, 0><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l);
+        k_prep<T, 0><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l, key0, nfirst);
     else if (p.path == HOS_PATH_SPLIT_FP16)
-        k_prep<T, 1><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l);
+        k_prep<T, 1><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l, key0, nfirst);
     else
-        k_prep<T, 2><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l);
+        k_prep<T, 2><<<blocks, 256, 0, s>>>(x, p.n, p.npad, stats, xf, win4, h, l, key0, nfirst);
 }
 
-hipError_t launch_prep(const void *x, int dtype, const SeriesPlan &p, char *ws, hipStream_t s)
+hipError_t launch_prep(const void *x, int dtype, const SeriesPlan &p, char *ws, hipStream_t s,
+                       int64_t key0, int64_t nfirst)
 {
+    if (nfirst < 0)
+        nfirst = p.n;
     if (dtype == HOS_F64)
-        launch_prep_t<double>((const double *)x, p, ws, s);
+        launch_prep_t<double>((const double *)x, p, ws, s, key0, nfirst);
     else
-        launch_prep_t<float>((const float *)x, p, ws, s);
+        launch_prep_t<float>((const float *)x, p, ws, s, key0, nfirst);
+    return hipGetLastError();
+}
+
+// Streaming: fold one piece's block partials (sum, min, max) into the
+// running totals acc (3 doubles), in piece order; first = 1 starts them.
+__global__ void __launch_bounds__(64)
+k_mom_accumulate(const double *__restrict__ part, int nblk, int first, double *__restrict__ acc)
+{
+    if (threadIdx.x != 0)
+        return;
+    double sum = 0.0, mn = __builtin_huge_val(), mx = -__builtin_huge_val();
+    for (int b = 0; b < nblk; ++b) {
+        sum += part[3 * b];
+        mn = fmin(mn, part[3 * b + 1]);
+        mx = fmax(mx, part[3 * b + 2]);
+    }
+    if (first) {
+        acc[0] = sum;
+        acc[1] = mn;
+        acc[2] = mx;
+    } else {
+        acc[0] += sum;
+        acc[1] = fmin(acc[1], mn);
+        acc[2] = fmax(acc[2], mx);
+    }
+}
+
+hipError_t launch_moments_piece(const void *x, int dtype, int64_t len, int first,
+                                const SeriesPlan &p, char *ws, double *acc, hipStream_t s)
+{
+    double *part = (double *)(ws + p.off_mpart);
+    if (dtype == HOS_F64)
+        k_moments_partial<double><<<MOM_BLOCKS, 256, 0, s>>>((const double *)x, len, part);
+    else
+        k_moments_partial<float><<<MOM_BLOCKS, 256, 0, s>>>((const float *)x, len, part);
+    k_mom_accumulate<<<1, 64, 0, s>>>(part, MOM_BLOCKS, first, acc);
+    return hipGetLastError();
+}
+
+// The statistics of the whole record from the running totals.
+hipError_t launch_moments_total(const double *acc, int64_t n, uint32_t flags, int top,
+                                double *stats, hipStream_t s)
+{
+    k_moments_final<<<1, 256, 0, s>>>(acc, 1, n, flags, top, stats);
     return hipGetLastError();
 }
 

@@ -163,3 +163,33 @@ def test_c5_plan():
     assert info["P"] == 25 * 26 * 27 // 6 and info["RB"] == (info["P"] + 31) // 32
     assert info["NCB"] == 1 and info["WX"] >= 32 * info["NCB"] + 16
     assert info["S"] * info["CPS"] >= info["C"]
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(piece=4096 + 512), hos.HOS_EINVAL),   # not a multiple of 1024
+    (dict(piece=2048), hos.HOS_EINVAL),         # below 4096
+    (dict(piece=4096, M=5000, nfft=10000), hos.HOS_EINVAL),   # shorter than M
+    (dict(x=None), hos.HOS_EINVAL),
+    (dict(c3=None, B=None), hos.HOS_EINVAL),
+    (dict(ws_bytes=1000), hos.HOS_EWORKSPACE),
+])
+def test_streamed_validation_before_device(kw, code):
+    a = dict(x=FAKE, dtype=hos.HOS_F32, n=1 << 20, M=64, window=hos.HOS_WIN_PARZEN, nfft=128,
+             path=hos.HOS_PATH_FP32, flags=0, piece=1 << 16, c3=FAKE, B=FAKE, ws=FAKE,
+             ws_bytes=1 << 40)
+    a.update(kw)
+    st = hos.lib().hos_bispectrum_streamed(a["x"], a["dtype"], a["n"], a["M"], a["window"],
+                                          a["nfft"], a["path"], a["flags"], a["piece"], a["c3"],
+                                          a["B"], a["ws"], a["ws_bytes"], None)
+    assert st == code
+
+
+def test_streamed_workspace_independent_of_n():
+    import ctypes
+    sizes = []
+    for n in (1 << 22, 1 << 26, 1 << 30):
+        b = ctypes.c_size_t(0)
+        assert hos.lib().hos_bispectrum_streamed_workspace(n, 512, 1024, 1, 0, 1 << 20,
+                                                          ctypes.byref(b)) == 0
+        sizes.append(b.value)
+    assert sizes[0] == sizes[1] == sizes[2]

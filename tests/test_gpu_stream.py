@@ -1,0 +1,81 @@
+"""GPU parity of the streamed bispectrum (a record in host memory, read in
+pieces with an M-sample halo through a device workspace independent of n)
+against the FP64 oracle, and against the in-memory call on the same record.
+Bars as for one series (normwise 1e-6 FP32, 1e-5 split)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-6, "split_fp16": 1e-5, "split_bf16": 1e-5}
+
+
+def _hos():
+    import paper_1805_11775_amd as hos
+    assert hos.hos_device_check() == hos.HOS_OK, "no gfx950 device"
+    return hos
+
+
+def _err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("path", list(TOL))
+@pytest.mark.parametrize("n,M,piece", [
+    (20000, 64, 4096),         # five pieces, the last one partial
+    (8242, 100, 4096),         # last piece of 50 samples, shorter than M
+    (5000, 33, 8192),          # one piece
+    (8193, 20, 4096),          # last piece of one sample
+])
+def test_parity(path, n, M, piece):
+    hos = _hos()
+    x = synth.quadratic_process(n, 500 + n).astype(np.float32)
+    print("case: n=%d M=%d piece=%d path=%s" % (n, M, piece, path), flush=True)
+    c3, B = hos.bispectrum_streamed(torch.from_numpy(x), M, piece=piece, path=path)
+    torch.cuda.synchronize()
+    N = hos.default_nfft(M)
+    c_ref, B_ref = oracle.bispectrum(x, M, N)
+    e1, e2 = _err(c3.cpu().numpy(), c_ref), _err(B.cpu().numpy(), B_ref)
+    print("rel err c3 %.3e B %.3e" % (e1, e2))
+    assert e1 < TOL[path] and e2 < TOL[path]
+
+
+def test_float64_pinned_and_uncentred():
+    hos = _hos()
+    x = synth.iid_exp_centered(12345, 7) + 3.0
+    xt = torch.from_numpy(x).pin_memory()
+    for center in (True, False):
+        c3, B = hos.bispectrum_streamed(xt, 40, piece=4096, path="fp32", center=center)
+        torch.cuda.synchronize()
+        c_ref, B_ref = oracle.bispectrum(x, 40, hos.default_nfft(40), centered=center)
+        assert _err(c3.cpu().numpy(), c_ref) < 1e-6 and _err(B.cpu().numpy(), B_ref) < 1e-6
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_matches_in_memory_call_at_size(path):
+    """n = 2^22 float32 quadratic process, M = 512, pieces of 2^20: the
+    streamed result against the in-memory call on the same record (same
+    operand rounding, same 512-sample accumulation blocks) and against the
+    oracle at sampled lags."""
+    hos = _hos()
+    x = synth.quadratic_process(1 << 22, 77).astype(np.float32)
+    cs, Bs = hos.bispectrum_streamed(torch.from_numpy(x).pin_memory(), 512, piece=1 << 20,
+                                     path=path)
+    cm, Bm = hos.bispectrum(torch.from_numpy(x).cuda(), 512, path=path)
+    torch.cuda.synchronize()
+    cs, cm = cs.cpu().numpy(), cm.cpu().numpy()
+    d1 = _err(cs, cm)
+    d2 = _err(Bs.cpu().numpy(), Bm.cpu().numpy())
+    print("streamed vs in-memory: c3 %.3e B %.3e" % (d1, d2))
+    assert d1 < 1e-9 and d2 < 1e-9
+    rng = np.random.default_rng(2)
+    w = rng.integers(-512, 513, (120, 2))
+    w = w[np.abs(w[:, 0] - w[:, 1]) <= 512]
+    ref = oracle.c3_at(x, w[:, 0], w[:, 1])
+    e = float(np.max(np.abs(cs[w[:, 0] + 512, w[:, 1] + 512] - ref)) / np.max(np.abs(ref)))
+    print("sampled rel err %.3e" % e)
+    assert e < TOL[path]
