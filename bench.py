@@ -21,7 +21,9 @@ x_t = e_t + 0.4 e_{t-1} e_{t-2} e_{t-3}, M = 48, six-factor Parzen window,
 ``batched`` (4096 uneven series in one call), ``loss`` (bispectrum-matching
 loss forward and adjoint), ``segments`` (the headline series in 16
 segments, each centred on its own mean, cumulants averaged), ``order5``
-(the fifth cumulant and its 4-D spectrum, n = 2^18, M = 24) and
+(the fifth cumulant and its 4-D spectrum, n = 2^18, M = 24), ``streamed``
+(a host-resident record of 2^26 samples read in pieces, host-to-device
+copies inside the timed region) and
 ``direct_method`` (Algorithm DBS with
 window-sum smoothing, n = 2^16 as one part, 1023 x 1023 box, with an HBM
 roofline of the smoothing kernel).
@@ -446,6 +448,87 @@ def bench_segments(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds)
     return rec
 
 
+def bench_streamed(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds):
+    """A record in pinned host memory streamed through the device
+    (hos_bispectrum_streamed): n = 2^26 float32 quadratic process, M = 512,
+    Parzen window, 1024 x 1024 DFT, pieces of 2^22 samples.  The time runs
+    from the host-resident record to c3 and B on the device, so it includes
+    both passes of host-to-device copies; beside it, the in-memory call on
+    the same record already resident in HBM and a plain copy of the record
+    to the device (the host link's rate)."""
+    x, cfg = synth.workload_streamed()
+    M, N, piece = cfg["M"], cfg["nfft"], cfg["piece"]
+    n = x.size
+    xh = torch.from_numpy(x).pin_memory()
+    xd = torch.empty(n, dtype=torch.float32, device="cuda")
+    copy_ms = _time(torch, lambda: xd.copy_(xh, non_blocking=True), 5, 2)
+    lagsums = float(n) * (2 * M + 1) ** 2
+    flops = 2.0 * n * (M + 1) * (M + 2) / 2
+    w1, w2 = sample_lags(M, 40, seed=17)
+    ref = oracle.c3_at(x, w1, w2)
+    ref[np.abs(w1 - w2) > M] = 0.0
+    reps, warm = max(3, steps // 10), max(1, warmup // 10)
+    out = {}
+    for path in paths:
+        wsb = hos.hos_bispectrum_workspace(n, M, N, hos.PATHS[path], 0)
+        wsm = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        mem_ms = _time(torch, lambda: hos.bispectrum(xd, M, N, path=path, workspace=wsm),
+                       reps, warm)
+        cm, _ = hos.bispectrum(xd, M, N, path=path, workspace=wsm)
+        cm = cm.cpu().numpy()
+        del wsm
+        c3, _ = hos.bispectrum_streamed(xh, M, piece=piece, nfft=N, path=path)
+        sz = hos.hos_bispectrum_streamed_workspace(n, M, N, hos.PATHS[path], hos.HOS_F32,
+                                                   piece)
+        wss = torch.empty(sz, dtype=torch.uint8, device="cuda")
+        ms = _time(torch, lambda: hos.bispectrum_streamed(xh, M, piece=piece, nfft=N, path=path,
+                                                         workspace=wss), reps, warm)
+        c3 = c3.cpu().numpy()
+        err = float(np.max(np.abs(c3[w1 + M, w2 + M] - ref)) / np.max(np.abs(ref)))
+        dmem = float(np.max(np.abs(c3 - cm)) / np.max(np.abs(cm)))
+        out[path] = {"ms_per_call": ms, "value": lagsums / (ms * 1e-3), "rel_err": err,
+                     "within_tol": err <= TOL[path], "in_memory_ms": mem_ms,
+                     "rel_diff_vs_in_memory": dmem, "workspace_bytes": sz,
+                     "in_memory_workspace_bytes": wsb,
+                     "pass2_copy_hidden_frac": (mem_ms + 2 * copy_ms - ms) / copy_ms}
+        print("bench: streamed %s %.2f ms/call (in memory %.2f, copy %.2f), err %.2e" %
+              (path, ms, mem_ms, copy_ms, err), file=sys.stderr, flush=True)
+        del wss
+    head = "split_fp16" if "split_fp16" in out else next(iter(out))
+    h = out[head]
+    link_bytes = 2.0 * n * 4 + (n // piece) * M * 4   # both passes, with the halos
+    rec = {"metric": METRIC, "value": h["value"], "unit": "lag-sums/s",
+           "ms_per_step": h["ms_per_call"], "dtype": DTYPE[head],
+           "config": {"workload": "streamed bispectrum of a host-resident n=2^26 float32 "
+                                  "quadratic-process record (pinned), M=512, Parzen window, "
+                                  "1024x1024 DFT, pieces of 2^22 samples",
+                      "n": n, "M": M, "nfft": N, "piece": piece, "path": head},
+           "host_link": {"bytes_per_call": link_bytes,
+                         "achieved_GBps": link_bytes / (h["ms_per_call"] * 1e-3) / 1e9,
+                         "plain_copy_GBps": n * 4 / (copy_ms * 1e-3) / 1e9,
+                         "plain_copy_ms": copy_ms},
+           # pass one (the record's mean and scale) must end before any
+           # operand is formed, so it cannot overlap compute: the two-pass
+           # bound is the in-memory call plus one copy of the record
+           "bound_ms": {"in_memory": h["in_memory_ms"], "one_copy": copy_ms,
+                        "two_pass": h["in_memory_ms"] + copy_ms,
+                        "frac": (h["in_memory_ms"] + copy_ms) / h["ms_per_call"]},
+           "paths": out}
+    del xd
+    if cpu_seconds > 0:
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < cpu_seconds:
+            oracle.c3_at(x, w1[k % w1.size:k % w1.size + 1], w2[k % w1.size:k % w1.size + 1])
+            k += 1
+        t = time.perf_counter() - t0
+        rec["cpu_oracle"] = {"value": k * float(n) / t, "unit": "lag-sums/s",
+                             "cores": 1, "kind": "oracle",
+                             "sample": "%d lags x %d samples, FP64 brute-force c3 (%.1f s)" %
+                                       (k, n, t)}
+    return rec
+
+
 def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds, sweep_box=True):
     """The direct method (Algorithm DBS with window-sum smoothing): one
     float32 quadratic-process series of 2^16 samples as one part, a
@@ -561,6 +644,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tri", action="store_true", help="skip the trispectrum record")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and loss records")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the streamed (host-resident record) record")
     ap.add_argument("--no-dbs", action="store_true", help="skip the direct-method record")
     ap.add_argument("--no-dbs-sweep", action="store_true",
                     help="time the direct method at its workload's box size only")
@@ -651,6 +736,9 @@ def main():
                                         args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
     if not args.no_batch:
         rec["segments"] = bench_segments(hos, torch, oracle, synth, list(paths), args.steps,
+                                         args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
+    if not args.no_stream:
+        rec["streamed"] = bench_streamed(hos, torch, oracle, synth, list(paths), args.steps,
                                          args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
     if not args.no_dbs:
         rec["direct_method"] = bench_dbs(hos, torch, oracle, synth, args.steps, args.warmup,

@@ -235,11 +235,18 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  * window-sum theorems, for the indirect estimator): the same c3 and B as
  * hos_bispectrum on the whole record, computed through a device workspace
  * whose size depends on the piece length P and M but not on n.  The record
- * is read twice in pieces of P samples (hipMemcpyAsync on `stream`): first
- * for its FP64 mean and scale, then each piece with the M samples after it,
- * whose sums are added to a running FP64 table.
- *   x_host  host memory, n samples (pinned memory lets the copies run at
- *           full speed; pageable memory works too), HOS_F32 or HOS_F64.
+ * is read twice in pieces of P samples: first for its FP64 mean and scale,
+ * then each piece with the M samples after it, whose sums are added to a
+ * running FP64 table.  The copies run on a copy stream of the library's
+ * own (one per device, made at the first call and kept until the process
+ * ends) into two staging buffers of the workspace, so a piece's copy
+ * overlaps the kernels of the one before; events order them against
+ * `stream`, whose completion implies every copy's.
+ *   x_host  host memory, n samples, HOS_F32 or HOS_F64.  With pinned memory
+ *           the call returns once everything is queued; the record must
+ *           stay valid and unchanged until `stream` has passed the call.
+ *           Pageable memory works too (the runtime stages it, and the call
+ *           returns about when the last piece's copy has been taken).
  *   piece   P: a multiple of 1024, >= 4096, >= M.
  *   c3, B, window, nfft, path, flags: as hos_bispectrum (device outputs).
  * Workspace: hos_bispectrum_streamed_workspace (dtype sets the size of the

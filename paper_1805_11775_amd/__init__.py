@@ -409,6 +409,15 @@ def dbs(x, P: int, M3: int, center: bool = True, workspace=None, timed: bool = F
     return B
 
 
+def hos_bispectrum_streamed_workspace(n, M, nfft, path, dtype, piece) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib().hos_bispectrum_streamed_workspace(int(n), int(M), int(nfft), int(path),
+                                                int(dtype), int(piece), ctypes.byref(out))
+    if st != HOS_OK:
+        raise HosError(st, "hos_bispectrum_streamed_workspace")
+    return out.value
+
+
 def bispectrum_streamed(x, M: int, piece: int = 1 << 22, nfft: int | None = None,
                         window: str = "parzen", path: str = "fp32", center: bool = True,
                         device="cuda", return_c3: bool = True, return_B: bool = True,
@@ -432,14 +441,10 @@ def bispectrum_streamed(x, M: int, piece: int = 1 << 22, nfft: int | None = None
     if nfft is None:
         nfft = default_nfft(M, window)
     nf = nfft if return_B else 0
-    out = ctypes.c_size_t(0)
-    st = lib().hos_bispectrum_streamed_workspace(n, M, nf, pth, dtype, int(piece),
-                                                ctypes.byref(out))
-    if st != HOS_OK:
-        raise HosError(st, "hos_bispectrum_streamed_workspace")
+    ws_bytes = hos_bispectrum_streamed_workspace(n, M, nf, pth, dtype, piece)
     dev = torch.device(device)
-    if workspace is None or workspace.numel() < out.value:
-        workspace = torch.empty(out.value, dtype=torch.uint8, device=dev)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     c3 = torch.empty((2 * M + 1, 2 * M + 1), dtype=torch.float64,
                      device=dev) if return_c3 else None
     B = torch.empty((nfft, nfft), dtype=torch.complex128, device=dev) if return_B else None

@@ -13,6 +13,16 @@
 // reduced table is added to a running FP64 table.  The sum over the pieces
 // is the sum over the record, so the result is the whole record's c3 and B
 // (up to the order of FP64 additions).
+//
+// Copies run on a copy stream of the library's own (one per device, made
+// at first use, default priority) into two staging buffers taken in turn:
+// the copy of the next piece overlaps the kernels of the current one.
+// Events order the two streams both ways: a piece's kernels wait until its
+// copy has landed, and a copy into a buffer waits until the kernels of the
+// piece it held two steps earlier are done (and, for the first two copies,
+// until the caller's stream has reached the call, which may still be using
+// the workspace).
+#include <mutex>
 #include <string.h>
 
 #include "hos_internal.h"
@@ -43,7 +53,7 @@ int64_t piece_data(int64_t n, int32_t M, int64_t P, int64_t k)
 struct StreamLayout {
     int64_t P, halo;          // piece length, halo samples
     size_t plan_bytes;        // largest single-series plan of a piece
-    size_t off_acc, off_mom, off_x, total;
+    size_t off_acc, off_mom, off_x[2], total;
 };
 
 int stream_layout(int64_t n, int32_t M, int32_t nfft, int32_t path, int64_t P, int esize,
@@ -74,10 +84,90 @@ int stream_layout(int64_t n, int32_t M, int32_t nfft, int32_t path, int64_t P, i
     size_t o = L.plan_bytes;
     L.off_acc = o;  o = al256(o + (size_t)(M + 1) * (M + 1) * sizeof(double));
     L.off_mom = o;  o = al256(o + 4 * sizeof(double));
-    L.off_x = o;    o = al256(o + (size_t)data_max * esize);
+    L.off_x[0] = o; o = al256(o + (size_t)data_max * esize);
+    L.off_x[1] = o; o = al256(o + (size_t)data_max * esize);
     L.total = o;
     return HOS_OK;
 }
+
+constexpr int STREAM_MAX_DEVICES = 64;
+
+// The copy stream of the current device, made once and kept until the
+// process ends.
+hipError_t copy_stream(hipStream_t &cs)
+{
+    static std::mutex mu;
+    static hipStream_t streams[STREAM_MAX_DEVICES] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= STREAM_MAX_DEVICES)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            streams[dev] = nullptr;
+            return e;
+        }
+    }
+    cs = streams[dev];
+    return hipSuccess;
+}
+
+// Staging of the record's pieces through the two buffers (see the top of
+// the file).  put() copies bytes from the host into the next buffer and
+// makes the caller's stream wait for it; done() marks the end of the
+// kernels that read the buffer put() returned last.
+struct Stager {
+    hipStream_t s = nullptr, cs = nullptr;
+    hipEvent_t start = nullptr, ready[2] = {}, freed[2] = {};
+    char *buf[2] = {};
+    int64_t step = 0;
+
+    hipError_t init(hipStream_t stream, char *b0, char *b1)
+    {
+        s = stream;
+        buf[0] = b0;
+        buf[1] = b1;
+        hipError_t e = copy_stream(cs);
+        hipEvent_t *all[5] = {&start, &ready[0], &ready[1], &freed[0], &freed[1]};
+        for (hipEvent_t *ev : all)
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(start, s);
+        return e;
+    }
+    hipError_t put(const char *src, size_t bytes, char *&dst)
+    {
+        const int b = (int)(step & 1);
+        hipError_t e = hipStreamWaitEvent(cs, step < 2 ? start : freed[b], 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(buf[b], src, bytes, hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess)
+            e = hipEventRecord(ready[b], cs);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, ready[b], 0);
+        dst = buf[b];
+        return e;
+    }
+    hipError_t done()
+    {
+        return hipEventRecord(freed[(step++) & 1], s);
+    }
+    // Events still pending are released by the runtime once they complete;
+    // the caller's stream has waited for every copy, so its completion
+    // implies theirs.
+    ~Stager()
+    {
+        hipEvent_t all[5] = {start, ready[0], ready[1], freed[0], freed[1]};
+        for (hipEvent_t ev : all)
+            if (ev)
+                hipEventDestroy(ev);
+    }
+};
 
 }  // namespace
 
@@ -154,21 +244,26 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
     char *w = (char *)ws;
     double *acc = (double *)(w + L.off_acc);
     double *mom = (double *)(w + L.off_mom);
-    char *xd = w + L.off_x;
     const char *xh = (const char *)x_host;
     const int64_t pieces = (n + piece - 1) / piece;
-    hipError_t e = hipSuccess;
+    Stager stg;
+    hipError_t e = stg.init(stream, w + L.off_x[0], w + L.off_x[1]);
 
     // pass one: sum, minimum, maximum of the record, piece by piece (p0 is
     // the plan of a full piece with its halo, within the workspace layout)
     C3Plan p0;
     make_c3_plan(piece_data(n, M, piece, 0), M, path, B ? nfft : 0, p0);
+    char *xd = nullptr;
     for (int64_t k = 0; k < pieces && e == hipSuccess; ++k) {
         const int64_t g0 = k * piece, len = piece_len(n, piece, k);
-        e = hipMemcpyAsync(xd, xh + g0 * esize, (size_t)len * esize, hipMemcpyHostToDevice,
-                           stream);
+        // a record of one piece is staged whole (it is its own halo) and
+        // read again by pass two from the same buffer
+        const int64_t cp = pieces == 1 ? n : len;
+        e = stg.put(xh + g0 * esize, (size_t)cp * esize, xd);
         if (e == hipSuccess)
             e = launch_moments_piece(xd, dtype, len, k == 0, p0, w, mom, stream);
+        if (e == hipSuccess && pieces > 1)
+            e = stg.done();
     }
     // the record's mean and scale into the stats every piece plan reads
     // (each plan puts its stats at offset 0 of the workspace)
@@ -187,12 +282,13 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
             e = hipErrorInvalidValue;
             break;
         }
-        e = hipMemcpyAsync(xd, xh + g0 * esize, (size_t)data * esize, hipMemcpyHostToDevice,
-                           stream);
+        if (pieces > 1)
+            e = stg.put(xh + g0 * esize, (size_t)data * esize, xd);
         if (e == hipSuccess) e = launch_prep(xd, dtype, p, w, stream, g0, len);
         if (e == hipSuccess) e = launch_c3_contract(p, w, stream);
         if (e == hipSuccess) e = launch_diag_dot(xd, dtype, p, w, stream, len);
         if (e == hipSuccess) e = launch_c3_reduce(p, w, stream);
+        if (e == hipSuccess && pieces > 1) e = stg.done();
         if (e == hipSuccess) {
             k_table_add<<<(unsigned)((ne + 255) / 256), 256, 0, stream>>>(
                 acc, (const double *)(w + p.off_cfull), ne, k == 0);

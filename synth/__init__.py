@@ -167,3 +167,11 @@ def workload_cumulant5(n: int = 1 << 18):
     """Order five: n = 2^18 float32 quartic process, maximum lag 24, 48^4 DFT."""
     x = quartic_process(n, SEED_BASE + 8).astype(np.float32)
     return x, dict(M=24, nfft=48)
+
+
+def workload_streamed(n: int = 1 << 26):
+    """A record held in host memory: n = 2^26 float32 quadratic process
+    (64 times the long bispectrum's series), maximum lag 512, 1024-point
+    DFT, read in pieces of 2^22 samples."""
+    x = quadratic_process(n, SEED_BASE + 9).astype(np.float32)
+    return x, dict(M=512, nfft=1024, piece=1 << 22)
