@@ -107,6 +107,8 @@ int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p, in
     p.npad = ((p.C * KC + p.WX + 64) + 63) / 64 * 64;
     int64_t db = n / 4096;
     p.dot_blocks = (int32_t)(db < 1 ? 1 : (db > 64 ? 64 : db));
+    const int64_t c3b = (n + C3D_BS - 1) / C3D_BS;
+    p.c3_blocks = (int32_t)(c3b > C3D_MAX_WG ? C3D_MAX_WG : c3b);
 
     size_t o = 0;
     p.off_stats = o;  o = align256(o + 64 * sizeof(double));
@@ -124,7 +126,7 @@ int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p, in
     p.off_c2 = o;     o = align256(o + (size_t)(M + 1) * sizeof(double));
     if (ord == 5) {
         p.off_c3part = o;
-        o = align256(o + (size_t)(M + 1) * (M + 2) / 2 * p.dot_blocks * sizeof(double));
+        o = align256(o + (size_t)(M + 1) * (M + 2) / 2 * p.c3_blocks * sizeof(double));
         p.off_c3tab = o;
         o = align256(o + (size_t)(M + 1) * (M + 1) * sizeof(double));
     }

@@ -91,10 +91,10 @@ __device__ inline double c4_at(const double *__restrict__ m4tab, const double *_
 // the first row with smallest offset c.
 __host__ __device__ inline int64_t triple_offset(int M, int c)
 {
-    int64_t s = 0;
-    for (int k = 0; k < c; ++k)
-        s += (int64_t)(M - k + 1) * (M - k + 2) / 2;
-    return s;
+    // sum over k < c of (M - k + 1)(M - k + 2)/2 = S(M) - S(M - c), with
+    // S(m) = (m + 1)(m + 2)(m + 3)/6 the number of pairs over lag ranges 0..m
+    const int64_t a = M, b = (int64_t)M - c;
+    return ((a + 1) * (a + 2) * (a + 3) - (b + 1) * (b + 2) * (b + 3)) / 6;
 }
 
 __device__ inline void sort5(int *v)
@@ -138,22 +138,6 @@ __device__ inline double c5_at(const double *__restrict__ m5tab, const double *_
             v5 -= c2[q[k] - q[j]] * c3tab[(u[2] - u[0]) * (M + 1) + (u[1] - u[0])];
         }
     return v5;
-}
-
-// Lag window of order five: d over the ten pairwise differences of
-// {0, t1, t2, t3, t4} (HOS_WIN_PARZEN), d(t1) d(t2) d(t3) d(t4) (separable),
-// or 1.
-__device__ inline double window5(int t1, int t2, int t3, int t4, int M, int window)
-{
-    if (window == HOS_WIN_NONE)
-        return 1.0;
-    const int o[5] = {0, t1, t2, t3, t4};
-    double w = parzen_d(t1, M) * parzen_d(t2, M) * parzen_d(t3, M) * parzen_d(t4, M);
-    if (window == HOS_WIN_PARZEN)
-        for (int j = 1; j < 5; ++j)
-            for (int k = j + 1; k < 5; ++k)
-                w *= parzen_d(o[k] - o[j], M);
-    return w;
 }
 
 // SplitMix64 output function (Steele, Lea and Flood, "Fast splittable

@@ -179,6 +179,7 @@ struct C4Plan : SeriesPlan {
     int32_t S;         // sample-axis ranges
     int32_t CPS;       // chunks per range
     int32_t dot_blocks;// workgroups per c2 lag
+    int32_t c3_blocks; // order five: workgroups of the c3 sums (k_c3_dot)
     int64_t C;         // chunks of KC samples
     size_t off_part, off_m4, off_c2part, off_c2, off_twid, total;
     size_t off_c3part, off_c3tab;   // order five: third-order corrections
@@ -187,6 +188,8 @@ struct C4Plan : SeriesPlan {
 constexpr int C4_MAX_M = 127;      // 4 column blocks per pair block
 constexpr int C5_MAX_M = 40;       // order five: (2M+1)^4 lags of output
 constexpr int C5_MAX_NFFT = 96;    // order five: N^4 complex128 spectrum
+constexpr int C3D_BS = 512;        // order five: samples per step of k_c3_dot
+constexpr int C3D_MAX_WG = 1024;   // its workgroups (each strides over sample blocks)
 constexpr int C4_MAX_NFFT = 512;   // N^3 complex128 <= 2 GiB
 
 constexpr int MOM_BLOCKS = 256;     // blocks of the moments pass

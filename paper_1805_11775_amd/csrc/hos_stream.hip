@@ -196,6 +196,8 @@ static int check_stream_args(int64_t n, int32_t M, int32_t window, int32_t nfft,
         const int64_t need = window != HOS_WIN_NONE ? 2 * (int64_t)M : 2 * (int64_t)M + 1;
         if (nfft < need || nfft < 2)
             return HOS_EINVAL;
+    } else if (nfft < 0) {
+        return HOS_EINVAL;
     }
     return HOS_OK;
 }
@@ -229,7 +231,7 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
         return HOS_EINVAL;
     if (!st_aligned(ws, 256) || (c3 && !st_aligned(c3, 8)) || (B && !st_aligned(B, 16)))
         return HOS_EINVAL;
-    int st = check_stream_args(n, M, window, B ? nfft : 0, path, flags, piece, B != nullptr);
+    int st = check_stream_args(n, M, window, nfft, path, flags, piece, B != nullptr);
     if (st != HOS_OK)
         return st;
     const int esize = dtype == HOS_F64 ? 8 : 4;

@@ -23,6 +23,8 @@
 // cores, FP32 accumulation flushed to FP64, FP64 partials summed in a fixed
 // order.  One workgroup = 4 waves = 4 pair blocks over a contiguous range of
 // 512-sample chunks; all pair blocks read the same staged window of x.
+#include <algorithm>
+
 #include "hos_internal.h"
 #include "hos_device.h"
 
@@ -506,63 +508,161 @@ k_c4_out(const double *__restrict__ m4tab, const double *__restrict__ c2,
 
 // Order five needs the third-order cumulants for its corrections: the FP64
 // sums sum_i x~_i x~_{i+a} x~_{i+b} (scaled by s^3) over the pairs b <= a of
-// F, one block of workgroups per pair, from the input.
+// F, from the input.  A workgroup takes C3D_BS samples (and the M after
+// them) into LDS as FP64 x~ and strides over such blocks.  Thread t owns the
+// lag a = t mod (M+1) and every (256 / (M+1))-th run of C3D_RUN samples: it
+// forms the products x~_i x~_{i+a} of a run once and meets them with the
+// window x~_{i+b}, b = 0..a, held in registers, keeping its a + 1 sums in
+// registers too.  At the end the threads of one lag add their sums in slot
+// order and each pair's workgroup partial goes to dpart[pair][workgroup]
+// (fixed order throughout: the result is bitwise reproducible).
+constexpr int C3D_RUN = 8;
+constexpr int C3D_RED = 128 * (C5_MAX_M + 2);   // >= (256 / (M+1)) * pairs(M)
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_c3_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats, int M,
-         int nblocks, double *__restrict__ dpart)
+         double *__restrict__ dpart)
+{
+    __shared__ double sx[C3D_BS + C5_MAX_M + C3D_RUN];
+    __shared__ double red[C3D_RED];
+    const int tid = threadIdx.x;
+    const int L = M + 1, S = 256 / L, pairs = L * (L + 1) / 2;
+    const int a = tid % L, slot = tid / L;
+    const double mu = stats[0], sc = stats[1];
+    double acc[C5_MAX_M + 1];
+#pragma unroll
+    for (int b = 0; b <= C5_MAX_M; ++b)
+        acc[b] = 0.0;
+    const int64_t nblk = (n + C3D_BS - 1) / C3D_BS;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t i0 = blk * C3D_BS;
+        __syncthreads();   // every read of the previous block is done
+        for (int j = tid; j < C3D_BS + M + C3D_RUN; j += 256) {
+            const int64_t i = i0 + j;
+            sx[j] = i < n ? ((double)x[i] - mu) * sc : 0.0;
+        }
+        __syncthreads();
+        if (slot < S) {
+            for (int r = slot; r < C3D_BS / C3D_RUN; r += S) {
+                const int base = r * C3D_RUN;
+                double v[C3D_RUN + C5_MAX_M];
+#pragma unroll
+                for (int k = 0; k < C3D_RUN + C5_MAX_M; ++k)
+                    v[k] = k < C3D_RUN + M ? sx[base + k] : 0.0;
+                double y[C3D_RUN];
+#pragma unroll
+                for (int j = 0; j < C3D_RUN; ++j)
+                    y[j] = v[j] * sx[base + j + a];
+#pragma unroll
+                for (int b = 0; b <= C5_MAX_M; ++b)
+                    if (b <= a) {
+#pragma unroll
+                        for (int j = 0; j < C3D_RUN; ++j)
+                            acc[b] = fma(y[j], v[b + j], acc[b]);
+                    }
+            }
+        }
+    }
+    __syncthreads();
+    if (slot < S) {
+#pragma unroll
+        for (int b = 0; b <= C5_MAX_M; ++b)
+            if (b <= a)
+                red[slot * pairs + pair_offset(M, b) + (a - b)] = acc[b];
+    }
+    __syncthreads();
+    for (int pr = tid; pr < pairs; pr += 256) {
+        double s = 0.0;
+        for (int k = 0; k < S; ++k)
+            s += red[k * pairs + pr];
+        dpart[(int64_t)pr * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// c3tab[a][b] = (sum of partials) / (n s^3), b <= a (stride M + 1): one
+// workgroup per pair, a fixed-order tree over its workgroup partials.
+__global__ void __launch_bounds__(256)
+k_c3_final(const double *__restrict__ dpart, int M, int nblocks,
+           const double *__restrict__ stats, int64_t n, double *__restrict__ c3tab)
 {
     __shared__ double red[256];
-    const int pr = blockIdx.x / nblocks, blk = blockIdx.x % nblocks;
-    int a, b;
-    pair_ab(M, pr, a, b);
-    const double mu = stats[0], sc = stats[1];
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i + a < n; i += (int64_t)nblocks * 256)
-        acc += (((double)x[i] - mu) * sc) * (((double)x[i + a] - mu) * sc) *
-               (((double)x[i + b] - mu) * sc);
-    red[threadIdx.x] = acc;
+    const int pr = blockIdx.x;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += 256)
+        s += dpart[(int64_t)pr * nblocks + k];
+    red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w)
             red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        dpart[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) {
+        int a, b;
+        pair_ab(M, pr, a, b);
+        const double sc = stats[1];
+        c3tab[a * (M + 1) + b] = red[0] / ((double)n * sc * sc * sc);
+    }
 }
 
-// c3tab[a][b] = (sum of partials) / (n s^3), b <= a (stride M + 1).
-__global__ void __launch_bounds__(64)
-k_c3_final(const double *__restrict__ dpart, int M, int nblocks,
-           const double *__restrict__ stats, int64_t n, double *__restrict__ c3tab)
+// The small tables every order-five output reads, staged in LDS once per
+// workgroup: Parzen weights d(m) for |m| <= M (the values parzen_d gives),
+// c2(0..M) and the third-order cumulants c3tab[a][b] (stride M + 1).
+struct C5Tables {
+    double d[2 * C5_MAX_M + 1];
+    double c2[C5_MAX_M + 1];
+    double c3[(C5_MAX_M + 1) * (C5_MAX_M + 1)];
+};
+
+__device__ inline void load_c5_tables(C5Tables &t, const double *__restrict__ c2,
+                                      const double *__restrict__ c3tab, int M)
 {
-    const int pr = blockIdx.x * 64 + threadIdx.x;
-    if (pr >= (M + 1) * (M + 2) / 2)
-        return;
-    int a, b;
-    pair_ab(M, pr, a, b);
-    double s = 0.0;
-    for (int k = 0; k < nblocks; ++k)
-        s += dpart[(int64_t)pr * nblocks + k];
-    const double sc = stats[1];
-    c3tab[a * (M + 1) + b] = s / ((double)n * sc * sc * sc);
+    for (int i = threadIdx.x; i <= 2 * M; i += blockDim.x)
+        t.d[i] = parzen_d(i - M, M);
+    for (int i = threadIdx.x; i <= M; i += blockDim.x)
+        t.c2[i] = c2[i];
+    for (int i = threadIdx.x; i < (M + 1) * (M + 1); i += blockDim.x)
+        t.c3[i] = c3tab[i];
+    __syncthreads();
 }
 
+// window5 from the staged Parzen weights (0 beyond |m| > M).
+__device__ inline double window5_tab(const double *d, int t1, int t2, int t3, int t4, int M,
+                                     int window)
+{
+    if (window == HOS_WIN_NONE)
+        return 1.0;
+    auto dv = [&](int m) { return (m < -M || m > M) ? 0.0 : d[m + M]; };
+    double w = dv(t1) * dv(t2) * dv(t3) * dv(t4);
+    if (window == HOS_WIN_PARZEN)
+        w *= dv(t2 - t1) * dv(t3 - t1) * dv(t4 - t1) * dv(t3 - t2) * dv(t4 - t2) * dv(t4 - t3);
+    return w;
+}
+
+// Both kernels stride over their outputs from a bounded grid, so each
+// workgroup stages the tables once for many outputs; indices fit 32 bits
+// ((2M+1)^4 <= 81^4 and N^4 <= 96^4).
 __global__ void __launch_bounds__(256)
 k_c5_out(const double *__restrict__ m5tab, const double *__restrict__ c2,
          const double *__restrict__ c3tab, const double *__restrict__ stats, int M,
          double *__restrict__ out)
 {
-    const int64_t side = 2 * M + 1;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= side * side * side * side)
-        return;
-    const int t4 = (int)(idx % side) - M;
-    const int t3 = (int)((idx / side) % side) - M;
-    const int t2 = (int)((idx / (side * side)) % side) - M;
-    const int t1 = (int)(idx / (side * side * side)) - M;
-    out[idx] = c5_at(m5tab, c2, c3tab, M, stats[4] * stats[1], t1, t2, t3, t4);
+    __shared__ C5Tables tab;
+    load_c5_tables(tab, c2, c3tab, M);
+    const uint32_t side = 2 * M + 1, tot = side * side * side * side;
+    const double norm5 = stats[4] * stats[1];
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+         idx += gridDim.x * blockDim.x) {
+        uint32_t r = idx;
+        const int t4 = (int)(r % side) - M;
+        r /= side;
+        const int t3 = (int)(r % side) - M;
+        r /= side;
+        const int t2 = (int)(r % side) - M;
+        const int t1 = (int)(r / side) - M;
+        out[idx] = c5_at(m5tab, tab.c2, tab.c3, M, norm5, t1, t2, t3, t4);
+    }
 }
 
 // The windowed c5 folded onto the N^4 DFT grid (index w mod N, aliases
@@ -572,38 +672,46 @@ k_c5_fold(const double *__restrict__ m5tab, const double *__restrict__ c2,
           const double *__restrict__ c3tab, const double *__restrict__ stats, int M, int N,
           int window, double2 *__restrict__ Q)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t NN = (int64_t)N * N;
-    if (idx >= NN * NN)
-        return;
-    const int m[4] = {(int)(idx / (NN * N)), (int)((idx / NN) % N), (int)((idx / N) % N),
-                      (int)(idx % N)};
+    __shared__ C5Tables tab;
+    load_c5_tables(tab, c2, c3tab, M);
+    const uint32_t n = N, tot = n * n * n * n;
     const double norm5 = stats[4] * stats[1];
-    double sum = 0.0;
-    for (int k0 = 0; k0 < 2; ++k0) {
-        const int w1 = m[0] - k0 * N;
-        if (w1 < -M || w1 > M)
-            continue;
-        for (int k1 = 0; k1 < 2; ++k1) {
-            const int w2 = m[1] - k1 * N;
-            if (w2 < -M || w2 > M)
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+         idx += gridDim.x * blockDim.x) {
+        uint32_t r = idx;
+        int m[4];
+        m[3] = (int)(r % n);
+        r /= n;
+        m[2] = (int)(r % n);
+        r /= n;
+        m[1] = (int)(r % n);
+        m[0] = (int)(r / n);
+        double sum = 0.0;
+        for (int k0 = 0; k0 < 2; ++k0) {
+            const int w1 = m[0] - k0 * N;
+            if (w1 < -M || w1 > M)
                 continue;
-            for (int k2 = 0; k2 < 2; ++k2) {
-                const int w3 = m[2] - k2 * N;
-                if (w3 < -M || w3 > M)
+            for (int k1 = 0; k1 < 2; ++k1) {
+                const int w2 = m[1] - k1 * N;
+                if (w2 < -M || w2 > M)
                     continue;
-                for (int k3 = 0; k3 < 2; ++k3) {
-                    const int w4 = m[3] - k3 * N;
-                    if (w4 < -M || w4 > M)
+                for (int k2 = 0; k2 < 2; ++k2) {
+                    const int w3 = m[2] - k2 * N;
+                    if (w3 < -M || w3 > M)
                         continue;
-                    const double wv = window5(w1, w2, w3, w4, M, window);
-                    if (wv != 0.0)
-                        sum += wv * c5_at(m5tab, c2, c3tab, M, norm5, w1, w2, w3, w4);
+                    for (int k3 = 0; k3 < 2; ++k3) {
+                        const int w4 = m[3] - k3 * N;
+                        if (w4 < -M || w4 > M)
+                            continue;
+                        const double wv = window5_tab(tab.d, w1, w2, w3, w4, M, window);
+                        if (wv != 0.0)
+                            sum += wv * c5_at(m5tab, tab.c2, tab.c3, M, norm5, w1, w2, w3, w4);
+                    }
                 }
             }
         }
+        Q[idx] = make_double2(sum, 0.0);
     }
-    Q[idx] = make_double2(sum, 0.0);
 }
 
 template <int PATH, int WX>
@@ -691,15 +799,14 @@ hipError_t launch_c4_reduce(const void *x, int dtype, const C4Plan &p, char *ws,
     if (p.ord == 5) {
         const int pairs = (p.M + 1) * (p.M + 2) / 2;
         double *c3part = (double *)(ws + p.off_c3part);
-        const int g3 = pairs * p.dot_blocks;
         if (dtype == HOS_F64)
-            k_c3_dot<double><<<g3, 256, 0, s>>>((const double *)x, p.n, stats, p.M,
-                                                p.dot_blocks, c3part);
+            k_c3_dot<double><<<p.c3_blocks, 256, 0, s>>>((const double *)x, p.n, stats, p.M,
+                                                         c3part);
         else
-            k_c3_dot<float><<<g3, 256, 0, s>>>((const float *)x, p.n, stats, p.M,
-                                               p.dot_blocks, c3part);
-        k_c3_final<<<(pairs + 63) / 64, 64, 0, s>>>(c3part, p.M, p.dot_blocks, stats, p.n,
-                                                   (double *)(ws + p.off_c3tab));
+            k_c3_dot<float><<<p.c3_blocks, 256, 0, s>>>((const float *)x, p.n, stats, p.M,
+                                                        c3part);
+        k_c3_final<<<pairs, 256, 0, s>>>(c3part, p.M, p.c3_blocks, stats, p.n,
+                                          (double *)(ws + p.off_c3tab));
     }
     return hipGetLastError();
 }
@@ -711,14 +818,18 @@ hipError_t launch_c5_finish(const C4Plan &p, int window, int nfft, double *c5, d
     const double *c2 = (const double *)(ws + p.off_c2);
     const double *c3 = (const double *)(ws + p.off_c3tab);
     const double *stats = (const double *)(ws + p.off_stats);
+    // bounded grids: 8 workgroups per CU, each striding over its outputs
+    const int64_t gmax = 8 * 256;
     if (c5) {
         const int64_t side = 2 * p.M + 1, tot = side * side * side * side;
-        k_c5_out<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(m5, c2, c3, stats, p.M, c5);
+        const int64_t grid = std::min<int64_t>((tot + 255) / 256, gmax);
+        k_c5_out<<<(unsigned)grid, 256, 0, s>>>(m5, c2, c3, stats, p.M, c5);
     }
     if (Q) {
         const int64_t tot = (int64_t)nfft * nfft * nfft * nfft;
-        k_c5_fold<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(m5, c2, c3, stats, p.M, nfft,
-                                                               window, (double2 *)Q);
+        const int64_t grid = std::min<int64_t>((tot + 255) / 256, gmax);
+        k_c5_fold<<<(unsigned)grid, 256, 0, s>>>(m5, c2, c3, stats, p.M, nfft, window,
+                                                 (double2 *)Q);
     }
     return hipGetLastError();
 }

@@ -28,15 +28,53 @@ __global__ void k_twiddle(double2 *__restrict__ tw, int N)
 }
 
 // Sequence s starts at (s / b_in) * s_out + (s % b_in) * s_in; element k
-// of it sits k * es further.  CB sequences per workgroup.
+// of it sits k * es further.  CB sequences per workgroup, each sequence's
+// start computed once.  PP: two LDS buffers of CB * N complex values (sized
+// at launch); each Stockham stage reads one and writes the other, so a
+// thread holds one butterfly at a time -- for short transforms, where the
+// in-place stages would hold registers for butterflies that do not exist.
+// Otherwise one buffer and the in-place stages (all their butterfly slots
+// are used once CB * N fills the LDS area).
+constexpr int FFT_MAX_CB = 64;
+
+template <int R>
+__device__ inline void stockham_pingpong(const double2 *__restrict__ src,
+                                         double2 *__restrict__ dst,
+                                         const double2 *__restrict__ tw, int N, int Ns, int CB)
+{
+    const int nbf = N / R, total = CB * nbf, stride = N / (Ns * R);
+    for (int u = threadIdx.x; u < total; u += FFT_THREADS) {
+        const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
+        double2 v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const double2 x = src[cb * N + j + q * nbf];
+            v[q] = q == 0 ? x : cmul(x, tw[q * k * stride]);
+        }
+        dft_small<R>(v, tw, N);
+        const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int p = 0; p < R; ++p)
+            dst[cb * N + idxD + p * Ns] = v[p];
+    }
+    __syncthreads();
+}
+
+template <bool PP>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadices fr,
            int64_t nseq, int64_t es, int64_t b_in, int64_t s_in, int64_t s_out, int CB)
 {
-    __shared__ double2 sm[FFT_LDS_ELEMS];
+    extern __shared__ double2 sm[];
+    __shared__ int64_t base[FFT_MAX_CB];
     const int N = fr.n;
     const int64_t seq0 = (int64_t)blockIdx.x * CB;
     const int tot = CB * N;
+    for (int cb = threadIdx.x; cb < CB; cb += FFT_THREADS) {
+        const int64_t s = seq0 + cb;
+        base[cb] = s < nseq ? (s / b_in) * s_out + (s % b_in) * s_in : -1;
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
         int cb, k;
         if (es == 1) {
@@ -46,22 +84,37 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
             k = e / CB;
             cb = e - k * CB;
         }
-        const int64_t s = seq0 + cb;
-        if (s < nseq)
-            sm[cb * N + k] = data[(s / b_in) * s_out + (s % b_in) * s_in + k * es];
+        const int64_t b = base[cb];
+        if (b >= 0)
+            sm[cb * N + k] = data[b + k * es];
     }
     __syncthreads();
+    double2 *cur = sm, *nxt = sm + tot;
     int Ns = 1;
     for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
         const int R = fr.r[st];
-        if (R == 4)
-            stockham_stage<4>(sm, tw, N, Ns, CB);
-        else if (R == 2)
-            stockham_stage<2>(sm, tw, N, Ns, CB);
-        else if (R == 3)
-            stockham_stage<3>(sm, tw, N, Ns, CB);
-        else
-            stockham_stage<5>(sm, tw, N, Ns, CB);
+        if constexpr (PP) {
+            if (R == 4)
+                stockham_pingpong<4>(cur, nxt, tw, N, Ns, CB);
+            else if (R == 2)
+                stockham_pingpong<2>(cur, nxt, tw, N, Ns, CB);
+            else if (R == 3)
+                stockham_pingpong<3>(cur, nxt, tw, N, Ns, CB);
+            else
+                stockham_pingpong<5>(cur, nxt, tw, N, Ns, CB);
+            double2 *t = cur;
+            cur = nxt;
+            nxt = t;
+        } else {
+            if (R == 4)
+                stockham_stage<4>(sm, tw, N, Ns, CB);
+            else if (R == 2)
+                stockham_stage<2>(sm, tw, N, Ns, CB);
+            else if (R == 3)
+                stockham_stage<3>(sm, tw, N, Ns, CB);
+            else
+                stockham_stage<5>(sm, tw, N, Ns, CB);
+        }
         Ns *= R;
     }
     for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
@@ -73,20 +126,32 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
             k = e / CB;
             cb = e - k * CB;
         }
-        const int64_t s = seq0 + cb;
-        if (s < nseq)
-            data[(s / b_in) * s_out + (s % b_in) * s_in + k * es] = sm[cb * N + k];
+        const int64_t b = base[cb];
+        if (b >= 0)
+            data[b + k * es] = cur[cb * N + k];
     }
 }
 
 void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq, int64_t es,
               int64_t b_in, int64_t s_in, int64_t s_out, hipStream_t s)
 {
-    int CB = FFT_LDS_ELEMS / fr.n;
+    // ping-pong while both buffers of >= 8 sequences fit the 64 KB area
+    // (N <= 256), else in place
+    int CB = FFT_LDS_ELEMS / (2 * fr.n);
+    if (CB > 32)
+        CB = 32;
+    if (CB >= 8) {
+        const int64_t blocks = (nseq + CB - 1) / CB;
+        k_fft_axis<true><<<blocks, FFT_THREADS, 2 * (size_t)CB * fr.n * sizeof(double2), s>>>(
+            d, tw, fr, nseq, es, b_in, s_in, s_out, CB);
+        return;
+    }
+    CB = FFT_LDS_ELEMS / fr.n;
     if (CB > 32)
         CB = 32;
     const int64_t blocks = (nseq + CB - 1) / CB;
-    k_fft_axis<<<blocks, FFT_THREADS, 0, s>>>(d, tw, fr, nseq, es, b_in, s_in, s_out, CB);
+    k_fft_axis<false><<<blocks, FFT_THREADS, (size_t)CB * fr.n * sizeof(double2), s>>>(
+        d, tw, fr, nseq, es, b_in, s_in, s_out, CB);
 }
 
 }  // namespace

@@ -172,6 +172,8 @@ def test_c5_plan():
     (dict(x=None), hos.HOS_EINVAL),
     (dict(c3=None, B=None), hos.HOS_EINVAL),
     (dict(ws_bytes=1000), hos.HOS_EWORKSPACE),
+    (dict(B=None, nfft=-1), hos.HOS_EINVAL),
+    (dict(nfft=100), hos.HOS_EINVAL),          # below 2M with a window
 ])
 def test_streamed_validation_before_device(kw, code):
     a = dict(x=FAKE, dtype=hos.HOS_F32, n=1 << 20, M=64, window=hos.HOS_WIN_PARZEN, nfft=128,

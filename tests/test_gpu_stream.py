@@ -79,3 +79,24 @@ def test_matches_in_memory_call_at_size(path):
     e = float(np.max(np.abs(cs[w[:, 0] + 512, w[:, 1] + 512] - ref)) / np.max(np.abs(ref)))
     print("sampled rel err %.3e" % e)
     assert e < TOL[path]
+
+
+@pytest.mark.parametrize("M,nfft,window,return_B", [
+    (0, None, "parzen", True),      # lag 0 only
+    (40, 81, "none", True),         # odd DFT size (3^4), no window
+    (70, None, "parzen", False),    # c3 only
+])
+def test_edge_cases(M, nfft, window, return_B):
+    hos = _hos()
+    x = synth.iid_exp_centered(9000, 31 + M)
+    print("case: n=9000 M=%d nfft=%s window=%s B=%s" % (M, nfft, window, return_B), flush=True)
+    c3, B = hos.bispectrum_streamed(x, M, piece=4096, nfft=nfft, window=window,
+                                    path="split_fp16", return_B=return_B)
+    torch.cuda.synchronize()
+    N = nfft or hos.default_nfft(M, window)
+    c_ref, B_ref = oracle.bispectrum(x, M, N, window=window)
+    assert _err(c3.cpu().numpy(), c_ref) < TOL["split_fp16"]
+    if return_B:
+        assert _err(B.cpu().numpy(), B_ref) < TOL["split_fp16"]
+    else:
+        assert B is None
