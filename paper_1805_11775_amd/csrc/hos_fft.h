@@ -60,16 +60,17 @@ __device__ inline void dft_small(double2 *v, const double2 *__restrict__ tw, int
     }
 }
 
-template <int R>
+// THREADS: the workgroup size (FFT_THREADS unless a kernel says otherwise).
+template <int R, int THREADS = FFT_THREADS>
 __device__ inline void stockham_stage(double2 *sm, const double2 *__restrict__ tw, int N,
                                       int Ns, int CB)
 {
-    constexpr int MAXIT = (FFT_LDS_ELEMS / R + FFT_THREADS - 1) / FFT_THREADS;
+    constexpr int MAXIT = (FFT_LDS_ELEMS / R + THREADS - 1) / THREADS;
     const int nbf = N / R, total = CB * nbf, stride = N / (Ns * R);
     double2 v[MAXIT][R];
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
-        const int u = threadIdx.x + FFT_THREADS * it;
+        const int u = threadIdx.x + THREADS * it;
         if (u < total) {
             const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
 #pragma unroll
@@ -83,7 +84,7 @@ __device__ inline void stockham_stage(double2 *sm, const double2 *__restrict__ t
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
-        const int u = threadIdx.x + FFT_THREADS * it;
+        const int u = threadIdx.x + THREADS * it;
         if (u < total) {
             const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
             const int idxD = (j / Ns) * Ns * R + k;
@@ -121,6 +122,7 @@ inline FftRadices factor(int N)
     return f;
 }
 
+template <int THREADS = FFT_THREADS>
 __device__ inline void fft_lds(double2 *sm, const double2 *__restrict__ tw, const FftRadices &fr,
                                int CB)
 {
@@ -128,13 +130,13 @@ __device__ inline void fft_lds(double2 *sm, const double2 *__restrict__ tw, cons
     for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
         const int R = fr.r[st];
         if (R == 4)
-            stockham_stage<4>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<4, THREADS>(sm, tw, fr.n, Ns, CB);
         else if (R == 2)
-            stockham_stage<2>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<2, THREADS>(sm, tw, fr.n, Ns, CB);
         else if (R == 3)
-            stockham_stage<3>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<3, THREADS>(sm, tw, fr.n, Ns, CB);
         else
-            stockham_stage<5>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<5, THREADS>(sm, tw, fr.n, Ns, CB);
         Ns *= R;
     }
 }

@@ -37,13 +37,13 @@ __global__ void k_twiddle(double2 *__restrict__ tw, int N)
 // are used once CB * N fills the LDS area).
 constexpr int FFT_MAX_CB = 64;
 
-template <int R>
+template <int R, int THREADS>
 __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
                                          double2 *__restrict__ dst,
                                          const double2 *__restrict__ tw, int N, int Ns, int CB)
 {
     const int nbf = N / R, total = CB * nbf, stride = N / (Ns * R);
-    for (int u = threadIdx.x; u < total; u += FFT_THREADS) {
+    for (int u = threadIdx.x; u < total; u += THREADS) {
         const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
         double2 v[R];
 #pragma unroll
@@ -60,8 +60,8 @@ __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
     __syncthreads();
 }
 
-template <bool PP>
-__global__ void __launch_bounds__(FFT_THREADS)
+template <bool PP, int THREADS>
+__global__ void __launch_bounds__(THREADS)
 k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadices fr,
            int64_t nseq, int64_t es, int64_t b_in, int64_t s_in, int64_t s_out, int CB)
 {
@@ -70,12 +70,12 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
     const int N = fr.n;
     const int64_t seq0 = (int64_t)blockIdx.x * CB;
     const int tot = CB * N;
-    for (int cb = threadIdx.x; cb < CB; cb += FFT_THREADS) {
+    for (int cb = threadIdx.x; cb < CB; cb += THREADS) {
         const int64_t s = seq0 + cb;
         base[cb] = s < nseq ? (s / b_in) * s_out + (s % b_in) * s_in : -1;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+    for (int e = threadIdx.x; e < tot; e += THREADS) {
         int cb, k;
         if (es == 1) {
             cb = e / N;
@@ -95,29 +95,29 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
         const int R = fr.r[st];
         if constexpr (PP) {
             if (R == 4)
-                stockham_pingpong<4>(cur, nxt, tw, N, Ns, CB);
+                stockham_pingpong<4, THREADS>(cur, nxt, tw, N, Ns, CB);
             else if (R == 2)
-                stockham_pingpong<2>(cur, nxt, tw, N, Ns, CB);
+                stockham_pingpong<2, THREADS>(cur, nxt, tw, N, Ns, CB);
             else if (R == 3)
-                stockham_pingpong<3>(cur, nxt, tw, N, Ns, CB);
+                stockham_pingpong<3, THREADS>(cur, nxt, tw, N, Ns, CB);
             else
-                stockham_pingpong<5>(cur, nxt, tw, N, Ns, CB);
+                stockham_pingpong<5, THREADS>(cur, nxt, tw, N, Ns, CB);
             double2 *t = cur;
             cur = nxt;
             nxt = t;
         } else {
             if (R == 4)
-                stockham_stage<4>(sm, tw, N, Ns, CB);
+                stockham_stage<4, THREADS>(sm, tw, N, Ns, CB);
             else if (R == 2)
-                stockham_stage<2>(sm, tw, N, Ns, CB);
+                stockham_stage<2, THREADS>(sm, tw, N, Ns, CB);
             else if (R == 3)
-                stockham_stage<3>(sm, tw, N, Ns, CB);
+                stockham_stage<3, THREADS>(sm, tw, N, Ns, CB);
             else
-                stockham_stage<5>(sm, tw, N, Ns, CB);
+                stockham_stage<5, THREADS>(sm, tw, N, Ns, CB);
         }
         Ns *= R;
     }
-    for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
+    for (int e = threadIdx.x; e < tot; e += THREADS) {
         int cb, k;
         if (es == 1) {
             cb = e / N;
@@ -142,16 +142,24 @@ void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq,
         CB = 32;
     if (CB >= 8) {
         const int64_t blocks = (nseq + CB - 1) / CB;
-        k_fft_axis<true><<<blocks, FFT_THREADS, 2 * (size_t)CB * fr.n * sizeof(double2), s>>>(
+        k_fft_axis<true, FFT_THREADS><<<blocks, FFT_THREADS,
+                                        2 * (size_t)CB * fr.n * sizeof(double2), s>>>(
             d, tw, fr, nseq, es, b_in, s_in, s_out, CB);
         return;
     }
+    // in place: long transforms fill the LDS area with few sequences, so a
+    // workgroup of 1024 threads takes one butterfly per thread and stage
     CB = FFT_LDS_ELEMS / fr.n;
     if (CB > 32)
         CB = 32;
     const int64_t blocks = (nseq + CB - 1) / CB;
-    k_fft_axis<false><<<blocks, FFT_THREADS, (size_t)CB * fr.n * sizeof(double2), s>>>(
-        d, tw, fr, nseq, es, b_in, s_in, s_out, CB);
+    const size_t lds = (size_t)CB * fr.n * sizeof(double2);
+    if (fr.n >= 512)
+        k_fft_axis<false, 1024><<<blocks, 1024, lds, s>>>(d, tw, fr, nseq, es, b_in, s_in, s_out,
+                                                         CB);
+    else
+        k_fft_axis<false, FFT_THREADS><<<blocks, FFT_THREADS, lds, s>>>(d, tw, fr, nseq, es,
+                                                                       b_in, s_in, s_out, CB);
 }
 
 }  // namespace
@@ -304,8 +312,8 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
 // The full N x N spectrum of one series: fold + window into LDS, row DFTs with
 // two real rows per complex sequence (as k_pd_rows), every k2 written to B;
 // the column pass then runs in place (launch_fft_cols).
-template <int ELEMS>
-__global__ void __launch_bounds__(FFT_THREADS)
+template <int ELEMS, int THREADS>
+__global__ void __launch_bounds__(THREADS)
 k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, int M,
             const double2 *__restrict__ tw, FftRadices fr, int CBP, int window,
             double2 *__restrict__ B)
@@ -316,7 +324,7 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
     const double norm = stats[3];
     const bool pz = window != HOS_WIN_NONE;            // d on the lags
     const bool pdiff = window == HOS_WIN_PARZEN;        // and on their differences
-    for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
+    for (int m = threadIdx.x; m <= M; m += THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
     auto fold = [&](int m1, int m2) {
@@ -337,13 +345,13 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
         return sum;
     };
     const int m1_0 = blockIdx.x * 2 * CBP;
-    for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
+    for (int e = threadIdx.x; e < CBP * N; e += THREADS) {
         const int p = e / N, m2 = e - p * N, m1 = m1_0 + 2 * p;
         sm[e] = make_double2(fold(m1, m2), fold(m1 + 1, m2));
     }
     __syncthreads();
-    fft_lds(sm, tw, fr, CBP);
-    for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
+    fft_lds<THREADS>(sm, tw, fr, CBP);
+    for (int e = threadIdx.x; e < CBP * N; e += THREADS) {
         const int p = e / N, k = e - p * N, m1 = m1_0 + 2 * p;
         const double2 z = sm[p * N + k], zc = sm[p * N + (k == 0 ? 0 : N - k)];
         if (m1 < N)
@@ -451,12 +459,18 @@ hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int
                             const double2 *tw, double *B, hipStream_t s)
 {
     const FftRadices fr = factor(N);
+    // long rows: 1024 threads, one butterfly per thread and stage
     if (N <= PD_LDS_ELEMS) {
         const int CBP = PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
-        k_full_rows<PD_LDS_ELEMS><<<(N + 2 * CBP - 1) / (2 * CBP), FFT_THREADS, 0, s>>>(
-            cfull, stats, M, tw, fr, CBP, window, (double2 *)B);
+        const unsigned grid = (N + 2 * CBP - 1) / (2 * CBP);
+        if (N >= 512)
+            k_full_rows<PD_LDS_ELEMS, 1024><<<grid, 1024, 0, s>>>(cfull, stats, M, tw, fr, CBP,
+                                                                window, (double2 *)B);
+        else
+            k_full_rows<PD_LDS_ELEMS, FFT_THREADS><<<grid, FFT_THREADS, 0, s>>>(
+                cfull, stats, M, tw, fr, CBP, window, (double2 *)B);
     } else {
-        k_full_rows<FFT_LDS_ELEMS><<<(N + 1) / 2, FFT_THREADS, 0, s>>>(
+        k_full_rows<FFT_LDS_ELEMS, 1024><<<(N + 1) / 2, 1024, 0, s>>>(
             cfull, stats, M, tw, fr, 1, window, (double2 *)B);
     }
     return hipGetLastError();
