@@ -622,6 +622,8 @@ k_c3_reduce(const double *__restrict__ part, const int64_t *__restrict__ tfirst,
     const int64_t w_lo = sk_owner(g, sk_chunk_start(g, R, Cc, 0));
     const int64_t w_hi = sk_owner(g, sk_chunk_start(g, R, Cc, g.C - 1));
     double sum = 0.0;
+    // unrolled so the loads go out ahead; the adds keep their order
+#pragma unroll 8
     for (int64_t w = w_lo; w <= w_hi; ++w) {
         const int64_t slot = w * smax + (t - tfirst[w]);
         sum += part[slot * TILE + (int64_t)blk * 1024 + e];
@@ -922,6 +924,7 @@ k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict
     double *cfull = (double *)(ws + d.ws_off + d.o_cfull);
     const int e = threadIdx.x + 256 * q;
     double sum = 0.0;
+#pragma unroll 8
     for (int j = 0; j < t.nslot; ++j)
         sum += part[(t.slot0 + j) * TILE + (int64_t)blk * 1024 + e];
     const int v = e >> 6, lane = e & 63;

@@ -425,6 +425,8 @@ __device__ __forceinline__ void moment_reduce(const double *__restrict__ part, i
         return;
     const int e = threadIdx.x + 256 * q;
     double sum = 0.0;
+    // unrolled so the loads go out ahead; the adds keep their order
+#pragma unroll 8
     for (int s = 0; s < S; ++s)
         sum += part[(((int64_t)s * RB + rb) * NCB + cb) * 1024 + e];
     const int v = e >> 6, lane = e & 63;
