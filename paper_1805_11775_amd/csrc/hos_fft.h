@@ -60,12 +60,13 @@ __device__ inline void dft_small(double2 *v, const double2 *__restrict__ tw, int
     }
 }
 
-// THREADS: the workgroup size (FFT_THREADS unless a kernel says otherwise).
-template <int R, int THREADS = FFT_THREADS>
+// THREADS: the workgroup size; ELEMS: the complex values of the caller's
+// LDS area (CB * N <= ELEMS), which bounds the butterflies a thread holds.
+template <int R, int THREADS = FFT_THREADS, int ELEMS = FFT_LDS_ELEMS>
 __device__ inline void stockham_stage(double2 *sm, const double2 *__restrict__ tw, int N,
                                       int Ns, int CB)
 {
-    constexpr int MAXIT = (FFT_LDS_ELEMS / R + THREADS - 1) / THREADS;
+    constexpr int MAXIT = (ELEMS / R + THREADS - 1) / THREADS;
     const int nbf = N / R, total = CB * nbf, stride = N / (Ns * R);
     double2 v[MAXIT][R];
 #pragma unroll
@@ -122,7 +123,7 @@ inline FftRadices factor(int N)
     return f;
 }
 
-template <int THREADS = FFT_THREADS>
+template <int THREADS = FFT_THREADS, int ELEMS = FFT_LDS_ELEMS>
 __device__ inline void fft_lds(double2 *sm, const double2 *__restrict__ tw, const FftRadices &fr,
                                int CB)
 {
@@ -130,13 +131,13 @@ __device__ inline void fft_lds(double2 *sm, const double2 *__restrict__ tw, cons
     for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
         const int R = fr.r[st];
         if (R == 4)
-            stockham_stage<4, THREADS>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<4, THREADS, ELEMS>(sm, tw, fr.n, Ns, CB);
         else if (R == 2)
-            stockham_stage<2, THREADS>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<2, THREADS, ELEMS>(sm, tw, fr.n, Ns, CB);
         else if (R == 3)
-            stockham_stage<3, THREADS>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<3, THREADS, ELEMS>(sm, tw, fr.n, Ns, CB);
         else
-            stockham_stage<5, THREADS>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<5, THREADS, ELEMS>(sm, tw, fr.n, Ns, CB);
         Ns *= R;
     }
 }

@@ -260,7 +260,7 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
         sm[e] = make_double2(fold(m1, m2), fold(m1 + 1, m2));
     }
     __syncthreads();
-    fft_lds(sm, tw, fr, CBP);
+    fft_lds<FFT_THREADS, PD_LDS_ELEMS>(sm, tw, fr, CBP);
     double2 *T1 = (double2 *)(ws + d.grid_off);
     for (int e = threadIdx.x; e < CBP * K2; e += FFT_THREADS) {
         const int p = e / K2, k2 = e - p * K2, m1 = m1_0 + 2 * p;
@@ -299,7 +299,7 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
         }
     }
     __syncthreads();
-    fft_lds(sm, tw, fr, CB);
+    fft_lds<FFT_THREADS, PD_LDS_ELEMS>(sm, tw, fr, CB);
     const int half = H + 1;   // k1 <= H
     for (int e = threadIdx.x; e < CB * half; e += FFT_THREADS) {
         const int cb = e / half, k1 = e - cb * half, k2 = k2_0 + cb;
@@ -350,7 +350,7 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
         sm[e] = make_double2(fold(m1, m2), fold(m1 + 1, m2));
     }
     __syncthreads();
-    fft_lds<THREADS>(sm, tw, fr, CBP);
+    fft_lds<THREADS, ELEMS>(sm, tw, fr, CBP);
     for (int e = threadIdx.x; e < CBP * N; e += THREADS) {
         const int p = e / N, k = e - p * N, m1 = m1_0 + 2 * p;
         const double2 z = sm[p * N + k], zc = sm[p * N + (k == 0 ? 0 : N - k)];
@@ -410,7 +410,7 @@ k_tri_lines(const double *__restrict__ m4tab, const double *__restrict__ c2,
         sm[e] = make_double2(fold(L0 + 2 * p, m3), fold(L0 + 2 * p + 1, m3));
     }
     __syncthreads();
-    fft_lds(sm, tw, fr, CBP);
+    fft_lds<FFT_THREADS, PD_LDS_ELEMS>(sm, tw, fr, CBP);
     for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
         const int p = e / N, k = e - p * N;
         const int64_t L = L0 + 2 * p;
@@ -501,8 +501,13 @@ hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double 
                             int N, int window, const double2 *tw, double *T, hipStream_t s)
 {
     const FftRadices fr = factor(N);
-    const int CBP = PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
+    // line pairs per workgroup: what the LDS area holds, at most 32, and few
+    // enough that the grid has about 512 workgroups
     const int64_t lines = (int64_t)N * N;
+    int CBP = PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
+    const int64_t fill = lines / (2 * 512);
+    if (fill < CBP)
+        CBP = fill < 1 ? 1 : (int)fill;
     k_tri_lines<<<(unsigned)((lines + 2 * CBP - 1) / (2 * CBP)), FFT_THREADS, 0, s>>>(
         m4tab, c2, stats, M, tw, fr, CBP, window, (double2 *)T);
     return hipGetLastError();
