@@ -281,7 +281,7 @@ def _time(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def bench_batched(hos, torch, oracle, synth, paths, steps, warmup):
+def bench_batched(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0.0):
     """4096 float32 series of uneven length and lag in one batched call
     (principal-domain spectra only); metric sum_s n_s (2 M_s + 1)^2 / t."""
     xs, n, M = synth.workload_batched()
@@ -323,18 +323,44 @@ def bench_batched(hos, torch, oracle, synth, paths, steps, warmup):
               flush=True)
         del plan
     head = "split_fp16" if "split_fp16" in out else next(iter(out))
-    return {"metric": "cumulant lag-sums/s (sum_s n_s (2M_s+1)^2 / s)",
-            "value": out[head]["value"], "unit": "lag-sums/s",
-            "ms_per_step": out[head]["ms_per_call"], "dtype": DTYPE[head],
-            "config": {"workload": "4096 float32 series, n uniform in [1024, 65536], M uniform "
-                                   "in {32, 64, 128, 256}, even index N(0,1), odd index "
-                                   "Exp(1)-1; Parzen window, N = 2M; principal-domain spectra; "
-                                   "tiles from the autotuner",
-                       "series": len(n), "samples": int(np.sum(n)), "path": head},
-            "paths": out}
+    h = out[head]
+    rec = {"metric": "cumulant lag-sums/s (sum_s n_s (2M_s+1)^2 / s)",
+           "value": h["value"], "unit": "lag-sums/s",
+           "ms_per_step": h["ms_per_call"], "dtype": DTYPE[head],
+           "config": {"workload": "4096 float32 series, n uniform in [1024, 65536], M uniform "
+                                  "in {32, 64, 128, 256}, even index N(0,1), odd index "
+                                  "Exp(1)-1; Parzen window, N = 2M; principal-domain spectra; "
+                                  "tiles from the autotuner",
+                      "series": len(n), "samples": int(np.sum(n)), "path": head},
+           # the item contraction runs as one launch per tile class (4 x 4 and
+           # 2 x 2 blocks); the entry point's stage events time them together
+           "roofline": {"bound": "mfma", "kernel": "k_c3_items",
+                        "achieved": h["contract_tflops"], "peak": PEAK[head] / 1e12,
+                        "unit": "TFLOP/s", "frac": h["contract_frac"], "traffic": None,
+                        "flops_per_call": flops, "avg_call_ms": h["stage_ms"]["contract"]},
+           "paths": out}
+    if cpu_seconds > 0:
+        t0 = time.perf_counter()
+        k = lagsums_done = 0
+        w1, w2 = sample_lags(64, 64, seed=19)
+        while time.perf_counter() - t0 < cpu_seconds:
+            s_ = (37 * k) % len(n)
+            m = int(M[s_])
+            sel = (np.abs(w1) <= m) & (np.abs(w2) <= m) & (np.abs(w1 - w2) <= m)
+            oracle.c3_at(xs[s_], w1[sel], w2[sel])
+            lagsums_done += int(sel.sum()) * xs[s_].size
+            k += 1
+        t = time.perf_counter() - t0
+        rec["cpu_oracle"] = {"value": lagsums_done / t, "unit": "lag-sums/s",
+                             "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                         len(os.sched_getaffinity(0)))),
+                             "kind": "oracle",
+                             "sample": "%d series of the batch x up to 64 lags |w| <= 64, "
+                                       "FP64 brute-force c3 (%.1f s)" % (k, t)}
+    return rec
 
 
-def bench_loss(hos, torch, oracle, synth, paths, steps, warmup):
+def bench_loss(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0.0):
     """Loss forward and hand-written backward over 64 float32 N(0,1) series,
     n = 65536, M = 256, N = 512."""
     X, tgt, cfg = synth.workload_loss()
@@ -374,15 +400,35 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup):
               file=sys.stderr, flush=True)
         del plan
     head = "split_fp16" if "split_fp16" in out else next(iter(out))
-    return {"metric": "forward lag-sums/s; backward ms", "value": out[head]["fwd_value"],
-            "unit": "lag-sums/s", "dtype": DTYPE[head],
-            "config": {"workload": "bispectrum-matching loss, 64 float32 N(0,1) series, "
-                                   "n=65536, M=256, N=512, target from a quadratic-process "
-                                   "series; forward + hand-written adjoint",
-                       "batch": B_, "n": n_, "M": M, "nfft": N, "path": head},
-            "bwd_flops_definition": "2 n (3M^2+3M+1) per series: the quadratic form of the "
-                                    "(2M+1)-sample window over the hexagon",
-            "paths": out}
+    h = out[head]
+    rec = {"metric": "forward lag-sums/s; backward ms", "value": h["fwd_value"],
+           "unit": "lag-sums/s", "dtype": DTYPE[head],
+           "config": {"workload": "bispectrum-matching loss, 64 float32 N(0,1) series, "
+                                  "n=65536, M=256, N=512, target from a quadratic-process "
+                                  "series; forward + hand-written adjoint",
+                      "batch": B_, "n": n_, "M": M, "nfft": N, "path": head},
+           "bwd_flops_definition": "2 n (3M^2+3M+1) per series: the quadratic form of the "
+                                   "(2M+1)-sample window over the hexagon",
+           # the backward entry point has no stage events: the whole backward
+           # call is timed, so the adjoint contraction's own fraction (see its
+           # kernel trace) is higher than this one
+           "roofline": {"bound": "mfma", "kernel": "k_adj_contract",
+                        "achieved": h["bwd_tflops"], "peak": PEAK[head] / 1e12,
+                        "unit": "TFLOP/s", "frac": h["bwd_frac"], "traffic": None,
+                        "flops_per_call": bwd_flops, "avg_call_ms": h["bwd_ms"],
+                        "timed": "whole backward call"},
+           "paths": out}
+    if cpu_seconds > 0:
+        t0 = time.perf_counter()
+        oracle.bispectrum_pd(X[0], M, N)
+        t = time.perf_counter() - t0
+        rec["cpu_oracle"] = {"value": n_ * (2 * M + 1) ** 2 / t, "unit": "lag-sums/s",
+                             "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                         len(os.sched_getaffinity(0)))),
+                             "kind": "oracle",
+                             "sample": "the forward of one series of the 64 (c3 over the "
+                                       "hexagon by FP64 brute force, window, DFT; %.1f s)" % t}
+    return rec
 
 
 def bench_segments(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds):
@@ -729,9 +775,9 @@ def main():
     }
     if not args.no_batch:
         rec["batched"] = bench_batched(hos, torch, oracle, synth, list(paths), args.steps,
-                                       args.warmup)
+                                       args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
         rec["loss"] = bench_loss(hos, torch, oracle, synth, list(paths), args.steps,
-                                 args.warmup)
+                                 args.warmup, 0.0 if args.no_cpu_baseline else 1.0)
     if not args.no_tri:
         rec["trispectrum"] = bench_trispectrum(
             hos, torch, oracle, synth, list(paths), args.steps, args.warmup,
