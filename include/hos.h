@@ -288,7 +288,8 @@ int hos_cumulant5(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t wi
                   int32_t nfft, int32_t path, uint32_t flags, double *c5, double *Q, void *ws,
                   size_t ws_bytes, hipStream_t stream);
 /* stage_ms (host, 5 floats): moments and operands, contraction, reduction
- * with c2 / c3 and the fold, the 4-D DFT, total.  Synchronises the stream. */
+ * with c2 / c3, the fold and the DFT along the last axis, the DFTs along
+ * the other three axes, total.  Synchronises the stream. */
 int hos_cumulant5_timed(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
                         int32_t nfft, int32_t path, uint32_t flags, double *c5, double *Q,
                         void *ws, size_t ws_bytes, hipStream_t stream, float *stage_ms);

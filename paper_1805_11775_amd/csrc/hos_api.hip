@@ -483,7 +483,7 @@ static int cumulant5_impl(const void *x, int32_t dtype, int64_t n, int32_t M, in
     if (e == hipSuccess && Q) e = launch_twiddles(tw, nfft, stream);
     if (e == hipSuccess) e = launch_c5_finish(p, window, nfft, c5, Q, w, stream);
     if (e == hipSuccess) e = mark(3);
-    if (e == hipSuccess && Q) e = launch_fft4_axes(Q, nfft, tw, stream);
+    if (e == hipSuccess && Q) e = launch_fft4_tail(Q, nfft, tw, stream);
     if (e == hipSuccess) e = mark(4);
     return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
 }

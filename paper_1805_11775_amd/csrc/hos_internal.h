@@ -359,6 +359,6 @@ hipError_t launch_c4_finish(const C4Plan &p, int window, int nfft, double *c4, d
                             char *ws, hipStream_t s);
 hipError_t launch_c5_finish(const C4Plan &p, int window, int nfft, double *c5, double *Q,
                             char *ws, hipStream_t s);
-hipError_t launch_fft4_axes(double *Q, int N, const double2 *tw, hipStream_t s);
+hipError_t launch_fft4_tail(double *Q, int N, const double2 *tw, hipStream_t s);
 
 }  // namespace hos

@@ -27,6 +27,7 @@
 
 #include "hos_internal.h"
 #include "hos_device.h"
+#include "hos_fft.h"
 
 namespace hos {
 
@@ -668,41 +669,41 @@ k_c5_out(const double *__restrict__ m5tab, const double *__restrict__ c2,
 }
 
 // The windowed c5 folded onto the N^4 DFT grid (index w mod N, aliases
-// summed), as complex values for the in-place axis transforms.
+// summed) and transformed along the last axis in LDS: a workgroup takes
+// CBP pairs of lines L = (m1 N + m2) N + m3, the two real lines of a pair
+// travel as one complex sequence Z (lines L and L + 1 as its real and
+// imaginary parts), and after the DFT
+//   X_L(k) = (Z(k) + conj Z(N-k)) / 2,  X_{L+1}(k) = (Z(k) - conj Z(N-k)) / 2i
+// go to Q; the three other axes follow (launch_fft4_tail).
+constexpr int C5L_LDS = 2048;   // complex values of the line buffer
+
 __global__ void __launch_bounds__(256)
-k_c5_fold(const double *__restrict__ m5tab, const double *__restrict__ c2,
-          const double *__restrict__ c3tab, const double *__restrict__ stats, int M, int N,
-          int window, double2 *__restrict__ Q)
+k_c5_lines(const double *__restrict__ m5tab, const double *__restrict__ c2,
+           const double *__restrict__ c3tab, const double *__restrict__ stats, int M,
+           const double2 *__restrict__ tw, FftRadices fr, int CBP, int window,
+           double2 *__restrict__ Q)
 {
+    __shared__ double2 sm[C5L_LDS];
     __shared__ C5Tables tab;
     load_c5_tables(tab, c2, c3tab, M);
-    const uint32_t n = N, tot = n * n * n * n;
+    const int N = fr.n;
+    const uint32_t lines = (uint32_t)N * N * N;
     const double norm5 = stats[4] * stats[1];
-    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
-         idx += gridDim.x * blockDim.x) {
-        uint32_t r = idx;
-        int m[4];
-        m[3] = (int)(r % n);
-        r /= n;
-        m[2] = (int)(r % n);
-        r /= n;
-        m[1] = (int)(r % n);
-        m[0] = (int)(r / n);
+    auto fold = [&](uint32_t L, int m4) {
         double sum = 0.0;
-        for (int k0 = 0; k0 < 2; ++k0) {
-            const int w1 = m[0] - k0 * N;
+        if (L >= lines)
+            return sum;
+        const int m3 = (int)(L % N), m2 = (int)((L / N) % N), m1 = (int)(L / ((uint32_t)N * N));
+        for (int w1 = m1 - N; w1 <= m1; w1 += N) {
             if (w1 < -M || w1 > M)
                 continue;
-            for (int k1 = 0; k1 < 2; ++k1) {
-                const int w2 = m[1] - k1 * N;
+            for (int w2 = m2 - N; w2 <= m2; w2 += N) {
                 if (w2 < -M || w2 > M)
                     continue;
-                for (int k2 = 0; k2 < 2; ++k2) {
-                    const int w3 = m[2] - k2 * N;
+                for (int w3 = m3 - N; w3 <= m3; w3 += N) {
                     if (w3 < -M || w3 > M)
                         continue;
-                    for (int k3 = 0; k3 < 2; ++k3) {
-                        const int w4 = m[3] - k3 * N;
+                    for (int w4 = m4 - N; w4 <= m4; w4 += N) {
                         if (w4 < -M || w4 > M)
                             continue;
                         const double wv = window5_tab(tab.d, w1, w2, w3, w4, M, window);
@@ -712,7 +713,23 @@ k_c5_fold(const double *__restrict__ m5tab, const double *__restrict__ c2,
                 }
             }
         }
-        Q[idx] = make_double2(sum, 0.0);
+        return sum;
+    };
+    const uint32_t L0 = blockIdx.x * 2u * (uint32_t)CBP;
+    for (int e = threadIdx.x; e < CBP * N; e += 256) {
+        const int p = e / N, m4 = e - p * N;
+        sm[e] = make_double2(fold(L0 + 2 * p, m4), fold(L0 + 2 * p + 1, m4));
+    }
+    __syncthreads();
+    fft_lds<256, C5L_LDS>(sm, tw, fr, CBP);
+    for (int e = threadIdx.x; e < CBP * N; e += 256) {
+        const int p = e / N, k = e - p * N;
+        const uint32_t L = L0 + 2 * p;
+        const double2 z = sm[p * N + k], zc = sm[p * N + (k == 0 ? 0 : N - k)];
+        if (L < lines)
+            Q[(int64_t)L * N + k] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+        if (L + 1 < lines)
+            Q[(int64_t)(L + 1) * N + k] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
     }
 }
 
@@ -827,11 +844,14 @@ hipError_t launch_c5_finish(const C4Plan &p, int window, int nfft, double *c5, d
         const int64_t grid = std::min<int64_t>((tot + 255) / 256, gmax);
         k_c5_out<<<(unsigned)grid, 256, 0, s>>>(m5, c2, c3, stats, p.M, c5);
     }
-    if (Q) {
-        const int64_t tot = (int64_t)nfft * nfft * nfft * nfft;
-        const int64_t grid = std::min<int64_t>((tot + 255) / 256, gmax);
-        k_c5_fold<<<(unsigned)grid, 256, 0, s>>>(m5, c2, c3, stats, p.M, nfft, window,
-                                                 (double2 *)Q);
+    if (Q) {   // fold, window and the transforms along the last axis
+        const FftRadices fr = factor(nfft);
+        const int64_t lines = (int64_t)nfft * nfft * nfft;
+        const int CBP = std::min(32, C5L_LDS / nfft);
+        const int64_t grid = (lines + 2 * CBP - 1) / (2 * CBP);
+        k_c5_lines<<<(unsigned)grid, 256, 0, s>>>(
+            m5, c2, c3, stats, p.M, (const double2 *)(ws + p.off_twid), fr, CBP, window,
+            (double2 *)Q);
     }
     return hipGetLastError();
 }

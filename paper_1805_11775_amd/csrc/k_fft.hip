@@ -476,20 +476,20 @@ hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int
     return hipGetLastError();
 }
 
-// In-place DFTs along k1 of an N x N row-major complex array.
-// In-place 4-D DFT of an N^4 row-major complex grid, one axis at a time.
-hipError_t launch_fft4_axes(double *Q, int N, const double2 *tw, hipStream_t s)
+// The first three axes of an in-place N^4 DFT whose last axis is done
+// (k_c5_lines transforms along it as it folds).
+hipError_t launch_fft4_tail(double *Q, int N, const double2 *tw, hipStream_t s)
 {
     double2 *d = (double2 *)Q;
     const FftRadices fr = factor(N);
     const int64_t N2 = (int64_t)N * N, N3 = N2 * N;
-    fft_axis(d, tw, fr, N3, 1, 1, 0, N, s);       // along the last axis
     fft_axis(d, tw, fr, N3, N, N, 1, N2, s);      // third
     fft_axis(d, tw, fr, N3, N2, N2, 1, N3, s);    // second
     fft_axis(d, tw, fr, N3, N3, N3, 1, 0, s);     // first
     return hipGetLastError();
 }
 
+// In-place DFTs along k1 of an N x N row-major complex array.
 hipError_t launch_fft_cols(double *B, int N, const double2 *tw, hipStream_t s)
 {
     fft_axis((double2 *)B, tw, factor(N), N, N, N, 1, 0, s);
