@@ -373,7 +373,9 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0.0)
     lagsums = float(B_ * n_ * (2 * M + 1) ** 2)
     hexagon = 3 * M * M + 3 * M + 1
     fwd_flops = B_ * 2.0 * n_ * (M + 1) * (M + 2) / 2
-    bwd_flops = B_ * 2.0 * n_ * hexagon   # the quadratic form over the hexagon per sample
+    # the quadratic form of the (2M+1)-sample window over the hexagon has a
+    # symmetric kernel: one MAC per unordered lag pair, (|H| + 2M + 1) / 2
+    bwd_flops = B_ * float(n_) * (hexagon + 2 * M + 1)
     dL = torch.ones((), dtype=torch.float64, device="cuda")
     out = {}
     for path in paths:
@@ -407,8 +409,9 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0.0)
                                   "n=65536, M=256, N=512, target from a quadratic-process "
                                   "series; forward + hand-written adjoint",
                       "batch": B_, "n": n_, "M": M, "nfft": N, "path": head},
-           "bwd_flops_definition": "2 n (3M^2+3M+1) per series: the quadratic form of the "
-                                   "(2M+1)-sample window over the hexagon",
+           "bwd_flops_definition": "n (|H| + 2M + 1) per series, |H| = 3M^2+3M+1: one MAC "
+                                   "per unordered lag pair of the symmetric quadratic form of "
+                                   "the (2M+1)-sample window over the hexagon",
            # the backward entry point has no stage events: the whole backward
            # call is timed, so the adjoint contraction's own fraction (see its
            # kernel trace) is higher than this one
