@@ -50,6 +50,7 @@ if ROOT not in sys.path:
 METRIC = "cumulant lag-sums/s (n·(2M+1)^2/s), split-prec vs FP32 at ≤1e-5 rel err"
 METRIC4 = "cumulant lag-sums/s (n·(2M+1)^3/s)"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_c3_contract_n2p20_M512_traffic.txt")
+MFMA_BUSY_FILE = os.path.join(ROOT, "profiles", "k_c3_contract_n2p20_M512_mfma_busy.txt")
 C3_SOURCE = os.path.join(ROOT, "paper_1805_11775_amd", "csrc", "k_c3.hip")
 DBS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dbs_box_n2p16_M3_1023_traffic.txt")
 DBS_SOURCE = os.path.join(ROOT, "paper_1805_11775_amd", "csrc", "k_dbs.hip")
@@ -648,6 +649,24 @@ def bench_dbs(hos, torch, oracle, synth, steps, warmup, cpu_seconds, sweep_box=T
     return rec
 
 
+def profile_value(path, key, source):
+    """One figure of a committed PMC summary, if it was taken on the
+    current kernel source; else None."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != hashlib.sha256(open(source, "rb").read()).hexdigest():
+        return None
+    try:
+        return float(kv[key])
+    except (KeyError, ValueError):
+        return None
+
+
 def traffic_record(path=TRAFFIC_FILE, source=C3_SOURCE):
     """HBM bytes per launch of a kernel from its committed PMC summary, if
     that was taken on the current kernel source."""
@@ -683,9 +702,20 @@ def cpu_baseline(oracle, x, M, seconds):
     t = time.perf_counter() - t0
     return {"value": w1.size * n / t, "unit": "lag-sums/s",
             "cores": int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))),
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": "%d lags of the hexagon x n=%d samples, FP64 brute-force c3 "
                       "(%.1f s)" % (w1.size, n, t)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -773,7 +803,11 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_c3_contract", "achieved": flops / t_k / 1e12,
                      "peak": PEAK[head] / 1e12, "unit": "TFLOP/s",
                      "frac": flops / t_k / PEAK[head], "traffic": traffic_record(),
-                     "flops_per_launch": flops, "avg_launch_ms": hp["stage_ms"]["contract"]},
+                     "flops_per_launch": flops, "avg_launch_ms": hp["stage_ms"]["contract"],
+                     # matrix-core busy cycles over the kernel's cycles (rocprofv3 PMC),
+                     # issued work: three FP16 products per algorithmic MAC plus the
+                     # blocks' triangle waste
+                     "mfma_busy": profile_value(MFMA_BUSY_FILE, "mfma_busy_frac", C3_SOURCE)},
         "paths": paths,
     }
     if not args.no_batch:
