@@ -100,3 +100,30 @@ def test_edge_cases(M, nfft, window, return_B):
         assert _err(B.cpu().numpy(), B_ref) < TOL["split_fp16"]
     else:
         assert B is None
+
+
+def test_workload_sampled():
+    """The streamed workload at its full size: n = 2^26 float32 quadratic
+    process in pinned host memory, pieces of 2^22, M = 512, split FP16 (the
+    configuration the benchmark times).  c3 at sampled lags against the
+    oracle's sums; B against the in-memory call on the same record, which
+    the streamed call equals up to the order of FP64 additions."""
+    hos = _hos()
+    x, cfg = synth.workload_streamed()
+    M, N, piece = cfg["M"], cfg["nfft"], cfg["piece"]
+    print("case: streamed workload n=%d M=%d piece=%d" % (x.size, M, piece), flush=True)
+    xh = torch.from_numpy(x).pin_memory()
+    cs, Bs = hos.bispectrum_streamed(xh, M, piece=piece, nfft=N, path="split_fp16")
+    cm, Bm = hos.bispectrum(xh.cuda(), M, N, path="split_fp16")
+    torch.cuda.synchronize()
+    d = _err(Bs.cpu().numpy(), Bm.cpu().numpy())
+    print("B streamed vs in-memory %.3e" % d)
+    assert d < 1e-9
+    rng = np.random.default_rng(5)
+    w = rng.integers(-M, M + 1, (40, 2))
+    w = w[np.abs(w[:, 0] - w[:, 1]) <= M]
+    ref = oracle.c3_at(x, w[:, 0], w[:, 1])
+    got = cs.cpu().numpy()[w[:, 0] + M, w[:, 1] + M]
+    e = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print("sampled rel err %.3e" % e)
+    assert e < TOL["split_fp16"]
