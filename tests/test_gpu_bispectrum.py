@@ -158,3 +158,60 @@ def test_long_workload_sampled(path):
     for k1, k2 in [(0, 0), (1, 2), (17, 300), (511, 512), (1023, 5)]:
         e = np.exp(-2j * np.pi * (k1 * lag[:, None] + k2 * lag[None, :]) / N)
         assert abs(np.sum(cw * e) - B[k1, k2]) < 1e-10 * np.max(np.abs(B))
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_max_lag_c3_only(path):
+    """M = 8192, the largest lag of the entry point (c3 only: a spectrum
+    needs N >= 2M and N <= 4096).  n = 20000, so most lags reach past the
+    record; c3 at sampled lags against the oracle's sums."""
+    hos = _hos()
+    M, n = 8192, 20000
+    x = synth.quadratic_process(n, 91).astype(np.float32)
+    t = torch.from_numpy(x).cuda()
+    print("case: max lag n=%d M=%d path=%s c3 only" % (n, M, path), flush=True)
+    c3, B = hos.bispectrum(t, M, path=path, return_B=False)
+    torch.cuda.synchronize()
+    assert B is None
+    rng = np.random.default_rng(12)
+    w = rng.integers(-M, M + 1, (300, 2))
+    w = w[np.abs(w[:, 0] - w[:, 1]) <= M]
+    w = np.concatenate([w, [[0, 0], [1, 2], [2, 1], [-1, 1], [M, M], [-M, 0], [5000, 4999]]])
+    ref = oracle.c3_at(x, w[:, 0], w[:, 1])
+    got = c3[torch.from_numpy(w[:, 0] + M).cuda(), torch.from_numpy(w[:, 1] + M).cuda()]
+    e = _rel(got.cpu().numpy(), ref)
+    print("sampled rel err c3 %.3e" % e)
+    assert e < TOL[path]
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_max_dft(path):
+    """N = 4096, the largest DFT, at M = 2048 (n = 8000): c3 at sampled lags
+    against the oracle, and the spectrum's symmetries B(k1, k2) = B(k2, k1)
+    = conj B(-k1, -k2) (mod N) at sampled points, which hold for the
+    windowed c3 at any size."""
+    hos = _hos()
+    M, n, N = 2048, 8000, 4096
+    x = synth.iid_exp_centered(n, 92).astype(np.float32)
+    t = torch.from_numpy(x).cuda()
+    print("case: max dft n=%d M=%d N=%d path=%s" % (n, M, N, path), flush=True)
+    c3, B = hos.bispectrum(t, M, nfft=N, path=path)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(13)
+    w = rng.integers(-M, M + 1, (300, 2))
+    w = w[np.abs(w[:, 0] - w[:, 1]) <= M]
+    w = np.concatenate([w, [[0, 0], [M, M], [-M, 0]]])
+    ref = oracle.c3_at(x, w[:, 0], w[:, 1])
+    got = c3[torch.from_numpy(w[:, 0] + M).cuda(), torch.from_numpy(w[:, 1] + M).cuda()]
+    e = _rel(got.cpu().numpy(), ref)
+    print("sampled rel err c3 %.3e" % e)
+    assert e < TOL[path]
+    k = torch.from_numpy(rng.integers(0, N, (4000, 2))).cuda()
+    b = B[k[:, 0], k[:, 1]]
+    bt = B[k[:, 1], k[:, 0]]
+    bc = B[(-k[:, 0]) % N, (-k[:, 1]) % N].conj()
+    scale = float(B.abs().max())
+    s1 = float((b - bt).abs().max()) / scale
+    s2 = float((b - bc).abs().max()) / scale
+    print("symmetry %.3e %.3e" % (s1, s2))
+    assert s1 < 1e-12 and s2 < 1e-12

@@ -119,3 +119,39 @@ def test_workload_sampled(path):
                                    k[2] * lag[None, None, :, None] +
                                    k[3] * lag[None, None, None, :]) / N)
         assert abs(np.sum(cw * ph) - Q[k]) < 1e-9 * np.max(np.abs(Q))
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_max_lag_and_dft(path):
+    """M = 40 and N = 96, the largest lag and DFT of order five (n = 3000):
+    c5 at sampled lags against the oracle's sums (error against the fifth
+    absolute moment, as above), and the spectrum's symmetries: Q is
+    Hermitian and invariant under permutations of (k1..k4), at sampled
+    points."""
+    hos = _hos()
+    M, N, n = 40, 96, 3000
+    x = synth.quartic_process(n, 93).astype(np.float32)
+    t = torch.from_numpy(x).cuda()
+    print("case: order five max n=%d M=%d N=%d path=%s" % (n, M, N, path), flush=True)
+    c5, Q = hos.cumulant5(t, M, nfft=N, path=path)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(14)
+    w = rng.integers(-M, M + 1, (400, 4))
+    lo = np.minimum(0, w.min(1)); hi = np.maximum(0, w.max(1))
+    w = w[hi - lo <= M]
+    w = np.concatenate([w, [[0, 0, 0, 0], [1, 2, 3, 4], [M, M, 0, M]]])
+    ref = oracle.c5_at(x, w[:, 0], w[:, 1], w[:, 2], w[:, 3])
+    idx = [torch.from_numpy(w[:, j] + M).cuda() for j in range(4)]
+    got = c5[idx[0], idx[1], idx[2], idx[3]].cpu().numpy()
+    e = float(np.max(np.abs(got - ref))) / _scale(x)
+    print("sampled err c5 %.3e" % e)
+    assert e < TOL[path]
+    k = torch.from_numpy(rng.integers(0, N, (4000, 4))).cuda()
+    q = Q[k[:, 0], k[:, 1], k[:, 2], k[:, 3]]
+    qp = Q[k[:, 2], k[:, 0], k[:, 3], k[:, 1]]
+    qc = Q[(-k[:, 0]) % N, (-k[:, 1]) % N, (-k[:, 2]) % N, (-k[:, 3]) % N].conj()
+    scale = float(Q.abs().max())
+    s1 = float((q - qp).abs().max()) / scale
+    s2 = float((q - qc).abs().max()) / scale
+    print("symmetry %.3e %.3e" % (s1, s2))
+    assert s1 < 1e-12 and s2 < 1e-12

@@ -90,6 +90,7 @@ def _pd_big(P):
     (8192, 8192, 21),          # two-pass part DFT (64 x 128), one part
     (12000, 6000, 100),        # two-pass DFT with part sums (K = 2)
     (4096, 4096, 1500),        # 2048-wide strips, 549 output columns each
+    (16384, 16384, 2048),      # the largest box: 2048-wide strips of one output column
 ])
 def test_sampled_grids(n, P, M3):
     x = synth.iid_exp_centered(n, 7).astype(np.float32)
