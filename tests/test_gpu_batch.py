@@ -276,3 +276,28 @@ def test_batch_separable_window():
         _, B_ref = oracle.bispectrum(xs[s], Ms, N, window="separable")
         k1, k2 = oracle.pd_indices(N)
         assert _rel(B[pdo:pdo + npd], B_ref[k1, k2]) < 1e-6, s
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_max_lag_in_batch(path):
+    """M = 1024 (N = 2048, the largest DFT of a batch) beside two small
+    series: c3 and the principal-domain spectrum of every series against
+    the oracle."""
+    hos = _hos()
+    n = [4000, 1500, 2100]
+    M = [1024, 32, 7]
+    xs = [synth.iid_exp_centered(k, 60 + i).astype(np.float32) for i, k in enumerate(n)]
+    plan = hos.BatchPlan(n, M, path=path)
+    print("case: batch with M=1024, path %s" % path, flush=True)
+    c3, B = hos.bispectrum_batched(torch.from_numpy(np.concatenate(xs)).cuda(), plan)
+    torch.cuda.synchronize()
+    c3, B = c3.cpu().numpy(), B.cpu().numpy()
+    S = plan.series()
+    for s in range(len(n)):
+        Ms, N, npd, c3o, pdo = int(S[s, 1]), int(S[s, 2]), int(S[s, 3]), int(S[s, 5]), int(S[s, 6])
+        c_ref, B_ref = oracle.bispectrum(xs[s], Ms, N)
+        k1, k2 = oracle.pd_indices(N)
+        got_c = c3[c3o:c3o + (2 * Ms + 1) ** 2].reshape(2 * Ms + 1, 2 * Ms + 1)
+        e1, e2 = _rel(got_c, c_ref), _rel(B[pdo:pdo + npd], B_ref[k1, k2])
+        print("series %d n=%d M=%d N=%d: c3 %.3e B_pd %.3e" % (s, n[s], Ms, N, e1, e2))
+        assert e1 < TOL[path] and e2 < TOL[path], (s, e1, e2)

@@ -206,3 +206,38 @@ def test_separable_window(path):
     e = _err(T, T_ref, np.max(np.abs(T_ref)))
     print("separable T rel err %.3e" % e)
     assert e < TOL[path] and _err(c4, c_ref, _m4_origin(x)) < TOL[path]
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_max_dft(path):
+    """N = 512, the largest trispectrum DFT (2.1 GB), at M = 127 (n = 900):
+    c4 at sampled lags against the oracle's sums, and the spectrum's
+    symmetries -- Hermitian, and invariant under permutations of
+    (k1, k2, k3) -- at sampled points."""
+    hos = _hos()
+    M, N, n = 127, 512, 900
+    x = synth.cubic_process(n, 94).astype(np.float32)
+    t = torch.from_numpy(x).cuda()
+    print("case: trispectrum max dft n=%d M=%d N=%d path=%s" % (n, M, N, path), flush=True)
+    c4, T = hos.trispectrum(t, M, nfft=N, path=path)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(15)
+    w = rng.integers(-M, M + 1, (400, 3))
+    lo = np.minimum(0, w.min(1)); hi = np.maximum(0, w.max(1))
+    w = w[hi - lo <= M]
+    w = np.concatenate([w, [[0, 0, 0], [1, 2, 3], [M, M, 0]]])
+    ref = oracle.c4_at(x, w[:, 0], w[:, 1], w[:, 2])
+    idx = [torch.from_numpy(w[:, j] + M).cuda() for j in range(3)]
+    got = c4[idx[0], idx[1], idx[2]].cpu().numpy()
+    e = _err(got, ref, _m4_origin(x))
+    print("sampled err c4 %.3e" % e)
+    assert e < TOL[path]
+    k = torch.from_numpy(rng.integers(0, N, (4000, 3))).cuda()
+    q = T[k[:, 0], k[:, 1], k[:, 2]]
+    qp = T[k[:, 2], k[:, 0], k[:, 1]]
+    qc = T[(-k[:, 0]) % N, (-k[:, 1]) % N, (-k[:, 2]) % N].conj()
+    scale = float(T.abs().max())
+    s1 = float((q - qp).abs().max()) / scale
+    s2 = float((q - qc).abs().max()) / scale
+    print("symmetry %.3e %.3e" % (s1, s2))
+    assert s1 < 1e-12 and s2 < 1e-12
