@@ -470,8 +470,46 @@ __device__ __forceinline__ void box_run(const double2 *__restrict__ F,
             ++r;
         }
     };
+    // While the box fills, nothing is emitted and the rows only enter, so
+    // the first P0 rows are summed per widened column without scans, in v
+    // (zero and unused until then; v[m] holds column e0 + m meanwhile); at
+    // the first later step one scan of those sums puts their window sums
+    // into v, which is what the per-row scans would have added (window sums
+    // are linear; only the order of the FP64 additions differs).
+    const int P0 = ((M3 - 1) / RPS) * RPS;
+    bool primed = P0 == 0;
     // Row steps st .. st + RPS - 1 from their difference rows.
     auto stepn = [&](double2 (&d)[RPS][CPT], int st) {
+        if (st + RPS <= P0) {
+#pragma unroll
+            for (int k = 0; k < RPS; ++k)
+#pragma unroll
+                for (int m = 0; m < CPT; ++m)
+                    v[m] = cadd(v[m], d[k][m]);
+            return;
+        }
+        if (!primed) {
+            double2 Vp[CPT], xp;
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                Vp[m] = v[m];
+                v[m] = make_double2(0.0, 0.0);
+            }
+            scan1(Vp, wtot[0], xp);
+            lds_barrier();
+            scan2(Vp, wtot[0], xp, lrow[0]);
+            lds_barrier();
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const int j = t + NT * k;
+                if (j < TW) {
+                    const double2 top = lrow[0][sw(j + M3 - 1)];
+                    const double2 bot = j > 0 ? lrow[0][sw(j - 1)] : make_double2(0.0, 0.0);
+                    v[k] = cadd(v[k], csub(top, bot));
+                }
+            }
+            primed = true;
+        }
         double2 x[RPS];
 #pragma unroll
         for (int k = 0; k < RPS; ++k)
