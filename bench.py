@@ -739,8 +739,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the contraction would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the library has no multi-GPU "
+              "path", file=sys.stderr)
         sys.exit(2)
     if "OMP_NUM_THREADS" not in os.environ:
         os.environ["OMP_NUM_THREADS"] = str(len(os.sched_getaffinity(0)))

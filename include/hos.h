@@ -37,7 +37,7 @@
  *            B: nfft x nfft interleaved complex128, row-major, frequency
  *            (k1,k2) at k1*nfft + k2, unshifted.
  *            B(k1,k2) = sum_w W(w) c3(w) exp(-2 pi i (k1 w1 + k2 w2)/nfft),
- *            unnormalised, with the sign of the DFT in Algorithm DBS step 3.
+ *            unnormalised, with the sign of the DFT in Algorithm DBS's part DFT.
  *            c4: (2M+1)^3 row-major float64, lag (t1,t2,t3) at
  *            ((t1+M)*(2M+1) + (t2+M))*(2M+1) + (t3+M); lags whose span
  *            max(0,t1,t2,t3) - min(0,t1,t2,t3) exceeds M are 0.
@@ -68,14 +68,14 @@ typedef enum hos_status {
     HOS_EWORKSPACE = -2,   /* ws_bytes is smaller than the workspace query   */
     HOS_EDEVICE = -3,      /* a HIP call or kernel launch failed              */
     HOS_ENODEVICE = -4,    /* no usable gfx950 device is visible              */
-    HOS_EUNSUPPORTED = -5  /* valid request this build does not implement     */
+    HOS_EUNSUPPORTED = -5  /* valid request the library does not implement   */
 } hos_status;
 
 /* Element type of the input series. */
 typedef enum hos_dtype { HOS_F32 = 0, HOS_F64 = 1 } hos_dtype;
 
 /* Lag window applied before the DFT.  The paper smooths in frequency with
- * an M3 x M3 box (Algorithm DBS step 5); this library smooths in the lag
+ * an M3 x M3 box (Algorithm DBS's box smoothing); this library smooths in the lag
  * domain instead.  HOS_WIN_PARZEN uses the Parzen window d(m) with scale
  * L = M: W3(w1,w2) = d(w1) d(w2) d(w1-w2) for the bispectrum and the
  * product of d over the six pairwise differences of {0,t1,t2,t3} for the
@@ -314,7 +314,7 @@ int hos_c5_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  *
  * Outputs are packed in series order: c3 of series s (its (2M+1)^2 block,
  * layout as above) starts at element sum_{t<s} (2M[t]+1)^2; B on the
- * principal domain 0 <= k2 <= k1, k1+k2 < N/2 (Algorithm DBS step 4, here on
+ * principal domain 0 <= k2 <= k1, k1+k2 < N/2 (Algorithm DBS's raw bispectrum, here on
  * the N grid), in row-major (k1, then k2) order, starts at complex element
  * sum_{t<s} npd(N[t]).  hos_batch_series reports every offset.
  * ------------------------------------------------------------------------
@@ -402,7 +402,7 @@ int hos_bispectrum_loss_bwd(const void *x, int32_t dtype, const void *plan_host,
                             hipStream_t stream);
 
 /*
- * Segment averaging (Algorithm DBS steps 1, 2 and 6 around the cumulant):
+ * Segment averaging (Algorithm DBS's split into parts, per-part mean removal and average over parts, around the cumulant):
  * the series of a batch plan are the segments of one record, each centred on
  * its own mean; their third cumulants are averaged,
  *   c3(w) = (1/S) sum_s c3_s(w),
@@ -427,14 +427,14 @@ int hos_bispectrum_segments(const void *x, int32_t dtype, const void *plan_host,
  * The first K = floor(n / P) * P samples are cut into K parts of P samples
  * (trailing samples are not used).  Each part loses its own mean (FP64;
  * kept with HOS_NO_CENTER) and gets a P-point DFT
- *     F_i(k) = sum_u x_i(u) exp(-2 pi i u k / P)                  (step 3).
+ *     F_i(k) = sum_u x_i(u) exp(-2 pi i u k / P).
  * The raw bispectrum of a part is F_i(k1) F_i(k2) conj F_i(k1 + k2) / P
- * (step 4, indices modulo P; the conjugate on the third factor is what
+ * (indices modulo P; the conjugate on the third factor is what
  * makes the estimate agree with the Fourier transform of the third
  * moment).  It is averaged over the M3 x M3 box of offsets
  * n1, n2 in [-floor(M3/2), M3 - 1 - floor(M3/2)] around each point, indices
- * modulo P (step 5; for even M3 this is the printed range -M3/2 .. M3/2-1),
- * and over the K parts (step 6).  Every value is computed in FP64.
+ * modulo P (for even M3 this is the printed range -M3/2 .. M3/2-1), and
+ * over the K parts.  Every value is computed in FP64.
  *
  * Output: the principal domain 0 <= k2 <= k1, k1 + k2 < P/2 of the P grid,
  * row-major in (k1, k2) -- row k1 (0 <= k1 <= H = floor((P-1)/2)) holds

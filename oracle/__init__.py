@@ -7,7 +7,7 @@ the product path never calls into it.
 
 What it computes, and the passages it follows (arXiv:1805.11775):
 
-* mean removal -- Section 1, Algorithm DBS step 2 (subtract the mean of a
+* mean removal -- Section 1, Algorithm DBS's per-part mean removal (subtract the mean of a
   part), with the whole record as one part (Section 4.1 uses K = 1);
 * the third and fourth sample cumulants -- Section 1 "Problem Statement"
   (moments of order k, cumulants as functions of moments, time averages in
@@ -15,9 +15,9 @@ What it computes, and the passages it follows (arXiv:1805.11775):
   ``hos_oracle.c``;
 * the spectra as Fourier transforms of the cumulants -- Section 1 (the
   bispectrum transforms the third cumulant, the trispectrum the fourth),
-  with the DFT sign of Algorithm DBS step 3 (exp(-j 2 pi u k / M),
+  with the DFT sign of Algorithm DBS's part DFT (exp(-j 2 pi u k / M),
   unnormalised);
-* the principal domain 0 <= k2 <= k1, k1 + k2 < N/2 -- Algorithm DBS step 4.
+* the principal domain 0 <= k2 <= k1, k1 + k2 < N/2 -- Algorithm DBS's raw bispectrum.
 
 Where the paper is silent (normalisation 1/n, lag-window shape, output
 region, loss), each function below states the reading it uses.
@@ -89,7 +89,7 @@ def _f64(x):
 
 
 # --------------------------------------------------------------------------
-# Step 1: mean removal (Algorithm DBS step 2 with one part, K = 1).
+# Stage 1: mean removal (Algorithm DBS's per-part mean removal with one part, K = 1).
 # --------------------------------------------------------------------------
 def center(x) -> np.ndarray:
     """x - mean(x) in FP64 (input widened exactly from float32 if needed)."""
@@ -104,7 +104,7 @@ def _prep(x, centered: bool) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# Step 2: sample cumulants (Section 1, Problem Statement), brute force.
+# Stage 2: sample cumulants (Section 1, Problem Statement), brute force.
 # --------------------------------------------------------------------------
 def c3_at(x, w1, w2, centered: bool = True) -> np.ndarray:
     """c3(w1[k], w2[k]) = (1/n) sum_t x_t x_{t+w1} x_{t+w2}, any lags."""
@@ -251,7 +251,7 @@ def c5_support(x, M: int, centered: bool = True) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# Step 3: lag window (the paper smooths in frequency with a box; the
+# Stage 3: lag window (the paper smooths in frequency with a box; the
 # workloads use the Parzen lag window instead -- a reading).
 # --------------------------------------------------------------------------
 def parzen(m, L: int) -> np.ndarray:
@@ -310,8 +310,8 @@ def window5(M: int, kind: str = "parzen") -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# Step 4: the DFT (Section 1: spectra are Fourier transforms of cumulants;
-# sign and normalisation of Algorithm DBS step 3).
+# Stage 4: the DFT (Section 1: spectra are Fourier transforms of cumulants;
+# sign and normalisation of Algorithm DBS's part DFT).
 # --------------------------------------------------------------------------
 def place_circular(c: np.ndarray, M: int, N: int) -> np.ndarray:
     """Fold a lag-domain array on [-M, M]^d onto the N^d DFT grid: the value
@@ -357,11 +357,12 @@ def trispectrum(x, M: int, nfft: int, window: str = "parzen",
 
 def bispectrum_segments(x, P: int, M: int, nfft: int, window: str = "parzen",
                         centered: bool = True):
-    """Segment averaging for the indirect estimator: Algorithm DBS steps 1,
-    2 and 6 around the cumulant.  K = floor(n / P) segments of P consecutive
-    samples (trailing samples unused), each centred on its own mean (step 2),
-    the third cumulant of each (the single-series estimator above, with the
-    segment as the record), their average over the segments (step 6), then
+    """Segment averaging for the indirect estimator: Algorithm DBS's split
+    into parts, per-part mean removal and average over parts, around the
+    cumulant.  K = floor(n / P) segments of P consecutive samples (trailing
+    samples unused), each centred on its own mean, the third cumulant of
+    each (the single-series estimator above, with the segment as the
+    record), their average over the segments, then
     the window and the DFT as in ``bispectrum``.  Returns (c3, B)."""
     x = _f64(x)
     K = x.size // P
@@ -374,7 +375,7 @@ def bispectrum_segments(x, P: int, M: int, nfft: int, window: str = "parzen",
 
 
 # --------------------------------------------------------------------------
-# Principal domain (Algorithm DBS step 4) and the matching loss.
+# Principal domain (Algorithm DBS's raw bispectrum) and the matching loss.
 # --------------------------------------------------------------------------
 def pd_indices(N: int):
     """(k1, k2) of the principal domain 0 <= k2 <= k1, k1 + k2 < N/2,
@@ -453,11 +454,11 @@ def loss_grad_at(x, M: int, nfft: int, target_pd, idx, window: str = "parzen") -
 # The paper's direct method (Algorithm DBS), in its own step order.
 # Readings: K = floor(n / P) parts of P samples (trailing samples unused);
 # the raw bispectrum uses F(k1) F(k2) conj(F(k1+k2)) / P (the conjugate the
-# printed step 4 lacks); the M3 x M3 box takes exactly M3 offsets per axis,
+# printed raw bispectrum lacks); the M3 x M3 box takes exactly M3 offsets per axis,
 # n in [-floor(M3/2), M3 - 1 - floor(M3/2)], indices modulo P.
 # --------------------------------------------------------------------------
 def dbs_raw(part) -> np.ndarray:
-    """Steps 2-4 for one part: mean removed, P-point DFT, and the raw
+    """Algorithm DBS for one part: mean removed, P-point DFT, and the raw
     bispectrum C(k1, k2) = F(k1) F(k2) conj(F(k1 + k2)) / P on the whole
     P x P grid (indices modulo P)."""
     xp = _f64(part)
@@ -469,7 +470,7 @@ def dbs_raw(part) -> np.ndarray:
 
 
 def dbs_smooth(C, M3: int) -> np.ndarray:
-    """Step 5: average of C over the M3 x M3 box of offsets around each
+    """Algorithm DBS's box smoothing: average of C over the M3 x M3 box of offsets around each
     point, indices modulo the grid size (written as the double sum)."""
     lo = M3 // 2
     out = np.zeros_like(C)

@@ -7,7 +7,7 @@
 namespace hos {
 
 // Parzen lag window d(m) with scale L (the lag-window reading of the
-// smoothing step, Algorithm DBS step 5): 1 - 6r^2 + 6r^3 for r = |m|/L <=
+// smoothing step, Algorithm DBS's box smoothing): 1 - 6r^2 + 6r^3 for r = |m|/L <=
 // 1/2, 2(1 - r)^3 for 1/2 < r <= 1, 0 beyond.  At L = 0 it is its L -> 0+
 // limit: 1 at m = 0, 0 elsewhere.
 __device__ inline double parzen_d(int m, int L)

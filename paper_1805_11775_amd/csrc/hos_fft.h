@@ -2,7 +2,7 @@
 // kernels: small forward DFTs in registers, one self-sorting (Stockham)
 // mixed-radix 4/2/3/5 stage over sequences held in LDS, and the radix plan.
 //
-// Transforms are unnormalised with the sign of Algorithm DBS step 3,
+// Transforms are unnormalised with the sign of Algorithm DBS's part DFT,
 //     X(k) = sum_u x(u) exp(-2 pi i u k / N),
 // and take their twiddles from a table of the N roots of unity.
 #pragma once

@@ -3,7 +3,7 @@
 // terms from the series instead of storing anything of the forward pass.
 //
 // Loss: L = sum_k |B(k) - T(k)|^2 over the principal domain, B the windowed
-// DFT of c3 (Algorithm DBS steps 3-4 for the sign and the domain).  With
+// DFT of c3 (the part DFT and raw bispectrum of Algorithm DBS for the sign and the domain).  With
 // R = B - T, the weight of each lag is
 //     G(w) = dL/dc3(w) = 2 W3(w) Re sum_k R_k e^{+2 pi i <k,w>/N},
 // obtained as the real part of a forward DFT of conj(2 R) placed on the

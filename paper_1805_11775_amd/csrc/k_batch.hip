@@ -1,7 +1,7 @@
 // k_batch.hip -- per-series finishing of a batch: the c3 output, the
 // principal-domain spectra (k_fft.hip) and the bispectrum-matching loss.
 //
-// Principal domain (Algorithm DBS step 4, on the N grid): 0 <= k2 <= k1 and
+// Principal domain (Algorithm DBS's raw bispectrum, on the N grid): 0 <= k2 <= k1 and
 // k1 + k2 < N/2, i.e. k1 + k2 <= H = floor((N-1)/2).  Its points are stored
 // in row-major order (k1, then k2): row k1 holds min(k1, H - k1) + 1 points.
 #include "hos_internal.h"

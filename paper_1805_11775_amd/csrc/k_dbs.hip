@@ -1,10 +1,10 @@
 // k_dbs.hip -- the direct bispectrum method (Algorithm DBS) with the
 // window-sum smoothing of Section 3 (Algorithm WS and its 2-D form).
 //
-// Steps 1-3: the series is cut into K parts of P samples (trailing samples
-// unused), each part loses its own FP64 mean and gets a P-point DFT F_i.
-// Step 4's raw bispectrum F_i(k1) F_i(k2) conj F_i(k1 + k2) / P, step 5's
-// M3 x M3 box average and step 6's average over parts are all linear, so
+// The series is cut into K parts of P samples (trailing samples unused),
+// each part loses its own FP64 mean and gets a P-point DFT F_i.  The raw
+// bispectrum F_i(k1) F_i(k2) conj F_i(k1 + k2) / P, the M3 x M3 box average
+// and the average over parts are all linear, so
 // the parts are summed first and the sum is smoothed once:
 //     B(k1, k2) = 1 / (K P M3^2) sum_{q, c in box} sum_i F_i(q) F_i(c) conj F_i(q + c),
 // the box being q in [k1 - lo, k1 + hi], c in [k2 - lo, k2 + hi],
@@ -60,7 +60,7 @@ __device__ inline int64_t pd_row_off(int r, int H)
     return tri(m + 1) + tri(H - m) - tri((int64_t)H + 1 - r);
 }
 
-// Step 2: partial sums of each part, MEAN_SPAN samples per workgroup.
+// Per-part mean removal: partial sums of each part, MEAN_SPAN samples per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_dbs_psum(const T *__restrict__ x, int P, int bpp, double *__restrict__ psum)
@@ -98,7 +98,7 @@ __device__ inline double part_mean(const double *__restrict__ psum, int64_t part
     return s / (double)P;
 }
 
-// Step 3, P <= DBS_LDS_FFT: CB whole parts per workgroup in LDS.
+// Part DFT, P <= DBS_LDS_FFT: CB whole parts per workgroup in LDS.
 template <typename T>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_dbs_fft1(const T *__restrict__ x, const double *__restrict__ psum, int bpp, int64_t K,
@@ -127,7 +127,7 @@ k_dbs_fft1(const T *__restrict__ x, const double *__restrict__ psum, int bpp, in
     }
 }
 
-// Step 3, P = P1 * P2 > DBS_LDS_FFT, first pass: with u = P2 n1 + n2 and
+// Part DFT, P = P1 * P2 > DBS_LDS_FFT, first pass: with u = P2 n1 + n2 and
 // k = k1 + P1 k2, the length-P1 DFTs over n1 for every n2, each output
 // multiplied by exp(-2 pi i n2 k1 / P), stored at [k1][n2].
 template <typename T>

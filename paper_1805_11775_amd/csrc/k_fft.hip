@@ -1,7 +1,7 @@
 // k_fft.hip -- FP64 complex DFTs of the windowed cumulants.
 //
 // The spectrum is the Fourier transform of the cumulant (Section 1), taken
-// as an unnormalised DFT with the sign of Algorithm DBS step 3,
+// as an unnormalised DFT with the sign of Algorithm DBS's part DFT,
 //     X(k) = sum_u x(u) exp(-2 pi i u k / N).
 // Multi-dimensional transforms are done one axis at a time in place.  Each
 // workgroup loads CB whole sequences into LDS, runs a self-sorting

@@ -9,7 +9,7 @@
 // span a > M are outside the hexagon and set to 0.
 //
 // The lag window replaces the paper's frequency-domain box smoothing
-// (Algorithm DBS step 5): W3(w1,w2) = d(w1) d(w2) d(w1-w2) with the Parzen
+// (Algorithm DBS's box smoothing): W3(w1,w2) = d(w1) d(w2) d(w1-w2) with the Parzen
 // d and scale L = M.  The windowed cumulant is folded onto the N x N DFT
 // grid (index w mod N; aliased lags add), which makes the grid DFT equal
 // to sum_w W3(w) c3(w) exp(-2 pi i <k,w>/N) exactly; the fold happens inside

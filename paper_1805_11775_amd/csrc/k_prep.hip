@@ -1,7 +1,7 @@
 // k_prep.hip -- mean removal and operand preparation (FP64 on the way in).
 //
-// Step 1 of the estimator is the mean removal of Algorithm DBS step 2, with
-// the whole record as the one part (Section 4.1 uses K = 1).  The mean is a
+// The estimator starts with Algorithm DBS's per-part mean removal, with the
+// whole record as the one part (Section 4.1 uses K = 1).  The mean is a
 // fixed-order FP64 reduction.  The centred series is then multiplied by an
 // exact power of two s that puts max|x~ s| in [2^(top-1), 2^top): [64, 128)
 // for the third order and [16, 32) for the fourth, which keeps every FP16

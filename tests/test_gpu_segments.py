@@ -1,5 +1,5 @@
-"""GPU parity of segment averaging (Algorithm DBS steps 1, 2 and 6 around
-the cumulant) against the FP64 oracle.  Bars as for one series: normwise
+"""GPU parity of segment averaging (Algorithm DBS's split into parts, per-part mean removal and
+average over parts, around the cumulant) against the FP64 oracle.  Bars as for one series: normwise
 1e-6 (FP32 path) and 1e-5 (split paths) for c3 over the hexagon and for B
 over the grid."""
 import numpy as np

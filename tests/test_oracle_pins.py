@@ -132,8 +132,9 @@ def test_c3_all_lag_sum_is_cube_of_sum():
 @pytest.mark.parametrize("N", [19, 24, 7])
 def test_direct_equals_indirect_bispectrum(N):
     """No window and M = n-1: the lag-domain DFT equals (1/n) X(k1) X(k2)
-    X*(k1+k2) with X the N-point FFT of the centred record -- Algorithm DBS
-    step 4 with one part and the conjugate on the third factor.  N = 7 checks
+    X*(k1+k2) with X the N-point FFT of the centred record -- the raw
+    bispectrum of Algorithm DBS with one part and the conjugate on the third
+    factor.  N = 7 checks
     the folding of aliased lags."""
     x = synth.iid_exp_centered(10, 21)
     n = x.size
