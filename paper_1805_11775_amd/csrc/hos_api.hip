@@ -27,7 +27,8 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     p.TS = 32 * p.NB;
     p.NBR = (M + 31) / 32;
     p.nleft = 1 + M / 32;
-    const int64_t C = (n + KC - 1) / KC;
+    const int64_t KCX = c3_stage_len(path, p.NB);   // samples per chunk
+    const int64_t C = (n + KCX - 1) / KCX;
     SkGeom &g = p.sk;
     g.TR = p.NBR > 0 ? (p.NBR + p.NB - 1) / p.NB : 0;
     // a tile's time is set by its busiest wave: a strip of NB blocks on every
@@ -44,7 +45,7 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
         G = 1;
     g.G = (int32_t)G;
     p.smax = g.TR > 0 ? sk_max_segments(g) : 0;
-    p.npad = ((C * KC + (int64_t)g.TR * p.TS + 64) + 63) / 64 * 64;
+    p.npad = ((C * KCX + (int64_t)g.TR * p.TS + 64) + 63) / 64 * 64;
     // leftover diagonal sums: one pass over x in 1024-sample blocks
     // (k_diag_fused) when nleft <= 32, else nleft x 64 strided blocks
     if (p.nleft <= 32) {

@@ -301,6 +301,14 @@ hipError_t launch_dbs(const void *x, int dtype, uint32_t flags, const DbsPlan &p
 
 // Element count of one FP64 partial tile.
 inline int64_t tile_elems(int NB) { return (int64_t)(32 * NB) * (32 * NB); }
+// Samples of one stream-K chunk of the single-series contraction: two KC
+// sub-chunks per staged chunk on the split paths with 4-block tiles, one
+// elsewhere (the FP32 path stages through registers; 2-block tiles keep two
+// workgroups per CU within the LDS).
+__host__ __device__ constexpr int c3_stage_len(int path, int NB)
+{
+    return (path != HOS_PATH_FP32 && NB == 4) ? 2 * KC : KC;
+}
 
 // ---------------------------------------------------------------------------
 // Launchers (enqueue on `s`, return hipError_t of the last launch).

@@ -15,16 +15,20 @@
 //               (Yhi*Thi + Yhi*Tlo + Ylo*Thi).
 // Y is formed in registers from FP32 x (one multiply per element; the split
 // rounds the exact FMA residual), T comes pre-split from the window tables.
-// FP32 accumulators are flushed into FP64 registers after every chunk of
-// KC = 512 samples; a workgroup's FP64 partial tile goes to the workspace
-// and k_c3_reduce sums the partials of a tile in workgroup order.
+// FP32 accumulators are flushed into FP64 registers after every staged chunk
+// (KC = 512 samples; 2 KC on the split paths' 4-block tiles); a workgroup's
+// FP64 partial tile goes to the workspace and k_c3_reduce sums the partials
+// of a tile in workgroup order.
 //
 // Staging.  Per chunk a workgroup copies three contiguous runs of 16-byte
-// entries into LDS (prefetched into registers during the previous chunk's
-// compute, double-buffered, one barrier per chunk):
-//   s_xi  x_i, i in [i0, i0+KC)                       plain floats
-//   s_xa  win4 entries [i0+r0, i0+r0+KC+TS)           rows' x_{i+r+1}
-//   s_xb  win4 (FP32) or win8 hi|lo (split) entries [i0+b0, i0+b0+KC+TS)
+// entries into LDS (prefetched during the previous chunk's compute -- through
+// registers, or on the split paths straight into LDS -- double-buffered, one
+// barrier per chunk):
+//   s_xi  x_i, i in [i0, i0+L)                        plain floats
+//   s_xa  win4 entries [i0+r0, i0+r0+L+TS)            rows' x_{i+r+1}
+//   s_xb  win4 (FP32) or win8 hi|lo (split) entries [i0+b0, i0+b0+L+TS)
+// with L the chunk length; a chunk of 2 KC is computed as two KC sub-chunks
+// whose runs start KC entries apart.
 // Entry o of a window table holds the 4 floats / 8 halves starting at
 // sample o, so a lane's operand run x_{i+b .. i+b+7} is one (split) or two
 // (FP32) aligned ds_read_b128 whatever its start sample, and consecutive
@@ -392,13 +396,13 @@ __device__ __attribute__((always_inline)) inline void dispatch_compute(int ncol,
 }
 
 // One chunk's LDS operands (xi | xa | xb, contiguous 16-byte entries).
-template <int PATH, int NB>
+template <int PATH, int NB, int KCX = KC>
 struct ChunkLds {
     static constexpr bool SPLIT = PATH != HOS_PATH_FP32;
     static constexpr int NW = NB;                   // waves per workgroup
     static constexpr int TS = 32 * NB;
-    static constexpr int WLEN = KC + TS;            // window entries per chunk
-    static constexpr int NXI = KC / 4;              // float4 entries of x_i
+    static constexpr int WLEN = KCX + TS;           // window entries per chunk
+    static constexpr int NXI = KCX / 4;             // float4 entries of x_i
     static constexpr int NXB = SPLIT ? 2 * WLEN : WLEN;
     static constexpr int TOTAL = NXI + WLEN + NXB;  // 16-byte entries
     static constexpr int NCH = TOTAL / 64;          // 1 KB wave-chunks
@@ -449,6 +453,74 @@ load_chunk(u32x4 (&stg)[NPW], const float *__restrict__ xf, const uint4 *__restr
     }
 }
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// Split paths of the single-series kernel: the window regions go straight
+// from global memory into the LDS buffer (gfx950's 16-byte global_load_lds:
+// lane l writes entry l of the wave-chunk, the same layout store_chunk
+// writes), which frees the staging registers; only the x_i run, whose sign
+// depends on the chunk's parity, passes through registers.  The loads land in
+// the buffer the workgroup is not computing on; store_xi waits for them
+// before the barrier that hands the buffer over.
+template <int PATH, int NB, int KCX>
+struct XiRegs {
+    typedef ChunkLds<PATH, NB, KCX> CL;
+    static constexpr int N = (CL::NXI / 64 + CL::NW - 1) / CL::NW;
+    u32x4 r[N];
+};
+
+template <int PATH, int NB, int KCX>
+__device__ __attribute__((always_inline)) inline void
+load_chunk_dma(XiRegs<PATH, NB, KCX> &xr, const float *__restrict__ xf, const uint4 *__restrict__ win4,
+               const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l, const SkPos &p,
+               ChunkLds<PATH, NB, KCX> &L, int wave, int lane)
+{
+    typedef ChunkLds<PATH, NB, KCX> CL;
+    const int64_t i0 = p.c * KCX;
+    const int64_t ra0 = i0 + (int64_t)p.R * CL::TS, rb0 = i0 + (int64_t)p.Cc * CL::TS;
+    const u32x4 *xf4 = (const u32x4 *)xf;
+    const u32x4 *w4 = (const u32x4 *)win4, *w8h = (const u32x4 *)win8h,
+                *w8l = (const u32x4 *)win8l;
+    u32x4 *base = (u32x4 *)&L;
+#pragma unroll
+    for (int m = 0; m < CL::NPW; ++m) {
+        const int j = wave + CL::NW * m;
+        const int e = 64 * j;
+        if (j >= CL::NCH)
+            continue;
+        if (e < CL::NXI) {
+            if (m < XiRegs<PATH, NB, KCX>::N)
+                xr.r[m] = xf4[(i0 >> 2) + e + lane];
+            continue;
+        }
+        const u32x4 *src;
+        if (e < CL::NXI + CL::WLEN)
+            src = w4 + ra0 + (e - CL::NXI);
+        else {
+            const int e2 = e - CL::NXI - CL::WLEN;
+            src = e2 < CL::WLEN ? w8h + rb0 + e2 : w8l + rb0 + (e2 - CL::WLEN);
+        }
+        __builtin_amdgcn_global_load_lds((glb_void_t *)(src + lane), (lds_void_t *)(base + e), 16,
+                                         0, 0);
+    }
+}
+
+template <int PATH, int NB, int KCX>
+__device__ __attribute__((always_inline)) inline void
+store_xi(const XiRegs<PATH, NB, KCX> &xr, ChunkLds<PATH, NB, KCX> &L, int wave, int lane, bool neg)
+{
+    typedef ChunkLds<PATH, NB, KCX> CL;
+    u32x4 *base = (u32x4 *)&L;
+#pragma unroll
+    for (int m = 0; m < XiRegs<PATH, NB, KCX>::N; ++m) {
+        const int j = wave + CL::NW * m;
+        if (64 * j < CL::NXI)
+            base[64 * j + lane] = xr.r[m] ^ (neg ? 0x80000000u : 0u);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // neg: store the x_i run with its sign flipped (odd chunks).
 template <int PATH, int NB, int NPW>
 __device__ __attribute__((always_inline)) inline void
@@ -473,7 +545,12 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
               const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
               double *__restrict__ part, SkGeom g, int64_t smax, int NBR)
 {
-    typedef ChunkLds<PATH, NB> CL;
+    constexpr bool SPLIT = PATH != HOS_PATH_FP32;
+    // samples staged per barrier: split paths with 4-block tiles stage two
+    // KC-sample sub-chunks at once (116 KB of LDS), which halves the
+    // barriers, prologues and FP64 flushes per sample
+    constexpr int KCX = c3_stage_len(PATH, NB);
+    typedef ChunkLds<PATH, NB, KCX> CL;
     constexpr int64_t TILE = (int64_t)CL::TS * CL::TS;
 
     __shared__ CL buf[2];
@@ -516,21 +593,33 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
     set_layout(q);
 
     u32x4 stg[CL::NPW];
-    load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, q, wave, lane);
-    store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
+    XiRegs<PATH, NB, KCX> xr;
+    if constexpr (!SPLIT) {
+        load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, q, wave, lane);
+        store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
+    } else {
+        load_chunk_dma<PATH, NB, KCX>(xr, xf, win4, win8h, win8l, q, buf[0], wave, lane);
+        store_xi<PATH, NB, KCX>(xr, buf[0], wave, lane, q.c & 1);
+    }
     __syncthreads();
 
-    // Each step prefetches the next chunk into registers, computes on the
-    // current LDS buffer, flushes FP32 -> FP64, writes the partial tile at a
-    // segment end, then stores the prefetched chunk into the other buffer.
+    // Each step prefetches the next chunk (into registers, or for the split
+    // paths straight into the other LDS buffer), computes on the current
+    // buffer, flushes FP32 -> FP64, writes the partial tile at a segment end,
+    // then stores the prefetched chunk (the split paths: its x_i run).
     // One barrier per chunk: a buffer is rewritten only after every wave has
     // passed the barrier that follows its last use.
     int cur = 0;
     for (;;) {
         SkPos nq = q;
         const bool has_next = sk_next(g, nq) && sk_chunk_start(g, nq.R, nq.Cc, nq.c) < S1;
-        if (has_next)
-            load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, nq, wave, lane);
+        if (has_next) {
+            if constexpr (!SPLIT)
+                load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, nq, wave, lane);
+            else
+                load_chunk_dma<PATH, NB, KCX>(xr, xf, win4, win8h, win8l, nq, buf[cur ^ 1],
+                                              wave, lane);
+        }
 
         const float sgn = (q.c & 1) ? -1.0f : 1.0f;
         if constexpr (PATH == HOS_PATH_FP32) {
@@ -540,6 +629,9 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
         } else {
             dispatch_compute<PATH, NB>(ncol, buf[cur].xi, buf[cur].xa, buf[cur].xb, CL::WLEN,
                                        wave, rl, h, acc, acc64);
+            if constexpr (KCX == 2 * KC)   // the second sub-chunk: every run shifted by KC
+                dispatch_compute<PATH, NB>(ncol, buf[cur].xi + KC / 4, buf[cur].xa + KC,
+                                           buf[cur].xb + KC, CL::WLEN, wave, rl, h, acc, acc64);
         }
         if constexpr (PATH != HOS_PATH_FP32)   // the FP32 path flushes inside
             flush_acc<NB, true>(acc, acc64, sgn);
@@ -575,7 +667,10 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
         if (!has_next)
             break;
         cur ^= 1;
-        store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane, nq.c & 1);
+        if constexpr (!SPLIT)
+            store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane, nq.c & 1);
+        else
+            store_xi<PATH, NB, KCX>(xr, buf[cur], wave, lane, nq.c & 1);
         __syncthreads();
         if (seg_end)
             set_layout(nq);
