@@ -117,10 +117,11 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         d.NBR = (d.M + 31) / 32;
         d.TR = d.NBR > 0 ? (d.NBR + d.NB - 1) / d.NB : 0;
         d.nleft = 1 + d.M / 32;
-        d.C = (d.n + KC - 1) / KC;
+        const int64_t kcx = c3_stage_len(path, d.NB);   // samples per chunk
+        d.C = (d.n + kcx - 1) / kcx;
         d.KP = adj ? (int32_t)up(2 * d.M + 1, 32) : 0;
         d.lpad = adj ? up(d.M, 64) : 0;
-        int64_t npad = up(d.C * KC + (int64_t)d.TR * 32 * d.NB + 64, 64);
+        int64_t npad = up(d.C * kcx + (int64_t)d.TR * 32 * d.NB + 64, 64);
         if (adj)
             npad = std::max<int64_t>(npad, up(up(d.n, 256) + 256 + d.KP + 128, 64));
         d.npad = npad;

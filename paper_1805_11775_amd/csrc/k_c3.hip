@@ -874,7 +874,9 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
            const int32_t *__restrict__ wgfirst, const char *__restrict__ ws,
            double *__restrict__ part)
 {
-    typedef ChunkLds<PATH, NB> CL;
+    constexpr bool SPLIT = PATH != HOS_PATH_FP32;
+    constexpr int KCX = c3_stage_len(PATH, NB);   // as in k_c3_contract
+    typedef ChunkLds<PATH, NB, KCX> CL;
     constexpr int64_t TILE = (int64_t)CL::TS * CL::TS;
 
     __shared__ CL buf[2];
@@ -920,8 +922,14 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
     set_layout(q, sp.NBR);
 
     u32x4 stg[CL::NPW];
-    load_chunk<PATH, NB, CL::NPW>(stg, sp.xf, sp.w4, sp.w8h, sp.w8l, q, wave, lane);
-    store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
+    XiRegs<PATH, NB, KCX> xr;
+    if constexpr (!SPLIT) {
+        load_chunk<PATH, NB, CL::NPW>(stg, sp.xf, sp.w4, sp.w8h, sp.w8l, q, wave, lane);
+        store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
+    } else {
+        load_chunk_dma<PATH, NB, KCX>(xr, sp.xf, sp.w4, sp.w8h, sp.w8l, q, buf[0], wave, lane);
+        store_xi<PATH, NB, KCX>(xr, buf[0], wave, lane, q.c & 1);
+    }
     __syncthreads();
 
     int cur = 0;
@@ -943,8 +951,14 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
         } else {
             has_next = false;
         }
-        if (has_next)
-            load_chunk<PATH, NB, CL::NPW>(stg, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq, wave, lane);
+        if (has_next) {
+            if constexpr (!SPLIT)
+                load_chunk<PATH, NB, CL::NPW>(stg, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq, wave,
+                                              lane);
+            else
+                load_chunk_dma<PATH, NB, KCX>(xr, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq,
+                                              buf[cur ^ 1], wave, lane);
+        }
 
         const float sgn = (q.c & 1) ? -1.0f : 1.0f;
         if constexpr (PATH == HOS_PATH_FP32) {
@@ -953,6 +967,9 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
         } else {
             dispatch_compute<PATH, NB>(ncol, buf[cur].xi, buf[cur].xa, buf[cur].xb, CL::WLEN,
                                        wave, rl, h, acc, acc64);
+            if constexpr (KCX == 2 * KC)
+                dispatch_compute<PATH, NB>(ncol, buf[cur].xi + KC / 4, buf[cur].xa + KC,
+                                           buf[cur].xb + KC, CL::WLEN, wave, rl, h, acc, acc64);
         }
         if constexpr (PATH != HOS_PATH_FP32)
             flush_acc<NB, true>(acc, acc64, sgn);
@@ -986,7 +1003,10 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
         if (!has_next)
             break;
         cur ^= 1;
-        store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane, nq.c & 1);
+        if constexpr (!SPLIT)
+            store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane, nq.c & 1);
+        else
+            store_xi<PATH, NB, KCX>(xr, buf[cur], wave, lane, nq.c & 1);
         __syncthreads();
         if (new_item) {
             ++k;

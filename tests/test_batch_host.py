@@ -62,7 +62,9 @@ def test_items_cover_every_chunk_once(n, M, path):
                 continue
             nbr = (M[s] + 31) // 32
             tr = (nbr + NB - 1) // NB if nbr else 0
-            expect += tr * (tr + 1) // 2 * ((n[s] + 511) // 512)
+            # chunk length: 1024 samples on the split paths' 4-block tiles, else 512
+            L = 1024 if (cls == 1 and path != "fp32") else 512
+            expect += tr * (tr + 1) // 2 * ((n[s] + L - 1) // L)
         assert len(seen) == expect
         if slots:
             assert slots == set(range(len(slots)))
