@@ -55,10 +55,13 @@ def test_small_workload_exp_n2048_M64(path):
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("n,M", [(700, 0), (700, 1), (701, 5), (3001, 31), (3001, 32),
                                  (3001, 33), (4100, 95), (2500, 128), (3001, 160),
-                                 (1537, 200)])
+                                 (1537, 200), (700, 100), (1024, 96), (1025, 128),
+                                 (2048, 129)])
 def test_parity_grid(path, n, M):
-    """Ragged lengths (not multiples of the 512-sample chunk) and lags below,
-    at and above the 32-block and 128-tile boundaries."""
+    """Ragged lengths (not multiples of the 512-sample chunk, nor of the
+    1024-sample chunk that 4-block split tiles stage), a record shorter than
+    one such chunk, exact multiples, and lags below, at and above the
+    32-block and 128-tile boundaries."""
     x = synth.quadratic_process(n, 1000 + n + M).astype(np.float32)
     c3, B = _run(x, M, path=path)
     c3_ref, B_ref = oracle.bispectrum(x, M, B.shape[0])
