@@ -94,7 +94,8 @@ typedef enum hos_window {
  *                        FP16 products (hi*hi + hi*lo + lo*hi), FP32
  *                        accumulation;
  *   HOS_PATH_SPLIT_BF16  the same with BF16 halves.
- * FP32 partial sums are flushed into FP64 every 512 samples. */
+ * FP32 partial sums are flushed into FP64 every 512 samples (every 1024 in
+ * the third-order contraction's split paths for M >= 96). */
 typedef enum hos_path {
     HOS_PATH_FP32 = 0,
     HOS_PATH_SPLIT_FP16 = 1,

@@ -33,7 +33,7 @@ namespace hos {
 // cost range and writes one FP64 partial tile per tile it touches, so the
 // cross-workgroup reduction is a fixed-order sum (deterministic).
 // ---------------------------------------------------------------------------
-constexpr int KC = 512;           // samples per chunk; FP32 -> FP64 flush period
+constexpr int KC = 512;           // samples per (sub-)chunk; FP32 -> FP64 flush period
 constexpr int GROUP = 16;         // samples per matrix-core k-group
 constexpr int WG_THREADS = 256;   // 4 waves of 64
 
@@ -213,7 +213,7 @@ struct SeriesDesc {
     int64_t npad;         // table entries from sample 0 (zero beyond n)
     int64_t lpad;         // zero table entries before sample 0
     int32_t M, N, NB, NBR, TR, nleft, npd, group, KP, cls;
-    int64_t C;            // 512-sample chunks
+    int64_t C;            // chunks of c3_stage_len(path, NB) samples
     // byte offsets inside the series region; table offsets point at sample 0
     int64_t o_stats, o_mpart, o_xf, o_win4, o_win8h, o_win8l, o_cfull, o_dpart;
     int64_t o_gtil, o_k64, o_kh, o_kl;   // adjoint buffers (plans made for the adjoint)
