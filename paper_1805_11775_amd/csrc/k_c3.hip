@@ -1067,12 +1067,27 @@ k_bdiag(const T *__restrict__ x, const SeriesDesc *__restrict__ sd, char *__rest
     const T *xs = x + d.x_off;
     const int64_t n = d.n, a = 32 * (int64_t)left;
     const double mu = stats[0], sc = stats[1];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i + a < n; i += 256) {
-        const double u = ((double)xs[i + a] - mu) * sc;
-        s += (((double)xs[i] - mu) * sc) * u * u;
+    // four independent partial sums per thread (samples i, i+256, i+512,
+    // i+768 of each 1024-sample stride) so that the loads go out together;
+    // combined in a fixed order, then the fixed tree
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = threadIdx.x;
+    for (; i + 768 + a < n; i += 1024) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double u = ((double)xs[i + 256 * k + a] - mu) * sc;
+            s4[k] += (((double)xs[i + 256 * k] - mu) * sc) * u * u;
+        }
     }
-    red[threadIdx.x] = s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {   // the tail: at most three more samples
+        const int64_t j = i + 256 * k;
+        if (j + a < n) {
+            const double u = ((double)xs[j + a] - mu) * sc;
+            s4[k] += (((double)xs[j] - mu) * sc) * u * u;
+        }
+    }
+    red[threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w)
