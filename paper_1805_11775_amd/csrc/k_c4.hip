@@ -465,10 +465,25 @@ k_c2_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats, i
     __shared__ double red[256];
     const int d = blockIdx.x / nblocks, blk = blockIdx.x % nblocks;
     const double mu = stats[0], sc = stats[1];
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i + d < n; i += (int64_t)nblocks * 256)
-        acc += (((double)x[i] - mu) * sc) * (((double)x[i + d] - mu) * sc);
-    red[threadIdx.x] = acc;
+    // four independent partial sums per thread (so the loads go out
+    // together), combined in a fixed order
+    const int64_t stride = (int64_t)nblocks * 256;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = (int64_t)blk * 256 + threadIdx.x;
+    for (; i + 3 * stride + d < n; i += 4 * stride) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t j = i + k * stride;
+            a4[k] += (((double)x[j] - mu) * sc) * (((double)x[j + d] - mu) * sc);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t j = i + k * stride;
+        if (j + d < n)
+            a4[k] += (((double)x[j] - mu) * sc) * (((double)x[j + d] - mu) * sc);
+    }
+    red[threadIdx.x] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w)
@@ -488,6 +503,8 @@ k_c2_final(const double *__restrict__ dpart, int M, int nblocks, const double *_
     if (d > M)
         return;
     double s = 0.0;
+    // unrolled so the loads go out ahead; the adds keep their order
+#pragma unroll 8
     for (int k = 0; k < nblocks; ++k)
         s += dpart[d * nblocks + k];
     const double sc = stats[1];
