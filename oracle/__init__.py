@@ -135,8 +135,11 @@ def span3(M: int) -> np.ndarray:
 def c3_hexagon(x, M: int, centered: bool = True) -> np.ndarray:
     """c3 on the hexagon |w1|,|w2|,|w1-w2| <= M, zero on the two corners.
 
-    Output-region reading: the lags requested are |w| <= M; the corner lags
-    (|w1 - w2| > M) are set to 0 because the lag window vanishes there.
+    Output-region reading: the lags requested are |w| <= M; the hexagon is
+    the set of those lags whose whole six-fold symmetry orbit stays inside
+    the square, so an estimate over it keeps the symmetries of c3 (and B
+    those of the bispectrum).  The corner lags (|w1 - w2| > M) are outside
+    it and set to 0; the Parzen window W3 vanishes there in any case.
     """
     c = c3_square(x, M, centered)
     c[span3(M) > M] = 0.0
@@ -191,7 +194,9 @@ def span4(M: int) -> np.ndarray:
 
 
 def c4_support(x, M: int, centered: bool = True) -> np.ndarray:
-    """c4 on {span(0,t1,t2,t3) <= M}, zero elsewhere in the cube."""
+    """c4 on {span(0,t1,t2,t3) <= M}, zero elsewhere in the cube: the lags
+    of the cube whose whole 24-fold symmetry orbit stays inside the cube
+    (the hexagon's counterpart one order up)."""
     c = c4_cube(x, M, centered)
     c[span4(M) > M] = 0.0
     return c
@@ -325,13 +330,17 @@ def place_circular(c: np.ndarray, M: int, N: int) -> np.ndarray:
 
 
 def bispectrum(x, M: int, nfft: int, window: str = "parzen",
-               centered: bool = True):
-    """(c3 on the hexagon, B = 2D DFT of the windowed c3 on an N x N grid).
+               centered: bool = True, full_square: bool = False):
+    """(c3 over the lag region, B = 2D DFT of the windowed c3 on an N x N grid).
 
     B(k1,k2) = sum_w W3(w) c3(w) exp(-2 pi i (k1 w1 + k2 w2)/N), unshifted
-    frequency order, no normalisation.
+    frequency order, no normalisation.  The lag region is the hexagon (the
+    lags of the square whose whole six-fold orbit stays in the square, zero
+    on the two corners) or, with ``full_square``, every lag |w1|, |w2| <= M
+    (Section 1, Problem Statement: the sample cumulant at every lag up to
+    the maximum lag).
     """
-    c = c3_hexagon(x, M, centered)
+    c = c3_square(x, M, centered) if full_square else c3_hexagon(x, M, centered)
     cw = c * window3(M, window)
     B = np.fft.fft2(place_circular(cw, M, nfft))
     return c, B

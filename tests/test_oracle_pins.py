@@ -429,6 +429,133 @@ def test_separable_window_hand_values():
     assert oracle.window4(M, "parzen")[2 + M, -2 + M, 1 + M] == 0.0
 
 
+def test_window4_hand_values():
+    """W4 = product of d over the six pairwise differences of {0,t1,t2,t3}
+    against hand-worked products at M = 8 (tests/golden/window4_points.txt):
+    two lags whose six differences are non-zero and distinct, and six lags
+    that vanish through exactly one factor each."""
+    M = 8
+    W = oracle.window4(M)
+    for row in _load_gold("window4_points.txt"):
+        t = tuple(int(v) for v in row[:3])
+        t1, t2, t3 = t
+        diffs = (abs(t1), abs(t2), abs(t3), abs(t2 - t1), abs(t3 - t1), abs(t3 - t2))
+        assert diffs == tuple(int(v) for v in row[3:9]), t   # the fixture's own bookkeeping
+        expect = row[9] / row[10]
+        got = W[t1 + M, t2 + M, t3 + M]
+        assert got == expect, (t, got, expect)
+
+
+def test_window4_24_fold_symmetry_and_support():
+    """W4 takes one value on each orbit of the 24-fold lag symmetry (any of
+    the four offsets as origin, the other three in any order), and is zero
+    exactly where the span of {0,t1,t2,t3} reaches M."""
+    M = 6
+    W = oracle.window4(M)
+    f = lambda t: W[t[0] + M, t[1] + M, t[2] + M]
+    for t in itertools.product(range(-M, M + 1), repeat=3):
+        pts = (0,) + t
+        span = max(pts) - min(pts)
+        assert (f(t) == 0.0) == (span >= M), t
+        for origin in pts:
+            rest = list(pts)
+            rest.remove(origin)
+            for perm in itertools.permutations(rest):
+                img = tuple(p - origin for p in perm)
+                if max(abs(v) for v in img) <= M:
+                    assert abs(f(img) - f(t)) < 1e-15, (t, img)
+
+
+def test_c4_support_boundary():
+    """c4_support keeps every lag of span M (equal to the literal loops there,
+    and non-zero) and zeroes every lag of span M + 1 or more."""
+    M = 3
+    x = synth.cubic_process(40, 12)
+    xt = brute.center(list(x))
+    c = oracle.c4_support(x, M)
+    kept = 0
+    for t in itertools.product(range(-M, M + 1), repeat=3):
+        pts = (0,) + t
+        span = max(pts) - min(pts)
+        v = c[tuple(v + M for v in t)]
+        if span <= M:
+            ref = brute.c4(xt, *t)
+            assert abs(v - ref) < 1e-13, t
+            if span == M:
+                assert ref != 0.0
+                kept += 1
+        else:
+            assert v == 0.0, t
+    assert kept > 0
+
+
+def test_trispectrum_hermitian_and_permutation_symmetry():
+    """T from the oracle's own composition (c4 on its support, W4, 3-D DFT):
+    T(k) = conj T(-k), T is invariant under permutations of (k1, k2, k3) and
+    under k1 -> -k1-k2-k3 (the fourth frequency of the 24-fold symmetry)."""
+    M, N = 5, 10
+    x = synth.cubic_process(300, 13)
+    _, T = oracle.trispectrum(x, M, N)
+    k = np.arange(N)
+    K1, K2, K3 = np.meshgrid(k, k, k, indexing="ij")
+    tol = 1e-13 * np.abs(T).max()
+    np.testing.assert_allclose(T, np.conj(T[(-K1) % N, (-K2) % N, (-K3) % N]), atol=tol)
+    for perm in itertools.permutations(range(3)):
+        np.testing.assert_allclose(T, T.transpose(perm), atol=tol)
+    np.testing.assert_allclose(T, T[(-K1 - K2 - K3) % N, K2, K3], atol=tol)
+
+
+def test_trispectrum_matches_direct_lag_sum():
+    """At sampled frequencies T equals the direct sum over every lag of the
+    cube of W4 c4 e^{-2 pi i <k, t>/N}, with W4 and c4 formed here from the
+    literal loops and hand-expanded Parzen products (aliases included, N < 2M+1)."""
+    M, N = 3, 5
+    x = synth.cubic_process(60, 14)
+    xt = brute.center(list(x))
+    _, T = oracle.trispectrum(x, M, N)
+
+    def d(m):
+        r = abs(m) / M
+        return 1 - 6 * r * r + 6 * r ** 3 if r <= 0.5 else (2 * (1 - r) ** 3 if r <= 1 else 0.0)
+
+    lags = list(itertools.product(range(-M, M + 1), repeat=3))
+    vals = []
+    for t in lags:
+        t1, t2, t3 = t
+        w = d(t1) * d(t2) * d(t3) * d(t2 - t1) * d(t3 - t1) * d(t3 - t2)
+        vals.append(w * brute.c4(xt, *t) if w != 0.0 else 0.0)
+    for kk in [(0, 0, 0), (1, 2, 3), (4, 0, 2), (3, 3, 1)]:
+        s = sum(v * np.exp(-2j * np.pi * (kk[0] * t[0] + kk[1] * t[1] + kk[2] * t[2]) / N)
+                for v, t in zip(vals, lags))
+        assert abs(s - T[kk]) < 1e-12 * np.abs(T).max(), kk
+
+
+def test_bispectrum_full_square_region():
+    """With full_square the oracle returns c3 at every lag of the square
+    (the corners equal the literal loops) and transforms all of it: at no
+    window, B - B(hexagon) is the DFT of the corners alone, here checked at
+    one frequency against the corner lags summed one by one."""
+    n, M, N = 30, 5, 11
+    x = synth.quadratic_process(n, 15)
+    xt = brute.center(list(x))
+    c_sq, B_sq = oracle.bispectrum(x, M, N, window="none", full_square=True)
+    c_hx, B_hx = oracle.bispectrum(x, M, N, window="none")
+    corner = 0j
+    k1, k2 = 2, 7
+    for w1 in range(-M, M + 1):
+        for w2 in range(-M, M + 1):
+            v = brute.c3(xt, w1, w2)
+            assert abs(c_sq[w1 + M, w2 + M] - v) < 1e-14
+            if abs(w1 - w2) > M:
+                assert c_hx[w1 + M, w2 + M] == 0.0
+                corner += v * np.exp(-2j * np.pi * (k1 * w1 + k2 * w2) / N)
+    assert abs((B_sq - B_hx)[k1, k2] - corner) < 1e-13
+    # the Parzen window vanishes on the corners: both regions give one B
+    _, B1 = oracle.bispectrum(x, M, 2 * M, full_square=True)
+    _, B2 = oracle.bispectrum(x, M, 2 * M)
+    assert np.max(np.abs(B1 - B2)) < 1e-15 * np.max(np.abs(B2))
+
+
 # --------------------------------------------------------------------------
 # The direct method (Algorithm DBS)
 # --------------------------------------------------------------------------
