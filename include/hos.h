@@ -68,7 +68,9 @@ typedef enum hos_status {
     HOS_EWORKSPACE = -2,   /* ws_bytes is smaller than the workspace query   */
     HOS_EDEVICE = -3,      /* a HIP call or kernel launch failed              */
     HOS_ENODEVICE = -4,    /* no usable gfx950 device is visible              */
-    HOS_EUNSUPPORTED = -5  /* valid request the library does not implement   */
+    HOS_EUNSUPPORTED = -5, /* valid request the library does not implement   */
+    HOS_ESCRATCH = -6      /* the request needs more than the fixed scratch of
+                              hos_bispectrum_noalloc (HOS_NOALLOC_SCRATCH_BYTES) */
 } hos_status;
 
 /* Element type of the input series. */
@@ -164,6 +166,29 @@ int hos_bispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M,
                          int32_t window, int32_t nfft, int32_t path, uint32_t flags,
                          double *c3, double *B, void *ws, size_t ws_bytes,
                          hipStream_t stream, float *stage_ms);
+
+/*
+ * hos_bispectrum without a caller workspace and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Arguments and results as for hos_bispectrum.  The workspace is a device
+ * array of HOS_NOALLOC_SCRATCH_BYTES inside the library, one per device,
+ * held from the library's first use on that device until the process ends.
+ * The call makes no hipMalloc/hipFree and no allocating library call; its
+ * first call on a device looks up that device's array (hipGetSymbolAddress).
+ * Requests whose hos_bispectrum_workspace size exceeds
+ * HOS_NOALLOC_SCRATCH_BYTES return HOS_ESCRATCH before any HIP call (at
+ * n = 2^20, M = 512: 86 MiB on the FP32 path, 118 MiB on the split paths).
+ * Every call on one device shares that device's array: calls that overlap
+ * in time on one device race and must be serialised by the caller (one
+ * stream, or synchronisation between them).  Nothing in the array needs to
+ * be zero on entry; it keeps the last call's contents.
+ */
+#define HOS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20) /* 128 MiB per device */
+int hos_bispectrum_noalloc(const void *x, int32_t dtype, int64_t n, int32_t M,
+                           int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                           double *c3, double *B, hipStream_t stream);
 
 /*
  * Host-only introspection of the contraction plan (no HIP call, no device

@@ -30,6 +30,8 @@ HOS_EWORKSPACE = -2
 HOS_EDEVICE = -3
 HOS_ENODEVICE = -4
 HOS_EUNSUPPORTED = -5
+HOS_ESCRATCH = -6
+HOS_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 HOS_F32 = 0
 HOS_F64 = 1
@@ -75,6 +77,8 @@ def _load_lib():
         "hos_bispectrum_timed": (ctypes.c_int, [vp, i32, i64, i32, i32, i32, i32, u32,
                                                 vp, vp, vp, sz, vp,
                                                 ctypes.POINTER(ctypes.c_float)]),
+        "hos_bispectrum_noalloc": (ctypes.c_int, [vp, i32, i64, i32, i32, i32, i32, u32,
+                                                  vp, vp, vp]),
         "hos_c3_plan_info": (ctypes.c_int, [i64, i32, i32, p64, i32]),
         "hos_trispectrum_workspace": (ctypes.c_int, [i64, i32, i32, i32, u32,
                                                      ctypes.POINTER(sz)]),
@@ -177,6 +181,15 @@ def hos_bispectrum_timed(x_ptr, dtype, n, M, window, nfft, path, flags, c3_ptr, 
                                    int(nfft), int(path), int(flags), c3_ptr, B_ptr, ws_ptr,
                                    int(ws_bytes), stream, ms)
     return st, dict(zip(STAGES, list(ms)))
+
+
+def hos_bispectrum_noalloc(x_ptr, dtype, n, M, window, nfft, path, flags, c3_ptr, B_ptr,
+                           stream) -> int:
+    """Raw call of the non-allocating entry point (the library's fixed
+    per-device scratch is the workspace); returns the status code."""
+    return lib().hos_bispectrum_noalloc(x_ptr, int(dtype), int(n), int(M), int(window),
+                                        int(nfft), int(path), int(flags), c3_ptr, B_ptr,
+                                        stream)
 
 
 def hos_c3_plan_info(n, M, path) -> dict:

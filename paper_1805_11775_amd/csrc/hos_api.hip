@@ -214,6 +214,69 @@ static int device_ok()
 
 int device_ok_public() { return device_ok(); }
 
+// Host-side validation of a hos_bispectrum call (everything but the
+// workspace) and its plan; no HIP call.
+int bispectrum_check(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                          int32_t nfft, int32_t path, uint32_t flags, const double *c3,
+                          const double *B, C3Plan &p)
+{
+    if (!x || (!c3 && !B))
+        return HOS_EINVAL;
+    if (dtype != HOS_F32 && dtype != HOS_F64)
+        return HOS_EINVAL;
+    if (!aligned(x, dtype == HOS_F64 ? 8 : 4))
+        return HOS_EINVAL;
+    if ((c3 && !aligned(c3, 8)) || (B && !aligned(B, 16)))
+        return HOS_EINVAL;
+    int st = check_bispectrum_args(n, M, window, B ? nfft : 0, path, flags, B != nullptr);
+    if (st != HOS_OK)
+        return st;
+    make_c3_plan(n, M, path, B ? nfft : 0, p);
+    return HOS_OK;
+}
+
+// Shared body of hos_bispectrum, hos_bispectrum_timed and
+// hos_bispectrum_noalloc: validation, plan, and the launch sequence.  `ev`
+// (8 events or NULL) brackets the stages.
+int bispectrum_run(const void *x, int32_t dtype, int64_t n, int32_t M,
+                           int32_t window, int32_t nfft, int32_t path, uint32_t flags,
+                           double *c3, double *B, void *ws, size_t ws_bytes,
+                           hipStream_t stream, hipEvent_t *ev)
+{
+    if (!ws || !aligned(ws, 256))
+        return HOS_EINVAL;
+    C3Plan p;
+    int st = bispectrum_check(x, dtype, n, M, window, nfft, path, flags, c3, B, p);
+    if (st != HOS_OK)
+        return st;
+    if (ws_bytes < p.total)
+        return HOS_EWORKSPACE;
+    st = device_ok();
+    if (st != HOS_OK)
+        return st;
+
+    char *w = (char *)ws;
+    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], stream) : hipSuccess; };
+    double2 *tw = B ? (double2 *)(w + p.off_twid) : nullptr;
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = launch_moments(x, dtype, n, flags, p, w, stream);
+    if (e == hipSuccess) e = mark(1);
+    if (e == hipSuccess) e = launch_prep(x, dtype, p, w, stream);
+    if (e == hipSuccess) e = mark(2);
+    if (e == hipSuccess) e = launch_c3_contract(p, w, stream);
+    if (e == hipSuccess) e = mark(3);
+    if (e == hipSuccess) e = launch_diag_dot(x, dtype, p, w, stream);
+    if (e == hipSuccess) e = mark(4);
+    if (e == hipSuccess) e = launch_c3_reduce(p, w, stream);
+    if (e == hipSuccess) e = mark(5);
+    if (e == hipSuccess && B) e = launch_twiddles(tw, nfft, stream);
+    if (e == hipSuccess) e = launch_c3_finish(p, window, nfft, c3, B, w, stream);
+    if (e == hipSuccess) e = mark(6);
+    if (e == hipSuccess && B) e = launch_fft_cols(B, nfft, tw, stream);
+    if (e == hipSuccess) e = mark(7);
+    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
+}
+
 }  // namespace hos
 
 using namespace hos;
@@ -229,6 +292,7 @@ const char *hos_strerror(int status)
     case HOS_EDEVICE: return "HIP device error";
     case HOS_ENODEVICE: return "no gfx950 device available";
     case HOS_EUNSUPPORTED: return "unsupported request";
+    case HOS_ESCRATCH: return "request exceeds the fixed scratch of the non-allocating entry point";
     default: return "unknown status";
     }
 }
@@ -260,59 +324,11 @@ int hos_bispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path, u
     return HOS_OK;
 }
 
-// Shared body of hos_bispectrum and hos_bispectrum_timed: validation, plan,
-// and the launch sequence.  `ev` (8 events or NULL) brackets the stages.
-static int bispectrum_impl(const void *x, int32_t dtype, int64_t n, int32_t M,
-                           int32_t window, int32_t nfft, int32_t path, uint32_t flags,
-                           double *c3, double *B, void *ws, size_t ws_bytes,
-                           hipStream_t stream, hipEvent_t *ev)
-{
-    if (!x || !ws || (!c3 && !B))
-        return HOS_EINVAL;
-    if (dtype != HOS_F32 && dtype != HOS_F64)
-        return HOS_EINVAL;
-    if (!aligned(x, dtype == HOS_F64 ? 8 : 4) || !aligned(ws, 256))
-        return HOS_EINVAL;
-    if ((c3 && !aligned(c3, 8)) || (B && !aligned(B, 16)))
-        return HOS_EINVAL;
-    int st = check_bispectrum_args(n, M, window, B ? nfft : 0, path, flags, B != nullptr);
-    if (st != HOS_OK)
-        return st;
-    C3Plan p;
-    make_c3_plan(n, M, path, B ? nfft : 0, p);
-    if (ws_bytes < p.total)
-        return HOS_EWORKSPACE;
-    st = device_ok();
-    if (st != HOS_OK)
-        return st;
-
-    char *w = (char *)ws;
-    auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], stream) : hipSuccess; };
-    double2 *tw = B ? (double2 *)(w + p.off_twid) : nullptr;
-    hipError_t e = mark(0);
-    if (e == hipSuccess) e = launch_moments(x, dtype, n, flags, p, w, stream);
-    if (e == hipSuccess) e = mark(1);
-    if (e == hipSuccess) e = launch_prep(x, dtype, p, w, stream);
-    if (e == hipSuccess) e = mark(2);
-    if (e == hipSuccess) e = launch_c3_contract(p, w, stream);
-    if (e == hipSuccess) e = mark(3);
-    if (e == hipSuccess) e = launch_diag_dot(x, dtype, p, w, stream);
-    if (e == hipSuccess) e = mark(4);
-    if (e == hipSuccess) e = launch_c3_reduce(p, w, stream);
-    if (e == hipSuccess) e = mark(5);
-    if (e == hipSuccess && B) e = launch_twiddles(tw, nfft, stream);
-    if (e == hipSuccess) e = launch_c3_finish(p, window, nfft, c3, B, w, stream);
-    if (e == hipSuccess) e = mark(6);
-    if (e == hipSuccess && B) e = launch_fft_cols(B, nfft, tw, stream);
-    if (e == hipSuccess) e = mark(7);
-    return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
-}
-
 int hos_bispectrum(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
                    int32_t nfft, int32_t path, uint32_t flags, double *c3, double *B,
                    void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    return bispectrum_impl(x, dtype, n, M, window, nfft, path, flags, c3, B, ws, ws_bytes,
+    return bispectrum_run(x, dtype, n, M, window, nfft, path, flags, c3, B, ws, ws_bytes,
                            stream, nullptr);
 }
 
@@ -327,7 +343,7 @@ int hos_bispectrum_timed(const void *x, int32_t dtype, int64_t n, int32_t M, int
     for (; made < 8; ++made)
         if (hipEventCreate(&ev[made]) != hipSuccess)
             break;
-    int st = made == 8 ? bispectrum_impl(x, dtype, n, M, window, nfft, path, flags, c3, B,
+    int st = made == 8 ? bispectrum_run(x, dtype, n, M, window, nfft, path, flags, c3, B,
                                          ws, ws_bytes, stream, ev)
                        : HOS_EDEVICE;
     if (st == HOS_OK) {

@@ -196,6 +196,16 @@ constexpr int MOM_BLOCKS = 256;     // blocks of the moments pass
 constexpr int SK_MAX_WG = 256;      // persistent workgroups of the contraction
 
 int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p);
+// Host-side validation of a hos_bispectrum call (all but the workspace) and
+// its plan; no HIP call.
+int bispectrum_check(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                     int32_t nfft, int32_t path, uint32_t flags, const double *c3,
+                     const double *B, C3Plan &p);
+// Validation, plan and launch sequence of hos_bispectrum on the workspace
+// `ws` (`ev`: 8 stage events or NULL).
+int bispectrum_run(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
+                   int32_t nfft, int32_t path, uint32_t flags, double *c3, double *B,
+                   void *ws, size_t ws_bytes, hipStream_t stream, hipEvent_t *ev);
 int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p, int ord);
 int c4_window_entries(int M);
 

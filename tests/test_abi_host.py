@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_strerror():
     assert hos.hos_version() == 10000
-    for code in (0, -1, -2, -3, -4, -5, 7):
+    for code in (0, -1, -2, -3, -4, -5, -6, 7):
         assert isinstance(hos.hos_strerror(code), str)
 
 
@@ -64,6 +64,42 @@ def test_validation_before_device(kw, code):
                             a["path"], a["flags"], a["c3"], a["B"], a["ws"],
                             a["ws_bytes"], a["stream"])
     assert st == code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=1), hos.HOS_EINVAL),
+    (dict(M=100, n=100), hos.HOS_EINVAL),
+    (dict(path=3), hos.HOS_EINVAL),
+    (dict(window=3), hos.HOS_EINVAL),
+    (dict(dtype=5), hos.HOS_EINVAL),
+    (dict(flags=8), hos.HOS_EINVAL),
+    (dict(nfft=127), hos.HOS_EINVAL),
+    (dict(x=None), hos.HOS_EINVAL),
+    (dict(x=FAKE + 2), hos.HOS_EINVAL),
+    (dict(B=FAKE + 8), hos.HOS_EINVAL),
+    (dict(c3=None, B=None), hos.HOS_EINVAL),
+    # beyond the fixed scratch: 2^22 samples at M = 512 need ~470 MiB
+    (dict(n=1 << 22, M=512, nfft=1024, path=hos.HOS_PATH_SPLIT_FP16), hos.HOS_ESCRATCH),
+    (dict(n=1 << 21, M=512, nfft=1024, path=hos.HOS_PATH_SPLIT_FP16), hos.HOS_ESCRATCH),
+])
+def test_noalloc_validation_before_device(kw, code):
+    """The non-allocating entry point rejects bad arguments, and requests
+    beyond its fixed scratch, on the host before any HIP call."""
+    a = dict(x=FAKE, dtype=hos.HOS_F32, n=4096, M=64, window=hos.HOS_WIN_PARZEN,
+             nfft=128, path=hos.HOS_PATH_FP32, flags=0, c3=FAKE, B=FAKE, stream=None)
+    a.update(kw)
+    st = hos.hos_bispectrum_noalloc(a["x"], a["dtype"], a["n"], a["M"], a["window"],
+                                    a["nfft"], a["path"], a["flags"], a["c3"], a["B"],
+                                    a["stream"])
+    assert st == code
+    assert "scratch" in hos.hos_strerror(hos.HOS_ESCRATCH)
+
+
+def test_noalloc_scratch_covers_the_headline_shape():
+    # the largest single-series shape the benchmark runs fits the fixed scratch
+    for path in (hos.HOS_PATH_FP32, hos.HOS_PATH_SPLIT_FP16, hos.HOS_PATH_SPLIT_BF16):
+        assert hos.hos_bispectrum_workspace(1 << 20, 512, 1024, path) <= \
+            hos.HOS_NOALLOC_SCRATCH_BYTES
 
 
 def test_workspace_query():
