@@ -340,27 +340,33 @@ def bispectrum(x, M: int, nfft: int, window: str = "parzen",
     (Section 1, Problem Statement: the sample cumulant at every lag up to
     the maximum lag).
     """
-    c = c3_square(x, M, centered) if full_square else c3_hexagon(x, M, centered)
-    cw = c * window3(M, window)
-    B = np.fft.fft2(place_circular(cw, M, nfft))
+    sq = c3_square(x, M, centered)
+    c = sq if full_square else np.where(span3(M) > M, 0.0, sq)
+    # B transforms the windowed sample cumulant over every lag of the square
+    # (Section 1, Problem Statement); the Parzen product W3 vanishes on the
+    # corners, the separable window and no window do not
+    B = np.fft.fft2(place_circular(sq * window3(M, window), M, nfft))
     return c, B
 
 
 def spectrum5(x, M: int, nfft: int, window: str = "parzen", centered: bool = True):
     """(c5 on its support, Q = 4D DFT of the windowed c5 on an N^4 grid): the
     order-5 member of the family (the paper's k-th order spectrum)."""
-    c = c5_support(x, M, centered)
-    cw = c * window5(M, window)
-    Q = np.fft.fftn(place_circular(cw, M, nfft))
+    hyper = c5_hyper(x, M, centered)
+    c = np.where(span5(M) > M, 0.0, hyper)
+    Q = np.fft.fftn(place_circular(hyper * window5(M, window), M, nfft))
     return c, Q
 
 
 def trispectrum(x, M: int, nfft: int, window: str = "parzen",
                 centered: bool = True):
     """(c4 on its support, T = 3D DFT of the windowed c4 on an N^3 grid)."""
-    c = c4_support(x, M, centered)
-    cw = c * window4(M, window)
-    T = np.fft.fftn(place_circular(cw, M, nfft))
+    cube = c4_cube(x, M, centered)
+    c = np.where(span4(M) > M, 0.0, cube)
+    # T transforms the windowed sample cumulant over the whole cube; the
+    # Parzen product over the six differences vanishes where the span
+    # exceeds M, the separable window and no window do not
+    T = np.fft.fftn(place_circular(cube * window4(M, window), M, nfft))
     return c, T
 
 
@@ -377,9 +383,10 @@ def bispectrum_segments(x, P: int, M: int, nfft: int, window: str = "parzen",
     K = x.size // P
     c = np.zeros((2 * M + 1, 2 * M + 1))
     for i in range(K):
-        c += c3_hexagon(x[i * P:(i + 1) * P], M, centered)
+        c += c3_square(x[i * P:(i + 1) * P], M, centered)
     c /= K
     B = np.fft.fft2(place_circular(c * window3(M, window), M, nfft))
+    c[span3(M) > M] = 0.0
     return c, B
 
 
@@ -417,8 +424,8 @@ def bispectrum_loss(X, M: int, nfft: int, target_pd, window: str = "parzen"):
 def loss_weight(x, M: int, nfft: int, target_pd, window: str = "parzen") -> np.ndarray:
     """G(w) = dL/dc3(w) over the square for one series: with R = B - target
     on the principal domain and B = sum_w W3(w) c3(w) e^{-2 pi i <k,w>/N},
-    dL/dc3(w) = 2 W3(w) Re sum_k R_k e^{+2 pi i <k,w>/N}; lags outside the
-    hexagon (where c3 is defined as 0) get 0."""
+    dL/dc3(w) = 2 W3(w) Re sum_k R_k e^{+2 pi i <k,w>/N}, over every lag of
+    the square (the Parzen product W3 makes it 0 on the corners)."""
     k1, k2 = pd_indices(nfft)
     R = bispectrum_pd(x, M, nfft, window) - np.asarray(target_pd, dtype=np.complex128)
     Rm = np.zeros((nfft, nfft), dtype=np.complex128)
@@ -426,9 +433,7 @@ def loss_weight(x, M: int, nfft: int, target_pd, window: str = "parzen") -> np.n
     w = np.arange(-M, M + 1)
     E = np.exp(2j * np.pi * np.outer(np.arange(nfft), w) / nfft)   # E[k, w]
     S = E.T @ Rm @ E                                               # sum_k R_k e^{+i..}
-    G = 2.0 * window3(M, window) * S.real
-    G[span3(M) > M] = 0.0
-    return G
+    return 2.0 * window3(M, window) * S.real
 
 
 def bispectrum_loss_grad(X, M: int, nfft: int, target_pd, window: str = "parzen",

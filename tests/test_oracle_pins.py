@@ -531,15 +531,20 @@ def test_trispectrum_matches_direct_lag_sum():
 
 
 def test_bispectrum_full_square_region():
-    """With full_square the oracle returns c3 at every lag of the square
-    (the corners equal the literal loops) and transforms all of it: at no
-    window, B - B(hexagon) is the DFT of the corners alone, here checked at
-    one frequency against the corner lags summed one by one."""
+    """c3 is returned on the hexagon (corners 0) or, with full_square, at
+    every lag of the square, the corners equal to the literal loops.  B
+    transforms the windowed sample cumulant over the whole square whatever
+    c3's region (Section 1, Problem Statement: the cumulant at every lag up
+    to the maximum lag): at no window B minus the DFT of the hexagon part is
+    the DFT of the corners, checked at one frequency against the corner
+    lags summed one by one; the Parzen product vanishes on the corners."""
     n, M, N = 30, 5, 11
     x = synth.quadratic_process(n, 15)
     xt = brute.center(list(x))
     c_sq, B_sq = oracle.bispectrum(x, M, N, window="none", full_square=True)
     c_hx, B_hx = oracle.bispectrum(x, M, N, window="none")
+    assert np.array_equal(B_sq, B_hx)
+    B_hex_only = np.fft.fft2(oracle.place_circular(c_hx, M, N))
     corner = 0j
     k1, k2 = 2, 7
     for w1 in range(-M, M + 1):
@@ -548,12 +553,49 @@ def test_bispectrum_full_square_region():
             assert abs(c_sq[w1 + M, w2 + M] - v) < 1e-14
             if abs(w1 - w2) > M:
                 assert c_hx[w1 + M, w2 + M] == 0.0
+                assert v != 0.0
                 corner += v * np.exp(-2j * np.pi * (k1 * w1 + k2 * w2) / N)
-    assert abs((B_sq - B_hx)[k1, k2] - corner) < 1e-13
-    # the Parzen window vanishes on the corners: both regions give one B
+    assert abs((B_sq - B_hex_only)[k1, k2] - corner) < 1e-13
+    # the separable window is nonzero on the corners too: d(w1) d(w2)
+    _, B_sep = oracle.bispectrum(x, M, 2 * M, window="separable")
+    W = oracle.window3(M, "separable")
+    assert np.max(W[oracle.span3(M) > M]) > 0.0
+    ref = np.fft.fft2(oracle.place_circular(c_sq * W, M, 2 * M))
+    assert np.max(np.abs(B_sep - ref)) < 1e-15 * np.max(np.abs(ref))
+    # the Parzen product vanishes on the corners: both regions give one B
     _, B1 = oracle.bispectrum(x, M, 2 * M, full_square=True)
     _, B2 = oracle.bispectrum(x, M, 2 * M)
     assert np.max(np.abs(B1 - B2)) < 1e-15 * np.max(np.abs(B2))
+    Wp = oracle.window3(M, "parzen")
+    assert np.all(Wp[oracle.span3(M) > M] == 0.0)
+
+
+def test_trispectrum_uses_the_whole_cube_off_parzen():
+    """T transforms the windowed c4 over the whole cube: with the separable
+    window (nonzero where the span exceeds M) it differs from the transform
+    of the span <= M part by the transform of the rest, checked at one
+    frequency against those lags summed one by one from the literal loops."""
+    n, M, N = 14, 3, 7
+    x = synth.cubic_process(n, 16)
+    xt = brute.center(list(x))
+    c, T = oracle.trispectrum(x, M, N, window="separable")
+    W = oracle.window4(M, "separable")
+    T_support = np.fft.fftn(oracle.place_circular(c * W, M, N))
+    kk = (1, 3, 2)
+    rest = 0j
+    lags = range(-M, M + 1)
+    for t1 in lags:
+        for t2 in lags:
+            for t3 in lags:
+                span = max(0, t1, t2, t3) - min(0, t1, t2, t3)
+                if span > M:
+                    w = W[t1 + M, t2 + M, t3 + M]
+                    rest += w * brute.c4(xt, t1, t2, t3) * np.exp(
+                        -2j * np.pi * (kk[0] * t1 + kk[1] * t2 + kk[2] * t3) / N)
+                else:
+                    assert abs(c[t1 + M, t2 + M, t3 + M] - brute.c4(xt, t1, t2, t3)) < 1e-14
+    assert abs(rest) > 1e-6
+    assert abs((T - T_support)[kk] - rest) < 1e-12 * np.max(np.abs(T))
 
 
 # --------------------------------------------------------------------------
