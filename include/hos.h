@@ -33,11 +33,20 @@
  *            formed the same way (the zero-mean moment-to-cumulant relation;
  *            Section 1 defines cumulants through the moments).
  * Layouts.   c3: (2M+1)^2 row-major float64, lag (w1,w2) at
- *            (w1+M)*(2M+1) + (w2+M); lags with |w1-w2| > M are 0.
+ *            (w1+M)*(2M+1) + (w2+M).  By default only the hexagon
+ *            |w1-w2| <= M is filled and the two corners of the square are
+ *            0; with HOS_FULL_SQUARE every lag |w1|,|w2| <= M holds its
+ *            sample cumulant.
  *            B: nfft x nfft interleaved complex128, row-major, frequency
  *            (k1,k2) at k1*nfft + k2, unshifted.
  *            B(k1,k2) = sum_w W(w) c3(w) exp(-2 pi i (k1 w1 + k2 w2)/nfft),
- *            unnormalised, with the sign of the DFT in Algorithm DBS's part DFT.
+ *            unnormalised, with the sign of the DFT in Algorithm DBS's part DFT,
+ *            the sum over every lag |w1|,|w2| <= M (the sample cumulant at
+ *            the corners is computed whenever W is nonzero there: always
+ *            for HOS_WIN_NONE and HOS_WIN_PARZEN_SEPARABLE, never needed for
+ *            HOS_WIN_PARZEN, which vanishes at |w1-w2| >= M).
+ *            With HOS_PD_ONLY: only the principal domain 0 <= k2 <= k1,
+ *            k1+k2 < nfft/2, row-major in (k1, then k2), packed.
  *            c4: (2M+1)^3 row-major float64, lag (t1,t2,t3) at
  *            ((t1+M)*(2M+1) + (t2+M))*(2M+1) + (t3+M); lags whose span
  *            max(0,t1,t2,t3) - min(0,t1,t2,t3) exceeds M are 0.
@@ -106,6 +115,8 @@ typedef enum hos_path {
 
 /* Flags. */
 #define HOS_NO_CENTER 1u     /* use x as given (no mean removal); for tests      */
+#define HOS_FULL_SQUARE 2u   /* hos_bispectrum[_streamed]: fill c3's corners     */
+#define HOS_PD_ONLY 4u       /* hos_bispectrum: B on the principal domain only   */
 #define HOS_PLAN_ADJOINT 16u /* batch plan flag: also lay out the adjoint buffers */
 #define HOS_PLAN_SEGMENTS 32u /* batch plan flag: lay out hos_bispectrum_segments' buffers */
 
@@ -119,7 +130,8 @@ int hos_version(void);
 int hos_device_check(void);
 
 /*
- * Workspace size for hos_bispectrum.
+ * Workspace size for hos_bispectrum.  It does not depend on the window:
+ * the corner lags some windows need reuse the partial-sum region.
  *   n      series length, n >= 2.
  *   M      maximum lag, 0 <= M < n.
  *   nfft   DFT size per axis, or 0 when no spectrum is requested.
@@ -141,10 +153,17 @@ int hos_bispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
  *            nfft >= 2M with either Parzen window (it vanishes at |w| = M),
  *            nfft >= 2M+1 with HOS_WIN_NONE; ignored when B is NULL.
  *   path     hos_path.
+ *   flags    HOS_NO_CENTER, HOS_FULL_SQUARE (c3 at the corners |w1-w2| > M
+ *            too: the sums over F' = {0 <= b <= M, M < a <= b + M} of the
+ *            sorted offsets {0, b, a}, computed by a second contraction of
+ *            the same shape), HOS_PD_ONLY (B on the principal domain).
  *   c3       device, (2M+1)^2 float64 (layout above), or NULL.
- *   B        device, nfft^2 complex128 (layout above), or NULL.
- *   ws       device workspace of at least hos_bispectrum_workspace() bytes,
- *            256-byte aligned; its contents on entry do not matter.
+ *   B        device, nfft^2 complex128 (layout above), or with HOS_PD_ONLY
+ *            npd complex128, npd = sum over k1 = 0 .. H of
+ *            max(0, min(k1, H - k1) + 1), H = floor((nfft-1)/2); or NULL.
+ *   ws       device workspace of at least hos_bispectrum_workspace() bytes
+ *            (queried with the same flags), 256-byte aligned; its contents
+ *            on entry do not matter.
  * At least one of c3 and B must be non-NULL.
  */
 int hos_bispectrum(const void *x, int32_t dtype, int64_t n, int32_t M,
@@ -157,7 +176,8 @@ int hos_bispectrum(const void *x, int32_t dtype, int64_t n, int32_t M,
  * results; additionally records HIP events around each stage on `stream`,
  * WAITS for the stream, and writes the elapsed milliseconds to stage_ms
  * (host, 8 floats): [0] mean/range pass, [1] operand preparation,
- * [2] contraction, [3] leftover diagonal sums, [4] partial reduction,
+ * [2] contraction, [3] leftover diagonal sums, [4] partial reduction (with
+ * the corner contraction and its reduction when the square is computed),
  * [5] mirror, window and the DFT along k2 (+ twiddles), [6] the DFT along
  * k1, [7] total.  Creates and
  * destroys its own events (no device memory is allocated).
@@ -226,9 +246,11 @@ int hos_trispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
  *            nfft >= 2M (Parzen) / 2M+1 (no window); ignored when T is NULL.
  *   c4       device, (2M+1)^3 float64 (layout above), or NULL.
  *   T        device, nfft^3 complex128 (layout above), or NULL.
- * At least one of c4 and T must be non-NULL.  With HOS_WIN_PARZEN the lag
- * window is the product of d(m), scale L = M, over the six pairwise
- * differences of {0, t1, t2, t3}.
+ * At least one of c4 and T must be non-NULL.  The lag window must be
+ * HOS_WIN_PARZEN: the product of d(m), scale L = M, over the six pairwise
+ * differences of {0, t1, t2, t3}, which vanishes wherever the span exceeds
+ * M.  The other windows are nonzero at lags of span up to 2M, which this
+ * contraction does not cover: they return HOS_EUNSUPPORTED.
  */
 int hos_trispectrum(const void *x, int32_t dtype, int64_t n, int32_t M,
                     int32_t window, int32_t nfft, int32_t path, uint32_t flags,
@@ -262,8 +284,9 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  * hos_bispectrum on the whole record, computed through a device workspace
  * whose size depends on the piece length P and M but not on n.  The record
  * is read twice in pieces of P samples: first for its FP64 mean and scale,
- * then each piece with the M samples after it, whose sums are added to a
- * running FP64 table.  The copies run on a copy stream of the library's
+ * then each piece with the M samples after it (2M when the square's corners
+ * are computed: HOS_FULL_SQUARE, or a window that is nonzero there), whose
+ * sums are added to a running FP64 table.  The copies run on a copy stream of the library's
  * own (one per device, made at the first call and kept until the process
  * ends) into two staging buffers of the workspace, so a piece's copy
  * overlaps the kernels of the one before; events order them against
@@ -274,9 +297,10 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  *           Pageable memory works too (the runtime stages it, and the call
  *           returns about when the last piece's copy has been taken).
  *   piece   P: a multiple of 1024, >= 4096, >= M.
- *   c3, B, window, nfft, path, flags: as hos_bispectrum (device outputs).
+ *   c3, B, window, nfft, path: as hos_bispectrum (device outputs).
+ *   flags   HOS_NO_CENTER, HOS_FULL_SQUARE (as hos_bispectrum).
  * Workspace: hos_bispectrum_streamed_workspace (dtype sets the size of the
- * piece buffer).  Results equal hos_bispectrum's up to the order of FP64
+ * piece buffer; the size covers the corners whatever the window).  Results equal hos_bispectrum's up to the order of FP64
  * additions.
  */
 int hos_bispectrum_streamed_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
@@ -296,9 +320,10 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
  * offsets {0, t1, t2, t3, t4} into a pair and a triple:
  *   c5 = m5 - sum over the ten pairs {j,k} of c2(o_k - o_j) c3(the other three),
  * with c2 and c3 the sample cumulants of the same series.  Lags whose span
- * max - min of {0, t1..t4} exceeds M are 0.  Window (window = HOS_WIN_PARZEN):
- * d over the ten pairwise differences of the offsets (L = M);
- * HOS_WIN_PARZEN_SEPARABLE: d(t1) d(t2) d(t3) d(t4); HOS_WIN_NONE: 1.
+ * max - min of {0, t1..t4} exceeds M are 0.  Window: HOS_WIN_PARZEN, d over
+ * the ten pairwise differences of the offsets (L = M), which vanishes
+ * wherever the span exceeds M; the other windows would need lags of span up
+ * to 2M and return HOS_EUNSUPPORTED.
  *   Q(k1..k4) = sum_t W5(t) c5(t) exp(-2 pi i <k, t> / N).
  * Outputs: c5 (2M+1)^4 float64 row-major, lag t at t+M per axis; Q N^4
  * interleaved complex128, unshifted.  Either may be NULL (not both).  Limits:
@@ -330,7 +355,7 @@ int hos_c5_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  * A batch is described by a PLAN built on the host (no device needed):
  * series s has n[s] samples, stored at x + sum_{t<s} n[t] of one packed
  * device array, and maximum lag M[s].  Its DFT size is the smallest
- * 2^a 3^b 5^c >= 2M[s] (Parzen) or 2M[s]+1 (no window).  The plan lays out
+ * 2^a 3^b 5^c >= 2M[s].  The plan lays out
  * the workspace and cuts every series' c3 contraction into work items
  * (series, tile, chunk range) that it assigns to persistent workgroups by
  * the longest-processing-time rule.  The caller copies the plan bytes
@@ -348,8 +373,10 @@ int hos_c5_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
 
 /* Plan and workspace sizes for a batch.  n, M: host arrays of `batch`
  * entries (n >= 2, 0 <= M < n, DFT size N <= 2048, i.e. M <= 1024 with
- * the Parzen window and M <= 1023 without; M <= 320 with HOS_PLAN_ADJOINT).
- * window: hos_window.  flags: HOS_NO_CENTER, HOS_PLAN_SEGMENTS (see
+ * the Parzen window; M <= 320 with HOS_PLAN_ADJOINT).
+ * window: HOS_WIN_PARZEN (batches compute the hexagon only, so the windows
+ * that are nonzero at its corners return HOS_EUNSUPPORTED).
+ * flags: HOS_NO_CENTER, HOS_PLAN_SEGMENTS (see
  * hos_bispectrum_segments; needs one M for every series), HOS_PLAN_ADJOINT (lay out the
  * buffers hos_bispectrum_loss_bwd needs).  tile_nb: NULL, or a host array
  * of `batch` tile choices for the contraction, 0 = built-in rule, 2 = tiles

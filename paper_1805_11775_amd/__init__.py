@@ -42,6 +42,8 @@ HOS_PATH_FP32 = 0
 HOS_PATH_SPLIT_FP16 = 1
 HOS_PATH_SPLIT_BF16 = 2
 HOS_NO_CENTER = 1
+HOS_FULL_SQUARE = 2
+HOS_PD_ONLY = 4
 HOS_PLAN_ADJOINT = 16
 HOS_PLAN_SEGMENTS = 32
 
@@ -300,6 +302,12 @@ def _next_fft_size(m: int) -> int:
         k += 1
 
 
+def pd_count(N: int) -> int:
+    """Points of the principal domain 0 <= k2 <= k1, k1 + k2 < N/2."""
+    H = (N - 1) // 2
+    return sum(min(k1, H - k1) + 1 for k1 in range(H + 1))
+
+
 def default_nfft(M: int, window: str = "parzen") -> int:
     need = 2 * M if window != "none" else 2 * M + 1
     return _next_fft_size(max(need, 2))
@@ -312,9 +320,12 @@ def _stream_handle(device):
 
 def bispectrum(x, M: int, nfft: int | None = None, window: str = "parzen",
                path: str = "fp32", center: bool = True, return_c3: bool = True,
-               return_B: bool = True, workspace=None):
-    """c3 over |w| <= M ((2M+1)^2 float64) and the windowed 2D DFT B
-    (nfft x nfft complex128) of a 1-D float32/float64 CUDA tensor.
+               return_B: bool = True, workspace=None, full_square: bool = False,
+               pd_only: bool = False):
+    """c3 over |w| <= M ((2M+1)^2 float64; the hexagon, or with
+    ``full_square`` every lag of the square) and the windowed 2D DFT B
+    (nfft x nfft complex128, or with ``pd_only`` the principal domain,
+    packed) of a 1-D float32/float64 CUDA tensor.
 
     Returns (c3 or None, B or None).  ``workspace`` may be a uint8 CUDA
     tensor of at least ``hos_bispectrum_workspace`` bytes to reuse.
@@ -330,14 +341,19 @@ def bispectrum(x, M: int, nfft: int | None = None, window: str = "parzen",
     win = WINDOWS[window]
     if nfft is None:
         nfft = default_nfft(M, window)
-    flags = 0 if center else HOS_NO_CENTER
+    flags = (0 if center else HOS_NO_CENTER) | (HOS_FULL_SQUARE if full_square else 0) | \
+        (HOS_PD_ONLY if pd_only else 0)
     ws_bytes = hos_bispectrum_workspace(n, M, nfft if return_B else 0, pth, flags)
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=x.device)
     c3 = torch.empty((2 * M + 1, 2 * M + 1), dtype=torch.float64,
                      device=x.device) if return_c3 else None
-    B = torch.empty((nfft, nfft), dtype=torch.complex128,
-                    device=x.device) if return_B else None
+    if not return_B:
+        B = None
+    elif pd_only:
+        B = torch.empty(pd_count(nfft), dtype=torch.complex128, device=x.device)
+    else:
+        B = torch.empty((nfft, nfft), dtype=torch.complex128, device=x.device)
     st = hos_bispectrum(x.data_ptr(), HOS_F64 if x.dtype == torch.float64 else HOS_F32,
                         n, M, win, nfft if return_B else 0, pth, flags,
                         c3.data_ptr() if c3 is not None else None,
@@ -434,11 +450,14 @@ def hos_bispectrum_streamed_workspace(n, M, nfft, path, dtype, piece) -> int:
 def bispectrum_streamed(x, M: int, piece: int = 1 << 22, nfft: int | None = None,
                         window: str = "parzen", path: str = "fp32", center: bool = True,
                         device="cuda", return_c3: bool = True, return_B: bool = True,
-                        workspace=None):
+                        workspace=None, full_square: bool = False):
     """``hos_bispectrum_streamed``: c3 and B of a record held in host memory
     (a CPU torch tensor, ideally pinned, or a numpy array), streamed in
     pieces of ``piece`` samples through a device workspace independent of
-    n.  Outputs are CUDA tensors on ``device``."""
+    n.  Outputs are CUDA tensors on ``device``.  A pinned record is still
+    being read by the library's copies when the call returns, so for a
+    pinned ``x`` this waits for the stream before returning (the caller's
+    tensor may be freed, and its block reused, as soon as it returns)."""
     import numpy as np
     import torch
     if isinstance(x, np.ndarray):
@@ -461,12 +480,15 @@ def bispectrum_streamed(x, M: int, piece: int = 1 << 22, nfft: int | None = None
     c3 = torch.empty((2 * M + 1, 2 * M + 1), dtype=torch.float64,
                      device=dev) if return_c3 else None
     B = torch.empty((nfft, nfft), dtype=torch.complex128, device=dev) if return_B else None
+    flags = (0 if center else HOS_NO_CENTER) | (HOS_FULL_SQUARE if full_square else 0)
     st = lib().hos_bispectrum_streamed(
-        x.data_ptr(), dtype, n, M, win, nf, pth, 0 if center else HOS_NO_CENTER, int(piece),
+        x.data_ptr(), dtype, n, M, win, nf, pth, flags, int(piece),
         c3.data_ptr() if c3 is not None else None, B.data_ptr() if B is not None else None,
         workspace.data_ptr(), workspace.numel(), _stream_handle(dev))
     if st != HOS_OK:
         raise HosError(st, "hos_bispectrum_streamed")
+    if x.is_pinned():
+        torch.cuda.current_stream(dev).synchronize()
     return c3, B
 
 

@@ -13,13 +13,15 @@ namespace hos {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
+int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p, bool corners,
+                 bool full_grid)
 {
     memset(&p, 0, sizeof(p));
     p.n = n;
     p.M = M;
     p.path = path;
     p.scale_top = 7;
+    p.amax = corners ? 2 * M : M;
     // Split paths: 4 column blocks per wave amortise the product-row split
     // (2-block tiles for small M); FP32 path: 128 x 128 tiles with a 2 x 2
     // block window per wave.
@@ -45,7 +47,9 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
         G = 1;
     g.G = (int32_t)G;
     p.smax = g.TR > 0 ? sk_max_segments(g) : 0;
-    p.npad = ((C * KCX + (int64_t)g.TR * p.TS + 64) + 63) / 64 * 64;
+    // the corner contraction reads its Hankel columns M + 1 samples further on
+    const int64_t coff = p.amax > M ? (int64_t)M + 1 : 0;
+    p.npad = ((C * KCX + (int64_t)g.TR * p.TS + coff + 64) + 63) / 64 * 64;
     // leftover diagonal sums: one pass over x in 1024-sample blocks
     // (k_diag_fused) when nleft <= 32, else nleft x 64 strided blocks
     if (p.nleft <= 32) {
@@ -75,6 +79,10 @@ int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p)
     if (nfft > 0) {
         p.off_twid = o;
         o = align256(o + (size_t)nfft * 2 * sizeof(double));
+        if (full_grid) {
+            p.off_bfull = o;
+            o = align256(o + (size_t)nfft * nfft * 2 * sizeof(double));
+        }
     }
     p.total = o;
     return HOS_OK;
@@ -141,10 +149,16 @@ int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p, in
 
 static bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr & (a - 1)) == 0; }
 
+// n is capped at 2^31 samples: the one-dimensional grids over the padded
+// series (operand tables, diagonal sums) then stay far inside the 32-bit
+// work-item range of a launch.
+constexpr int64_t MAX_SERIES = (int64_t)1 << 31;
+
 static int check_bispectrum_args(int64_t n, int32_t M, int32_t window, int32_t nfft,
-                                 int32_t path, uint32_t flags, bool want_B)
+                                 int32_t path, uint32_t flags, bool want_B,
+                                 uint32_t allowed = HOS_NO_CENTER)
 {
-    if (n < 2 || n > ((int64_t)1 << 40))
+    if (n < 2 || n > MAX_SERIES)
         return HOS_EINVAL;
     if (M < 0 || (int64_t)M >= n || M > 8192)
         return HOS_EINVAL;
@@ -152,7 +166,7 @@ static int check_bispectrum_args(int64_t n, int32_t M, int32_t window, int32_t n
         return HOS_EINVAL;
     if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN && window != HOS_WIN_PARZEN_SEPARABLE)
         return HOS_EINVAL;
-    if (flags & ~HOS_NO_CENTER)
+    if (flags & ~allowed)
         return HOS_EINVAL;
     if (want_B) {
         if (!fft_size_ok(nfft))
@@ -174,6 +188,14 @@ static int check_c5_args(int64_t n, int32_t M, int32_t window, int32_t nfft, int
     if (want_Q && nfft > C5_MAX_NFFT)
         return HOS_EINVAL;
     return check_bispectrum_args(n, M, window, nfft, path, flags, want_Q);
+}
+
+// Windows the fourth- and fifth-order paths cover: their contractions fill
+// the lags of span <= M only, where the Parzen product over every pairwise
+// difference lives; the other windows need spans up to 2M.
+static int check_high_order_window(int32_t window)
+{
+    return window == HOS_WIN_PARZEN ? HOS_OK : HOS_EUNSUPPORTED;
 }
 
 static int check_trispectrum_args(int64_t n, int32_t M, int32_t window, int32_t nfft,
@@ -214,6 +236,14 @@ static int device_ok()
 
 int device_ok_public() { return device_ok(); }
 
+// The square's corners |w1 - w2| > M are computed when c3 is asked for them
+// or when the window does not vanish there (everything but the Parzen
+// product with d(w1 - w2), which is 0 from |w1 - w2| = M on).
+bool bispectrum_needs_corners(int32_t window, uint32_t flags, bool want_B)
+{
+    return (flags & HOS_FULL_SQUARE) || (want_B && window != HOS_WIN_PARZEN);
+}
+
 // Host-side validation of a hos_bispectrum call (everything but the
 // workspace) and its plan; no HIP call.
 int bispectrum_check(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
@@ -228,10 +258,12 @@ int bispectrum_check(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t
         return HOS_EINVAL;
     if ((c3 && !aligned(c3, 8)) || (B && !aligned(B, 16)))
         return HOS_EINVAL;
-    int st = check_bispectrum_args(n, M, window, B ? nfft : 0, path, flags, B != nullptr);
+    int st = check_bispectrum_args(n, M, window, B ? nfft : 0, path, flags, B != nullptr,
+                                   HOS_NO_CENTER | HOS_FULL_SQUARE | HOS_PD_ONLY);
     if (st != HOS_OK)
         return st;
-    make_c3_plan(n, M, path, B ? nfft : 0, p);
+    make_c3_plan(n, M, path, B ? nfft : 0, p, bispectrum_needs_corners(window, flags, B != nullptr),
+                 B && (flags & HOS_PD_ONLY));
     return HOS_OK;
 }
 
@@ -258,21 +290,31 @@ int bispectrum_run(const void *x, int32_t dtype, int64_t n, int32_t M,
     char *w = (char *)ws;
     auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], stream) : hipSuccess; };
     double2 *tw = B ? (double2 *)(w + p.off_twid) : nullptr;
+    const bool pd_only = B && (flags & HOS_PD_ONLY);
+    // the N x N grid: the output itself, or staged in the workspace and then
+    // reduced to its principal domain
+    double *grid = pd_only ? (double *)(w + p.off_bfull) : B;
+    const int c3_amax = (flags & HOS_FULL_SQUARE) ? 2 * M : M;
     hipError_t e = mark(0);
     if (e == hipSuccess) e = launch_moments(x, dtype, n, flags, p, w, stream);
     if (e == hipSuccess) e = mark(1);
     if (e == hipSuccess) e = launch_prep(x, dtype, p, w, stream);
     if (e == hipSuccess) e = mark(2);
-    if (e == hipSuccess) e = launch_c3_contract(p, w, stream);
+    if (e == hipSuccess) e = launch_c3_contract(p, w, stream, 0);
     if (e == hipSuccess) e = mark(3);
     if (e == hipSuccess) e = launch_diag_dot(x, dtype, p, w, stream);
     if (e == hipSuccess) e = mark(4);
-    if (e == hipSuccess) e = launch_c3_reduce(p, w, stream);
+    if (e == hipSuccess) e = launch_c3_reduce(p, w, stream, 0);
+    // the square's corners: the same contraction with the Hankel columns
+    // shifted by M + 1 samples, on the partial-sum region just reduced
+    if (e == hipSuccess && p.amax > M) e = launch_c3_contract(p, w, stream, 1);
+    if (e == hipSuccess && p.amax > M) e = launch_c3_reduce(p, w, stream, 1);
     if (e == hipSuccess) e = mark(5);
     if (e == hipSuccess && B) e = launch_twiddles(tw, nfft, stream);
-    if (e == hipSuccess) e = launch_c3_finish(p, window, nfft, c3, B, w, stream);
+    if (e == hipSuccess) e = launch_c3_finish(p, window, nfft, c3, c3_amax, grid, w, stream);
     if (e == hipSuccess) e = mark(6);
-    if (e == hipSuccess && B) e = launch_fft_cols(B, nfft, tw, stream);
+    if (e == hipSuccess && B) e = launch_fft_cols(grid, nfft, tw, stream);
+    if (e == hipSuccess && pd_only) e = launch_pd_gather(grid, nfft, B, stream);
     if (e == hipSuccess) e = mark(7);
     return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
 }
@@ -313,13 +355,17 @@ int hos_bispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path, u
     if (!bytes)
         return HOS_EINVAL;
     const int win = HOS_WIN_NONE;
-    int st = check_bispectrum_args(n, M, win, nfft > 0 ? nfft : 0, path, flags, false);
+    int st = check_bispectrum_args(n, M, win, nfft > 0 ? nfft : 0, path, flags, false,
+                                   HOS_NO_CENTER | HOS_FULL_SQUARE | HOS_PD_ONLY);
     if (st != HOS_OK)
         return st;
     if (nfft > 0 && !fft_size_ok(nfft))
         return HOS_EINVAL;
+    // every layout has room for the corners (the windows that are nonzero
+    // there need them whatever the flags say); they cost M + 1 samples of
+    // operand padding, the table keeps them in its upper triangle
     C3Plan p;
-    make_c3_plan(n, M, path, nfft, p);
+    make_c3_plan(n, M, path, nfft, p, true, nfft > 0 && (flags & HOS_PD_ONLY));
     *bytes = p.total;
     return HOS_OK;
 }
@@ -393,6 +439,8 @@ static int trispectrum_impl(const void *x, int32_t dtype, int64_t n, int32_t M,
     if ((c4 && !aligned(c4, 8)) || (T && !aligned(T, 16)))
         return HOS_EINVAL;
     int st = check_trispectrum_args(n, M, window, T ? nfft : 0, path, flags, T != nullptr);
+    if (st == HOS_OK)
+        st = check_high_order_window(window);
     if (st != HOS_OK)
         return st;
     C4Plan p;
@@ -478,6 +526,8 @@ static int cumulant5_impl(const void *x, int32_t dtype, int64_t n, int32_t M, in
     if ((c5 && !aligned(c5, 8)) || (Q && !aligned(Q, 16)))
         return HOS_EINVAL;
     int st = check_c5_args(n, M, window, Q ? nfft : 0, path, flags, Q != nullptr);
+    if (st == HOS_OK)
+        st = check_high_order_window(window);
     if (st != HOS_OK)
         return st;
     C4Plan p;

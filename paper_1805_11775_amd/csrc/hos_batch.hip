@@ -64,6 +64,10 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         return HOS_EINVAL;
     if (flags & ~(HOS_NO_CENTER | HOS_PLAN_ADJOINT | HOS_PLAN_SEGMENTS))
         return HOS_EINVAL;
+    // batches compute each series' hexagon only: the windows that are nonzero
+    // at the square's corners would need the corner sums as well
+    if (window != HOS_WIN_PARZEN)
+        return HOS_EUNSUPPORTED;
     const bool adj = (flags & HOS_PLAN_ADJOINT) != 0;
     const bool split = path != HOS_PATH_FP32;
     BatchHeader h;
@@ -76,7 +80,9 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
     h.uniform_M = M[0];
     h.uniform_n = n[0];
     for (int s = 0; s < batch; ++s) {
-        if (n[s] < 2 || n[s] > ((int64_t)1 << 36) || M[s] < 0 || (int64_t)M[s] >= n[s] ||
+        // n <= 2^31: the operand-table grid spans the longest series in one
+        // dimension and must stay inside a launch's 32-bit work-item range
+        if (n[s] < 2 || n[s] > ((int64_t)1 << 31) || M[s] < 0 || (int64_t)M[s] >= n[s] ||
             M[s] > 2048)
             return HOS_EINVAL;
         if (adj && M[s] > ADJ_MAX_M)
@@ -566,7 +572,8 @@ int hos_bispectrum_segments(const void *x, int32_t dtype, const void *plan_host,
     if (e == hipSuccess) e = launch_seg_average(*h, dp, w, stream);
     if (e == hipSuccess && B) e = launch_twiddles(tw, N, stream);
     if (e == hipSuccess)
-        e = launch_c3_finish_table(avg, avg + ne, M, (int)h->window, N, tw, c3, B, stream);
+        e = launch_c3_finish_table(avg, avg + ne, M, M, (int)h->window, N, tw, c3, M, B,
+                                   stream);
     if (e == hipSuccess && B) e = launch_fft_cols(B, N, tw, stream);
     return e == hipSuccess ? HOS_OK : HOS_EDEVICE;
 }

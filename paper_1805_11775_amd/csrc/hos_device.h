@@ -34,18 +34,22 @@ __device__ inline double window3(int w1, int w2, int M, int window)
     return window == HOS_WIN_PARZEN ? s * parzen_d(w1 - w2, M) : s;
 }
 
-// c3(w1, w2) from the fundamental-region table C[a][b] (row stride M + 1):
-// the offsets {0, w1, w2} shifted by their minimum and sorted are {0, b, a};
-// lags with span a > M lie outside the hexagon and give 0.
-__device__ inline double c3_from_table(const double *__restrict__ cfull, int M, double norm,
-                                       int w1, int w2)
+// c3(w1, w2) from the (M+1) x (M+1) table of third-order sums: the offsets
+// {0, w1, w2} shifted by their minimum and sorted are {0, b, a}.  The lower
+// triangle holds the fundamental region F of the hexagon, C[a][b] at
+// [a][b] (b <= a <= M).  The square's corners (M < a <= 2M, a - M <= b <= M),
+// present when amax = 2M, sit in the upper triangle: C[a][b] at [c][b] with
+// c = a - M - 1 < b.  Lags with span a > amax give 0.
+__device__ inline double c3_from_table(const double *__restrict__ cfull, int M, int amax,
+                                       double norm, int w1, int w2)
 {
     const int mn = min(0, min(w1, w2)), mx = max(0, max(w1, w2));
     const int a = mx - mn;
-    if (a > M)
+    if (a > amax)
         return 0.0;
     const int b = (w1 + w2) - mn - mx - mn;
-    return cfull[(int64_t)a * (M + 1) + b] / norm;
+    const int row = a <= M ? a : a - M - 1;
+    return cfull[(int64_t)row * (M + 1) + b] / norm;
 }
 
 // Fourth-order table helpers.  The lag pairs (a, b), 0 <= b <= a <= M, are

@@ -159,11 +159,12 @@ struct C3Plan : SeriesPlan {
     int32_t NB;        // 32-blocks per tile side (2 or 4) = waves per workgroup
     int32_t TS;        // tile side in samples (32 * NB)
     int32_t NBR;       // 32-block rows: rows r = 0 .. M-1
+    int32_t amax;      // largest span in the table: M (hexagon) or 2M (square)
     int32_t nleft;     // leftover diagonal sums C[a][a], a = 0 and a = 32k <= M
     int32_t dot_blocks;// workgroups per leftover sum
     int64_t smax;      // partial slots per workgroup
     SkGeom sk;
-    size_t off_part, off_tfirst, off_cfull, off_dpart, off_twid, total;
+    size_t off_part, off_tfirst, off_cfull, off_dpart, off_twid, off_bfull, total;
 };
 
 // Trispectrum plan.  The lag pairs (a, b), 0 <= b <= a <= M, are numbered
@@ -195,7 +196,12 @@ constexpr int C4_MAX_NFFT = 512;   // N^3 complex128 <= 2 GiB
 constexpr int MOM_BLOCKS = 256;     // blocks of the moments pass
 constexpr int SK_MAX_WG = 256;      // persistent workgroups of the contraction
 
-int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p);
+// corners: also the square's corner lags (spans a = M+1 .. 2M, kept in the
+// table's upper triangle; their contraction reuses the partial-sum region);
+// full_grid: stage the N x N spectrum in the workspace (for a
+// principal-domain-only output).
+int make_c3_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C3Plan &p,
+                 bool corners = false, bool full_grid = false);
 // Host-side validation of a hos_bispectrum call (all but the workspace) and
 // its plan; no HIP call.
 int bispectrum_check(const void *x, int32_t dtype, int64_t n, int32_t M, int32_t window,
@@ -331,21 +337,29 @@ hipError_t launch_moments_piece(const void *x, int dtype, int64_t len, int first
                                 const SeriesPlan &p, char *ws, double *acc, hipStream_t s);
 hipError_t launch_moments_total(const double *acc, int64_t n, uint32_t flags, int top,
                                 double *stats, hipStream_t s);
-hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s);
+// region 0: the fundamental region F; region 1: the square's corners (the
+// Hankel columns M + 1 samples further on, spans a = M+1 .. 2M).
+hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s, int region = 0);
 hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws,
                            hipStream_t s, int64_t nfirst = -1);
-hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s);
-hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3,
+hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s, int region = 0);
+// c3 (lags of span <= c3_amax, 0 beyond) and the row transforms of B from a
+// table holding spans <= amax (stats[3] divides it).
+hipError_t launch_c3_finish(const C3Plan &p, int window, int nfft, double *c3, int c3_amax,
                             double *B, char *ws, hipStream_t s);
-hipError_t launch_c3_finish_table(const double *cfull, const double *stats, int M, int window,
-                                  int nfft, const double2 *tw, double *c3, double *B,
-                                  hipStream_t s);
+hipError_t launch_c3_finish_table(const double *cfull, const double *stats, int M, int amax,
+                                  int window, int nfft, const double2 *tw, double *c3,
+                                  int c3_amax, double *B, hipStream_t s);
+// B_pd[j] = the j-th principal-domain point (row-major k1, then k2) of the
+// N x N grid B.
+hipError_t launch_pd_gather(const double *B, int N, double *B_pd, hipStream_t s);
+bool bispectrum_needs_corners(int32_t window, uint32_t flags, bool want_B);
 hipError_t launch_seg_average(const BatchHeader &hdr, const char *dplan, char *ws,
                               hipStream_t s);
 bool fft_size_ok(int N);
 hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s);
-hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int N, int window,
-                            const double2 *tw, double *B, hipStream_t s);
+hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int amax, int N,
+                            int window, const double2 *tw, double *B, hipStream_t s);
 hipError_t launch_fft_cols(double *B, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double *stats, int M,
                             int N, int window, const double2 *tw, double *T, hipStream_t s);

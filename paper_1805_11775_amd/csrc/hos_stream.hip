@@ -42,12 +42,13 @@ k_table_add(double *__restrict__ acc, const double *__restrict__ add, int64_t co
 
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// samples piece k reads: its own, then up to M of the next piece's
+// samples piece k reads: its own, then up to `halo` of the next pieces' (M,
+// or 2M when the square's corners are computed)
 int64_t piece_len(int64_t n, int64_t P, int64_t k) { return n - k * P < P ? n - k * P : P; }
-int64_t piece_data(int64_t n, int32_t M, int64_t P, int64_t k)
+int64_t piece_data(int64_t n, int64_t halo, int64_t P, int64_t k)
 {
     const int64_t len = piece_len(n, P, k), rest = n - k * P;
-    return rest < len + M ? rest : len + M;
+    return rest < len + halo ? rest : len + halo;
 }
 
 struct StreamLayout {
@@ -61,20 +62,20 @@ int stream_layout(int64_t n, int32_t M, int32_t nfft, int32_t path, int64_t P, i
 {
     memset(&L, 0, sizeof(L));
     L.P = P;
-    L.halo = M;
-    // pieces k hold samples [kP, kP + len) and read data = min(len + M,
+    L.halo = 2 * (int64_t)M;   // the layout covers the corners whatever the window
+    // pieces k hold samples [kP, kP + len) and read data = min(len + halo,
     // n - kP) of them; every piece before the last two reads the same data
     // run as piece 0, so the plans of pieces 0, pieces-2 and pieces-1 bound
-    // them all
+    // them all (a shorter halo only shrinks a plan)
     const int64_t pieces = (n + P - 1) / P;
     size_t mx = 0;
     int64_t data_max = 0;
     for (int64_t k : {(int64_t)0, pieces - 2, pieces - 1}) {
         if (k < 0)
             continue;
-        const int64_t data = piece_data(n, M, P, k);
+        const int64_t data = piece_data(n, L.halo, P, k);
         C3Plan p;
-        make_c3_plan(data, M, path, nfft, p);
+        make_c3_plan(data, M, path, nfft, p, true);
         if (p.total > mx)
             mx = p.total;
         if (data > data_max)
@@ -188,7 +189,7 @@ static int check_stream_args(int64_t n, int32_t M, int32_t window, int32_t nfft,
         return HOS_EINVAL;
     if (window != HOS_WIN_NONE && window != HOS_WIN_PARZEN && window != HOS_WIN_PARZEN_SEPARABLE)
         return HOS_EINVAL;
-    if (flags & ~HOS_NO_CENTER)
+    if (flags & ~(HOS_NO_CENTER | HOS_FULL_SQUARE))
         return HOS_EINVAL;
     if (want_B) {
         if (!fft_size_ok(nfft))
@@ -254,7 +255,9 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
     // pass one: sum, minimum, maximum of the record, piece by piece (p0 is
     // the plan of a full piece with its halo, within the workspace layout)
     C3Plan p0;
-    make_c3_plan(piece_data(n, M, piece, 0), M, path, B ? nfft : 0, p0);
+    const bool corners = bispectrum_needs_corners(window, flags, B != nullptr);
+    const int64_t halo = corners ? 2 * (int64_t)M : M;
+    make_c3_plan(piece_data(n, halo, piece, 0), M, path, B ? nfft : 0, p0, corners);
     char *xd = nullptr;
     for (int64_t k = 0; k < pieces && e == hipSuccess; ++k) {
         const int64_t g0 = k * piece, len = piece_len(n, piece, k);
@@ -277,9 +280,9 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
     const int64_t ne = (int64_t)(M + 1) * (M + 1);
     for (int64_t k = 0; k < pieces && e == hipSuccess; ++k) {
         const int64_t g0 = k * piece, len = piece_len(n, piece, k);
-        const int64_t data = piece_data(n, M, piece, k);
+        const int64_t data = piece_data(n, halo, piece, k);
         C3Plan p;
-        make_c3_plan(data, M, path, B ? nfft : 0, p);
+        make_c3_plan(data, M, path, B ? nfft : 0, p, corners);
         if (al256(p.total) > L.plan_bytes) {   // the layout bounds every piece's plan
             e = hipErrorInvalidValue;
             break;
@@ -287,9 +290,11 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
         if (pieces > 1)
             e = stg.put(xh + g0 * esize, (size_t)data * esize, xd);
         if (e == hipSuccess) e = launch_prep(xd, dtype, p, w, stream, g0, len);
-        if (e == hipSuccess) e = launch_c3_contract(p, w, stream);
+        if (e == hipSuccess) e = launch_c3_contract(p, w, stream, 0);
         if (e == hipSuccess) e = launch_diag_dot(xd, dtype, p, w, stream, len);
-        if (e == hipSuccess) e = launch_c3_reduce(p, w, stream);
+        if (e == hipSuccess) e = launch_c3_reduce(p, w, stream, 0);
+        if (e == hipSuccess && corners) e = launch_c3_contract(p, w, stream, 1);
+        if (e == hipSuccess && corners) e = launch_c3_reduce(p, w, stream, 1);
         if (e == hipSuccess && pieces > 1) e = stg.done();
         if (e == hipSuccess) {
             k_table_add<<<(unsigned)((ne + 255) / 256), 256, 0, stream>>>(
@@ -303,7 +308,8 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
         if (B)
             e = launch_twiddles(tw, nfft, stream);
         if (e == hipSuccess)
-            e = launch_c3_finish_table(acc, stats, M, window, nfft, tw, c3, B, stream);
+            e = launch_c3_finish_table(acc, stats, M, p0.amax, window, nfft, tw, c3,
+                                       (flags & HOS_FULL_SQUARE) ? 2 * M : M, B, stream);
         if (e == hipSuccess && B)
             e = launch_fft_cols(B, nfft, tw, stream);
     }

@@ -24,7 +24,7 @@ k_bc3_out(const SeriesDesc *__restrict__ sd, const char *__restrict__ ws, double
     const char *r = ws + d.ws_off;
     const double *stats = (const double *)(r + d.o_stats);
     const int w1 = (int)(idx / side) - d.M, w2 = (int)(idx % side) - d.M;
-    c3[d.c3_off + idx] = c3_from_table((const double *)(r + d.o_cfull), d.M, stats[3], w1, w2);
+    c3[d.c3_off + idx] = c3_from_table((const double *)(r + d.o_cfull), d.M, d.M, stats[3], w1, w2);
 }
 
 // Per-series sum over the principal domain of |B - target|^2 (fixed order).

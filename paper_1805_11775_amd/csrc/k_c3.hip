@@ -422,11 +422,11 @@ template <int PATH, int NB, int NPW>
 __device__ __attribute__((always_inline)) inline void
 load_chunk(u32x4 (&stg)[NPW], const float *__restrict__ xf, const uint4 *__restrict__ win4,
            const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l, const SkPos &p,
-           int wave, int lane)
+           int wave, int lane, int64_t coff)
 {
     typedef ChunkLds<PATH, NB> CL;
     const int64_t i0 = p.c * KC;
-    const int64_t ra0 = i0 + (int64_t)p.R * CL::TS, rb0 = i0 + (int64_t)p.Cc * CL::TS;
+    const int64_t ra0 = i0 + (int64_t)p.R * CL::TS, rb0 = i0 + (int64_t)p.Cc * CL::TS + coff;
     const u32x4 *xf4 = (const u32x4 *)xf;
     const u32x4 *w4 = (const u32x4 *)win4, *w8h = (const u32x4 *)win8h,
                 *w8l = (const u32x4 *)win8l;
@@ -474,11 +474,11 @@ template <int PATH, int NB, int KCX>
 __device__ __attribute__((always_inline)) inline void
 load_chunk_dma(XiRegs<PATH, NB, KCX> &xr, const float *__restrict__ xf, const uint4 *__restrict__ win4,
                const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l, const SkPos &p,
-               ChunkLds<PATH, NB, KCX> &L, int wave, int lane)
+               ChunkLds<PATH, NB, KCX> &L, int wave, int lane, int64_t coff)
 {
     typedef ChunkLds<PATH, NB, KCX> CL;
     const int64_t i0 = p.c * KCX;
-    const int64_t ra0 = i0 + (int64_t)p.R * CL::TS, rb0 = i0 + (int64_t)p.Cc * CL::TS;
+    const int64_t ra0 = i0 + (int64_t)p.R * CL::TS, rb0 = i0 + (int64_t)p.Cc * CL::TS + coff;
     const u32x4 *xf4 = (const u32x4 *)xf;
     const u32x4 *w4 = (const u32x4 *)win4, *w8h = (const u32x4 *)win8h,
                 *w8l = (const u32x4 *)win8l;
@@ -538,12 +538,15 @@ store_chunk(const u32x4 (&stg)[NPW], ChunkLds<PATH, NB> &L, int wave, int lane, 
 }
 
 // The persistent contraction kernel: NB waves per workgroup, wave rw owning
-// the 32-row strip rw of every tile it visits.
+// the 32-row strip rw of every tile it visits.  coff shifts the Hankel
+// columns: 0 for the fundamental region (column b = sample offset b), M + 1
+// for the square's corners (column c = sample offset M + 1 + c, the same
+// lower-triangular tile set since a corner sum needs c <= r).
 template <int PATH, int NB>
 __global__ void __launch_bounds__(64 * NB, 1)
 k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
               const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
-              double *__restrict__ part, SkGeom g, int64_t smax, int NBR)
+              double *__restrict__ part, SkGeom g, int64_t smax, int NBR, int64_t coff)
 {
     constexpr bool SPLIT = PATH != HOS_PATH_FP32;
     // samples staged per barrier: split paths with 4-block tiles stage two
@@ -595,10 +598,10 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
     u32x4 stg[CL::NPW];
     XiRegs<PATH, NB, KCX> xr;
     if constexpr (!SPLIT) {
-        load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, q, wave, lane);
+        load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, q, wave, lane, coff);
         store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
     } else {
-        load_chunk_dma<PATH, NB, KCX>(xr, xf, win4, win8h, win8l, q, buf[0], wave, lane);
+        load_chunk_dma<PATH, NB, KCX>(xr, xf, win4, win8h, win8l, q, buf[0], wave, lane, coff);
         store_xi<PATH, NB, KCX>(xr, buf[0], wave, lane, q.c & 1);
     }
     __syncthreads();
@@ -615,10 +618,10 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
         const bool has_next = sk_next(g, nq) && sk_chunk_start(g, nq.R, nq.Cc, nq.c) < S1;
         if (has_next) {
             if constexpr (!SPLIT)
-                load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, nq, wave, lane);
+                load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, nq, wave, lane, coff);
             else
                 load_chunk_dma<PATH, NB, KCX>(xr, xf, win4, win8h, win8l, nq, buf[cur ^ 1],
-                                              wave, lane);
+                                              wave, lane, coff);
         }
 
         const float sgn = (q.c & 1) ? -1.0f : 1.0f;
@@ -698,7 +701,7 @@ k_sk_tfirst(SkGeom g, int64_t *__restrict__ tfirst)
 template <int NB>
 __global__ void __launch_bounds__(256)
 k_c3_reduce(const double *__restrict__ part, const int64_t *__restrict__ tfirst, SkGeom g,
-            int64_t smax, int NBR, int M, double *__restrict__ cfull)
+            int64_t smax, int NBR, int M, int corner, double *__restrict__ cfull)
 {
     constexpr int64_t TILE = (int64_t)(32 * NB) * (32 * NB);
     // blockIdx.x = (tile, 32-block, quarter of the block's 1024 elements)
@@ -729,8 +732,17 @@ k_c3_reduce(const double *__restrict__ part, const int64_t *__restrict__ tfirst,
     const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
     const int col = lane & 31;
     const int r = Rg * 32 + row, b = Bg * 32 + col;
-    if (r < M && (Bg < Rg || col <= row + 1))
-        cfull[(int64_t)(r + 1) * (M + 1) + b] = sum;
+    if (!corner) {
+        // F: C[r+1][b] for b <= r + 1
+        if (r < M && (Bg < Rg || col <= row + 1))
+            cfull[(int64_t)(r + 1) * (M + 1) + b] = sum;
+    } else {
+        // corners: column b is the offset M + 1 + b, so the sum is C[M+1+b][r+1],
+        // a lag of the square iff (M + 1 + b) - (r + 1) <= M, i.e. b <= r; it
+        // goes to the table's upper triangle at [b][r+1]
+        if (r < M && (Bg < Rg || col <= row))
+            cfull[(int64_t)b * (M + 1) + (r + 1)] = sum;
+    }
 }
 
 // Leftover diagonal sums C[a][a] = sum_i x~_i x~_{i+a}^2 for a = 0 and
@@ -924,10 +936,11 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
     u32x4 stg[CL::NPW];
     XiRegs<PATH, NB, KCX> xr;
     if constexpr (!SPLIT) {
-        load_chunk<PATH, NB, CL::NPW>(stg, sp.xf, sp.w4, sp.w8h, sp.w8l, q, wave, lane);
+        load_chunk<PATH, NB, CL::NPW>(stg, sp.xf, sp.w4, sp.w8h, sp.w8l, q, wave, lane, 0);
         store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
     } else {
-        load_chunk_dma<PATH, NB, KCX>(xr, sp.xf, sp.w4, sp.w8h, sp.w8l, q, buf[0], wave, lane);
+        load_chunk_dma<PATH, NB, KCX>(xr, sp.xf, sp.w4, sp.w8h, sp.w8l, q, buf[0], wave, lane,
+                                      0);
         store_xi<PATH, NB, KCX>(xr, buf[0], wave, lane, q.c & 1);
     }
     __syncthreads();
@@ -954,10 +967,10 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
         if (has_next) {
             if constexpr (!SPLIT)
                 load_chunk<PATH, NB, CL::NPW>(stg, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq, wave,
-                                              lane);
+                                              lane, 0);
             else
                 load_chunk_dma<PATH, NB, KCX>(xr, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq,
-                                              buf[cur ^ 1], wave, lane);
+                                              buf[cur ^ 1], wave, lane, 0);
         }
 
         const float sgn = (q.c & 1) ? -1.0f : 1.0f;
@@ -1107,31 +1120,34 @@ void launch_items_t(const BatchHeader &h, int cls, const char *dplan, char *ws, 
 }
 
 template <int PATH, int NB>
-void launch_contract_t(const C3Plan &p, char *ws, hipStream_t s)
+void launch_contract_t(const C3Plan &p, char *ws, hipStream_t s, int64_t coff)
 {
     k_c3_contract<PATH, NB><<<p.sk.G, 64 * NB, 0, s>>>(
         (const float *)(ws + p.off_xf), (const uint4 *)(ws + p.off_win4),
         (const uint4 *)(ws + p.off_win8h), (const uint4 *)(ws + p.off_win8l),
-        (double *)(ws + p.off_part), p.sk, p.smax, p.NBR);
+        (double *)(ws + p.off_part), p.sk, p.smax, p.NBR, coff);
 }
 
 }  // namespace
 
-hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s)
+hipError_t launch_c3_contract(const C3Plan &p, char *ws, hipStream_t s, int region)
 {
+    if (region == 1 && p.amax <= p.M)
+        return hipErrorInvalidValue;   // the plan has no corner rows
+    const int64_t coff = region == 1 ? (int64_t)p.M + 1 : 0;
     if (p.M > 0) {
         if (p.NB == 4) {
             if (p.path == HOS_PATH_FP32)
-                launch_contract_t<HOS_PATH_FP32, 4>(p, ws, s);
+                launch_contract_t<HOS_PATH_FP32, 4>(p, ws, s, coff);
             else if (p.path == HOS_PATH_SPLIT_FP16)
-                launch_contract_t<HOS_PATH_SPLIT_FP16, 4>(p, ws, s);
+                launch_contract_t<HOS_PATH_SPLIT_FP16, 4>(p, ws, s, coff);
             else
-                launch_contract_t<HOS_PATH_SPLIT_BF16, 4>(p, ws, s);
+                launch_contract_t<HOS_PATH_SPLIT_BF16, 4>(p, ws, s, coff);
         } else {
             if (p.path == HOS_PATH_SPLIT_FP16)
-                launch_contract_t<HOS_PATH_SPLIT_FP16, 2>(p, ws, s);
+                launch_contract_t<HOS_PATH_SPLIT_FP16, 2>(p, ws, s, coff);
             else
-                launch_contract_t<HOS_PATH_SPLIT_BF16, 2>(p, ws, s);
+                launch_contract_t<HOS_PATH_SPLIT_BF16, 2>(p, ws, s, coff);
         }
     }
     return hipGetLastError();
@@ -1163,8 +1179,10 @@ hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws, 
     return hipGetLastError();
 }
 
-hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s)
+hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s, int region)
 {
+    if (region == 1 && p.amax <= p.M)
+        return hipErrorInvalidValue;
     double *cfull = (double *)(ws + p.off_cfull);
     if (p.M > 0) {
         const int64_t ntiles = (int64_t)p.sk.TR * (p.sk.TR + 1) / 2;
@@ -1173,14 +1191,15 @@ hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s)
         if (NB == 4)
             k_c3_reduce<4><<<ntiles * NB * NB * 4, 256, 0, s>>>(
                 (const double *)(ws + p.off_part), (const int64_t *)(ws + p.off_tfirst), p.sk,
-                p.smax, p.NBR, p.M, cfull);
+                p.smax, p.NBR, p.M, region, cfull);
         else
             k_c3_reduce<2><<<ntiles * NB * NB * 4, 256, 0, s>>>(
                 (const double *)(ws + p.off_part), (const int64_t *)(ws + p.off_tfirst), p.sk,
-                p.smax, p.NBR, p.M, cfull);
+                p.smax, p.NBR, p.M, region, cfull);
     }
-    k_diag_final<<<p.nleft, 256, 0, s>>>((const double *)(ws + p.off_dpart), p.nleft,
-                                        p.dot_blocks, p.M, cfull);
+    if (region == 0)   // the diagonal sums C[a][a], a = 0 and a = 32k, belong to F
+        k_diag_final<<<p.nleft, 256, 0, s>>>((const double *)(ws + p.off_dpart), p.nleft,
+                                            p.dot_blocks, p.M, cfull);
     return hipGetLastError();
 }
 

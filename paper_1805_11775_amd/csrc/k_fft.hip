@@ -246,9 +246,9 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
                 for (int w2 = m2 - N; w2 <= m2; w2 += N) {
                     const int dw = w1 - w2;
                     if (w2 < -M || w2 > M || dw < -M || dw > M)
-                        continue;   // outside the hexagon c3 is 0
+                        continue;   // batches hold the hexagon only (Parzen window)
                     sum += dwin[abs(w1)] * dwin[abs(w2)] * (pdiff ? dwin[abs(dw)] : 1.0) *
-                           c3_from_table(cfull, M, norm, w1, w2);
+                           c3_from_table(cfull, M, M, norm, w1, w2);
                 }
             }
         }
@@ -315,7 +315,7 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
 template <int ELEMS, int THREADS>
 __global__ void __launch_bounds__(THREADS)
 k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, int M,
-            const double2 *__restrict__ tw, FftRadices fr, int CBP, int window,
+            int amax, const double2 *__restrict__ tw, FftRadices fr, int CBP, int window,
             double2 *__restrict__ B)
 {
     __shared__ double2 sm[ELEMS];
@@ -335,10 +335,15 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
                     continue;
                 for (int w2 = m2 - N; w2 <= m2; w2 += N) {
                     const int dw = w1 - w2;
-                    if (w2 < -M || w2 > M || dw < -M || dw > M)
+                    if (w2 < -M || w2 > M)
+                        continue;
+                    // the square's corners: 0 under the Parzen product (its
+                    // d(w1 - w2) vanishes from |w1 - w2| = M on), otherwise
+                    // taken from the table when it holds them
+                    if ((dw < -M || dw > M) && (pdiff || amax == M))
                         continue;
                     sum += dwin[abs(w1)] * dwin[abs(w2)] * (pdiff ? dwin[abs(dw)] : 1.0) *
-                           c3_from_table(cfull, M, norm, w1, w2);
+                           c3_from_table(cfull, M, amax, norm, w1, w2);
                 }
             }
         }
@@ -455,8 +460,8 @@ hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window
 }
 
 // Fold, window and row transforms of one series' N x N spectrum into B.
-hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int N, int window,
-                            const double2 *tw, double *B, hipStream_t s)
+hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int amax, int N,
+                            int window, const double2 *tw, double *B, hipStream_t s)
 {
     const FftRadices fr = factor(N);
     // long rows: 1024 threads, one butterfly per thread and stage
@@ -464,14 +469,14 @@ hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int
         const int CBP = PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
         const unsigned grid = (N + 2 * CBP - 1) / (2 * CBP);
         if (N >= 512)
-            k_full_rows<PD_LDS_ELEMS, 1024><<<grid, 1024, 0, s>>>(cfull, stats, M, tw, fr, CBP,
-                                                                window, (double2 *)B);
+            k_full_rows<PD_LDS_ELEMS, 1024><<<grid, 1024, 0, s>>>(cfull, stats, M, amax, tw, fr,
+                                                                CBP, window, (double2 *)B);
         else
             k_full_rows<PD_LDS_ELEMS, FFT_THREADS><<<grid, FFT_THREADS, 0, s>>>(
-                cfull, stats, M, tw, fr, CBP, window, (double2 *)B);
+                cfull, stats, M, amax, tw, fr, CBP, window, (double2 *)B);
     } else {
         k_full_rows<FFT_LDS_ELEMS, 1024><<<(N + 1) / 2, 1024, 0, s>>>(
-            cfull, stats, M, tw, fr, 1, window, (double2 *)B);
+            cfull, stats, M, amax, tw, fr, 1, window, (double2 *)B);
     }
     return hipGetLastError();
 }

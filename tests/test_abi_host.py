@@ -6,6 +6,7 @@ import re
 
 import pytest
 
+import oracle
 import paper_1805_11775_amd as hos
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -54,6 +55,11 @@ FAKE = 0x10000  # any aligned non-null address; validation fails before use
     (dict(ws=FAKE + 64), hos.HOS_EINVAL),    # workspace not 256-aligned
     (dict(c3=None, B=None), hos.HOS_EINVAL),
     (dict(ws_bytes=16), hos.HOS_EWORKSPACE),
+    (dict(n=(1 << 31) + 1, M=64), hos.HOS_EINVAL),      # beyond the series limit
+    (dict(flags=hos.HOS_FULL_SQUARE, ws_bytes=16), hos.HOS_EWORKSPACE),   # flag accepted
+    (dict(flags=hos.HOS_PD_ONLY | hos.HOS_FULL_SQUARE | hos.HOS_NO_CENTER, ws_bytes=16),
+     hos.HOS_EWORKSPACE),
+    (dict(flags=16), hos.HOS_EINVAL),                   # a batch-plan flag
 ])
 def test_validation_before_device(kw, code):
     a = dict(x=FAKE, dtype=hos.HOS_F32, n=4096, M=64, window=hos.HOS_WIN_PARZEN,
@@ -102,6 +108,25 @@ def test_noalloc_scratch_covers_the_headline_shape():
             hos.HOS_NOALLOC_SCRATCH_BYTES
 
 
+@pytest.mark.parametrize("n,M,N,path", [(1 << 20, 512, 1024, 1), (5000, 33, 72, 0),
+                                         (4096, 100, 200, 2)])
+def test_workspace_flags(n, M, N, path):
+    """The corner rows are in every layout (their need depends on the window,
+    which the query does not take); the principal-domain output stages the
+    full grid in the workspace."""
+    base = hos.hos_bispectrum_workspace(n, M, N, path)
+    assert hos.hos_bispectrum_workspace(n, M, N, path, hos.HOS_FULL_SQUARE) == base
+    pd = hos.hos_bispectrum_workspace(n, M, N, path, hos.HOS_PD_ONLY)
+    assert base + 16 * N * N <= pd <= base + 16 * N * N + 256
+    assert hos.hos_bispectrum_workspace(n, M, 0, path, hos.HOS_PD_ONLY) == \
+        hos.hos_bispectrum_workspace(n, M, 0, path)
+
+
+def test_pd_count_matches_the_oracle():
+    for N in (2, 3, 4, 7, 16, 33, 128, 1024):
+        assert hos.pd_count(N) == len(oracle.pd_indices(N)[0])
+
+
 def test_workspace_query():
     b = hos.hos_bispectrum_workspace(1 << 20, 512, 1024, hos.HOS_PATH_SPLIT_FP16)
     b32 = hos.hos_bispectrum_workspace(1 << 20, 512, 1024, hos.HOS_PATH_FP32)
@@ -143,6 +168,10 @@ def test_schedule_covers_every_chunk_once(n, M, path):
     (dict(T=FAKE + 8), hos.HOS_EINVAL),       # complex128 needs 16-byte alignment
     (dict(c4=None, T=None), hos.HOS_EINVAL),
     (dict(ws_bytes=1024), hos.HOS_EWORKSPACE),
+    # windows nonzero where the span exceeds M: outside the contraction's region
+    (dict(window=hos.HOS_WIN_NONE, nfft=100), hos.HOS_EUNSUPPORTED),
+    (dict(window=hos.HOS_WIN_PARZEN_SEPARABLE), hos.HOS_EUNSUPPORTED),
+    (dict(flags=hos.HOS_FULL_SQUARE), hos.HOS_EINVAL),
 ])
 def test_trispectrum_validation_before_device(kw, code):
     a = dict(x=FAKE, dtype=hos.HOS_F32, n=1 << 18, M=48, window=hos.HOS_WIN_PARZEN,
@@ -182,6 +211,8 @@ def test_c4_plan(n, M, path):
     (dict(c5=None, Q=None), hos.HOS_EINVAL),
     (dict(Q=FAKE + 8), hos.HOS_EINVAL),
     (dict(ws_bytes=16), hos.HOS_EWORKSPACE),
+    (dict(window=hos.HOS_WIN_NONE, nfft=18), hos.HOS_EUNSUPPORTED),
+    (dict(window=hos.HOS_WIN_PARZEN_SEPARABLE), hos.HOS_EUNSUPPORTED),
 ])
 def test_cumulant5_validation_before_device(kw, code):
     a = dict(x=FAKE, dtype=hos.HOS_F32, n=4096, M=8, window=hos.HOS_WIN_PARZEN,
@@ -210,6 +241,8 @@ def test_c5_plan():
     (dict(ws_bytes=1000), hos.HOS_EWORKSPACE),
     (dict(B=None, nfft=-1), hos.HOS_EINVAL),
     (dict(nfft=100), hos.HOS_EINVAL),          # below 2M with a window
+    (dict(flags=hos.HOS_FULL_SQUARE, ws_bytes=1000), hos.HOS_EWORKSPACE),   # accepted
+    (dict(flags=hos.HOS_PD_ONLY), hos.HOS_EINVAL),   # one series' call only
 ])
 def test_streamed_validation_before_device(kw, code):
     a = dict(x=FAKE, dtype=hos.HOS_F32, n=1 << 20, M=64, window=hos.HOS_WIN_PARZEN, nfft=128,

@@ -88,7 +88,17 @@ def test_lpt_balance(n, M, path):
         assert np.all(load > 0)
 
 
-@pytest.mark.parametrize("window", ["parzen", "none"])
+@pytest.mark.parametrize("window", ["none", "separable"])
+def test_plan_rejects_windows_nonzero_at_the_corners(window):
+    """Batches compute each series' hexagon only; the windows that do not
+    vanish at the square's corners are refused before any device work."""
+    n, M = synth.batched_series(8, 3)[1:]
+    with pytest.raises(hos.HosError) as e:
+        hos.BatchPlan(n, M, window=window, path="split_fp16")
+    assert e.value.status == hos.HOS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("window", ["parzen"])
 def test_series_layout(window):
     n, M = synth.batched_series(40, 3)[1:]
     plan = hos.BatchPlan(n, M, window=window, path="split_fp16")

@@ -160,22 +160,21 @@ def test_loss_gradient(path):
         assert e < TOL[path]
 
 
-def test_loss_gradient_no_window_float64():
+def test_loss_gradient_float64():
     hos = _hos()
-    n, M, N = 1500, 12, 25
+    n, M, N = 1500, 12, 24
     X = np.stack([synth.iid_exp_centered(n, 80 + b) for b in range(2)])
     tgt = synth.quadratic_process(n, 98)
     k1, k2 = oracle.pd_indices(N)
-    target = oracle.bispectrum(tgt, M, N, window="none")[1][k1, k2]
-    plan = hos.BatchPlan([n, n], [M, M], window="none", path="fp32", adjoint=True)
+    target = oracle.bispectrum(tgt, M, N)[1][k1, k2]
+    plan = hos.BatchPlan([n, n], [M, M], path="fp32", adjoint=True)
     x = torch.from_numpy(X).cuda()
     loss, B = hos.bispectrum_loss_fwd(x, torch.from_numpy(target), plan)
     dx = hos.bispectrum_loss_bwd(x, torch.from_numpy(target), B,
                                  torch.ones((), dtype=torch.float64), plan)
     torch.cuda.synchronize()
-    assert abs(float(loss) - oracle.bispectrum_loss(X, M, N, target, "none")) < \
-        1e-6 * float(loss)
-    ref = oracle.bispectrum_loss_grad(X, M, N, target, "none")
+    assert abs(float(loss) - oracle.bispectrum_loss(X, M, N, target)) < 1e-6 * float(loss)
+    ref = oracle.bispectrum_loss_grad(X, M, N, target)
     assert _rel(dx.cpu().numpy(), ref) < 1e-6
 
 
@@ -262,20 +261,6 @@ def test_forced_tile_classes_match_oracle(tile):
         assert _rel(got, c_ref) < 1e-5 and _rel(B[pdo:pdo + npd], B_ref[k1, k2]) < 1e-5, s
 
 
-def test_batch_separable_window():
-    hos = _hos()
-    xs, n, M = _uneven()
-    plan = hos.BatchPlan(n, M, window="separable", path="fp32")
-    x = torch.from_numpy(np.concatenate(xs)).cuda()
-    _, B = hos.bispectrum_batched(x, plan, return_c3=False)
-    torch.cuda.synchronize()
-    B = B.cpu().numpy()
-    S = plan.series()
-    for s in range(len(n)):
-        Ms, N, npd, pdo = (int(v) for v in (S[s, 1], S[s, 2], S[s, 3], S[s, 6]))
-        _, B_ref = oracle.bispectrum(xs[s], Ms, N, window="separable")
-        k1, k2 = oracle.pd_indices(N)
-        assert _rel(B[pdo:pdo + npd], B_ref[k1, k2]) < 1e-6, s
 
 
 @pytest.mark.parametrize("path", ["split_fp16", "fp32"])

@@ -29,14 +29,16 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-def _run(x_np, M, nfft=None, window="parzen", path="fp32", center=True, dtype=None):
+def _run(x_np, M, nfft=None, window="parzen", path="fp32", center=True, dtype=None,
+         full_square=False, pd_only=False):
     hos = _hos()
     t = torch.from_numpy(np.ascontiguousarray(x_np)).to("cuda")
     if dtype is not None:
         t = t.to(dtype)
-    print("case: n=%d M=%d nfft=%s window=%s path=%s dtype=%s" %
-          (t.numel(), M, nfft, window, path, t.dtype), flush=True)
-    c3, B = hos.bispectrum(t, M, nfft=nfft, window=window, path=path, center=center)
+    print("case: n=%d M=%d nfft=%s window=%s path=%s dtype=%s square=%s pd=%s" %
+          (t.numel(), M, nfft, window, path, t.dtype, full_square, pd_only), flush=True)
+    c3, B = hos.bispectrum(t, M, nfft=nfft, window=window, path=path, center=center,
+                           full_square=full_square, pd_only=pd_only)
     torch.cuda.synchronize()
     return c3.cpu().numpy(), B.cpu().numpy()
 
@@ -79,6 +81,83 @@ def test_gaussian_near_zero_cumulant(path):
     e = _rel(c3, oracle.c3_hexagon(x, 64))
     print("rel err c3 %.3e" % e)
     assert e < TOL[path]
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("n,M", [(700, 1), (701, 5), (3001, 31), (3001, 32), (3001, 33),
+                                 (4100, 95), (2500, 128), (3001, 160), (1537, 200),
+                                 (700, 100), (1024, 96), (2048, 129)])
+def test_full_square_grid(path, n, M):
+    """HOS_FULL_SQUARE: c3 at every lag of the square, the corners
+    |w1 - w2| > M included, element by element against the oracle's literal
+    sums over the whole square; on the hexagon it is bitwise the default
+    call's c3, and under the Parzen window (0 on the corners) B is too."""
+    x = synth.quadratic_process(n, 2000 + n + M).astype(np.float32)
+    c3, B = _run(x, M, path=path, full_square=True)
+    c3_ref, B_ref = oracle.bispectrum(x, M, B.shape[0], full_square=True)
+    e1, e2 = _rel(c3, c3_ref), _rel(B, B_ref)
+    corner = oracle.span3(M) > M
+    e3 = float(np.max(np.abs(c3 - c3_ref)[corner]) / np.max(np.abs(c3_ref))) if M > 0 else 0.0
+    print("rel err c3 %.3e (corners %.3e) B %.3e" % (e1, e3, e2))
+    assert e1 < TOL[path] and e2 < TOL[path], (n, M, e1, e2)
+    assert M == 0 or np.max(np.abs(c3[corner])) > 0.0
+    c3h, Bh = _run(x, M, path=path)
+    assert np.array_equal(c3h[~corner], c3[~corner]) and np.all(c3h[corner] == 0.0)
+    assert np.array_equal(Bh, B)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("window", ["none", "separable"])
+def test_windows_nonzero_on_the_corners(path, window):
+    """No window and the separable window weight the corners: B transforms
+    the sample cumulant over the whole square (computed internally whatever
+    the flags), against the oracle's; c3 stays on the hexagon unless asked."""
+    n, M = 5003, 130
+    x = synth.iid_exp_centered(n, 77).astype(np.float32)
+    N = 270   # 2 * 3^3 * 5 >= 2M + 1
+    c3, B = _run(x, M, nfft=N, window=window, path=path)
+    c3_ref, B_ref = oracle.bispectrum(x, M, N, window=window)
+    e1, e2 = _rel(c3, c3_ref), _rel(B, B_ref)
+    print("rel err c3 %.3e B %.3e" % (e1, e2))
+    assert e1 < TOL[path] and e2 < TOL[path]
+    assert np.all(c3[oracle.span3(M) > M] == 0.0)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("N", [128, 135, 150, 250])
+def test_principal_domain_only(path, N):
+    """HOS_PD_ONLY: B packed on 0 <= k2 <= k1, k1 + k2 < N/2 in row-major
+    order, bitwise the full grid's values there, and against the oracle."""
+    x = synth.quadratic_process(9000, 31).astype(np.float32)
+    M = 60
+    _, Bfull = _run(x, M, nfft=N, path=path)
+    _, Bpd = _run(x, M, nfft=N, path=path, pd_only=True)
+    k1, k2 = oracle.pd_indices(N)
+    assert Bpd.shape == (len(k1),)
+    assert np.array_equal(Bpd, Bfull[k1, k2])
+    B_ref = oracle.bispectrum_pd(x, M, N)
+    assert _rel(Bpd, B_ref) < TOL[path]
+
+
+@pytest.mark.timeout(600)
+def test_headline_full_square_against_oracle():
+    """n = 2^20 float32 quadratic process, M = 512, 1024-point DFT on the
+    split-FP16 path: c3 over the whole square ((2M+1)^2 lags: the hexagon
+    the benchmark times plus the corners) and B at every frequency, element
+    by element against the oracle (about 1.1e12 FP64 products)."""
+    x, cfg = synth.workload_long_bispectrum()
+    M, N = cfg["M"], cfg["nfft"]
+    c3, B = _run(x, M, N, path="split_fp16", full_square=True)
+    print("oracle: full square at n=%d M=%d" % (x.size, M), flush=True)
+    c3_ref, B_ref = oracle.bispectrum(x, M, N, full_square=True)
+    hexagon = oracle.span3(M) <= M
+    e_hex = float(np.max(np.abs(c3 - c3_ref)[hexagon]) / np.max(np.abs(c3_ref[hexagon])))
+    e_sq, e_B = _rel(c3, c3_ref), _rel(B, B_ref)
+    print("rel err c3 hexagon %.3e square %.3e B %.3e" % (e_hex, e_sq, e_B), flush=True)
+    assert e_hex < 1e-5 and e_sq < 1e-5 and e_B < 1e-5
+    # the benchmark's call (hexagon) returns bitwise the same hexagon
+    c3h, Bh = _run(x, M, N, path="split_fp16")
+    assert np.array_equal(c3h[hexagon], c3[hexagon]) and np.array_equal(Bh, B)
 
 
 @pytest.mark.parametrize("window", ["none", "parzen", "separable"])

@@ -36,9 +36,9 @@ def _err(a, b):
 @pytest.mark.parametrize("path", list(TOL))
 @pytest.mark.parametrize("n,P,M,window", [
     (4000, 1000, 20, "parzen"),     # four segments
-    (5003, 1000, 33, "none"),       # trailing samples unused, odd DFT size
+    (5003, 1000, 33, "parzen"),     # trailing samples unused
     (3000, 3000, 64, "parzen"),     # one segment
-    (9000, 300, 5, "separable"),    # thirty short segments
+    (9000, 300, 5, "parzen"),       # thirty short segments
     (2400, 600, 100, "parzen"),     # 4 x 4-block tiles
 ])
 def test_parity(path, n, P, M, window):

@@ -63,8 +63,8 @@ def test_matches_in_memory_call_at_size(path):
     oracle at sampled lags."""
     hos = _hos()
     x = synth.quadratic_process(1 << 22, 77).astype(np.float32)
-    cs, Bs = hos.bispectrum_streamed(torch.from_numpy(x).pin_memory(), 512, piece=1 << 20,
-                                     path=path)
+    xh = torch.from_numpy(x).pin_memory()   # held until the copies have landed
+    cs, Bs = hos.bispectrum_streamed(xh, 512, piece=1 << 20, path=path)
     cm, Bm = hos.bispectrum(torch.from_numpy(x).cuda(), 512, path=path)
     torch.cuda.synchronize()
     cs, cm = cs.cpu().numpy(), cm.cpu().numpy()
@@ -79,6 +79,32 @@ def test_matches_in_memory_call_at_size(path):
     e = float(np.max(np.abs(cs[w[:, 0] + 512, w[:, 1] + 512] - ref)) / np.max(np.abs(ref)))
     print("sampled rel err %.3e" % e)
     assert e < TOL[path]
+
+
+@pytest.mark.parametrize("path", list(TOL))
+@pytest.mark.parametrize("n,M,piece,window", [
+    (20000, 64, 4096, "parzen"),       # five pieces, halo 2M = 128
+    (8242, 100, 4096, "parzen"),       # last piece of 50 samples, halo 200
+    (13000, 150, 4096, "separable"),   # corners weighted by the window
+    (9000, 30, 4096, "none"),
+])
+def test_full_square(path, n, M, piece, window):
+    """HOS_FULL_SQUARE on a streamed record: every piece carries a 2M-sample
+    halo so the corner sums (offsets up to 2M) see the next pieces' samples;
+    c3 over the whole square and B against the oracle."""
+    hos = _hos()
+    x = synth.quadratic_process(n, 700 + n).astype(np.float32)
+    xh = torch.from_numpy(x)
+    N = hos.default_nfft(M, window)
+    print("case: square n=%d M=%d piece=%d window=%s path=%s" % (n, M, piece, window, path),
+          flush=True)
+    c3, B = hos.bispectrum_streamed(xh, M, piece=piece, nfft=N, window=window, path=path,
+                                    full_square=True)
+    torch.cuda.synchronize()
+    c_ref, B_ref = oracle.bispectrum(x, M, N, window=window, full_square=True)
+    e1, e2 = _err(c3.cpu().numpy(), c_ref), _err(B.cpu().numpy(), B_ref)
+    print("rel err c3 %.3e B %.3e" % (e1, e2))
+    assert e1 < TOL[path] and e2 < TOL[path]
 
 
 @pytest.mark.parametrize("M,nfft,window,return_B", [
