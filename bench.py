@@ -333,9 +333,9 @@ def bench_batched(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0
                                   "Exp(1)-1; Parzen window, N = 2M; principal-domain spectra; "
                                   "tiles from the autotuner",
                       "series": len(n), "samples": int(np.sum(n)), "path": head},
-           # the item contraction runs as one launch per tile class (4 x 4 and
-           # 2 x 2 blocks); the entry point's stage events time them together
-           "roofline": {"bound": "mfma", "kernel": "k_c3_items",
+           # one persistent launch over the work items of both tile classes
+           # (4 x 4 and 2 x 2 blocks; k_c3_items_u, or k_c3_items on the FP32 path)
+           "roofline": {"bound": "mfma", "kernel": "k_c3_items_u" if head != "fp32" else "k_c3_items",
                         "achieved": h["contract_tflops"], "peak": PEAK[head] / 1e12,
                         "unit": "TFLOP/s", "frac": h["contract_frac"], "traffic": None,
                         "flops_per_call": flops, "avg_call_ms": h["stage_ms"]["contract"]},

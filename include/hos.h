@@ -399,8 +399,11 @@ int hos_batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t wi
  * tile classes (items0, items1, G0, G1), the common M (or -1), the largest
  * principal domain.  hos_batch_series: 8 int64 per series = n, M, N, npd,
  * x offset, c3 offset, B offset, tile class.  hos_batch_items: 8 int64 per
- * work item of class cls = class, workgroup, series, tile row, tile
- * column, first chunk, end chunk, partial slot. */
+ * work item of class cls (0: 2 x 2 blocks, 1: 4 x 4 blocks, -1: every item)
+ * in launch order = class, workgroup, series, tile row, tile column, first
+ * chunk, end chunk, partial slot.  The contraction is ONE persistent launch
+ * over the items of both classes (G0 = G1 workgroups); a workgroup runs its
+ * 4 x 4 items, then its 2 x 2 items. */
 int hos_batch_plan_info(const void *plan, int64_t *info, int32_t ninfo);
 int hos_batch_series(const void *plan, int64_t *out, int64_t cap);
 int hos_batch_items(const void *plan, int32_t cls, int64_t *out, int64_t cap);

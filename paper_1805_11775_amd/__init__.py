@@ -617,8 +617,11 @@ class BatchPlan:
         return out
 
     def items(self, cls):
+        """Work items of tile class cls (0: 2 x 2 blocks, 1: 4 x 4 blocks, -1:
+        all) in launch order, 8 columns (see hos_batch_items)."""
         import numpy as np
-        k = self.info["items%d" % cls]
+        k = (self.info["items0"] + self.info["items1"]) if cls < 0 else \
+            self.info["items%d" % cls]
         out = np.zeros((max(k, 1), 8), dtype=np.int64)
         st = lib().hos_batch_items(self.host.ctypes.data, int(cls), _i64p(out), out.size)
         if st != HOS_OK:

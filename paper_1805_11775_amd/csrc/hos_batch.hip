@@ -123,7 +123,7 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         d.NBR = (d.M + 31) / 32;
         d.TR = d.NBR > 0 ? (d.NBR + d.NB - 1) / d.NB : 0;
         d.nleft = 1 + d.M / 32;
-        const int64_t kcx = c3_stage_len(path, d.NB);   // samples per chunk
+        const int64_t kcx = batch_stage_len(path);   // samples per chunk, both classes
         d.C = (d.n + kcx - 1) / kcx;
         d.KP = adj ? (int32_t)up(2 * d.M + 1, 32) : 0;
         d.lpad = adj ? up(d.M, 64) : 0;
@@ -215,54 +215,67 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         o = a256(o + a256((ne + 64) * sizeof(double)) + (size_t)sd[0].N * 16);
     }
 
-    // contraction work items, per tile class
-    std::vector<C3Item> items[BATCH_CLASSES];
-    std::vector<int32_t> wgfirst[BATCH_CLASSES];
+    // Contraction work items of both tile classes in ONE list for one
+    // persistent launch: every (series, tile) is cut into chunk ranges of
+    // about `piece` cost units, and the items go to the workgroups by the
+    // longest-processing-time rule.  Cost of one chunk: split paths, 14 for
+    // a 4 x 4-block tile (its busiest wave: 4 blocks x 1024 samples) and 5
+    // for a 2 x 2-block tile (2 blocks x 512 samples: a quarter of the
+    // matrix-core work at twice the product-row work per block; the ratio
+    // 2.8 is the one the contraction's timings give on MI355X, e.g. 1 tile
+    // of 4 x 4 blocks against 3 tiles of 2 x 2 blocks at M = 128); FP32 path
+    // (4 x 4 blocks only, 2 x 2 windows per wave), 4 off and 3 on the
+    // diagonal.  Partial slots are numbered per class (one partial arena
+    // and tile list per class).
+    std::vector<C3Item> items;
+    std::vector<int64_t> cost;
+    std::vector<int32_t> wgfirst;
     std::vector<C3TileRef> tiles[BATCH_CLASSES];
-    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
-        const int64_t gmax = cls ? 256 : 512;
-        const int cf = split ? 1 : 4, cd = split ? 1 : 3;
-        int64_t units = 0;
-        for (auto &d : sd)
-            if (d.cls == cls)
-                units += ((int64_t)d.TR * (d.TR - 1) / 2 * cf + (int64_t)d.TR * cd) * d.C;
-        if (units == 0)
-            continue;
-        const int64_t piece = std::max<int64_t>(1, units / (4 * gmax));  // cost per item
-        std::vector<int64_t> cost;
-        int64_t slot = 0;
-        for (int s = 0; s < batch; ++s) {
-            const SeriesDesc &d = sd[s];
-            if (d.cls != cls)
-                continue;
-            for (int R = 0; R < d.TR; ++R)
-                for (int Cc = 0; Cc <= R; ++Cc) {
-                    const int ct = Cc == R ? cd : cf;
-                    const int64_t pc = std::max<int64_t>(1, piece / ct);
-                    C3TileRef t;
-                    t.series = s;
-                    t.R = R;
-                    t.Cc = Cc;
-                    t.slot0 = slot;
-                    t.nslot = 0;
-                    for (int64_t c0 = 0; c0 < d.C; c0 += pc) {
-                        C3Item it;
-                        it.series = s;
-                        it.R = R;
-                        it.Cc = Cc;
-                        it.pad = 0;
-                        it.c0 = c0;
-                        it.c1 = std::min<int64_t>(d.C, c0 + pc);
-                        it.slot = slot++;
-                        items[cls].push_back(it);
-                        cost.push_back((it.c1 - it.c0) * ct);
-                        t.nslot++;
-                    }
-                    tiles[cls].push_back(t);
+    auto chunk_cost = [&](int cls, bool diag) -> int {
+        if (!split)
+            return diag ? 3 : 4;
+        return cls ? 14 : 5;
+    };
+    int64_t units = 0;
+    for (auto &d : sd)
+        for (int R = 0; R < d.TR; ++R)
+            for (int Cc = 0; Cc <= R; ++Cc)
+                units += chunk_cost(d.cls, Cc == R) * d.C;
+    const int64_t gmax = BATCH_MAX_WG;
+    const int64_t piece = std::max<int64_t>(1, units / (4 * gmax));  // cost per item
+    int64_t slots[BATCH_CLASSES] = {0, 0};
+    for (int s = 0; s < batch; ++s) {
+        const SeriesDesc &d = sd[s];
+        for (int R = 0; R < d.TR; ++R)
+            for (int Cc = 0; Cc <= R; ++Cc) {
+                const int ct = chunk_cost(d.cls, Cc == R);
+                const int64_t pc = std::max<int64_t>(1, piece / ct);
+                C3TileRef t;
+                t.series = s;
+                t.R = R;
+                t.Cc = Cc;
+                t.slot0 = slots[d.cls];
+                t.nslot = 0;
+                for (int64_t c0 = 0; c0 < d.C; c0 += pc) {
+                    C3Item it;
+                    it.series = s;
+                    it.R = R;
+                    it.Cc = Cc;
+                    it.pad = d.cls;
+                    it.c0 = c0;
+                    it.c1 = std::min<int64_t>(d.C, c0 + pc);
+                    it.slot = slots[d.cls]++;
+                    items.push_back(it);
+                    cost.push_back((it.c1 - it.c0) * ct);
+                    t.nslot++;
+                    h.n_items[d.cls]++;
                 }
-        }
-        const int64_t ni = (int64_t)items[cls].size();
-        const int64_t G = std::min<int64_t>(gmax, ni);
+                tiles[d.cls].push_back(t);
+            }
+    }
+    const int64_t ni = (int64_t)items.size();
+    const int64_t G = std::min<int64_t>(gmax, ni);
+    if (ni > 0) {
         // longest processing time first, ties in plan order
         std::vector<int64_t> ord(ni);
         for (int64_t k = 0; k < ni; ++k)
@@ -282,31 +295,37 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         }
         std::vector<C3Item> sorted;
         sorted.reserve(ni);
-        wgfirst[cls].push_back(0);
+        wgfirst.push_back(0);
         for (int64_t w = 0; w < G; ++w) {
-            for (int64_t k : per[w])
-                sorted.push_back(items[cls][k]);
-            wgfirst[cls].push_back((int32_t)sorted.size());
+            // the kernel runs a workgroup's 4 x 4-block items first, then its
+            // 2 x 2-block items (one loop per class)
+            for (int cls = 1; cls >= 0; --cls)
+                for (int64_t k : per[w])
+                    if (items[k].pad == cls)
+                        sorted.push_back(items[k]);
+            wgfirst.push_back((int32_t)sorted.size());
         }
-        items[cls].swap(sorted);
-        h.n_items[cls] = ni;
+        items.swap(sorted);
+    }
+    h.n_items_all = ni;
+    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
         h.G[cls] = G;
         h.n_tiles[cls] = (int64_t)tiles[cls].size();
         const int64_t tile = (int64_t)(32 * (cls ? 4 : 2)) * (32 * (cls ? 4 : 2));
         h.part_off[cls] = (int64_t)o;
-        o = a256(o + (size_t)slot * tile * sizeof(double));
+        o = a256(o + (size_t)slots[cls] * tile * sizeof(double));
     }
     h.ws_bytes = (int64_t)o;
 
-    // blob: header | series | (items | wgfirst | tiles) per class | groups
+    // blob: header | series | items | wgfirst | tiles per class | groups
     size_t b = up(sizeof(BatchHeader), 64);
     h.series_off = (int64_t)b;
     b += sizeof(SeriesDesc) * batch;
+    h.items_off = (int64_t)b;
+    b += sizeof(C3Item) * items.size();
+    h.wgfirst_off = (int64_t)b;
+    b += up(sizeof(int32_t) * wgfirst.size(), 8);
     for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
-        h.items_off[cls] = (int64_t)b;
-        b += sizeof(C3Item) * items[cls].size();
-        h.wgfirst_off[cls] = (int64_t)b;
-        b += up(sizeof(int32_t) * wgfirst[cls].size(), 8);
         h.tiles_off[cls] = (int64_t)b;
         b += sizeof(C3TileRef) * tiles[cls].size();
     }
@@ -327,15 +346,13 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
     memset(p, 0, h.blob_bytes);
     memcpy(p, &h, sizeof(h));
     memcpy(p + h.series_off, sd.data(), sizeof(SeriesDesc) * batch);
-    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
-        if (!items[cls].empty())
-            memcpy(p + h.items_off[cls], items[cls].data(), sizeof(C3Item) * items[cls].size());
-        if (!wgfirst[cls].empty())
-            memcpy(p + h.wgfirst_off[cls], wgfirst[cls].data(),
-                   sizeof(int32_t) * wgfirst[cls].size());
+    if (!items.empty())
+        memcpy(p + h.items_off, items.data(), sizeof(C3Item) * items.size());
+    if (!wgfirst.empty())
+        memcpy(p + h.wgfirst_off, wgfirst.data(), sizeof(int32_t) * wgfirst.size());
+    for (int cls = 0; cls < BATCH_CLASSES; ++cls)
         if (!tiles[cls].empty())
             memcpy(p + h.tiles_off[cls], tiles[cls].data(), sizeof(C3TileRef) * tiles[cls].size());
-    }
     memcpy(p + h.groups_off, groups.data(), sizeof(FftGroup) * groups.size());
     memcpy(p + h.gseries_off, gseries.data(), sizeof(int32_t) * batch);
     return HOS_OK;
@@ -409,18 +426,23 @@ int hos_batch_plan_info(const void *plan, int64_t *info, int32_t ninfo)
 int hos_batch_items(const void *plan, int32_t cls, int64_t *out, int64_t cap)
 {
     const BatchHeader *h = plan_header(plan);
-    if (!h || !out || cls < 0 || cls >= BATCH_CLASSES)
+    if (!h || !out || cls < -1 || cls >= BATCH_CLASSES)
         return HOS_EINVAL;
-    const int64_t ni = h->n_items[cls];
+    const int64_t ni = cls < 0 ? h->n_items_all : h->n_items[cls];
     if (cap < ni * 8)
         return HOS_EINVAL;
+    if (h->n_items_all == 0)
+        return HOS_OK;
     const char *p = (const char *)plan;
-    const C3Item *it = (const C3Item *)(p + h->items_off[cls]);
-    const int32_t *wf = (const int32_t *)(p + h->wgfirst_off[cls]);
-    for (int64_t w = 0; w < h->G[cls]; ++w)
+    const C3Item *it = (const C3Item *)(p + h->items_off);
+    const int32_t *wf = (const int32_t *)(p + h->wgfirst_off);
+    int64_t row = 0;
+    for (int64_t w = 0; w < h->G[0]; ++w)
         for (int64_t k = wf[w]; k < wf[w + 1]; ++k) {
-            int64_t *r = out + 8 * k;
-            r[0] = cls;
+            if (cls >= 0 && it[k].pad != cls)
+                continue;
+            int64_t *r = out + 8 * row++;
+            r[0] = it[k].pad;
             r[1] = w;
             r[2] = it[k].series;
             r[3] = it[k].R;

@@ -236,7 +236,8 @@ struct SeriesDesc {
 };
 
 struct C3Item {           // one (series, tile, chunk range) of the contraction
-    int32_t series, R, Cc, pad;
+    int32_t series, R, Cc;
+    int32_t pad;          // tile class: 1 = 4 x 4 blocks, 0 = 2 x 2 blocks
     int64_t c0, c1;       // chunks [c0, c1)
     int64_t slot;         // partial tile written
 };
@@ -255,6 +256,7 @@ struct FftGroup {         // series sharing one DFT size, grids contiguous
 
 constexpr int64_t BATCH_MAGIC = 0x484f53424154434bLL;   // "HOSBATCK"
 constexpr int BATCH_CLASSES = 2;                         // tiles of 2 x 2 / 4 x 4 blocks
+constexpr int BATCH_MAX_WG = 256;                        // persistent workgroups, one per CU
 
 struct BatchHeader {
     int64_t magic, blob_bytes, ws_bytes;
@@ -264,8 +266,9 @@ struct BatchHeader {
     int64_t uniform_M, uniform_n;   // shared by every series, else -1
     int64_t c3_total, pd_total, x_total;
     int64_t series_off;             // byte offsets of the arrays inside the blob
-    int64_t items_off[BATCH_CLASSES], n_items[BATCH_CLASSES];
-    int64_t wgfirst_off[BATCH_CLASSES], G[BATCH_CLASSES];
+    int64_t items_off, n_items_all;  // every work item, both classes, in workgroup order
+    int64_t n_items[BATCH_CLASSES];  // items per class
+    int64_t wgfirst_off, G[BATCH_CLASSES];   // one launch: G[0] = G[1] workgroups
     int64_t tiles_off[BATCH_CLASSES], n_tiles[BATCH_CLASSES];
     int64_t part_off[BATCH_CLASSES];  // byte offsets of the partial arenas in the workspace
     int64_t groups_off, n_groups;
@@ -324,6 +327,13 @@ inline int64_t tile_elems(int NB) { return (int64_t)(32 * NB) * (32 * NB); }
 __host__ __device__ constexpr int c3_stage_len(int path, int NB)
 {
     return (path != HOS_PATH_FP32 && NB == 4) ? 2 * KC : KC;
+}
+
+// Samples per staged chunk of the batch contraction: both tile classes of
+// the split paths stage 1024 samples (one launch, one LDS layout size).
+__host__ __device__ constexpr int batch_stage_len(int path)
+{
+    return path != HOS_PATH_FP32 ? 2 * KC : KC;
 }
 
 // ---------------------------------------------------------------------------

@@ -115,9 +115,11 @@ __device__ __attribute__((always_inline)) inline void pin_agpr(double &v)
 }
 
 // sgn = -1 undoes the negated product rows of an odd chunk (see below).
-template <int NB, bool PIN>
-__device__ inline void flush_acc(floatx16 (&acc)[NB], double (&acc64)[NB][16], float sgn)
+// The first NB of the NA accumulator blocks are flushed.
+template <int NB, bool PIN, int NA = NB>
+__device__ inline void flush_acc(floatx16 (&acc)[NA], double (&acc64)[NA][16], float sgn)
 {
+    static_assert(NB <= NA, "flushing more blocks than the arrays hold");
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
@@ -210,12 +212,13 @@ __device__ __attribute__((always_inline)) inline void split_rows(Yrow<PATH> &y, 
 // the LDS latency); only VALU ops may cross them, so the split interleaves
 // with the matrix-core ops.  The FP32 path has the same structure with one
 // multiply per product and 8 matrix-core steps per block per group.
-template <int PATH, int NB, int NCOL>
+template <int PATH, int NB, int NCOL, int NA = NB>
 __device__ __attribute__((always_inline)) inline void chunk_compute(const float4 *__restrict__ sxi,
                                      const float4 *__restrict__ sxa,
                                      const uint4 *__restrict__ sxb, int wlen, int rw, int rl,
-                                     int h, floatx16 (&acc)[NB], double (&acc64)[NB][16])
+                                     int h, floatx16 (&acc)[NA], double (&acc64)[NA][16])
 {
+    static_assert(NCOL <= NB && NB <= NA, "column blocks beyond the accumulator arrays");
     constexpr int NG = KC / GROUP;
     constexpr int UMAX = NG - 1 + 2 * (NCOL - 1);   // last window used
     constexpr bool SPLIT = PATH != HOS_PATH_FP32;
@@ -370,36 +373,38 @@ __device__ inline int wave_cols(int NB, bool diag, int rw, int tileR, int NBR)
     return diag ? rw + 1 : NB;
 }
 
-template <int PATH, int NB>
+// NB: column blocks of the tile; the accumulator arrays hold NA >= NB blocks.
+template <int PATH, int NB, int NA = NB>
 __device__ __attribute__((always_inline)) inline void dispatch_compute(int ncol, const float4 *sxi, const float4 *sxa,
                                         const uint4 *sxb, int wlen, int rw, int rl, int h,
-                                        floatx16 (&acc)[NB], double (&acc64)[NB][16])
+                                        floatx16 (&acc)[NA], double (&acc64)[NA][16])
 {
     switch (ncol) {
     case 1:
-        chunk_compute<PATH, NB, 1>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+        chunk_compute<PATH, NB, 1, NA>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
         break;
     case 2:
-        chunk_compute<PATH, NB, 2>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+        chunk_compute<PATH, NB, 2, NA>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
         break;
     case 3:
         if constexpr (NB >= 3)
-            chunk_compute<PATH, NB, 3>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+            chunk_compute<PATH, NB, 3, NA>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
         break;
     case 4:
         if constexpr (NB >= 4)
-            chunk_compute<PATH, NB, 4>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+            chunk_compute<PATH, NB, 4, NA>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
         break;
     default:
         break;  // 0: this strip has no output in the tile
     }
 }
 
-// One chunk's LDS operands (xi | xa | xb, contiguous 16-byte entries).
-template <int PATH, int NB, int KCX = KC>
+// One chunk's LDS operands (xi | xa | xb, contiguous 16-byte entries) for
+// a tile of NB x NB blocks, staged by a workgroup of NWG waves.
+template <int PATH, int NB, int KCX = KC, int NWG = NB>
 struct ChunkLds {
     static constexpr bool SPLIT = PATH != HOS_PATH_FP32;
-    static constexpr int NW = NB;                   // waves per workgroup
+    static constexpr int NW = NWG;                  // waves per workgroup
     static constexpr int TS = 32 * NB;
     static constexpr int WLEN = KCX + TS;           // window entries per chunk
     static constexpr int NXI = KCX / 4;             // float4 entries of x_i
@@ -463,20 +468,20 @@ typedef __attribute__((address_space(1))) void glb_void_t;
 // depends on the chunk's parity, passes through registers.  The loads land in
 // the buffer the workgroup is not computing on; store_xi waits for them
 // before the barrier that hands the buffer over.
-template <int PATH, int NB, int KCX>
-struct XiRegs {
-    typedef ChunkLds<PATH, NB, KCX> CL;
-    static constexpr int N = (CL::NXI / 64 + CL::NW - 1) / CL::NW;
+template <int N>
+struct XiRegsN {
     u32x4 r[N];
 };
+template <class CL>
+using XiRegs = XiRegsN<(CL::NXI / 64 + CL::NW - 1) / CL::NW>;
 
-template <int PATH, int NB, int KCX>
+template <class CL>
 __device__ __attribute__((always_inline)) inline void
-load_chunk_dma(XiRegs<PATH, NB, KCX> &xr, const float *__restrict__ xf, const uint4 *__restrict__ win4,
+load_chunk_dma(XiRegs<CL> &xr, const float *__restrict__ xf, const uint4 *__restrict__ win4,
                const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l, const SkPos &p,
-               ChunkLds<PATH, NB, KCX> &L, int wave, int lane, int64_t coff)
+               CL &L, int wave, int lane, int64_t coff)
 {
-    typedef ChunkLds<PATH, NB, KCX> CL;
+    constexpr int KCX = CL::NXI * 4;
     const int64_t i0 = p.c * KCX;
     const int64_t ra0 = i0 + (int64_t)p.R * CL::TS, rb0 = i0 + (int64_t)p.Cc * CL::TS + coff;
     const u32x4 *xf4 = (const u32x4 *)xf;
@@ -490,7 +495,7 @@ load_chunk_dma(XiRegs<PATH, NB, KCX> &xr, const float *__restrict__ xf, const ui
         if (j >= CL::NCH)
             continue;
         if (e < CL::NXI) {
-            if (m < XiRegs<PATH, NB, KCX>::N)
+            if (m < (int)(sizeof(xr.r) / sizeof(xr.r[0])))
                 xr.r[m] = xf4[(i0 >> 2) + e + lane];
             continue;
         }
@@ -506,14 +511,13 @@ load_chunk_dma(XiRegs<PATH, NB, KCX> &xr, const float *__restrict__ xf, const ui
     }
 }
 
-template <int PATH, int NB, int KCX>
+template <class CL>
 __device__ __attribute__((always_inline)) inline void
-store_xi(const XiRegs<PATH, NB, KCX> &xr, ChunkLds<PATH, NB, KCX> &L, int wave, int lane, bool neg)
+store_xi(const XiRegs<CL> &xr, CL &L, int wave, int lane, bool neg)
 {
-    typedef ChunkLds<PATH, NB, KCX> CL;
     u32x4 *base = (u32x4 *)&L;
 #pragma unroll
-    for (int m = 0; m < XiRegs<PATH, NB, KCX>::N; ++m) {
+    for (int m = 0; m < (int)(sizeof(xr.r) / sizeof(xr.r[0])); ++m) {
         const int j = wave + CL::NW * m;
         if (64 * j < CL::NXI)
             base[64 * j + lane] = xr.r[m] ^ (neg ? 0x80000000u : 0u);
@@ -596,13 +600,13 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
     set_layout(q);
 
     u32x4 stg[CL::NPW];
-    XiRegs<PATH, NB, KCX> xr;
+    XiRegs<CL> xr;
     if constexpr (!SPLIT) {
         load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, q, wave, lane, coff);
         store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
     } else {
-        load_chunk_dma<PATH, NB, KCX>(xr, xf, win4, win8h, win8l, q, buf[0], wave, lane, coff);
-        store_xi<PATH, NB, KCX>(xr, buf[0], wave, lane, q.c & 1);
+        load_chunk_dma<CL>(xr, xf, win4, win8h, win8l, q, buf[0], wave, lane, coff);
+        store_xi<CL>(xr, buf[0], wave, lane, q.c & 1);
     }
     __syncthreads();
 
@@ -620,7 +624,7 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
             if constexpr (!SPLIT)
                 load_chunk<PATH, NB, CL::NPW>(stg, xf, win4, win8h, win8l, nq, wave, lane, coff);
             else
-                load_chunk_dma<PATH, NB, KCX>(xr, xf, win4, win8h, win8l, nq, buf[cur ^ 1],
+                load_chunk_dma<CL>(xr, xf, win4, win8h, win8l, nq, buf[cur ^ 1],
                                               wave, lane, coff);
         }
 
@@ -673,7 +677,7 @@ k_c3_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
         if constexpr (!SPLIT)
             store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane, nq.c & 1);
         else
-            store_xi<PATH, NB, KCX>(xr, buf[cur], wave, lane, nq.c & 1);
+            store_xi<CL>(xr, buf[cur], wave, lane, nq.c & 1);
         __syncthreads();
         if (seg_end)
             set_layout(nq);
@@ -934,14 +938,14 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
     set_layout(q, sp.NBR);
 
     u32x4 stg[CL::NPW];
-    XiRegs<PATH, NB, KCX> xr;
+    XiRegs<CL> xr;
     if constexpr (!SPLIT) {
         load_chunk<PATH, NB, CL::NPW>(stg, sp.xf, sp.w4, sp.w8h, sp.w8l, q, wave, lane, 0);
         store_chunk<PATH, NB, CL::NPW>(stg, buf[0], wave, lane, q.c & 1);
     } else {
-        load_chunk_dma<PATH, NB, KCX>(xr, sp.xf, sp.w4, sp.w8h, sp.w8l, q, buf[0], wave, lane,
+        load_chunk_dma<CL>(xr, sp.xf, sp.w4, sp.w8h, sp.w8l, q, buf[0], wave, lane,
                                       0);
-        store_xi<PATH, NB, KCX>(xr, buf[0], wave, lane, q.c & 1);
+        store_xi<CL>(xr, buf[0], wave, lane, q.c & 1);
     }
     __syncthreads();
 
@@ -969,7 +973,7 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
                 load_chunk<PATH, NB, CL::NPW>(stg, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq, wave,
                                               lane, 0);
             else
-                load_chunk_dma<PATH, NB, KCX>(xr, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq,
+                load_chunk_dma<CL>(xr, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq,
                                               buf[cur ^ 1], wave, lane, 0);
         }
 
@@ -1019,7 +1023,7 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
         if constexpr (!SPLIT)
             store_chunk<PATH, NB, CL::NPW>(stg, buf[cur], wave, lane, nq.c & 1);
         else
-            store_xi<PATH, NB, KCX>(xr, buf[cur], wave, lane, nq.c & 1);
+            store_xi<CL>(xr, buf[cur], wave, lane, nq.c & 1);
         __syncthreads();
         if (new_item) {
             ++k;
@@ -1028,6 +1032,176 @@ k_c3_items(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
             set_layout(nq, sp.NBR);
         }
         q = nq;
+    }
+}
+
+// The batch contraction of the split paths in ONE persistent launch over
+// both tile classes.  Workgroups have 4 waves and stage 1024-sample chunks
+// (as k_c3_contract's 4-block tiles).  On an item of 4 x 4 blocks wave w
+// owns strip w.  On an item of 2 x 2 blocks the waves w and w + 2 share
+// strip w & 1: wave w < 2 computes the first 512 samples of every chunk and
+// wave w + 2 the second 512 (a split of the sample axis inside the
+// workgroup, so the class runs at the same 4 waves and the same chunk); at
+// the item's end waves 2 and 3 hand their FP64 sums over through LDS and
+// waves 0 and 1 add them (a fixed order) and write the partial.  A
+// workgroup's list (one LPT schedule over both classes) holds its 4 x 4
+// items first; each class runs in a loop of its own, so each loop keeps the
+// register budget of a one-class kernel.
+template <int PATH, int CLS>
+__device__ __attribute__((always_inline)) inline void
+items_loop(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items, int k, int k1,
+           const char *__restrict__ ws, double *__restrict__ part, uint4 *lds, int bufsz,
+           double *hand, int wave, int lane)
+{
+    constexpr int NB = CLS ? 4 : 2;
+    typedef ChunkLds<PATH, NB, 2 * KC, 4> CL;
+    constexpr int64_t TILE = (int64_t)CL::TS * CL::TS;
+    const int rl = lane & 31, h = lane >> 5;
+    const int strip = CLS ? wave : (wave & 1);
+    auto buf = [&](int b) -> CL & { return *reinterpret_cast<CL *>(lds + b * bufsz); };
+
+    C3Item it = items[k];
+    SeriesPtrs sp = series_ptrs(sd[it.series], ws);
+    SkPos q;
+    q.R = it.R;
+    q.Cc = it.Cc;
+    q.c = it.c0;
+
+    floatx16 acc[NB];
+    double acc64[NB][16];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            acc[cb][v] = 0.0f;
+            acc64[cb][v] = 0.0;
+            pin_agpr(acc64[cb][v]);
+        }
+    int ncol = __builtin_amdgcn_readfirstlane(wave_cols(NB, q.Cc == q.R, strip, q.R, sp.NBR));
+
+    XiRegs<CL> xr;
+    load_chunk_dma<CL>(xr, sp.xf, sp.w4, sp.w8h, sp.w8l, q, buf(0), wave, lane, 0);
+    store_xi<CL>(xr, buf(0), wave, lane, q.c & 1);
+    __syncthreads();
+
+    int cur = 0;
+    for (;;) {
+        SkPos nq = q;
+        C3Item nit = it;
+        SeriesPtrs nsp = sp;
+        bool has_next = true, new_item = false;
+        if (q.c + 1 < it.c1) {
+            nq.c = q.c + 1;
+        } else if (k + 1 < k1) {
+            nit = items[k + 1];
+            nsp = series_ptrs(sd[nit.series], ws);
+            nq.R = nit.R;
+            nq.Cc = nit.Cc;
+            nq.c = nit.c0;
+            new_item = true;
+        } else {
+            has_next = false;
+        }
+        if (has_next)
+            load_chunk_dma<CL>(xr, nsp.xf, nsp.w4, nsp.w8h, nsp.w8l, nq, buf(cur ^ 1), wave,
+                               lane, 0);
+
+        const float sgn = (q.c & 1) ? -1.0f : 1.0f;
+        CL &B = buf(cur);
+        if constexpr (CLS) {
+            dispatch_compute<PATH, 4>(ncol, B.xi, B.xa, B.xb, CL::WLEN, strip, rl, h, acc, acc64);
+            dispatch_compute<PATH, 4>(ncol, B.xi + KC / 4, B.xa + KC, B.xb + KC, CL::WLEN, strip,
+                                      rl, h, acc, acc64);
+        } else {
+            const int o = (wave >> 1) * KC;   // this wave's half of the chunk
+            dispatch_compute<PATH, 2>(ncol, B.xi + o / 4, B.xa + o, B.xb + o, CL::WLEN, strip,
+                                      rl, h, acc, acc64);
+        }
+        flush_acc<NB, true>(acc, acc64, sgn);
+
+        if (!has_next || new_item) {
+            double *dst = part + it.slot * TILE;
+            if constexpr (CLS) {
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    if (cb < ncol) {
+#pragma unroll
+                        for (int v = 0; v < 16; ++v)
+                            dst[((strip * 4 + cb) * 16 + v) * 64 + lane] = acc64[cb][v];
+                    }
+            } else {
+                // the second half's sums to the first half's waves, in LDS
+                if (wave >= 2) {
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                        for (int v = 0; v < 16; ++v)
+                            hand[((strip * 2 + cb) * 16 + v) * 64 + lane] = acc64[cb][v];
+                }
+                __syncthreads();
+                if (wave < 2) {
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        if (cb < ncol) {
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) {
+                                const int e = ((strip * 2 + cb) * 16 + v) * 64 + lane;
+                                dst[e] = acc64[cb][v] + hand[e];
+                            }
+                        }
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    acc64[cb][v] = 0.0;
+                    pin_agpr(acc64[cb][v]);
+                }
+        }
+        if (!has_next)
+            break;
+        cur ^= 1;
+        store_xi<CL>(xr, buf(cur), wave, lane, nq.c & 1);
+        __syncthreads();
+        if (new_item) {
+            ++k;
+            it = nit;
+            sp = nsp;
+            ncol = __builtin_amdgcn_readfirstlane(
+                wave_cols(NB, nq.Cc == nq.R, strip, nq.R, sp.NBR));
+        }
+        q = nq;
+    }
+}
+
+template <int PATH>
+__global__ void __launch_bounds__(256, 1)
+k_c3_items_u(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items,
+             const int32_t *__restrict__ wgfirst, const char *__restrict__ ws,
+             double *__restrict__ part2, double *__restrict__ part4)
+{
+    static_assert(PATH != HOS_PATH_FP32, "the FP32 path has one tile class");
+    typedef ChunkLds<PATH, 4, 2 * KC, 4> CL4;
+    typedef ChunkLds<PATH, 2, 2 * KC, 4> CL2;
+    constexpr int BUF = (int)((sizeof(CL4) > sizeof(CL2) ? sizeof(CL4) : sizeof(CL2)) / 16);
+    constexpr int HAND = 2 * 2 * 16 * 64 / 2;   // waves 2, 3: 2 blocks x 16 x 64 doubles
+
+    __shared__ uint4 lds[2 * BUF + HAND];
+    double *hand = (double *)(lds + 2 * BUF);
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int k0 = wgfirst[blockIdx.x], k1 = wgfirst[blockIdx.x + 1];
+    int mid = k0;   // the 4 x 4 items come first
+    while (mid < k1 && items[mid].pad == 1)
+        ++mid;
+    if (k0 < mid)
+        items_loop<PATH, 1>(sd, items, k0, mid, ws, part4, lds, BUF, hand, wave, lane);
+    if (mid < k1) {
+        if (k0 < mid)
+            __syncthreads();   // the first loop's last reads of the buffers are done
+        items_loop<PATH, 0>(sd, items, mid, k1, ws, part2, lds, BUF, hand, wave, lane);
     }
 }
 
@@ -1111,12 +1285,22 @@ k_bdiag(const T *__restrict__ x, const SeriesDesc *__restrict__ sd, char *__rest
         ((double *)(r + d.o_cfull))[a * (d.M + 1) + a] = red[0];
 }
 
-template <int PATH, int NB>
-void launch_items_t(const BatchHeader &h, int cls, const char *dplan, char *ws, hipStream_t s)
+// FP32 path: one tile class (4 x 4 blocks), the generic per-class kernel.
+void launch_items_fp32(const BatchHeader &h, const char *dplan, char *ws, hipStream_t s)
 {
-    k_c3_items<PATH, NB><<<(unsigned)h.G[cls], 64 * NB, 0, s>>>(
-        (const SeriesDesc *)(dplan + h.series_off), (const C3Item *)(dplan + h.items_off[cls]),
-        (const int32_t *)(dplan + h.wgfirst_off[cls]), ws, (double *)(ws + h.part_off[cls]));
+    k_c3_items<HOS_PATH_FP32, 4><<<(unsigned)h.G[1], 256, 0, s>>>(
+        (const SeriesDesc *)(dplan + h.series_off), (const C3Item *)(dplan + h.items_off),
+        (const int32_t *)(dplan + h.wgfirst_off), ws, (double *)(ws + h.part_off[1]));
+}
+
+// Split paths: both classes in one launch.
+template <int PATH>
+void launch_items_u(const BatchHeader &h, const char *dplan, char *ws, hipStream_t s)
+{
+    k_c3_items_u<PATH><<<(unsigned)h.G[0], 256, 0, s>>>(
+        (const SeriesDesc *)(dplan + h.series_off), (const C3Item *)(dplan + h.items_off),
+        (const int32_t *)(dplan + h.wgfirst_off), ws, (double *)(ws + h.part_off[0]),
+        (double *)(ws + h.part_off[1]));
 }
 
 template <int PATH, int NB>
@@ -1207,26 +1391,18 @@ hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s, int region
 
 namespace hos {
 
+// One persistent launch over every work item of the batch.
 hipError_t launch_batch_contract(const BatchHeader &h, const char *dplan, char *ws,
                                  hipStream_t s)
 {
-    for (int cls = 0; cls < BATCH_CLASSES; ++cls) {
-        if (h.n_items[cls] == 0)
-            continue;
-        if (cls == 1) {
-            if (h.path == HOS_PATH_FP32)
-                launch_items_t<HOS_PATH_FP32, 4>(h, cls, dplan, ws, s);
-            else if (h.path == HOS_PATH_SPLIT_FP16)
-                launch_items_t<HOS_PATH_SPLIT_FP16, 4>(h, cls, dplan, ws, s);
-            else
-                launch_items_t<HOS_PATH_SPLIT_BF16, 4>(h, cls, dplan, ws, s);
-        } else {
-            if (h.path == HOS_PATH_SPLIT_FP16)
-                launch_items_t<HOS_PATH_SPLIT_FP16, 2>(h, cls, dplan, ws, s);
-            else
-                launch_items_t<HOS_PATH_SPLIT_BF16, 2>(h, cls, dplan, ws, s);
-        }
-    }
+    if (h.n_items_all == 0)
+        return hipGetLastError();
+    if (h.path == HOS_PATH_FP32)
+        launch_items_fp32(h, dplan, ws, s);
+    else if (h.path == HOS_PATH_SPLIT_FP16)
+        launch_items_u<HOS_PATH_SPLIT_FP16>(h, dplan, ws, s);
+    else
+        launch_items_u<HOS_PATH_SPLIT_BF16>(h, dplan, ws, s);
     return hipGetLastError();
 }
 

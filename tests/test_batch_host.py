@@ -62,30 +62,52 @@ def test_items_cover_every_chunk_once(n, M, path):
                 continue
             nbr = (M[s] + 31) // 32
             tr = (nbr + NB - 1) // NB if nbr else 0
-            # chunk length: 1024 samples on the split paths' 4-block tiles, else 512
-            L = 1024 if (cls == 1 and path != "fp32") else 512
+            # chunk length: 1024 samples on the split paths (both tile classes,
+            # one launch), 512 on the FP32 path
+            L = 1024 if path != "fp32" else 512
             expect += tr * (tr + 1) // 2 * ((n[s] + L - 1) // L)
         assert len(seen) == expect
         if slots:
             assert slots == set(range(len(slots)))
 
 
+_MIXED = synth.batched_series(120, 4)[1:]
+
+
+@pytest.mark.parametrize("n,M,path", CASES + [(list(_MIXED[0]), list(_MIXED[1]), "split_fp16")])
+def test_one_launch_order(n, M, path):
+    """Every item of both classes in one list: each workgroup's 4 x 4-block
+    items precede its 2 x 2-block items (the kernel runs one loop per class),
+    and the list is grouped by workgroup."""
+    plan = hos.BatchPlan(n, M, path=path)
+    it = plan.items(-1)
+    assert len(it) == plan.info["items0"] + plan.info["items1"]
+    assert np.all(np.diff(it[:, 1]) >= 0)
+    for w in np.unique(it[:, 1]):
+        cls = it[it[:, 1] == w, 0]
+        assert np.all(np.diff(cls) <= 0), w   # 1 ... 1 0 ... 0
+
+
 @pytest.mark.parametrize("n,M,path", CASES)
 def test_lpt_balance(n, M, path):
-    """Longest-processing-time assignment: no workgroup carries more than
-    the mean load plus one item (the greedy rule's bound)."""
+    """One launch for both tile classes: one set of workgroups, and the
+    longest-processing-time assignment over the items of both classes keeps
+    every workgroup within the mean load plus one item (the greedy rule's
+    bound).  Chunk costs: 14 for a 4 x 4-block tile and 5 for a 2 x 2-block
+    tile on the split paths; 4 off and 3 on the diagonal on the FP32 path."""
     plan = hos.BatchPlan(n, M, path=path)
-    for cls in (0, 1):
-        it = plan.items(cls)
-        if len(it) == 0:
-            continue
-        cost = (it[:, 6] - it[:, 5]).astype(float)
-        if path == "fp32":
-            cost *= np.where(it[:, 3] == it[:, 4], 3.0, 4.0)
-        G = plan.info["G%d" % cls]
-        load = np.bincount(it[:, 1], weights=cost, minlength=G)
-        assert load.max() <= load.sum() / G + cost.max() + 1e-9
-        assert np.all(load > 0)
+    assert plan.info["G0"] == plan.info["G1"]
+    G = plan.info["G0"]
+    rows = [plan.items(c) for c in (0, 1)]
+    it = np.concatenate([r for r in rows if len(r)])
+    cost = (it[:, 6] - it[:, 5]).astype(float)
+    if path == "fp32":
+        cost *= np.where(it[:, 3] == it[:, 4], 3.0, 4.0)
+    else:
+        cost *= np.where(it[:, 0] == 1, 14.0, 5.0)
+    load = np.bincount(it[:, 1], weights=cost, minlength=G)
+    assert load.max() <= load.sum() / G + cost.max() + 1e-9
+    assert np.all(load > 0) and G <= 256
 
 
 @pytest.mark.parametrize("window", ["none", "separable"])
