@@ -213,7 +213,70 @@ namespace {
 
 __device__ inline int pd_len(int k1, int H) { return k1 <= H ? min(k1, H - k1) + 1 : 0; }
 
+// First packed index of principal-domain row k1 (rows hold min(k1, H - k1)
+// + 1 points: k1 + 1 up to h = floor(H / 2), H - k1 + 1 after).
+__device__ inline int pd_row_start(int k1, int H)
+{
+    const int h = H / 2, p = k1 < h + 1 ? k1 : h + 1;
+    int start = p * (p + 1) / 2;
+    if (k1 > h + 1)
+        start += (k1 - h - 1) * (H + 1) - ((k1 - 1) * k1 / 2 - h * (h + 1) / 2);
+    return start;
+}
+
+// The windowed cumulant folded onto grid point (m1, m2) of the N x N DFT
+// grid: the sum of W3 c3 over the lags w = m (mod N).  Lag w lies in
+// [-M, M] and N >= 2M, so each axis has one alias candidate -- the centred
+// representative m or m - N -- except at m = M when N = 2M, where both
+// candidates +-M carry a Parzen factor d(M) = 0 (and N = 2M is allowed only
+// with a Parzen window).  So the fold is the centred lag's term alone: one
+// table read per grid point, no loop.  The square's corners |w1 - w2| > M
+// count only without the Parzen product (its d(w1 - w2) vanishes there)
+// and only when the table holds them (amax > M).
+struct FoldArgs {
+    const double *cfull;
+    const double *dwin;   // d(0..M) (or 1: no window)
+    double norm;
+    int M, amax, N;
+    bool pdiff;           // Parzen product: d on the difference too
+};
+
+__device__ __attribute__((always_inline)) inline double fold_centred(const FoldArgs &f, int m1,
+                                                                     int m2)
+{
+    const int w1 = m1 <= f.N / 2 ? m1 : m1 - f.N;
+    const int w2 = m2 <= f.N / 2 ? m2 : m2 - f.N;
+    const int dw = w1 - w2;
+    const bool in = m1 < f.N && abs(w1) <= f.M && abs(w2) <= f.M &&
+                    (abs(dw) <= f.M || (!f.pdiff && f.amax > f.M));
+    if (!in)
+        return 0.0;
+    const double wt = f.dwin[abs(w1)] * f.dwin[abs(w2)] * (f.pdiff ? f.dwin[abs(dw)] : 1.0);
+    return wt * c3_from_table(f.cfull, f.M, f.amax, f.norm, w1, w2);
+}
+
 constexpr int PD_LDS_ELEMS = 2048;   // complex doubles per workgroup (32 KB): 4+ per CU
+
+// Workgroups are dispatched to the 8 XCDs round robin by their linear index,
+// and each XCD has its own L2.  The spectra kernels read one series' table
+// (rows) or grid (columns) from every one of that series' workgroups, so
+// the grid is laid out to keep a series on one XCD: linear index w runs on
+// XCD w % 8, and the k-th workgroup of XCD x (k = w / 8) takes block k % NBLK
+// of series x + 8 (k / NBLK).  Returns false for the padding workgroups.
+constexpr int N_XCD = 8;
+
+__device__ inline bool xcd_series_block(int count, int nblk, int &series, int &blk)
+{
+    const int w = blockIdx.x, x = w % N_XCD, k = w / N_XCD;
+    series = x + N_XCD * (k / nblk);
+    blk = k % nblk;
+    return series < count;
+}
+
+inline unsigned xcd_grid(int count, int nblk)
+{
+    return (unsigned)(N_XCD * ((count + N_XCD - 1) / N_XCD) * nblk);
+}
 
 // Rows: blockIdx.y = series of group g, blockIdx.x = block of 2 CBP rows m1.
 // The folded rows are real, so rows m1 and m1 + 1 travel as the real and
@@ -222,42 +285,31 @@ constexpr int PD_LDS_ELEMS = 2048;   // complex doubles per workgroup (32 KB): 4
 // T1[m1][k2] (k2 < K2) goes to the series' grid region.
 __global__ void __launch_bounds__(FFT_THREADS)
 k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, int first,
-          char *__restrict__ ws, const double2 *__restrict__ tw, FftRadices fr, int CBP,
-          int window)
+          int count, int nblk, char *__restrict__ ws, const double2 *__restrict__ tw,
+          FftRadices fr, int CBP, int window)
 {
     __shared__ double2 sm[PD_LDS_ELEMS];
-    __shared__ double dwin[FFT_LDS_ELEMS / 2 + 1];   // d(m), m = 0..M (M <= N/2)
-    const SeriesDesc &d = sd[gser[first + blockIdx.y]];
+    __shared__ double dwin[PD_LDS_ELEMS / 2 + 1];   // d(m), m = 0..M (M <= N/2 <= 1024)
+    int si, blk;
+    if (!xcd_series_block(count, nblk, si, blk))
+        return;
+    const SeriesDesc &d = sd[gser[first + si]];
     const int N = fr.n, M = d.M, K2 = N / 4 + 1;
     const char *r = ws + d.ws_off;
-    const double *cfull = (const double *)(r + d.o_cfull);
-    const double norm = ((const double *)(r + d.o_stats))[3];
     const bool pz = window != HOS_WIN_NONE;            // d on the lags
-    const bool pdiff = window == HOS_WIN_PARZEN;        // and on their differences
     for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
-    auto fold = [&](int m1, int m2) {
-        double sum = 0.0;
-        if (m1 < N) {
-            for (int w1 = m1 - N; w1 <= m1; w1 += N) {
-                if (w1 < -M || w1 > M)
-                    continue;
-                for (int w2 = m2 - N; w2 <= m2; w2 += N) {
-                    const int dw = w1 - w2;
-                    if (w2 < -M || w2 > M || dw < -M || dw > M)
-                        continue;   // batches hold the hexagon only (Parzen window)
-                    sum += dwin[abs(w1)] * dwin[abs(w2)] * (pdiff ? dwin[abs(dw)] : 1.0) *
-                           c3_from_table(cfull, M, M, norm, w1, w2);
-                }
-            }
-        }
-        return sum;
-    };
-    const int m1_0 = blockIdx.x * 2 * CBP;
+    // batches hold the hexagon only (Parzen window)
+    const FoldArgs f = {(const double *)(r + d.o_cfull), dwin,
+                        ((const double *)(r + d.o_stats))[3], M, M, N,
+                        window == HOS_WIN_PARZEN};
+    const int m1_0 = blk * 2 * CBP;
+    // unrolled so that the table reads of several points are in flight at once
+#pragma unroll 4
     for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
         const int p = e / N, m2 = e - p * N, m1 = m1_0 + 2 * p;
-        sm[e] = make_double2(fold(m1, m2), fold(m1 + 1, m2));
+        sm[e] = make_double2(fold_centred(f, m1, m2), fold_centred(f, m1 + 1, m2));
     }
     __syncthreads();
     fft_lds<FFT_THREADS, PD_LDS_ELEMS>(sm, tw, fr, CBP);
@@ -278,26 +330,24 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
 // writes the principal-domain points of those columns.
 __global__ void __launch_bounds__(FFT_THREADS)
 k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, int first,
-          const char *__restrict__ ws, const double2 *__restrict__ tw, FftRadices fr, int CB,
-          double2 *__restrict__ B_pd)
+          int count, int nblk, const char *__restrict__ ws, const double2 *__restrict__ tw,
+          FftRadices fr, int CB, double2 *__restrict__ B_pd)
 {
     __shared__ double2 sm[PD_LDS_ELEMS];
     __shared__ int rowstart[FFT_LDS_ELEMS / 2 + 1];
-    const SeriesDesc &d = sd[gser[first + blockIdx.y]];
+    int si, blk;
+    if (!xcd_series_block(count, nblk, si, blk))
+        return;
+    const SeriesDesc &d = sd[gser[first + si]];
     const int N = fr.n, K2 = N / 4 + 1, H = (N - 1) / 2;
-    const int k2_0 = blockIdx.x * CB;
+    const int k2_0 = blk * CB;
     const double2 *T1 = (const double2 *)(ws + d.grid_off);
     for (int e = threadIdx.x; e < CB * N; e += FFT_THREADS) {
         const int m1 = e / CB, cb = e - m1 * CB, k2 = k2_0 + cb;
         sm[cb * N + m1] = k2 < K2 ? T1[(int64_t)m1 * K2 + k2] : make_double2(0.0, 0.0);
     }
-    if (threadIdx.x == 0) {
-        int p = 0;
-        for (int a = 0; a <= H && a < N / 2 + 1; ++a) {
-            rowstart[a] = p;
-            p += pd_len(a, H);
-        }
-    }
+    for (int a = threadIdx.x; a <= H && a < N / 2 + 1; a += FFT_THREADS)
+        rowstart[a] = pd_row_start(a, H);
     __syncthreads();
     fft_lds<FFT_THREADS, PD_LDS_ELEMS>(sm, tw, fr, CB);
     const int half = H + 1;   // k1 <= H
@@ -321,38 +371,16 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
     __shared__ double2 sm[ELEMS];
     __shared__ double dwin[FFT_LDS_ELEMS / 2 + 1];
     const int N = fr.n;
-    const double norm = stats[3];
     const bool pz = window != HOS_WIN_NONE;            // d on the lags
-    const bool pdiff = window == HOS_WIN_PARZEN;        // and on their differences
     for (int m = threadIdx.x; m <= M; m += THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
-    auto fold = [&](int m1, int m2) {
-        double sum = 0.0;
-        if (m1 < N) {
-            for (int w1 = m1 - N; w1 <= m1; w1 += N) {
-                if (w1 < -M || w1 > M)
-                    continue;
-                for (int w2 = m2 - N; w2 <= m2; w2 += N) {
-                    const int dw = w1 - w2;
-                    if (w2 < -M || w2 > M)
-                        continue;
-                    // the square's corners: 0 under the Parzen product (its
-                    // d(w1 - w2) vanishes from |w1 - w2| = M on), otherwise
-                    // taken from the table when it holds them
-                    if ((dw < -M || dw > M) && (pdiff || amax == M))
-                        continue;
-                    sum += dwin[abs(w1)] * dwin[abs(w2)] * (pdiff ? dwin[abs(dw)] : 1.0) *
-                           c3_from_table(cfull, M, amax, norm, w1, w2);
-                }
-            }
-        }
-        return sum;
-    };
+    const FoldArgs f = {cfull, dwin, stats[3], M, amax, N, window == HOS_WIN_PARZEN};
     const int m1_0 = blockIdx.x * 2 * CBP;
+#pragma unroll 4
     for (int e = threadIdx.x; e < CBP * N; e += THREADS) {
         const int p = e / N, m2 = e - p * N, m1 = m1_0 + 2 * p;
-        sm[e] = make_double2(fold(m1, m2), fold(m1 + 1, m2));
+        sm[e] = make_double2(fold_centred(f, m1, m2), fold_centred(f, m1 + 1, m2));
     }
     __syncthreads();
     fft_lds<THREADS, ELEMS>(sm, tw, fr, CBP);
@@ -448,10 +476,11 @@ hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window
             CB = 32;
         const int K2 = N / 4 + 1;
         if (CB >= 1) {
-            k_pd_rows<<<dim3((N + 2 * CB - 1) / (2 * CB), gr.count), FFT_THREADS, 0, s>>>(
-                sd, gser, (int)gr.first, ws, tw, fr, CB, window);
-            k_pd_cols<<<dim3((K2 + CB - 1) / CB, gr.count), FFT_THREADS, 0, s>>>(
-                sd, gser, (int)gr.first, ws, tw, fr, CB, (double2 *)B_pd);
+            const int rb = (N + 2 * CB - 1) / (2 * CB), cbk = (K2 + CB - 1) / CB;
+            k_pd_rows<<<xcd_grid(gr.count, rb), FFT_THREADS, 0, s>>>(
+                sd, gser, (int)gr.first, gr.count, rb, ws, tw, fr, CB, window);
+            k_pd_cols<<<xcd_grid(gr.count, cbk), FFT_THREADS, 0, s>>>(
+                sd, gser, (int)gr.first, gr.count, cbk, ws, tw, fr, CB, (double2 *)B_pd);
         } else {
             return hipErrorInvalidValue;   // N > 2048: not planned for batches
         }
