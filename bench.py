@@ -292,9 +292,16 @@ def bench_batched(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0
     from paper_1805_11775_amd import tune as hos_tune
     out = {}
     for path in paths:
-        print("bench: batched path %s (tuning tiles)" % path, file=sys.stderr, flush=True)
-        tuned = hos_tune.tune(sorted(set(int(m) for m in M)), path=path, series=32, reps=3)
-        plan = hos.BatchPlan(n, M, path=path, tile=tuned["choices"])
+        # the shipped table tuned on this device (the tests' plan too), else tune now
+        table = hos_tune.load(hos_tune.device_key(path))
+        source = "shipped table (%s)" % os.path.basename(hos_tune.SHIPPED)
+        if table is None:
+            print("bench: batched path %s (tuning tiles)" % path, file=sys.stderr, flush=True)
+            table = hos_tune.tune(sorted(set(int(m) for m in M)), path=path, series=32, reps=3)
+            source = "tuned in this run"
+        print("bench: batched path %s, tiles from the %s" % (path, source), file=sys.stderr,
+              flush=True)
+        plan = hos.BatchPlan(n, M, path=path, tile=hos_tune.tiles_for(n, M, table))
         plan.to(x.device)
         ms = _time(torch, lambda: hos.bispectrum_batched(x, plan, return_c3=False),
                    max(2, steps // 10), max(1, warmup // 10))
@@ -315,8 +322,8 @@ def bench_batched(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0
                      "contract_frac": flops / (stage_ms["contract"] * 1e-3) / PEAK[path],
                      "frac_whole_call": flops / (ms * 1e-3) / PEAK[path],
                      "rel_err_B_pd_shortest_series": err, "within_tol": err <= TOL[path],
-                     "tile_choices": {str(k): v for k, v in tuned["choices"].items()},
-                     "tune_ms": {str(k): v for k, v in tuned["ms"].items()},
+                     "tile_choices": {str(k): v for k, v in table["choices"].items()},
+                     "tile_buckets": table["edges"], "tile_source": source,
                      "work_items": [plan.info["items0"], plan.info["items1"]],
                      "workgroups": [plan.info["G0"], plan.info["G1"]],
                      "ws_bytes": plan.info["ws_bytes"]}
@@ -331,7 +338,7 @@ def bench_batched(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0
            "config": {"workload": "4096 float32 series, n uniform in [1024, 65536], M uniform "
                                   "in {32, 64, 128, 256}, even index N(0,1), odd index "
                                   "Exp(1)-1; Parzen window, N = 2M; principal-domain spectra; "
-                                  "tiles from the autotuner",
+                                  "tiles from the autotuner (per lag and length bucket)",
                       "series": len(n), "samples": int(np.sum(n)), "path": head},
            # one persistent launch over the work items of both tile classes
            # (4 x 4 and 2 x 2 blocks; k_c3_items_u, or k_c3_items on the FP32 path)

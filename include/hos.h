@@ -405,6 +405,31 @@ int hos_batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t wi
  * over the items of both classes (G0 = G1 workgroups); a workgroup runs its
  * 4 x 4 items, then its 2 x 2 items. */
 int hos_batch_plan_info(const void *plan, int64_t *info, int32_t ninfo);
+
+/*
+ * The batch tile tuner (the choice passed to hos_batch_plan as tile_nb),
+ * timed on the device.  For every maximum lag Ms[i] and length bucket j
+ * (lengths n_edges[j] <= n < n_edges[j+1]) it builds a synthetic batch of
+ * `series` uniform(-1, 1) float32 series with lengths spread evenly over the
+ * bucket, plans it with every candidate tile (2 and 4 blocks on the split
+ * paths, 4 on the FP32 path), builds the operand tables once, and times
+ * the contraction launch alone `reps` times (HIP events; the median
+ * counts).
+ *   path      hos_path.
+ *   Ms        host, nM lags, 0 <= M <= 1024, M + 2 < n_edges[nb]; 1 <= nM <= 64.
+ *   n_edges   host, nb + 1 increasing lengths (2 <= n <= 2^24); 1 <= nb <= 16.
+ *   series    series per synthetic batch, 1 .. 4096; reps 1 .. 100.
+ *   ws        device workspace of hos_tune_workspace() bytes, 256-byte aligned.
+ *   tile_out  host, nM x nb: the faster tile (2 or 4) per (M, bucket).
+ *   ms_out    host, nM x nb x 2: median contraction milliseconds of the
+ *             2-block and 4-block tiles (-1 where not a candidate).
+ * WAITS for `stream`.  HOS_EINVAL for bad sizes (checked on the host first).
+ */
+int hos_tune_workspace(int32_t path, const int32_t *Ms, int32_t nM, const int64_t *n_edges,
+                       int32_t nb, int32_t series, size_t *bytes);
+int hos_tune(int32_t path, const int32_t *Ms, int32_t nM, const int64_t *n_edges, int32_t nb,
+             int32_t series, int32_t reps, void *ws, size_t ws_bytes, int32_t *tile_out,
+             float *ms_out, hipStream_t stream);
 int hos_batch_series(const void *plan, int64_t *out, int64_t cap);
 int hos_batch_items(const void *plan, int32_t cls, int64_t *out, int64_t cap);
 

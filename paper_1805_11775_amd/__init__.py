@@ -108,6 +108,11 @@ def _load_lib():
         "hos_batch_plan": (ctypes.c_int, [i32, p64, ctypes.POINTER(ctypes.c_int32), i32, i32,
                                           u32, ctypes.POINTER(ctypes.c_int32), vp, sz]),
         "hos_batch_plan_info": (ctypes.c_int, [vp, p64, i32]),
+        "hos_tune_workspace": (ctypes.c_int, [i32, ctypes.POINTER(ctypes.c_int32), i32, p64, i32,
+                                              i32, ctypes.POINTER(sz)]),
+        "hos_tune": (ctypes.c_int, [i32, ctypes.POINTER(ctypes.c_int32), i32, p64, i32, i32, i32,
+                                    vp, sz, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_float), vp]),
         "hos_batch_series": (ctypes.c_int, [vp, p64, i64]),
         "hos_batch_items": (ctypes.c_int, [vp, i32, p64, i64]),
         "hos_bispectrum_batched": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),

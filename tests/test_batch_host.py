@@ -215,7 +215,8 @@ def test_tile_choice_moves_series_between_classes():
 
 def test_tune_module_imports():
     from paper_1805_11775_amd import tune
-    assert tune.CANDIDATES["fp32"] == (4,)
+    assert list(tune.DEFAULT_EDGES) == sorted(tune.DEFAULT_EDGES)
+    assert tune.DEFAULT_EDGES[0] <= 1024 and tune.DEFAULT_EDGES[-1] > 65536
 
 
 def test_segments_plan_and_validation():
@@ -235,3 +236,46 @@ def test_segments_plan_and_validation():
     assert f(FAKE, 0, plain.host.ctypes.data, FAKE, FAKE, FAKE, FAKE,
              plain.info["ws_bytes"], None) == hos.HOS_EINVAL     # plan without the flag
     assert f(None, 0, ph, FAKE, FAKE, FAKE, FAKE, wsb, None) == hos.HOS_EINVAL
+
+
+def _tune_args(Ms, edges, series=8):
+    Mc = (ctypes.c_int32 * len(Ms))(*Ms)
+    Ec = (ctypes.c_int64 * len(edges))(*edges)
+    return Mc, len(Ms), Ec, len(edges) - 1, series
+
+
+@pytest.mark.parametrize("Ms,edges,series,code", [
+    ([32, 128], [1024, 4096, 65537], 8, hos.HOS_OK),
+    ([32], [1024, 1024], 8, hos.HOS_EINVAL),          # empty bucket
+    ([32], [4096, 1024], 8, hos.HOS_EINVAL),          # decreasing edges
+    ([2000], [1024, 65537], 8, hos.HOS_EINVAL),       # lag beyond the batch limit
+    ([500], [100, 400], 8, hos.HOS_EINVAL),           # lag not below the lengths
+    ([32], [1024, 4096], 0, hos.HOS_EINVAL),          # no series
+])
+def test_tune_validation_before_device(Ms, edges, series, code):
+    """hos_tune's sizes are checked on the host; the workspace query covers
+    the largest synthetic batch and plan."""
+    Mc, nM, Ec, nb, se = _tune_args(Ms, edges, series)
+    b = ctypes.c_size_t(0)
+    assert hos.lib().hos_tune_workspace(1, Mc, nM, Ec, nb, se, ctypes.byref(b)) == code
+    if code == hos.HOS_OK:
+        assert b.value > 8 * (edges[-1] - 1) * 4
+    tiles = (ctypes.c_int32 * 8)()
+    ms = (ctypes.c_float * 16)()
+    st = hos.lib().hos_tune(1, Mc, nM, Ec, nb, se, 3, ctypes.c_void_p(0x10000), 16, tiles, ms,
+                            None)
+    assert st == (hos.HOS_EWORKSPACE if code == hos.HOS_OK else code)
+
+
+def test_tuned_table_lookup():
+    """tiles_for maps each series to its lag's row and its length's bucket;
+    the shipped table covers the batch workload's lags on every path."""
+    from paper_1805_11775_amd import tune
+    table = {"edges": [1024, 4096, 65537], "choices": {32: [2, 4], 256: [4, 2]}}
+    assert tune.tiles_for([1024, 4095, 4096, 65536, 3000], [32, 32, 32, 256, 64], table) == \
+        [2, 2, 4, 2, 0]
+    for path in ("split_fp16", "split_bf16", "fp32"):
+        t = tune.load("gfx950:256:" + path)
+        assert t is not None and sorted(t["choices"]) == [32, 64, 128, 256]
+        assert all(v in ((4,) if path == "fp32" else (2, 4))
+                   for row in t["choices"].values() for v in row)

@@ -74,12 +74,16 @@ def test_batch_deterministic():
 
 def test_workload_batch_sampled():
     """4096 float32 series, n in [1024, 65536], M in {32, 64, 128, 256}
-    (the batched benchmark shape, one launch per tile class): c3 at sampled
-    lags of a stratified subset against the oracle, the principal-domain
-    spectra of two series in full."""
+    (the batched benchmark shape and plan: the tiles of the shipped tuned
+    table, one launch over both tile classes): c3 at sampled lags of a
+    stratified subset against the oracle, the principal-domain spectra of two
+    series in full."""
     hos = _hos()
+    from paper_1805_11775_amd import tune
     xs, n, M = synth.workload_batched()
-    plan = hos.BatchPlan(n, M, path="split_fp16")
+    table = tune.load(tune.device_key("split_fp16"))
+    assert table is not None, "no shipped tile table for this device"
+    plan = hos.BatchPlan(n, M, path="split_fp16", tile=tune.tiles_for(n, M, table))
     print("case: batch of %d, ws %.1f GB, items %s" %
           (len(n), plan.info["ws_bytes"] / 1e9, (plan.info["items0"], plan.info["items1"])),
           flush=True)
@@ -218,18 +222,28 @@ def test_loss_workload_sampled(path):
     assert np.isfinite(float(loss))
 
 
-def test_tuner_choices_are_valid_and_correct():
-    """The tuner returns one tile choice per lag among the candidates, and a
-    plan built from them matches the oracle."""
+def test_tuner_choices_are_valid_and_correct(tmp_path):
+    """hos_tune through the tuner: one tile choice per (lag, length bucket)
+    among the candidates with its timings, merged into a cache under the
+    device's key and read back; a plan built from the choices matches the
+    oracle."""
     hos = _hos()
     from paper_1805_11775_amd import tune
-    res = tune.tune([32, 128], path="split_fp16", n_lo=1024, n_hi=8192, series=6, reps=2)
+    cache = str(tmp_path / "tiles.json")
+    res = tune.tune([32, 128], path="split_fp16", edges=(1024, 2048, 8192), series=6, reps=2,
+                    cache=cache)
     print("tuned:", res, flush=True)
     assert set(res["choices"]) == {32, 128}
-    assert all(v in (2, 4) for v in res["choices"].values())
+    assert all(v in (2, 4) for row in res["choices"].values() for v in row)
+    assert all(len(row) == 2 for row in res["choices"].values())
+    assert all(t > 0 for row in res["ms"].values() for pair in row for t in pair)
+    table = tune.load(tune.device_key("split_fp16"), cache)
+    assert table["choices"] == res["choices"] and table["edges"] == [1024, 2048, 8192]
     xs = [synth.iid_exp_centered(3000, 91).astype(np.float32),
           synth.iid_gauss(2500, 92).astype(np.float32)]
-    plan = hos.BatchPlan([3000, 2500], [32, 128], path="split_fp16", tile=res["choices"])
+    tiles = tune.tiles_for([3000, 2500], [32, 128], table)
+    assert tiles == [res["choices"][32][1], res["choices"][128][1]]
+    plan = hos.BatchPlan([3000, 2500], [32, 128], path="split_fp16", tile=tiles)
     c3, B = hos.bispectrum_batched(torch.from_numpy(np.concatenate(xs)).cuda(), plan)
     torch.cuda.synchronize()
     S = plan.series()
