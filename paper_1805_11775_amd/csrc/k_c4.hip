@@ -207,12 +207,12 @@ c4_store(const u32x4 (&stg)[NPW], C4Lds<PATH, WX> &L, int wave, int lane, bool n
     }
 }
 
-// One chunk for one wave: row block rows (lane rl holds row (a, b[, c]);
-// `live` zeroes the rows past the end) against NCOL column blocks.  Order
+// One chunk for one wave: row block rows (lane rl holds row (a, b[, c]))
+// against NCOL column blocks.  Order
 // four: product row x_i x_{i+a} x_{i+b}; order five: x_i x_{i+a} x_{i+b}
 // x_{i+c}; its last factor is split from the exact FP32 product.
 template <int ORD, int PATH, int WX, int NCOL>
-__device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, int c, float live,
+__device__ __attribute__((always_inline)) inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, int c,
                                 int rl, int h, floatx16 (&acc)[NCOL],
                                 double (&acc64)[NCOL][16], float sgn)
 {
@@ -225,9 +225,11 @@ __device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, int c, f
         unpack8(L.xi[ib >> 2], L.xi[(ib >> 2) + 1], xi);
         unpack8(L.xw[ib + a], L.xw[ib + a + 4], xa);
         unpack8(L.xw[ib + b], L.xw[ib + b + 4], xb);
+        // rows past the last pair compute with a = b = 0 and are never
+        // read back (the reduction keeps rows r < P only)
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            p[j] = xi[j] * xa[j] * live;
+            p[j] = xi[j] * xa[j];
         if constexpr (ORD == 5) {
             // x_{i+b} joins the product; x_{i+c} is the last factor
             float xc[8];
@@ -292,10 +294,10 @@ __device__ inline void c4_chunk(const C4Lds<PATH, WX> &L, int a, int b, int c, f
 // over the workgroup, so every wave takes the same instantiation and meets
 // the same barriers).
 template <int ORD, int PATH, int WX, int NCOL>
-__device__ inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict__ xf,
+__device__ __attribute__((always_inline)) inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict__ xf,
                               const uint4 *__restrict__ win4, const uint4 *__restrict__ win8h,
                               const uint4 *__restrict__ win8l, double *__restrict__ part,
-                              int a, int b, int c3, float live, int rb, int s, int RB, int NCB,
+                              int a, int b, int c3, int rb, int s, int RB, int NCB,
                               int64_t c0, int64_t c1, int wave, int lane)
 {
     const int rl = lane & 31, h = lane >> 5;
@@ -320,7 +322,7 @@ __device__ inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict
         const bool has_next = c + 1 < c1;
         if (has_next)
             c4_load<PATH, WX>(stg, xf, win4, win8h, win8l, (c + 1) * KC, wave, lane);
-        c4_chunk<ORD, PATH, WX, NCOL>(buf[cur], a, b, c3, live, rl, h, acc, acc64,
+        c4_chunk<ORD, PATH, WX, NCOL>(buf[cur], a, b, c3, rl, h, acc, acc64,
                                       (c & 1) ? -1.0f : 1.0f);
         if (!has_next)
             break;
@@ -341,8 +343,10 @@ __device__ inline void c4_run(C4Lds<PATH, WX> (&buf)[2], const float *__restrict
 
 // Grid (ceil(RB/4), S): workgroup (x, s) runs row blocks 4x .. 4x+3 over
 // chunks [s*CPS, min((s+1)*CPS, C)) and writes one FP64 partial per row
-// block and column block.
-template <int ORD, int PATH, int WX>
+// block and column block.  NMAX bounds the column blocks a row block can
+// need (ceil((M+1)/32)); instantiating no more keeps the accumulators, and
+// so the registers, to what the lag range uses.
+template <int ORD, int PATH, int WX, int NMAX>
 __device__ __forceinline__ void moment_contract(C4Lds<PATH, WX> (&buf)[2],
                                                 const float *__restrict__ xf,
                                                 const uint4 *__restrict__ win4,
@@ -364,11 +368,8 @@ __device__ __forceinline__ void moment_contract(C4Lds<PATH, WX> (&buf)[2],
     // this lane's row; column blocks = those of the workgroup's last row
     // (rows are ordered by their bound, so it has the largest)
     int a = 0, b = 0, c = 0, bound = 0;
-    float live = 0.0f;
-    if (rb < RB && rb * 32 + rl < P) {
+    if (rb < RB && rb * 32 + rl < P)
         row_offsets<ORD>(M, rb * 32 + rl, a, b, c, bound);
-        live = 1.0f;
-    }
     int last = blockIdx.x * 128 + 127;
     if (last > P - 1)
         last = P - 1;
@@ -378,8 +379,8 @@ __device__ __forceinline__ void moment_contract(C4Lds<PATH, WX> (&buf)[2],
     switch (ncol) {
 #define C4CASE(K)                                                                           \
     case K:                                                                                 \
-        if constexpr (32 * K <= WX)                                                         \
-            c4_run<ORD, PATH, WX, K>(buf, xf, win4, win8h, win8l, part, a, b, c, live, rb, s, \
+        if constexpr (32 * K <= WX && K <= NMAX)                                            \
+            c4_run<ORD, PATH, WX, K>(buf, xf, win4, win8h, win8l, part, a, b, c, rb, s,       \
                                      RB, NCB, c0, c1, wave, lane);                          \
         break;
         C4CASE(1) C4CASE(2) C4CASE(3) C4CASE(4)
@@ -389,26 +390,31 @@ __device__ __forceinline__ void moment_contract(C4Lds<PATH, WX> (&buf)[2],
     }
 }
 
-template <int PATH, int WX>
+// Up to two column blocks the accumulators and operands fit 256 registers:
+// two workgroups per compute unit (two waves per SIMD) hide each other's
+// latencies.
+template <int PATH, int WX, int NMAX>
 __global__ void __launch_bounds__(256, 1)
 k_c4_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
               const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
               double *__restrict__ part, int M, int P, int RB, int NCB, int64_t C, int CPS)
 {
     __shared__ C4Lds<PATH, WX> buf[2];
-    moment_contract<4, PATH, WX>(buf, xf, win4, win8h, win8l, part, M, P, RB, NCB, C, CPS);
+    moment_contract<4, PATH, WX, NMAX>(buf, xf, win4, win8h, win8l, part, M, P, RB, NCB, C,
+                                       CPS);
 }
 
 // Order five: rows (a, b, c), product row x_i x_{i+a} x_{i+b} x_{i+c}
 // against the Hankel columns x_{i+d}, d <= c.
-template <int PATH, int WX>
+template <int PATH, int WX, int NMAX>
 __global__ void __launch_bounds__(256, 1)
 k_c5_contract(const float *__restrict__ xf, const uint4 *__restrict__ win4,
               const uint4 *__restrict__ win8h, const uint4 *__restrict__ win8l,
               double *__restrict__ part, int M, int P, int RB, int NCB, int64_t C, int CPS)
 {
     __shared__ C4Lds<PATH, WX> buf[2];
-    moment_contract<5, PATH, WX>(buf, xf, win4, win8h, win8l, part, M, P, RB, NCB, C, CPS);
+    moment_contract<5, PATH, WX, NMAX>(buf, xf, win4, win8h, win8l, part, M, P, RB, NCB, C,
+                                       CPS);
 }
 
 // Sum the S chunk-range partials of one (row block, column block) in a fixed
@@ -750,44 +756,44 @@ k_c5_lines(const double *__restrict__ m5tab, const double *__restrict__ c2,
     }
 }
 
-template <int PATH, int WX>
+template <int PATH, int WX, int NMAX>
 void launch_c4_t(const C4Plan &p, char *ws, hipStream_t s)
 {
     dim3 grid((p.RB + 3) / 4, p.S);
-    k_c4_contract<PATH, WX><<<grid, 256, 0, s>>>(
+    k_c4_contract<PATH, WX, NMAX><<<grid, 256, 0, s>>>(
         (const float *)(ws + p.off_xf), (const uint4 *)(ws + p.off_win4),
         (const uint4 *)(ws + p.off_win8h), (const uint4 *)(ws + p.off_win8l),
         (double *)(ws + p.off_part), p.M, p.P, p.RB, p.NCB, p.C, p.CPS);
 }
 
-template <int PATH, int WX>
+template <int PATH, int WX, int NMAX>
 void launch_c5_t(const C4Plan &p, char *ws, hipStream_t s)
 {
     dim3 grid((p.RB + 3) / 4, p.S);
-    k_c5_contract<PATH, WX><<<grid, 256, 0, s>>>(
+    k_c5_contract<PATH, WX, NMAX><<<grid, 256, 0, s>>>(
         (const float *)(ws + p.off_xf), (const uint4 *)(ws + p.off_win4),
         (const uint4 *)(ws + p.off_win8h), (const uint4 *)(ws + p.off_win8l),
         (double *)(ws + p.off_part), p.M, p.P, p.RB, p.NCB, p.C, p.CPS);
 }
 
-template <int WX>
+template <int WX, int NMAX>
 void launch_c4_path(const C4Plan &p, char *ws, hipStream_t s)
 {
     if (p.ord == 5) {
         if (p.path == HOS_PATH_FP32)
-            launch_c5_t<HOS_PATH_FP32, WX>(p, ws, s);
+            launch_c5_t<HOS_PATH_FP32, WX, NMAX>(p, ws, s);
         else if (p.path == HOS_PATH_SPLIT_FP16)
-            launch_c5_t<HOS_PATH_SPLIT_FP16, WX>(p, ws, s);
+            launch_c5_t<HOS_PATH_SPLIT_FP16, WX, NMAX>(p, ws, s);
         else
-            launch_c5_t<HOS_PATH_SPLIT_BF16, WX>(p, ws, s);
+            launch_c5_t<HOS_PATH_SPLIT_BF16, WX, NMAX>(p, ws, s);
         return;
     }
     if (p.path == HOS_PATH_FP32)
-        launch_c4_t<HOS_PATH_FP32, WX>(p, ws, s);
+        launch_c4_t<HOS_PATH_FP32, WX, NMAX>(p, ws, s);
     else if (p.path == HOS_PATH_SPLIT_FP16)
-        launch_c4_t<HOS_PATH_SPLIT_FP16, WX>(p, ws, s);
+        launch_c4_t<HOS_PATH_SPLIT_FP16, WX, NMAX>(p, ws, s);
     else
-        launch_c4_t<HOS_PATH_SPLIT_BF16, WX>(p, ws, s);
+        launch_c4_t<HOS_PATH_SPLIT_BF16, WX, NMAX>(p, ws, s);
 }
 
 }  // namespace
@@ -807,11 +813,16 @@ int c4_window_entries(int M)
 
 hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s)
 {
-    switch (p.WX) {
-    case 64: launch_c4_path<64>(p, ws, s); break;
-    case 128: launch_c4_path<128>(p, ws, s); break;
-    default: launch_c4_path<192>(p, ws, s); break;
-    }
+    // the window (WX) and the largest column-block count (NCB) of the lag
+    // range: WX 64 holds one block, 128 two or three, 192 four
+    if (p.WX == 64)
+        launch_c4_path<64, 1>(p, ws, s);
+    else if (p.WX == 128 && p.NCB <= 2)
+        launch_c4_path<128, 2>(p, ws, s);
+    else if (p.WX == 128)
+        launch_c4_path<128, 3>(p, ws, s);
+    else
+        launch_c4_path<192, 4>(p, ws, s);
     return hipGetLastError();
 }
 
