@@ -384,6 +384,10 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0.0)
     # the quadratic form of the (2M+1)-sample window over the hexagon has a
     # symmetric kernel: one MAC per unordered lag pair, (|H| + 2M + 1) / 2
     bwd_flops = B_ * float(n_) * (hexagon + 2 * M + 1)
+    # the smallest count of the adjoint: the lag weights folded onto F and the
+    # two products Z = H G_F^T, Z' = H G_F (one MAC per sample and F entry
+    # each), 2 n (M+1)(M+2) FLOP per series
+    bwd_flops_fold = B_ * 2.0 * n_ * (M + 1) * (M + 2)
     dL = torch.ones((), dtype=torch.float64, device="cuda")
     out = {}
     for path in paths:
@@ -404,6 +408,7 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0.0)
                      "fwd_tflops": fwd_flops / (t_f * 1e-3) / 1e12,
                      "bwd_tflops": bwd_flops / (t_b * 1e-3) / 1e12,
                      "bwd_frac": bwd_flops / (t_b * 1e-3) / PEAK[path],
+                     "bwd_frac_fold_count": bwd_flops_fold / (t_b * 1e-3) / PEAK[path],
                      "loss": float(loss), "rel_err_B_pd_series37": err,
                      "within_tol": err <= TOL[path]}
         print("bench: loss %s fwd %.3f ms bwd %.3f ms err %.2e" % (path, t_f, t_b, err),
@@ -419,7 +424,10 @@ def bench_loss(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds=0.0)
                       "batch": B_, "n": n_, "M": M, "nfft": N, "path": head},
            "bwd_flops_definition": "n (|H| + 2M + 1) per series, |H| = 3M^2+3M+1: one MAC "
                                    "per unordered lag pair of the symmetric quadratic form of "
-                                   "the (2M+1)-sample window over the hexagon",
+                                   "the (2M+1)-sample window over the hexagon; "
+                                   "bwd_frac_fold_count prices the call at the folded "
+                                   "count 2 n (M+1)(M+2) per series instead",
+           "bwd_flops_fold": bwd_flops_fold,
            # the backward entry point has no stage events: the whole backward
            # call is timed, so the adjoint contraction's own fraction (see its
            # kernel trace) is higher than this one

@@ -147,6 +147,7 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         if (adj) {
             const size_t kp2 = (size_t)d.KP * d.KP;
             d.o_gtil = r;  r = a256(r + (size_t)d.n * sizeof(double));
+            d.o_gtab = r;  r = a256(r + (size_t)(2 * d.M + 1) * (2 * d.M + 1) * sizeof(double));
             d.o_k64 = r;   r = a256(r + kp2 * sizeof(double));
             d.o_kh = r;    r = a256(r + kp2 * (split ? 2 : 4));
             if (split) {

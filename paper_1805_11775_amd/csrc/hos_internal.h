@@ -232,7 +232,7 @@ struct SeriesDesc {
     int64_t C;            // chunks of c3_stage_len(path, NB) samples
     // byte offsets inside the series region; table offsets point at sample 0
     int64_t o_stats, o_mpart, o_xf, o_win4, o_win8h, o_win8l, o_cfull, o_dpart;
-    int64_t o_gtil, o_k64, o_kh, o_kl;   // adjoint buffers (plans made for the adjoint)
+    int64_t o_gtil, o_gtab, o_k64, o_kh, o_kl;   // adjoint buffers (plans made for the adjoint)
 };
 
 struct C3Item {           // one (series, tile, chunk range) of the contraction
@@ -375,7 +375,8 @@ hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double 
                             int N, int window, const double2 *tw, double *T, hipStream_t s);
 hipError_t launch_fft3_tail(double *T, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s);
-hipError_t launch_fft2_batch(double *grids, int N, int count, const double2 *tw, hipStream_t s);
+hipError_t launch_fft2_batch(double *grids, int N, int count, int live, const double2 *tw,
+                             hipStream_t s);
 hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window, char *ws,
                              double *B_pd, hipStream_t s);
 

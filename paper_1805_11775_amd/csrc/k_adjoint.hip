@@ -32,20 +32,31 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int ADJ_ROWS = 256;   // rows j per workgroup: 4 waves x 2 blocks of 32
 
-__device__ inline int pd_row_len(int k1, int H) { return k1 <= H ? min(k1, H - k1) + 1 : 0; }
-
+// Packed index of (k1, k2) in the principal domain 0 <= k2 <= k1,
+// k1 + k2 <= H = floor((N-1)/2), or -1.  Row k1 holds min(k1, H - k1) + 1
+// points: k1 + 1 up to h = floor(H/2), H - k1 + 1 after.
 __device__ inline int pd_index(int k1, int k2, int N)
 {
     const int H = (N - 1) / 2;
     if (k2 > k1 || k1 + k2 > H)
         return -1;
-    int p = 0;
-    for (int a = 0; a < k1; ++a)
-        p += pd_row_len(a, H);
-    return p + k2;
+    const int h = H / 2, p = k1 < h + 1 ? k1 : h + 1;
+    int start = p * (p + 1) / 2;
+    if (k1 > h + 1)
+        start += (k1 - h - 1) * (H + 1) - ((k1 - 1) * k1 / 2 - h * (h + 1) / 2);
+    return start + k2;
 }
 
-// grid = conj(2 dL (B - T)) on the principal domain, 0 elsewhere.
+// The bits of max |K2| (slot 6 of a series' statistics) accumulate by an
+// atomic maximum over non-negative doubles, whose order is that of their
+// bit patterns: the result does not depend on the order of the updates.
+__device__ inline unsigned long long *kmax_bits(const SeriesDesc &d, char *ws)
+{
+    return (unsigned long long *)((double *)(ws + d.ws_off + d.o_stats) + 6);
+}
+
+// grid = conj(2 dL (B - T)) on the principal domain, 0 elsewhere; also
+// clears the running max |K2| that k_adj_kbuild fills.
 __global__ void __launch_bounds__(256)
 k_adj_resid(const SeriesDesc *__restrict__ sd, const double2 *__restrict__ B_pd,
             const double2 *__restrict__ target, const double *__restrict__ dL,
@@ -54,6 +65,8 @@ k_adj_resid(const SeriesDesc *__restrict__ sd, const double2 *__restrict__ B_pd,
     const SeriesDesc &d = sd[blockIdx.y];
     const int N = d.N;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx == 0)
+        *kmax_bits(d, ws) = 0ull;
     if (idx >= (int64_t)N * N)
         return;
     const int p = pd_index((int)(idx / N), (int)(idx % N), N);
@@ -76,59 +89,72 @@ __device__ inline double g_at(const double2 *__restrict__ F, int N, int M, int w
     return window3(w1, w2, M, window) * F[(int64_t)m1 * N + m2].x;
 }
 
-// K2 in FP64 over [0, KP)^2 (u' = u + M, v' = v + M; padding is 0).
+// The windowed lag weights G(w) once per lag of the square (0 outside the
+// hexagon), so that the quadratic form's kernel below reads them back
+// instead of evaluating the window six times per entry.
 __global__ void __launch_bounds__(256)
-k_adj_kbuild(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int window)
+k_adj_gtab(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int window)
 {
     const SeriesDesc &d = sd[blockIdx.y];
-    const int KP = d.KP, M = d.M;
+    const int M = d.M, S = 2 * M + 1;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)KP * KP)
+    if (idx >= (int64_t)S * S)
         return;
-    const int up = (int)(idx / KP), vp = (int)(idx % KP);
-    double val = 0.0;
-    const int bu = up >> 5, bv = vp >> 5;
-    if (up <= 2 * M && vp <= 2 * M && bv >= bu) {
-        const double2 *F = (const double2 *)(ws + d.grid_off);
-        const int u = up - M, v = vp - M;
-        auto K = [&](int a, int b) {
-            return g_at(F, d.N, M, window, a, b) + g_at(F, d.N, M, window, -a, b - a) +
-                   g_at(F, d.N, M, window, b - a, -a);
-        };
-        const double ks = 0.5 * (K(u, v) + K(v, u)) / (double)d.n;
-        val = bv > bu ? 2.0 * ks : ks;
-    }
-    ((double *)(ws + d.ws_off + d.o_k64))[idx] = val;
+    const double2 *F = (const double2 *)(ws + d.grid_off);
+    const int w1 = (int)(idx / S) - M, w2 = (int)(idx % S) - M;
+    ((double *)(ws + d.ws_off + d.o_gtab))[idx] = g_at(F, d.N, M, window, w1, w2);
 }
 
-// Power-of-two scale sk with max|K2| sk in [2^14, 2^15): stats[5] = sk.
-__global__ void __launch_bounds__(1024)
-k_adj_kmax(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
+// K2 in FP64 over [0, KP)^2 (u' = u + M, v' = v + M; padding is 0), and the
+// running max |K2| (a workgroup's maximum, then one atomic maximum).
+__global__ void __launch_bounds__(256)
+k_adj_kbuild(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
 {
-    __shared__ double red[1024];
-    const SeriesDesc &d = sd[blockIdx.x];
-    char *r = ws + d.ws_off;
-    const double *k64 = (const double *)(r + d.o_k64);
-    const int64_t tot = (int64_t)d.KP * d.KP;
-    double m = 0.0;
-    for (int64_t i = threadIdx.x; i < tot; i += 1024)
-        m = fmax(m, fabs(k64[i]));
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        double sk = 1.0;
-        if (red[0] > 0.0 && isfinite(red[0])) {
-            int e;
-            frexp(red[0], &e);
-            sk = ldexp(1.0, 15 - e);
+    __shared__ double red[4];
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int KP = d.KP, M = d.M, S = 2 * M + 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double val = 0.0;
+    if (idx < (int64_t)KP * KP) {
+        const int up = (int)(idx / KP), vp = (int)(idx % KP);
+        const int bu = up >> 5, bv = vp >> 5;
+        if (up <= 2 * M && vp <= 2 * M && bv >= bu) {
+            const double *Gt = (const double *)(ws + d.ws_off + d.o_gtab);
+            const int u = up - M, v = vp - M;
+            auto G = [&](int a, int b) {
+                return (a < -M || a > M || b < -M || b > M)
+                           ? 0.0 : Gt[(int64_t)(a + M) * S + (b + M)];
+            };
+            auto K = [&](int a, int b) { return G(a, b) + G(-a, b - a) + G(b - a, -a); };
+            const double ks = 0.5 * (K(u, v) + K(v, u)) / (double)d.n;
+            val = bv > bu ? 2.0 * ks : ks;
         }
-        ((double *)(r + d.o_stats))[5] = sk;
+        ((double *)(ws + d.ws_off + d.o_k64))[idx] = val;
     }
+    double m = fabs(val);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        atomicMax(kmax_bits(d, ws), (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// Power-of-two scale sk with max|K2| sk in [2^14, 2^15) (1 when K2 is 0 or
+// not finite).
+__device__ inline double kscale(double mx)
+{
+    double sk = 1.0;
+    if (mx > 0.0 && isfinite(mx)) {
+        int e;
+        frexp(mx, &e);
+        sk = ldexp(1.0, 15 - e);
+    }
+    return sk;
 }
 
 // K2 sk rounded for the matrix cores: FP32, or hi + lo halves.
@@ -142,7 +168,9 @@ k_adj_ksplit(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
         return;
     char *r = ws + d.ws_off;
     // rows of odd 32-blocks of u are stored negated (see k_adj_contract)
-    const double sk = ((const double *)(r + d.o_stats))[5];
+    const double sk = kscale(__longlong_as_double((long long)*kmax_bits(d, ws)));
+    if (idx == 0)
+        ((double *)(r + d.o_stats))[5] = sk;   // for k_adj_final
     const double sg = ((idx / d.KP) >> 5) & 1 ? -1.0 : 1.0;
     const float v = (float)(((const double *)(r + d.o_k64))[idx] * sk * sg);
     if constexpr (PATH == HOS_PATH_FP32) {
@@ -353,13 +381,15 @@ hipError_t launch_batch_adjoint(const void *x, int dtype, const BatchHeader &h, 
         double2 *tw = (double2 *)(ws + gr.twid_off);
         hipError_t e = launch_twiddles(tw, gr.N, s);
         if (e == hipSuccess)
-            e = launch_fft2_batch((double *)(ws + gr.grid_off), gr.N, gr.count, tw, s);
+            // the residual sits on the principal domain: rows k1 <= (N - 1) / 2
+            e = launch_fft2_batch((double *)(ws + gr.grid_off), gr.N, gr.count,
+                                  (gr.N - 1) / 2 + 1, tw, s);
         if (e != hipSuccess)
             return e;
     }
-    const int64_t k2 = h.max_KP * h.max_KP;
-    k_adj_kbuild<<<dim3((unsigned)((k2 + 255) / 256), B), 256, 0, s>>>(sd, ws, window);
-    k_adj_kmax<<<B, 1024, 0, s>>>(sd, ws);
+    const int64_t k2 = h.max_KP * h.max_KP, sq = (2 * h.max_M + 1) * (2 * h.max_M + 1);
+    k_adj_gtab<<<dim3((unsigned)((sq + 255) / 256), B), 256, 0, s>>>(sd, ws, window);
+    k_adj_kbuild<<<dim3((unsigned)((k2 + 255) / 256), B), 256, 0, s>>>(sd, ws);
     const dim3 gk((unsigned)((k2 + 255) / 256), B);
     if (h.path == HOS_PATH_FP32) {
         k_adj_ksplit<HOS_PATH_FP32><<<gk, 256, 0, s>>>(sd, ws);

@@ -187,13 +187,16 @@ hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s)
 namespace hos {
 
 // In-place 2-D DFTs of `count` contiguous N x N row-major complex grids.
-hipError_t launch_fft2_batch(double *grids, int N, int count, const double2 *tw, hipStream_t s)
+// Only the first `live` rows of each grid may be nonzero (the rest are 0 and
+// stay 0 under the row transforms, which therefore skip them).
+hipError_t launch_fft2_batch(double *grids, int N, int count, int live, const double2 *tw,
+                             hipStream_t s)
 {
     double2 *d = (double2 *)grids;
     const FftRadices fr = factor(N);
-    const int64_t rows = (int64_t)count * N;
-    fft_axis(d, tw, fr, rows, 1, 1, 0, N, s);                    // along k2, every grid
-    fft_axis(d, tw, fr, rows, N, N, 1, (int64_t)N * N, s);       // along k1
+    const int64_t N2 = (int64_t)N * N;
+    fft_axis(d, tw, fr, (int64_t)count * live, 1, live, N, N2, s);   // along k2, live rows
+    fft_axis(d, tw, fr, (int64_t)count * N, N, N, 1, N2, s);         // along k1
     return hipGetLastError();
 }
 
