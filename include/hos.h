@@ -283,14 +283,17 @@ int hos_c4_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  * window-sum theorems, for the indirect estimator): the same c3 and B as
  * hos_bispectrum on the whole record, computed through a device workspace
  * whose size depends on the piece length P and M but not on n.  The record
- * is read twice in pieces of P samples: first for its FP64 mean and scale,
- * then each piece with the M samples after it (2M when the square's corners
+ * is read twice: first for its FP64 mean and scale, then in pieces of P
+ * samples, each with the M samples after it (2M when the square's corners
  * are computed: HOS_FULL_SQUARE, or a window that is nonzero there), whose
- * sums are added to a running FP64 table.  The copies run on a copy stream of the library's
- * own (one per device, made at the first call and kept until the process
- * ends) into two staging buffers of the workspace, so a piece's copy
- * overlaps the kernels of the one before; events order them against
- * `stream`, whose completion implies every copy's.
+ * sums are added to a running FP64 table.  The first pass reads a record
+ * in pinned host memory that the device maps at the same address
+ * (hipHostMalloc, or hipHostRegister with mapping) in place, in one launch;
+ * any other record it copies piece by piece.  The copies run on a copy
+ * stream of the library's own (one per device, made at the first call and
+ * kept until the process ends) into two staging buffers of the workspace,
+ * so a piece's copy overlaps the kernels of the one before; events order
+ * them against `stream`, whose completion implies every copy's.
  *   x_host  host memory, n samples, HOS_F32 or HOS_F64.  With pinned memory
  *           the call returns once everything is queued; the record must
  *           stay valid and unchanged until `stream` has passed the call.

@@ -3,9 +3,13 @@
 // not on n (the memory frugality of Section 3's window-sum theorems, applied
 // to the indirect estimator).
 //
-// The record is read twice, piece by piece (P samples a piece).  Pass one
-// accumulates the sum, minimum and maximum in FP64, in piece order, giving
-// the whole record's mean and scale.  Pass two copies each piece together
+// The record is read twice.  Pass one gives the whole record's FP64 mean
+// and scale.  A record in pinned host memory that the device addresses at
+// the same address (hipHostMalloc'd, or registered as mapped) is read in
+// place by the moments kernels of the in-memory call, in one launch over
+// the whole record, with no copies and no host calls per piece; any other
+// record is copied piece by piece (P samples a piece) and the sum, minimum
+// and maximum are accumulated in FP64, in piece order.  Pass two copies each piece together
 // with the next M samples (its halo) and runs the single-series stages on
 // it: the operands are rounded with the keys of their place in the record,
 // the first factor x_i stops at the piece's end, so the contraction and the
@@ -170,6 +174,37 @@ struct Stager {
     }
 };
 
+// True when the device can read [x, x + bytes) in place: pinned host memory
+// mapped at the same address, the whole range inside one allocation.  A
+// failed query (pageable memory) is cleared so that it does not surface as
+// the error of a later launch.
+bool device_visible(const void *x, size_t bytes)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, x) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type != hipMemoryTypeHost)
+        return false;
+    void *dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, const_cast<void *>(x), 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    hipDeviceptr_t start = nullptr;
+    size_t size = 0;
+    if (hipPointerGetAttribute(&start, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR,
+                               (hipDeviceptr_t)x) != hipSuccess ||
+        hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, (hipDeviceptr_t)x) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uintptr_t lo = (uintptr_t)start, p = (uintptr_t)x;
+    return dp == x && start != nullptr && p >= lo && bytes <= size && p - lo <= size - bytes;
+}
+
 }  // namespace
 
 }  // namespace hos
@@ -252,29 +287,36 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
     Stager stg;
     hipError_t e = stg.init(stream, w + L.off_x[0], w + L.off_x[1]);
 
-    // pass one: sum, minimum, maximum of the record, piece by piece (p0 is
+    // pass one: the record's mean and scale into the stats every piece plan
+    // reads (each plan puts its stats at offset 0 of the workspace; p0 is
     // the plan of a full piece with its halo, within the workspace layout)
     C3Plan p0;
     const bool corners = bispectrum_needs_corners(window, flags, B != nullptr);
     const int64_t halo = corners ? 2 * (int64_t)M : M;
     make_c3_plan(piece_data(n, halo, piece, 0), M, path, B ? nfft : 0, p0, corners);
-    char *xd = nullptr;
-    for (int64_t k = 0; k < pieces && e == hipSuccess; ++k) {
-        const int64_t g0 = k * piece, len = piece_len(n, piece, k);
-        // a record of one piece is staged whole (it is its own halo) and
-        // read again by pass two from the same buffer
-        const int64_t cp = pieces == 1 ? n : len;
-        e = stg.put(xh + g0 * esize, (size_t)cp * esize, xd);
-        if (e == hipSuccess)
-            e = launch_moments_piece(xd, dtype, len, k == 0, p0, w, mom, stream);
-        if (e == hipSuccess && pieces > 1)
-            e = stg.done();
-    }
-    // the record's mean and scale into the stats every piece plan reads
-    // (each plan puts its stats at offset 0 of the workspace)
     double *stats = (double *)(w + p0.off_stats);
-    if (e == hipSuccess)
-        e = launch_moments_total(mom, n, flags, p0.scale_top, stats, stream);
+    const bool direct = device_visible(x_host, (size_t)n * esize);
+    char *xd = nullptr;
+    if (direct) {   // in place, as the in-memory call does it
+        if (e == hipSuccess)
+            e = launch_moments(x_host, dtype, n, flags, p0, w, stream);
+    } else {        // sum, minimum, maximum piece by piece
+        for (int64_t k = 0; k < pieces && e == hipSuccess; ++k) {
+            const int64_t g0 = k * piece, len = piece_len(n, piece, k);
+            // a record of one piece is staged whole (it is its own halo)
+            // and read again by pass two from the same buffer
+            const int64_t cp = pieces == 1 ? n : len;
+            e = stg.put(xh + g0 * esize, (size_t)cp * esize, xd);
+            if (e == hipSuccess)
+                e = launch_moments_piece(xd, dtype, len, k == 0, p0, w, mom, stream);
+            if (e == hipSuccess && pieces > 1)
+                e = stg.done();
+        }
+        if (e == hipSuccess)
+            e = launch_moments_total(mom, n, flags, p0.scale_top, stats, stream);
+    }
+    // a one-piece record staged by pass one is already in its buffer
+    const bool staged_whole = !direct && pieces == 1;
 
     // pass two: each piece with its halo through the single-series stages
     const int64_t ne = (int64_t)(M + 1) * (M + 1);
@@ -287,7 +329,7 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
             e = hipErrorInvalidValue;
             break;
         }
-        if (pieces > 1)
+        if (!staged_whole)
             e = stg.put(xh + g0 * esize, (size_t)data * esize, xd);
         if (e == hipSuccess) e = launch_prep(xd, dtype, p, w, stream, g0, len);
         if (e == hipSuccess) e = launch_c3_contract(p, w, stream, 0);

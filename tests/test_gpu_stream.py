@@ -55,6 +55,32 @@ def test_float64_pinned_and_uncentred():
         assert _err(c3.cpu().numpy(), c_ref) < 1e-6 and _err(B.cpu().numpy(), B_ref) < 1e-6
 
 
+@pytest.mark.parametrize("n,piece", [(20000, 4096), (5000, 8192)])
+def test_pinned_read_in_place(n, piece):
+    """A record in pinned memory is read in place by the first pass (a view
+    at an offset into a larger pinned block; five pieces, and one piece);
+    the result equals the pageable copy path's up to the order of the FP64
+    additions of the mean, and the oracle's."""
+    hos = _hos()
+    x = synth.quadratic_process(n, 900 + n).astype(np.float32)
+    blk = torch.zeros(n + 11, dtype=torch.float32).pin_memory()
+    blk[5:5 + n] = torch.from_numpy(x)
+    view = blk[5:5 + n]
+    assert view.is_pinned() and view.data_ptr() != blk.data_ptr()
+    print("case: pinned view n=%d piece=%d" % (n, piece), flush=True)
+    cp, Bp = hos.bispectrum_streamed(view, 64, piece=piece, path="split_fp16")
+    cq, Bq = hos.bispectrum_streamed(torch.from_numpy(x.copy()), 64, piece=piece,
+                                     path="split_fp16")
+    torch.cuda.synchronize()
+    d1 = _err(cp.cpu().numpy(), cq.cpu().numpy())
+    d2 = _err(Bp.cpu().numpy(), Bq.cpu().numpy())
+    print("pinned vs pageable: c3 %.3e B %.3e" % (d1, d2))
+    assert d1 < 1e-12 and d2 < 1e-12
+    c_ref, B_ref = oracle.bispectrum(x, 64, hos.default_nfft(64))
+    assert _err(cp.cpu().numpy(), c_ref) < TOL["split_fp16"]
+    assert _err(Bp.cpu().numpy(), B_ref) < TOL["split_fp16"]
+
+
 @pytest.mark.parametrize("path", ["split_fp16", "fp32"])
 def test_matches_in_memory_call_at_size(path):
     """n = 2^22 float32 quadratic process, M = 512, pieces of 2^20: the
