@@ -1,6 +1,7 @@
 // hos_fft.h -- FP64 complex FFT building blocks shared by the spectra
 // kernels: small forward DFTs in registers, one self-sorting (Stockham)
-// mixed-radix 4/2/3/5 stage over sequences held in LDS, and the radix plan.
+// mixed-radix 8/4/2/3/5 stage over sequences held in LDS, and the radix
+// plan (radix 8 first: fewer stages, so fewer LDS passes and barriers).
 //
 // Transforms are unnormalised with the sign of Algorithm DBS's part DFT,
 //     X(k) = sum_u x(u) exp(-2 pi i u k / N),
@@ -15,6 +16,7 @@ constexpr int FFT_LDS_ELEMS = 4096;   // complex doubles per workgroup (64 KB)
 
 struct FftRadices {
     int n;
+    int lg;      // log2(n) for a power of two, else -1 (index math by shifts)
     int r[16];
 };
 
@@ -40,6 +42,22 @@ __device__ inline void dft_small(double2 *v, const double2 *__restrict__ tw, int
         // -i * d13 = (d13.y, -d13.x)
         v[1] = make_double2(d02.x + d13.y, d02.y - d13.x);
         v[3] = make_double2(d02.x - d13.y, d02.y + d13.x);
+    } else if constexpr (R == 8) {
+        // two 4-point DFTs (even, odd samples) joined by the eighth roots
+        // of unity: X(p) = E(p) + w^p O(p), X(p+4) = E(p) - w^p O(p),
+        // w = exp(-i pi/4) = c (1 - i)
+        constexpr double c = 0.70710678118654752440;   // cos(pi/4)
+        double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<4>(e, tw, N);
+        dft_small<4>(o, tw, N);
+        const double2 t[4] = {o[0], make_double2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x)),
+                              make_double2(o[2].y, -o[2].x),
+                              make_double2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y))};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = make_double2(e[q].x + t[q].x, e[q].y + t[q].y);
+            v[q + 4] = make_double2(e[q].x - t[q].x, e[q].y - t[q].y);
+        }
     } else {
         double2 in[R];
 #pragma unroll
@@ -60,23 +78,59 @@ __device__ inline void dft_small(double2 *v, const double2 *__restrict__ tw, int
     }
 }
 
+// LDS index of complex element i of an FFT area laid out with one padding
+// element after every 2^PADSH (PADSH = 0: no padding).  The first radix-8
+// stages write their outputs 8 or 64 elements apart; with a pad after every
+// 8 elements (128 bytes) those strides no longer fall on the same LDS banks.
+// An area of E elements then takes E + E / 2^PADSH slots.
+template <int PADSH>
+__device__ __attribute__((always_inline)) inline int lds_at(int i)
+{
+    return PADSH ? i + (i >> PADSH) : i;
+}
+
+template <int PADSH>
+constexpr int lds_slots(int elems)
+{
+    return PADSH ? elems + (elems >> PADSH) : elems;
+}
+
 // THREADS: the workgroup size; ELEMS: the complex values of the caller's
 // LDS area (CB * N <= ELEMS), which bounds the butterflies a thread holds.
-template <int R, int THREADS = FFT_THREADS, int ELEMS = FFT_LDS_ELEMS>
+// lgN, lgNs: log2 of N and Ns when N is a power of two (then so is Ns, and
+// the butterfly indices come from shifts and masks), else -1.  PADSH: the
+// area's padding (lds_at).
+template <int R, int THREADS = FFT_THREADS, int ELEMS = FFT_LDS_ELEMS, int PADSH = 0>
 __device__ inline void stockham_stage(double2 *sm, const double2 *__restrict__ tw, int N,
-                                      int Ns, int CB)
+                                      int Ns, int CB, int lgN, int lgNs)
 {
     constexpr int MAXIT = (ELEMS / R + THREADS - 1) / THREADS;
+    constexpr int LGR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : -1;
     const int nbf = N / R, total = CB * nbf, stride = N / (Ns * R);
+    const bool p2 = LGR > 0 && lgN >= 0;
     double2 v[MAXIT][R];
+    int dst[MAXIT];
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
         const int u = threadIdx.x + THREADS * it;
         if (u < total) {
-            const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
+            int cb, j, jq, k;
+            if (p2) {
+                cb = u >> (lgN - LGR);
+                j = u & (nbf - 1);
+                jq = j >> lgNs;
+                k = j & (Ns - 1);
+            } else {
+                cb = u / nbf;
+                j = u - cb * nbf;
+                jq = j / Ns;
+                k = j - jq * Ns;
+            }
+            dst[it] = cb * N + jq * Ns * R + k;
+            const int src = cb * N + j;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                double2 x = sm[cb * N + j + q * nbf];
+                double2 x = sm[lds_at<PADSH>(src + q * nbf)];
                 v[it][q] = q == 0 ? x : cmul(x, tw[q * k * stride]);
             }
             dft_small<R>(v[it], tw, N);
@@ -87,11 +141,9 @@ __device__ inline void stockham_stage(double2 *sm, const double2 *__restrict__ t
     for (int it = 0; it < MAXIT; ++it) {
         const int u = threadIdx.x + THREADS * it;
         if (u < total) {
-            const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
-            const int idxD = (j / Ns) * Ns * R + k;
 #pragma unroll
             for (int p = 0; p < R; ++p)
-                sm[cb * N + idxD + p * Ns] = v[it][p];
+                sm[lds_at<PADSH>(dst[it] + p * Ns)] = v[it][p];
         }
     }
     __syncthreads();
@@ -101,7 +153,12 @@ inline FftRadices factor(int N)
 {
     FftRadices f;
     f.n = N;
+    f.lg = (N > 0 && (N & (N - 1)) == 0) ? __builtin_ctz((unsigned)N) : -1;
     int m = N, k = 0;
+    while (m % 8 == 0) {
+        f.r[k++] = 8;
+        m /= 8;
+    }
     while (m % 4 == 0) {
         f.r[k++] = 4;
         m /= 4;
@@ -123,22 +180,25 @@ inline FftRadices factor(int N)
     return f;
 }
 
-template <int THREADS = FFT_THREADS, int ELEMS = FFT_LDS_ELEMS>
+template <int THREADS = FFT_THREADS, int ELEMS = FFT_LDS_ELEMS, int PADSH = 0>
 __device__ inline void fft_lds(double2 *sm, const double2 *__restrict__ tw, const FftRadices &fr,
                                int CB)
 {
-    int Ns = 1;
+    int Ns = 1, lgNs = 0;
     for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
         const int R = fr.r[st];
-        if (R == 4)
-            stockham_stage<4, THREADS, ELEMS>(sm, tw, fr.n, Ns, CB);
+        if (R == 8)
+            stockham_stage<8, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);
+        else if (R == 4)
+            stockham_stage<4, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);
         else if (R == 2)
-            stockham_stage<2, THREADS, ELEMS>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<2, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);
         else if (R == 3)
-            stockham_stage<3, THREADS, ELEMS>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<3, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);
         else
-            stockham_stage<5, THREADS, ELEMS>(sm, tw, fr.n, Ns, CB);
+            stockham_stage<5, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);
         Ns *= R;
+        lgNs += R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0;
     }
 }
 

@@ -40,11 +40,25 @@ constexpr int FFT_MAX_CB = 64;
 template <int R, int THREADS>
 __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
                                          double2 *__restrict__ dst,
-                                         const double2 *__restrict__ tw, int N, int Ns, int CB)
+                                         const double2 *__restrict__ tw, int N, int Ns, int CB,
+                                         int lgN, int lgNs)
 {
+    constexpr int LGR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : -1;
     const int nbf = N / R, total = CB * nbf, stride = N / (Ns * R);
+    const bool p2 = LGR > 0 && lgN >= 0;
     for (int u = threadIdx.x; u < total; u += THREADS) {
-        const int cb = u / nbf, j = u - cb * nbf, k = j % Ns;
+        int cb, j, jq, k;
+        if (p2) {
+            cb = u >> (lgN - LGR);
+            j = u & (nbf - 1);
+            jq = j >> lgNs;
+            k = j & (Ns - 1);
+        } else {
+            cb = u / nbf;
+            j = u - cb * nbf;
+            jq = j / Ns;
+            k = j - jq * Ns;
+        }
         double2 v[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -52,7 +66,7 @@ __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
             v[q] = q == 0 ? x : cmul(x, tw[q * k * stride]);
         }
         dft_small<R>(v, tw, N);
-        const int idxD = (j / Ns) * Ns * R + k;
+        const int idxD = jq * Ns * R + k;
 #pragma unroll
         for (int p = 0; p < R; ++p)
             dst[cb * N + idxD + p * Ns] = v[p];
@@ -90,32 +104,38 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
     }
     __syncthreads();
     double2 *cur = sm, *nxt = sm + tot;
-    int Ns = 1;
+    int Ns = 1, lgNs = 0;
+    const int lg = fr.lg;
     for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
         const int R = fr.r[st];
         if constexpr (PP) {
-            if (R == 4)
-                stockham_pingpong<4, THREADS>(cur, nxt, tw, N, Ns, CB);
+            if (R == 8)
+                stockham_pingpong<8, THREADS>(cur, nxt, tw, N, Ns, CB, lg, lgNs);
+            else if (R == 4)
+                stockham_pingpong<4, THREADS>(cur, nxt, tw, N, Ns, CB, lg, lgNs);
             else if (R == 2)
-                stockham_pingpong<2, THREADS>(cur, nxt, tw, N, Ns, CB);
+                stockham_pingpong<2, THREADS>(cur, nxt, tw, N, Ns, CB, lg, lgNs);
             else if (R == 3)
-                stockham_pingpong<3, THREADS>(cur, nxt, tw, N, Ns, CB);
+                stockham_pingpong<3, THREADS>(cur, nxt, tw, N, Ns, CB, lg, lgNs);
             else
-                stockham_pingpong<5, THREADS>(cur, nxt, tw, N, Ns, CB);
+                stockham_pingpong<5, THREADS>(cur, nxt, tw, N, Ns, CB, lg, lgNs);
             double2 *t = cur;
             cur = nxt;
             nxt = t;
         } else {
-            if (R == 4)
-                stockham_stage<4, THREADS>(sm, tw, N, Ns, CB);
+            if (R == 8)
+                stockham_stage<8, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
+            else if (R == 4)
+                stockham_stage<4, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
             else if (R == 2)
-                stockham_stage<2, THREADS>(sm, tw, N, Ns, CB);
+                stockham_stage<2, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
             else if (R == 3)
-                stockham_stage<3, THREADS>(sm, tw, N, Ns, CB);
+                stockham_stage<3, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
             else
-                stockham_stage<5, THREADS>(sm, tw, N, Ns, CB);
+                stockham_stage<5, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
         }
         Ns *= R;
+        lgNs += R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0;
     }
     for (int e = threadIdx.x; e < tot; e += THREADS) {
         int cb, k;
@@ -259,6 +279,7 @@ __device__ __attribute__((always_inline)) inline double fold_centred(const FoldA
 }
 
 constexpr int PD_LDS_ELEMS = 2048;   // complex doubles per workgroup (32 KB): 4+ per CU
+constexpr int PD_PAD = 3;            // the batch spectra's LDS padding (lds_at)
 
 // Workgroups are dispatched to the 8 XCDs round robin by their linear index,
 // and each XCD has its own L2.  The spectra kernels read one series' table
@@ -291,7 +312,7 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
           int count, int nblk, char *__restrict__ ws, const double2 *__restrict__ tw,
           FftRadices fr, int CBP, int window)
 {
-    __shared__ double2 sm[PD_LDS_ELEMS];
+    __shared__ double2 sm[lds_slots<PD_PAD>(PD_LDS_ELEMS)];
     __shared__ double dwin[PD_LDS_ELEMS / 2 + 1];   // d(m), m = 0..M (M <= N/2 <= 1024)
     int si, blk;
     if (!xcd_series_block(count, nblk, si, blk))
@@ -308,18 +329,25 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
                         ((const double *)(r + d.o_stats))[3], M, M, N,
                         window == HOS_WIN_PARZEN};
     const int m1_0 = blk * 2 * CBP;
-    // unrolled so that the table reads of several points are in flight at once
+    // A wave covers all CBP row pairs of 64 / CBP consecutive columns: off
+    // the table's rows (w2 beyond w1, or of the other sign) a point reads
+    // the table down a column or a diagonal, and the block's 2 CBP
+    // consecutive rows then share cache lines there, where 64 consecutive
+    // columns of one row would touch 64 lines.  Unrolled so that the table
+    // reads of several points are in flight at once.
 #pragma unroll 4
     for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
-        const int p = e / N, m2 = e - p * N, m1 = m1_0 + 2 * p;
-        sm[e] = make_double2(fold_centred(f, m1, m2), fold_centred(f, m1 + 1, m2));
+        const int m2 = e / CBP, p = e - m2 * CBP, m1 = m1_0 + 2 * p;
+        sm[lds_at<PD_PAD>(p * N + m2)] =
+            make_double2(fold_centred(f, m1, m2), fold_centred(f, m1 + 1, m2));
     }
     __syncthreads();
-    fft_lds<FFT_THREADS, PD_LDS_ELEMS>(sm, tw, fr, CBP);
+    fft_lds<FFT_THREADS, PD_LDS_ELEMS, PD_PAD>(sm, tw, fr, CBP);
     double2 *T1 = (double2 *)(ws + d.grid_off);
     for (int e = threadIdx.x; e < CBP * K2; e += FFT_THREADS) {
         const int p = e / K2, k2 = e - p * K2, m1 = m1_0 + 2 * p;
-        const double2 z = sm[p * N + k2], zc = sm[p * N + (k2 == 0 ? 0 : N - k2)];
+        const double2 z = sm[lds_at<PD_PAD>(p * N + k2)],
+                      zc = sm[lds_at<PD_PAD>(p * N + (k2 == 0 ? 0 : N - k2))];
         // conj(Z(N-k)) = (zc.x, -zc.y)
         if (m1 < N)
             T1[(int64_t)m1 * K2 + k2] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
@@ -336,7 +364,7 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
           int count, int nblk, const char *__restrict__ ws, const double2 *__restrict__ tw,
           FftRadices fr, int CB, double2 *__restrict__ B_pd)
 {
-    __shared__ double2 sm[PD_LDS_ELEMS];
+    __shared__ double2 sm[lds_slots<PD_PAD>(PD_LDS_ELEMS)];
     __shared__ int rowstart[FFT_LDS_ELEMS / 2 + 1];
     int si, blk;
     if (!xcd_series_block(count, nblk, si, blk))
@@ -347,17 +375,18 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
     const double2 *T1 = (const double2 *)(ws + d.grid_off);
     for (int e = threadIdx.x; e < CB * N; e += FFT_THREADS) {
         const int m1 = e / CB, cb = e - m1 * CB, k2 = k2_0 + cb;
-        sm[cb * N + m1] = k2 < K2 ? T1[(int64_t)m1 * K2 + k2] : make_double2(0.0, 0.0);
+        sm[lds_at<PD_PAD>(cb * N + m1)] =
+            k2 < K2 ? T1[(int64_t)m1 * K2 + k2] : make_double2(0.0, 0.0);
     }
     for (int a = threadIdx.x; a <= H && a < N / 2 + 1; a += FFT_THREADS)
         rowstart[a] = pd_row_start(a, H);
     __syncthreads();
-    fft_lds<FFT_THREADS, PD_LDS_ELEMS>(sm, tw, fr, CB);
+    fft_lds<FFT_THREADS, PD_LDS_ELEMS, PD_PAD>(sm, tw, fr, CB);
     const int half = H + 1;   // k1 <= H
     for (int e = threadIdx.x; e < CB * half; e += FFT_THREADS) {
         const int cb = e / half, k1 = e - cb * half, k2 = k2_0 + cb;
         if (k2 < K2 && k2 <= k1 && k1 + k2 <= H)
-            B_pd[d.pd_off + rowstart[k1] + k2] = sm[cb * N + k1];
+            B_pd[d.pd_off + rowstart[k1] + k2] = sm[lds_at<PD_PAD>(cb * N + k1)];
     }
 }
 
