@@ -167,12 +167,21 @@ k_adj_ksplit(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
     if (idx >= (int64_t)d.KP * d.KP)
         return;
     char *r = ws + d.ws_off;
+    // idx enumerates the stored order: k_adj_contract's B fragments, one per
+    // (32-block U of u, 32-block V of v, 16-wide k-group g), each 64 lanes x
+    // 8 consecutive v of one row u (lane = u mod 32 + 32 h, v = 32V + 16g +
+    // 8h + e), so that a wave's fragment load is one contiguous run
+    const int NU = d.KP >> 5;
+    const int e = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
+    const int64_t f = idx >> 9;
+    const int g = (int)(f & 1), V = (int)((f >> 1) % NU), U = (int)((f >> 1) / NU);
+    const int u = U * 32 + (lane & 31), vv = V * 32 + 16 * g + 8 * (lane >> 5) + e;
     // rows of odd 32-blocks of u are stored negated (see k_adj_contract)
     const double sk = kscale(__longlong_as_double((long long)*kmax_bits(d, ws)));
     if (idx == 0)
         ((double *)(r + d.o_stats))[5] = sk;   // for k_adj_final
-    const double sg = ((idx / d.KP) >> 5) & 1 ? -1.0 : 1.0;
-    const float v = (float)(((const double *)(r + d.o_k64))[idx] * sk * sg);
+    const double sg = (U & 1) ? -1.0 : 1.0;
+    const float v = (float)(((const double *)(r + d.o_k64))[(int64_t)u * d.KP + vv] * sk * sg);
     if constexpr (PATH == HOS_PATH_FP32) {
         ((float *)(r + d.o_kh))[idx] = v;
     } else if constexpr (PATH == HOS_PATH_SPLIT_FP16) {
@@ -204,8 +213,12 @@ __device__ inline floatx16 mma16(uint4 a, uint4 b, floatx16 c)
 // KP + 64 - M), in LDS; wave w owns rows j0 + 64w + [0, 64) as two 32-row
 // blocks.  For each 32-column block U of u it accumulates Z = H K2^T over
 // the v blocks V >= U within the hexagon's reach (A = Hankel rows from LDS,
-// B = K2 rows from global memory), then folds x_{j+u} Z[j][u] into FP64
-// row partials; the 32 columns are summed across lanes at the end.
+// B = K2 rows from global memory; the first block starts the accumulators
+// from zero inside the matrix-core op), then folds x_{j+u} Z[j][u] into
+// FP64 row partials with one fused multiply-add per element (x in FP64 from
+// LDS; the product of two FP32 values is exact in FP64, so this rounds as a
+// product followed by a sum would); the 32 columns are summed across lanes
+// at the end.
 template <int PATH>
 __global__ void __launch_bounds__(256, 2)
 k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
@@ -220,13 +233,17 @@ k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
     constexpr bool SPLIT = PATH != HOS_PATH_FP32;
     float4 *s_f4 = (float4 *)lds;
     uint4 *s_h = lds + WA, *s_l = lds + 2 * WA;
+    double *s_d = (double *)(lds + (SPLIT ? 3 : 1) * WA);   // x in FP64, WA + 4 values
     {
         // this series' window (WA is the largest over the batch)
         const int WAs = ADJ_ROWS + KP + 64;
         const int64_t g0 = j0 - M;
         const float4 *f4 = (const float4 *)(r + d.o_win4);
+        const float *xf = (const float *)(r + d.o_xf);
         for (int e = threadIdx.x; e < WAs; e += 256)
             s_f4[e] = f4[g0 + e];
+        for (int e = threadIdx.x; e < WAs + 4; e += 256)
+            s_d[e] = (double)xf[g0 + e];
         if constexpr (SPLIT) {
             const uint4 *h = (const uint4 *)(r + d.o_win8h), *l = (const uint4 *)(r + d.o_win8l);
             for (int e = threadIdx.x; e < WAs; e += 256) {
@@ -246,33 +263,34 @@ k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
         E0[v] = 0.0;
         E1[v] = 0.0;
     }
+    // B fragments as k_adj_ksplit stores them: fragment (U, V, g) holds
+    // lane l's 8 values at [(frag * 64 + l) * 8, + 8)
     const uint4 *kh = (const uint4 *)(r + d.o_kh), *kl = (const uint4 *)(r + d.o_kl);
+    const floatx16 zero = {};
     for (int U = 0; U < NU; ++U) {
         floatx16 a0, a1;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            a0[v] = 0.0f;
-            a1[v] = 0.0f;
-        }
         const int Vmax = min(NU - 1, U + reach);
-        const int64_t krow = (int64_t)(U * 32 + rl) * KP;
-        for (int V = U; V <= Vmax; ++V) {
+        // one v block: 2 k-groups of 16; the first op of each accumulator in
+        // block V = U starts from zero
+        auto vstep = [&](int V, bool first) __attribute__((always_inline)) {
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
                 const int vl = V * 32 + 16 * g + 8 * h;   // first v' of this lane's 8
+                const bool z = first && g == 0;
+                const int64_t fl = ((int64_t)(U * NU + V) * 2 + g) * 64 + lane;
                 if constexpr (SPLIT) {
-                    const uint4 bh = kh[(krow + vl) >> 3], bl = kl[(krow + vl) >> 3];
+                    const uint4 bh = kh[fl], bl = kl[fl];
                     const uint4 ah0 = s_h[jr0 + rl + vl], al0 = s_l[jr0 + rl + vl];
                     const uint4 ah1 = s_h[jr1 + rl + vl], al1 = s_l[jr1 + rl + vl];
-                    a0 = mma16<PATH>(ah0, bh, a0);
-                    a1 = mma16<PATH>(ah1, bh, a1);
+                    a0 = mma16<PATH>(ah0, bh, z ? zero : a0);
+                    a1 = mma16<PATH>(ah1, bh, z ? zero : a1);
                     a0 = mma16<PATH>(ah0, bl, a0);
                     a1 = mma16<PATH>(ah1, bl, a1);
                     a0 = mma16<PATH>(al0, bh, a0);
                     a1 = mma16<PATH>(al1, bh, a1);
                 } else {
                     const float4 *kf = (const float4 *)(r + d.o_kh);
-                    const float4 b0 = kf[(krow + vl) >> 2], b1 = kf[((krow + vl) >> 2) + 1];
+                    const float4 b0 = kf[2 * fl], b1 = kf[2 * fl + 1];
                     const float4 x00 = s_f4[jr0 + rl + vl], x01 = s_f4[jr0 + rl + vl + 4];
                     const float4 x10 = s_f4[jr1 + rl + vl], x11 = s_f4[jr1 + rl + vl + 4];
                     const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
@@ -280,29 +298,32 @@ k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
                     const float xb[8] = {x10.x, x10.y, x10.z, x10.w, x11.x, x11.y, x11.z, x11.w};
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[e], bb[e], a0, 0, 0, 0);
-                        a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xb[e], bb[e], a1, 0, 0, 0);
+                        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[e], bb[e],
+                                                                  z && e == 0 ? zero : a0, 0, 0, 0);
+                        a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xb[e], bb[e],
+                                                                  z && e == 0 ? zero : a1, 0, 0, 0);
                     }
                 }
             }
-        }
+        };
+        vstep(U, true);
+        for (int V = U + 1; V <= Vmax; ++V)
+            vstep(V, false);
         // fold x_{j+u} Z[j][u]: element v of a lane is row 8(v/4) + 4h + v%4,
         // column u' = 32U + rl.  Odd U ran on negated K2 rows, so the
         // matrix cores' rounding bias (toward -infinity) alternates in sign
-        // between column blocks and cancels; the sign is undone here.
+        // between column blocks and cancels; the sign is undone here, on x
+        // (exact).
         const double sg = (U & 1) ? -1.0 : 1.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float4 y0 = s_f4[jr0 + 8 * q + 4 * h + U * 32 + rl];
-            const float4 y1 = s_f4[jr1 + 8 * q + 4 * h + U * 32 + rl];
-            E0[4 * q + 0] += sg * ((double)a0[4 * q + 0] * (double)y0.x);
-            E0[4 * q + 1] += sg * ((double)a0[4 * q + 1] * (double)y0.y);
-            E0[4 * q + 2] += sg * ((double)a0[4 * q + 2] * (double)y0.z);
-            E0[4 * q + 3] += sg * ((double)a0[4 * q + 3] * (double)y0.w);
-            E1[4 * q + 0] += sg * ((double)a1[4 * q + 0] * (double)y1.x);
-            E1[4 * q + 1] += sg * ((double)a1[4 * q + 1] * (double)y1.y);
-            E1[4 * q + 2] += sg * ((double)a1[4 * q + 2] * (double)y1.z);
-            E1[4 * q + 3] += sg * ((double)a1[4 * q + 3] * (double)y1.w);
+            const double *y0 = s_d + jr0 + 8 * q + 4 * h + U * 32 + rl;
+            const double *y1 = s_d + jr1 + 8 * q + 4 * h + U * 32 + rl;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                E0[4 * q + c] = __builtin_fma((double)a0[4 * q + c], sg * y0[c], E0[4 * q + c]);
+                E1[4 * q + c] = __builtin_fma((double)a1[4 * q + c], sg * y1[c], E1[4 * q + c]);
+            }
         }
     }
     // sum each row over the 32 columns (the lanes of a half-wave)
@@ -358,7 +379,7 @@ template <int PATH>
 void launch_adj_contract(const BatchHeader &h, const SeriesDesc *sd, char *ws, hipStream_t s)
 {
     const int WA = (int)(ADJ_ROWS + h.max_KP + 64);
-    const size_t lds = (size_t)WA * 16 * (PATH == HOS_PATH_FP32 ? 1 : 3);
+    const size_t lds = (size_t)WA * 16 * (PATH == HOS_PATH_FP32 ? 1 : 3) + (size_t)(WA + 4) * 8;
     const dim3 grid((unsigned)((h.max_n + ADJ_ROWS - 1) / ADJ_ROWS), (unsigned)h.batch);
     k_adj_contract<PATH><<<grid, 256, lds, s>>>(sd, ws, WA);
 }

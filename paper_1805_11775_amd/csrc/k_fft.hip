@@ -36,6 +36,7 @@ __global__ void k_twiddle(double2 *__restrict__ tw, int N)
 // Otherwise one buffer and the in-place stages (all their butterfly slots
 // are used once CB * N fills the LDS area).
 constexpr int FFT_MAX_CB = 64;
+constexpr int AXIS_PAD = 3;   // padding of the in-place axis transforms' LDS area (lds_at)
 
 template <int R, int THREADS>
 __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
@@ -81,6 +82,8 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
 {
     extern __shared__ double2 sm[];
     __shared__ int64_t base[FFT_MAX_CB];
+    // the in-place stages use a padded area (lds_at), the ping-pong ones not
+    constexpr int PAD = PP ? 0 : AXIS_PAD;
     const int N = fr.n;
     const int64_t seq0 = (int64_t)blockIdx.x * CB;
     const int tot = CB * N;
@@ -100,7 +103,7 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
         }
         const int64_t b = base[cb];
         if (b >= 0)
-            sm[cb * N + k] = data[b + k * es];
+            sm[lds_at<PAD>(cb * N + k)] = data[b + k * es];
     }
     __syncthreads();
     double2 *cur = sm, *nxt = sm + tot;
@@ -124,15 +127,15 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
             nxt = t;
         } else {
             if (R == 8)
-                stockham_stage<8, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
+                stockham_stage<8, THREADS, FFT_LDS_ELEMS, PAD>(sm, tw, N, Ns, CB, lg, lgNs);
             else if (R == 4)
-                stockham_stage<4, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
+                stockham_stage<4, THREADS, FFT_LDS_ELEMS, PAD>(sm, tw, N, Ns, CB, lg, lgNs);
             else if (R == 2)
-                stockham_stage<2, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
+                stockham_stage<2, THREADS, FFT_LDS_ELEMS, PAD>(sm, tw, N, Ns, CB, lg, lgNs);
             else if (R == 3)
-                stockham_stage<3, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
+                stockham_stage<3, THREADS, FFT_LDS_ELEMS, PAD>(sm, tw, N, Ns, CB, lg, lgNs);
             else
-                stockham_stage<5, THREADS>(sm, tw, N, Ns, CB, lg, lgNs);
+                stockham_stage<5, THREADS, FFT_LDS_ELEMS, PAD>(sm, tw, N, Ns, CB, lg, lgNs);
         }
         Ns *= R;
         lgNs += R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0;
@@ -148,7 +151,7 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
         }
         const int64_t b = base[cb];
         if (b >= 0)
-            data[b + k * es] = cur[cb * N + k];
+            data[b + k * es] = cur[lds_at<PAD>(cb * N + k)];
     }
 }
 
@@ -173,7 +176,7 @@ void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq,
     if (CB > 32)
         CB = 32;
     const int64_t blocks = (nseq + CB - 1) / CB;
-    const size_t lds = (size_t)CB * fr.n * sizeof(double2);
+    const size_t lds = (size_t)lds_slots<AXIS_PAD>(CB * fr.n) * sizeof(double2);
     if (fr.n >= 512)
         k_fft_axis<false, 1024><<<blocks, 1024, lds, s>>>(d, tw, fr, nseq, es, b_in, s_in, s_out,
                                                          CB);
