@@ -129,7 +129,7 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
         d.lpad = adj ? up(d.M, 64) : 0;
         int64_t npad = up(d.C * kcx + (int64_t)d.TR * 32 * d.NB + 64, 64);
         if (adj)
-            npad = std::max<int64_t>(npad, up(up(d.n, 256) + 256 + d.KP + 128, 64));
+            npad = std::max<int64_t>(npad, up(up(d.n, ADJ_ROWS) + ADJ_ROWS + d.KP + 128, 64));
         d.npad = npad;
         const int64_t ent = d.lpad + d.npad;
         d.ws_off = (int64_t)o;

@@ -30,7 +30,6 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int ADJ_ROWS = 256;   // rows j per workgroup: 4 waves x 2 blocks of 32
 
 // Packed index of (k1, k2) in the principal domain 0 <= k2 <= k1,
 // k1 + k2 <= H = floor((N-1)/2), or -1.  Row k1 holds min(k1, H - k1) + 1
@@ -209,20 +208,23 @@ __device__ inline floatx16 mma16(uint4 a, uint4 b, floatx16 c)
 }
 
 // g_j s^2 sk for ADJ_ROWS rows j per workgroup (blockIdx.y = series).  The
-// workgroup stages the table entries its rows touch, [j0 - M, j0 + ROWS +
-// KP + 64 - M), in LDS; wave w owns rows j0 + 64w + [0, 64) as two 32-row
-// blocks.  For each 32-column block U of u it accumulates Z = H K2^T over
-// the v blocks V >= U within the hexagon's reach (A = Hankel rows from LDS,
-// B = K2 rows from global memory; the first block starts the accumulators
-// from zero inside the matrix-core op), then folds x_{j+u} Z[j][u] into
-// FP64 row partials with one fused multiply-add per element (x in FP64 from
-// LDS; the product of two FP32 values is exact in FP64, so this rounds as a
-// product followed by a sum would); the 32 columns are summed across lanes
-// at the end.
+// workgroup stages the table entries its rows touch, [j0 - M, j0 + ADJ_ROWS
+// + KP - M), in LDS; wave w owns rows j0 + 32 ADJ_NRB w + [0, 32 ADJ_NRB) as
+// ADJ_NRB blocks of 32.  For each 32-block U of u it accumulates the
+// transposed product Z^T = K2 H^T over the v blocks V >= U within the
+// hexagon's reach (A = the K2 fragments from global memory, B = Hankel
+// columns x_{j+v} from LDS; the first block starts the accumulators from
+// zero inside the matrix-core op).  In that orientation a lane's column is
+// one row j and its 16 values are 16 of the u, so the fold
+// g_j += sum_u x_{j+u} Z[j][u] stays inside the lane: one FP64 multiply-add
+// per value into a per-block partial (x in FP64 from LDS, the FP32 x FP32
+// product exact in FP64), one FP64 partial per row block per lane, and the
+// two lanes of a row are added at the end.
 template <int PATH>
 __global__ void __launch_bounds__(256, 2)
 k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
 {
+    constexpr int NRB = ADJ_NRB;
     extern __shared__ uint4 lds[];
     const SeriesDesc &d = sd[blockIdx.y];
     const int64_t j0 = (int64_t)blockIdx.x * ADJ_ROWS;
@@ -231,77 +233,75 @@ k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
     const int M = d.M, KP = d.KP, NU = KP >> 5, reach = (M + 31) >> 5;
     char *r = ws + d.ws_off;
     constexpr bool SPLIT = PATH != HOS_PATH_FP32;
+    // split paths: hi | lo window tables and the FP64 pairs; FP32: the FP32
+    // window table and the FP64 pairs (WA entries each)
     float4 *s_f4 = (float4 *)lds;
-    uint4 *s_h = lds + WA, *s_l = lds + 2 * WA;
-    double *s_d = (double *)(lds + (SPLIT ? 3 : 1) * WA);   // x in FP64, WA + 4 values
+    uint4 *s_h = lds, *s_l = lds + WA;
+    double2 *s_d2 = (double2 *)(lds + (SPLIT ? 2 : 1) * WA);
     {
         // this series' window (WA is the largest over the batch)
-        const int WAs = ADJ_ROWS + KP + 64;
+        const int WAs = ADJ_ROWS + KP;
         const int64_t g0 = j0 - M;
-        const float4 *f4 = (const float4 *)(r + d.o_win4);
         const float *xf = (const float *)(r + d.o_xf);
-        for (int e = threadIdx.x; e < WAs; e += 256)
-            s_f4[e] = f4[g0 + e];
-        for (int e = threadIdx.x; e < WAs + 4; e += 256)
-            s_d[e] = (double)xf[g0 + e];
         if constexpr (SPLIT) {
             const uint4 *h = (const uint4 *)(r + d.o_win8h), *l = (const uint4 *)(r + d.o_win8l);
             for (int e = threadIdx.x; e < WAs; e += 256) {
                 s_h[e] = h[g0 + e];
                 s_l[e] = l[g0 + e];
             }
+        } else {
+            const float4 *f4 = (const float4 *)(r + d.o_win4);
+            for (int e = threadIdx.x; e < WAs; e += 256)
+                s_f4[e] = f4[g0 + e];
         }
+        // entry e = (x_{g0+e}, x_{g0+e+1}) in FP64
+        for (int e = threadIdx.x; e < WAs; e += 256)
+            s_d2[e] = make_double2((double)xf[g0 + e], (double)xf[g0 + e + 1]);
     }
     __syncthreads();
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, rl = lane & 31, h = lane >> 5;
-    const int jr0 = wave * 64, jr1 = wave * 64 + 32;
-    double E0[16], E1[16];
+    const int jw = wave * 32 * NRB + rl;   // this lane's row j - j0 in block 0
+    double E[NRB];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        E0[v] = 0.0;
-        E1[v] = 0.0;
-    }
-    // B fragments as k_adj_ksplit stores them: fragment (U, V, g) holds
+    for (int b = 0; b < NRB; ++b)
+        E[b] = 0.0;
+    // A fragments as k_adj_ksplit stores them: fragment (U, V, g) holds
     // lane l's 8 values at [(frag * 64 + l) * 8, + 8)
     const uint4 *kh = (const uint4 *)(r + d.o_kh), *kl = (const uint4 *)(r + d.o_kl);
     const floatx16 zero = {};
     for (int U = 0; U < NU; ++U) {
-        floatx16 a0, a1;
+        floatx16 a[NRB];
         const int Vmax = min(NU - 1, U + reach);
-        // one v block: 2 k-groups of 16; the first op of each accumulator in
-        // block V = U starts from zero
+        // one v block: 2 k-groups of 16
         auto vstep = [&](int V, bool first) __attribute__((always_inline)) {
 #pragma unroll
             for (int g = 0; g < 2; ++g) {
-                const int vl = V * 32 + 16 * g + 8 * h;   // first v' of this lane's 8
+                const int vl = V * 32 + 16 * g + 8 * h;   // first v of this lane's 8
                 const bool z = first && g == 0;
                 const int64_t fl = ((int64_t)(U * NU + V) * 2 + g) * 64 + lane;
                 if constexpr (SPLIT) {
-                    const uint4 bh = kh[fl], bl = kl[fl];
-                    const uint4 ah0 = s_h[jr0 + rl + vl], al0 = s_l[jr0 + rl + vl];
-                    const uint4 ah1 = s_h[jr1 + rl + vl], al1 = s_l[jr1 + rl + vl];
-                    a0 = mma16<PATH>(ah0, bh, z ? zero : a0);
-                    a1 = mma16<PATH>(ah1, bh, z ? zero : a1);
-                    a0 = mma16<PATH>(ah0, bl, a0);
-                    a1 = mma16<PATH>(ah1, bl, a1);
-                    a0 = mma16<PATH>(al0, bh, a0);
-                    a1 = mma16<PATH>(al1, bh, a1);
+                    const uint4 kH = kh[fl], kL = kl[fl];
+#pragma unroll
+                    for (int b = 0; b < NRB; ++b) {
+                        const uint4 xh = s_h[jw + 32 * b + vl], xl = s_l[jw + 32 * b + vl];
+                        a[b] = mma16<PATH>(kH, xh, z ? zero : a[b]);
+                        a[b] = mma16<PATH>(kL, xh, a[b]);
+                        a[b] = mma16<PATH>(kH, xl, a[b]);
+                    }
                 } else {
                     const float4 *kf = (const float4 *)(r + d.o_kh);
                     const float4 b0 = kf[2 * fl], b1 = kf[2 * fl + 1];
-                    const float4 x00 = s_f4[jr0 + rl + vl], x01 = s_f4[jr0 + rl + vl + 4];
-                    const float4 x10 = s_f4[jr1 + rl + vl], x11 = s_f4[jr1 + rl + vl + 4];
-                    const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-                    const float xa[8] = {x00.x, x00.y, x00.z, x00.w, x01.x, x01.y, x01.z, x01.w};
-                    const float xb[8] = {x10.x, x10.y, x10.z, x10.w, x11.x, x11.y, x11.z, x11.w};
+                    const float kk[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[e], bb[e],
-                                                                  z && e == 0 ? zero : a0, 0, 0, 0);
-                        a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(xb[e], bb[e],
-                                                                  z && e == 0 ? zero : a1, 0, 0, 0);
+                    for (int b = 0; b < NRB; ++b) {
+                        const float4 x0 = s_f4[jw + 32 * b + vl], x1 = s_f4[jw + 32 * b + vl + 4];
+                        const float xx[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            a[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                                kk[e], xx[e], z && e == 0 ? zero : a[b], 0, 0, 0);
                     }
                 }
             }
@@ -309,43 +309,34 @@ k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
         vstep(U, true);
         for (int V = U + 1; V <= Vmax; ++V)
             vstep(V, false);
-        // fold x_{j+u} Z[j][u]: element v of a lane is row 8(v/4) + 4h + v%4,
-        // column u' = 32U + rl.  Odd U ran on negated K2 rows, so the
-        // matrix cores' rounding bias (toward -infinity) alternates in sign
-        // between column blocks and cancels; the sign is undone here, on x
-        // (exact).
+        // fold: value v of a lane is u = 32U + 8(v/4) + 4h + v%4 of its row
+        // j.  Odd U ran on negated K2 rows, so the matrix cores' rounding
+        // bias (toward -infinity) alternates in sign between blocks and
+        // cancels; the sign is undone on the block's partial (exact).
         const double sg = (U & 1) ? -1.0 : 1.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double *y0 = s_d + jr0 + 8 * q + 4 * h + U * 32 + rl;
-            const double *y1 = s_d + jr1 + 8 * q + 4 * h + U * 32 + rl;
+        for (int b = 0; b < NRB; ++b) {
+            double part = 0.0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                E0[4 * q + c] = __builtin_fma((double)a0[4 * q + c], sg * y0[c], E0[4 * q + c]);
-                E1[4 * q + c] = __builtin_fma((double)a1[4 * q + c], sg * y1[c], E1[4 * q + c]);
+            for (int q = 0; q < 4; ++q) {
+                const int o = jw + 32 * b + 32 * U + 8 * q + 4 * h;
+                const double2 y01 = s_d2[o], y23 = s_d2[o + 2];
+                part = __builtin_fma((double)a[b][4 * q + 0], y01.x, part);
+                part = __builtin_fma((double)a[b][4 * q + 1], y01.y, part);
+                part = __builtin_fma((double)a[b][4 * q + 2], y23.x, part);
+                part = __builtin_fma((double)a[b][4 * q + 3], y23.y, part);
             }
+            E[b] = __builtin_fma(sg, part, E[b]);
         }
     }
-    // sum each row over the 32 columns (the lanes of a half-wave)
+    // the two lanes of a row (h = 0, 1) hold disjoint u
+    double *gt = (double *)(r + d.o_gtil);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-#pragma unroll
-        for (int off = 1; off < 32; off <<= 1) {
-            E0[v] += __shfl_xor(E0[v], off, 64);
-            E1[v] += __shfl_xor(E1[v], off, 64);
-        }
-    }
-    if (rl == 0) {
-        double *gt = (double *)(r + d.o_gtil);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int row = 8 * (v >> 2) + 4 * h + (v & 3);
-            const int64_t ja = j0 + jr0 + row, jb = j0 + jr1 + row;
-            if (ja < d.n)
-                gt[ja] = E0[v];
-            if (jb < d.n)
-                gt[jb] = E1[v];
-        }
+    for (int b = 0; b < NRB; ++b) {
+        const double t = E[b] + __shfl_xor(E[b], 32, 64);
+        const int64_t j = j0 + jw + 32 * b;
+        if (h == 0 && j < d.n)
+            gt[j] = t;
     }
 }
 
@@ -378,8 +369,8 @@ k_adj_final(const SeriesDesc *__restrict__ sd, const char *__restrict__ ws, T *_
 template <int PATH>
 void launch_adj_contract(const BatchHeader &h, const SeriesDesc *sd, char *ws, hipStream_t s)
 {
-    const int WA = (int)(ADJ_ROWS + h.max_KP + 64);
-    const size_t lds = (size_t)WA * 16 * (PATH == HOS_PATH_FP32 ? 1 : 3) + (size_t)(WA + 4) * 8;
+    const int WA = (int)(ADJ_ROWS + h.max_KP);
+    const size_t lds = (size_t)WA * 16 * (PATH == HOS_PATH_FP32 ? 2 : 3);
     const dim3 grid((unsigned)((h.max_n + ADJ_ROWS - 1) / ADJ_ROWS), (unsigned)h.batch);
     k_adj_contract<PATH><<<grid, 256, lds, s>>>(sd, ws, WA);
 }
