@@ -282,8 +282,8 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
                uint32_t flags, const int32_t *tile_nb, void *blob, size_t blob_bytes,
                BatchHeader *hdr_out);
 int device_ok_public();
-constexpr int ADJ_MAX_M = 320;     // staged adjoint window <= 57 KB of LDS
-constexpr int ADJ_NRB = 4;         // adjoint contraction: 32-row blocks per wave
+constexpr int ADJ_MAX_M = 320;     // staged adjoint window <= 81 KB of LDS
+constexpr int ADJ_NRB = 8;         // adjoint contraction: 32-row blocks per wave
 constexpr int ADJ_ROWS = 4 * 32 * ADJ_NRB;   // rows j per workgroup (four waves)
 
 // ---------------------------------------------------------------------------

@@ -183,6 +183,35 @@ def test_loss_gradient_float64():
 
 
 @pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_loss_gradient_largest_lag(path):
+    """The adjoint at the largest lag it takes (M = 320, N = 640: the
+    largest staged window, several 1024-row workgroups of the contraction,
+    series of uneven length with partial last workgroups) against the
+    oracle's full gradient."""
+    hos = _hos()
+    n, M, N = [2600, 1900], 320, 640
+    X = [synth.iid_exp_centered(k, 90 + i).astype(np.float32) for i, k in enumerate(n)]
+    tgt = synth.quadratic_process(2400, 97)
+    k1, k2 = oracle.pd_indices(N)
+    target = oracle.bispectrum(tgt, M, N)[1][k1, k2]
+    plan = hos.BatchPlan(n, [M, M], path=path, adjoint=True)
+    print("case: loss gradient M=320, path %s" % path, flush=True)
+    x = torch.from_numpy(np.concatenate(X)).cuda()
+    loss, B = hos.bispectrum_loss_fwd(x, torch.from_numpy(target), plan)
+    dx = hos.bispectrum_loss_bwd(x, torch.from_numpy(target), B,
+                                 torch.ones((), dtype=torch.float64), plan)
+    torch.cuda.synchronize()
+    dx = dx.cpu().numpy()
+    off = 0
+    for b, xb in enumerate(X):
+        ref = oracle.bispectrum_loss_grad(xb, M, N, target)
+        e = _rel(dx[off:off + xb.size], ref)
+        print("series %d grad rel err %.3e" % (b, e))
+        assert e < TOL[path]
+        off += xb.size
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
 def test_loss_workload_sampled(path):
     """64 float32 N(0,1) series of n = 65536, M = 256, N = 512 (the
     differentiable-bispectrum shape): loss of two series and gradient
