@@ -104,8 +104,10 @@ k_adj_gtab(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int window)
     ((double *)(ws + d.ws_off + d.o_gtab))[idx] = g_at(F, d.N, M, window, w1, w2);
 }
 
-// K2 in FP64 over [0, KP)^2 (u' = u + M, v' = v + M; padding is 0), and the
-// running max |K2| (a workgroup's maximum, then one atomic maximum).
+// K2 in FP64 over the 32-blocks on and above the block diagonal of
+// [0, KP)^2 (u' = u + M, v' = v + M; padding is 0; the blocks below are
+// never read, so they are not written), and the running max |K2| (a
+// workgroup's maximum, then one atomic maximum).
 __global__ void __launch_bounds__(256)
 k_adj_kbuild(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
 {
@@ -114,10 +116,10 @@ k_adj_kbuild(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
     const int KP = d.KP, M = d.M, S = 2 * M + 1;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double val = 0.0;
-    if (idx < (int64_t)KP * KP) {
-        const int up = (int)(idx / KP), vp = (int)(idx % KP);
-        const int bu = up >> 5, bv = vp >> 5;
-        if (up <= 2 * M && vp <= 2 * M && bv >= bu) {
+    const int up = (int)(idx / KP), vp = (int)(idx % KP);
+    const int bu = up >> 5, bv = vp >> 5;
+    if (idx < (int64_t)KP * KP && bv >= bu) {
+        if (up <= 2 * M && vp <= 2 * M) {
             const double *Gt = (const double *)(ws + d.ws_off + d.o_gtab);
             const int u = up - M, v = vp - M;
             auto G = [&](int a, int b) {
@@ -174,6 +176,8 @@ k_adj_ksplit(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
     const int e = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
     const int64_t f = idx >> 9;
     const int g = (int)(f & 1), V = (int)((f >> 1) % NU), U = (int)((f >> 1) / NU);
+    if (V < U)
+        return;   // below the block diagonal: never read
     const int u = U * 32 + (lane & 31), vv = V * 32 + 16 * g + 8 * (lane >> 5) + e;
     // rows of odd 32-blocks of u are stored negated (see k_adj_contract)
     const double sk = kscale(__longlong_as_double((long long)*kmax_bits(d, ws)));
