@@ -377,8 +377,8 @@ hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double 
                             int N, int window, const double2 *tw, double *T, hipStream_t s);
 hipError_t launch_fft3_tail(double *T, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s);
-hipError_t launch_fft2_batch(double *grids, int N, int count, int live, const double2 *tw,
-                             hipStream_t s);
+hipError_t launch_fft2_batch(double *grids, int N, int count, int rows, int cols,
+                             const double2 *tw, hipStream_t s);
 hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window, char *ws,
                              double *B_pd, hipStream_t s);
 

@@ -62,20 +62,23 @@ k_adj_resid(const SeriesDesc *__restrict__ sd, const double2 *__restrict__ B_pd,
             char *__restrict__ ws)
 {
     const SeriesDesc &d = sd[blockIdx.y];
-    const int N = d.N;
+    const int N = d.N, H = (N - 1) / 2, C2 = H / 2 + 1;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx == 0)
         *kmax_bits(d, ws) = 0ull;
-    if (idx >= (int64_t)N * N)
+    // the corner k1 <= H, k2 <= H / 2 holds the principal domain; the DFT
+    // reads nothing outside it
+    if (idx >= (int64_t)(H + 1) * C2)
         return;
-    const int p = pd_index((int)(idx / N), (int)(idx % N), N);
+    const int k1 = (int)(idx / C2), k2 = (int)(idx % C2);
+    const int p = pd_index(k1, k2, N);
     double2 v = make_double2(0.0, 0.0);
     if (p >= 0) {
         const double2 b = B_pd[d.pd_off + p], t = target[p];
         const double c = 2.0 * dL[0];
         v = make_double2(c * (b.x - t.x), -c * (b.y - t.y));
     }
-    ((double2 *)(ws + d.grid_off))[idx] = v;
+    ((double2 *)(ws + d.grid_off))[(int64_t)k1 * N + k2] = v;
 }
 
 // G(w) from the transformed grid (0 outside the hexagon).
@@ -388,18 +391,20 @@ hipError_t launch_batch_adjoint(const void *x, int dtype, const BatchHeader &h, 
     (void)x;
     const SeriesDesc *sd = (const SeriesDesc *)(dplan + h.series_off);
     const int B = (int)h.batch;
-    const int64_t n2 = h.max_N * h.max_N;
-    k_adj_resid<<<dim3((unsigned)((n2 + 255) / 256), B), 256, 0, s>>>(
+    const int64_t Hm = (h.max_N - 1) / 2, corner = (Hm + 1) * (Hm / 2 + 1);
+    k_adj_resid<<<dim3((unsigned)((corner + 255) / 256), B), 256, 0, s>>>(
         sd, (const double2 *)B_pd, (const double2 *)target, dL, ws);
     const FftGroup *groups = (const FftGroup *)((const char *)&h + h.groups_off);
     for (int g = 0; g < (int)h.n_groups; ++g) {
         const FftGroup &gr = groups[g];
         double2 *tw = (double2 *)(ws + gr.twid_off);
         hipError_t e = launch_twiddles(tw, gr.N, s);
+        // the residual sits on the principal domain: rows k1 <= H = (N - 1) / 2,
+        // columns k2 <= H / 2
+        const int H = (gr.N - 1) / 2;
         if (e == hipSuccess)
-            // the residual sits on the principal domain: rows k1 <= (N - 1) / 2
-            e = launch_fft2_batch((double *)(ws + gr.grid_off), gr.N, gr.count,
-                                  (gr.N - 1) / 2 + 1, tw, s);
+            e = launch_fft2_batch((double *)(ws + gr.grid_off), gr.N, gr.count, H + 1, H / 2 + 1,
+                                  tw, s);
         if (e != hipSuccess)
             return e;
     }

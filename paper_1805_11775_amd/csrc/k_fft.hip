@@ -78,7 +78,8 @@ __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
 template <bool PP, int THREADS>
 __global__ void __launch_bounds__(THREADS)
 k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadices fr,
-           int64_t nseq, int64_t es, int64_t b_in, int64_t s_in, int64_t s_out, int CB)
+           int64_t nseq, int64_t es, int64_t b_in, int64_t s_in, int64_t s_out, int CB,
+           int live)
 {
     extern __shared__ double2 sm[];
     __shared__ int64_t base[FFT_MAX_CB];
@@ -103,7 +104,7 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
         }
         const int64_t b = base[cb];
         if (b >= 0)
-            sm[lds_at<PAD>(cb * N + k)] = data[b + k * es];
+            sm[lds_at<PAD>(cb * N + k)] = k < live ? data[b + k * es] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     double2 *cur = sm, *nxt = sm + tot;
@@ -155,9 +156,13 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
     }
 }
 
+// Elements k >= live of every sequence are taken as 0 and not read (live =
+// N: all of them).
 void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq, int64_t es,
-              int64_t b_in, int64_t s_in, int64_t s_out, hipStream_t s)
+              int64_t b_in, int64_t s_in, int64_t s_out, hipStream_t s, int live = -1)
 {
+    if (live < 0)
+        live = fr.n;
     // ping-pong while both buffers of >= 8 sequences fit the 64 KB area
     // (N <= 256), else in place
     int CB = FFT_LDS_ELEMS / (2 * fr.n);
@@ -167,7 +172,7 @@ void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq,
         const int64_t blocks = (nseq + CB - 1) / CB;
         k_fft_axis<true, FFT_THREADS><<<blocks, FFT_THREADS,
                                         2 * (size_t)CB * fr.n * sizeof(double2), s>>>(
-            d, tw, fr, nseq, es, b_in, s_in, s_out, CB);
+            d, tw, fr, nseq, es, b_in, s_in, s_out, CB, live);
         return;
     }
     // in place: long transforms fill the LDS area with few sequences, so a
@@ -179,10 +184,11 @@ void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq,
     const size_t lds = (size_t)lds_slots<AXIS_PAD>(CB * fr.n) * sizeof(double2);
     if (fr.n >= 512)
         k_fft_axis<false, 1024><<<blocks, 1024, lds, s>>>(d, tw, fr, nseq, es, b_in, s_in, s_out,
-                                                         CB);
+                                                         CB, live);
     else
         k_fft_axis<false, FFT_THREADS><<<blocks, FFT_THREADS, lds, s>>>(d, tw, fr, nseq, es,
-                                                                       b_in, s_in, s_out, CB);
+                                                                       b_in, s_in, s_out, CB,
+                                                                       live);
 }
 
 }  // namespace
@@ -209,17 +215,19 @@ hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s)
 
 namespace hos {
 
-// In-place 2-D DFTs of `count` contiguous N x N row-major complex grids.
-// Only the first `live` rows of each grid may be nonzero (the rest are 0 and
-// stay 0 under the row transforms, which therefore skip them).
-hipError_t launch_fft2_batch(double *grids, int N, int count, int live, const double2 *tw,
-                             hipStream_t s)
+// In-place 2-D DFTs of `count` contiguous N x N row-major complex grids
+// whose input is nonzero only in the first `rows` rows and `cols` columns;
+// nothing outside that corner is read (it may hold anything).  The columns
+// k2 < cols are transformed first (their elements k1 >= rows taken as 0),
+// then every row (its elements k2 >= cols taken as 0).
+hipError_t launch_fft2_batch(double *grids, int N, int count, int rows, int cols,
+                             const double2 *tw, hipStream_t s)
 {
     double2 *d = (double2 *)grids;
     const FftRadices fr = factor(N);
     const int64_t N2 = (int64_t)N * N;
-    fft_axis(d, tw, fr, (int64_t)count * live, 1, live, N, N2, s);   // along k2, live rows
-    fft_axis(d, tw, fr, (int64_t)count * N, N, N, 1, N2, s);         // along k1
+    fft_axis(d, tw, fr, (int64_t)count * cols, N, cols, 1, N2, s, rows);   // along k1
+    fft_axis(d, tw, fr, (int64_t)count * N, 1, N, N, N2, s, cols);         // along k2
     return hipGetLastError();
 }
 
