@@ -40,8 +40,9 @@ __device__ inline double window3(int w1, int w2, int M, int window)
 // [a][b] (b <= a <= M).  The square's corners (M < a <= 2M, a - M <= b <= M),
 // present when amax = 2M, sit in the upper triangle: C[a][b] at [c][b] with
 // c = a - M - 1 < b.  Lags with span a > amax give 0.
-__device__ inline double c3_from_table(const double *__restrict__ cfull, int M, int amax,
-                                       double norm, int w1, int w2)
+// The table entry of lag (w1, w2), not yet divided by n s^3.
+__device__ inline double c3_table_sum(const double *__restrict__ cfull, int M, int amax, int w1,
+                                      int w2)
 {
     const int mn = min(0, min(w1, w2)), mx = max(0, max(w1, w2));
     const int a = mx - mn;
@@ -49,7 +50,13 @@ __device__ inline double c3_from_table(const double *__restrict__ cfull, int M, 
         return 0.0;
     const int b = (w1 + w2) - mn - mx - mn;
     const int row = a <= M ? a : a - M - 1;
-    return cfull[(int64_t)row * (M + 1) + b] / norm;
+    return cfull[(int64_t)row * (M + 1) + b];
+}
+
+__device__ inline double c3_from_table(const double *__restrict__ cfull, int M, int amax,
+                                       double norm, int w1, int w2)
+{
+    return c3_table_sum(cfull, M, amax, w1, w2) / norm;
 }
 
 // Fourth-order table helpers.  The lag pairs (a, b), 0 <= b <= a <= M, are

@@ -270,7 +270,7 @@ __device__ inline int pd_row_start(int k1, int H)
 struct FoldArgs {
     const double *cfull;
     const double *dwin;   // d(0..M) (or 1: no window)
-    double norm;
+    double inv_norm;      // 1 / (n s^3), formed once per thread
     int M, amax, N;
     bool pdiff;           // Parzen product: d on the difference too
 };
@@ -286,7 +286,7 @@ __device__ __attribute__((always_inline)) inline double fold_centred(const FoldA
     if (!in)
         return 0.0;
     const double wt = f.dwin[abs(w1)] * f.dwin[abs(w2)] * (f.pdiff ? f.dwin[abs(dw)] : 1.0);
-    return wt * c3_from_table(f.cfull, f.M, f.amax, f.norm, w1, w2);
+    return (wt * f.inv_norm) * c3_table_sum(f.cfull, f.M, f.amax, w1, w2);
 }
 
 constexpr int PD_LDS_ELEMS = 2048;   // complex doubles per workgroup (32 KB): 4+ per CU
@@ -337,7 +337,7 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
     __syncthreads();
     // batches hold the hexagon only (Parzen window)
     const FoldArgs f = {(const double *)(r + d.o_cfull), dwin,
-                        ((const double *)(r + d.o_stats))[3], M, M, N,
+                        1.0 / ((const double *)(r + d.o_stats))[3], M, M, N,
                         window == HOS_WIN_PARZEN};
     const int m1_0 = blk * 2 * CBP;
     // A wave covers all CBP row pairs of 64 / CBP consecutive columns: off
@@ -418,7 +418,7 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
     for (int m = threadIdx.x; m <= M; m += THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
-    const FoldArgs f = {cfull, dwin, stats[3], M, amax, N, window == HOS_WIN_PARZEN};
+    const FoldArgs f = {cfull, dwin, 1.0 / stats[3], M, amax, N, window == HOS_WIN_PARZEN};
     const int m1_0 = blockIdx.x * 2 * CBP;
 #pragma unroll 4
     for (int e = threadIdx.x; e < CBP * N; e += THREADS) {
