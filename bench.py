@@ -701,6 +701,25 @@ def traffic_record(path=TRAFFIC_FILE, source=C3_SOURCE):
         return None
 
 
+def issued_flops(flops):
+    """FLOP the split-FP16 c3 contraction issues per launch: its MFMA count
+    from the committed PMC summary (while it matches the source) x 2*32*32*16,
+    else three products per algorithmic MAC (which leaves out the blocks'
+    triangle waste)."""
+    n = profile_value(MFMA_BUSY_FILE, "sq_insts_mfma", C3_SOURCE)
+    return n * 2.0 * 32 * 32 * 16 if n else 3.0 * flops
+
+
+def ceiling_record(hos, path, issued_flops_per_s):
+    """The measured matrix-core ceiling for ``path`` and the issued rate's
+    fraction of it."""
+    r = hos.mfma_rate(path, 1 << 19)
+    return {"tflops": r["tflops"], "frac_of_peak": r["tflops"] * 1e12 / PEAK[path],
+            "issued_tflops": issued_flops_per_s / 1e12,
+            "issued_frac_of_ceiling": issued_flops_per_s / (r["tflops"] * 1e12),
+            "probe": "4 waves/CU, 4 independent 32x32 MFMA chains, %.1f ms" % r["ms"]}
+
+
 def cpu_baseline(oracle, x, M, seconds):
     """Oracle c3 (FP64 brute force, OpenMP) on a bounded sample of lags of
     the same series; rate in lag-sums/s."""
@@ -822,7 +841,11 @@ def main():
                      # matrix-core busy cycles over the kernel's cycles (rocprofv3 PMC),
                      # issued work: three FP16 products per algorithmic MAC plus the
                      # blocks' triangle waste
-                     "mfma_busy": profile_value(MFMA_BUSY_FILE, "mfma_busy_frac", C3_SOURCE)},
+                     "mfma_busy": profile_value(MFMA_BUSY_FILE, "mfma_busy_frac", C3_SOURCE),
+                     # the matrix cores' attainable rate on this device, measured
+                     # now (hos_mfma_rate: independent ops only), and the
+                     # contraction's issued MFMA rate against it
+                     "mfma_ceiling": ceiling_record(hos, head, issued_flops(flops) / t_k)},
         "paths": paths,
     }
     if not args.no_batch:

@@ -433,6 +433,21 @@ int hos_tune_workspace(int32_t path, const int32_t *Ms, int32_t nM, const int64_
 int hos_tune(int32_t path, const int32_t *Ms, int32_t nM, const int64_t *n_edges, int32_t nb,
              int32_t series, int32_t reps, void *ws, size_t ws_bytes, int32_t *tile_out,
              float *ms_out, hipStream_t stream);
+/*
+ * Measurement helper (not a step of the estimator): the matrix cores'
+ * attainable rate on the current device.  One four-wave workgroup per
+ * compute unit issues `iters` rounds of four independent 32 x 32 MFMA ops
+ * per wave (v_mfma_f32_32x32x16_f16 / _bf16 for the split paths,
+ * v_mfma_f32_32x32x2_f32 for HOS_PATH_FP32) and nothing else; a short
+ * warm-up launch precedes the timed one.
+ *   iters      1 .. 2^24 (2^19 runs for about 40 ms on MI355X).
+ *   ms_out     host: the timed launch's milliseconds (HIP events).
+ *   flops_out  host: the FLOP that launch issued (2 x 32 x 32 x k per op).
+ * WAITS for `stream`.  Writes no device memory.  HOS_EINVAL for a bad path
+ * or count (checked before any HIP call).
+ */
+int hos_mfma_rate(int32_t path, int32_t iters, float *ms_out, double *flops_out,
+                  hipStream_t stream);
 int hos_batch_series(const void *plan, int64_t *out, int64_t cap);
 int hos_batch_items(const void *plan, int32_t cls, int64_t *out, int64_t cap);
 

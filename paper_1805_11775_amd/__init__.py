@@ -113,6 +113,8 @@ def _load_lib():
         "hos_tune": (ctypes.c_int, [i32, ctypes.POINTER(ctypes.c_int32), i32, p64, i32, i32, i32,
                                     vp, sz, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_float), vp]),
+        "hos_mfma_rate": (ctypes.c_int, [i32, i32, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_double), vp]),
         "hos_batch_series": (ctypes.c_int, [vp, p64, i64]),
         "hos_batch_items": (ctypes.c_int, [vp, i32, p64, i64]),
         "hos_bispectrum_batched": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
@@ -321,6 +323,21 @@ def default_nfft(M: int, window: str = "parzen") -> int:
 def _stream_handle(device):
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def mfma_rate(path: str = "split_fp16", iters: int = 1 << 19, device="cuda") -> dict:
+    """``hos_mfma_rate``: the matrix cores' attainable rate on ``device``
+    (independent 32 x 32 ops, one wave per SIMD; a measurement helper, not a
+    step of the estimator).  Returns {"ms", "flops", "tflops"}."""
+    import torch
+    ms = ctypes.c_float(0.0)
+    fl = ctypes.c_double(0.0)
+    st = lib().hos_mfma_rate(PATHS[path], int(iters), ctypes.byref(ms), ctypes.byref(fl),
+                             _stream_handle(torch.device(device)))
+    if st != HOS_OK:
+        raise HosError(st, "hos_mfma_rate")
+    return {"ms": float(ms.value), "flops": float(fl.value),
+            "tflops": float(fl.value) / (float(ms.value) * 1e-3) / 1e12}
 
 
 def bispectrum(x, M: int, nfft: int | None = None, window: str = "parzen",

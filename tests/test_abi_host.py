@@ -122,6 +122,16 @@ def test_workspace_flags(n, M, N, path):
         hos.hos_bispectrum_workspace(n, M, 0, path)
 
 
+@pytest.mark.parametrize("path,iters", [(7, 100), (hos.HOS_PATH_SPLIT_FP16, 0),
+                                        (hos.HOS_PATH_FP32, (1 << 24) + 1)])
+def test_mfma_rate_validation_before_device(path, iters):
+    ms, fl = ctypes.c_float(0.0), ctypes.c_double(0.0)
+    assert hos.lib().hos_mfma_rate(path, iters, ctypes.byref(ms), ctypes.byref(fl),
+                                   None) == hos.HOS_EINVAL
+    assert hos.lib().hos_mfma_rate(hos.HOS_PATH_SPLIT_FP16, 100, None, ctypes.byref(fl),
+                                   None) == hos.HOS_EINVAL
+
+
 def test_pd_count_matches_the_oracle():
     for N in (2, 3, 4, 7, 16, 33, 128, 1024):
         assert hos.pd_count(N) == len(oracle.pd_indices(N)[0])

@@ -297,3 +297,13 @@ def test_max_dft(path):
     s2 = float((b - bc).abs().max()) / scale
     print("symmetry %.3e %.3e" % (s1, s2))
     assert s1 < 1e-12 and s2 < 1e-12
+
+
+@pytest.mark.parametrize("path,peak", [("split_fp16", 2.5166e15), ("fp32", 157.3e12)])
+def test_mfma_rate_probe(path, peak):
+    """The measurement helper behind the benchmark's matrix-core ceiling: a
+    positive rate below the published dense peak."""
+    hos = _hos()
+    r = hos.mfma_rate(path, 1 << 16)
+    print("mfma rate %s: %.1f TFLOP/s in %.2f ms" % (path, r["tflops"], r["ms"]))
+    assert r["ms"] > 0.0 and 0.05 * peak < r["tflops"] * 1e12 < 1.02 * peak
