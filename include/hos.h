@@ -375,7 +375,8 @@ int hos_c5_plan_info(int64_t n, int32_t M, int32_t path, int64_t *info, int32_t 
  */
 
 /* Plan and workspace sizes for a batch.  n, M: host arrays of `batch`
- * entries (n >= 2, 0 <= M < n, DFT size N <= 2048, i.e. M <= 1024 with
+ * entries (1 <= batch <= 65535: the series index is a grid dimension of
+ * the per-series kernels; n >= 2, 0 <= M < n, DFT size N <= 2048, i.e. M <= 1024 with
  * the Parzen window; M <= 320 with HOS_PLAN_ADJOINT).
  * window: HOS_WIN_PARZEN (batches compute the hexagon only, so the windows
  * that are nonzero at its corners return HOS_EUNSUPPORTED).

@@ -56,7 +56,7 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
                uint32_t flags, const int32_t *tile_nb, void *blob, size_t blob_bytes,
                BatchHeader *hdr_out)
 {
-    if (batch < 1 || batch > (1 << 20) || !n || !M)
+    if (batch < 1 || batch > BATCH_MAX_SERIES || !n || !M)
         return HOS_EINVAL;
     if (path != HOS_PATH_FP32 && path != HOS_PATH_SPLIT_FP16 && path != HOS_PATH_SPLIT_BF16)
         return HOS_EINVAL;

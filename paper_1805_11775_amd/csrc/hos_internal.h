@@ -256,6 +256,7 @@ struct FftGroup {         // series sharing one DFT size, grids contiguous
 
 constexpr int64_t BATCH_MAGIC = 0x484f53424154434bLL;   // "HOSBATCK"
 constexpr int BATCH_CLASSES = 2;                         // tiles of 2 x 2 / 4 x 4 blocks
+constexpr int BATCH_MAX_SERIES = 65535;   // series index = grid y of the per-series kernels
 constexpr int BATCH_MAX_WG = 256;                        // persistent workgroups, one per CU
 
 struct BatchHeader {

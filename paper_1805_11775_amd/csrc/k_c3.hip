@@ -1237,16 +1237,16 @@ k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict
         cfull[(int64_t)(r + 1) * (M + 1) + b] = sum;
 }
 
-// Leftover diagonal sums: one workgroup per (series, leftover a = 32
-// blockIdx.y <= M); strided FP64 partial sums from the input combined by a
+// Leftover diagonal sums: one workgroup per (leftover a = 32 blockIdx.x <=
+// M, series); strided FP64 partial sums from the input combined by a
 // fixed-order tree into C[a][a].
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_bdiag(const T *__restrict__ x, const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
 {
     __shared__ double red[256];
-    const SeriesDesc &d = sd[blockIdx.x];
-    const int left = blockIdx.y;
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int left = blockIdx.x;
     if (left >= d.nleft)
         return;
     char *r = ws + d.ws_off;
@@ -1420,7 +1420,9 @@ hipError_t launch_batch_reduce(const void *x, int dtype, const BatchHeader &h, c
         else
             k_c3_reduce_items<2><<<(unsigned)(h.n_tiles[cls] * 4 * 4), 256, 0, s>>>(sd, t, part, ws);
     }
-    const dim3 grid((unsigned)h.batch, (unsigned)h.max_nleft);
+    // a series' diagonals in consecutive workgroups, so that its samples are
+    // read from HBM once and from L2 for the other diagonals
+    const dim3 grid((unsigned)h.max_nleft, (unsigned)h.batch);
     if (dtype == HOS_F64)
         k_bdiag<double><<<grid, 256, 0, s>>>((const double *)x, sd, ws);
     else

@@ -279,3 +279,19 @@ def test_tuned_table_lookup():
         assert t is not None and sorted(t["choices"]) == [32, 64, 128, 256]
         assert all(v in ((4,) if path == "fp32" else (2, 4))
                    for row in t["choices"].values() for v in row)
+
+
+def test_batch_series_count_bound():
+    """The series index is a grid dimension of the per-series kernels, so a
+    plan takes at most 65535 series (refused on the host before any launch)."""
+    import ctypes
+    import numpy as np
+    for count, want in ((65535, hos.HOS_OK), (65536, hos.HOS_EINVAL)):
+        n = np.full(count, 64, dtype=np.int64)
+        M = np.zeros(count, dtype=np.int32)
+        pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        st = hos.lib().hos_batch_plan_size(
+            count, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            M.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), hos.HOS_WIN_PARZEN,
+            hos.HOS_PATH_SPLIT_FP16, 0, None, ctypes.byref(pb), ctypes.byref(wb))
+        assert st == want, (count, st)
