@@ -212,14 +212,13 @@ __device__ __attribute__((always_inline)) inline void split_rows(Yrow<PATH> &y, 
 // the LDS latency); only VALU ops may cross them, so the split interleaves
 // with the matrix-core ops.  The FP32 path has the same structure with one
 // multiply per product and 8 matrix-core steps per block per group.
-template <int PATH, int NB, int NCOL, int NA = NB>
+template <int PATH, int NB, int NCOL, int NA = NB, int NG = KC / GROUP>
 __device__ __attribute__((always_inline)) inline void chunk_compute(const float4 *__restrict__ sxi,
                                      const float4 *__restrict__ sxa,
                                      const uint4 *__restrict__ sxb, int wlen, int rw, int rl,
                                      int h, floatx16 (&acc)[NA], double (&acc64)[NA][16])
 {
     static_assert(NCOL <= NB && NB <= NA, "column blocks beyond the accumulator arrays");
-    constexpr int NG = KC / GROUP;
     constexpr int UMAX = NG - 1 + 2 * (NCOL - 1);   // last window used
     constexpr bool SPLIT = PATH != HOS_PATH_FP32;
     if constexpr (SPLIT) {
@@ -373,26 +372,27 @@ __device__ inline int wave_cols(int NB, bool diag, int rw, int tileR, int NBR)
     return diag ? rw + 1 : NB;
 }
 
-// NB: column blocks of the tile; the accumulator arrays hold NA >= NB blocks.
-template <int PATH, int NB, int NA = NB>
+// NB: column blocks of the tile; the accumulator arrays hold NA >= NB blocks;
+// NG: 16-sample groups (a KC-sample run by default).
+template <int PATH, int NB, int NA = NB, int NG = KC / GROUP>
 __device__ __attribute__((always_inline)) inline void dispatch_compute(int ncol, const float4 *sxi, const float4 *sxa,
                                         const uint4 *sxb, int wlen, int rw, int rl, int h,
                                         floatx16 (&acc)[NA], double (&acc64)[NA][16])
 {
     switch (ncol) {
     case 1:
-        chunk_compute<PATH, NB, 1, NA>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+        chunk_compute<PATH, NB, 1, NA, NG>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
         break;
     case 2:
-        chunk_compute<PATH, NB, 2, NA>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+        chunk_compute<PATH, NB, 2, NA, NG>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
         break;
     case 3:
         if constexpr (NB >= 3)
-            chunk_compute<PATH, NB, 3, NA>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+            chunk_compute<PATH, NB, 3, NA, NG>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
         break;
     case 4:
         if constexpr (NB >= 4)
-            chunk_compute<PATH, NB, 4, NA>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
+            chunk_compute<PATH, NB, 4, NA, NG>(sxi, sxa, sxb, wlen, rw, rl, h, acc, acc64);
         break;
     default:
         break;  // 0: this strip has no output in the tile
@@ -1057,7 +1057,10 @@ items_loop(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items, 
     typedef ChunkLds<PATH, NB, 2 * KC, 4> CL;
     constexpr int64_t TILE = (int64_t)CL::TS * CL::TS;
     const int rl = lane & 31, h = lane >> 5;
-    const int strip = CLS ? wave : (wave & 1);
+    // 2 x 2 items of a series with one 32-row block (M < 33) have no strip
+    // 1: the four waves then run strip 0 on the four quarters of the chunk
+    // (else the strip-1 waves would idle)
+    auto strip_of = [&](int nbr) { return CLS ? wave : (nbr == 1 ? 0 : (wave & 1)); };
     auto buf = [&](int b) -> CL & { return *reinterpret_cast<CL *>(lds + b * bufsz); };
 
     C3Item it = items[k];
@@ -1077,6 +1080,7 @@ items_loop(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items, 
             acc64[cb][v] = 0.0;
             pin_agpr(acc64[cb][v]);
         }
+    int strip = strip_of(sp.NBR);
     int ncol = __builtin_amdgcn_readfirstlane(wave_cols(NB, q.Cc == q.R, strip, q.R, sp.NBR));
 
     XiRegs<CL> xr;
@@ -1112,6 +1116,10 @@ items_loop(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items, 
             dispatch_compute<PATH, 4>(ncol, B.xi, B.xa, B.xb, CL::WLEN, strip, rl, h, acc, acc64);
             dispatch_compute<PATH, 4>(ncol, B.xi + KC / 4, B.xa + KC, B.xb + KC, CL::WLEN, strip,
                                       rl, h, acc, acc64);
+        } else if (sp.NBR == 1) {
+            const int o = wave * (KC / 2);   // this wave's quarter of the chunk
+            dispatch_compute<PATH, 2, 2, KC / GROUP / 2>(ncol, B.xi + o / 4, B.xa + o, B.xb + o,
+                                                         CL::WLEN, 0, rl, h, acc, acc64);
         } else {
             const int o = (wave >> 1) * KC;   // this wave's half of the chunk
             dispatch_compute<PATH, 2>(ncol, B.xi + o / 4, B.xa + o, B.xb + o, CL::WLEN, strip,
@@ -1129,6 +1137,21 @@ items_loop(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items, 
                         for (int v = 0; v < 16; ++v)
                             dst[((strip * 4 + cb) * 16 + v) * 64 + lane] = acc64[cb][v];
                     }
+            } else if (sp.NBR == 1) {
+                // waves 1-3's quarters to wave 0, in LDS, added in wave order
+                if (wave >= 1) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v)
+                        hand[((wave - 1) * 16 + v) * 64 + lane] = acc64[0][v];
+                }
+                __syncthreads();
+                if (wave == 0) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int e = v * 64 + lane;
+                        dst[e] = ((acc64[0][v] + hand[e]) + hand[1024 + e]) + hand[2048 + e];
+                    }
+                }
             } else {
                 // the second half's sums to the first half's waves, in LDS
                 if (wave >= 2) {
@@ -1168,6 +1191,7 @@ items_loop(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items, 
             ++k;
             it = nit;
             sp = nsp;
+            strip = strip_of(sp.NBR);
             ncol = __builtin_amdgcn_readfirstlane(
                 wave_cols(NB, nq.Cc == nq.R, strip, nq.R, sp.NBR));
         }
