@@ -354,17 +354,19 @@ k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
     }
     __syncthreads();
     fft_lds<FFT_THREADS, PD_LDS_ELEMS, PD_PAD>(sm, tw, fr, CBP);
+    // T1 is column-major, [k2][m1], so that the column pass reads whole
+    // columns; a thread writes rows m1, m1 + 1 of one column and the CBP
+    // threads of a column write its 2 CBP consecutive rows
     double2 *T1 = (double2 *)(ws + d.grid_off);
     for (int e = threadIdx.x; e < CBP * K2; e += FFT_THREADS) {
-        const int p = e / K2, k2 = e - p * K2, m1 = m1_0 + 2 * p;
+        const int k2 = e / CBP, p = e - k2 * CBP, m1 = m1_0 + 2 * p;
         const double2 z = sm[lds_at<PD_PAD>(p * N + k2)],
                       zc = sm[lds_at<PD_PAD>(p * N + (k2 == 0 ? 0 : N - k2))];
         // conj(Z(N-k)) = (zc.x, -zc.y)
         if (m1 < N)
-            T1[(int64_t)m1 * K2 + k2] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+            T1[(int64_t)k2 * N + m1] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
         if (m1 + 1 < N)
-            T1[(int64_t)(m1 + 1) * K2 + k2] =
-                make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+            T1[(int64_t)k2 * N + m1 + 1] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
     }
 }
 
@@ -383,19 +385,21 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
     const SeriesDesc &d = sd[gser[first + si]];
     const int N = fr.n, K2 = N / 4 + 1, H = (N - 1) / 2;
     const int k2_0 = blk * CB;
-    const double2 *T1 = (const double2 *)(ws + d.grid_off);
+    const double2 *T1 = (const double2 *)(ws + d.grid_off);   // [k2][m1]
     for (int e = threadIdx.x; e < CB * N; e += FFT_THREADS) {
-        const int m1 = e / CB, cb = e - m1 * CB, k2 = k2_0 + cb;
+        const int cb = e / N, m1 = e - cb * N, k2 = k2_0 + cb;
         sm[lds_at<PD_PAD>(cb * N + m1)] =
-            k2 < K2 ? T1[(int64_t)m1 * K2 + k2] : make_double2(0.0, 0.0);
+            k2 < K2 ? T1[(int64_t)k2 * N + m1] : make_double2(0.0, 0.0);
     }
     for (int a = threadIdx.x; a <= H && a < N / 2 + 1; a += FFT_THREADS)
         rowstart[a] = pd_row_start(a, H);
     __syncthreads();
     fft_lds<FFT_THREADS, PD_LDS_ELEMS, PD_PAD>(sm, tw, fr, CB);
+    // consecutive threads take consecutive k2 of one row k1: the CB points a
+    // row holds in this block are contiguous in the packed output
     const int half = H + 1;   // k1 <= H
     for (int e = threadIdx.x; e < CB * half; e += FFT_THREADS) {
-        const int cb = e / half, k1 = e - cb * half, k2 = k2_0 + cb;
+        const int k1 = e / CB, cb = e - k1 * CB, k2 = k2_0 + cb;
         if (k2 < K2 && k2 <= k1 && k1 + k2 <= H)
             B_pd[d.pd_off + rowstart[k1] + k2] = sm[lds_at<PD_PAD>(cb * N + k1)];
     }
