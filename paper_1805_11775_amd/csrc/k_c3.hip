@@ -47,10 +47,14 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // promotable 1
 template <int PATH>
 struct SplitOps;
 
-// FP16 halves of the product y = xi * xa: hi = RNE16(y) and lo =
-// RNE16(y - hi), both taken by one fused multiply-add each straight from
-// the exact product (v_fma_mix{lo,hi}_f16 round a full-precision fma to
-// FP16 and write one half of a packed register), two VALU ops per element.
+// FP16 halves of the product y = xi * xa: hi = RNE16(fl32(y)) by one
+// packed conversion per two elements, and lo = RNE16(y - hi) by one fused
+// multiply-add per element straight from the exact product
+// (v_fma_mix{lo,hi}_f16 round a full-precision fma to FP16 and write one
+// half of a packed register); |y - hi - lo| <= 2^-22 |y|.  The mixed FMA
+// issues at about a third of the FP32 FMA rate on this chip, so hi comes
+// from the FP32 product and the conversion instead (2 multiplies + 1
+// conversion in place of 2 mixed FMAs per two elements).
 template <>
 struct SplitOps<HOS_PATH_SPLIT_FP16> {
     typedef halfx8 vec;
@@ -60,9 +64,8 @@ struct SplitOps<HOS_PATH_SPLIT_FP16> {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             uint32_t hv, lv;
-            asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(hv) : "v"(xi[2 * p]), "v"(xa[2 * p]));
-            asm("v_fma_mixhi_f16 %0, %1, %2, 0"
-                : "+v"(hv) : "v"(xi[2 * p + 1]), "v"(xa[2 * p + 1]));
+            const float y0 = xi[2 * p] * xa[2 * p], y1 = xi[2 * p + 1] * xa[2 * p + 1];
+            asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(hv) : "v"(y0), "v"(y1));
             asm("v_fma_mixlo_f16 %0, %1, %2, -%3 op_sel_hi:[0,0,1]"
                 : "=v"(lv) : "v"(xi[2 * p]), "v"(xa[2 * p]), "v"(hv));
             asm("v_fma_mixhi_f16 %0, %1, %2, -%3 op_sel:[0,0,1] op_sel_hi:[0,0,1]"

@@ -90,16 +90,16 @@ struct C4Ops;
 template <>
 struct C4Ops<HOS_PATH_SPLIT_FP16> {
     typedef halfx8 vec;
-    // hi/lo of p * q rounded from the exact product (see the c3 split)
+    // hi = RNE16(fl32(p q)), lo = RNE16(p q - hi) from the exact product
+    // (see the c3 split)
     __device__ static inline void split(const float *p, const float *q, vec &h, vec &l)
     {
         uint32_t hw[4], lw[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             uint32_t hv, lv;
-            asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(hv) : "v"(p[2 * k]), "v"(q[2 * k]));
-            asm("v_fma_mixhi_f16 %0, %1, %2, 0"
-                : "+v"(hv) : "v"(p[2 * k + 1]), "v"(q[2 * k + 1]));
+            const float y0 = p[2 * k] * q[2 * k], y1 = p[2 * k + 1] * q[2 * k + 1];
+            asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(hv) : "v"(y0), "v"(y1));
             asm("v_fma_mixlo_f16 %0, %1, %2, -%3 op_sel_hi:[0,0,1]"
                 : "=v"(lv) : "v"(p[2 * k]), "v"(q[2 * k]), "v"(hv));
             asm("v_fma_mixhi_f16 %0, %1, %2, -%3 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
