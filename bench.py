@@ -67,6 +67,34 @@ def sample_lags(M, k, seed=11):
     return np.concatenate([orbit[:, 0], w1]), np.concatenate([orbit[:, 1], w2])
 
 
+def graph_replay_ms(torch, call, steps, warmup):
+    """ms per replay of one call captured in a HIP graph: the same kernels on
+    the same (resident) input, without the host's per-launch overhead.  The
+    warm-up runs on a side stream of default priority, as capture wants; the
+    call must enqueue on the current stream."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            call()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def run_path(hos, torch, xt, M, N, path, steps, warmup):
     n = xt.numel()
     pth = hos.PATHS[path]
@@ -80,6 +108,11 @@ def run_path(hos, torch, xt, M, N, path, steps, warmup):
 
     def call():
         st = hos.hos_bispectrum(*args)
+        if st != hos.HOS_OK:
+            raise hos.HosError(st, "hos_bispectrum")
+
+    def call_current():
+        st = hos.hos_bispectrum(*args[:-1], hos._stream_handle(xt.device))
         if st != hos.HOS_OK:
             raise hos.HosError(st, "hos_bispectrum")
 
@@ -102,7 +135,9 @@ def run_path(hos, torch, xt, M, N, path, steps, warmup):
             raise hos.HosError(st, "hos_bispectrum_timed")
         stages.append(d)
     stage_ms = {k: float(np.mean([d[k] for d in stages])) for k in stages[0]}
-    return ms, stage_ms, c3.cpu().numpy()
+    # the returned c3 is the last graph replay's: the error check covers it
+    gms = graph_replay_ms(torch, call_current, steps, warmup)
+    return ms, stage_ms, c3.cpu().numpy(), gms
 
 
 def run_tri_path(hos, torch, xt, M, N, path, steps, warmup):
@@ -118,6 +153,11 @@ def run_tri_path(hos, torch, xt, M, N, path, steps, warmup):
 
     def call():
         st = hos.hos_trispectrum(*args)
+        if st != hos.HOS_OK:
+            raise hos.HosError(st, "hos_trispectrum")
+
+    def call_current():
+        st = hos.hos_trispectrum(*args[:-1], hos._stream_handle(xt.device))
         if st != hos.HOS_OK:
             raise hos.HosError(st, "hos_trispectrum")
 
@@ -139,7 +179,8 @@ def run_tri_path(hos, torch, xt, M, N, path, steps, warmup):
             raise hos.HosError(st, "hos_trispectrum_timed")
         stages.append(d)
     stage_ms = {k: float(np.mean([d[k] for d in stages])) for k in stages[0]}
-    return ms, stage_ms, c4.cpu().numpy()
+    gms = graph_replay_ms(torch, call_current, steps, warmup)
+    return ms, stage_ms, c4.cpu().numpy(), gms
 
 
 def bench_trispectrum(hos, torch, oracle, synth, paths, steps, warmup, cpu_seconds):
@@ -158,11 +199,12 @@ def bench_trispectrum(hos, torch, oracle, synth, paths, steps, warmup, cpu_secon
     out = {}
     for path in paths:
         print("bench: trispectrum path %s" % path, file=sys.stderr, flush=True)
-        ms, stage_ms, c4 = run_tri_path(hos, torch, xt, M, N, path, steps, warmup)
+        ms, stage_ms, c4, gms = run_tri_path(hos, torch, xt, M, N, path, steps, warmup)
         got = c4[t[:, 0] + M, t[:, 1] + M, t[:, 2] + M]
         err = float(np.max(np.abs(got - ref)) / m4_0)
         t_k = stage_ms["contract"] * 1e-3
         out[path] = {"ms_per_step": ms, "value": lagsums / (ms * 1e-3), "rel_err_m4": err,
+                     "graph_ms_per_step": gms,
                      "within_tol": err <= TOL[path], "stage_ms": stage_ms,
                      "contract_tflops": flops / t_k / 1e12,
                      "contract_frac": flops / t_k / PEAK[path]}
@@ -809,11 +851,12 @@ def main():
     paths = {}
     for path in args.paths.split(","):
         print("bench: path %s" % path, file=sys.stderr, flush=True)
-        ms, stage_ms, c3 = run_path(hos, torch, xt, M, N, path, args.steps, args.warmup)
+        ms, stage_ms, c3, gms = run_path(hos, torch, xt, M, N, path, args.steps, args.warmup)
         err = float(np.max(np.abs(c3[w1 + M, w2 + M] - ref)) / np.max(np.abs(ref)))
         t_k = stage_ms["contract"] * 1e-3
         paths[path] = {
             "ms_per_step": ms, "value": lagsums / (ms * 1e-3), "rel_err": err,
+            "graph_ms_per_step": gms, "graph_value": lagsums / (gms * 1e-3),
             "within_tol": err <= TOL[path], "stage_ms": stage_ms,
             "contract_tflops": flops / t_k / 1e12,
             "contract_frac": flops / t_k / PEAK[path],

@@ -17,7 +17,11 @@
  *            after the call returns.
  * Streams.   All work is enqueued on `stream` (NULL = the default stream) and
  *            the call returns without waiting for it.  Results are ready
- *            when the stream is synchronised.
+ *            when the stream is synchronised.  hos_bispectrum and
+ *            hos_trispectrum enqueue kernels only (no allocation, copy,
+ *            memset or host wait), so a call can be captured into a HIP
+ *            graph and replayed; the *_timed variants, the streamed entry
+ *            point and hos_tune wait on the host and cannot be captured.
  * Errors.    Every function returns an hos_status code; no exception or
  *            abort crosses the ABI.  Arguments are validated on the host,
  *            before any HIP call, so a rejected call touches no device state.
