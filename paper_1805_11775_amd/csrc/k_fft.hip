@@ -75,6 +75,11 @@ __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
     __syncthreads();
 }
 
+// global loads in flight per thread while staging: the ping-pong variant
+// (short transforms, many sequences per workgroup) gains from 8; the
+// in-place one (long transforms, 4-element runs per row) measured slower
+constexpr int AXIS_BATCH_PP = 8;
+
 template <bool PP, int THREADS>
 __global__ void __launch_bounds__(THREADS)
 k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadices fr,
@@ -93,18 +98,42 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
         base[cb] = s < nseq ? (s / b_in) * s_out + (s % b_in) * s_in : -1;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < tot; e += THREADS) {
-        int cb, k;
-        if (es == 1) {
-            cb = e / N;
-            k = e - cb * N;
-        } else {
-            k = e / CB;
-            cb = e - k * CB;
+    // Thread t moves the elements e = t, t + THREADS, ... of the CB x N
+    // block; with es == 1 k runs fastest (a sequence is contiguous), else
+    // cb (the sequences are neighbours).  The pair (fast, slow) advances by
+    // (THREADS mod F, THREADS / F) without a division, and AXIS_BATCH loads
+    // go out before their LDS stores.
+    constexpr int AXIS_BATCH = PP ? AXIS_BATCH_PP : 1;
+    const int F = es == 1 ? N : CB;
+    const int df = THREADS % F, ds = THREADS / F;
+    {
+        int f = threadIdx.x % F, sl = threadIdx.x / F;
+        for (int e0 = threadIdx.x; e0 < tot; e0 += AXIS_BATCH * THREADS) {
+            double2 v[AXIS_BATCH];
+            int at[AXIS_BATCH];
+#pragma unroll
+            for (int u = 0; u < AXIS_BATCH; ++u) {
+                at[u] = -1;
+                if (e0 + u * THREADS < tot) {
+                    const int cb = es == 1 ? sl : f, k = es == 1 ? f : sl;
+                    const int64_t b = base[cb];
+                    if (b >= 0) {
+                        v[u] = k < live ? data[b + k * es] : make_double2(0.0, 0.0);
+                        at[u] = lds_at<PAD>(cb * N + k);
+                    }
+                }
+                f += df;
+                sl += ds;
+                if (f >= F) {
+                    f -= F;
+                    ++sl;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < AXIS_BATCH; ++u)
+                if (at[u] >= 0)
+                    sm[at[u]] = v[u];
         }
-        const int64_t b = base[cb];
-        if (b >= 0)
-            sm[lds_at<PAD>(cb * N + k)] = k < live ? data[b + k * es] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     double2 *cur = sm, *nxt = sm + tot;
@@ -141,18 +170,20 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
         Ns *= R;
         lgNs += R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0;
     }
-    for (int e = threadIdx.x; e < tot; e += THREADS) {
-        int cb, k;
-        if (es == 1) {
-            cb = e / N;
-            k = e - cb * N;
-        } else {
-            k = e / CB;
-            cb = e - k * CB;
+    {
+        int f = threadIdx.x % F, sl = threadIdx.x / F;
+        for (int e = threadIdx.x; e < tot; e += THREADS) {
+            const int cb = es == 1 ? sl : f, k = es == 1 ? f : sl;
+            const int64_t b = base[cb];
+            if (b >= 0)
+                data[b + k * es] = cur[lds_at<PAD>(cb * N + k)];
+            f += df;
+            sl += ds;
+            if (f >= F) {
+                f -= F;
+                ++sl;
+            }
         }
-        const int64_t b = base[cb];
-        if (b >= 0)
-            data[b + k * es] = cur[lds_at<PAD>(cb * N + k)];
     }
 }
 
