@@ -712,6 +712,11 @@ k_c5_lines(const double *__restrict__ m5tab, const double *__restrict__ c2,
     const int N = fr.n;
     const uint32_t lines = (uint32_t)N * N * N;
     const double norm5 = stats[4] * stats[1];
+    // the ten-difference Parzen product (the only window the spectra take)
+    // vanishes once the span of {0, w1, .., w4} reaches M (d(m) = 0 from
+    // |m| = M on; at M = 0 from |m| = 1): such lags are skipped before any
+    // factor is formed, whole lines (the span of {0, w1, w2, w3}) at once
+    const int zspan = M > 0 ? M : 1;
     auto fold = [&](uint32_t L, int m4) {
         double sum = 0.0;
         if (L >= lines)
@@ -726,8 +731,15 @@ k_c5_lines(const double *__restrict__ m5tab, const double *__restrict__ c2,
                 for (int w3 = m3 - N; w3 <= m3; w3 += N) {
                     if (w3 < -M || w3 > M)
                         continue;
+                    const int lo3 = min(min(0, w1), min(w2, w3)),
+                              hi3 = max(max(0, w1), max(w2, w3));
+                    if (window == HOS_WIN_PARZEN && hi3 - lo3 >= zspan)
+                        continue;
                     for (int w4 = m4 - N; w4 <= m4; w4 += N) {
                         if (w4 < -M || w4 > M)
+                            continue;
+                        if (window == HOS_WIN_PARZEN &&
+                            max(hi3, w4) - min(lo3, w4) >= zspan)
                             continue;
                         const double wv = window5_tab(tab.d, w1, w2, w3, w4, M, window);
                         if (wv != 0.0)
