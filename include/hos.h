@@ -337,7 +337,9 @@ int hos_bispectrum_streamed(const void *x_host, int32_t dtype, int64_t n, int32_
  * M <= 40, N <= 96 (2, 3, 5-smooth, >= 2M with a window, >= 2M+1 without).
  * The fifth moments come from the matrix cores (rows x_i x_{i+a} x_{i+b}
  * x_{i+c}, 0 <= c <= b <= a <= M, against the columns x_{i+d}, d <= c);
- * c2 and c3 are FP64 sums over the input.
+ * c2 and c3 are FP64 sums over the input.  Q folds the c5 cube: with c5 =
+ * NULL the workspace holds that cube ((2M+1)^4 float64; the workspace size
+ * for nfft > 0 includes it).
  * ------------------------------------------------------------------------
  */
 int hos_cumulant5_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path, uint32_t flags,

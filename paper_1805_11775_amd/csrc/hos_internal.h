@@ -184,6 +184,7 @@ struct C4Plan : SeriesPlan {
     int64_t C;         // chunks of KC samples
     size_t off_part, off_m4, off_c2part, off_c2, off_twid, total;
     size_t off_c3part, off_c3tab;   // order five: third-order corrections
+    size_t off_c5cube;              // order five with a spectrum: the (2M+1)^4 cumulant
 };
 
 constexpr int C4_MAX_M = 127;      // 4 column blocks per pair block

@@ -692,7 +692,9 @@ k_c5_out(const double *__restrict__ m5tab, const double *__restrict__ c2,
 }
 
 // The windowed c5 folded onto the N^4 DFT grid (index w mod N, aliases
-// summed) and transformed along the last axis in LDS: a workgroup takes
+// summed; c5 read from the (2M+1)^4 cube k_c5_out wrote, whose zeros
+// beyond span M lie where the window vanishes anyway) and transformed
+// along the last axis in LDS: a workgroup takes
 // CBP pairs of lines L = (m1 N + m2) N + m3, the two real lines of a pair
 // travel as one complex sequence Z (lines L and L + 1 as its real and
 // imaginary parts), and after the DFT
@@ -701,17 +703,17 @@ k_c5_out(const double *__restrict__ m5tab, const double *__restrict__ c2,
 constexpr int C5L_LDS = 2048;   // complex values of the line buffer
 
 __global__ void __launch_bounds__(256)
-k_c5_lines(const double *__restrict__ m5tab, const double *__restrict__ c2,
-           const double *__restrict__ c3tab, const double *__restrict__ stats, int M,
-           const double2 *__restrict__ tw, FftRadices fr, int CBP, int window,
-           double2 *__restrict__ Q)
+k_c5_lines(const double *__restrict__ c5, int M, const double2 *__restrict__ tw, FftRadices fr,
+           int CBP, int window, double2 *__restrict__ Q)
 {
     __shared__ double2 sm[C5L_LDS];
-    __shared__ C5Tables tab;
-    load_c5_tables(tab, c2, c3tab, M);
+    __shared__ double dwin[2 * C5_MAX_M + 1];
+    for (int i = threadIdx.x; i <= 2 * M; i += blockDim.x)
+        dwin[i] = parzen_d(i - M, M);
+    __syncthreads();
     const int N = fr.n;
     const uint32_t lines = (uint32_t)N * N * N;
-    const double norm5 = stats[4] * stats[1];
+    const uint32_t side = 2 * M + 1;
     // the ten-difference Parzen product (the only window the spectra take)
     // vanishes once the span of {0, w1, .., w4} reaches M (d(m) = 0 from
     // |m| = M on; at M = 0 from |m| = 1): such lags are skipped before any
@@ -735,15 +737,18 @@ k_c5_lines(const double *__restrict__ m5tab, const double *__restrict__ c2,
                               hi3 = max(max(0, w1), max(w2, w3));
                     if (window == HOS_WIN_PARZEN && hi3 - lo3 >= zspan)
                         continue;
+                    const uint32_t row =
+                        (((uint32_t)(w1 + M) * side + (uint32_t)(w2 + M)) * side +
+                         (uint32_t)(w3 + M)) * side;
                     for (int w4 = m4 - N; w4 <= m4; w4 += N) {
                         if (w4 < -M || w4 > M)
                             continue;
                         if (window == HOS_WIN_PARZEN &&
                             max(hi3, w4) - min(lo3, w4) >= zspan)
                             continue;
-                        const double wv = window5_tab(tab.d, w1, w2, w3, w4, M, window);
+                        const double wv = window5_tab(dwin, w1, w2, w3, w4, M, window);
                         if (wv != 0.0)
-                            sum += wv * c5_at(m5tab, tab.c2, tab.c3, M, norm5, w1, w2, w3, w4);
+                            sum += wv * c5[row + (uint32_t)(w4 + M)];
                     }
                 }
             }
@@ -879,19 +884,21 @@ hipError_t launch_c5_finish(const C4Plan &p, int window, int nfft, double *c5, d
     const double *stats = (const double *)(ws + p.off_stats);
     // bounded grids: 8 workgroups per CU, each striding over its outputs
     const int64_t gmax = 8 * 256;
-    if (c5) {
+    // the spectrum folds the cumulant cube: the caller's c5, or a workspace
+    // copy when only Q is asked for
+    double *cube = c5 ? c5 : (Q ? (double *)(ws + p.off_c5cube) : nullptr);
+    if (cube) {
         const int64_t side = 2 * p.M + 1, tot = side * side * side * side;
         const int64_t grid = std::min<int64_t>((tot + 255) / 256, gmax);
-        k_c5_out<<<(unsigned)grid, 256, 0, s>>>(m5, c2, c3, stats, p.M, c5);
+        k_c5_out<<<(unsigned)grid, 256, 0, s>>>(m5, c2, c3, stats, p.M, cube);
     }
     if (Q) {   // fold, window and the transforms along the last axis
         const FftRadices fr = factor(nfft);
         const int64_t lines = (int64_t)nfft * nfft * nfft;
         const int CBP = std::min(32, C5L_LDS / nfft);
         const int64_t grid = (lines + 2 * CBP - 1) / (2 * CBP);
-        k_c5_lines<<<(unsigned)grid, 256, 0, s>>>(
-            m5, c2, c3, stats, p.M, (const double2 *)(ws + p.off_twid), fr, CBP, window,
-            (double2 *)Q);
+        k_c5_lines<<<(unsigned)grid, 256, 0, s>>>(cube, p.M, (const double2 *)(ws + p.off_twid),
+                                                  fr, CBP, window, (double2 *)Q);
     }
     return hipGetLastError();
 }

@@ -157,3 +157,15 @@ def test_max_lag_and_dft(path):
     s2 = float((q - qc).abs().max()) / scale
     print("symmetry %.3e %.3e" % (s1, s2))
     assert s1 < 1e-12 and s2 < 1e-12
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_spectrum_alone_equals_spectrum_with_cumulant(path):
+    """Asking for Q alone folds the cumulant cube from the workspace instead
+    of the caller's c5 array: the same kernels on the same data, so Q must
+    equal the Q of the call that also returns c5, bit for bit."""
+    x = synth.quartic_process(2500, 71).astype(np.float32)
+    _, Q_both = _run(x, 12, 32, path=path)
+    c5_none, Q_only = _run(x, 12, 32, path=path, return_c5=False)
+    assert c5_none is None
+    assert np.array_equal(Q_only, Q_both)
