@@ -235,7 +235,9 @@ int hos_c3_schedule(int64_t n, int32_t M, int32_t path, int64_t *owner, int64_t 
 
 /*
  * Workspace size for hos_trispectrum; arguments as for
- * hos_bispectrum_workspace, with the limits of hos_trispectrum.
+ * hos_bispectrum_workspace, with the limits of hos_trispectrum.  T folds
+ * the c4 cube: with c4 = NULL the workspace holds that cube ((2M+1)^3
+ * float64; the size for nfft > 0 includes it).
  */
 int hos_trispectrum_workspace(int64_t n, int32_t M, int32_t nfft, int32_t path,
                               uint32_t flags, size_t *bytes);

@@ -142,11 +142,12 @@ int make_c4_plan(int64_t n, int32_t M, int32_t path, int32_t nfft, C4Plan &p, in
     if (nfft > 0) {
         p.off_twid = o;
         o = align256(o + (size_t)nfft * 2 * sizeof(double));
-        if (ord == 5) {
-            const size_t side = 2 * (size_t)M + 1;
-            p.off_c5cube = o;
-            o = align256(o + side * side * side * side * sizeof(double));
-        }
+        // the cumulant cube the spectrum folds (used when the caller asks
+        // for the spectrum alone)
+        const size_t side = 2 * (size_t)M + 1;
+        const size_t cube = ord == 5 ? side * side * side * side : side * side * side;
+        p.off_cube = o;
+        o = align256(o + cube * sizeof(double));
     }
     p.total = o;
     return HOS_OK;

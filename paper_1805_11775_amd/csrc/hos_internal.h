@@ -184,7 +184,7 @@ struct C4Plan : SeriesPlan {
     int64_t C;         // chunks of KC samples
     size_t off_part, off_m4, off_c2part, off_c2, off_twid, total;
     size_t off_c3part, off_c3tab;   // order five: third-order corrections
-    size_t off_c5cube;              // order five with a spectrum: the (2M+1)^4 cumulant
+    size_t off_cube;                // with a spectrum: the (2M+1)^3 c4 / (2M+1)^4 c5 cube
 };
 
 constexpr int C4_MAX_M = 127;      // 4 column blocks per pair block
@@ -375,8 +375,8 @@ hipError_t launch_twiddles(double2 *tw, int N, hipStream_t s);
 hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int amax, int N,
                             int window, const double2 *tw, double *B, hipStream_t s);
 hipError_t launch_fft_cols(double *B, int N, const double2 *tw, hipStream_t s);
-hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double *stats, int M,
-                            int N, int window, const double2 *tw, double *T, hipStream_t s);
+hipError_t launch_tri_lines(const double *c4, int M, int N, int window, const double2 *tw,
+                            double *T, hipStream_t s);
 hipError_t launch_fft3_tail(double *T, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s);
 hipError_t launch_fft2_batch(double *grids, int N, int count, int rows, int cols,

@@ -886,7 +886,7 @@ hipError_t launch_c5_finish(const C4Plan &p, int window, int nfft, double *c5, d
     const int64_t gmax = 8 * 256;
     // the spectrum folds the cumulant cube: the caller's c5, or a workspace
     // copy when only Q is asked for
-    double *cube = c5 ? c5 : (Q ? (double *)(ws + p.off_c5cube) : nullptr);
+    double *cube = c5 ? c5 : (Q ? (double *)(ws + p.off_cube) : nullptr);
     if (cube) {
         const int64_t side = 2 * p.M + 1, tot = side * side * side * side;
         const int64_t grid = std::min<int64_t>((tot + 255) / 256, gmax);
@@ -909,12 +909,15 @@ hipError_t launch_c4_finish(const C4Plan &p, int window, int nfft, double *c4, d
     const double *m4 = (const double *)(ws + p.off_m4);
     const double *c2 = (const double *)(ws + p.off_c2);
     const double *stats = (const double *)(ws + p.off_stats);
-    if (c4) {
+    // the spectrum folds the cumulant cube: the caller's c4, or a workspace
+    // copy when only T is asked for
+    double *cube = c4 ? c4 : (T ? (double *)(ws + p.off_cube) : nullptr);
+    if (cube) {
         const int64_t side = 2 * p.M + 1, tot = side * side * side;
-        k_c4_out<<<(tot + 255) / 256, 256, 0, s>>>(m4, c2, stats, p.M, c4);
+        k_c4_out<<<(tot + 255) / 256, 256, 0, s>>>(m4, c2, stats, p.M, cube);
     }
     if (T) {   // fold + window + the m3 transforms (k_fft.hip); k2 and k1 follow
-        hipError_t e = launch_tri_lines(m4, c2, stats, p.M, nfft, window,
+        hipError_t e = launch_tri_lines(cube, p.M, nfft, window,
                                         (const double2 *)(ws + p.off_twid), T, s);
         if (e != hipSuccess)
             return e;

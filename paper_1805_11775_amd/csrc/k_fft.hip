@@ -477,15 +477,14 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
 // real lines per complex sequence, every k3 written to T; the k2 and k1
 // passes follow (launch_fft3_tail).
 __global__ void __launch_bounds__(FFT_THREADS)
-k_tri_lines(const double *__restrict__ m4tab, const double *__restrict__ c2,
-            const double *__restrict__ stats, int M, const double2 *__restrict__ tw,
-            FftRadices fr, int CBP, int window, double2 *__restrict__ T)
+k_tri_lines(const double *__restrict__ c4, int M, const double2 *__restrict__ tw, FftRadices fr,
+            int CBP, int window, double2 *__restrict__ T)
 {
     __shared__ double2 sm[PD_LDS_ELEMS];
     __shared__ double dwin[PD_LDS_ELEMS / 2 + 1];
     const int N = fr.n;
     const int64_t lines = (int64_t)N * N;
-    const double norm4 = stats[4];
+    const int side = 2 * M + 1;
     const bool pz = window != HOS_WIN_NONE;            // d on the lags
     const bool pdiff = window == HOS_WIN_PARZEN;        // and on their differences
     for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
@@ -509,7 +508,7 @@ k_tri_lines(const double *__restrict__ m4tab, const double *__restrict__ c2,
                     const double w = pdiff ? wl * dwin[abs(t2 - t1)] * dwin[abs(t3 - t1)] *
                                                  dwin[abs(t3 - t2)]
                                            : wl;
-                    sum += w * c4_at(m4tab, c2, M, norm4, t1, t2, t3);
+                    sum += w * c4[((int64_t)(t1 + M) * side + (t2 + M)) * side + (t3 + M)];
                 }
             }
         }
@@ -609,8 +608,8 @@ hipError_t launch_fft_cols(double *B, int N, const double2 *tw, hipStream_t s)
 }
 
 // Fold, window and m3 transforms of the trispectrum grid into T.
-hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double *stats, int M,
-                            int N, int window, const double2 *tw, double *T, hipStream_t s)
+hipError_t launch_tri_lines(const double *c4, int M, int N, int window, const double2 *tw,
+                            double *T, hipStream_t s)
 {
     const FftRadices fr = factor(N);
     // line pairs per workgroup: what the LDS area holds, at most 32, and few
@@ -621,7 +620,7 @@ hipError_t launch_tri_lines(const double *m4tab, const double *c2, const double 
     if (fill < CBP)
         CBP = fill < 1 ? 1 : (int)fill;
     k_tri_lines<<<(unsigned)((lines + 2 * CBP - 1) / (2 * CBP)), FFT_THREADS, 0, s>>>(
-        m4tab, c2, stats, M, tw, fr, CBP, window, (double2 *)T);
+        c4, M, tw, fr, CBP, window, (double2 *)T);
     return hipGetLastError();
 }
 

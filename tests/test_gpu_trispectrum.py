@@ -242,3 +242,19 @@ def test_max_dft(path):
     s2 = float((q - qc).abs().max()) / scale
     print("symmetry %.3e %.3e" % (s1, s2))
     assert s1 < 1e-12 and s2 < 1e-12
+
+
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_spectrum_alone_equals_spectrum_with_cumulant(path):
+    """Asking for T alone folds the c4 cube from the workspace instead of the
+    caller's c4 array: the same kernels on the same data, so T must equal
+    the T of the call that also returns c4, bit for bit."""
+    hos = _hos()
+    x = synth.cubic_process(3000, 83).astype(np.float32)
+    t = torch.from_numpy(x).cuda()
+    print("case: T alone n=3000 M=20 N=48 path=%s" % path, flush=True)
+    _, T_both = hos.trispectrum(t, 20, nfft=48, path=path)
+    c4_none, T_only = hos.trispectrum(t, 20, nfft=48, path=path, return_c4=False)
+    torch.cuda.synchronize()
+    assert c4_none is None
+    assert torch.equal(T_only, T_both)
