@@ -110,39 +110,110 @@ k_adj_gtab(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int window)
 // K2 in FP64 over the 32-blocks on and above the block diagonal of
 // [0, KP)^2 (u' = u + M, v' = v + M; padding is 0; the blocks below are
 // never read, so they are not written), and the running max |K2| (a
-// workgroup's maximum, then one atomic maximum).
+// workgroup's maximum, then one atomic maximum).  One workgroup per block
+// (bu, bv), bv >= bu; thread t holds row u' = 32 bu + t / 8 and the four
+// columns v' = 32 bv + 4 (t mod 8) + j.  Of the six terms of
+// K(u,v) + K(v,u) = G(u,v) + G(-u,v-u) + G(v-u,-u) + G(v,u) + G(-v,u-v) + G(u-v,-v)
+// the first two run along rows of G as v runs and are read directly; the
+// other four would run down columns or diagonals, so each is first staged
+// in LDS as the rectangle of G rows it touches (at most 63 x 32), read
+// along rows.
+constexpr int KB_LD = 33;   // LDS row pitch (doubles) of a staged rectangle
+
 __global__ void __launch_bounds__(256)
 k_adj_kbuild(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
 {
+    __shared__ double buf[64 * KB_LD];
     __shared__ double red[4];
     const SeriesDesc &d = sd[blockIdx.y];
-    const int KP = d.KP, M = d.M, S = 2 * M + 1;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double val = 0.0;
-    const int up = (int)(idx / KP), vp = (int)(idx % KP);
-    const int bu = up >> 5, bv = vp >> 5;
-    if (idx < (int64_t)KP * KP && bv >= bu) {
+    const int KP = d.KP, M = d.M, S = 2 * M + 1, NB = KP >> 5;
+    // block number -> (bu, bv), bv >= bu, row-major over the upper triangle
+    int t = blockIdx.x, bu = 0;
+    while (bu < NB && t >= NB - bu) {
+        t -= NB - bu;
+        ++bu;
+    }
+    if (bu >= NB)
+        return;   // beyond this series' blocks (uniform over the workgroup)
+    const int bv = bu + t;
+    const double *Gt = (const double *)(ws + d.ws_off + d.o_gtab);
+    auto G = [&](int a, int b) {
+        return (a < -M || a > M || b < -M || b > M) ? 0.0 : Gt[(int64_t)(a + M) * S + (b + M)];
+    };
+    const int tid = threadIdx.x;
+    const int iu = tid >> 3, jv = 4 * (tid & 7);
+    const int u0 = 32 * bu - M, v0 = 32 * bv - M;
+    const int u = u0 + iu;
+    double acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = v0 + jv + j;
+        acc[j] = G(u, v) + G(-u, v - u);
+    }
+    // stage the rectangle rows [r0, r0 + nr) x columns [c0, c0 + 32) of G,
+    // then add buf[row(j) - r0][col(j) - c0] to acc[j]
+    auto stage = [&](int r0, int nr, int c0) {
+        __syncthreads();
+        for (int e = tid; e < nr * 32; e += 256) {
+            const int rr = e >> 5, cc = e & 31;
+            buf[rr * KB_LD + cc] = G(r0 + rr, c0 + cc);
+        }
+        __syncthreads();
+    };
+    // G(v - u, -u): rows v - u in [v0 - u0 - 31, v0 - u0 + 31], columns -u
+    stage(v0 - u0 - 31, 63, -u0 - 31);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = v0 + jv + j;
+        acc[j] += buf[(v - u - (v0 - u0 - 31)) * KB_LD + (-u - (-u0 - 31))];
+    }
+    // G(v, u): rows v in [v0, v0 + 32), columns u
+    stage(v0, 32, u0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        acc[j] += buf[(jv + j) * KB_LD + iu];
+    // G(u - v, -v): rows u - v in [u0 - v0 - 31, u0 - v0 + 31], columns -v
+    stage(u0 - v0 - 31, 63, -v0 - 31);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = v0 + jv + j;
+        acc[j] += buf[(u - v - (u0 - v0 - 31)) * KB_LD + (-v - (-v0 - 31))];
+    }
+    // G(-v, u - v): rows -v in [-v0 - 31, -v0], columns u - v in
+    // [u0 - v0 - 31, u0 - v0 + 31]: staged transposed (row = column offset)
+    __syncthreads();
+    for (int e = tid; e < 32 * 63; e += 256) {
+        // consecutive threads read consecutive columns of one row of G
+        const int rr = e / 63, cc = e - rr * 63;   // rr: -v offset, cc: u - v offset
+        buf[cc * KB_LD + rr] = G(-v0 - 31 + rr, u0 - v0 - 31 + cc);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int v = v0 + jv + j;
+        acc[j] += buf[(u - v - (u0 - v0 - 31)) * KB_LD + (-v - (-v0 - 31))];
+    }
+    const int up = 32 * bu + iu;
+    double m = 0.0;
+    double *K64 = (double *)(ws + d.ws_off + d.o_k64);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int vp = 32 * bv + jv + j;
+        double val = 0.0;
         if (up <= 2 * M && vp <= 2 * M) {
-            const double *Gt = (const double *)(ws + d.ws_off + d.o_gtab);
-            const int u = up - M, v = vp - M;
-            auto G = [&](int a, int b) {
-                return (a < -M || a > M || b < -M || b > M)
-                           ? 0.0 : Gt[(int64_t)(a + M) * S + (b + M)];
-            };
-            auto K = [&](int a, int b) { return G(a, b) + G(-a, b - a) + G(b - a, -a); };
-            const double ks = 0.5 * (K(u, v) + K(v, u)) / (double)d.n;
+            const double ks = 0.5 * acc[j] / (double)d.n;
             val = bv > bu ? 2.0 * ks : ks;
         }
-        ((double *)(ws + d.ws_off + d.o_k64))[idx] = val;
+        K64[(int64_t)up * KP + vp] = val;
+        m = fmax(m, fabs(val));
     }
-    double m = fabs(val);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         m = fmax(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = m;
+    if ((tid & 63) == 0)
+        red[tid >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
         atomicMax(kmax_bits(d, ws), (unsigned long long)__double_as_longlong(m));
     }
@@ -410,7 +481,8 @@ hipError_t launch_batch_adjoint(const void *x, int dtype, const BatchHeader &h, 
     }
     const int64_t k2 = h.max_KP * h.max_KP, sq = (2 * h.max_M + 1) * (2 * h.max_M + 1);
     k_adj_gtab<<<dim3((unsigned)((sq + 255) / 256), B), 256, 0, s>>>(sd, ws, window);
-    k_adj_kbuild<<<dim3((unsigned)((k2 + 255) / 256), B), 256, 0, s>>>(sd, ws);
+    const int64_t nbk = h.max_KP / 32;
+    k_adj_kbuild<<<dim3((unsigned)(nbk * (nbk + 1) / 2), B), 256, 0, s>>>(sd, ws);
     const dim3 gk((unsigned)((k2 + 255) / 256), B);
     if (h.path == HOS_PATH_FP32) {
         k_adj_ksplit<HOS_PATH_FP32><<<gk, 256, 0, s>>>(sd, ws);
