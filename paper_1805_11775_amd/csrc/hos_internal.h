@@ -379,8 +379,10 @@ hipError_t launch_tri_lines(const double *c4, int M, int N, int window, const do
                             double *T, hipStream_t s);
 hipError_t launch_fft3_tail(double *T, int N, const double2 *tw, hipStream_t s);
 hipError_t launch_c4_contract(const C4Plan &p, char *ws, hipStream_t s);
-hipError_t launch_fft2_batch(double *grids, int N, int count, int rows, int cols,
-                             const double2 *tw, hipStream_t s);
+// The adjoint's residual DFT of one size group and its lag weights G into
+// each series' lag table (k_fft.hip).
+hipError_t launch_adj_gweights(const FftGroup &gr, const SeriesDesc *sd, const int32_t *gser,
+                               int window, char *ws, hipStream_t s);
 hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window, char *ws,
                              double *B_pd, hipStream_t s);
 

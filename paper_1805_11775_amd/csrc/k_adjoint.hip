@@ -81,32 +81,6 @@ k_adj_resid(const SeriesDesc *__restrict__ sd, const double2 *__restrict__ B_pd,
     ((double2 *)(ws + d.grid_off))[(int64_t)k1 * N + k2] = v;
 }
 
-// G(w) from the transformed grid (0 outside the hexagon).
-__device__ inline double g_at(const double2 *__restrict__ F, int N, int M, int window, int w1,
-                              int w2)
-{
-    if (w1 < -M || w1 > M || w2 < -M || w2 > M || w1 - w2 < -M || w1 - w2 > M)
-        return 0.0;
-    const int m1 = w1 < 0 ? w1 + N : w1, m2 = w2 < 0 ? w2 + N : w2;
-    return window3(w1, w2, M, window) * F[(int64_t)m1 * N + m2].x;
-}
-
-// The windowed lag weights G(w) once per lag of the square (0 outside the
-// hexagon), so that the quadratic form's kernel below reads them back
-// instead of evaluating the window six times per entry.
-__global__ void __launch_bounds__(256)
-k_adj_gtab(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int window)
-{
-    const SeriesDesc &d = sd[blockIdx.y];
-    const int M = d.M, S = 2 * M + 1;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)S * S)
-        return;
-    const double2 *F = (const double2 *)(ws + d.grid_off);
-    const int w1 = (int)(idx / S) - M, w2 = (int)(idx % S) - M;
-    ((double *)(ws + d.ws_off + d.o_gtab))[idx] = g_at(F, d.N, M, window, w1, w2);
-}
-
 // K2 in FP64 over the 32-blocks on and above the block diagonal of
 // [0, KP)^2 (u' = u + M, v' = v + M; padding is 0; the blocks below are
 // never read, so they are not written), and the running max |K2| (a
@@ -466,21 +440,17 @@ hipError_t launch_batch_adjoint(const void *x, int dtype, const BatchHeader &h, 
     k_adj_resid<<<dim3((unsigned)((corner + 255) / 256), B), 256, 0, s>>>(
         sd, (const double2 *)B_pd, (const double2 *)target, dL, ws);
     const FftGroup *groups = (const FftGroup *)((const char *)&h + h.groups_off);
+    const int32_t *gser = (const int32_t *)(dplan + h.gseries_off);
     for (int g = 0; g < (int)h.n_groups; ++g) {
         const FftGroup &gr = groups[g];
-        double2 *tw = (double2 *)(ws + gr.twid_off);
-        hipError_t e = launch_twiddles(tw, gr.N, s);
-        // the residual sits on the principal domain: rows k1 <= H = (N - 1) / 2,
-        // columns k2 <= H / 2
-        const int H = (gr.N - 1) / 2;
+        hipError_t e = launch_twiddles((double2 *)(ws + gr.twid_off), gr.N, s);
+        // the residual's 2-D DFT, whose second pass writes the lag weights
         if (e == hipSuccess)
-            e = launch_fft2_batch((double *)(ws + gr.grid_off), gr.N, gr.count, H + 1, H / 2 + 1,
-                                  tw, s);
+            e = launch_adj_gweights(gr, sd, gser, window, ws, s);
         if (e != hipSuccess)
             return e;
     }
-    const int64_t k2 = h.max_KP * h.max_KP, sq = (2 * h.max_M + 1) * (2 * h.max_M + 1);
-    k_adj_gtab<<<dim3((unsigned)((sq + 255) / 256), B), 256, 0, s>>>(sd, ws, window);
+    const int64_t k2 = h.max_KP * h.max_KP;
     const int64_t nbk = h.max_KP / 32;
     k_adj_kbuild<<<dim3((unsigned)(nbk * (nbk + 1) / 2), B), 256, 0, s>>>(sd, ws);
     const dim3 gk((unsigned)((k2 + 255) / 256), B);

@@ -251,14 +251,91 @@ namespace hos {
 // nothing outside that corner is read (it may hold anything).  The columns
 // k2 < cols are transformed first (their elements k1 >= rows taken as 0),
 // then every row (its elements k2 >= cols taken as 0).
-hipError_t launch_fft2_batch(double *grids, int N, int count, int rows, int cols,
-                             const double2 *tw, hipStream_t s)
+namespace {
+
+// The adjoint's lag weights straight from the residual's DFT along k2: CB
+// rows m1 of one series' grid (its k1 pass done; columns k2 >= live are 0)
+// are transformed in LDS, and each row writes the lag table rows it holds,
+// G(w1, w2) = W3(w) Re(row[w2 mod N]) for w1 = m1 and m1 - N within [-M, M],
+// every w2 in [-M, M], 0 off the hexagon (N >= 2M: every lag has one grid
+// point).  The N x N grid is never written.  blockIdx = (row block, series
+// of the group).
+template <int THREADS>
+__global__ void __launch_bounds__(THREADS)
+k_adj_grows(const double2 *__restrict__ grids, const SeriesDesc *__restrict__ sd,
+            const int32_t *__restrict__ gser, int64_t first, const double2 *__restrict__ tw,
+            FftRadices fr, int CB, int live, int window, char *__restrict__ ws)
 {
-    double2 *d = (double2 *)grids;
+    extern __shared__ double2 sm[];
+    __shared__ double dwin[ADJ_MAX_M + 1];   // Parzen weights d(|m|) (1 without a window)
+    const int N = fr.n;
+    const SeriesDesc &d = sd[gser[first + blockIdx.y]];
+    const int M = d.M, S = 2 * M + 1;
+    const int m1_0 = blockIdx.x * CB;
+    const int nrow = N - m1_0 < CB ? N - m1_0 : CB;
+    const double2 *F = grids + (int64_t)blockIdx.y * N * N + (int64_t)m1_0 * N;
+    for (int m = threadIdx.x; m <= M; m += THREADS)
+        dwin[m] = window != HOS_WIN_NONE ? parzen_d(m, M) : 1.0;
+    for (int e = threadIdx.x; e < CB * N; e += THREADS) {
+        const int cb = e / N, k = e - cb * N;
+        sm[lds_at<AXIS_PAD>(e)] = cb < nrow && k < live ? F[e] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    fft_lds<THREADS, FFT_LDS_ELEMS, AXIS_PAD>(sm, tw, fr, CB);
+    double *G = (double *)(ws + d.ws_off + d.o_gtab);
+    // row cb holds w1 = m1 (when m1 <= M) and w1 = m1 - N (when m1 >= N - M);
+    // (cb, j) advance by (THREADS / S, THREADS mod S) without a division
+    for (int alias = 0; alias < 2; ++alias) {
+        int cb = threadIdx.x / S, j = threadIdx.x - cb * S;
+        const int dcb = THREADS / S, dj = THREADS - dcb * S;
+        for (; cb < nrow; ) {
+            const int m1 = m1_0 + cb, w1 = alias ? m1 - N : m1, w2 = j - M;
+            if (w1 >= -M && w1 <= M) {
+                const int m2 = w2 < 0 ? w2 + N : w2, dd = w1 - w2;
+                double g = 0.0;
+                if (dd >= -M && dd <= M) {
+                    double w = dwin[abs(w1)] * dwin[abs(w2)];
+                    if (window == HOS_WIN_PARZEN)
+                        w *= dwin[abs(dd)];
+                    g = w * sm[lds_at<AXIS_PAD>(cb * N + m2)].x;
+                }
+                G[(int64_t)(w1 + M) * S + j] = g;
+            }
+            cb += dcb;
+            j += dj;
+            if (j >= S) {
+                j -= S;
+                ++cb;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adj_gweights(const FftGroup &gr, const SeriesDesc *sd, const int32_t *gser,
+                               int window, char *ws, hipStream_t s)
+{
+    double2 *d = (double2 *)(ws + gr.grid_off);
+    const double2 *tw = (const double2 *)(ws + gr.twid_off);
+    const int N = gr.N;
     const FftRadices fr = factor(N);
     const int64_t N2 = (int64_t)N * N;
-    fft_axis(d, tw, fr, (int64_t)count * cols, N, cols, 1, N2, s, rows);   // along k1
-    fft_axis(d, tw, fr, (int64_t)count * N, 1, N, N, N2, s, cols);         // along k2
+    // the residual sits on the principal domain: rows k1 <= H = (N - 1) / 2,
+    // columns k2 <= H / 2
+    const int H = (N - 1) / 2, rows = H + 1, cols = H / 2 + 1;
+    fft_axis(d, tw, fr, (int64_t)gr.count * cols, N, cols, 1, N2, s, rows);   // along k1
+    int CB = FFT_LDS_ELEMS / N;
+    if (CB > 32)
+        CB = 32;
+    const dim3 grid((unsigned)((N + CB - 1) / CB), (unsigned)gr.count);
+    const size_t lds = (size_t)lds_slots<AXIS_PAD>(CB * N) * sizeof(double2);
+    if (N >= 512)
+        k_adj_grows<1024><<<grid, 1024, lds, s>>>(d, sd, gser, gr.first, tw, fr, CB, cols, window,
+                                                  ws);
+    else
+        k_adj_grows<FFT_THREADS><<<grid, FFT_THREADS, lds, s>>>(d, sd, gser, gr.first, tw, fr, CB,
+                                                                cols, window, ws);
     return hipGetLastError();
 }
 
