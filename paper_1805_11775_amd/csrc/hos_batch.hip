@@ -149,6 +149,8 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
             d.o_gtil = r;  r = a256(r + (size_t)d.n * sizeof(double));
             d.o_gtab = r;  r = a256(r + (size_t)(2 * d.M + 1) * (2 * d.M + 1) * sizeof(double));
             d.o_k64 = r;   r = a256(r + kp2 * sizeof(double));
+            d.o_msum = r;
+            r = a256(r + (size_t)((d.n + ADJ_MEAN_BLOCK - 1) / ADJ_MEAN_BLOCK) * sizeof(double));
             d.o_kh = r;    r = a256(r + kp2 * (split ? 2 : 4));
             if (split) {
                 d.o_kl = r;  r = a256(r + kp2 * 2);

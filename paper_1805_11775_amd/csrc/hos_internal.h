@@ -234,7 +234,10 @@ struct SeriesDesc {
     // byte offsets inside the series region; table offsets point at sample 0
     int64_t o_stats, o_mpart, o_xf, o_win4, o_win8h, o_win8l, o_cfull, o_dpart;
     int64_t o_gtil, o_gtab, o_k64, o_kh, o_kl;   // adjoint buffers (plans made for the adjoint)
+    int64_t o_msum;       // adjoint: block sums of the gradient for its mean
 };
+
+constexpr int ADJ_MEAN_BLOCK = 4096;   // samples per block sum of the gradient's mean
 
 struct C3Item {           // one (series, tile, chunk range) of the contraction
     int32_t series, R, Cc;

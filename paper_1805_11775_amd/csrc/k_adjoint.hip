@@ -393,29 +393,62 @@ k_adj_contract(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int WA)
 }
 
 // dx_j = (g_j - mean g) / (s^2 sk), mean in a fixed order.
-template <typename T>
-__global__ void __launch_bounds__(1024)
-k_adj_final(const SeriesDesc *__restrict__ sd, const char *__restrict__ ws, T *__restrict__ dx)
+// Block sums of g~ for the mean: workgroup (b, series) adds the samples
+// [b L, (b + 1) L) (L = ADJ_MEAN_BLOCK) by a fixed tree.
+
+__global__ void __launch_bounds__(256)
+k_adj_msum(const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
 {
-    __shared__ double red[1024];
-    const SeriesDesc &d = sd[blockIdx.x];
+    __shared__ double red[256];
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int64_t j0 = (int64_t)blockIdx.x * ADJ_MEAN_BLOCK;
+    if (j0 >= d.n)
+        return;
     const char *r = ws + d.ws_off;
     const double *gt = (const double *)(r + d.o_gtil);
-    const double *stats = (const double *)(r + d.o_stats);
     double s = 0.0;
-    for (int64_t j = threadIdx.x; j < d.n; j += 1024)
-        s += gt[j];
+#pragma unroll
+    for (int q = 0; q < ADJ_MEAN_BLOCK / 256; ++q) {
+        const int64_t j = j0 + threadIdx.x + 256 * q;
+        s += j < d.n ? gt[j] : 0.0;
+    }
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w)
             red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    const double mean = red[0] / (double)d.n;
+    if (threadIdx.x == 0)
+        ((double *)(ws + d.ws_off + d.o_msum))[blockIdx.x] = red[0];
+}
+
+// dx_j = (g_j - mean g) / (s^2 sk): the mean from the block sums added in
+// block order, then workgroup (b, series) writes block b.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_adj_final(const SeriesDesc *__restrict__ sd, const char *__restrict__ ws, T *__restrict__ dx)
+{
+    const SeriesDesc &d = sd[blockIdx.y];
+    const int64_t j0 = (int64_t)blockIdx.x * ADJ_MEAN_BLOCK;
+    if (j0 >= d.n)
+        return;
+    const char *r = ws + d.ws_off;
+    const double *gt = (const double *)(r + d.o_gtil);
+    const double *bs = (const double *)(r + d.o_msum);
+    const double *stats = (const double *)(r + d.o_stats);
+    const int nb = (int)((d.n + ADJ_MEAN_BLOCK - 1) / ADJ_MEAN_BLOCK);
+    double sum = 0.0;
+    for (int b = 0; b < nb; ++b)
+        sum += bs[b];
+    const double mean = sum / (double)d.n;
     const double inv = 1.0 / (stats[1] * stats[1] * stats[5]);
-    for (int64_t j = threadIdx.x; j < d.n; j += 1024)
-        dx[d.x_off + j] = (T)((gt[j] - mean) * inv);
+#pragma unroll
+    for (int q = 0; q < ADJ_MEAN_BLOCK / 256; ++q) {
+        const int64_t j = j0 + threadIdx.x + 256 * q;
+        if (j < d.n)
+            dx[d.x_off + j] = (T)((gt[j] - mean) * inv);
+    }
 }
 
 template <int PATH>
@@ -464,10 +497,12 @@ hipError_t launch_batch_adjoint(const void *x, int dtype, const BatchHeader &h, 
         k_adj_ksplit<HOS_PATH_SPLIT_BF16><<<gk, 256, 0, s>>>(sd, ws);
         launch_adj_contract<HOS_PATH_SPLIT_BF16>(h, sd, ws, s);
     }
+    const dim3 gm((unsigned)((h.max_n + ADJ_MEAN_BLOCK - 1) / ADJ_MEAN_BLOCK), (unsigned)B);
+    k_adj_msum<<<gm, 256, 0, s>>>(sd, ws);
     if (dtype == HOS_F64)
-        k_adj_final<double><<<B, 1024, 0, s>>>(sd, ws, (double *)dx);
+        k_adj_final<double><<<gm, 256, 0, s>>>(sd, ws, (double *)dx);
     else
-        k_adj_final<float><<<B, 1024, 0, s>>>(sd, ws, (float *)dx);
+        k_adj_final<float><<<gm, 256, 0, s>>>(sd, ws, (float *)dx);
     return hipGetLastError();
 }
 
