@@ -182,6 +182,35 @@ def test_loss_gradient_float64():
     assert _rel(dx.cpu().numpy(), ref) < 1e-6
 
 
+@pytest.mark.parametrize("M", [7, 11])
+def test_loss_gradient_dft_sizes_above_2M(M):
+    """DFT sizes other than 2M: M = 7 takes N = 15 (odd: one lag per grid
+    row), M = 11 takes N = 24 (row 12 holds no lag of [-M, M]); the lag
+    weights come straight from the residual's row transforms either way."""
+    hos = _hos()
+    n = 1800
+    N = hos.default_nfft(M)
+    assert N > 2 * M
+    X = np.stack([synth.iid_exp_centered(n, 60 + M + b) for b in range(2)]).astype(np.float32)
+    tgt = synth.quadratic_process(n, 61)
+    k1, k2 = oracle.pd_indices(N)
+    target = oracle.bispectrum(tgt, M, N)[1][k1, k2]
+    plan = hos.BatchPlan([n, n], [M, M], path="split_fp16", adjoint=True)
+    assert (plan.series()[:, 2] == N).all()
+    print("case: loss gradient M=%d N=%d" % (M, N), flush=True)
+    x = torch.from_numpy(X).cuda()
+    loss, B = hos.bispectrum_loss_fwd(x, torch.from_numpy(target), plan)
+    dx = hos.bispectrum_loss_bwd(x, torch.from_numpy(target), B,
+                                 torch.ones((), dtype=torch.float64), plan)
+    torch.cuda.synchronize()
+    ref = oracle.bispectrum_loss_grad(X, M, N, target)
+    dx = dx.cpu().numpy()
+    for b in range(2):
+        e = _rel(dx[b], ref[b])
+        print("series %d grad rel err %.3e" % (b, e))
+        assert e < TOL["split_fp16"]
+
+
 @pytest.mark.parametrize("path", ["split_fp16", "fp32"])
 def test_loss_gradient_largest_lag(path):
     """The adjoint at the largest lag it takes (M = 320, N = 640: the
