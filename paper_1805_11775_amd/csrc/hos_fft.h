@@ -25,6 +25,15 @@ __device__ inline double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Root i of the table (i < N <= 2^20): the byte offset is formed in 32 bits
+// and added to the table's uniform base, one VALU op instead of a 64-bit
+// address per load.
+__device__ __attribute__((always_inline)) inline double2 tw_at(const double2 *__restrict__ tw,
+                                                               int i)
+{
+    return *(const double2 *)((const char *)tw + (unsigned)i * 16u);
+}
+
 // Forward DFT of size R in registers.
 template <int R>
 __device__ inline void dft_small(double2 *v, const double2 *__restrict__ tw, int N)
@@ -69,7 +78,7 @@ __device__ inline void dft_small(double2 *v, const double2 *__restrict__ tw, int
             double2 acc = in[0];
 #pragma unroll
             for (int q = 1; q < R; ++q) {
-                double2 t = cmul(in[q], tw[((p * q) % R) * step]);
+                double2 t = cmul(in[q], tw_at(tw, ((p * q) % R) * step));
                 acc.x += t.x;
                 acc.y += t.y;
             }
@@ -131,7 +140,7 @@ __device__ inline void stockham_stage(double2 *sm, const double2 *__restrict__ t
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 double2 x = sm[lds_at<PADSH>(src + q * nbf)];
-                v[it][q] = q == 0 ? x : cmul(x, tw[q * k * stride]);
+                v[it][q] = q == 0 ? x : cmul(x, tw_at(tw, q * k * stride));
             }
             dft_small<R>(v[it], tw, N);
         }
@@ -147,6 +156,68 @@ __device__ inline void stockham_stage(double2 *sm, const double2 *__restrict__ t
         }
     }
     __syncthreads();
+}
+
+// One Stockham stage with every size known at compile time (N a power of
+// two, CB sequences of it in LDS): the butterfly indices are shifts and
+// masks of constants, and where NBF (resp. NS) is a multiple of the
+// padding period the R padded LDS slots of a butterfly are one base plus
+// constant offsets.  Same arithmetic as stockham_stage.
+template <int R, int N, int NS, int CB, int THREADS, int PADSH>
+__device__ inline void stockham_stage_c(double2 *sm, const double2 *__restrict__ tw)
+{
+    constexpr int NBF = N / R, TOTAL = CB * NBF, STRIDE = N / (NS * R);
+    constexpr int MAXIT = (TOTAL + THREADS - 1) / THREADS;
+    constexpr int P = 1 << PADSH;
+    double2 v[MAXIT][R];
+    int dst[MAXIT];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int u = threadIdx.x + THREADS * it;
+        if (TOTAL % THREADS == 0 || u < TOTAL) {
+            const int cb = u / NBF, j = u % NBF, jq = j / NS, k = j % NS;
+            dst[it] = cb * N + jq * NS * R + k;
+            const int src = cb * N + j;
+            const int base = lds_at<PADSH>(src);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int at = (PADSH && NBF % P == 0) ? base + q * NBF + ((q * NBF) >> PADSH)
+                                                       : lds_at<PADSH>(src + q * NBF);
+                const double2 x = sm[at];
+                v[it][q] = q == 0 ? x : cmul(x, tw_at(tw, q * k * STRIDE));
+            }
+            dft_small<R>(v[it], tw, N);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int u = threadIdx.x + THREADS * it;
+        if (TOTAL % THREADS == 0 || u < TOTAL) {
+            const int base = lds_at<PADSH>(dst[it]);
+#pragma unroll
+            for (int p = 0; p < R; ++p) {
+                const int at = (PADSH && NS % P == 0) ? base + p * NS + ((p * NS) >> PADSH)
+                                                      : lds_at<PADSH>(dst[it] + p * NS);
+                sm[at] = v[it][p];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// The stages of a compile-time power-of-two N from NS on, radix 8 first,
+// then one 4 or 2 -- the radix order of factor(), so the results equal
+// fft_lds's bit for bit.
+template <int N, int NS, int CB, int THREADS, int PADSH>
+__device__ inline void fft_lds_c(double2 *sm, const double2 *__restrict__ tw)
+{
+    if constexpr (NS < N) {
+        constexpr int REM = N / NS;
+        constexpr int R = REM % 8 == 0 ? 8 : REM % 4 == 0 ? 4 : 2;
+        stockham_stage_c<R, N, NS, CB, THREADS, PADSH>(sm, tw);
+        fft_lds_c<N, NS * R, CB, THREADS, PADSH>(sm, tw);
+    }
 }
 
 inline FftRadices factor(int N)
@@ -180,7 +251,10 @@ inline FftRadices factor(int N)
     return f;
 }
 
-template <int THREADS = FFT_THREADS, int ELEMS = FFT_LDS_ELEMS, int PADSH = 0>
+// POW2: N is a power of two (fr.lg >= 0), so only the radix 8/4/2 stages are
+// compiled in -- the radix-3/5 butterflies need the most registers, and a
+// kernel is allocated for its largest stage.
+template <int THREADS = FFT_THREADS, int ELEMS = FFT_LDS_ELEMS, int PADSH = 0, bool POW2 = false>
 __device__ inline void fft_lds(double2 *sm, const double2 *__restrict__ tw, const FftRadices &fr,
                                int CB)
 {
@@ -191,7 +265,7 @@ __device__ inline void fft_lds(double2 *sm, const double2 *__restrict__ tw, cons
             stockham_stage<8, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);
         else if (R == 4)
             stockham_stage<4, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);
-        else if (R == 2)
+        else if (R == 2 || POW2)
             stockham_stage<2, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);
         else if (R == 3)
             stockham_stage<3, THREADS, ELEMS, PADSH>(sm, tw, fr.n, Ns, CB, fr.lg, lgNs);

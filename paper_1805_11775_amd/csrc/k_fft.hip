@@ -64,7 +64,7 @@ __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const double2 x = src[cb * N + j + q * nbf];
-            v[q] = q == 0 ? x : cmul(x, tw[q * k * stride]);
+            v[q] = q == 0 ? x : cmul(x, tw_at(tw, q * k * stride));
         }
         dft_small<R>(v, tw, N);
         const int idxD = jq * Ns * R + k;
@@ -400,6 +400,13 @@ __device__ __attribute__((always_inline)) inline double fold_centred(const FoldA
 constexpr int PD_LDS_ELEMS = 2048;   // complex doubles per workgroup (32 KB): 4+ per CU
 constexpr int PD_PAD = 3;            // the batch spectra's LDS padding (lds_at)
 
+// Sequences per workgroup of the batch spectra: as many as PD_LDS_ELEMS
+// holds, at most 32.
+__host__ __device__ constexpr int pd_cb(int N)
+{
+    return N <= 0 ? 1 : PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
+}
+
 // Workgroups are dispatched to the 8 XCDs round robin by their linear index,
 // and each XCD has its own L2.  The spectra kernels read one series' table
 // (rows) or grid (columns) from every one of that series' workgroups, so
@@ -426,90 +433,189 @@ inline unsigned xcd_grid(int count, int nblk)
 // imaginary parts of one complex sequence; after its DFT Z,
 //   X_{m1}(k) = (Z(k) + conj Z(N-k)) / 2,  X_{m1+1}(k) = (Z(k) - conj Z(N-k)) / 2i.
 // T1[m1][k2] (k2 < K2) goes to the series' grid region.
-__global__ void __launch_bounds__(FFT_THREADS)
+// NC: N fixed at compile time (a power of two, >= 64; CBP is then pd_cb(NC)),
+// else 0.  POW2: N is a power of two.  At least 3 waves per SIMD: the LDS
+// area admits 3 workgroups per CU even at its largest.
+template <bool POW2, int NC>
+__global__ void __launch_bounds__(FFT_THREADS, 3)
 k_pd_rows(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, int first,
           int count, int nblk, char *__restrict__ ws, const double2 *__restrict__ tw,
-          FftRadices fr, int CBP, int window)
+          FftRadices fr, int CBP_, int window)
 {
-    __shared__ double2 sm[lds_slots<PD_PAD>(PD_LDS_ELEMS)];
-    __shared__ double dwin[PD_LDS_ELEMS / 2 + 1];   // d(m), m = 0..M (M <= N/2 <= 1024)
+    const int N = NC ? NC : fr.n, CBP = NC ? pd_cb(NC) : CBP_;
+    // LDS sized at launch: the padded CBP x N area, then d(m) for m = 0..N/2
+    // (M <= N/2)
+    extern __shared__ double2 sm[];
+    double *dwin = (double *)(sm + lds_slots<PD_PAD>(CBP * N));
     int si, blk;
     if (!xcd_series_block(count, nblk, si, blk))
         return;
     const SeriesDesc &d = sd[gser[first + si]];
-    const int N = fr.n, M = d.M, K2 = N / 4 + 1;
+    const int M = d.M, K2 = N / 4 + 1, half = N / 2;
     const char *r = ws + d.ws_off;
     const bool pz = window != HOS_WIN_NONE;            // d on the lags
+    const bool pdiff = window == HOS_WIN_PARZEN;        // and on their difference
     for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
-    // batches hold the hexagon only (Parzen window)
-    const FoldArgs f = {(const double *)(r + d.o_cfull), dwin,
-                        1.0 / ((const double *)(r + d.o_stats))[3], M, M, N,
-                        window == HOS_WIN_PARZEN};
+    // Batches hold the hexagon |w1|, |w2|, |w1 - w2| <= M only, so the span
+    // a of a lag is at most M and its table row is a itself (c3_table_sum
+    // with amax = M); table offsets stay below (M + 1)^2 and fit 32 bits.
+    const double *cf = (const double *)(r + d.o_cfull);
+    const double inv_norm = 1.0 / ((const double *)(r + d.o_stats))[3];
     const int m1_0 = blk * 2 * CBP;
     // A wave covers all CBP row pairs of 64 / CBP consecutive columns: off
     // the table's rows (w2 beyond w1, or of the other sign) a point reads
     // the table down a column or a diagonal, and the block's 2 CBP
     // consecutive rows then share cache lines there, where 64 consecutive
-    // columns of one row would touch 64 lines.  Unrolled so that the table
-    // reads of several points are in flight at once.
-#pragma unroll 4
-    for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
-        const int m2 = e / CBP, p = e - m2 * CBP, m1 = m1_0 + 2 * p;
-        sm[lds_at<PD_PAD>(p * N + m2)] =
-            make_double2(fold_centred(f, m1, m2), fold_centred(f, m1 + 1, m2));
+    // columns of one row would touch 64 lines.  Element e = m2 CBP + p of
+    // thread t runs over e = t, t + FFT_THREADS, ...: (m2, p) advances by
+    // (FFT_THREADS / CBP, FFT_THREADS % CBP) with a carry, no division.
+    // The windowed, folded value of grid point (m1, m2) is the centred lag's
+    // term alone (fold_centred); the products keep its order, so the values
+    // equal that helper's bit for bit.  The table and d(m) reads are not
+    // branched on: a point off the hexagon reads entry 0 and d(0) and its
+    // value is then selected to 0, so the loads of FOLD_BATCH iterations (two
+    // points each) go out together instead of one latency per point.
+    constexpr int FOLD_BATCH = 4;
+    {
+        const int dp = FFT_THREADS % CBP, dm = FFT_THREADS / CBP;
+        int p = threadIdx.x % CBP, m2 = threadIdx.x / CBP;
+        for (int e0 = threadIdx.x; e0 < CBP * N; e0 += FOLD_BATCH * FFT_THREADS) {
+            double c[FOLD_BATCH][2], w[FOLD_BATCH][2];
+            bool in[FOLD_BATCH][2];
+            int at[FOLD_BATCH];
+#pragma unroll
+            for (int u = 0; u < FOLD_BATCH; ++u) {
+                const int w2 = m2 <= half ? m2 : m2 - N;
+                const bool cin = e0 + u * FFT_THREADS < CBP * N && abs(w2) <= M;
+                const double d2 = dwin[cin ? abs(w2) : 0];
+                at[u] = lds_at<PD_PAD>(p * N + m2);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int m1 = m1_0 + 2 * p + h;
+                    const int w1 = m1 <= half ? m1 : m1 - N, dw = w1 - w2;
+                    const bool ok = cin && m1 < N && abs(w1) <= M && abs(dw) <= M;
+                    const int mn = min(0, min(w1, w2)), mx = max(0, max(w1, w2));
+                    const unsigned off =
+                        ok ? (unsigned)((mx - mn) * (M + 1) + (w1 + w2 - mx - 2 * mn)) : 0u;
+                    c[u][h] = cf[off];
+                    w[u][h] = dwin[ok ? abs(w1) : 0] * d2 * (pdiff ? dwin[ok ? abs(dw) : 0] : 1.0);
+                    in[u][h] = ok;
+                }
+                p += dp;
+                m2 += dm;
+                if (p >= CBP) {
+                    p -= CBP;
+                    ++m2;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < FOLD_BATCH; ++u)
+                if (e0 + u * FFT_THREADS < CBP * N)
+                    sm[at[u]] = make_double2(in[u][0] ? (w[u][0] * inv_norm) * c[u][0] : 0.0,
+                                             in[u][1] ? (w[u][1] * inv_norm) * c[u][1] : 0.0);
+        }
     }
     __syncthreads();
-    fft_lds<FFT_THREADS, PD_LDS_ELEMS, PD_PAD>(sm, tw, fr, CBP);
+    if constexpr (NC > 0)
+        fft_lds_c<NC, 1, pd_cb(NC), FFT_THREADS, PD_PAD>(sm, tw);
+    else
+        fft_lds<FFT_THREADS, PD_LDS_ELEMS, PD_PAD, POW2>(sm, tw, fr, CBP);
     // T1 is column-major, [k2][m1], so that the column pass reads whole
     // columns; a thread writes rows m1, m1 + 1 of one column and the CBP
     // threads of a column write its 2 CBP consecutive rows
     double2 *T1 = (double2 *)(ws + d.grid_off);
-    for (int e = threadIdx.x; e < CBP * K2; e += FFT_THREADS) {
-        const int k2 = e / CBP, p = e - k2 * CBP, m1 = m1_0 + 2 * p;
-        const double2 z = sm[lds_at<PD_PAD>(p * N + k2)],
-                      zc = sm[lds_at<PD_PAD>(p * N + (k2 == 0 ? 0 : N - k2))];
-        // conj(Z(N-k)) = (zc.x, -zc.y)
-        if (m1 < N)
-            T1[(int64_t)k2 * N + m1] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
-        if (m1 + 1 < N)
-            T1[(int64_t)k2 * N + m1 + 1] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+    {
+        const int dp = FFT_THREADS % CBP, dk = FFT_THREADS / CBP;
+        int p = threadIdx.x % CBP, k2 = threadIdx.x / CBP;
+        for (int e = threadIdx.x; e < CBP * K2; e += FFT_THREADS) {
+            const int m1 = m1_0 + 2 * p;
+            const double2 z = sm[lds_at<PD_PAD>(p * N + k2)],
+                          zc = sm[lds_at<PD_PAD>(p * N + (k2 == 0 ? 0 : N - k2))];
+            // conj(Z(N-k)) = (zc.x, -zc.y)
+            double2 *col = T1 + (int64_t)k2 * N;
+            if (m1 < N)
+                col[m1] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+            if (m1 + 1 < N)
+                col[m1 + 1] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+            p += dp;
+            k2 += dk;
+            if (p >= CBP) {
+                p -= CBP;
+                ++k2;
+            }
+        }
     }
 }
 
 // Columns: blockIdx.x = block of CB columns k2 < K2; transforms along m1 and
 // writes the principal-domain points of those columns.
-__global__ void __launch_bounds__(FFT_THREADS)
+template <bool POW2, int NC>
+__global__ void __launch_bounds__(FFT_THREADS, 3)
 k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, int first,
           int count, int nblk, const char *__restrict__ ws, const double2 *__restrict__ tw,
-          FftRadices fr, int CB, double2 *__restrict__ B_pd)
+          FftRadices fr, int CB_, double2 *__restrict__ B_pd)
 {
-    __shared__ double2 sm[lds_slots<PD_PAD>(PD_LDS_ELEMS)];
-    __shared__ int rowstart[FFT_LDS_ELEMS / 2 + 1];
+    const int N = NC ? NC : fr.n, CB = NC ? pd_cb(NC) : CB_;
+    // LDS sized at launch: the padded CB x N area, then the packed starts of
+    // rows k1 = 0..N/2
+    extern __shared__ double2 sm[];
+    int *rowstart = (int *)(sm + lds_slots<PD_PAD>(CB * N));
     int si, blk;
     if (!xcd_series_block(count, nblk, si, blk))
         return;
     const SeriesDesc &d = sd[gser[first + si]];
-    const int N = fr.n, K2 = N / 4 + 1, H = (N - 1) / 2;
+    const int K2 = N / 4 + 1, H = (N - 1) / 2;
     const int k2_0 = blk * CB;
-    const double2 *T1 = (const double2 *)(ws + d.grid_off);   // [k2][m1]
-    for (int e = threadIdx.x; e < CB * N; e += FFT_THREADS) {
-        const int cb = e / N, m1 = e - cb * N, k2 = k2_0 + cb;
-        sm[lds_at<PD_PAD>(cb * N + m1)] =
-            k2 < K2 ? T1[(int64_t)k2 * N + m1] : make_double2(0.0, 0.0);
+    // the block's CB columns are contiguous in T1 ([k2][m1]): element e =
+    // cb N + m1 of the block sits at T1 + k2_0 N + e
+    const double2 *T1 = (const double2 *)(ws + d.grid_off) + (int64_t)k2_0 * N;
+    const int live = (K2 - k2_0 < CB ? K2 - k2_0 : CB) * N;   // elements of columns k2 < K2
+    // COL_BATCH loads in flight per thread before their LDS stores (4 where
+    // the radix-3/5 stages already set the register budget); past the live
+    // columns a thread reads element 0 (always live) and stores 0
+    constexpr int COL_BATCH = POW2 ? 8 : 4;
+    for (int e0 = threadIdx.x; e0 < CB * N; e0 += COL_BATCH * FFT_THREADS) {
+        double2 v[COL_BATCH];
+#pragma unroll
+        for (int u = 0; u < COL_BATCH; ++u) {
+            const int e = e0 + u * FFT_THREADS;
+            v[u] = T1[e < live ? e : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < COL_BATCH; ++u) {
+            const int e = e0 + u * FFT_THREADS;
+            if (e < CB * N)
+                sm[lds_at<PD_PAD>(e)] = e < live ? v[u] : make_double2(0.0, 0.0);
+        }
     }
     for (int a = threadIdx.x; a <= H && a < N / 2 + 1; a += FFT_THREADS)
         rowstart[a] = pd_row_start(a, H);
     __syncthreads();
-    fft_lds<FFT_THREADS, PD_LDS_ELEMS, PD_PAD>(sm, tw, fr, CB);
+    if constexpr (NC > 0)
+        fft_lds_c<NC, 1, pd_cb(NC), FFT_THREADS, PD_PAD>(sm, tw);
+    else
+        fft_lds<FFT_THREADS, PD_LDS_ELEMS, PD_PAD, POW2>(sm, tw, fr, CB);
     // consecutive threads take consecutive k2 of one row k1: the CB points a
-    // row holds in this block are contiguous in the packed output
+    // row holds in this block are contiguous in the packed output; (cb, k1)
+    // advances by (FFT_THREADS mod CB, FFT_THREADS / CB) with a carry
     const int half = H + 1;   // k1 <= H
-    for (int e = threadIdx.x; e < CB * half; e += FFT_THREADS) {
-        const int k1 = e / CB, cb = e - k1 * CB, k2 = k2_0 + cb;
-        if (k2 < K2 && k2 <= k1 && k1 + k2 <= H)
-            B_pd[d.pd_off + rowstart[k1] + k2] = sm[lds_at<PD_PAD>(cb * N + k1)];
+    double2 *out = B_pd + d.pd_off;
+    {
+        const int dcb = FFT_THREADS % CB, dk = FFT_THREADS / CB;
+        int cb = threadIdx.x % CB, k1 = threadIdx.x / CB;
+        for (int e = threadIdx.x; e < CB * half; e += FFT_THREADS) {
+            const int k2 = k2_0 + cb;
+            if (k2 < K2 && k2 <= k1 && k1 + k2 <= H)
+                out[rowstart[k1] + k2] = sm[lds_at<PD_PAD>(cb * N + k1)];
+            cb += dcb;
+            k1 += dk;
+            if (cb >= CB) {
+                cb -= CB;
+                ++k1;
+            }
+        }
     }
 }
 
@@ -625,16 +731,37 @@ hipError_t launch_pd_spectra(const BatchHeader &h, const char *dplan, int window
         if (e != hipSuccess)
             return e;
         const FftRadices fr = factor(N);
-        int CB = PD_LDS_ELEMS / N;
-        if (CB > 32)
-            CB = 32;
+        const int CB = pd_cb(N);
         const int K2 = N / 4 + 1;
         if (CB >= 1) {
             const int rb = (N + 2 * CB - 1) / (2 * CB), cbk = (K2 + CB - 1) / CB;
-            k_pd_rows<<<xcd_grid(gr.count, rb), FFT_THREADS, 0, s>>>(
-                sd, gser, (int)gr.first, gr.count, rb, ws, tw, fr, CB, window);
-            k_pd_cols<<<xcd_grid(gr.count, cbk), FFT_THREADS, 0, s>>>(
-                sd, gser, (int)gr.first, gr.count, cbk, ws, tw, fr, CB, (double2 *)B_pd);
+            const size_t area = (size_t)lds_slots<PD_PAD>(CB * N) * sizeof(double2);
+            const size_t lds_r = area + (size_t)(N / 2 + 1) * sizeof(double),
+                         lds_c = area + (size_t)(N / 2 + 1) * sizeof(int);
+            const dim3 gr_r(xcd_grid(gr.count, rb)), gr_c(xcd_grid(gr.count, cbk));
+            const int first = (int)gr.first;
+            double2 *Bp = (double2 *)B_pd;
+#define HOS_PD_LAUNCH(P2, NCV)                                                              \
+    do {                                                                                    \
+        k_pd_rows<P2, NCV><<<gr_r, FFT_THREADS, lds_r, s>>>(sd, gser, first, gr.count, rb, \
+                                                            ws, tw, fr, CB, window);        \
+        k_pd_cols<P2, NCV><<<gr_c, FFT_THREADS, lds_c, s>>>(sd, gser, first, gr.count, cbk, \
+                                                            ws, tw, fr, CB, Bp);            \
+    } while (0)
+            switch (N) {
+            case 64: HOS_PD_LAUNCH(true, 64); break;
+            case 128: HOS_PD_LAUNCH(true, 128); break;
+            case 256: HOS_PD_LAUNCH(true, 256); break;
+            case 512: HOS_PD_LAUNCH(true, 512); break;
+            case 1024: HOS_PD_LAUNCH(true, 1024); break;
+            case 2048: HOS_PD_LAUNCH(true, 2048); break;
+            default:
+                if (fr.lg >= 0)
+                    HOS_PD_LAUNCH(true, 0);
+                else
+                    HOS_PD_LAUNCH(false, 0);
+            }
+#undef HOS_PD_LAUNCH
         } else {
             return hipErrorInvalidValue;   // N > 2048: not planned for batches
         }
