@@ -168,8 +168,13 @@ __device__ inline void prep_block(const T *__restrict__ x, int64_t n, int64_t o0
     const int64_t o = o0 + t;
     if (o >= oend)
         return;
-    xf[o] = o < nfirst ? sv[t] : 0.0f;
-    win4[o] = make_float4(sv[t], sv[t + 1], sv[t + 2], sv[t + 3]);
+    // the tables are written once and read by another kernel: streaming
+    // (nontemporal) stores
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    typedef unsigned int u32x4n __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(o < nfirst ? sv[t] : 0.0f, xf + o);
+    __builtin_nontemporal_store(f32x4{sv[t], sv[t + 1], sv[t + 2], sv[t + 3]},
+                                (f32x4 *)(win4 + o));
     if constexpr (MODE != 0) {
         uint32_t hw[4], lw[4];
 #pragma unroll
@@ -185,8 +190,8 @@ __device__ inline void prep_block(const T *__restrict__ x, int64_t n, int64_t o0
             hw[e / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
             lw[e / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
         }
-        win8h[o] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-        win8l[o] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        __builtin_nontemporal_store(u32x4n{hw[0], hw[1], hw[2], hw[3]}, (u32x4n *)(win8h + o));
+        __builtin_nontemporal_store(u32x4n{lw[0], lw[1], lw[2], lw[3]}, (u32x4n *)(win8l + o));
     }
 }
 
