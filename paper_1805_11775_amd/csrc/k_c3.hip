@@ -1264,52 +1264,131 @@ k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict
         cfull[(int64_t)(r + 1) * (M + 1) + b] = sum;
 }
 
-// Leftover diagonal sums: one workgroup per (leftover a = 32 blockIdx.x <=
-// M, series); strided FP64 partial sums from the input combined by a
-// fixed-order tree into C[a][a].
-template <typename T>
+// Leftover diagonal sums C[a][a] = sum_i x~_i x~_{i+a}^2, a = 32 k <= M,
+// in FP64 from the input.  Workgroup (c, s) takes the BD_BLK-sample blocks
+// c, c + nchunk, ... of series s: their centred, scaled samples x~ (plus the
+// 32 (nleft - 1) halo) pass through LDS, formed once per sample, while the
+// next block's loads are already in flight; each thread takes consecutive
+// sample pairs (one 16-byte LDS read per pair and diagonal) and accumulates
+// every diagonal of the series.  A fixed-order reduction per diagonal (wave
+// butterfly, then the four waves in order) leaves the chunk's partial in
+// dpart[k nchunk + c]; k_bdiag_final sums the chunks in order.  x~ is 0 past
+// the series' end.  MAXL bounds nleft = 1 + M / 32.
+constexpr int BD_BLK = 2048;
+constexpr int BD_MAXLEFT = 33;   // 1 + M / 32 for M <= 1024
+
+template <typename T, int MAXL>
 __global__ void __launch_bounds__(256)
-k_bdiag(const T *__restrict__ x, const SeriesDesc *__restrict__ sd, char *__restrict__ ws)
+k_bdiag(const T *__restrict__ x, const SeriesDesc *__restrict__ sd, char *__restrict__ ws,
+        int nchunk)
 {
-    __shared__ double red[256];
+    constexpr int STAGE = BD_BLK + 32 * (MAXL - 1);
+    constexpr int LB = (STAGE + 255) / 256;
+    __shared__ __attribute__((aligned(16))) double sx[STAGE];   // read as double2
+    __shared__ double wsum[4][MAXL];
     const SeriesDesc &d = sd[blockIdx.y];
-    const int left = blockIdx.x;
-    if (left >= d.nleft)
-        return;
+    const int nleft = d.nleft, c = blockIdx.x;
     char *r = ws + d.ws_off;
     const double *stats = (const double *)(r + d.o_stats);
     const T *xs = x + d.x_off;
-    const int64_t n = d.n, a = 32 * (int64_t)left;
+    const int64_t n = d.n;
     const double mu = stats[0], sc = stats[1];
-    // four independent partial sums per thread (samples i, i+256, i+512,
-    // i+768 of each 1024-sample stride) so that the loads go out together;
-    // combined in a fixed order, then the fixed tree
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t i = threadIdx.x;
-    for (; i + 768 + a < n; i += 1024) {
+    const int live = BD_BLK + 32 * (nleft - 1);   // staged samples per block
+    double acc[MAXL];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double u = ((double)xs[i + 256 * k + a] - mu) * sc;
-            s4[k] += (((double)xs[i + 256 * k] - mu) * sc) * u * u;
-        }
-    }
+    for (int k = 0; k < MAXL; ++k)
+        acc[k] = 0.0;
+    T v[LB];
+    auto fetch = [&](int64_t i0) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {   // the tail: at most three more samples
-        const int64_t j = i + 256 * k;
-        if (j + a < n) {
-            const double u = ((double)xs[j + a] - mu) * sc;
-            s4[k] += (((double)xs[j] - mu) * sc) * u * u;
+        for (int u = 0; u < LB; ++u) {
+            const int64_t i = i0 + threadIdx.x + 256 * u;
+            v[u] = xs[i < n ? i : 0];
         }
-    }
-    red[threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
+    };
+    int64_t i0 = (int64_t)c * BD_BLK;
+    if (i0 < n)
+        fetch(i0);
+    for (; i0 < n; i0 += (int64_t)nchunk * BD_BLK) {
+        __syncthreads();   // the previous block's reads are done
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < live)
+                sx[e] = i0 + e < n ? ((double)v[u] - mu) * sc : 0.0;
+        }
         __syncthreads();
+        const int64_t next = i0 + (int64_t)nchunk * BD_BLK;
+        if (next < n)
+            fetch(next);   // in flight during this block's sums
+#pragma unroll
+        for (int q = 0; q < BD_BLK / 512; ++q) {
+            const int j = 2 * threadIdx.x + 512 * q;
+            const double2 xi = *(const double2 *)&sx[j];
+#pragma unroll
+            for (int k = 0; k < MAXL; ++k)
+                if (k < nleft) {
+                    const double2 u = *(const double2 *)&sx[j + 32 * k];
+                    acc[k] += xi.x * u.x * u.x;
+                    acc[k] += xi.y * u.y * u.y;
+                }
+        }
     }
-    if (threadIdx.x == 0)
-        ((double *)(r + d.o_cfull))[a * (d.M + 1) + a] = red[0];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < MAXL; ++k) {
+        if (k < nleft) {
+            double t = acc[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+                t += __shfl_xor(t, off, 64);
+            if (lane == 0)
+                wsum[wv][k] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nleft) {
+        const int k = threadIdx.x;
+        ((double *)(r + d.o_dpart))[k * nchunk + c] =
+            ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
+    }
+}
+
+// C[a][a], a = 32 k: the chunk partials of diagonal k summed in chunk order.
+__global__ void __launch_bounds__(64)
+k_bdiag_final(const SeriesDesc *__restrict__ sd, char *__restrict__ ws, int nchunk)
+{
+    const SeriesDesc &d = sd[blockIdx.x];
+    char *r = ws + d.ws_off;
+    const double *dpart = (const double *)(r + d.o_dpart);
+    for (int k = threadIdx.x; k < d.nleft; k += 64) {
+        double t = 0.0;
+        for (int c = 0; c < nchunk; ++c)
+            t += dpart[k * nchunk + c];
+        const int64_t a = 32 * (int64_t)k;
+        ((double *)(r + d.o_cfull))[a * (d.M + 1) + a] = t;
+    }
+}
+
+template <typename T>
+void launch_bdiag_t(const T *x, const BatchHeader &h, const SeriesDesc *sd, char *ws,
+                    hipStream_t s)
+{
+    // enough chunks per series for about 2048 workgroups in all, at most the
+    // dot_blocks slots the plan gave each diagonal
+    int64_t nchunk = (2048 + h.batch - 1) / h.batch;
+    if (nchunk > h.dot_blocks)
+        nchunk = h.dot_blocks;
+    if (nchunk < 1)
+        nchunk = 1;
+    const dim3 grid((unsigned)nchunk, (unsigned)h.batch);
+    if (h.max_nleft <= 9)
+        k_bdiag<T, 9><<<grid, 256, 0, s>>>(x, sd, ws, (int)nchunk);
+    else if (h.max_nleft <= 17)
+        k_bdiag<T, 17><<<grid, 256, 0, s>>>(x, sd, ws, (int)nchunk);
+    else
+        k_bdiag<T, BD_MAXLEFT><<<grid, 256, 0, s>>>(x, sd, ws, (int)nchunk);
+    k_bdiag_final<<<(unsigned)h.batch, 64, 0, s>>>(sd, ws, (int)nchunk);
 }
 
 // FP32 path: one tile class (4 x 4 blocks), the generic per-class kernel.
@@ -1447,13 +1526,13 @@ hipError_t launch_batch_reduce(const void *x, int dtype, const BatchHeader &h, c
         else
             k_c3_reduce_items<2><<<(unsigned)(h.n_tiles[cls] * 4 * 4), 256, 0, s>>>(sd, t, part, ws);
     }
-    // a series' diagonals in consecutive workgroups, so that its samples are
-    // read from HBM once and from L2 for the other diagonals
-    const dim3 grid((unsigned)h.max_nleft, (unsigned)h.batch);
+    // every leftover diagonal of a series in one pass over its samples
+    if (h.max_nleft > BD_MAXLEFT)
+        return hipErrorInvalidValue;
     if (dtype == HOS_F64)
-        k_bdiag<double><<<grid, 256, 0, s>>>((const double *)x, sd, ws);
+        launch_bdiag_t((const double *)x, h, sd, ws, s);
     else
-        k_bdiag<float><<<grid, 256, 0, s>>>((const float *)x, sd, ws);
+        launch_bdiag_t((const float *)x, h, sd, ws, s);
     return hipGetLastError();
 }
 

@@ -35,11 +35,26 @@ __device__ inline void moments_partial_body(const T *__restrict__ x, int64_t n, 
     __shared__ double s_sum[256], s_min[256], s_max[256];
     double sum = 0.0, mn = __builtin_huge_val(), mx = -__builtin_huge_val();
     const int64_t stride = (int64_t)nblk * blockDim.x;
-    for (int64_t t = (int64_t)blk * blockDim.x + threadIdx.x; t < n; t += stride) {
-        double v = (double)x[t];
-        sum += v;
-        mn = fmin(mn, v);
-        mx = fmax(mx, v);
+    // MOM_BATCH loads go out together (past the end: sample 0, not summed);
+    // the sums keep the one-sample order
+    constexpr int MOM_BATCH = 4;
+    for (int64_t t0 = (int64_t)blk * blockDim.x + threadIdx.x; t0 < n;
+         t0 += MOM_BATCH * stride) {
+        T v[MOM_BATCH];
+#pragma unroll
+        for (int u = 0; u < MOM_BATCH; ++u) {
+            const int64_t t = t0 + u * stride;
+            v[u] = x[t < n ? t : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < MOM_BATCH; ++u) {
+            if (t0 + u * stride < n) {
+                const double w = (double)v[u];
+                sum += w;
+                mn = fmin(mn, w);
+                mx = fmax(mx, w);
+            }
+        }
     }
     const int tid = threadIdx.x;
     s_sum[tid] = sum;
