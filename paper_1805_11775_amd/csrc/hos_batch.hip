@@ -95,7 +95,11 @@ int batch_plan(int32_t batch, const int64_t *n, const int32_t *M, int32_t window
             h.uniform_n = -1;
         h.max_n = std::max<int64_t>(h.max_n, n[s]);
     }
+    // moment blocks per series: one per 4096 samples of the longest series,
+    // but no more than about 16384 workgroups in all (a large batch fills
+    // the chip with a few blocks per series)
     h.momb = std::min<int64_t>(256, std::max<int64_t>(1, (h.max_n + 4095) / 4096));
+    h.momb = std::max<int64_t>(1, std::min<int64_t>(h.momb, (16384 + batch - 1) / batch));
     h.dot_blocks = std::min<int64_t>(64, std::max<int64_t>(1, h.max_n / 4096));
 
     std::vector<SeriesDesc> sd(batch);

@@ -1233,17 +1233,17 @@ k_c3_items_u(const SeriesDesc *__restrict__ sd, const C3Item *__restrict__ items
 }
 
 // Sum the slots of one (series, tile) in order and scatter one 32 x 32 block
-// into the series' C[a][b] table.  One workgroup per (tile, block).
+// into the series' C[a][b] table.  One workgroup per (tile, block), each
+// thread four elements of it: the four loads of a slot go out together and
+// each element's slots are added in slot order.
 template <int NB>
 __global__ void __launch_bounds__(256)
 k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict__ tiles,
                   const double *__restrict__ part, char *__restrict__ ws)
 {
     constexpr int64_t TILE = (int64_t)(32 * NB) * (32 * NB);
-    // blockIdx.x = (tile, 32-block, quarter of the block's 1024 elements)
-    const int q = blockIdx.x & 3;
-    const C3TileRef t = tiles[(blockIdx.x >> 2) / (NB * NB)];
-    const int blk = (blockIdx.x >> 2) % (NB * NB);
+    const C3TileRef t = tiles[blockIdx.x / (NB * NB)];
+    const int blk = blockIdx.x % (NB * NB);
     const SeriesDesc &d = sd[t.series];
     const int bR = blk / NB, bC = blk % NB;
     const int Rg = t.R * NB + bR, Bg = t.Cc * NB + bC;
@@ -1251,17 +1251,28 @@ k_c3_reduce_items(const SeriesDesc *__restrict__ sd, const C3TileRef *__restrict
         return;
     const int M = d.M;
     double *cfull = (double *)(ws + d.ws_off + d.o_cfull);
-    const int e = threadIdx.x + 256 * q;
-    double sum = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < t.nslot; ++j)
-        sum += part[(t.slot0 + j) * TILE + (int64_t)blk * 1024 + e];
-    const int v = e >> 6, lane = e & 63;
-    const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    const int col = lane & 31;
-    const int r = Rg * 32 + row, b = Bg * 32 + col;
-    if (r < M && (Bg < Rg || col <= row + 1))
-        cfull[(int64_t)(r + 1) * (M + 1) + b] = sum;
+    const double *src = part + t.slot0 * TILE + (int64_t)blk * 1024 + threadIdx.x;
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int j = 0; j < t.nslot; ++j) {
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            v[q] = src[j * TILE + 256 * q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            sum[q] += v[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int v = e >> 6, lane = e & 63;
+        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = lane & 31;
+        const int r = Rg * 32 + row, b = Bg * 32 + col;
+        if (r < M && (Bg < Rg || col <= row + 1))
+            cfull[(int64_t)(r + 1) * (M + 1) + b] = sum[q];
+    }
 }
 
 // Leftover diagonal sums C[a][a] = sum_i x~_i x~_{i+a}^2, a = 32 k <= M,
@@ -1522,9 +1533,9 @@ hipError_t launch_batch_reduce(const void *x, int dtype, const BatchHeader &h, c
         const C3TileRef *t = (const C3TileRef *)(dplan + h.tiles_off[cls]);
         const double *part = (const double *)(ws + h.part_off[cls]);
         if (cls == 1)
-            k_c3_reduce_items<4><<<(unsigned)(h.n_tiles[cls] * 16 * 4), 256, 0, s>>>(sd, t, part, ws);
+            k_c3_reduce_items<4><<<(unsigned)(h.n_tiles[cls] * 16), 256, 0, s>>>(sd, t, part, ws);
         else
-            k_c3_reduce_items<2><<<(unsigned)(h.n_tiles[cls] * 4 * 4), 256, 0, s>>>(sd, t, part, ws);
+            k_c3_reduce_items<2><<<(unsigned)(h.n_tiles[cls] * 4), 256, 0, s>>>(sd, t, part, ws);
     }
     // every leftover diagonal of a series in one pass over its samples
     if (h.max_nleft > BD_MAXLEFT)

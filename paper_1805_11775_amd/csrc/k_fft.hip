@@ -383,6 +383,11 @@ struct FoldArgs {
     bool pdiff;           // Parzen product: d on the difference too
 };
 
+// Branch-free: a point off the support reads table entry 0 and d(0) and is
+// then selected to 0, so the reads of several points can be in flight at
+// once.  On the support the span a = max(0, w1, w2) - min(0, w1, w2) is at
+// most amax (the hexagon has a <= M; the corners, only without the Parzen
+// product, a <= 2M = amax), so the table entry is c3_table_sum's.
 __device__ __attribute__((always_inline)) inline double fold_centred(const FoldArgs &f, int m1,
                                                                      int m2)
 {
@@ -391,10 +396,14 @@ __device__ __attribute__((always_inline)) inline double fold_centred(const FoldA
     const int dw = w1 - w2;
     const bool in = m1 < f.N && abs(w1) <= f.M && abs(w2) <= f.M &&
                     (abs(dw) <= f.M || (!f.pdiff && f.amax > f.M));
-    if (!in)
-        return 0.0;
-    const double wt = f.dwin[abs(w1)] * f.dwin[abs(w2)] * (f.pdiff ? f.dwin[abs(dw)] : 1.0);
-    return (wt * f.inv_norm) * c3_table_sum(f.cfull, f.M, f.amax, w1, w2);
+    const int mn = min(0, min(w1, w2)), mx = max(0, max(w1, w2));
+    const int a = mx - mn, b = (w1 + w2) - mn - mx - mn;
+    const int row = a <= f.M ? a : a - f.M - 1;
+    const unsigned off = in ? (unsigned)(row * (f.M + 1) + b) : 0u;
+    const double c = f.cfull[off];
+    const double wt = f.dwin[in ? abs(w1) : 0] * f.dwin[in ? abs(w2) : 0] *
+                      (f.pdiff ? f.dwin[in ? abs(dw) : 0] : 1.0);
+    return in ? (wt * f.inv_norm) * c : 0.0;
 }
 
 constexpr int PD_LDS_ELEMS = 2048;   // complex doubles per workgroup (32 KB): 4+ per CU

@@ -37,7 +37,7 @@ __device__ inline void moments_partial_body(const T *__restrict__ x, int64_t n, 
     const int64_t stride = (int64_t)nblk * blockDim.x;
     // MOM_BATCH loads go out together (past the end: sample 0, not summed);
     // the sums keep the one-sample order
-    constexpr int MOM_BATCH = 4;
+    constexpr int MOM_BATCH = 8;
     for (int64_t t0 = (int64_t)blk * blockDim.x + threadIdx.x; t0 < n;
          t0 += MOM_BATCH * stride) {
         T v[MOM_BATCH];
