@@ -409,11 +409,16 @@ __device__ __attribute__((always_inline)) inline double fold_centred(const FoldA
 constexpr int PD_LDS_ELEMS = 2048;   // complex doubles per workgroup (32 KB): 4+ per CU
 constexpr int PD_PAD = 3;            // the batch spectra's LDS padding (lds_at)
 
-// Sequences per workgroup of the batch spectra: as many as PD_LDS_ELEMS
-// holds, at most 32.
+// Sequences per workgroup of the batch spectra: PD_LDS_ELEMS complex values
+// for N >= 512, PD_LDS_ELEMS / 2 below (the smaller area lets six
+// workgroups share a CU instead of four; measured faster for N <= 256 and
+// slower at 512), at most 32 sequences.
 __host__ __device__ constexpr int pd_cb(int N)
 {
-    return N <= 0 ? 1 : PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
+    return N <= 0 ? 1
+                  : (N >= 512 ? PD_LDS_ELEMS : PD_LDS_ELEMS / 2) / N > 32
+                        ? 32
+                        : (N >= 512 ? PD_LDS_ELEMS : PD_LDS_ELEMS / 2) / N;
 }
 
 // Workgroups are dispatched to the 8 XCDs round robin by their linear index,
