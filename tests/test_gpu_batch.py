@@ -61,6 +61,34 @@ def test_uneven_batch_matches_oracle(path):
         assert e1 < TOL[path] and e2 < TOL[path], (s, e1, e2)
 
 
+@pytest.mark.parametrize("path", ["split_fp16", "fp32"])
+def test_batch_spectra_each_dft_size(path):
+    """One short series per DFT size of the batch spectra's fixed-size
+    kernels (N = 64, 128, 256, 512, 1024) and one size they leave to the
+    general kernels (N = 200): c3 and the principal-domain spectrum of every
+    series against the oracle, element by element."""
+    hos = _hos()
+    M = [32, 64, 128, 256, 512, 100]
+    n = [1300, 1400, 1500, 1600, 1700, 1250]
+    xs = [(synth.iid_gauss(k, 90 + i) if i % 2 == 0 else synth.iid_exp_centered(k, 90 + i))
+          .astype(np.float32) for i, k in enumerate(n)]
+    plan = hos.BatchPlan(n, M, path=path)
+    S = plan.series()
+    assert [int(v) for v in S[:, 2]] == [64, 128, 256, 512, 1024, 200]
+    print("case: batch spectra sizes, path %s" % path, flush=True)
+    c3, B = hos.bispectrum_batched(torch.from_numpy(np.concatenate(xs)).cuda(), plan)
+    torch.cuda.synchronize()
+    c3, B = c3.cpu().numpy(), B.cpu().numpy()
+    for s in range(len(n)):
+        Ms, N, npd, c3o, pdo = int(S[s, 1]), int(S[s, 2]), int(S[s, 3]), int(S[s, 5]), int(S[s, 6])
+        c_ref, B_ref = oracle.bispectrum(xs[s], Ms, N)
+        k1, k2 = oracle.pd_indices(N)
+        got_c = c3[c3o:c3o + (2 * Ms + 1) ** 2].reshape(2 * Ms + 1, 2 * Ms + 1)
+        e1, e2 = _rel(got_c, c_ref), _rel(B[pdo:pdo + npd], B_ref[k1, k2])
+        print("series %d n=%d M=%d N=%d: c3 %.3e B_pd %.3e" % (s, n[s], Ms, N, e1, e2))
+        assert e1 < TOL[path] and e2 < TOL[path], (s, e1, e2)
+
+
 def test_batch_deterministic():
     hos = _hos()
     xs, n, M = _uneven()
