@@ -783,53 +783,83 @@ k_diag_dot(const T *__restrict__ x, int64_t n, const double *__restrict__ stats,
         dpart[blockIdx.x] = red[0];
 }
 
-// The same sums for nleft <= DIAG_FUSED_MAX leftovers in one pass over x:
-// workgroup b stages x~ (FP64) for the samples [1024 b, 1024 (b+1)) plus the
-// 32 (nleft-1) halo in LDS; each thread accumulates every leftover's
-// products for its 4 samples; waves reduce by lane shuffles, then the 4 wave
-// sums are added in order.  dpart[left * nblocks + b].
+// The same sums for nleft <= DIAG_FUSED_MAX leftovers in one pass over x.
+// Workgroup c takes the 2048-sample blocks c, c + gridDim.x, ...: it stages
+// x~ (FP64, 0 past n) for the block plus the 32 (nleft - 1) halo in LDS while
+// the next block's loads are in flight, and each thread accumulates every
+// leftover's products for its consecutive sample pairs (one 16-byte LDS read
+// per pair and leftover; the first factor is 0 from nfirst on).  Waves
+// reduce by lane shuffles, then the 4 wave sums are added in order:
+// dpart[left * gridDim.x + c].  MAXL bounds nleft.
 constexpr int DIAG_FUSED_MAX = 32;
+constexpr int DF_BLK = 2048;
+constexpr int DF_MAX_WG = 256;
 
-template <typename T>
+template <typename T, int MAXL>
 __global__ void __launch_bounds__(256)
 k_diag_fused(const T *__restrict__ x, int64_t n, const double *__restrict__ stats, int nleft,
              double *__restrict__ dpart, int64_t nfirst)
 {
-    __shared__ double sx[1024 + 32 * (DIAG_FUSED_MAX - 1)];
-    __shared__ double wsum[4][DIAG_FUSED_MAX];
+    constexpr int STAGE = DF_BLK + 32 * (MAXL - 1);
+    constexpr int LB = (STAGE + 255) / 256;
+    __shared__ __attribute__((aligned(16))) double sx[STAGE];   // read as double2
+    __shared__ double wsum[4][MAXL];
     const double mu = stats[0], sc = stats[1];
-    const int64_t i0 = (int64_t)blockIdx.x * 1024;
-    const int halo = 32 * (nleft - 1);
-    for (int e = threadIdx.x; e < 1024 + halo; e += 256) {
-        const int64_t i = i0 + e;
-        sx[e] = i < n ? ((double)x[i] - mu) * sc : 0.0;
-    }
-    __syncthreads();
-    double acc[DIAG_FUSED_MAX];
+    const int live = DF_BLK + 32 * (nleft - 1);
+    const int64_t step = (int64_t)gridDim.x * DF_BLK;
+    double acc[MAXL];
 #pragma unroll
-    for (int k = 0; k < DIAG_FUSED_MAX; ++k)
+    for (int k = 0; k < MAXL; ++k)
         acc[k] = 0.0;
+    T v[LB];
+    auto fetch = [&](int64_t i0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int j = threadIdx.x + 256 * q;
-        const double xi = i0 + j < nfirst ? sx[j] : 0.0;
+        for (int u = 0; u < LB; ++u) {
+            const int64_t i = i0 + threadIdx.x + 256 * u;
+            v[u] = x[i < n ? i : 0];
+        }
+    };
+    int64_t i0 = (int64_t)blockIdx.x * DF_BLK;
+    if (i0 < n)
+        fetch(i0);
+    for (; i0 < n; i0 += step) {
+        __syncthreads();   // the previous block's reads are done
 #pragma unroll
-        for (int k = 0; k < DIAG_FUSED_MAX; ++k)
-            if (k < nleft) {
-                const double u = sx[j + 32 * k];
-                acc[k] += xi * u * u;
-            }
+        for (int u = 0; u < LB; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < live)
+                sx[e] = i0 + e < n ? ((double)v[u] - mu) * sc : 0.0;
+        }
+        __syncthreads();
+        if (i0 + step < n)
+            fetch(i0 + step);   // in flight during this block's sums
+#pragma unroll
+        for (int q = 0; q < DF_BLK / 512; ++q) {
+            const int j = 2 * threadIdx.x + 512 * q;
+            double2 xi = *(const double2 *)&sx[j];
+            if (i0 + j >= nfirst)
+                xi.x = 0.0;
+            if (i0 + j + 1 >= nfirst)
+                xi.y = 0.0;
+#pragma unroll
+            for (int k = 0; k < MAXL; ++k)
+                if (k < nleft) {
+                    const double2 u = *(const double2 *)&sx[j + 32 * k];
+                    acc[k] += xi.x * u.x * u.x;
+                    acc[k] += xi.y * u.y * u.y;
+                }
+        }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < DIAG_FUSED_MAX; ++k) {
+    for (int k = 0; k < MAXL; ++k) {
         if (k < nleft) {
-            double v = acc[k];
+            double t = acc[k];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1)
-                v += __shfl_xor(v, off, 64);
+                t += __shfl_xor(t, off, 64);
             if (lane == 0)
-                wsum[wv][k] = v;
+                wsum[wv][k] = t;
         }
     }
     __syncthreads();
@@ -837,6 +867,14 @@ k_diag_fused(const T *__restrict__ x, int64_t n, const double *__restrict__ stat
         const int k = threadIdx.x;
         dpart[k * gridDim.x + blockIdx.x] = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
     }
+}
+
+// Workgroups of k_diag_fused for n samples (the plan's dot_blocks = ceil(n /
+// 1024) slots per leftover hold them).
+inline int diag_fused_grid(int64_t n)
+{
+    const int64_t b = (n + DF_BLK - 1) / DF_BLK;
+    return (int)(b < 1 ? 1 : (b > DF_MAX_WG ? DF_MAX_WG : b));
 }
 
 // C[a][a] = the leftover's block partials summed in block order (strided over
@@ -1462,12 +1500,25 @@ hipError_t launch_diag_dot(const void *x, int dtype, const C3Plan &p, char *ws, 
     if (nfirst < 0)
         nfirst = p.n;
     if (p.nleft <= DIAG_FUSED_MAX) {   // the plan made dot_blocks = ceil(n / 1024)
-        if (dtype == HOS_F64)
-            k_diag_fused<double><<<p.dot_blocks, 256, 0, s>>>((const double *)x, p.n, stats,
-                                                              p.nleft, dpart, nfirst);
-        else
-            k_diag_fused<float><<<p.dot_blocks, 256, 0, s>>>((const float *)x, p.n, stats,
-                                                             p.nleft, dpart, nfirst);
+        const int g = diag_fused_grid(p.n);
+#define HOS_DIAG_FUSED(T, L)                                                              \
+    k_diag_fused<T, L><<<g, 256, 0, s>>>((const T *)x, p.n, stats, p.nleft, dpart, nfirst)
+        if (dtype == HOS_F64) {
+            if (p.nleft <= 9)
+                HOS_DIAG_FUSED(double, 9);
+            else if (p.nleft <= 17)
+                HOS_DIAG_FUSED(double, 17);
+            else
+                HOS_DIAG_FUSED(double, DIAG_FUSED_MAX);
+        } else {
+            if (p.nleft <= 9)
+                HOS_DIAG_FUSED(float, 9);
+            else if (p.nleft <= 17)
+                HOS_DIAG_FUSED(float, 17);
+            else
+                HOS_DIAG_FUSED(float, DIAG_FUSED_MAX);
+        }
+#undef HOS_DIAG_FUSED
         return hipGetLastError();
     }
     const int grid = p.nleft * p.dot_blocks;
@@ -1499,8 +1550,9 @@ hipError_t launch_c3_reduce(const C3Plan &p, char *ws, hipStream_t s, int region
                 p.smax, p.NBR, p.M, region, cfull);
     }
     if (region == 0)   // the diagonal sums C[a][a], a = 0 and a = 32k, belong to F
-        k_diag_final<<<p.nleft, 256, 0, s>>>((const double *)(ws + p.off_dpart), p.nleft,
-                                            p.dot_blocks, p.M, cfull);
+        k_diag_final<<<p.nleft, 256, 0, s>>>(
+            (const double *)(ws + p.off_dpart), p.nleft,
+            p.nleft <= DIAG_FUSED_MAX ? diag_fused_grid(p.n) : p.dot_blocks, p.M, cfull);
     return hipGetLastError();
 }
 

@@ -91,7 +91,13 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
     // the in-place stages use a padded area (lds_at), the ping-pong ones not
     constexpr int PAD = PP ? 0 : AXIS_PAD;
     const int N = fr.n;
-    const int64_t seq0 = (int64_t)blockIdx.x * CB;
+    // Workgroups go to the 8 XCDs round robin.  When the grid divides by 8,
+    // XCD x takes the x-th eighth of the sequence blocks in order, so that
+    // neighbouring blocks -- whose strided rows share cache lines -- meet in
+    // one L2 instead of each fetching whole lines for half their bytes.
+    const unsigned G = gridDim.x, w = blockIdx.x;
+    const unsigned blk = G % 8 == 0 ? (w % 8) * (G / 8) + w / 8 : w;
+    const int64_t seq0 = (int64_t)blk * CB;
     const int tot = CB * N;
     for (int cb = threadIdx.x; cb < CB; cb += THREADS) {
         const int64_t s = seq0 + cb;
