@@ -80,17 +80,21 @@ __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
 // in-place one (long transforms, 4-element runs per row) measured slower
 constexpr int AXIS_BATCH_PP = 8;
 
-template <bool PP, int THREADS>
+// NC: in place with N fixed at compile time (1024, CB = FFT_LDS_ELEMS / NC:
+// constant stage indices), else 0.
+template <bool PP, int THREADS, int NC = 0>
 __global__ void __launch_bounds__(THREADS)
 k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadices fr,
-           int64_t nseq, int64_t es, int64_t b_in, int64_t s_in, int64_t s_out, int CB,
+           int64_t nseq, int64_t es, int64_t b_in, int64_t s_in, int64_t s_out, int CB_,
            int live)
 {
+    static_assert(NC == 0 || !PP, "compile-time sizes are in place only");
+    const int CB = NC ? FFT_LDS_ELEMS / NC : CB_;
     extern __shared__ double2 sm[];
     __shared__ int64_t base[FFT_MAX_CB];
     // the in-place stages use a padded area (lds_at), the ping-pong ones not
     constexpr int PAD = PP ? 0 : AXIS_PAD;
-    const int N = fr.n;
+    const int N = NC ? NC : fr.n;
     // Workgroups go to the 8 XCDs round robin.  When the grid divides by 8,
     // XCD x takes the x-th eighth of the sequence blocks in order, so that
     // neighbouring blocks -- whose strided rows share cache lines -- meet in
@@ -145,7 +149,9 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
     double2 *cur = sm, *nxt = sm + tot;
     int Ns = 1, lgNs = 0;
     const int lg = fr.lg;
-    for (int st = 0; st < 16 && fr.r[st] > 0; ++st) {
+    if constexpr (NC > 0)
+        fft_lds_c<NC, 1, FFT_LDS_ELEMS / NC, THREADS, PAD>(sm, tw);
+    for (int st = 0; NC == 0 && st < 16 && fr.r[st] > 0; ++st) {
         const int R = fr.r[st];
         if constexpr (PP) {
             if (R == 8)
@@ -219,7 +225,10 @@ void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq,
         CB = 32;
     const int64_t blocks = (nseq + CB - 1) / CB;
     const size_t lds = (size_t)lds_slots<AXIS_PAD>(CB * fr.n) * sizeof(double2);
-    if (fr.n >= 512)
+    if (fr.n == 1024 && CB == FFT_LDS_ELEMS / 1024)
+        k_fft_axis<false, 1024, 1024><<<blocks, 1024, lds, s>>>(d, tw, fr, nseq, es, b_in, s_in,
+                                                               s_out, CB, live);
+    else if (fr.n >= 512)
         k_fft_axis<false, 1024><<<blocks, 1024, lds, s>>>(d, tw, fr, nseq, es, b_in, s_in, s_out,
                                                          CB, live);
     else
@@ -643,15 +652,17 @@ k_pd_cols(const SeriesDesc *__restrict__ sd, const int32_t *__restrict__ gser, i
 // The full N x N spectrum of one series: fold + window into LDS, row DFTs with
 // two real rows per complex sequence (as k_pd_rows), every k2 written to B;
 // the column pass then runs in place (launch_fft_cols).
-template <int ELEMS, int THREADS>
+// NC: N fixed at compile time (1024: the FFT stages' indices and the loop
+// counts become constants; CBP is then ELEMS / NC), else 0.
+template <int ELEMS, int THREADS, int NC = 0>
 __global__ void __launch_bounds__(THREADS)
 k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, int M,
-            int amax, const double2 *__restrict__ tw, FftRadices fr, int CBP, int window,
+            int amax, const double2 *__restrict__ tw, FftRadices fr, int CBP_, int window,
             double2 *__restrict__ B)
 {
     __shared__ double2 sm[ELEMS];
     __shared__ double dwin[FFT_LDS_ELEMS / 2 + 1];
-    const int N = fr.n;
+    const int N = NC ? NC : fr.n, CBP = NC ? ELEMS / NC : CBP_;
     const bool pz = window != HOS_WIN_NONE;            // d on the lags
     for (int m = threadIdx.x; m <= M; m += THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
@@ -664,7 +675,10 @@ k_full_rows(const double *__restrict__ cfull, const double *__restrict__ stats, 
         sm[e] = make_double2(fold_centred(f, m1, m2), fold_centred(f, m1 + 1, m2));
     }
     __syncthreads();
-    fft_lds<THREADS, ELEMS>(sm, tw, fr, CBP);
+    if constexpr (NC > 0)
+        fft_lds_c<NC, 1, ELEMS / NC, THREADS, 0>(sm, tw);
+    else
+        fft_lds<THREADS, ELEMS>(sm, tw, fr, CBP);
     for (int e = threadIdx.x; e < CBP * N; e += THREADS) {
         const int p = e / N, k = e - p * N, m1 = m1_0 + 2 * p;
         const double2 z = sm[p * N + k], zc = sm[p * N + (k == 0 ? 0 : N - k)];
@@ -798,7 +812,10 @@ hipError_t launch_full_rows(const double *cfull, const double *stats, int M, int
     if (N <= PD_LDS_ELEMS) {
         const int CBP = PD_LDS_ELEMS / N > 32 ? 32 : PD_LDS_ELEMS / N;
         const unsigned grid = (N + 2 * CBP - 1) / (2 * CBP);
-        if (N >= 512)
+        if (N == 1024)
+            k_full_rows<PD_LDS_ELEMS, 1024, 1024><<<grid, 1024, 0, s>>>(
+                cfull, stats, M, amax, tw, fr, CBP, window, (double2 *)B);
+        else if (N >= 512)
             k_full_rows<PD_LDS_ELEMS, 1024><<<grid, 1024, 0, s>>>(cfull, stats, M, amax, tw, fr,
                                                                 CBP, window, (double2 *)B);
         else
