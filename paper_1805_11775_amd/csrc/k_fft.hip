@@ -75,32 +75,93 @@ __device__ inline void stockham_pingpong(const double2 *__restrict__ src,
     __syncthreads();
 }
 
+// factor()'s radix order as a constant: radix i of N (8s, then 4s, 2s, 3s,
+// 5s), 0 past the last.
+__host__ __device__ constexpr int radix_at(int N, int i)
+{
+    const int rs[5] = {8, 4, 2, 3, 5};
+    for (int k = 0; k < 5; ++k)
+        while (N % rs[k] == 0) {
+            if (i == 0)
+                return rs[k];
+            --i;
+            N /= rs[k];
+        }
+    return 0;
+}
+
+// stockham_pingpong with N, NS and CB fixed at compile time: the same
+// arithmetic, constant indices.
+template <int R, int N, int NS, int CB, int THREADS>
+__device__ inline void stockham_pingpong_c(const double2 *__restrict__ src,
+                                           double2 *__restrict__ dst,
+                                           const double2 *__restrict__ tw)
+{
+    constexpr int NBF = N / R, TOTAL = CB * NBF, STRIDE = N / (NS * R);
+    for (int u = threadIdx.x; u < TOTAL; u += THREADS) {
+        const int cb = u / NBF, j = u % NBF, jq = j / NS, k = j % NS;
+        double2 v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const double2 x = src[cb * N + j + q * NBF];
+            v[q] = q == 0 ? x : cmul(x, tw_at(tw, q * k * STRIDE));
+        }
+        dft_small<R>(v, tw, N);
+        const int idxD = cb * N + jq * NS * R + k;
+#pragma unroll
+        for (int p = 0; p < R; ++p)
+            dst[idxD + p * NS] = v[p];
+    }
+    __syncthreads();
+}
+
+// The ping-pong stages of a compile-time N from stage I on; returns the
+// buffer that holds the result.
+template <int N, int I, int NS, int CB, int THREADS>
+__device__ inline double2 *fft_pp_c(double2 *cur, double2 *nxt, const double2 *__restrict__ tw)
+{
+    constexpr int R = radix_at(N, I);
+    if constexpr (R == 0) {
+        return cur;
+    } else {
+        stockham_pingpong_c<R, N, NS, CB, THREADS>(cur, nxt, tw);
+        return fft_pp_c<N, I + 1, NS * R, CB, THREADS>(nxt, cur, tw);
+    }
+}
+
 // global loads in flight per thread while staging: the ping-pong variant
 // (short transforms, many sequences per workgroup) gains from 8; the
 // in-place one (long transforms, 4-element runs per row) measured slower
 constexpr int AXIS_BATCH_PP = 8;
 
-// NC: in place with N fixed at compile time (1024, CB = FFT_LDS_ELEMS / NC:
-// constant stage indices), else 0.
+// NC: N fixed at compile time (constant stage indices), else 0; CB is then
+// axis_cb(PP, NC), the host's choice for that N.
+__host__ __device__ constexpr int axis_cb(bool pp, int N)
+{
+    return (pp ? FFT_LDS_ELEMS / (2 * N) : FFT_LDS_ELEMS / N) > 32
+               ? 32
+               : (pp ? FFT_LDS_ELEMS / (2 * N) : FFT_LDS_ELEMS / N);
+}
+
 template <bool PP, int THREADS, int NC = 0>
 __global__ void __launch_bounds__(THREADS)
 k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadices fr,
            int64_t nseq, int64_t es, int64_t b_in, int64_t s_in, int64_t s_out, int CB_,
            int live)
 {
-    static_assert(NC == 0 || !PP, "compile-time sizes are in place only");
-    const int CB = NC ? FFT_LDS_ELEMS / NC : CB_;
+    const int CB = NC ? axis_cb(PP, NC) : CB_;
     extern __shared__ double2 sm[];
     __shared__ int64_t base[FFT_MAX_CB];
     // the in-place stages use a padded area (lds_at), the ping-pong ones not
     constexpr int PAD = PP ? 0 : AXIS_PAD;
     const int N = NC ? NC : fr.n;
-    // Workgroups go to the 8 XCDs round robin.  When the grid divides by 8,
-    // XCD x takes the x-th eighth of the sequence blocks in order, so that
-    // neighbouring blocks -- whose strided rows share cache lines -- meet in
-    // one L2 instead of each fetching whole lines for half their bytes.
-    const unsigned G = gridDim.x, w = blockIdx.x;
-    const unsigned blk = G % 8 == 0 ? (w % 8) * (G / 8) + w / 8 : w;
+    // Workgroups go to the 8 XCDs round robin.  XCD x takes the x-th eighth
+    // of the sequence blocks in order (of the largest multiple of 8 of them;
+    // the rest keep their place), so that neighbouring blocks -- whose
+    // strided rows share cache lines -- meet in one L2 instead of each
+    // fetching whole lines for half their bytes.
+    const unsigned G = gridDim.x, w = blockIdx.x, G8 = G & ~7u;
+    const unsigned blk = w < G8 ? (w % 8) * (G8 / 8) + w / 8 : w;
     const int64_t seq0 = (int64_t)blk * CB;
     const int tot = CB * N;
     for (int cb = threadIdx.x; cb < CB; cb += THREADS) {
@@ -149,8 +210,10 @@ k_fft_axis(double2 *__restrict__ data, const double2 *__restrict__ tw, FftRadice
     double2 *cur = sm, *nxt = sm + tot;
     int Ns = 1, lgNs = 0;
     const int lg = fr.lg;
-    if constexpr (NC > 0)
-        fft_lds_c<NC, 1, FFT_LDS_ELEMS / NC, THREADS, PAD>(sm, tw);
+    if constexpr (NC > 0 && PP)
+        cur = fft_pp_c<NC, 0, 1, axis_cb(true, NC), THREADS>(sm, sm + tot, tw);
+    else if constexpr (NC > 0)
+        fft_lds_c<NC, 1, axis_cb(false, NC), THREADS, PAD>(sm, tw);
     for (int st = 0; NC == 0 && st < 16 && fr.r[st] > 0; ++st) {
         const int R = fr.r[st];
         if constexpr (PP) {
@@ -213,9 +276,17 @@ void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq,
         CB = 32;
     if (CB >= 8) {
         const int64_t blocks = (nseq + CB - 1) / CB;
-        k_fft_axis<true, FFT_THREADS><<<blocks, FFT_THREADS,
-                                        2 * (size_t)CB * fr.n * sizeof(double2), s>>>(
-            d, tw, fr, nseq, es, b_in, s_in, s_out, CB, live);
+        const size_t lds = 2 * (size_t)CB * fr.n * sizeof(double2);
+        // the trispectrum's and order five's default sizes at compile time
+        if (fr.n == 96)
+            k_fft_axis<true, FFT_THREADS, 96><<<blocks, FFT_THREADS, lds, s>>>(
+                d, tw, fr, nseq, es, b_in, s_in, s_out, CB, live);
+        else if (fr.n == 48)
+            k_fft_axis<true, FFT_THREADS, 48><<<blocks, FFT_THREADS, lds, s>>>(
+                d, tw, fr, nseq, es, b_in, s_in, s_out, CB, live);
+        else
+            k_fft_axis<true, FFT_THREADS><<<blocks, FFT_THREADS, lds, s>>>(
+                d, tw, fr, nseq, es, b_in, s_in, s_out, CB, live);
         return;
     }
     // in place: long transforms fill the LDS area with few sequences, so a
@@ -225,7 +296,7 @@ void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq,
         CB = 32;
     const int64_t blocks = (nseq + CB - 1) / CB;
     const size_t lds = (size_t)lds_slots<AXIS_PAD>(CB * fr.n) * sizeof(double2);
-    if (fr.n == 1024 && CB == FFT_LDS_ELEMS / 1024)
+    if (fr.n == 1024)
         k_fft_axis<false, 1024, 1024><<<blocks, 1024, lds, s>>>(d, tw, fr, nseq, es, b_in, s_in,
                                                                s_out, CB, live);
     else if (fr.n >= 512)
@@ -707,31 +778,31 @@ k_tri_lines(const double *__restrict__ c4, int M, const double2 *__restrict__ tw
     for (int m = threadIdx.x; m <= M; m += FFT_THREADS)
         dwin[m] = pz ? parzen_d(m, M) : 1.0;
     __syncthreads();
+    // The fold onto grid point (m1, m2, m3) is the centred lag's term alone:
+    // N >= 2M, so an axis has one alias candidate in [-M, M] -- or, at m = M
+    // when N = 2M, two (+-M) whose Parzen factor d(M) is 0, as is the
+    // centred one's (the trispectrum's spectrum takes the Parzen window
+    // only).  Branch-free: a point off the support reads the cube's entry 0
+    // and d(0) and is then selected to 0, so the reads of several points are
+    // in flight at once.  The window's products keep the alias sum's order.
     auto fold = [&](int64_t L, int m3) {
-        double sum = 0.0;
-        if (L >= lines)
-            return sum;
         const int m1 = (int)(L / N), m2 = (int)(L - (int64_t)m1 * N);
-        for (int t1 = m1 - N; t1 <= m1; t1 += N) {
-            if (t1 < -M || t1 > M)
-                continue;
-            for (int t2 = m2 - N; t2 <= m2; t2 += N) {
-                if (t2 < -M || t2 > M || abs(t2 - t1) > M)
-                    continue;
-                for (int t3 = m3 - N; t3 <= m3; t3 += N) {
-                    if (t3 < -M || t3 > M || abs(t3 - t1) > M || abs(t3 - t2) > M)
-                        continue;   // outside the span <= M support c4 is 0
-                    const double wl = dwin[abs(t1)] * dwin[abs(t2)] * dwin[abs(t3)];
-                    const double w = pdiff ? wl * dwin[abs(t2 - t1)] * dwin[abs(t3 - t1)] *
-                                                 dwin[abs(t3 - t2)]
-                                           : wl;
-                    sum += w * c4[((int64_t)(t1 + M) * side + (t2 + M)) * side + (t3 + M)];
-                }
-            }
-        }
-        return sum;
+        const int t1 = m1 <= N / 2 ? m1 : m1 - N, t2 = m2 <= N / 2 ? m2 : m2 - N,
+                  t3 = m3 <= N / 2 ? m3 : m3 - N;
+        const bool ok = L < lines && abs(t1) <= M && abs(t2) <= M && abs(t3) <= M &&
+                        abs(t2 - t1) <= M && abs(t3 - t1) <= M && abs(t3 - t2) <= M;
+        const int64_t at =
+            ok ? ((int64_t)(t1 + M) * side + (t2 + M)) * side + (t3 + M) : 0;
+        const double c = c4[at];
+        const int a1 = ok ? abs(t1) : 0, a2 = ok ? abs(t2) : 0, a3 = ok ? abs(t3) : 0;
+        const double wl = dwin[a1] * dwin[a2] * dwin[a3];
+        const double w = pdiff ? wl * dwin[ok ? abs(t2 - t1) : 0] * dwin[ok ? abs(t3 - t1) : 0] *
+                                     dwin[ok ? abs(t3 - t2) : 0]
+                               : wl;
+        return ok ? 0.0 + w * c : 0.0;
     };
     const int64_t L0 = (int64_t)blockIdx.x * 2 * CBP;
+#pragma unroll 4
     for (int e = threadIdx.x; e < CBP * N; e += FFT_THREADS) {
         const int p = e / N, m3 = e - p * N;
         sm[e] = make_double2(fold(L0 + 2 * p, m3), fold(L0 + 2 * p + 1, m3));
