@@ -136,11 +136,19 @@ constexpr int AXIS_BATCH_PP = 8;
 
 // NC: N fixed at compile time (constant stage indices), else 0; CB is then
 // axis_cb(PP, NC), the host's choice for that N.
+// Ping-pong workgroups take at most 16 sequences for N <= 64 (measured: the
+// 48-point passes 49 -> 41 us, with six workgroups per CU instead of three),
+// else at most 32 (the 96-point passes measured slower at 16).
+__host__ __device__ constexpr int axis_pp_max_cb(int N)
+{
+    return N <= 64 ? 16 : 32;
+}
+
 __host__ __device__ constexpr int axis_cb(bool pp, int N)
 {
-    return (pp ? FFT_LDS_ELEMS / (2 * N) : FFT_LDS_ELEMS / N) > 32
-               ? 32
-               : (pp ? FFT_LDS_ELEMS / (2 * N) : FFT_LDS_ELEMS / N);
+    return pp ? (FFT_LDS_ELEMS / (2 * N) > axis_pp_max_cb(N) ? axis_pp_max_cb(N)
+                                                             : FFT_LDS_ELEMS / (2 * N))
+              : (FFT_LDS_ELEMS / N > 32 ? 32 : FFT_LDS_ELEMS / N);
 }
 
 template <bool PP, int THREADS, int NC = 0>
@@ -271,9 +279,9 @@ void fft_axis(double2 *d, const double2 *tw, const FftRadices &fr, int64_t nseq,
         live = fr.n;
     // ping-pong while both buffers of >= 8 sequences fit the 64 KB area
     // (N <= 256), else in place
-    int CB = FFT_LDS_ELEMS / (2 * fr.n);
-    if (CB > 32)
-        CB = 32;
+    // (axis_cb: a smaller LDS area lets more workgroups share a CU, and 16
+    // neighbouring sequences still make 256-byte runs of a strided axis)
+    int CB = axis_cb(true, fr.n);
     if (CB >= 8) {
         const int64_t blocks = (nseq + CB - 1) / CB;
         const size_t lds = 2 * (size_t)CB * fr.n * sizeof(double2);
